@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark of the local-energy path on one MI355X.
+
+One step = one pass of the hot path over one batch already resident in HBM:
+sample-hash build + E_loc lookup kernel + finish kernel (nqs_eloc_eval) and
+the weighted energy/variance reduction (nqs_energy, which synchronises).  The
+Pauli table is built and uploaded once before the timed region (it is
+resident across VMC steps); its setup time is reported separately.
+
+Default workload: 40 qubits (20 orbitals, 10 alpha + 10 beta), full
+Jordan-Wigner table (46,171 X groups, 233,001 terms), 65,536 unique sector
+samples with geometric counts, log|psi| ~ N(0, 2), phase ~ U[0, 2 pi), FP64.
+
+Prints ONE JSON line.  Metric: E_loc pair-evaluations per second, where a
+pair is one (unique sample, X group) combination, N_s * G per batch.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2506_23809_amd", "csrc", "nqs_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eloc_lookup_nq40.json")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes(n_s, words, n_groups, n_terms, probes, hits, hit_terms):
+    """Bytes the method must move for one batch: samples in (key, a, phi),
+    E_loc out, one 32-byte granule per lookup, the table once, and for each
+    hit the partner's (a, phi) plus the hit group's terms."""
+    wb = 8 * words
+    return (n_s * (wb + 24 + 16) + probes * 32 + (n_groups + n_terms) * (wb + 8)
+            + hits * 16 + hit_terms * (wb + 8))
+
+
+def cpu_baseline(w, threads, budget_s=20.0):
+    """The oracle as it stands, on the host cores, on a bounded sample."""
+    import numpy as np
+    import oracle
+    n = w.n_samples
+    G = oracle.n_groups(w.x)
+    rows = np.arange(min(n, 256), dtype=np.int64)
+    t0 = time.perf_counter()
+    oracle.eloc_rows(w.n_qubits, w.x, w.z, w.c, w.samples, w.log_amp, w.phase, rows,
+                     threads=threads)
+    t_probe = time.perf_counter() - t0
+    per_row = t_probe / len(rows)
+    if per_row * n <= budget_s:
+        t0 = time.perf_counter()
+        oracle.eloc(w.n_qubits, w.x, w.z, w.c, w.samples, w.log_amp, w.phase, threads=threads)
+        dt = time.perf_counter() - t0
+        done = n
+        sample = f"all {n} samples (full S x S double loop)"
+    else:
+        m = max(256, int(budget_s / per_row))
+        sel = np.random.default_rng(0).choice(n, size=m, replace=False).astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.eloc_rows(w.n_qubits, w.x, w.z, w.c, w.samples, w.log_amp, w.phase, sel,
+                         threads=threads)
+        dt = time.perf_counter() - t0
+        done = m
+        sample = f"{m} of {n} sample rows, each against all {n} samples"
+    return {"value": done * G / dt, "unit": "pair-evals/s", "cores": threads,
+            "kind": "oracle", "sample": sample, "seconds": round(dt, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg1", choices=["cfg0", "cfg1", "cfg2"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32k"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE {world}); multi-GPU sharding is described in DESIGN.md, not run.",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2506_23809_amd as nqs
+    import workloads
+
+    def log(msg):
+        if not args.quiet:
+            print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    cfg = {"cfg0": 0, "cfg1": 1, "cfg2": 2}[args.workload]
+    t0 = time.perf_counter()
+    w = workloads.config(cfg)
+    log(f"workload {w.name}: {w.n_samples} samples, {w.x.shape[0]} terms "
+        f"({time.perf_counter() - t0:.1f} s to generate)")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    G, T, table_bytes = ham.info()
+    words = 1 if w.n_qubits <= 63 else 2
+    log(f"table: {G} groups, {T} terms, {table_bytes / 1e6:.1f} MB, setup {setup_ms:.1f} ms")
+
+    S = nqs.to_device_samples(w.samples, dev)
+    la = torch.from_numpy(w.log_amp).to(dev)
+    ph = torch.from_numpy(w.phase).to(dev)
+    wt = torch.from_numpy(w.weights).to(dev)
+    out = torch.empty((w.n_samples, 2), dtype=torch.float64, device=dev)
+
+    def step():
+        ham.eloc_into(out, S, la, ph, wt, precision=args.precision)
+        return nqs.energy(wt, out)
+
+    for k in range(args.warmup):
+        step()
+        log(f"warmup {k + 1}/{args.warmup}")
+    ham.sync()
+    st = ham.stats()
+    ham.profile(True)
+    kms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        mean, var, sw = step()          # nqs_energy synchronises the stream
+        kms.append(ham.last_kernel_ms())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ham.profile(False)
+    ham.sync()
+    ms_per_step = elapsed * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, E = {mean.real:.10f}, var = {var:.4e}")
+
+    kms = np.array(kms)
+    hash_ms, lookup_ms, finish_ms = (float(v) for v in kms.mean(axis=0))
+    pairs = st["pairs"]
+    value = pairs / (ms_per_step / 1e3)
+    # bytes per launch of the lookup kernel (everything except the diagonal group)
+    n_diag_terms = int(np.sum((w.x[:, 0] == 0) & (w.x[:, 1] == 0)))
+    hit_terms = st["terms"] - w.n_samples * n_diag_terms
+    b_alg = algorithmic_bytes(w.n_samples, words, G, T, st["probes"], st["hits"], max(hit_terms, 0))
+    achieved = b_alg / (lookup_ms / 1e3) / 1e9
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            with open(TRAFFIC_FILE) as f:
+                tr = json.load(f)
+            if tr.get("kernel_source_sha256_16") == kernel_source_hash() and \
+                    tr.get("workload") == w.name:
+                traffic = tr.get("hbm_bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+
+    res = {
+        "metric": "E_loc pair-evals/s",
+        "value": value,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+kahan/f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: {w.n_qubits} qubits ({w.K} orbitals, {w.n_alpha}a+{w.n_beta}b), "
+                        f"{w.n_samples} unique sector samples, geometric counts, "
+                        f"log|psi|~N(0,2), phase~U[0,2pi), JW table G={G} T={T}",
+            "n_qubits": w.n_qubits, "n_samples": w.n_samples, "n_groups": G, "n_terms": T,
+            "precision": args.precision,
+        },
+        "roofline": {
+            "kernel": "eloc_probe_kernel",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": b_alg,
+            "kernel_ms": lookup_ms,
+        },
+        "kernel_ms": {"hash_build": hash_ms, "eloc_lookup": lookup_ms, "eloc_finish": finish_ms},
+        "counts": st,
+        "probes_per_s": st["probes"] / (ms_per_step / 1e3),
+        "setup_ms": setup_ms,
+        "energy": {"re": mean.real, "im": mean.imag, "var": var, "sum_w": sw},
+    }
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        log(f"cpu baseline: oracle on {threads} threads")
+        res["cpu_baseline"] = cpu_baseline(w, threads)
+        log(f"cpu baseline: {res['cpu_baseline']}")
+    else:
+        res["cpu_baseline"] = None
+    ham.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

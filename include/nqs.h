@@ -1,0 +1,198 @@
+/*
+ * nqs.h - C ABI of the MI355X local-energy library (libnqs.so).
+ *
+ * The library evaluates the sample-space local energy of a neural-network
+ * quantum state for a qubit Hamiltonian given as Pauli strings:
+ *
+ *   E_loc(x) = sum_{x' in S} <x|H|x'> psi(x') / psi(x)      (Eq. 5)
+ *
+ * over a batch S of unique occupation-number samples, where psi is known
+ * only on S (the psi lookup table of the sample-space energy, Sec. IV-C);
+ * an x' outside S contributes nothing.  It also returns the count-weighted
+ * energy mean and variance of Eq. 1.
+ *
+ * Conventions (all entry points):
+ *  - Qubit j is bit (j % 64) of word (j / 64); masks and samples are two
+ *    uint64 words per item, [n][2], word 0 holding qubits 0..63.  Bits at or
+ *    above n_qubits must be zero.  With the molecular ordering of Sec. II-A,
+ *    spin orbital (p, alpha) is qubit 2p and (p, beta) is qubit 2p + 1.
+ *  - A Pauli term (x, z, c) is c * P with P = i^{popc(x & z)} X^x Z^z, so
+ *    every P is Hermitian.  Terms with an odd number of Y factors
+ *    (popc(x & z) odd) have purely imaginary matrix elements and cannot
+ *    occur in a real molecular Hamiltonian; they are rejected.
+ *  - psi(x) = exp(a(x) + i phi(x)): a is ln|psi| (not ln|psi|^2).
+ *  - Buffers marked "device" are HIP device pointers on the current device;
+ *    "host" buffers are ordinary host memory.  The caller owns every buffer
+ *    it passes and must keep device buffers alive until the work enqueued on
+ *    hip_stream has completed.  hip_stream is a hipStream_t (NULL = the
+ *    default stream).
+ *  - Return value: NQS_OK (0) or a negative NQS_E_* code; a description of
+ *    the last error on the calling thread is available from
+ *    nqs_last_error().  No exception crosses the ABI.  Errors found while
+ *    device work runs (duplicate samples, bits out of range, negative
+ *    counts) are latched on the handle and returned by the next nqs_sync().
+ */
+#ifndef NQS_H
+#define NQS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    NQS_OK = 0,
+    NQS_E_ARG = -1,       /* null pointer, negative size, unknown option, non-finite value */
+    NQS_E_RANGE = -2,     /* n_qubits outside [1, 127], or a bit at or above n_qubits set */
+    NQS_E_NONREAL = -3,   /* a term with an odd number of Y factors */
+    NQS_E_DUPLICATE = -4, /* a sample occurs twice in one batch */
+    NQS_E_NOMEM = -5,     /* host or device allocation failed */
+    NQS_E_DEVICE = -6,    /* a HIP runtime call failed */
+    NQS_E_STATE = -7      /* handle used in a state that does not allow the call */
+};
+
+enum {
+    NQS_FP64 = 0,        /* every sum and product in FP64 */
+    NQS_FP32_KAHAN = 1   /* term sums in FP32 with compensation; FP64 amplitude ratios */
+};
+
+typedef struct nqs_ham_s *nqs_ham; /* opaque, owned by the library */
+
+/* Text of the last error reported on the calling thread ("" if none). */
+const char *nqs_last_error(void);
+
+/* ABI version of this header (major * 100 + minor). */
+int nqs_version(void);
+
+/*
+ * Build the resident Pauli table of a Hamiltonian (Eq. 2 mapped to qubits).
+ *
+ *   x_masks, z_masks : host, [n_terms][2] uint64, the X and Z bits of each term.
+ *   coeffs           : host, [n_terms] double, the real coefficients c_t.
+ *   spin_masks       : host, [2][2] uint64 {alpha, beta} qubit masks, or NULL.
+ *                      When both are non-zero and every sample of a batch has
+ *                      the same (N_alpha, N_beta), flips that change either
+ *                      count are skipped without a lookup (they cannot land
+ *                      in S).  NULL or all-zero switches the filter off.
+ *   hip_stream       : stream for the upload.
+ *
+ * Terms are validated (bits below n_qubits, finite coefficients, even Y
+ * count), the phase i^{ny} is folded into the coefficient, equal strings
+ * are merged by summing in input order, and the table is grouped by X
+ * mask (ascending (X, Z) order; the X = 0 group, if present, is group 0).
+ * No threshold is applied.  The copy to the device is asynchronous on
+ * hip_stream; the host arrays may be freed when this call returns.
+ *
+ * Errors: NQS_E_ARG (null out or arrays, n_terms < 0, non-finite c,
+ * overlapping spin masks), NQS_E_RANGE, NQS_E_NONREAL, NQS_E_NOMEM,
+ * NQS_E_DEVICE.  On error *out is set to NULL.
+ */
+int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *x_masks,
+                   const uint64_t *z_masks, const double *coeffs, const uint64_t *spin_masks,
+                   void *hip_stream);
+
+/* Group count G, merged term count T and device bytes held by the table. */
+int nqs_ham_info(nqs_ham h, int64_t *n_groups, int64_t *n_terms, int64_t *device_bytes);
+
+/* Release the handle, its device table and its scratch.  Waits for the
+ * handle's outstanding work first.  NULL is accepted. */
+int nqs_ham_destroy(nqs_ham h);
+
+/*
+ * Host-only form of the table builder used by nqs_ham_create (no device
+ * needed).  Call once with all output pointers NULL to obtain *n_groups and
+ * *n_merged, then again with buffers of those sizes:
+ *   group_x  [n_groups][2] uint64   X mask of each group
+ *   group_off[n_groups + 1] int64   term range of each group
+ *   term_z   [n_merged][2] uint64   Z mask of each merged term
+ *   term_c   [n_merged] double      folded coefficient c * (-1)^{ny/2}
+ * Same validation and errors as nqs_ham_create.
+ */
+int nqs_table_host(int n_qubits, int64_t n_terms, const uint64_t *x_masks,
+                   const uint64_t *z_masks, const double *coeffs, int64_t *n_groups,
+                   int64_t *n_merged, uint64_t *group_x, int64_t *group_off, uint64_t *term_z,
+                   double *term_c);
+
+/*
+ * Local energies of one batch (Eq. 5 over S, Alg. 3's per-sample outer loop).
+ *
+ *   samples : device, [n][2] uint64, unique bit strings, bits >= n_qubits zero.
+ *   weights : device, [n] int64 counts >= 0, or NULL.  Counts do not change
+ *             E_loc; when given they are checked for negatives.
+ *   log_amp : device, [n] double, a(x) = ln|psi(x)|.
+ *   phase   : device, [n] double, phi(x).
+ *   eloc    : device, [n][2] double (re, im) output, caller-owned.
+ *   precision: NQS_FP64 or NQS_FP32_KAHAN.
+ *
+ * Asynchronous on hip_stream (no host synchronisation).  The handle's
+ * scratch (sample hash, partial sums) is reused; a handle may be used from
+ * one stream at a time.  n = 0 is a no-op.  Errors: NQS_E_ARG, NQS_E_STATE
+ * (bad handle), NQS_E_NOMEM, NQS_E_DEVICE synchronously; NQS_E_DUPLICATE and
+ * NQS_E_RANGE (sample bits, negative counts) from the next nqs_sync().
+ */
+int nqs_eloc_eval(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weights,
+                  const double *log_amp, const double *phase, double *eloc, int precision,
+                  void *hip_stream);
+
+/*
+ * Count-weighted energy of Eq. 1 over unique samples:
+ *   out[0] = Re E, out[1] = Im E with E = sum w E_loc / sum w,
+ *   out[2] = sum w |E_loc - E|^2 / sum w (population variance, second pass),
+ *   out[3] = sum w.
+ * weights: device [n] int64; eloc: device [n][2] double; out: host [4].
+ * The reduction order is fixed, so repeated calls give identical bits.
+ * Synchronises hip_stream before returning.  Errors: NQS_E_ARG (n <= 0,
+ * null pointers, sum w == 0), NQS_E_NOMEM, NQS_E_DEVICE.
+ */
+int nqs_energy(int64_t n, const int64_t *weights, const double *eloc, double out[4],
+               void *hip_stream);
+
+/* Wait for hip_stream and return the first error latched by device work of
+ * this handle since the previous nqs_sync (then clear it). */
+int nqs_sync(nqs_ham h, void *hip_stream);
+
+/*
+ * Counters of the last nqs_eloc_eval on this handle (valid after nqs_sync):
+ *   out[0] pairs   = n * G (sample, group) pair-evaluations
+ *   out[1] probes  = pairs that passed the sector test (lookups)
+ *   out[2] hits    = lookups that found x' in S (off-diagonal)
+ *   out[3] terms   = Pauli terms evaluated (diagonal group plus hit groups)
+ */
+int nqs_eval_stats(nqs_ham h, int64_t out[4]);
+
+/*
+ * Kernel timing.  nqs_profile(h, 1) makes every later nqs_eloc_eval on h
+ * record HIP events on its stream around each kernel stage; after the
+ * stream has completed, nqs_last_kernel_ms(h, out) returns the durations in
+ * milliseconds of the last evaluation:
+ *   out[0] sample-hash build (clear + insert)
+ *   out[1] E_loc lookup kernel (all non-diagonal groups)
+ *   out[2] E_loc finish kernel (diagonal group + partial sums)
+ * Errors: NQS_E_STATE (bad handle, profiling off, nothing recorded yet),
+ * NQS_E_DEVICE.
+ */
+int nqs_profile(nqs_ham h, int enable);
+int nqs_last_kernel_ms(nqs_ham h, float out[3]);
+
+/*
+ * Test hook: nqs_eloc_eval with the lookup results recorded (same kernels,
+ * extra stores switched on).
+ *   hit_idx  : device [n][G] int32 or NULL.  For group g of sample i: the
+ *              index j of x' = x_i ^ X_g in S, or -1 when x' is not in S or
+ *              the group failed the sector test; the X = 0 group records i.
+ *   sign_bits: device [n][(T + 7) / 8] uint8 or NULL, zero-filled by the
+ *              caller.  Bit t is popc(Z_t & x_i) & 1 for every term t the
+ *              kernel evaluated for sample i (X = 0 group and hit groups);
+ *              other bits stay zero.
+ * Other arguments and errors as nqs_eloc_eval (FP64 only).
+ */
+int nqs_debug_dump(nqs_ham h, int64_t n, const uint64_t *samples, const double *log_amp,
+                   const double *phase, double *eloc, int32_t *hit_idx, uint8_t *sign_bits,
+                   void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NQS_H */

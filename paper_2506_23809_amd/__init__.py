@@ -1,0 +1,244 @@
+"""Python binding of libnqs.so, the MI355X local-energy library.
+
+Argument marshalling only: every step of the local-energy path runs in the
+library's HIP kernels.  PyTorch provides device memory and the current HIP
+stream.  There is no CPU fallback: if ``libnqs.so`` is missing the import of
+the library raises.
+
+    ham = Hamiltonian(x, z, c, n_qubits, spin_masks)      # nqs_ham_create
+    e   = ham.eloc(samples, log_amp, phase, weights)        # nqs_eloc_eval -> complex128 [n]
+    mean, var, sum_w = energy(weights, e)                   # nqs_energy
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnqs.so")
+
+NQS_OK = 0
+NQS_E_ARG = -1
+NQS_E_RANGE = -2
+NQS_E_NONREAL = -3
+NQS_E_DUPLICATE = -4
+NQS_E_NOMEM = -5
+NQS_E_DEVICE = -6
+NQS_E_STATE = -7
+
+NQS_FP64 = 0
+NQS_FP32_KAHAN = 1
+_PRECISION = {"fp64": NQS_FP64, "fp32k": NQS_FP32_KAHAN, "fp32_kahan": NQS_FP32_KAHAN}
+
+# Every symbol include/nqs.h declares.
+EXPORTS = ("nqs_last_error", "nqs_version", "nqs_ham_create", "nqs_ham_info", "nqs_ham_destroy",
+           "nqs_table_host", "nqs_eloc_eval", "nqs_energy", "nqs_sync", "nqs_eval_stats",
+           "nqs_debug_dump", "nqs_profile", "nqs_last_kernel_ms")
+
+
+class NQSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"nqs error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libnqs.so and declare its signatures; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run paper_2506_23809_amd/build.py "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(path)
+    P, I, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    sig = {
+        "nqs_last_error": (ctypes.c_char_p, []),
+        "nqs_version": (I, []),
+        "nqs_ham_create": (I, [P, I, I64, P, P, P, P, P]),
+        "nqs_ham_info": (I, [P, P, P, P]),
+        "nqs_ham_destroy": (I, [P]),
+        "nqs_table_host": (I, [I, I64, P, P, P, P, P, P, P, P, P]),
+        "nqs_eloc_eval": (I, [P, I64, P, P, P, P, P, I, P]),
+        "nqs_energy": (I, [I64, P, P, P, P]),
+        "nqs_sync": (I, [P, P]),
+        "nqs_eval_stats": (I, [P, P]),
+        "nqs_debug_dump": (I, [P, I64, P, P, P, P, P, P, P]),
+        "nqs_profile": (I, [P, I]),
+        "nqs_last_kernel_ms": (I, [P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != NQS_OK:
+        raise NQSError(rc, load_library().nqs_last_error().decode())
+
+
+def _np_u64(a, shape_cols=2):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint64).reshape(-1, shape_cols))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, dtype, ncols=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if ncols is not None and (t.dim() != 2 or t.shape[1] != ncols):
+        raise ValueError(f"expected shape [n, {ncols}]")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def table_host(n_qubits, x, z, c):
+    """Host-only table builder (nqs_table_host): (group_x, group_off, term_z, term_c)."""
+    lib = load_library()
+    x, z = _np_u64(x), _np_u64(z)
+    c = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+    G = ctypes.c_int64()
+    T = ctypes.c_int64()
+    args = (int(n_qubits), x.shape[0], x.ctypes.data, z.ctypes.data, c.ctypes.data)
+    _check(lib.nqs_table_host(*args, ctypes.byref(G), ctypes.byref(T), None, None, None, None))
+    gx = np.zeros((G.value, 2), np.uint64)
+    go = np.zeros(G.value + 1, np.int64)
+    tz = np.zeros((T.value, 2), np.uint64)
+    tc = np.zeros(T.value, np.float64)
+    _check(lib.nqs_table_host(*args, ctypes.byref(G), ctypes.byref(T), gx.ctypes.data,
+                              go.ctypes.data, tz.ctypes.data, tc.ctypes.data))
+    return gx, go, tz, tc
+
+
+class Hamiltonian:
+    """A resident Pauli table on the current device (nqs_ham_create)."""
+
+    def __init__(self, x, z, c, n_qubits, spin_masks=None, stream=None):
+        lib = load_library()
+        x, z = _np_u64(x), _np_u64(z)
+        c = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+        if not (x.shape[0] == z.shape[0] == c.shape[0]):
+            raise ValueError("x, z and c must have the same number of terms")
+        sm = None if spin_masks is None else _np_u64(spin_masks)
+        h = ctypes.c_void_p()
+        _check(lib.nqs_ham_create(ctypes.byref(h), int(n_qubits), x.shape[0], x.ctypes.data,
+                                  z.ctypes.data, c.ctypes.data,
+                                  None if sm is None else sm.ctypes.data, _stream(stream)))
+        self._h = h
+        self.n_qubits = int(n_qubits)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().nqs_ham_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        G, T, B = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load_library().nqs_ham_info(self._h, ctypes.byref(G), ctypes.byref(T),
+                                           ctypes.byref(B)))
+        return G.value, T.value, B.value
+
+    @property
+    def n_groups(self):
+        return self.info()[0]
+
+    @property
+    def n_terms(self):
+        return self.info()[1]
+
+    def eloc_into(self, out, samples, log_amp, phase, weights=None, precision="fp64",
+                  stream=None):
+        """nqs_eloc_eval into a float64 [n, 2] device tensor (asynchronous)."""
+        import torch
+        n = samples.shape[0]
+        wp = None if weights is None else _dptr(weights, torch.int64)
+        _check(load_library().nqs_eloc_eval(
+            self._h, n, _dptr(samples, torch.int64, 2), wp, _dptr(log_amp, torch.float64),
+            _dptr(phase, torch.float64), _dptr(out, torch.float64, 2), _PRECISION[precision],
+            _stream(stream)))
+        return out
+
+    def eloc(self, samples, log_amp, phase, weights=None, precision="fp64", stream=None):
+        """E_loc for a batch; returns a complex128 device tensor [n]."""
+        import torch
+        out = torch.empty((samples.shape[0], 2), dtype=torch.float64, device=samples.device)
+        self.eloc_into(out, samples, log_amp, phase, weights, precision, stream)
+        return torch.view_as_complex(out)
+
+    def sync(self, stream=None):
+        """Wait for the stream and raise the first device-detected error."""
+        _check(load_library().nqs_sync(self._h, _stream(stream)))
+
+    def stats(self):
+        out = (ctypes.c_int64 * 4)()
+        _check(load_library().nqs_eval_stats(self._h, out))
+        return {"pairs": out[0], "probes": out[1], "hits": out[2], "terms": out[3]}
+
+    def profile(self, enable=True):
+        """Record HIP events around each kernel stage of later evaluations."""
+        _check(load_library().nqs_profile(self._h, 1 if enable else 0))
+
+    def last_kernel_ms(self):
+        """(hash build, lookup kernel, finish kernel) durations of the last evaluation."""
+        out = (ctypes.c_float * 3)()
+        _check(load_library().nqs_last_kernel_ms(self._h, out))
+        return tuple(out)
+
+    def debug_dump(self, samples, log_amp, phase, hit_idx=None, sign_bits=None, stream=None):
+        """nqs_debug_dump: E_loc plus the recorded lookups / sign bits."""
+        import torch
+        n = samples.shape[0]
+        out = torch.empty((n, 2), dtype=torch.float64, device=samples.device)
+        hp = None if hit_idx is None else _dptr(hit_idx, torch.int32)
+        sp = None if sign_bits is None else _dptr(sign_bits, torch.uint8)
+        _check(load_library().nqs_debug_dump(
+            self._h, n, _dptr(samples, torch.int64, 2), _dptr(log_amp, torch.float64),
+            _dptr(phase, torch.float64), _dptr(out, torch.float64, 2), hp, sp, _stream(stream)))
+        return torch.view_as_complex(out)
+
+
+def energy(weights, eloc, stream=None):
+    """nqs_energy: (mean complex, variance, sum_w); synchronises the stream."""
+    import torch
+    if eloc.dtype == torch.complex128:
+        eloc = torch.view_as_real(eloc)
+    out = (ctypes.c_double * 4)()
+    n = weights.shape[0]
+    _check(load_library().nqs_energy(n, _dptr(weights, torch.int64),
+                                     _dptr(eloc.contiguous(), torch.float64, 2), out,
+                                     _stream(stream)))
+    return complex(out[0], out[1]), out[2], out[3]
+
+
+def to_device_samples(words, device="cuda"):
+    """uint64 [n, 2] numpy words -> int64 [n, 2] device tensor (same bits)."""
+    import torch
+    a = _np_u64(words).view(np.int64)
+    return torch.from_numpy(a.copy()).to(device)

@@ -1,0 +1,179 @@
+// Host-side Pauli table builder (no device code).
+//
+// The terms of H = sum_t c_t i^{ny_t} X^{x_t} Z^{z_t} enter as packed masks.
+// For a real Hamiltonian ny is even, and the matrix element between basis
+// states x (bra) and x' = x ^ X_t (ket) is
+//   <x| i^{ny} X^X Z^Z |x'> = <x| (-i)^{ny} Z^Z X^X |x'> = (-1)^{ny/2} (-1)^{popc(Z & x)},
+// using X^X Z^Z = (-1)^{ny} Z^Z X^X.  The constant (-1)^{ny/2} is folded into
+// the stored coefficient, so a kernel needs one popcount per term.  Terms are
+// grouped by X because every term of a group connects x to the same x'
+// (the per-ket inner loop of Alg. 3 becomes a loop over groups).
+#include "nqs_table.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "../../include/nqs.h"
+
+namespace nqs {
+
+namespace {
+
+inline int popc2(uint64_t a, uint64_t b) { return __builtin_popcountll(a) + __builtin_popcountll(b); }
+
+inline bool above(uint64_t w0, uint64_t w1, int nq) {
+    // true if any bit at index >= nq is set
+    if (nq >= 128) return false;
+    if (nq >= 64) {
+        int k = nq - 64;
+        return k < 64 && (w1 >> k) != 0;
+    }
+    return (w0 >> nq) != 0 || w1 != 0;
+}
+
+uint64_t splitmix64(uint64_t *s) {
+    uint64_t z = (*s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+LinearHash::LinearHash() {
+    uint64_t s = 0x6e71735f68617368ull;  // fixed seed: tables are reproducible
+    for (int j = 0; j < 128; ++j) r[j] = static_cast<uint32_t>(splitmix64(&s) >> 32);
+}
+
+uint32_t LinearHash::operator()(uint64_t w0, uint64_t w1) const {
+    uint32_t h = 0;
+    while (w0) {
+        h ^= r[__builtin_ctzll(w0)];
+        w0 &= w0 - 1;
+    }
+    while (w1) {
+        h ^= r[64 + __builtin_ctzll(w1)];
+        w1 &= w1 - 1;
+    }
+    return h;
+}
+
+int build_table(int n_qubits, int64_t n_terms, const uint64_t *x, const uint64_t *z,
+                const double *c, const uint64_t *spin_masks, HostTable *out, std::string *err) {
+    if (!out) { *err = "null output"; return NQS_E_ARG; }
+    if (n_qubits < 1 || n_qubits > kMaxQubits) {
+        *err = "n_qubits must be in [1, 127], got " + std::to_string(n_qubits);
+        return NQS_E_RANGE;
+    }
+    if (n_terms < 0) { *err = "n_terms < 0"; return NQS_E_ARG; }
+    if (n_terms > 0 && (!x || !z || !c)) { *err = "null term arrays"; return NQS_E_ARG; }
+    if (n_terms >= (int64_t(1) << 32)) { *err = "more than 2^32 terms"; return NQS_E_ARG; }
+
+    HostTable &T = *out;
+    T = HostTable();
+    T.n_qubits = n_qubits;
+    T.words = n_qubits <= 63 ? 1 : 2;
+
+    if (spin_masks) {
+        for (int k = 0; k < 4; ++k) T.spin[k / 2][k % 2] = spin_masks[k];
+        for (int s = 0; s < 2; ++s)
+            if (above(T.spin[s][0], T.spin[s][1], n_qubits)) {
+                *err = "spin mask has bits at or above n_qubits";
+                return NQS_E_RANGE;
+            }
+        if ((T.spin[0][0] & T.spin[1][0]) || (T.spin[0][1] & T.spin[1][1])) {
+            *err = "alpha and beta spin masks overlap";
+            return NQS_E_ARG;
+        }
+        bool a = T.spin[0][0] | T.spin[0][1], b = T.spin[1][0] | T.spin[1][1];
+        T.sector_filter = a && b;
+        if (!(a || b)) {
+            T.spin[0][0] = T.spin[0][1] = T.spin[1][0] = T.spin[1][1] = 0;
+        } else if (!(a && b)) {
+            *err = "spin masks: give both alpha and beta, or neither";
+            return NQS_E_ARG;
+        }
+    }
+
+    std::vector<double> folded(static_cast<size_t>(n_terms));
+    for (int64_t t = 0; t < n_terms; ++t) {
+        const uint64_t x0 = x[2 * t], x1 = x[2 * t + 1], z0 = z[2 * t], z1 = z[2 * t + 1];
+        if (above(x0, x1, n_qubits) || above(z0, z1, n_qubits)) {
+            *err = "term " + std::to_string(t) + " has a bit at or above n_qubits";
+            return NQS_E_RANGE;
+        }
+        if (!std::isfinite(c[t])) {
+            *err = "term " + std::to_string(t) + " has a non-finite coefficient";
+            return NQS_E_ARG;
+        }
+        const int ny = popc2(x0 & z0, x1 & z1);
+        if (ny & 1) {
+            *err = "term " + std::to_string(t) + " has an odd number of Y factors";
+            return NQS_E_NONREAL;
+        }
+        folded[t] = (ny & 2) ? -c[t] : c[t];
+    }
+
+    // stable order by (X hi, X lo, Z hi, Z lo): equal strings keep input order
+    std::vector<int64_t> ord(static_cast<size_t>(n_terms));
+    std::iota(ord.begin(), ord.end(), int64_t(0));
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+        if (x[2 * a + 1] != x[2 * b + 1]) return x[2 * a + 1] < x[2 * b + 1];
+        if (x[2 * a] != x[2 * b]) return x[2 * a] < x[2 * b];
+        if (z[2 * a + 1] != z[2 * b + 1]) return z[2 * a + 1] < z[2 * b + 1];
+        return z[2 * a] < z[2 * b];
+    });
+
+    const LinearHash lh;
+    T.tz.reserve(2 * static_cast<size_t>(n_terms));
+    T.tc.reserve(static_cast<size_t>(n_terms));
+    uint64_t px0 = 0, px1 = 0, pz0 = 0, pz1 = 0;
+    bool first = true;
+    for (int64_t k = 0; k < n_terms; ++k) {
+        const int64_t t = ord[k];
+        const uint64_t x0 = x[2 * t], x1 = x[2 * t + 1], z0 = z[2 * t], z1 = z[2 * t + 1];
+        const bool same_x = !first && x0 == px0 && x1 == px1;
+        if (same_x && z0 == pz0 && z1 == pz1) {
+            T.tc.back() += folded[t];  // merge equal strings
+            continue;
+        }
+        if (!same_x) {
+            T.gx.push_back(x0);
+            T.gx.push_back(x1);
+            T.goff.push_back(static_cast<int64_t>(T.tc.size()));
+        }
+        T.tz.push_back(z0);
+        T.tz.push_back(z1);
+        T.tc.push_back(folded[t]);
+        px0 = x0; px1 = x1; pz0 = z0; pz1 = z1;
+        first = false;
+    }
+    T.n_groups = static_cast<int64_t>(T.gx.size() / 2);
+    T.n_terms = static_cast<int64_t>(T.tc.size());
+    T.goff.push_back(T.n_terms);
+    T.has_diagonal = T.n_groups > 0 && T.gx[0] == 0 && T.gx[1] == 0;
+
+    T.gxa.resize(2 * T.n_groups);
+    T.gxb.resize(2 * T.n_groups);
+    T.gmeta.resize(T.n_groups);
+    T.ghx.resize(T.n_groups);
+    for (int64_t g = 0; g < T.n_groups; ++g) {
+        const uint64_t x0 = T.gx[2 * g], x1 = T.gx[2 * g + 1];
+        T.gxa[2 * g] = x0 & T.spin[0][0];
+        T.gxa[2 * g + 1] = x1 & T.spin[0][1];
+        T.gxb[2 * g] = x0 & T.spin[1][0];
+        T.gxb[2 * g + 1] = x1 & T.spin[1][1];
+        const int pa = popc2(T.gxa[2 * g], T.gxa[2 * g + 1]);
+        const int pb = popc2(T.gxb[2 * g], T.gxb[2 * g + 1]);
+        uint32_t meta = static_cast<uint32_t>(pa / 2) | (static_cast<uint32_t>(pb / 2) << 8);
+        if ((pa & 1) || (pb & 1)) meta |= kMetaInfeasible;
+        T.gmeta[g] = meta;
+        T.ghx[g] = lh(x0, x1);
+        T.max_group_terms =
+            std::max(T.max_group_terms, static_cast<int>(T.goff[g + 1] - T.goff[g]));
+    }
+    return NQS_OK;
+}
+
+}  // namespace nqs

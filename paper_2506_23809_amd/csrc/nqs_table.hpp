@@ -1,0 +1,52 @@
+// Host-side Pauli table: validation, phase folding, merge and group-by-X.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace nqs {
+
+// Maximum supported register width: samples and masks are two 64-bit words.
+constexpr int kMaxQubits = 127;
+
+// 32-bit GF(2)-linear hash of a bit string: the XOR of one random word per
+// set bit.  Linearity gives h(x ^ X) = h(x) ^ h(X), so the hash of a flipped
+// sample is one XOR away from the hash of the sample.
+struct LinearHash {
+    uint32_t r[128];
+    LinearHash();
+    uint32_t operator()(uint64_t w0, uint64_t w1) const;
+};
+
+struct HostTable {
+    int n_qubits = 0;
+    int words = 1;                 // 1 when n_qubits <= 63, else 2
+    int64_t n_groups = 0;
+    int64_t n_terms = 0;
+    bool has_diagonal = false;     // group 0 has X = 0
+    bool sector_filter = false;    // spin masks given and non-zero
+    uint64_t spin[2][2] = {{0, 0}, {0, 0}};
+    // groups, ascending by X
+    std::vector<uint64_t> gx;      // [G][2] flip mask
+    std::vector<uint64_t> gxa;     // [G][2] flip mask restricted to alpha qubits
+    std::vector<uint64_t> gxb;     // [G][2] flip mask restricted to beta qubits
+    std::vector<uint32_t> gmeta;   // [G] half counts and feasibility (see kMeta*)
+    std::vector<uint32_t> ghx;     // [G] linear hash of X
+    std::vector<int64_t> goff;     // [G + 1]
+    // merged terms, ascending by (X, Z)
+    std::vector<uint64_t> tz;      // [T][2]
+    std::vector<double> tc;        // [T] c * (-1)^{ny/2}
+    int max_group_terms = 0;
+};
+
+// gmeta layout: bits 0..7 half of popc(X & alpha), bits 8..15 half of
+// popc(X & beta), bit 16 set when either popcount is odd (the flip always
+// leaves the sector).
+constexpr uint32_t kMetaInfeasible = 1u << 16;
+
+// Returns 0 or a negative NQS_E_* code with *err describing it.
+int build_table(int n_qubits, int64_t n_terms, const uint64_t *x, const uint64_t *z,
+                const double *c, const uint64_t *spin_masks, HostTable *out, std::string *err);
+
+}  // namespace nqs

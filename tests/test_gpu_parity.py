@@ -1,0 +1,360 @@
+"""GPU parity: libnqs.so (through its C ABI) against the CPU FP64 oracle.
+
+Floating point: |E_gpu(x) - E_oracle(x)| <= 1e-12 * A(x) with A(x) the
+absolute scale sum over connected x' of |psi(x')/psi(x)| sum_t |c_t| that the
+oracle returns.  Integers (probe, hit and term counts, lookup indices, sign
+bits) must match exactly.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2506_23809_amd as nqs
+import workloads as W
+from oracle import dense
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "a GPU is required"
+    nqs.load_library()
+    return torch
+
+
+def upload(torch, samples, la, ph, weights=None):
+    S = nqs.to_device_samples(samples)
+    la_t = torch.from_numpy(np.ascontiguousarray(la, dtype=np.float64)).cuda()
+    ph_t = torch.from_numpy(np.ascontiguousarray(ph, dtype=np.float64)).cuda()
+    w_t = None
+    if weights is not None:
+        w_t = torch.from_numpy(np.ascontiguousarray(weights, dtype=np.int64)).cuda()
+    return S, la_t, ph_t, w_t
+
+
+def gpu_eloc(torch, w, samples=None, la=None, ph=None, weights=None, spin=True,
+             precision="fp64", ham=None):
+    samples = w.samples if samples is None else samples
+    la = w.log_amp if la is None else la
+    ph = w.phase if ph is None else ph
+    weights = w.weights if weights is None and samples is w.samples else weights
+    own = ham is None
+    if own:
+        ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks if spin else None)
+    S, la_t, ph_t, w_t = upload(torch, samples, la, ph, weights)
+    e = ham.eloc(S, la_t, ph_t, w_t, precision=precision)
+    ham.sync()
+    out = e.cpu().numpy()
+    stats = ham.stats()
+    if own:
+        ham.close()
+    return out, stats
+
+
+def assert_parity(e_gpu, e_orc, absum, tol=TOL):
+    err = np.abs(e_gpu - e_orc)
+    bad = err > tol * absum
+    assert not bad.any(), (f"{bad.sum()} rows off; worst ratio "
+                           f"{(err / np.maximum(absum, 1e-300)).max():.3e}")
+
+
+@pytest.fixture(scope="module")
+def cfg0(workload_cache):
+    return workload_cache(("config", 0))
+
+
+def test_cfg0_random_psi(torch_dev, cfg0):
+    say("cfg0 random psi, 12 qubits, 400 samples")
+    e, st = gpu_eloc(torch_dev, cfg0)
+    ref, ab, nc = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples, cfg0.log_amp, cfg0.phase)
+    assert_parity(e, ref, ab)
+    G, T, conn = W.closed_form_counts(6, 3)
+    assert st["pairs"] == 400 * G
+    assert st["probes"] == 400 * conn
+    assert st["hits"] == 400 * conn == int(nc.sum()) - 400
+    # energy (Eq. 1)
+    m_ref, v_ref, sw_ref = oracle.energy(cfg0.weights, ref)
+    S, la, ph, wt = upload(torch_dev, cfg0.samples, cfg0.log_amp, cfg0.phase, cfg0.weights)
+    et = torch_dev.from_numpy(np.stack([e.real, e.imag], 1).copy()).cuda()
+    m, v, sw = nqs.energy(wt, et)
+    scale = float(np.sum(cfg0.weights * np.abs(ref)) / np.sum(cfg0.weights))
+    assert sw == sw_ref == 400
+    assert abs(m - m_ref) <= 1e-12 * scale
+    assert abs(v - v_ref) <= 1e-12 * scale * scale
+
+
+def test_cfg0_ground_eigenvector(torch_dev, cfg0):
+    say("cfg0 exact ground eigenvector")
+    E0, v, _ = dense.sector_ground_state(cfg0.h, cfg0.eri, cfg0.samples)
+    la = np.log(np.abs(v))
+    ph = np.where(v < 0, math.pi, 0.0)
+    e, _ = gpu_eloc(torch_dev, cfg0, la=la, ph=ph, weights=np.ones(400, np.int64))
+    keep = np.abs(v) >= 1e-4 * np.abs(v).max()
+    assert np.abs(e[keep] - E0).max() <= 1e-10
+    amp = np.abs(v).max() / np.abs(v[~keep])
+    assert np.all(np.abs(e[~keep] - E0) <= 1e-14 * amp * abs(E0) + 1e-10)
+
+
+def expected_dump(w, samples, n_groups):
+    """hit_idx and sign bits implied by the oracle's connected pairs and the
+    input term list (sorted by (X, Z) exactly as the table is)."""
+    pairs = oracle.connected_pairs(w.x, samples)
+    gx = np.unique(w.x, axis=0)
+    order = np.lexsort((gx[:, 0], gx[:, 1]))
+    gx = gx[order]
+    key = {(int(a), int(b)): g for g, (a, b) in enumerate(gx)}
+    n = samples.shape[0]
+    hit = np.full((n, n_groups), -1, np.int32)
+    d = samples[pairs[:, 0]] ^ samples[pairs[:, 1]]
+    for (i, j), (d0, d1) in zip(pairs, d):
+        hit[i, key[(int(d0), int(d1))]] = j
+    # group of each term (terms are sorted by X first)
+    tg = np.array([key[(int(a), int(b))] for a, b in w.x])
+    T = w.x.shape[0]
+    bits = np.zeros((n, T), bool)
+    for i in range(n):
+        groups = np.nonzero(hit[i] >= 0)[0]
+        sel = np.isin(tg, groups)
+        par = (np.bitwise_count(w.z[sel, 0] & samples[i, 0]).astype(int)
+               + np.bitwise_count(w.z[sel, 1] & samples[i, 1]).astype(int)) & 1
+        bits[i, sel] = par.astype(bool)
+    packed = np.packbits(bits, axis=1, bitorder="little")
+    return hit, packed
+
+
+def run_dump(torch, w, samples, la, ph):
+    ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
+    G, T, _ = ham.info()
+    S, la_t, ph_t, _ = upload(torch, samples, la, ph)
+    hit = torch.full((samples.shape[0], G), -7, dtype=torch.int32, device="cuda")
+    bits = torch.zeros((samples.shape[0], (T + 7) // 8), dtype=torch.uint8, device="cuda")
+    e = ham.debug_dump(S, la_t, ph_t, hit, bits)
+    ham.sync()
+    out = (e.cpu().numpy(), hit.cpu().numpy(), bits.cpu().numpy(), G)
+    ham.close()
+    return out
+
+
+def test_cfg0_lookups_and_signs_bit_exact(torch_dev, cfg0):
+    say("cfg0 debug dump: lookups and sign bits")
+    e, hit, bits, G = run_dump(torch_dev, cfg0, cfg0.samples, cfg0.log_amp, cfg0.phase)
+    hit_ref, bits_ref = expected_dump(cfg0, cfg0.samples, G)
+    assert np.array_equal(hit, hit_ref)
+    assert np.array_equal(bits, bits_ref)
+    ref, ab, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples, cfg0.log_amp, cfg0.phase)
+    assert_parity(e, ref, ab)
+
+
+def test_cfg1_reduced_full_parity(torch_dev, workload_cache):
+    w = workload_cache(("config", 1, 4096))
+    say("cfg1 40 qubits, 4096 samples, full parity")
+    e, st = gpu_eloc(torch_dev, w)
+    ref, ab, nc = oracle.eloc(40, w.x, w.z, w.c, w.samples, w.log_amp, w.phase)
+    assert_parity(e, ref, ab)
+    G, T, conn = W.closed_form_counts(20, 10)
+    assert st["pairs"] == 4096 * G and st["probes"] == 4096 * conn
+    assert st["hits"] == int(nc.sum()) - 4096
+
+
+def test_cfg1_full_size(torch_dev, workload_cache):
+    w = workload_cache(("config", 1))
+    say("cfg1 40 qubits, 65536 samples, full oracle")
+    e, st = gpu_eloc(torch_dev, w)
+    ref, ab, nc = oracle.eloc(40, w.x, w.z, w.c, w.samples, w.log_amp, w.phase)
+    assert_parity(e, ref, ab)
+    G, T, conn = W.closed_form_counts(20, 10)
+    assert st["pairs"] == 65536 * G and st["probes"] == 65536 * conn
+    assert st["hits"] == int(nc.sum()) - 65536
+    say(f"cfg1 hits {st['hits']}")
+
+
+def test_cfg2_reduced_full_parity(torch_dev, workload_cache):
+    w = workload_cache(("config", 2, 2048))
+    say("cfg2 100 qubits, 2048 samples, full parity")
+    e, st = gpu_eloc(torch_dev, w)
+    ref, ab, nc = oracle.eloc(100, w.x, w.z, w.c, w.samples, w.log_amp, w.phase)
+    assert_parity(e, ref, ab)
+    assert st["hits"] == int(nc.sum()) - 2048
+
+
+def test_cfg2_full_size_sampled_rows(torch_dev, workload_cache):
+    w = workload_cache(("config", 2))
+    say("cfg2 100 qubits, 262144 samples, 192 sampled rows")
+    e, st = gpu_eloc(torch_dev, w)
+    rows = np.sort(np.random.default_rng(9).choice(w.n_samples, 192, replace=False))
+    rows[0], rows[-1] = 0, w.n_samples - 1
+    ref, ab, _ = oracle.eloc_rows(100, w.x, w.z, w.c, w.samples, w.log_amp, w.phase, rows)
+    assert_parity(e[rows], ref, ab)
+    G = oracle.n_groups(w.x)
+    G_dense, _, conn = W.closed_form_counts(50, 25)
+    assert st["pairs"] == w.n_samples * G
+    # every in-sector flip whose group exists is probed; the few groups whose
+    # merged coefficients fell below the drop threshold are probed by no one
+    assert w.n_samples * (conn - (G_dense - G)) <= st["probes"] <= w.n_samples * conn
+
+
+def _closure(K, n, seed):
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    from test_oracle_pins import closure_set
+    return closure_set(K, n, 2, 150, seed=seed)
+
+
+@pytest.mark.parametrize("K,n,L,cfg", [(20, 10, 4.0, 1), (50, 25, 6.0, 2)])
+def test_closure_sets_hit_heavy(torch_dev, K, n, L, cfg, workload_cache):
+    """Dense hit sets (a few states with all their singles and many doubles),
+    with flips on both sides of the 64-bit word boundary at 100 qubits."""
+    w = workload_cache(("config", cfg, 256))
+    S = _closure(K, n, seed=K)
+    rng = np.random.default_rng(4)
+    la, ph = rng.normal(0, 0.5, S.shape[0]), rng.uniform(0, 2 * math.pi, S.shape[0])
+    say(f"closure set {2 * K} qubits, {S.shape[0]} samples")
+    e, st = gpu_eloc(torch_dev, w, samples=S, la=la, ph=ph,
+                     weights=np.ones(S.shape[0], np.int64))
+    ref, ab, nc = oracle.eloc(2 * K, w.x, w.z, w.c, S, la, ph)
+    assert_parity(e, ref, ab)
+    assert st["hits"] == int(nc.sum()) - S.shape[0]
+    if K == 20:
+        sub = S[:300]
+        e2, hit, bits, G = run_dump(torch_dev, w, sub, la[:300], ph[:300])
+        hit_ref, bits_ref = expected_dump(w, sub, G)
+        assert np.array_equal(hit, hit_ref)
+        assert np.array_equal(bits, bits_ref)
+
+
+@pytest.mark.parametrize("nq", [10, 70])
+def test_general_pauli_sets_without_sector_filter(torch_dev, nq):
+    """Arbitrary X masks (popcount up to ~nq/3), even Y counts, no spin masks."""
+    rng = np.random.default_rng(nq)
+    T = 3000
+    xb = rng.random((T, nq)) < (0.3 if nq == 10 else 0.04)
+    zb = rng.random((T, nq)) < 0.4
+    # make the Y count even by clearing one Z bit where needed
+    for t in range(T):
+        ny = np.sum(xb[t] & zb[t])
+        if ny % 2:
+            k = np.nonzero(xb[t] & zb[t])[0][0]
+            zb[t, k] = False
+    x, z = W.pack_bits(xb), W.pack_bits(zb)
+    c = rng.normal(size=T)
+    n_s = 600 if nq == 10 else 3000
+    if nq == 10:
+        idx = np.sort(rng.choice(1 << nq, n_s, replace=False))
+        S = np.zeros((n_s, 2), np.uint64)
+        S[:, 0] = idx
+    else:
+        sb = rng.random((n_s, nq)) < 0.5
+        S = np.unique(W.pack_bits(sb), axis=0)
+        S = S[rng.permutation(S.shape[0])]
+        # add flips of existing samples by table masks so that hits occur
+        extra = S[:200] ^ x[rng.integers(0, T, 200)]
+        S = np.unique(np.concatenate([S, extra]), axis=0)
+        S = S[rng.permutation(S.shape[0])]
+    la, ph = rng.normal(0, 1, S.shape[0]), rng.uniform(0, 2 * math.pi, S.shape[0])
+    say(f"general Pauli set, {nq} qubits, {S.shape[0]} samples")
+    wl = W.Workload("gen", nq, nq // 2, 0, 0, x, z, c, W.spin_masks(nq), S,
+                    np.ones(S.shape[0], np.int64), la, ph)
+    e, st = gpu_eloc(torch_dev, wl, spin=False)
+    ref, ab, nc = oracle.eloc(nq, x, z, c, S, la, ph)
+    assert_parity(e, ref, ab)
+    has_diag = bool(np.any((x[:, 0] == 0) & (x[:, 1] == 0)))
+    assert st["hits"] == int(nc.sum()) - (S.shape[0] if has_diag else 0)
+
+
+def test_mixed_sectors_switch_the_filter_off(torch_dev, workload_cache):
+    """Samples from two (N_alpha, N_beta) sectors: no flip may be skipped."""
+    w = workload_cache(("config", 0))
+    other = W.sector_states(6, 2, 3)
+    S = np.concatenate([w.samples[:200], other[:150]])
+    rng = np.random.default_rng(8)
+    la, ph = rng.normal(0, 1, S.shape[0]), rng.uniform(0, 2 * math.pi, S.shape[0])
+    say("mixed sectors")
+    e, st = gpu_eloc(torch_dev, w, samples=S, la=la, ph=ph, weights=np.ones(S.shape[0], np.int64))
+    ref, ab, _ = oracle.eloc(12, w.x, w.z, w.c, S, la, ph)
+    assert_parity(e, ref, ab)
+    G, _, _ = W.closed_form_counts(6, 3)
+    assert st["probes"] == S.shape[0] * (G - 1)
+
+
+def test_errors_are_latched_and_reported(torch_dev, cfg0):
+    torch = torch_dev
+    ham = nqs.Hamiltonian(cfg0.x, cfg0.z, cfg0.c, 12, cfg0.spin_masks)
+    n = 50
+    la = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ph = torch.zeros(n, dtype=torch.float64, device="cuda")
+    say("error path: duplicate sample")
+    s = cfg0.samples[:n].copy()
+    s[7] = s[31]
+    S = nqs.to_device_samples(s)
+    ham.eloc(S, la, ph)
+    with pytest.raises(nqs.NQSError) as ex:
+        ham.sync()
+    assert ex.value.code == nqs.NQS_E_DUPLICATE
+    say("error path: bit above n_qubits")
+    s = cfg0.samples[:n].copy()
+    s[3, 0] |= np.uint64(1 << 12)
+    ham.eloc(nqs.to_device_samples(s), la, ph)
+    with pytest.raises(nqs.NQSError) as ex:
+        ham.sync()
+    assert ex.value.code == nqs.NQS_E_RANGE
+    say("error path: negative count")
+    wneg = torch.ones(n, dtype=torch.int64, device="cuda")
+    wneg[5] = -1
+    ham.eloc(nqs.to_device_samples(cfg0.samples[:n]), la, ph, weights=wneg)
+    with pytest.raises(nqs.NQSError) as ex:
+        ham.sync()
+    assert ex.value.code == nqs.NQS_E_RANGE
+    say("error path: recovery")
+    e = ham.eloc(nqs.to_device_samples(cfg0.samples[:n]), la, ph)
+    ham.sync()
+    ref, ab, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples[:n], np.zeros(n), np.zeros(n))
+    assert_parity(e.cpu().numpy(), ref, ab)
+    with pytest.raises(nqs.NQSError) as ex:
+        load = nqs.load_library()
+        import ctypes
+        rc = load.nqs_eloc_eval(ham.handle, n, ctypes.c_void_p(S.data_ptr()), None,
+                                ctypes.c_void_p(la.data_ptr()), ctypes.c_void_p(ph.data_ptr()),
+                                None, 0, None)
+        nqs._check(rc)
+    assert ex.value.code == nqs.NQS_E_ARG
+    ham.sync()
+    ham.close()
+
+
+def test_edge_sizes_determinism_and_permutation(torch_dev, cfg0):
+    torch = torch_dev
+    ham = nqs.Hamiltonian(cfg0.x, cfg0.z, cfg0.c, 12, cfg0.spin_masks)
+    say("edge sizes: n = 0, 1, 257")
+    empty = torch.zeros((0, 2), dtype=torch.int64, device="cuda")
+    z0 = torch.zeros(0, dtype=torch.float64, device="cuda")
+    assert ham.eloc(empty, z0, z0).shape[0] == 0
+    for n in (1, 257):
+        S, la, ph, _ = upload(torch, cfg0.samples[:n], cfg0.log_amp[:n], cfg0.phase[:n])
+        e = ham.eloc(S, la, ph)
+        ham.sync()
+        ref, ab, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples[:n], cfg0.log_amp[:n],
+                                 cfg0.phase[:n])
+        assert_parity(e.cpu().numpy(), ref, ab)
+    say("determinism and permutation")
+    S, la, ph, _ = upload(torch, cfg0.samples, cfg0.log_amp, cfg0.phase)
+    a = ham.eloc(S, la, ph).cpu().numpy()
+    b = ham.eloc(S, la, ph).cpu().numpy()
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    perm = np.random.default_rng(1).permutation(400)
+    Sp, lap, php, _ = upload(torch, cfg0.samples[perm], cfg0.log_amp[perm], cfg0.phase[perm])
+    c = ham.eloc(Sp, lap, php).cpu().numpy()
+    ref, ab, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples, cfg0.log_amp, cfg0.phase)
+    assert_parity(c, ref[perm], ab[perm])
+    ham.sync()
+    ham.close()

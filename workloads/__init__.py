@@ -246,7 +246,18 @@ class Workload:
         return int(self.samples.shape[0])
 
 
+_HAM_CACHE: dict = {}
+
+
 def _hamiltonian(seed_prefix, K: int, L: float):
+    key = (tuple(seed_prefix), K, L)
+    if key not in _HAM_CACHE:
+        _HAM_CACHE.clear()  # keep at most one (the 100-qubit table is ~400 MB)
+        _HAM_CACHE[key] = _make_hamiltonian(seed_prefix, K, L)
+    return _HAM_CACHE[key]
+
+
+def _make_hamiltonian(seed_prefix, K: int, L: float):
     rng = np.random.default_rng(list(seed_prefix) + [0])
     h, eri = integrals(rng, K, L)
     x, z, c = jw_terms(h, eri)
