@@ -81,18 +81,21 @@ int nqs_version(void);
  * count), the phase i^{ny} is folded into the coefficient, equal strings
  * are merged by summing in input order, and the table is grouped by X
  * mask (ascending (X, Z) order; the X = 0 group, if present, is group 0).
- * No threshold is applied.  The copy to the device is asynchronous on
- * hip_stream; the host arrays may be freed when this call returns.
+ * No threshold is applied.  The host arrays may be freed when this call
+ * returns.
  *
  * Errors: NQS_E_ARG (null out or arrays, n_terms < 0, non-finite c,
- * overlapping spin masks), NQS_E_RANGE, NQS_E_NONREAL, NQS_E_NOMEM,
- * NQS_E_DEVICE.  On error *out is set to NULL.
+ * overlapping spin masks, 2^26 or more X groups), NQS_E_RANGE,
+ * NQS_E_NONREAL, NQS_E_NOMEM, NQS_E_DEVICE.  On error *out is set to NULL.
+ * The call returns after the upload has completed.  A spin mask covering
+ * more than 64 qubits leaves the sector filter off.
  */
 int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *x_masks,
                    const uint64_t *z_masks, const double *coeffs, const uint64_t *spin_masks,
                    void *hip_stream);
 
-/* Group count G, merged term count T and device bytes held by the table. */
+/* Group count G, merged term count T and device bytes held by the handle
+ * (table plus scratch). */
 int nqs_ham_info(nqs_ham h, int64_t *n_groups, int64_t *n_terms, int64_t *device_bytes);
 
 /* Release the handle, its device table and its scratch.  Waits for the
@@ -154,12 +157,14 @@ int nqs_sync(nqs_ham h, void *hip_stream);
 
 /*
  * Counters of the last nqs_eloc_eval on this handle (valid after nqs_sync):
- *   out[0] pairs   = n * G (sample, group) pair-evaluations
- *   out[1] probes  = pairs that passed the sector test (lookups)
- *   out[2] hits    = lookups that found x' in S (off-diagonal)
- *   out[3] terms   = Pauli terms evaluated (diagonal group plus hit groups)
+ *   out[0] pairs      = n * G (sample, group) pair-evaluations
+ *   out[1] probes     = pairs that passed the sector test (lookups of x')
+ *   out[2] hits       = lookups that found x' in S (off-diagonal)
+ *   out[3] terms      = Pauli terms evaluated (diagonal group plus hit groups)
+ *   out[4] candidates = lookups that passed the on-chip filter and went to
+ *                       the hash table in device memory
  */
-int nqs_eval_stats(nqs_ham h, int64_t out[4]);
+int nqs_eval_stats(nqs_ham h, int64_t out[5]);
 
 /*
  * Kernel timing.  nqs_profile(h, 1) makes every later nqs_eloc_eval on h
@@ -181,14 +186,14 @@ int nqs_last_kernel_ms(nqs_ham h, float out[3]);
  *   hit_idx  : device [n][G] int32 or NULL.  For group g of sample i: the
  *              index j of x' = x_i ^ X_g in S, or -1 when x' is not in S or
  *              the group failed the sector test; the X = 0 group records i.
- *   sign_bits: device [n][(T + 7) / 8] uint8 or NULL, zero-filled by the
- *              caller.  Bit t is popc(Z_t & x_i) & 1 for every term t the
- *              kernel evaluated for sample i (X = 0 group and hit groups);
- *              other bits stay zero.
+ *   sign_bits: device [n][(T + 31) / 32] uint32 or NULL, zero-filled by the
+ *              caller.  Bit (t % 32) of word (t / 32) is popc(Z_t & x_i) & 1
+ *              for every term t the kernel evaluated for sample i (X = 0
+ *              group and hit groups); other bits stay zero.
  * Other arguments and errors as nqs_eloc_eval (FP64 only).
  */
 int nqs_debug_dump(nqs_ham h, int64_t n, const uint64_t *samples, const double *log_amp,
-                   const double *phase, double *eloc, int32_t *hit_idx, uint8_t *sign_bits,
+                   const double *phase, double *eloc, int32_t *hit_idx, uint32_t *sign_bits,
                    void *hip_stream);
 
 #ifdef __cplusplus

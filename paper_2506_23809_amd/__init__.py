@@ -197,9 +197,10 @@ class Hamiltonian:
         _check(load_library().nqs_sync(self._h, _stream(stream)))
 
     def stats(self):
-        out = (ctypes.c_int64 * 4)()
+        out = (ctypes.c_int64 * 5)()
         _check(load_library().nqs_eval_stats(self._h, out))
-        return {"pairs": out[0], "probes": out[1], "hits": out[2], "terms": out[3]}
+        return {"pairs": out[0], "probes": out[1], "hits": out[2], "terms": out[3],
+                "candidates": out[4]}
 
     def profile(self, enable=True):
         """Record HIP events around each kernel stage of later evaluations."""
@@ -217,7 +218,7 @@ class Hamiltonian:
         n = samples.shape[0]
         out = torch.empty((n, 2), dtype=torch.float64, device=samples.device)
         hp = None if hit_idx is None else _dptr(hit_idx, torch.int32)
-        sp = None if sign_bits is None else _dptr(sign_bits, torch.uint8)
+        sp = None if sign_bits is None else _dptr(sign_bits, torch.int32)
         _check(load_library().nqs_debug_dump(
             self._h, n, _dptr(samples, torch.int64, 2), _dptr(log_amp, torch.float64),
             _dptr(phase, torch.float64), _dptr(out, torch.float64, 2), hp, sp, _stream(stream)))

@@ -32,6 +32,11 @@ int fail_hip(hipError_t e, const char *what) {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+constexpr size_t kSmallBytes = 128;                  // counters, error latch, sector flag
+constexpr size_t kErrOffset = 8 * nqs::kCounters;    // after the counters
+constexpr size_t kMaxFilterWords = size_t(1) << 15;  // 128 KB Bloom bitmap
+constexpr int64_t kMaxGroups = int64_t(1) << 26;     // queue entries pack the group in 26 bits
+
 }  // namespace
 
 struct nqs_ham_s {
@@ -48,7 +53,8 @@ struct nqs_ham_s {
     int64_t shx_cap = 0;
     double *part = nullptr;
     int64_t part_cap = 0;  // doubles
-    void *small = nullptr; // counters[4] u64, err, mixed
+    uint32_t *filter = nullptr;  // Bloom bitmap, kMaxFilterWords words
+    void *small = nullptr; // counters[8] u64, err, mixed
     int64_t last_pairs = 0;
     bool ever_evaluated = false;
     // optional per-stage events: hash start, hash end / lookup start,
@@ -65,9 +71,10 @@ nqs::DevScratch scratch_of(nqs_ham h) {
     s.slots = h->slots;
     s.shx = h->shx;
     s.part = h->part;
+    s.filter = h->filter;
     s.counters = static_cast<unsigned long long *>(h->small);
-    s.err = reinterpret_cast<int *>(static_cast<char *>(h->small) + 32);
-    s.mixed = reinterpret_cast<int *>(static_cast<char *>(h->small) + 36);
+    s.err = reinterpret_cast<int *>(static_cast<char *>(h->small) + kErrOffset);
+    s.mixed = reinterpret_cast<int *>(static_cast<char *>(h->small) + kErrOffset + 4);
     uint32_t cap = h->slot_cap;
     s.slot_mask = cap - 1;
     int lg = 0;
@@ -116,7 +123,7 @@ bool valid_handle(nqs_ham h) { return h && h->table_mem && h->small; }
 
 int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weights,
               const double *log_amp, const double *phase, double *eloc, int precision,
-              int32_t *hit_idx, uint8_t *sign_bits, void *stream) {
+              int32_t *hit_idx, uint32_t *sign_bits, void *stream) {
     if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
     if (n < 0) return fail(NQS_E_ARG, "n < 0");
     if (precision != NQS_FP64 && precision != NQS_FP32_KAHAN)
@@ -130,15 +137,16 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
     const nqs::EvalLaunch L = nqs::plan_eval(h->dt, n, dump);
     int rc = ensure_scratch(h, n, L.n_chunks, st);
     if (rc) return rc;
-    const nqs::DevScratch sc = scratch_of(h);
+    nqs::DevScratch sc = scratch_of(h);
+    sc.filter_log2 = L.filter_log2;
     NQS_HIP(nqs::launch_reset(sc, st));
     if (h->profiling) NQS_HIP(hipEventRecord(h->ev[0], st));
     NQS_HIP(nqs::launch_hash(h->dt, sc, h->slot_cap, samples, weights, n, st));
     if (h->profiling) NQS_HIP(hipEventRecord(h->ev[1], st));
-    const int64_t sign_stride = (h->dt.n_terms + 7) / 8;
+    const int64_t sign_words = (h->dt.n_terms + 31) / 32;
     nqs::EvalStageEvents stages{h->profiling ? h->ev[2] : nullptr};
     NQS_HIP(nqs::launch_eloc(h->dt, sc, L, samples, log_amp, phase, eloc, precision, hit_idx,
-                             sign_bits, sign_stride, stages, st));
+                             sign_bits, sign_words, stages, st));
     if (h->profiling) {
         NQS_HIP(hipEventRecord(h->ev[3], st));
         h->profiled = true;
@@ -201,6 +209,7 @@ int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *
         return fail(NQS_E_NOMEM, "host allocation failed");
     }
     if (rc) return fail(rc, err);
+    if (T.n_groups >= kMaxGroups) return fail(NQS_E_ARG, "more than 2^26 X groups");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
 
     const int64_t G = T.n_groups, Tn = T.n_terms;
@@ -221,10 +230,8 @@ int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *
     };
     Piece pieces[] = {
         {T.gx.data(), sizeof(uint64_t) * T.gx.size(), 0},
-        {T.gxa.data(), sizeof(uint64_t) * T.gxa.size(), 0},
-        {T.gxb.data(), sizeof(uint64_t) * T.gxb.size(), 0},
-        {T.gmeta.data(), sizeof(uint32_t) * T.gmeta.size(), 0},
-        {T.ghx.data(), sizeof(uint32_t) * T.ghx.size(), 0},
+        {T.gsec.data(), sizeof(uint64_t) * T.gsec.size(), 0},
+        {T.ghm.data(), sizeof(uint32_t) * T.ghm.size(), 0},
         {goff32.data(), sizeof(uint32_t) * goff32.size(), 0},
         {T.tz.data(), sizeof(uint64_t) * T.tz.size(), 0},
         {T.tc.data(), sizeof(double) * T.tc.size(), 0},
@@ -247,8 +254,10 @@ int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *
         delete h;
         return fail(NQS_E_NOMEM, "device allocation of the Pauli table failed");
     }
-    if (hipMalloc(&h->small, 64) != hipSuccess) {
+    if (hipMalloc(&h->small, kSmallBytes) != hipSuccess ||
+        hipMalloc(&h->filter, kMaxFilterWords * 4) != hipSuccess) {
         (void)hipFree(h->table_mem);
+        if (h->small) (void)hipFree(h->small);
         delete h;
         return fail(NQS_E_NOMEM, "device allocation failed");
     }
@@ -258,11 +267,12 @@ int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *
         e = hipMemcpyAsync(base + p.off, p.src, p.bytes, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) break;
     }
-    if (e == hipSuccess) e = hipMemsetAsync(h->small, 0, 64, st);
+    if (e == hipSuccess) e = hipMemsetAsync(h->small, 0, kSmallBytes, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         (void)hipFree(h->table_mem);
         (void)hipFree(h->small);
+        (void)hipFree(h->filter);
         delete h;
         return fail_hip(e, "uploading the Pauli table");
     }
@@ -270,20 +280,19 @@ int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *
     h->words = T.words;
     nqs::DevTable &d = h->dt;
     d.gx = reinterpret_cast<const uint64_t *>(base + pieces[0].off);
-    d.gxa = reinterpret_cast<const uint64_t *>(base + pieces[1].off);
-    d.gxb = reinterpret_cast<const uint64_t *>(base + pieces[2].off);
-    d.gmeta = reinterpret_cast<const uint32_t *>(base + pieces[3].off);
-    d.ghx = reinterpret_cast<const uint32_t *>(base + pieces[4].off);
-    d.goff = reinterpret_cast<const uint32_t *>(base + pieces[5].off);
-    d.tz = reinterpret_cast<const uint64_t *>(base + pieces[6].off);
-    d.tc = reinterpret_cast<const double *>(base + pieces[7].off);
-    d.tc32 = reinterpret_cast<const float *>(base + pieces[8].off);
-    d.hr = reinterpret_cast<const uint32_t *>(base + pieces[9].off);
+    d.gsec = reinterpret_cast<const uint64_t *>(base + pieces[1].off);
+    d.ghm = reinterpret_cast<const uint32_t *>(base + pieces[2].off);
+    d.goff = reinterpret_cast<const uint32_t *>(base + pieces[3].off);
+    d.tz = reinterpret_cast<const uint64_t *>(base + pieces[4].off);
+    d.tc = reinterpret_cast<const double *>(base + pieces[5].off);
+    d.tc32 = reinterpret_cast<const float *>(base + pieces[6].off);
+    d.hr = reinterpret_cast<const uint32_t *>(base + pieces[7].off);
     d.n_groups = G;
     d.n_terms = Tn;
     d.n_qubits = n_qubits;
     d.has_diagonal = T.has_diagonal ? 1 : 0;
     d.sector_filter = T.sector_filter ? 1 : 0;
+    d.sector32 = T.sector32 ? 1 : 0;
     d.spin_a0 = T.spin[0][0];
     d.spin_a1 = T.spin[0][1];
     d.spin_b0 = T.spin[1][0];
@@ -298,7 +307,8 @@ int nqs_ham_info(nqs_ham h, int64_t *n_groups, int64_t *n_terms, int64_t *device
     if (n_terms) *n_terms = h->dt.n_terms;
     if (device_bytes)
         *device_bytes = h->table_bytes + static_cast<int64_t>(h->slot_bytes) +
-                        h->shx_cap * 4 + h->part_cap * 8 + 64;
+                        h->shx_cap * 4 + h->part_cap * 8 + kSmallBytes +
+                        static_cast<int64_t>(kMaxFilterWords * 4);
     return NQS_OK;
 }
 
@@ -308,6 +318,7 @@ int nqs_ham_destroy(nqs_ham h) {
     if (hipDeviceSynchronize() != hipSuccess) rc = fail(NQS_E_DEVICE, "synchronising before destroy");
     if (h->table_mem) (void)hipFree(h->table_mem);
     if (h->small) (void)hipFree(h->small);
+    if (h->filter) (void)hipFree(h->filter);
     if (h->slots) (void)hipFree(h->slots);
     if (h->shx) (void)hipFree(h->shx);
     if (h->part) (void)hipFree(h->part);
@@ -346,7 +357,7 @@ int nqs_last_kernel_ms(nqs_ham h, float out[3]) {
 }
 
 int nqs_debug_dump(nqs_ham h, int64_t n, const uint64_t *samples, const double *log_amp,
-                   const double *phase, double *eloc, int32_t *hit_idx, uint8_t *sign_bits,
+                   const double *phase, double *eloc, int32_t *hit_idx, uint32_t *sign_bits,
                    void *hip_stream) {
     if (!hit_idx && !sign_bits) return fail(NQS_E_ARG, "no dump buffer given");
     return eval_impl(h, n, samples, nullptr, log_amp, phase, eloc, NQS_FP64, hit_idx, sign_bits,
@@ -358,11 +369,11 @@ int nqs_sync(nqs_ham h, void *hip_stream) {
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     NQS_HIP(hipStreamSynchronize(st));
     int err = 0;
-    NQS_HIP(hipMemcpy(&err, static_cast<char *>(h->small) + 32, sizeof(int),
+    NQS_HIP(hipMemcpy(&err, static_cast<char *>(h->small) + kErrOffset, sizeof(int),
                       hipMemcpyDeviceToHost));
     if (err != 0) {
         const int zero = 0;
-        NQS_HIP(hipMemcpy(static_cast<char *>(h->small) + 32, &zero, sizeof(int),
+        NQS_HIP(hipMemcpy(static_cast<char *>(h->small) + kErrOffset, &zero, sizeof(int),
                           hipMemcpyHostToDevice));
         switch (err) {
             case NQS_E_DUPLICATE: return fail(err, "a sample occurs more than once in the batch");
@@ -373,16 +384,14 @@ int nqs_sync(nqs_ham h, void *hip_stream) {
     return NQS_OK;
 }
 
-int nqs_eval_stats(nqs_ham h, int64_t out[4]) {
+int nqs_eval_stats(nqs_ham h, int64_t out[5]) {
     if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
     if (!out) return fail(NQS_E_ARG, "null output");
     if (!h->ever_evaluated) return fail(NQS_E_STATE, "no evaluation on this handle yet");
-    unsigned long long c[4];
+    unsigned long long c[nqs::kCounters];
     NQS_HIP(hipMemcpy(c, h->small, sizeof(c), hipMemcpyDeviceToHost));
     out[0] = h->last_pairs;
-    out[1] = static_cast<int64_t>(c[1]);
-    out[2] = static_cast<int64_t>(c[2]);
-    out[3] = static_cast<int64_t>(c[3]);
+    for (int k = 1; k < 5; ++k) out[k] = static_cast<int64_t>(c[k]);
     return NQS_OK;
 }
 

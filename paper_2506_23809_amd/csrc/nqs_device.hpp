@@ -10,10 +10,8 @@ namespace nqs {
 // Resident Pauli table (structure of arrays, all device pointers).
 struct DevTable {
     const uint64_t *gx;    // [G][2] flip masks
-    const uint64_t *gxa;   // [G][2] alpha part of the flip mask
-    const uint64_t *gxb;   // [G][2] beta part of the flip mask
-    const uint32_t *gmeta; // [G] half counts | infeasible bit 16
-    const uint32_t *ghx;   // [G] linear hash of the flip mask
+    const uint64_t *gsec;  // [G][2] flip mask compressed to (alpha bits, beta bits)
+    const uint32_t *ghm;   // [G][2] (linear hash of X, sector key)
     const uint32_t *goff;  // [G + 1] term offsets
     const uint64_t *tz;    // [T][2] Z masks
     const double *tc;      // [T] folded coefficients
@@ -23,23 +21,32 @@ struct DevTable {
     int64_t n_terms;
     int n_qubits;
     int has_diagonal;
-    int sector_filter;
+    int sector_filter;     // compressed sector test available
+    int sector32;          // both compressed widths fit in 32 bits
     uint64_t spin_a0, spin_a1, spin_b0, spin_b1;
 };
+
+// Sector key of a group: (half popcount of its alpha flips) | (half popcount
+// of its beta flips) << 8.  A flip x -> x ^ X keeps (N_alpha, N_beta) iff
+// popc(x & X_alpha) | popc(x & X_beta) << 8 equals the key.  Flips with an
+// odd alpha or beta popcount always leave the sector and get a key no sample
+// can produce.
+constexpr uint32_t kSectorNever = 0xFFFFu;
 
 // Per-handle scratch for one batch.
 struct DevScratch {
     void *slots;            // hash slots (layout depends on the word count)
     uint32_t *shx;          // [n] linear hash of each sample
+    uint32_t *filter;       // [1 << filter_log2 words] Bloom bitmap of sample hashes
     double *part;           // [n_chunks][n][2] partial E_loc per group chunk
-    unsigned long long *counters;  // [4] pairs, probes, hits, terms
+    unsigned long long *counters;  // [8] pairs, probes, hits, terms, candidates
     int *err;               // first device-detected error (0 = none)
     int *mixed;             // set when samples span more than one sector
     uint32_t slot_mask;     // capacity - 1 (capacity is a power of two)
     uint32_t slot_shift;    // 32 - log2(capacity)
+    int filter_log2;        // log2 of the filter size in 32-bit words
 };
 
-constexpr uint32_t kMetaInfeasibleBit = 1u << 16;
 constexpr uint32_t kGoldenMul = 0x9E3779B1u;
 
 // Hash slots.  The claim protocol CASes idx from -1 to the sample index and
@@ -55,16 +62,15 @@ struct alignas(32) Slot2 {
     int32_t pad[3];
 };
 
-}  // namespace nqs
-
-namespace nqs {
-
 // Launch plan of one evaluation: sample tiles x group chunks.
 struct EvalLaunch {
     int64_t n;
     int64_t n_chunks;
     int64_t chunk_len;
     int64_t g_first;
+    int threads;        // lookup kernel block size
+    int filter_log2;    // filter words = 1 << filter_log2
+    size_t lds_bytes;   // dynamic LDS of the lookup kernel
 };
 
 // Optional event recorded between the lookup and the finish kernels.
@@ -79,10 +85,11 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
                        hipStream_t st);
 hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
                        const uint64_t *samples, const double *log_amp, const double *phase,
-                       double *eloc, int precision, int32_t *hit_idx, uint8_t *sign_bits,
-                       int64_t sign_stride, EvalStageEvents ev, hipStream_t st);
+                       double *eloc, int precision, int32_t *hit_idx, uint32_t *sign_bits,
+                       int64_t sign_words, EvalStageEvents ev, hipStream_t st);
 hipError_t launch_energy(const int64_t *w, const double *e, int64_t n, double *part,
                          double *result, double *out, hipStream_t st);
 constexpr int kEnergyPartDoubles = 3 * 256;
+constexpr int kCounters = 8;
 
 }  // namespace nqs

@@ -7,11 +7,21 @@
 // loop over kets runs over the X groups of the Pauli table instead of over
 // determinants: every term of group g connects x to x' = x ^ X_g, so one
 // lookup of x' in the sample hash (the psi lookup table of the sample-space
-// energy) decides the whole group.  The group stream is wave-uniform, so it
-// reaches the lanes through scalar loads.  A lookup hit evaluates
+// energy) decides the whole group.  A hit evaluates
 //   <x|H|x'> = sum_{t in g} c~_t (-1)^{popc(Z_t & x)}
-// with the folded coefficient c~ = c (-1)^{ny/2}, and multiplies it by
-// exp(a' - a) e^{i(phi' - phi)}.
+// with the folded coefficient c~ = c (-1)^{ny/2} (one popcount per term, the
+// parity step of Alg. 3) and multiplies it by exp(a' - a) e^{i(phi' - phi)}.
+//
+// Lookup pipeline of the E_loc kernel, per (sample, group) pair:
+//   1. sector test on compressed alpha/beta bit fields (flips that change
+//      N_alpha or N_beta cannot land in S when all samples share a sector);
+//   2. linear hash: h(x ^ X) = h(x) ^ h(X), one XOR;
+//   3. one bit of an LDS-resident Bloom bitmap of the sample hashes: most
+//      x' not in S stop here without touching global memory;
+//   4. survivors are compacted into a per-wave LDS queue (ballot + mbcnt)
+//      and looked up 64 at a time in the global open-addressing hash.
+// Group records stream through LDS in stages; the filter stays resident for
+// the whole block.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -50,6 +60,26 @@ __device__ __forceinline__ uint32_t linear_hash(const Key<W> &k, const uint32_t 
     return h;
 }
 
+// Bits of x selected by (m0, m1), packed to the low end in mask order.
+template <int W>
+__device__ __forceinline__ uint64_t compress(const Key<W> &x, uint64_t m0, uint64_t m1) {
+    uint64_t r = 0;
+    int k = 0;
+    while (m0) {
+        const int b = __builtin_ctzll(m0);
+        r |= ((x.w[0] >> b) & 1ull) << k++;
+        m0 &= m0 - 1;
+    }
+    if constexpr (W == 2) {
+        while (m1) {
+            const int b = __builtin_ctzll(m1);
+            r |= ((x.w[1] >> b) & 1ull) << k++;
+            m1 &= m1 - 1;
+        }
+    }
+    return r;
+}
+
 __device__ __forceinline__ uint32_t slot_of(uint32_t h, uint32_t shift) {
     return (h * kGoldenMul) >> shift;
 }
@@ -74,7 +104,8 @@ __device__ __forceinline__ bool key_eq(const typename SlotT<W>::type &s, const K
     }
 }
 
-// Index of key in the sample hash, or -1.
+// Index of key in the sample hash, or -1.  One slot is one aligned 16- or
+// 32-byte load holding both the key and its index.
 template <int W>
 __device__ __forceinline__ int32_t hash_find(const typename SlotT<W>::type *__restrict__ slots,
                                              uint32_t mask, uint32_t slot, const Key<W> &k) {
@@ -89,17 +120,44 @@ __device__ __forceinline__ int32_t hash_find(const typename SlotT<W>::type *__re
 
 __device__ __forceinline__ void latch(int *err, int code) { atomicCAS(err, 0, code); }
 
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(u), lane);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(u >> 32), lane);
+    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int lane) {
+    const uint32_t lo = __shfl(static_cast<uint32_t>(v), lane);
+    const uint32_t hi = __shfl(static_cast<uint32_t>(v >> 32), lane);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ double shfl_f64(double v, int lane) {
+    return __longlong_as_double(static_cast<long long>(
+        shfl_u64(static_cast<uint64_t>(__double_as_longlong(v)), lane)));
+}
+
+// Number of set bits of mask below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
 // ------------------------------------------------------------------ hash build
 
+// Clears the slot indices (to -1) and the Bloom bitmap (to 0).
 __global__ void hash_clear_kernel(int32_t *__restrict__ idx_words, int stride_words,
-                                  uint32_t capacity) {
+                                  uint32_t capacity, uint32_t *__restrict__ filter,
+                                  uint32_t filter_words) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < capacity) idx_words[static_cast<size_t>(s) * stride_words] = -1;
+    if (s < filter_words) filter[s] = 0u;
 }
 
 // One thread per sample: range check, sector uniformity, counts >= 0, linear
-// hash, and insertion by CAS on the slot index.  A duplicate key is found
-// by comparing against the sample that owns the slot.
+// hash, Bloom bit, and insertion by CAS on the slot index.  A duplicate key
+// is found by comparing against the sample that owns the slot.
 template <int W>
 __global__ void hash_build_kernel(DevTable tab, DevScratch sc,
                                   const uint64_t *__restrict__ samples,
@@ -108,7 +166,6 @@ __global__ void hash_build_kernel(DevTable tab, DevScratch sc,
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t w0 = samples[2 * i], w1 = samples[2 * i + 1];
-    // bits at or above n_qubits
     bool bad;
     const int nq = tab.n_qubits;
     if (nq >= 64) {
@@ -126,12 +183,14 @@ __global__ void hash_build_kernel(DevTable tab, DevScratch sc,
         const int rb = __popcll(s0 & tab.spin_b0) + __popcll(s1 & tab.spin_b1);
         if (na != ra || nb != rb) atomicOr(sc.mixed, 1);
     }
+    if (bad) return;
     Key<W> k;
     k.w[0] = w0;
     if constexpr (W == 2) k.w[1] = w1;
-    if (W == 1 && w1 != 0) return;  // already latched as out of range
     const uint32_t h = linear_hash<W>(k, tab.hr);
     sc.shx[i] = h;
+    const uint32_t fmask = (1u << sc.filter_log2) - 1u;
+    atomicOr(&sc.filter[(h >> 5) & fmask], 1u << (h & 31));
     S *slots = static_cast<S *>(sc.slots);
     uint32_t slot = slot_of(h, sc.slot_shift);
     for (uint32_t probe = 0; probe <= sc.slot_mask; ++probe) {
@@ -153,12 +212,31 @@ __global__ void hash_build_kernel(DevTable tab, DevScratch sc,
 
 // ------------------------------------------------------------------ E_loc
 
-constexpr int kProbeThreads = 256;
+constexpr int kLookupThreads = 1024;
+constexpr int kStage = 512;      // group records per LDS stage
+constexpr int kQueueCap = 128;   // per-wave candidate queue (flushed at 64)
+
+template <bool S32>
+struct StageRec;
+template <>
+struct alignas(16) StageRec<true> {
+    uint32_t ca, cb, hx, key;
+};
+template <>
+struct alignas(16) StageRec<false> {
+    uint64_t ca, cb;
+    uint32_t hx, key, pad0, pad1;
+};
+
+size_t lookup_lds_bytes(bool s32, int filter_log2, int threads) {
+    const size_t rec = s32 ? sizeof(StageRec<true>) : sizeof(StageRec<false>);
+    return (size_t(4) << filter_log2) + kStage * rec + size_t(threads / 64) * kQueueCap * 4;
+}
 
 // Sum of one group's terms for bra x: sum_t c~_t (-1)^{popc(Z_t & x)}.
 template <int W, bool DUMP>
 __device__ __forceinline__ double group_sum(const DevTable &tab, int64_t g, const Key<W> &x,
-                                            uint8_t *__restrict__ sign_row,
+                                            uint32_t *__restrict__ sign_row,
                                             unsigned long long *terms) {
     const uint32_t t0 = tab.goff[g], t1 = tab.goff[g + 1];
     double s = 0.0;
@@ -169,98 +247,192 @@ __device__ __forceinline__ double group_sum(const DevTable &tab, int64_t g, cons
         const double c = tab.tc[t];
         s += (par & 1) ? -c : c;
         if constexpr (DUMP) {
-            if (par & 1) sign_row[t >> 3] |= static_cast<uint8_t>(1u << (t & 7));
+            if (sign_row && (par & 1)) atomicOr(&sign_row[t >> 5], 1u << (t & 31));
         }
     }
     *terms += t1 - t0;
     return s;
 }
 
-// Grid: (sample tiles of 256) x (group chunks).  Each lane walks the groups of
-// its chunk in order and writes one partial sum, so the result does not
-// depend on scheduling.  The X = 0 group is left to the finish kernel.
-template <int W, bool DUMP>
-__global__ __launch_bounds__(kProbeThreads) void eloc_probe_kernel(
+// Grid: (sample tiles of blockDim) x (group chunks).  Each lane walks the
+// groups of its chunk in order; hits are added to the owning lane in queue
+// order, which is group order, so the partial sums do not depend on
+// scheduling.  The X = 0 group is left to the finish kernel.
+template <int W, bool S32, bool DUMP>
+__global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
     const double *__restrict__ log_amp, const double *__restrict__ phase, int64_t n,
     int64_t g_first, int64_t chunk_len, int32_t *__restrict__ hit_idx,
-    uint8_t *__restrict__ sign_bits, int64_t sign_stride) {
+    uint32_t *__restrict__ sign_bits, int64_t sign_words) {
     using S = typename SlotT<W>::type;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kProbeThreads + threadIdx.x;
+    using Rec = StageRec<S32>;
+    extern __shared__ uint4 smem4[];
+    const int fwords = 1 << sc.filter_log2;
+    uint32_t *filt = reinterpret_cast<uint32_t *>(smem4);
+    Rec *stage = reinterpret_cast<Rec *>(filt + fwords);
+    const int lane = threadIdx.x & 63;
+    uint32_t *queue = reinterpret_cast<uint32_t *>(stage + kStage) + (threadIdx.x >> 6) * kQueueCap;
+
+    const int64_t tile0 = static_cast<int64_t>(blockIdx.x) * blockDim.x;
+    const int64_t wave0 = tile0 + (threadIdx.x & ~63);
+    const int64_t i = tile0 + threadIdx.x;
     const bool active = i < n;
-    const int64_t chunk = blockIdx.y;
-    const int64_t g0 = g_first + chunk * chunk_len;
+    const int64_t g0 = g_first + static_cast<int64_t>(blockIdx.y) * chunk_len;
     const int64_t g1 = min(g0 + chunk_len, tab.n_groups);
-    const bool filter = tab.sector_filter && (*sc.mixed == 0);
+    const bool sector = tab.sector_filter && (*sc.mixed == 0);
     const S *__restrict__ slots = static_cast<const S *>(sc.slots);
+
+    // resident Bloom bitmap
+    {
+        const uint4 *gf = reinterpret_cast<const uint4 *>(sc.filter);
+        for (int k = threadIdx.x; k < (fwords >> 2); k += blockDim.x) smem4[k] = gf[k];
+    }
 
     Key<W> x;
     uint32_t hx = 0;
     double la = 0.0, ph = 0.0;
+    uint64_t xa = 0, xb = 0;
     if (active) {
         x = load_key<W>(samples, i);
         hx = sc.shx[i];
         la = log_amp[i];
         ph = phase[i];
+        if (sector) {
+            xa = compress<W>(x, tab.spin_a0, tab.spin_a1);
+            xb = compress<W>(x, tab.spin_b0, tab.spin_b1);
+        }
     } else {
 #pragma unroll
         for (int q = 0; q < W; ++q) x.w[q] = 0;
     }
-    uint8_t *sign_row = DUMP && active && sign_bits ? sign_bits + i * sign_stride : nullptr;
 
     double acc_re = 0.0, acc_im = 0.0;
-    unsigned long long n_probe = 0, n_hit = 0, n_terms = 0;
-    for (int64_t g = g0; g < g1; ++g) {
-        bool ok = active;
-        if (filter) {
-            int ca = 0, cb = 0;
+    unsigned long long n_probe = 0, n_cand = 0, n_hit = 0, n_terms = 0;
+    uint32_t qn = 0;  // queue length, identical in all lanes of the wave
+
+    // Look up queue entries [0, m): lane k takes entry k; hits go back to
+    // the owning lanes in entry order.
+    auto flush = [&](uint32_t m) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const uint32_t e = lane < static_cast<int>(m) ? queue[lane] : 0u;
+        const int l = static_cast<int>(e & 63u);
+        const int64_t g = g0 + static_cast<int64_t>(e >> 6);
+        Key<W> xl;
 #pragma unroll
-            for (int q = 0; q < W; ++q) {
-                ca += __popcll(x.w[q] & tab.gxa[2 * g + q]);
-                cb += __popcll(x.w[q] & tab.gxb[2 * g + q]);
-            }
-            const uint32_t meta = tab.gmeta[g];
-            ok = ok && ((static_cast<uint32_t>(ca) | (static_cast<uint32_t>(cb) << 8)) ==
-                        (meta & 0xFFFFu)) && !(meta & kMetaInfeasibleBit);
-        }
-        int32_t j = -1;
-        if (ok) {
-            ++n_probe;
+        for (int q = 0; q < W; ++q) xl.w[q] = shfl_u64(x.w[q], l);
+        const uint32_t hxl = __shfl(hx, l);
+        const double lal = shfl_f64(la, l), phl = shfl_f64(ph, l);
+        double cre = 0.0, cim = 0.0;
+        bool hit = false;
+        if (lane < static_cast<int>(m)) {
             Key<W> xp;
 #pragma unroll
-            for (int q = 0; q < W; ++q) xp.w[q] = x.w[q] ^ tab.gx[2 * g + q];
-            const uint32_t h = hx ^ tab.ghx[g];
-            j = hash_find<W>(slots, sc.slot_mask, slot_of(h, sc.slot_shift), xp);
+            for (int q = 0; q < W; ++q) xp.w[q] = xl.w[q] ^ tab.gx[2 * g + q];
+            const uint32_t h = hxl ^ tab.ghm[2 * g];
+            const int32_t j = hash_find<W>(slots, sc.slot_mask, slot_of(h, sc.slot_shift), xp);
+            if constexpr (DUMP) {
+                if (hit_idx) hit_idx[(wave0 + l) * tab.n_groups + g] = j;
+            }
             if (j >= 0) {
+                hit = true;
                 ++n_hit;
-                const double hsum = group_sum<W, DUMP>(tab, g, x, sign_row, &n_terms);
+                uint32_t *row = (DUMP && sign_bits) ? sign_bits + (wave0 + l) * sign_words : nullptr;
+                const double hsum = group_sum<W, DUMP>(tab, g, xl, row, &n_terms);
                 double sn, cs;
-                sincos(phase[j] - ph, &sn, &cs);
-                const double mag = exp(log_amp[j] - la);
-                acc_re += hsum * (mag * cs);
-                acc_im += hsum * (mag * sn);
+                sincos(phase[j] - phl, &sn, &cs);
+                const double mag = exp(log_amp[j] - lal);
+                cre = hsum * (mag * cs);
+                cim = hsum * (mag * sn);
             }
         }
-        if constexpr (DUMP) {
-            if (active && hit_idx) hit_idx[i * tab.n_groups + g] = j;
+        uint64_t hm = __ballot(hit);
+        while (hm) {
+            const int q = __builtin_ctzll(hm);
+            hm &= hm - 1;
+            const int owner = __builtin_amdgcn_readlane(l, q);
+            const double r = readlane_f64(cre, q);
+            const double im = readlane_f64(cim, q);
+            if (lane == owner) {
+                acc_re += r;
+                acc_im += im;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    };
+
+    for (int64_t sg = g0; sg < g1; sg += kStage) {
+        const int cnt = static_cast<int>(min(static_cast<int64_t>(kStage), g1 - sg));
+        __syncthreads();
+        for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+            const int64_t g = sg + k;
+            Rec r;
+            if constexpr (S32) {
+                r.ca = static_cast<uint32_t>(tab.gsec[2 * g]);
+                r.cb = static_cast<uint32_t>(tab.gsec[2 * g + 1]);
+            } else {
+                r.ca = tab.gsec[2 * g];
+                r.cb = tab.gsec[2 * g + 1];
+                r.pad0 = r.pad1 = 0;
+            }
+            r.hx = tab.ghm[2 * g];
+            r.key = tab.ghm[2 * g + 1];
+            stage[k] = r;
+        }
+        __syncthreads();
+        for (int k = 0; k < cnt; ++k) {
+            const Rec r = stage[k];
+            bool ins = active;
+            if (sector) {
+                uint32_t ca, cb;
+                if constexpr (S32) {
+                    ca = __popc(static_cast<uint32_t>(xa) & r.ca);
+                    cb = __popc(static_cast<uint32_t>(xb) & r.cb);
+                } else {
+                    ca = __popcll(xa & r.ca);
+                    cb = __popcll(xb & r.cb);
+                }
+                ins = ins && ((ca | (cb << 8)) == r.key);
+            }
+            const uint32_t h = hx ^ r.hx;
+            const uint32_t fw = filt[(h >> 5) & (fwords - 1)];
+            const bool cand = ins && ((fw >> (h & 31)) & 1u);
+            n_probe += ins;
+            n_cand += cand;
+            if constexpr (DUMP) {
+                if (active && !cand && hit_idx) hit_idx[i * tab.n_groups + sg + k] = -1;
+            }
+            const uint64_t cm = __ballot(cand);
+            if (cm) {
+                if (cand) queue[qn + lanes_below(cm)] = (static_cast<uint32_t>(sg + k - g0) << 6) |
+                                                        static_cast<uint32_t>(lane);
+                qn += static_cast<uint32_t>(__popcll(cm));
+                if (qn >= 64) {
+                    flush(64);
+                    qn -= 64;
+                    if (lane < static_cast<int>(qn)) queue[lane] = queue[64 + lane];
+                }
+            }
         }
     }
+    if (qn > 0) flush(qn);
+
     if (active) {
-        double *p = sc.part + 2 * (chunk * n + i);
+        double *p = sc.part + 2 * (static_cast<int64_t>(blockIdx.y) * n + i);
         p[0] = acc_re;
         p[1] = acc_im;
     }
-    // counters: one atomic per wave
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         n_probe += __shfl_xor(n_probe, off);
+        n_cand += __shfl_xor(n_cand, off);
         n_hit += __shfl_xor(n_hit, off);
         n_terms += __shfl_xor(n_terms, off);
     }
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         atomicAdd(&sc.counters[1], n_probe);
         atomicAdd(&sc.counters[2], n_hit);
         atomicAdd(&sc.counters[3], n_terms);
+        atomicAdd(&sc.counters[4], n_cand);
     }
 }
 
@@ -269,15 +441,15 @@ template <int W, bool DUMP>
 __global__ __launch_bounds__(256) void eloc_finish_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n,
     int64_t n_chunks, double *__restrict__ eloc, int32_t *__restrict__ hit_idx,
-    uint8_t *__restrict__ sign_bits, int64_t sign_stride) {
+    uint32_t *__restrict__ sign_bits, int64_t sign_words) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     unsigned long long n_terms = 0;
     if (i < n) {
         const Key<W> x = load_key<W>(samples, i);
         double re = 0.0, im = 0.0;
         if (tab.has_diagonal) {
-            uint8_t *sign_row = DUMP && sign_bits ? sign_bits + i * sign_stride : nullptr;
-            re = group_sum<W, DUMP>(tab, 0, x, sign_row, &n_terms);
+            uint32_t *row = (DUMP && sign_bits) ? sign_bits + i * sign_words : nullptr;
+            re = group_sum<W, DUMP>(tab, 0, x, row, &n_terms);
             if constexpr (DUMP) {
                 if (hit_idx) hit_idx[i * tab.n_groups] = static_cast<int32_t>(i);
             }
@@ -394,7 +566,7 @@ __global__ __launch_bounds__(kRedThreads) void energy_var_kernel(const double *_
 // ------------------------------------------------------------------ launchers
 
 __global__ void reset_kernel(unsigned long long *counters, int *mixed) {
-    if (threadIdx.x < 4) counters[threadIdx.x] = 0;
+    if (threadIdx.x < kCounters) counters[threadIdx.x] = 0;
     if (threadIdx.x == 0) *mixed = 0;
 }
 
@@ -406,13 +578,19 @@ hipError_t launch_reset(const DevScratch &sc, hipStream_t st) {
 EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump) {
     EvalLaunch L;
     L.n = n;
+    L.threads = kLookupThreads;
+    // Bloom bitmap: about 16 bits per sample, 512 B .. 128 KB
+    int lg = 7;
+    while (lg < 15 && (int64_t(1) << (lg + 5)) < 16 * n) ++lg;
+    L.filter_log2 = lg;
+    L.lds_bytes = lookup_lds_bytes(tab.sector32 != 0, lg, L.threads);
     L.g_first = tab.has_diagonal ? 1 : 0;
     const int64_t g_eff = tab.n_groups - L.g_first;
-    const int64_t tiles = (n + kProbeThreads - 1) / kProbeThreads;
+    const int64_t tiles = (n + L.threads - 1) / L.threads;
     int64_t chunks = 1;
     if (!dump && g_eff > 0) {
-        const int64_t want = (2048 + tiles - 1) / tiles;
-        const int64_t max_chunks = (g_eff + 255) / 256;
+        const int64_t want = (1024 + tiles - 1) / tiles;  // ~4 blocks per CU
+        const int64_t max_chunks = (g_eff + kStage - 1) / kStage;
         chunks = want < max_chunks ? want : max_chunks;
         if (chunks < 1) chunks = 1;
         if (chunks > 65535) chunks = 65535;
@@ -430,8 +608,10 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
     int32_t *idx0 = reinterpret_cast<int32_t *>(static_cast<char *>(sc.slots) +
                                                 (words == 1 ? offsetof(Slot1, idx)
                                                             : offsetof(Slot2, idx)));
-    hipLaunchKernelGGL(hash_clear_kernel, dim3((capacity + 255) / 256), dim3(256), 0, st, idx0,
-                       stride, capacity);
+    const uint32_t fwords = 1u << sc.filter_log2;
+    const uint32_t span = capacity > fwords ? capacity : fwords;
+    hipLaunchKernelGGL(hash_clear_kernel, dim3((span + 255) / 256), dim3(256), 0, st, idx0,
+                       stride, capacity, sc.filter, fwords);
     const dim3 grid(static_cast<unsigned>((n + 255) / 256));
     if (words == 1)
         hipLaunchKernelGGL(hash_build_kernel<1>, grid, dim3(256), 0, st, tab, sc, samples, weights, n);
@@ -440,37 +620,59 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
     return hipGetLastError();
 }
 
+template <int W, bool S32, bool D>
+hipError_t launch_lookup(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
+                         const uint64_t *samples, const double *log_amp, const double *phase,
+                         int32_t *hit_idx, uint32_t *sign_bits, int64_t sign_words,
+                         hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&eloc_lookup_kernel<W, S32, D>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const dim3 grid(static_cast<unsigned>((L.n + L.threads - 1) / L.threads),
+                    static_cast<unsigned>(L.n_chunks));
+    hipLaunchKernelGGL((eloc_lookup_kernel<W, S32, D>), grid, dim3(L.threads), L.lds_bytes, st,
+                       tab, sc, samples, log_amp, phase, L.n, L.g_first, L.chunk_len, hit_idx,
+                       sign_bits, sign_words);
+    return hipGetLastError();
+}
+
 hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
                        const uint64_t *samples, const double *log_amp, const double *phase,
-                       double *eloc, int precision, int32_t *hit_idx, uint8_t *sign_bits,
-                       int64_t sign_stride, EvalStageEvents ev, hipStream_t st) {
+                       double *eloc, int precision, int32_t *hit_idx, uint32_t *sign_bits,
+                       int64_t sign_words, EvalStageEvents ev, hipStream_t st) {
     (void)precision;
     const int words = tab.n_qubits <= 63 ? 1 : 2;
     const bool dump = hit_idx || sign_bits;
+    const bool s32 = tab.sector32 != 0;
     const int64_t n = L.n;
-    const dim3 pgrid(static_cast<unsigned>((n + kProbeThreads - 1) / kProbeThreads),
-                     static_cast<unsigned>(L.n_chunks));
-    const dim3 fgrid(static_cast<unsigned>((n + 255) / 256));
+    hipError_t e = hipSuccess;
     if (L.chunk_len > 0) {
-#define NQS_PROBE(Wd, D)                                                                       \
-    hipLaunchKernelGGL((eloc_probe_kernel<Wd, D>), pgrid, dim3(kProbeThreads), 0, st, tab, sc, \
-                       samples, log_amp, phase, n, L.g_first, L.chunk_len, hit_idx, sign_bits,  \
-                       sign_stride)
+#define NQS_LOOKUP(Wd, S, D) \
+    e = launch_lookup<Wd, S, D>(tab, sc, L, samples, log_amp, phase, hit_idx, sign_bits, sign_words, st)
         if (words == 1) {
-            if (dump) NQS_PROBE(1, true); else NQS_PROBE(1, false);
+            if (s32) { if (dump) NQS_LOOKUP(1, true, true); else NQS_LOOKUP(1, true, false); }
+            else { if (dump) NQS_LOOKUP(1, false, true); else NQS_LOOKUP(1, false, false); }
         } else {
-            if (dump) NQS_PROBE(2, true); else NQS_PROBE(2, false);
+            if (s32) { if (dump) NQS_LOOKUP(2, true, true); else NQS_LOOKUP(2, true, false); }
+            else { if (dump) NQS_LOOKUP(2, false, true); else NQS_LOOKUP(2, false, false); }
         }
-#undef NQS_PROBE
+#undef NQS_LOOKUP
+        if (e != hipSuccess) return e;
     }
     if (ev.after_lookup) {
-        const hipError_t e = hipEventRecord(ev.after_lookup, st);
+        e = hipEventRecord(ev.after_lookup, st);
         if (e != hipSuccess) return e;
     }
     const int64_t chunks = L.chunk_len > 0 ? L.n_chunks : 0;
+    const dim3 fgrid(static_cast<unsigned>((n + 255) / 256));
 #define NQS_FINISH(Wd, D)                                                                        \
     hipLaunchKernelGGL((eloc_finish_kernel<Wd, D>), fgrid, dim3(256), 0, st, tab, sc, samples, n, \
-                       chunks, eloc, hit_idx, sign_bits, sign_stride)
+                       chunks, eloc, hit_idx, sign_bits, sign_words)
     if (words == 1) {
         if (dump) NQS_FINISH(1, true); else NQS_FINISH(1, false);
     } else {

@@ -41,6 +41,22 @@ uint64_t splitmix64(uint64_t *s) {
 
 }  // namespace
 
+uint64_t compress_bits(uint64_t w0, uint64_t w1, uint64_t m0, uint64_t m1) {
+    uint64_t r = 0;
+    int k = 0;
+    while (m0) {
+        const int b = __builtin_ctzll(m0);
+        r |= ((w0 >> b) & 1ull) << k++;
+        m0 &= m0 - 1;
+    }
+    while (m1) {
+        const int b = __builtin_ctzll(m1);
+        r |= ((w1 >> b) & 1ull) << k++;
+        m1 &= m1 - 1;
+    }
+    return r;
+}
+
 LinearHash::LinearHash() {
     uint64_t s = 0x6e71735f68617368ull;  // fixed seed: tables are reproducible
     for (int j = 0; j < 128; ++j) r[j] = static_cast<uint32_t>(splitmix64(&s) >> 32);
@@ -87,7 +103,11 @@ int build_table(int n_qubits, int64_t n_terms, const uint64_t *x, const uint64_t
             return NQS_E_ARG;
         }
         bool a = T.spin[0][0] | T.spin[0][1], b = T.spin[1][0] | T.spin[1][1];
-        T.sector_filter = a && b;
+        const int wa = popc2(T.spin[0][0], T.spin[0][1]);
+        const int wb = popc2(T.spin[1][0], T.spin[1][1]);
+        // the compressed sector test works on one 64-bit word per spin
+        T.sector_filter = a && b && wa <= 64 && wb <= 64;
+        T.sector32 = T.sector_filter && wa <= 32 && wb <= 32;
         if (!(a || b)) {
             T.spin[0][0] = T.spin[0][1] = T.spin[1][0] = T.spin[1][1] = 0;
         } else if (!(a && b)) {
@@ -154,22 +174,19 @@ int build_table(int n_qubits, int64_t n_terms, const uint64_t *x, const uint64_t
     T.goff.push_back(T.n_terms);
     T.has_diagonal = T.n_groups > 0 && T.gx[0] == 0 && T.gx[1] == 0;
 
-    T.gxa.resize(2 * T.n_groups);
-    T.gxb.resize(2 * T.n_groups);
-    T.gmeta.resize(T.n_groups);
-    T.ghx.resize(T.n_groups);
+    T.gsec.resize(2 * T.n_groups);
+    T.ghm.resize(2 * T.n_groups);
     for (int64_t g = 0; g < T.n_groups; ++g) {
         const uint64_t x0 = T.gx[2 * g], x1 = T.gx[2 * g + 1];
-        T.gxa[2 * g] = x0 & T.spin[0][0];
-        T.gxa[2 * g + 1] = x1 & T.spin[0][1];
-        T.gxb[2 * g] = x0 & T.spin[1][0];
-        T.gxb[2 * g + 1] = x1 & T.spin[1][1];
-        const int pa = popc2(T.gxa[2 * g], T.gxa[2 * g + 1]);
-        const int pb = popc2(T.gxb[2 * g], T.gxb[2 * g + 1]);
-        uint32_t meta = static_cast<uint32_t>(pa / 2) | (static_cast<uint32_t>(pb / 2) << 8);
-        if ((pa & 1) || (pb & 1)) meta |= kMetaInfeasible;
-        T.gmeta[g] = meta;
-        T.ghx[g] = lh(x0, x1);
+        const uint64_t a0 = x0 & T.spin[0][0], a1 = x1 & T.spin[0][1];
+        const uint64_t b0 = x0 & T.spin[1][0], b1 = x1 & T.spin[1][1];
+        const int pa = popc2(a0, a1), pb = popc2(b0, b1);
+        T.gsec[2 * g] = T.sector_filter ? compress_bits(x0, x1, T.spin[0][0], T.spin[0][1]) : 0;
+        T.gsec[2 * g + 1] = T.sector_filter ? compress_bits(x0, x1, T.spin[1][0], T.spin[1][1]) : 0;
+        uint32_t key = static_cast<uint32_t>(pa / 2) | (static_cast<uint32_t>(pb / 2) << 8);
+        if ((pa & 1) || (pb & 1)) key = kSectorNeverKey;
+        T.ghm[2 * g] = lh(x0, x1);
+        T.ghm[2 * g + 1] = key;
         T.max_group_terms =
             std::max(T.max_group_terms, static_cast<int>(T.goff[g + 1] - T.goff[g]));
     }

@@ -25,14 +25,14 @@ struct HostTable {
     int64_t n_groups = 0;
     int64_t n_terms = 0;
     bool has_diagonal = false;     // group 0 has X = 0
-    bool sector_filter = false;    // spin masks given and non-zero
+    bool sector_filter = false;    // spin masks given, non-zero, each at most 64 qubits
+    bool sector32 = false;         // both spin masks hold at most 32 qubits
     uint64_t spin[2][2] = {{0, 0}, {0, 0}};
     // groups, ascending by X
     std::vector<uint64_t> gx;      // [G][2] flip mask
-    std::vector<uint64_t> gxa;     // [G][2] flip mask restricted to alpha qubits
-    std::vector<uint64_t> gxb;     // [G][2] flip mask restricted to beta qubits
-    std::vector<uint32_t> gmeta;   // [G] half counts and feasibility (see kMeta*)
-    std::vector<uint32_t> ghx;     // [G] linear hash of X
+    std::vector<uint64_t> gsec;    // [G][2] alpha flips and beta flips, each compressed
+                                   // to consecutive bits (order of the spin mask)
+    std::vector<uint32_t> ghm;     // [G][2] (linear hash of X, sector key)
     std::vector<int64_t> goff;     // [G + 1]
     // merged terms, ascending by (X, Z)
     std::vector<uint64_t> tz;      // [T][2]
@@ -40,10 +40,13 @@ struct HostTable {
     int max_group_terms = 0;
 };
 
-// gmeta layout: bits 0..7 half of popc(X & alpha), bits 8..15 half of
-// popc(X & beta), bit 16 set when either popcount is odd (the flip always
-// leaves the sector).
-constexpr uint32_t kMetaInfeasible = 1u << 16;
+// Sector key: half of popc(X & alpha) | half of popc(X & beta) << 8, or
+// kSectorNeverKey when either popcount is odd (the flip always leaves the
+// sector).
+constexpr uint32_t kSectorNeverKey = 0xFFFFu;
+
+// Bits of w selected by mask, packed to the low end in mask order.
+uint64_t compress_bits(uint64_t w0, uint64_t w1, uint64_t m0, uint64_t m1);
 
 // Returns 0 or a negative NQS_E_* code with *err describing it.
 int build_table(int n_qubits, int64_t n_terms, const uint64_t *x, const uint64_t *z,

@@ -130,8 +130,11 @@ def expected_dump(w, samples, n_groups):
         par = (np.bitwise_count(w.z[sel, 0] & samples[i, 0]).astype(int)
                + np.bitwise_count(w.z[sel, 1] & samples[i, 1]).astype(int)) & 1
         bits[i, sel] = par.astype(bool)
-    packed = np.packbits(bits, axis=1, bitorder="little")
-    return hit, packed
+    words = (T + 31) // 32
+    padded = np.zeros((n, 32 * words), bool)
+    padded[:, :T] = bits
+    packed = np.packbits(padded, axis=1, bitorder="little")
+    return hit, np.ascontiguousarray(packed).view("<i4")
 
 
 def run_dump(torch, w, samples, la, ph):
@@ -139,7 +142,7 @@ def run_dump(torch, w, samples, la, ph):
     G, T, _ = ham.info()
     S, la_t, ph_t, _ = upload(torch, samples, la, ph)
     hit = torch.full((samples.shape[0], G), -7, dtype=torch.int32, device="cuda")
-    bits = torch.zeros((samples.shape[0], (T + 7) // 8), dtype=torch.uint8, device="cuda")
+    bits = torch.zeros((samples.shape[0], (T + 31) // 32), dtype=torch.int32, device="cuda")
     e = ham.debug_dump(S, la_t, ph_t, hit, bits)
     ham.sync()
     out = (e.cpu().numpy(), hit.cpu().numpy(), bits.cpu().numpy(), G)
