@@ -16,8 +16,9 @@
 //   1. sector test on compressed alpha/beta bit fields (flips that change
 //      N_alpha or N_beta cannot land in S when all samples share a sector);
 //   2. linear hash: h(x ^ X) = h(x) ^ h(X), one XOR;
-//   3. one bit of an LDS-resident Bloom bitmap of the sample hashes: most
-//      x' not in S stop here without touching global memory;
+//   3. two bits of one word of an LDS-resident blocked Bloom bitmap of the
+//      sample hashes: most x' not in S stop here without touching global
+//      memory;
 //   4. survivors are compacted into a per-wave LDS queue (ballot + mbcnt)
 //      and looked up 64 at a time in the global open-addressing hash.
 // Group records stream through LDS in stages; the filter stays resident for
@@ -25,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/nqs.h"
 #include "nqs_device.hpp"
@@ -190,7 +192,7 @@ __global__ void hash_build_kernel(DevTable tab, DevScratch sc,
     const uint32_t h = linear_hash<W>(k, tab.hr);
     sc.shx[i] = h;
     const uint32_t fmask = (1u << sc.filter_log2) - 1u;
-    atomicOr(&sc.filter[(h >> 5) & fmask], 1u << (h & 31));
+    atomicOr(&sc.filter[(h >> 5) & fmask], (1u << (h & 31)) | (1u << (h >> 27)));
     S *slots = static_cast<S *>(sc.slots);
     uint32_t slot = slot_of(h, sc.slot_shift);
     for (uint32_t probe = 0; probe <= sc.slot_mask; ++probe) {
@@ -213,8 +215,11 @@ __global__ void hash_build_kernel(DevTable tab, DevScratch sc,
 // ------------------------------------------------------------------ E_loc
 
 constexpr int kLookupThreads = 1024;
-constexpr int kStage = 512;      // group records per LDS stage
+constexpr int kStage = 512;      // group records per LDS stage (multiple of kUnroll)
 constexpr int kQueueCap = 128;   // per-wave candidate queue (flushed at 64)
+constexpr int kUnroll = 4;       // groups tested per inner iteration
+constexpr uint32_t kPadKey = 0xFFFFFFFFu;  // stage padding: never a candidate
+static_assert(kStage % kUnroll == 0, "stage must hold whole unrolled iterations");
 
 template <bool S32>
 struct StageRec;
@@ -258,7 +263,7 @@ __device__ __forceinline__ double group_sum(const DevTable &tab, int64_t g, cons
 // groups of its chunk in order; hits are added to the owning lane in queue
 // order, which is group order, so the partial sums do not depend on
 // scheduling.  The X = 0 group is left to the finish kernel.
-template <int W, bool S32, bool DUMP>
+template <int W, bool S32, bool SEC, bool DUMP>
 __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
     const double *__restrict__ log_amp, const double *__restrict__ phase, int64_t n,
@@ -279,7 +284,6 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
     const bool active = i < n;
     const int64_t g0 = g_first + static_cast<int64_t>(blockIdx.y) * chunk_len;
     const int64_t g1 = min(g0 + chunk_len, tab.n_groups);
-    const bool sector = tab.sector_filter && (*sc.mixed == 0);
     const S *__restrict__ slots = static_cast<const S *>(sc.slots);
 
     // resident Bloom bitmap
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
         hx = sc.shx[i];
         la = log_amp[i];
         ph = phase[i];
-        if (sector) {
+        if (SEC && *sc.mixed == 0) {
             xa = compress<W>(x, tab.spin_a0, tab.spin_a1);
             xb = compress<W>(x, tab.spin_b0, tab.spin_b1);
         }
@@ -307,8 +311,11 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
     }
 
     double acc_re = 0.0, acc_im = 0.0;
-    unsigned long long n_probe = 0, n_cand = 0, n_hit = 0, n_terms = 0;
+    unsigned long long n_hit = 0, n_terms = 0;      // per lane
+    unsigned long long w_probe = 0, w_cand = 0;     // per wave (identical in all lanes)
     uint32_t qn = 0;  // queue length, identical in all lanes of the wave
+    const uint32_t fmask = static_cast<uint32_t>(fwords - 1);
+    const uint64_t amask = __ballot(active);  // lanes that own a sample
 
     // Look up queue entries [0, m): lane k takes entry k; hits go back to
     // the owning lanes in entry order.
@@ -360,59 +367,103 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     };
 
-    for (int64_t sg = g0; sg < g1; sg += kStage) {
-        const int cnt = static_cast<int>(min(static_cast<int64_t>(kStage), g1 - sg));
-        __syncthreads();
-        for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-            const int64_t g = sg + k;
-            Rec r;
-            if constexpr (S32) {
-                r.ca = static_cast<uint32_t>(tab.gsec[2 * g]);
-                r.cb = static_cast<uint32_t>(tab.gsec[2 * g + 1]);
-            } else {
-                r.ca = tab.gsec[2 * g];
-                r.cb = tab.gsec[2 * g + 1];
-                r.pad0 = r.pad1 = 0;
-            }
-            r.hx = tab.ghm[2 * g];
-            r.key = tab.ghm[2 * g + 1];
-            stage[k] = r;
-        }
-        __syncthreads();
-        for (int k = 0; k < cnt; ++k) {
-            const Rec r = stage[k];
-            bool ins = active;
-            if (sector) {
-                uint32_t ca, cb;
-                if constexpr (S32) {
-                    ca = __popc(static_cast<uint32_t>(xa) & r.ca);
-                    cb = __popc(static_cast<uint32_t>(xb) & r.cb);
+    // The sector test applies only when every sample of the batch has the
+    // same (N_alpha, N_beta); the hash build reports that in *sc.mixed.
+    auto run = [&](auto sec_c) {
+        constexpr bool SECV = decltype(sec_c)::value;
+        for (int64_t sg = g0; sg < g1; sg += kStage) {
+            const int cnt = static_cast<int>(min(static_cast<int64_t>(kStage), g1 - sg));
+            const int cnt_pad = (cnt + kUnroll - 1) / kUnroll * kUnroll;
+            __syncthreads();
+            for (int k = threadIdx.x; k < cnt_pad; k += blockDim.x) {
+                const int64_t g = sg + k;
+                Rec r;
+                if (k < cnt) {
+                    if constexpr (S32) {
+                        r.ca = static_cast<uint32_t>(tab.gsec[2 * g]);
+                        r.cb = static_cast<uint32_t>(tab.gsec[2 * g + 1]);
+                    } else {
+                        r.ca = tab.gsec[2 * g];
+                        r.cb = tab.gsec[2 * g + 1];
+                        r.pad0 = r.pad1 = 0;
+                    }
+                    r.hx = tab.ghm[2 * g];
+                    r.key = tab.ghm[2 * g + 1];
                 } else {
-                    ca = __popcll(xa & r.ca);
-                    cb = __popcll(xb & r.cb);
+                    r.ca = 0;
+                    r.cb = 0;
+                    if constexpr (!S32) r.pad0 = r.pad1 = 0;
+                    r.hx = 0;
+                    r.key = kPadKey;
                 }
-                ins = ins && ((ca | (cb << 8)) == r.key);
+                stage[k] = r;
             }
-            const uint32_t h = hx ^ r.hx;
-            const uint32_t fw = filt[(h >> 5) & (fwords - 1)];
-            const bool cand = ins && ((fw >> (h & 31)) & 1u);
-            n_probe += ins;
-            n_cand += cand;
-            if constexpr (DUMP) {
-                if (active && !cand && hit_idx) hit_idx[i * tab.n_groups + sg + k] = -1;
-            }
-            const uint64_t cm = __ballot(cand);
-            if (cm) {
-                if (cand) queue[qn + lanes_below(cm)] = (static_cast<uint32_t>(sg + k - g0) << 6) |
-                                                        static_cast<uint32_t>(lane);
-                qn += static_cast<uint32_t>(__popcll(cm));
-                if (qn >= 64) {
-                    flush(64);
-                    qn -= 64;
-                    if (lane < static_cast<int>(qn)) queue[lane] = queue[64 + lane];
+            __syncthreads();
+            for (int k = 0; k < cnt_pad; k += kUnroll) {
+                // phase 1: the records of kUnroll groups (wave-uniform LDS reads)
+                Rec r[kUnroll];
+    #pragma unroll
+                for (int u = 0; u < kUnroll; ++u) r[u] = stage[k + u];
+                // phase 2: filter words of the flipped samples
+                uint32_t h[kUnroll], fw[kUnroll];
+    #pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    h[u] = hx ^ r[u].hx;
+                    fw[u] = filt[(h[u] >> 5) & fmask];
+                }
+                // phase 3: sector test and filter bits
+                uint64_t ins_m[kUnroll], cand_m[kUnroll];
+    #pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    bool ins;
+                    if constexpr (SECV) {
+                        uint32_t ca, cb;
+                        if constexpr (S32) {
+                            ca = __popc(static_cast<uint32_t>(xa) & r[u].ca);
+                            cb = __popc(static_cast<uint32_t>(xb) & r[u].cb);
+                        } else {
+                            ca = __popcll(xa & r[u].ca);
+                            cb = __popcll(xb & r[u].cb);
+                        }
+                        ins = (ca | (cb << 8)) == r[u].key;
+                    } else {
+                        ins = r[u].key != kPadKey;
+                    }
+                    const bool bits = ((fw[u] >> (h[u] & 31)) & (fw[u] >> (h[u] >> 27)) & 1u) != 0u;
+                    ins_m[u] = __ballot(ins) & amask;
+                    cand_m[u] = __ballot(ins && bits) & amask;
+                }
+    #pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    w_probe += static_cast<unsigned long long>(__popcll(ins_m[u]));
+                    const uint64_t cm = cand_m[u];
+                    if constexpr (DUMP) {
+                        if (active && !((cm >> lane) & 1ull) && hit_idx && k + u < cnt)
+                            hit_idx[i * tab.n_groups + sg + k + u] = -1;
+                    }
+                    if (cm) {
+                        w_cand += static_cast<unsigned long long>(__popcll(cm));
+                        if ((cm >> lane) & 1ull)
+                            queue[qn + lanes_below(cm)] =
+                                (static_cast<uint32_t>(sg + k + u - g0) << 6) | static_cast<uint32_t>(lane);
+                        qn += static_cast<uint32_t>(__popcll(cm));
+                        if (qn >= 64) {
+                            flush(64);
+                            qn -= 64;
+                            if (lane < static_cast<int>(qn)) queue[lane] = queue[64 + lane];
+                        }
+                    }
                 }
             }
         }
+    };
+    if constexpr (SEC) {
+        if (*sc.mixed == 0)
+            run(std::true_type{});
+        else
+            run(std::false_type{});
+    } else {
+        run(std::false_type{});
     }
     if (qn > 0) flush(qn);
 
@@ -423,16 +474,14 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        n_probe += __shfl_xor(n_probe, off);
-        n_cand += __shfl_xor(n_cand, off);
         n_hit += __shfl_xor(n_hit, off);
         n_terms += __shfl_xor(n_terms, off);
     }
     if (lane == 0) {
-        atomicAdd(&sc.counters[1], n_probe);
+        atomicAdd(&sc.counters[1], w_probe);
         atomicAdd(&sc.counters[2], n_hit);
         atomicAdd(&sc.counters[3], n_terms);
-        atomicAdd(&sc.counters[4], n_cand);
+        atomicAdd(&sc.counters[4], w_cand);
     }
 }
 
@@ -620,7 +669,7 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
     return hipGetLastError();
 }
 
-template <int W, bool S32, bool D>
+template <int W, bool S32, bool SEC, bool D>
 hipError_t launch_lookup(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
                          const uint64_t *samples, const double *log_amp, const double *phase,
                          int32_t *hit_idx, uint32_t *sign_bits, int64_t sign_words,
@@ -628,14 +677,14 @@ hipError_t launch_lookup(const DevTable &tab, const DevScratch &sc, const EvalLa
     static bool attr_set = false;
     if (!attr_set) {
         const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&eloc_lookup_kernel<W, S32, D>),
+            reinterpret_cast<const void *>(&eloc_lookup_kernel<W, S32, SEC, D>),
             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const dim3 grid(static_cast<unsigned>((L.n + L.threads - 1) / L.threads),
                     static_cast<unsigned>(L.n_chunks));
-    hipLaunchKernelGGL((eloc_lookup_kernel<W, S32, D>), grid, dim3(L.threads), L.lds_bytes, st,
+    hipLaunchKernelGGL((eloc_lookup_kernel<W, S32, SEC, D>), grid, dim3(L.threads), L.lds_bytes, st,
                        tab, sc, samples, log_amp, phase, L.n, L.g_first, L.chunk_len, hit_idx,
                        sign_bits, sign_words);
     return hipGetLastError();
@@ -652,15 +701,24 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
     const int64_t n = L.n;
     hipError_t e = hipSuccess;
     if (L.chunk_len > 0) {
-#define NQS_LOOKUP(Wd, S, D) \
-    e = launch_lookup<Wd, S, D>(tab, sc, L, samples, log_amp, phase, hit_idx, sign_bits, sign_words, st)
+#define NQS_LOOKUP(Wd, S, SE, D)                                                             \
+    e = launch_lookup<Wd, S, SE, D>(tab, sc, L, samples, log_amp, phase, hit_idx, sign_bits, \
+                                    sign_words, st)
+#define NQS_LOOKUP_D(Wd, S, SE) \
+    if (dump) NQS_LOOKUP(Wd, S, SE, true); else NQS_LOOKUP(Wd, S, SE, false)
+        // the sector test needs spin masks (and, checked on the device, one
+        // (N_alpha, N_beta) over the batch)
+        const bool sec = tab.sector_filter != 0;
         if (words == 1) {
-            if (s32) { if (dump) NQS_LOOKUP(1, true, true); else NQS_LOOKUP(1, true, false); }
-            else { if (dump) NQS_LOOKUP(1, false, true); else NQS_LOOKUP(1, false, false); }
+            if (!sec) { NQS_LOOKUP_D(1, true, false); }
+            else if (s32) { NQS_LOOKUP_D(1, true, true); }
+            else { NQS_LOOKUP_D(1, false, true); }
         } else {
-            if (s32) { if (dump) NQS_LOOKUP(2, true, true); else NQS_LOOKUP(2, true, false); }
-            else { if (dump) NQS_LOOKUP(2, false, true); else NQS_LOOKUP(2, false, false); }
+            if (!sec) { NQS_LOOKUP_D(2, true, false); }
+            else if (s32) { NQS_LOOKUP_D(2, true, true); }
+            else { NQS_LOOKUP_D(2, false, true); }
         }
+#undef NQS_LOOKUP_D
 #undef NQS_LOOKUP
         if (e != hipSuccess) return e;
     }

@@ -25,8 +25,8 @@ def workload_cache():
         if key not in _CACHE:
             if fn is not None:
                 _CACHE[key] = fn()
-            elif isinstance(key, tuple) and key[0] == "config":
-                _CACHE[key] = workloads.config(*key[1:])
+            elif isinstance(key, tuple) and key[0] == "workload":
+                _CACHE[key] = workloads.workload(*key[1:])
             else:
                 raise KeyError(key)
         return _CACHE[key]

@@ -71,36 +71,36 @@ def assert_parity(e_gpu, e_orc, absum, tol=TOL):
 
 
 @pytest.fixture(scope="module")
-def cfg0(workload_cache):
-    return workload_cache(("config", 0))
+def nq12(workload_cache):
+    return workload_cache(("workload", "nq12"))
 
 
-def test_cfg0_random_psi(torch_dev, cfg0):
-    say("cfg0 random psi, 12 qubits, 400 samples")
-    e, st = gpu_eloc(torch_dev, cfg0)
-    ref, ab, nc = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples, cfg0.log_amp, cfg0.phase)
+def test_nq12_random_psi(torch_dev, nq12):
+    say("nq12 random psi, 12 qubits, 400 samples")
+    e, st = gpu_eloc(torch_dev, nq12)
+    ref, ab, nc = oracle.eloc(12, nq12.x, nq12.z, nq12.c, nq12.samples, nq12.log_amp, nq12.phase)
     assert_parity(e, ref, ab)
     G, T, conn = W.closed_form_counts(6, 3)
     assert st["pairs"] == 400 * G
     assert st["probes"] == 400 * conn
     assert st["hits"] == 400 * conn == int(nc.sum()) - 400
     # energy (Eq. 1)
-    m_ref, v_ref, sw_ref = oracle.energy(cfg0.weights, ref)
-    S, la, ph, wt = upload(torch_dev, cfg0.samples, cfg0.log_amp, cfg0.phase, cfg0.weights)
+    m_ref, v_ref, sw_ref = oracle.energy(nq12.weights, ref)
+    S, la, ph, wt = upload(torch_dev, nq12.samples, nq12.log_amp, nq12.phase, nq12.weights)
     et = torch_dev.from_numpy(np.stack([e.real, e.imag], 1).copy()).cuda()
     m, v, sw = nqs.energy(wt, et)
-    scale = float(np.sum(cfg0.weights * np.abs(ref)) / np.sum(cfg0.weights))
+    scale = float(np.sum(nq12.weights * np.abs(ref)) / np.sum(nq12.weights))
     assert sw == sw_ref == 400
     assert abs(m - m_ref) <= 1e-12 * scale
     assert abs(v - v_ref) <= 1e-12 * scale * scale
 
 
-def test_cfg0_ground_eigenvector(torch_dev, cfg0):
-    say("cfg0 exact ground eigenvector")
-    E0, v, _ = dense.sector_ground_state(cfg0.h, cfg0.eri, cfg0.samples)
+def test_nq12_ground_eigenvector(torch_dev, nq12):
+    say("nq12 exact ground eigenvector")
+    E0, v, _ = dense.sector_ground_state(nq12.h, nq12.eri, nq12.samples)
     la = np.log(np.abs(v))
     ph = np.where(v < 0, math.pi, 0.0)
-    e, _ = gpu_eloc(torch_dev, cfg0, la=la, ph=ph, weights=np.ones(400, np.int64))
+    e, _ = gpu_eloc(torch_dev, nq12, la=la, ph=ph, weights=np.ones(400, np.int64))
     keep = np.abs(v) >= 1e-4 * np.abs(v).max()
     assert np.abs(e[keep] - E0).max() <= 1e-10
     amp = np.abs(v).max() / np.abs(v[~keep])
@@ -150,19 +150,19 @@ def run_dump(torch, w, samples, la, ph):
     return out
 
 
-def test_cfg0_lookups_and_signs_bit_exact(torch_dev, cfg0):
-    say("cfg0 debug dump: lookups and sign bits")
-    e, hit, bits, G = run_dump(torch_dev, cfg0, cfg0.samples, cfg0.log_amp, cfg0.phase)
-    hit_ref, bits_ref = expected_dump(cfg0, cfg0.samples, G)
+def test_nq12_lookups_and_signs_bit_exact(torch_dev, nq12):
+    say("nq12 debug dump: lookups and sign bits")
+    e, hit, bits, G = run_dump(torch_dev, nq12, nq12.samples, nq12.log_amp, nq12.phase)
+    hit_ref, bits_ref = expected_dump(nq12, nq12.samples, G)
     assert np.array_equal(hit, hit_ref)
     assert np.array_equal(bits, bits_ref)
-    ref, ab, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples, cfg0.log_amp, cfg0.phase)
+    ref, ab, _ = oracle.eloc(12, nq12.x, nq12.z, nq12.c, nq12.samples, nq12.log_amp, nq12.phase)
     assert_parity(e, ref, ab)
 
 
-def test_cfg1_reduced_full_parity(torch_dev, workload_cache):
-    w = workload_cache(("config", 1, 4096))
-    say("cfg1 40 qubits, 4096 samples, full parity")
+def test_nq40_reduced_full_parity(torch_dev, workload_cache):
+    w = workload_cache(("workload", "nq40", 4096))
+    say("nq40 40 qubits, 4096 samples, full parity")
     e, st = gpu_eloc(torch_dev, w)
     ref, ab, nc = oracle.eloc(40, w.x, w.z, w.c, w.samples, w.log_amp, w.phase)
     assert_parity(e, ref, ab)
@@ -171,30 +171,30 @@ def test_cfg1_reduced_full_parity(torch_dev, workload_cache):
     assert st["hits"] == int(nc.sum()) - 4096
 
 
-def test_cfg1_full_size(torch_dev, workload_cache):
-    w = workload_cache(("config", 1))
-    say("cfg1 40 qubits, 65536 samples, full oracle")
+def test_nq40_full_size(torch_dev, workload_cache):
+    w = workload_cache(("workload", "nq40"))
+    say("nq40 40 qubits, 65536 samples, full oracle")
     e, st = gpu_eloc(torch_dev, w)
     ref, ab, nc = oracle.eloc(40, w.x, w.z, w.c, w.samples, w.log_amp, w.phase)
     assert_parity(e, ref, ab)
     G, T, conn = W.closed_form_counts(20, 10)
     assert st["pairs"] == 65536 * G and st["probes"] == 65536 * conn
     assert st["hits"] == int(nc.sum()) - 65536
-    say(f"cfg1 hits {st['hits']}")
+    say(f"nq40 hits {st['hits']}")
 
 
-def test_cfg2_reduced_full_parity(torch_dev, workload_cache):
-    w = workload_cache(("config", 2, 2048))
-    say("cfg2 100 qubits, 2048 samples, full parity")
+def test_nq100_reduced_full_parity(torch_dev, workload_cache):
+    w = workload_cache(("workload", "nq100", 2048))
+    say("nq100 100 qubits, 2048 samples, full parity")
     e, st = gpu_eloc(torch_dev, w)
     ref, ab, nc = oracle.eloc(100, w.x, w.z, w.c, w.samples, w.log_amp, w.phase)
     assert_parity(e, ref, ab)
     assert st["hits"] == int(nc.sum()) - 2048
 
 
-def test_cfg2_full_size_sampled_rows(torch_dev, workload_cache):
-    w = workload_cache(("config", 2))
-    say("cfg2 100 qubits, 262144 samples, 192 sampled rows")
+def test_nq100_full_size_sampled_rows(torch_dev, workload_cache):
+    w = workload_cache(("workload", "nq100"))
+    say("nq100 100 qubits, 262144 samples, 192 sampled rows")
     e, st = gpu_eloc(torch_dev, w)
     rows = np.sort(np.random.default_rng(9).choice(w.n_samples, 192, replace=False))
     rows[0], rows[-1] = 0, w.n_samples - 1
@@ -214,11 +214,11 @@ def _closure(K, n, seed):
     return closure_set(K, n, 2, 150, seed=seed)
 
 
-@pytest.mark.parametrize("K,n,L,cfg", [(20, 10, 4.0, 1), (50, 25, 6.0, 2)])
-def test_closure_sets_hit_heavy(torch_dev, K, n, L, cfg, workload_cache):
+@pytest.mark.parametrize("K,n,L,name", [(20, 10, 4.0, "nq40"), (50, 25, 6.0, "nq100")])
+def test_closure_sets_hit_heavy(torch_dev, K, n, L, name, workload_cache):
     """Dense hit sets (a few states with all their singles and many doubles),
     with flips on both sides of the 64-bit word boundary at 100 qubits."""
-    w = workload_cache(("config", cfg, 256))
+    w = workload_cache(("workload", name, 256))
     S = _closure(K, n, seed=K)
     rng = np.random.default_rng(4)
     la, ph = rng.normal(0, 0.5, S.shape[0]), rng.uniform(0, 2 * math.pi, S.shape[0])
@@ -277,7 +277,7 @@ def test_general_pauli_sets_without_sector_filter(torch_dev, nq):
 
 def test_mixed_sectors_switch_the_filter_off(torch_dev, workload_cache):
     """Samples from two (N_alpha, N_beta) sectors: no flip may be skipped."""
-    w = workload_cache(("config", 0))
+    w = workload_cache(("workload", "nq12"))
     other = W.sector_states(6, 2, 3)
     S = np.concatenate([w.samples[:200], other[:150]])
     rng = np.random.default_rng(8)
@@ -290,14 +290,14 @@ def test_mixed_sectors_switch_the_filter_off(torch_dev, workload_cache):
     assert st["probes"] == S.shape[0] * (G - 1)
 
 
-def test_errors_are_latched_and_reported(torch_dev, cfg0):
+def test_errors_are_latched_and_reported(torch_dev, nq12):
     torch = torch_dev
-    ham = nqs.Hamiltonian(cfg0.x, cfg0.z, cfg0.c, 12, cfg0.spin_masks)
+    ham = nqs.Hamiltonian(nq12.x, nq12.z, nq12.c, 12, nq12.spin_masks)
     n = 50
     la = torch.zeros(n, dtype=torch.float64, device="cuda")
     ph = torch.zeros(n, dtype=torch.float64, device="cuda")
     say("error path: duplicate sample")
-    s = cfg0.samples[:n].copy()
+    s = nq12.samples[:n].copy()
     s[7] = s[31]
     S = nqs.to_device_samples(s)
     ham.eloc(S, la, ph)
@@ -305,7 +305,7 @@ def test_errors_are_latched_and_reported(torch_dev, cfg0):
         ham.sync()
     assert ex.value.code == nqs.NQS_E_DUPLICATE
     say("error path: bit above n_qubits")
-    s = cfg0.samples[:n].copy()
+    s = nq12.samples[:n].copy()
     s[3, 0] |= np.uint64(1 << 12)
     ham.eloc(nqs.to_device_samples(s), la, ph)
     with pytest.raises(nqs.NQSError) as ex:
@@ -314,14 +314,14 @@ def test_errors_are_latched_and_reported(torch_dev, cfg0):
     say("error path: negative count")
     wneg = torch.ones(n, dtype=torch.int64, device="cuda")
     wneg[5] = -1
-    ham.eloc(nqs.to_device_samples(cfg0.samples[:n]), la, ph, weights=wneg)
+    ham.eloc(nqs.to_device_samples(nq12.samples[:n]), la, ph, weights=wneg)
     with pytest.raises(nqs.NQSError) as ex:
         ham.sync()
     assert ex.value.code == nqs.NQS_E_RANGE
     say("error path: recovery")
-    e = ham.eloc(nqs.to_device_samples(cfg0.samples[:n]), la, ph)
+    e = ham.eloc(nqs.to_device_samples(nq12.samples[:n]), la, ph)
     ham.sync()
-    ref, ab, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples[:n], np.zeros(n), np.zeros(n))
+    ref, ab, _ = oracle.eloc(12, nq12.x, nq12.z, nq12.c, nq12.samples[:n], np.zeros(n), np.zeros(n))
     assert_parity(e.cpu().numpy(), ref, ab)
     with pytest.raises(nqs.NQSError) as ex:
         load = nqs.load_library()
@@ -335,29 +335,29 @@ def test_errors_are_latched_and_reported(torch_dev, cfg0):
     ham.close()
 
 
-def test_edge_sizes_determinism_and_permutation(torch_dev, cfg0):
+def test_edge_sizes_determinism_and_permutation(torch_dev, nq12):
     torch = torch_dev
-    ham = nqs.Hamiltonian(cfg0.x, cfg0.z, cfg0.c, 12, cfg0.spin_masks)
+    ham = nqs.Hamiltonian(nq12.x, nq12.z, nq12.c, 12, nq12.spin_masks)
     say("edge sizes: n = 0, 1, 257")
     empty = torch.zeros((0, 2), dtype=torch.int64, device="cuda")
     z0 = torch.zeros(0, dtype=torch.float64, device="cuda")
     assert ham.eloc(empty, z0, z0).shape[0] == 0
     for n in (1, 257):
-        S, la, ph, _ = upload(torch, cfg0.samples[:n], cfg0.log_amp[:n], cfg0.phase[:n])
+        S, la, ph, _ = upload(torch, nq12.samples[:n], nq12.log_amp[:n], nq12.phase[:n])
         e = ham.eloc(S, la, ph)
         ham.sync()
-        ref, ab, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples[:n], cfg0.log_amp[:n],
-                                 cfg0.phase[:n])
+        ref, ab, _ = oracle.eloc(12, nq12.x, nq12.z, nq12.c, nq12.samples[:n], nq12.log_amp[:n],
+                                 nq12.phase[:n])
         assert_parity(e.cpu().numpy(), ref, ab)
     say("determinism and permutation")
-    S, la, ph, _ = upload(torch, cfg0.samples, cfg0.log_amp, cfg0.phase)
+    S, la, ph, _ = upload(torch, nq12.samples, nq12.log_amp, nq12.phase)
     a = ham.eloc(S, la, ph).cpu().numpy()
     b = ham.eloc(S, la, ph).cpu().numpy()
     assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
     perm = np.random.default_rng(1).permutation(400)
-    Sp, lap, php, _ = upload(torch, cfg0.samples[perm], cfg0.log_amp[perm], cfg0.phase[perm])
+    Sp, lap, php, _ = upload(torch, nq12.samples[perm], nq12.log_amp[perm], nq12.phase[perm])
     c = ham.eloc(Sp, lap, php).cpu().numpy()
-    ref, ab, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples, cfg0.log_amp, cfg0.phase)
+    ref, ab, _ = oracle.eloc(12, nq12.x, nq12.z, nq12.c, nq12.samples, nq12.log_amp, nq12.phase)
     assert_parity(c, ref[perm], ab[perm])
     ham.sync()
     ham.close()

@@ -30,9 +30,9 @@ def _ny(x, z):
                      for (a, a2), (b, b2) in zip(x, z)])
 
 
-@pytest.mark.parametrize("cfg", [0, 1])
-def test_table_groups_and_folds(cfg, workload_cache):
-    w = workload_cache(("config", cfg))
+@pytest.mark.parametrize("name", ["nq12", "nq40"])
+def test_table_groups_and_folds(name, workload_cache):
+    w = workload_cache(("workload", name))
     gx, go, tz, tc = nqs.table_host(w.n_qubits, w.x, w.z, w.c)
     G, T, _ = W.closed_form_counts(w.K, w.n_alpha)
     assert gx.shape[0] == G == oracle.n_groups(w.x)

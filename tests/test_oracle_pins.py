@@ -120,43 +120,43 @@ def test_hubbard_dimer_spectrum_golden():
 
 
 @pytest.fixture(scope="module")
-def cfg0(workload_cache):
-    return workload_cache(("config", 0))
+def nq12(workload_cache):
+    return workload_cache(("workload", "nq12"))
 
 
 @pytest.fixture(scope="module")
-def cfg0_dense(cfg0):
-    idx = [int(s[0]) for s in cfg0.samples]
-    Hp = dense.pauli_matrix(12, cfg0.x, cfg0.z, cfg0.c)
+def nq12_dense(nq12):
+    idx = [int(s[0]) for s in nq12.samples]
+    Hp = dense.pauli_matrix(12, nq12.x, nq12.z, nq12.c)
     return Hp[idx][:, idx].toarray()
 
 
-def test_oracle_equals_dense_on_random_subsets(cfg0, cfg0_dense):
+def test_oracle_equals_dense_on_random_subsets(nq12, nq12_dense):
     """E_loc(x) = (H_SS psi_S)_x / psi_x for random S inside the sector (Eq. 5, LUT semantics)."""
     rng = np.random.default_rng(11)
     for size in (1, 7, 64, 250, 400):
         sel = np.sort(rng.choice(400, size=size, replace=False))
-        S = cfg0.samples[sel]
+        S = nq12.samples[sel]
         la, ph = _random_psi(rng, size)
-        el, ab, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, S, la, ph)
-        ref = _dense_eloc(cfg0_dense[np.ix_(sel, sel)], la, ph)
+        el, ab, _ = oracle.eloc(12, nq12.x, nq12.z, nq12.c, S, la, ph)
+        ref = _dense_eloc(nq12_dense[np.ix_(sel, sel)], la, ph)
         assert np.all(np.abs(el - ref) <= 1e-12 * ab + 1e-300)
 
 
-def test_oracle_equals_fock_matrix_from_integrals(cfg0):
+def test_oracle_equals_fock_matrix_from_integrals(nq12):
     """Same check with H built from the integrals by Eq. 2, not from the Pauli table."""
-    Hf = dense.fock_matrix(cfg0.h, cfg0.eri, _ints(cfg0.samples))
-    el, ab, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples, cfg0.log_amp, cfg0.phase)
-    ref = _dense_eloc(Hf, cfg0.log_amp, cfg0.phase)
+    Hf = dense.fock_matrix(nq12.h, nq12.eri, _ints(nq12.samples))
+    el, ab, _ = oracle.eloc(12, nq12.x, nq12.z, nq12.c, nq12.samples, nq12.log_amp, nq12.phase)
+    ref = _dense_eloc(Hf, nq12.log_amp, nq12.phase)
     assert np.all(np.abs(el - ref) <= 1e-12 * ab)
 
 
-def test_oracle_ground_eigenvector_gives_constant_eloc(cfg0):
+def test_oracle_ground_eigenvector_gives_constant_eloc(nq12):
     """With psi the exact sector ground state, E_loc == E0 (zero-variance principle)."""
-    E0, v, _ = dense.sector_ground_state(cfg0.h, cfg0.eri, cfg0.samples)
+    E0, v, _ = dense.sector_ground_state(nq12.h, nq12.eri, nq12.samples)
     la = np.log(np.abs(v))
     ph = np.where(v < 0, math.pi, 0.0)
-    el, _, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples, la, ph)
+    el, _, _ = oracle.eloc(12, nq12.x, nq12.z, nq12.c, nq12.samples, la, ph)
     keep = np.abs(v) >= 1e-4 * np.abs(v).max()
     print(f"excluded small components: {(~keep).sum()} of {keep.size}")
     assert np.abs(el[keep] - E0).max() <= 1e-10
@@ -169,36 +169,36 @@ def test_oracle_ground_eigenvector_gives_constant_eloc(cfg0):
     assert var < 1e-18
 
 
-def test_oracle_unit_psi_gives_row_sums(cfg0, cfg0_dense):
+def test_oracle_unit_psi_gives_row_sums(nq12, nq12_dense):
     """psi == 1 over the whole sector: E_loc is the row sum of H, mean is 1'H1/|S|."""
-    n = cfg0.n_samples
-    el, _, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples, np.zeros(n), np.zeros(n))
-    rows = cfg0_dense.sum(axis=1)
+    n = nq12.n_samples
+    el, _, _ = oracle.eloc(12, nq12.x, nq12.z, nq12.c, nq12.samples, np.zeros(n), np.zeros(n))
+    rows = nq12_dense.sum(axis=1)
     assert np.abs(el - rows).max() < 1e-12
     mean, _, _ = oracle.energy(np.ones(n, np.int64), el)
-    assert abs(mean - cfg0_dense.sum() / n) < 1e-12
+    assert abs(mean - nq12_dense.sum() / n) < 1e-12
 
 
-def test_oracle_connected_count_closed_form(cfg0):
+def test_oracle_connected_count_closed_form(nq12):
     """Every sample connects to all in-sector single/double flips plus itself."""
     _, _, conn = W.closed_form_counts(6, 3)
-    _, _, nc = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, cfg0.samples, cfg0.log_amp, cfg0.phase)
+    _, _, nc = oracle.eloc(12, nq12.x, nq12.z, nq12.c, nq12.samples, nq12.log_amp, nq12.phase)
     assert (nc == conn + 1).all()
-    pairs = oracle.connected_pairs(cfg0.x, cfg0.samples)
+    pairs = oracle.connected_pairs(nq12.x, nq12.samples)
     assert pairs.shape[0] == 400 * (conn + 1)
 
 
-def test_oracle_hermitian_and_permutation(cfg0):
+def test_oracle_hermitian_and_permutation(nq12):
     """<x|H|x'> = conj(<x'|H|x>); permuting S permutes E_loc."""
-    pairs = oracle.connected_pairs(cfg0.x, cfg0.samples)
-    S = cfg0.samples
-    a = oracle.hij(cfg0.x, cfg0.z, cfg0.c, S[pairs[:, 0]], S[pairs[:, 1]])
-    b = oracle.hij(cfg0.x, cfg0.z, cfg0.c, S[pairs[:, 1]], S[pairs[:, 0]])
+    pairs = oracle.connected_pairs(nq12.x, nq12.samples)
+    S = nq12.samples
+    a = oracle.hij(nq12.x, nq12.z, nq12.c, S[pairs[:, 0]], S[pairs[:, 1]])
+    b = oracle.hij(nq12.x, nq12.z, nq12.c, S[pairs[:, 1]], S[pairs[:, 0]])
     assert np.abs(a - np.conj(b)).max() < 1e-13
     perm = np.random.default_rng(3).permutation(400)
-    el, _, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, S, cfg0.log_amp, cfg0.phase)
-    elp, _, _ = oracle.eloc(12, cfg0.x, cfg0.z, cfg0.c, S[perm], cfg0.log_amp[perm],
-                            cfg0.phase[perm])
+    el, _, _ = oracle.eloc(12, nq12.x, nq12.z, nq12.c, S, nq12.log_amp, nq12.phase)
+    elp, _, _ = oracle.eloc(12, nq12.x, nq12.z, nq12.c, S[perm], nq12.log_amp[perm],
+                            nq12.phase[perm])
     assert np.abs(elp - el[perm]).max() < 1e-12 * np.abs(el).max()
 
 

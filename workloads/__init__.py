@@ -13,9 +13,10 @@ Conventions
   Sec. II-A).  Qubit j is bit j % 64 of word j // 64; a set bit is occupied.
 * A Pauli term is (x, z, c) with P = i^{popc(x & z)} X^x Z^z, x and z packed
   as two uint64 words (lo word = qubits 0..63).
-* Seeds: numpy PCG64 ``default_rng([cfg, stream])`` with stream 0 integrals,
-  1 samples, 2 weights, 3 log-amplitudes, 4 phases; Hamiltonian j of a
-  batched family uses ``[cfg, 100 + j, stream]``.
+* Seeds: numpy PCG64 ``default_rng(prefix + [stream])`` with stream 0
+  integrals, 1 samples, 2 weights, 3 log-amplitudes, 4 phases; each named
+  workload has its own prefix, and Hamiltonian j of a batched family uses
+  the prefix ``[seed, 100 + j]``.
 """
 from __future__ import annotations
 
@@ -286,41 +287,46 @@ def molecule(seed_prefix, K: int, na: int, nb: int, n_samples: int, L: float = 4
                     phase=ph, h=h, eri=eri)
 
 
-def config(i: int, n_samples: int | None = None) -> Workload:
-    """The named workloads.
+WORKLOADS = ("nq12", "nq40", "nq100")
 
-    0: 12 qubits (6 orbitals, 3a+3b), all 400 sector states, weight 1,
-       log|psi| ~ N(0,1), phase ~ U[0, 2pi).
-    1: 40 qubits (20 orbitals, 10a+10b), 65,536 unique samples, geometric
-       weights, log|psi| ~ N(0,2).
-    2: 100 qubits (50 orbitals, 25a+25b), decay length 6, 262,144 samples.
-    n_samples overrides the sample count (a prefix-free redraw with the same
-    seeds), used for reduced test sizes.
+
+def workload(name: str, n_samples: int | None = None) -> Workload:
+    """The named molecule-shaped workloads.
+
+    nq12:  12 qubits (6 orbitals, 3a+3b), all 400 sector states, weight 1,
+           log|psi| ~ N(0,1), phase ~ U[0, 2pi); seed prefix [0].
+    nq40:  40 qubits (20 orbitals, 10a+10b), 65,536 unique samples,
+           geometric weights, log|psi| ~ N(0,2); seed prefix [1].
+    nq100: 100 qubits (50 orbitals, 25a+25b), decay length 6, 262,144
+           samples; seed prefix [2].
+    n_samples overrides the sample count (the same seeds, fewer draws),
+    used for reduced test sizes.
     """
-    if i == 0:
-        return molecule([0], 6, 3, 3, 400, L=4.0, log_sigma=1.0, name="cfg0-nq12",
+    if name == "nq12":
+        return molecule([0], 6, 3, 3, 400, L=4.0, log_sigma=1.0, name="nq12-all400",
                         all_states=True, unit_weights=True)
-    if i == 1:
-        return molecule([1], 20, 10, 10, n_samples or 65536, L=4.0, log_sigma=2.0,
-                        name="cfg1-nq40")
-    if i == 2:
-        return molecule([2], 50, 25, 25, n_samples or 262144, L=6.0, log_sigma=2.0,
-                        name="cfg2-nq100")
-    raise ValueError(f"unknown config {i}")
+    if name == "nq40":
+        n = n_samples or 65536
+        return molecule([1], 20, 10, 10, n, L=4.0, log_sigma=2.0, name=f"nq40-{n}")
+    if name == "nq100":
+        n = n_samples or 262144
+        return molecule([2], 50, 25, 25, n, L=6.0, log_sigma=2.0, name=f"nq100-{n}")
+    raise ValueError(f"unknown workload {name!r}; expected one of {WORKLOADS}")
 
 
-def batched_family(j: int, cfg: int = 3) -> Workload:
+def batched_family(j: int, seed: int = 3) -> Workload:
     """Hamiltonian j of the batched family: N_q drawn from {24, 28, ..., 80}
-    at half filling, sample count log-uniform in [1e3, 2e5]."""
-    rng = np.random.default_rng([cfg, 100 + j, 5])
+    at half filling, sample count log-uniform in [1e3, 2e5]; seed prefix
+    [seed, 100 + j]."""
+    rng = np.random.default_rng([seed, 100 + j, 5])
     nq = int(rng.choice(np.arange(24, 81, 4)))
     ns = int(round(math.exp(rng.uniform(math.log(1e3), math.log(2e5)))))
     K = nq // 2
     n = K // 2
     sector = math.comb(K, n) ** 2
     ns = min(ns, sector // 2)
-    return molecule([cfg, 100 + j], K, n, K - n, ns, L=4.0, log_sigma=2.0,
-                    name=f"fam{cfg}-{j}-nq{nq}")
+    return molecule([seed, 100 + j], K, n, K - n, ns, L=4.0, log_sigma=2.0,
+                    name=f"family{seed}-{j}-nq{nq}-{ns}")
 
 
 # ---------------------------------------------------------------- counting
