@@ -259,11 +259,71 @@ __device__ __forceinline__ double group_sum(const DevTable &tab, int64_t g, cons
     return s;
 }
 
+// ---- FP32 form with compensation (precision NQS_FP32_KAHAN)
+//
+// Coefficients are stored as FP32 pairs hi + lo (lo = c - hi rounded), the
+// sign (-1)^{popc(Z & x)} is applied by flipping sign bits, the hi parts
+// are added with Knuth's error-free TwoSum and the lo parts and the TwoSum
+// errors go into a compensation term; a product H * r keeps its rounding
+// error through fma.  The per-sample value s + c is widened to FP64 only
+// when it leaves the lane.
+
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+    s = a + b;
+    const float bp = s - a;
+    e = (a - (s - bp)) + (b - bp);
+}
+
+__device__ __forceinline__ float flip_sign(float v, int par) {
+    return __uint_as_float(__float_as_uint(v) ^ (static_cast<uint32_t>(par & 1) << 31));
+}
+
+struct AccF32 {
+    float s = 0.f, c = 0.f;
+    __device__ __forceinline__ void add(float v, float err) {
+        float t, e;
+        two_sum(s, v, t, e);
+        s = t;
+        c += e + err;
+    }
+    __device__ __forceinline__ double value() const {
+        return static_cast<double>(s) + static_cast<double>(c);
+    }
+};
+
+template <int W>
+__device__ __forceinline__ AccF32 group_sum_f32(const DevTable &tab, int64_t g, const Key<W> &x,
+                                                unsigned long long *terms) {
+    const uint32_t t0 = tab.goff[g], t1 = tab.goff[g + 1];
+    AccF32 a;
+    for (uint32_t t = t0; t < t1; ++t) {
+        int par = 0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) par += __popcll(tab.tz[2 * static_cast<size_t>(t) + q] & x.w[q]);
+        a.add(flip_sign(tab.tc32[2 * static_cast<size_t>(t)], par),
+              flip_sign(tab.tc32[2 * static_cast<size_t>(t) + 1], par));
+    }
+    *terms += t1 - t0;
+    return a;
+}
+
+// psi(x') / psi(x) in FP32 from the FP64 log-psi difference; the phase
+// difference is reduced to (-pi, pi] in FP64 before rounding.
+__device__ __forceinline__ void ratio_f32(double da, double dphi, float &rr, float &ri) {
+    constexpr double kTwoPi = 6.283185307179586476925286766559;
+    dphi -= kTwoPi * rint(dphi / kTwoPi);
+    const float mag = expf(static_cast<float>(da));
+    float sn, cs;
+    sincosf(static_cast<float>(dphi), &sn, &cs);
+    rr = mag * cs;
+    ri = mag * sn;
+}
+
 // Grid: (sample tiles of blockDim) x (group chunks).  Each lane walks the
 // groups of its chunk in order; hits are added to the owning lane in queue
 // order, which is group order, so the partial sums do not depend on
 // scheduling.  The X = 0 group is left to the finish kernel.
-template <int W, bool S32, bool SEC, bool DUMP>
+template <int W, bool S32, bool SEC, bool DUMP, int P>
 __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
     const double *__restrict__ log_amp, const double *__restrict__ phase, int64_t n,
@@ -310,7 +370,8 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
         for (int q = 0; q < W; ++q) x.w[q] = 0;
     }
 
-    double acc_re = 0.0, acc_im = 0.0;
+    double acc_re = 0.0, acc_im = 0.0;              // FP64 form
+    AccF32 fre, fim;                                // FP32 form
     unsigned long long n_hit = 0, n_terms = 0;      // per lane
     unsigned long long w_probe = 0, w_cand = 0;     // per wave (identical in all lanes)
     uint32_t qn = 0;  // queue length, identical in all lanes of the wave
@@ -330,6 +391,7 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
         const uint32_t hxl = __shfl(hx, l);
         const double lal = shfl_f64(la, l), phl = shfl_f64(ph, l);
         double cre = 0.0, cim = 0.0;
+        float pre = 0.f, ere = 0.f, pim = 0.f, eim = 0.f;
         bool hit = false;
         if (lane < static_cast<int>(m)) {
             Key<W> xp;
@@ -343,13 +405,24 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
             if (j >= 0) {
                 hit = true;
                 ++n_hit;
-                uint32_t *row = (DUMP && sign_bits) ? sign_bits + (wave0 + l) * sign_words : nullptr;
-                const double hsum = group_sum<W, DUMP>(tab, g, xl, row, &n_terms);
-                double sn, cs;
-                sincos(phase[j] - phl, &sn, &cs);
-                const double mag = exp(log_amp[j] - lal);
-                cre = hsum * (mag * cs);
-                cim = hsum * (mag * sn);
+                if constexpr (P == NQS_FP64) {
+                    uint32_t *row =
+                        (DUMP && sign_bits) ? sign_bits + (wave0 + l) * sign_words : nullptr;
+                    const double hsum = group_sum<W, DUMP>(tab, g, xl, row, &n_terms);
+                    double sn, cs;
+                    sincos(phase[j] - phl, &sn, &cs);
+                    const double mag = exp(log_amp[j] - lal);
+                    cre = hsum * (mag * cs);
+                    cim = hsum * (mag * sn);
+                } else {
+                    const AccF32 hs = group_sum_f32<W>(tab, g, xl, &n_terms);
+                    float rr, ri;
+                    ratio_f32(log_amp[j] - lal, phase[j] - phl, rr, ri);
+                    pre = hs.s * rr;
+                    ere = fmaf(hs.s, rr, -pre) + hs.c * rr;
+                    pim = hs.s * ri;
+                    eim = fmaf(hs.s, ri, -pim) + hs.c * ri;
+                }
             }
         }
         uint64_t hm = __ballot(hit);
@@ -357,11 +430,22 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
             const int q = __builtin_ctzll(hm);
             hm &= hm - 1;
             const int owner = __builtin_amdgcn_readlane(l, q);
-            const double r = readlane_f64(cre, q);
-            const double im = readlane_f64(cim, q);
-            if (lane == owner) {
-                acc_re += r;
-                acc_im += im;
+            if constexpr (P == NQS_FP64) {
+                const double r = readlane_f64(cre, q);
+                const double im = readlane_f64(cim, q);
+                if (lane == owner) {
+                    acc_re += r;
+                    acc_im += im;
+                }
+            } else {
+                const float a0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pre), q));
+                const float a1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ere), q));
+                const float b0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pim), q));
+                const float b1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(eim), q));
+                if (lane == owner) {
+                    fre.add(a0, a1);
+                    fim.add(b0, b1);
+                }
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -469,8 +553,13 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
 
     if (active) {
         double *p = sc.part + 2 * (static_cast<int64_t>(blockIdx.y) * n + i);
-        p[0] = acc_re;
-        p[1] = acc_im;
+        if constexpr (P == NQS_FP64) {
+            p[0] = acc_re;
+            p[1] = acc_im;
+        } else {
+            p[0] = fre.value();
+            p[1] = fim.value();
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -486,7 +575,7 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
 }
 
 // E_loc(x) = diagonal group sum + sum of the chunk partials in chunk order.
-template <int W, bool DUMP>
+template <int W, bool DUMP, int P>
 __global__ __launch_bounds__(256) void eloc_finish_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n,
     int64_t n_chunks, double *__restrict__ eloc, int32_t *__restrict__ hit_idx,
@@ -497,8 +586,12 @@ __global__ __launch_bounds__(256) void eloc_finish_kernel(
         const Key<W> x = load_key<W>(samples, i);
         double re = 0.0, im = 0.0;
         if (tab.has_diagonal) {
-            uint32_t *row = (DUMP && sign_bits) ? sign_bits + i * sign_words : nullptr;
-            re = group_sum<W, DUMP>(tab, 0, x, row, &n_terms);
+            if constexpr (P == NQS_FP64) {
+                uint32_t *row = (DUMP && sign_bits) ? sign_bits + i * sign_words : nullptr;
+                re = group_sum<W, DUMP>(tab, 0, x, row, &n_terms);
+            } else {
+                re = group_sum_f32<W>(tab, 0, x, &n_terms).value();
+            }
             if constexpr (DUMP) {
                 if (hit_idx) hit_idx[i * tab.n_groups] = static_cast<int32_t>(i);
             }
@@ -669,7 +762,7 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
     return hipGetLastError();
 }
 
-template <int W, bool S32, bool SEC, bool D>
+template <int W, bool S32, bool SEC, bool D, int P>
 hipError_t launch_lookup(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
                          const uint64_t *samples, const double *log_amp, const double *phase,
                          int32_t *hit_idx, uint32_t *sign_bits, int64_t sign_words,
@@ -677,14 +770,14 @@ hipError_t launch_lookup(const DevTable &tab, const DevScratch &sc, const EvalLa
     static bool attr_set = false;
     if (!attr_set) {
         const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&eloc_lookup_kernel<W, S32, SEC, D>),
+            reinterpret_cast<const void *>(&eloc_lookup_kernel<W, S32, SEC, D, P>),
             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const dim3 grid(static_cast<unsigned>((L.n + L.threads - 1) / L.threads),
                     static_cast<unsigned>(L.n_chunks));
-    hipLaunchKernelGGL((eloc_lookup_kernel<W, S32, SEC, D>), grid, dim3(L.threads), L.lds_bytes, st,
+    hipLaunchKernelGGL((eloc_lookup_kernel<W, S32, SEC, D, P>), grid, dim3(L.threads), L.lds_bytes, st,
                        tab, sc, samples, log_amp, phase, L.n, L.g_first, L.chunk_len, hit_idx,
                        sign_bits, sign_words);
     return hipGetLastError();
@@ -694,18 +787,20 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
                        const uint64_t *samples, const double *log_amp, const double *phase,
                        double *eloc, int precision, int32_t *hit_idx, uint32_t *sign_bits,
                        int64_t sign_words, EvalStageEvents ev, hipStream_t st) {
-    (void)precision;
     const int words = tab.n_qubits <= 63 ? 1 : 2;
     const bool dump = hit_idx || sign_bits;
+    const bool f32 = precision == NQS_FP32_KAHAN && !dump;
     const bool s32 = tab.sector32 != 0;
     const int64_t n = L.n;
     hipError_t e = hipSuccess;
     if (L.chunk_len > 0) {
-#define NQS_LOOKUP(Wd, S, SE, D)                                                             \
-    e = launch_lookup<Wd, S, SE, D>(tab, sc, L, samples, log_amp, phase, hit_idx, sign_bits, \
-                                    sign_words, st)
-#define NQS_LOOKUP_D(Wd, S, SE) \
-    if (dump) NQS_LOOKUP(Wd, S, SE, true); else NQS_LOOKUP(Wd, S, SE, false)
+#define NQS_LOOKUP(Wd, S, SE, D, Pr)                                                             \
+    e = launch_lookup<Wd, S, SE, D, Pr>(tab, sc, L, samples, log_amp, phase, hit_idx, sign_bits, \
+                                        sign_words, st)
+#define NQS_LOOKUP_D(Wd, S, SE)                      \
+    if (dump) NQS_LOOKUP(Wd, S, SE, true, NQS_FP64);  \
+    else if (f32) NQS_LOOKUP(Wd, S, SE, false, NQS_FP32_KAHAN); \
+    else NQS_LOOKUP(Wd, S, SE, false, NQS_FP64)
         // the sector test needs spin masks (and, checked on the device, one
         // (N_alpha, N_beta) over the batch)
         const bool sec = tab.sector_filter != 0;
@@ -728,13 +823,17 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
     }
     const int64_t chunks = L.chunk_len > 0 ? L.n_chunks : 0;
     const dim3 fgrid(static_cast<unsigned>((n + 255) / 256));
-#define NQS_FINISH(Wd, D)                                                                        \
-    hipLaunchKernelGGL((eloc_finish_kernel<Wd, D>), fgrid, dim3(256), 0, st, tab, sc, samples, n, \
-                       chunks, eloc, hit_idx, sign_bits, sign_words)
+#define NQS_FINISH(Wd, D, Pr)                                                                 \
+    hipLaunchKernelGGL((eloc_finish_kernel<Wd, D, Pr>), fgrid, dim3(256), 0, st, tab, sc, samples, \
+                       n, chunks, eloc, hit_idx, sign_bits, sign_words)
     if (words == 1) {
-        if (dump) NQS_FINISH(1, true); else NQS_FINISH(1, false);
+        if (dump) NQS_FINISH(1, true, NQS_FP64);
+        else if (f32) NQS_FINISH(1, false, NQS_FP32_KAHAN);
+        else NQS_FINISH(1, false, NQS_FP64);
     } else {
-        if (dump) NQS_FINISH(2, true); else NQS_FINISH(2, false);
+        if (dump) NQS_FINISH(2, true, NQS_FP64);
+        else if (f32) NQS_FINISH(2, false, NQS_FP32_KAHAN);
+        else NQS_FINISH(2, false, NQS_FP64);
     }
 #undef NQS_FINISH
     return hipGetLastError();

@@ -361,3 +361,44 @@ def test_edge_sizes_determinism_and_permutation(torch_dev, nq12):
     assert_parity(c, ref[perm], ab[perm])
     ham.sync()
     ham.close()
+
+
+# ---------------------------------------------------------------- FP32 + compensation form
+
+FP32_TOL = 1e-6      # per sample, relative to A(x); see the design doc (FP32 error budget)
+ENERGY_TOL_HA = 1e-6  # absolute, on Re <E>
+
+
+@pytest.mark.parametrize("name,n", [("nq12", None), ("nq40", 8192), ("nq40", None),
+                                    ("nq100", 4096)])
+def test_fp32_kahan_form(torch_dev, name, n, workload_cache):
+    w = workload_cache(("workload", name) if n is None else ("workload", name, n))
+    say(f"fp32k {w.name}")
+    e32, st32 = gpu_eloc(torch_dev, w, precision="fp32k")
+    e64, st64 = gpu_eloc(torch_dev, w)
+    ref, ab, _ = oracle.eloc(w.n_qubits, w.x, w.z, w.c, w.samples, w.log_amp, w.phase)
+    assert_parity(e64, ref, ab)
+    assert_parity(e32, ref, ab, tol=FP32_TOL)
+    # lookups are the same integer work in both forms
+    assert st32["probes"] == st64["probes"] and st32["hits"] == st64["hits"]
+    m_ref, v_ref, _ = oracle.energy(w.weights, ref)
+    m32, v32, _ = oracle.energy(w.weights, e32)
+    say(f"fp32k {w.name}: |dRe E| = {abs(m32.real - m_ref.real):.3e} Ha, "
+        f"max rel err {np.max(np.abs(e32 - ref) / ab):.2e}")
+    assert abs(m32.real - m_ref.real) <= ENERGY_TOL_HA
+
+
+def test_fp32_kahan_closure_set(torch_dev, workload_cache):
+    """Hit-heavy batch: every sample has hundreds of partners in S."""
+    w = workload_cache(("workload", "nq40", 256))
+    S = _closure(20, 10, seed=20)
+    rng = np.random.default_rng(4)
+    la, ph = rng.normal(0, 0.5, S.shape[0]), rng.uniform(0, 2 * math.pi, S.shape[0])
+    ones = np.ones(S.shape[0], np.int64)
+    say(f"fp32k closure set, {S.shape[0]} samples")
+    e32, _ = gpu_eloc(torch_dev, w, samples=S, la=la, ph=ph, weights=ones, precision="fp32k")
+    ref, ab, _ = oracle.eloc(40, w.x, w.z, w.c, S, la, ph)
+    assert_parity(e32, ref, ab, tol=FP32_TOL)
+    m_ref, _, _ = oracle.energy(ones, ref)
+    m32, _, _ = oracle.energy(ones, e32)
+    assert abs(m32.real - m_ref.real) <= ENERGY_TOL_HA
