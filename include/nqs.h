@@ -196,6 +196,86 @@ int nqs_debug_dump(nqs_ham h, int64_t n, const uint64_t *samples, const double *
                    const double *phase, double *eloc, int32_t *hit_idx, uint32_t *sign_bits,
                    void *hip_stream);
 
+
+/* ------------------------------------------------------------------ tuning
+ *
+ * Launch parameters of the lookup kernel.  Zero fields take the built-in
+ * default.  They change speed only: results do not depend on threads or
+ * filter_bits, and blocks_per_cu only moves the group-chunk boundaries, which
+ * reorders FP sums within rounding.
+ */
+typedef struct {
+    int32_t threads;       /* lookup block size: 256, 512 or 1024 (default 1024) */
+    int32_t filter_bits;   /* on-chip filter bits per sample, 4..64 (default 16; the
+                              bitmap is capped at 128 KB) */
+    int32_t blocks_per_cu; /* target work items per compute unit, 1..64 (default 4) */
+    int32_t reserved;      /* must be 0 */
+} nqs_tuning;
+
+/* Set (t != NULL) or clear (t == NULL) the handle's tuning.  NQS_E_ARG on a
+ * value out of range. */
+int nqs_set_tuning(nqs_ham h, const nqs_tuning *t);
+/* The tuning the handle uses (defaults filled in). */
+int nqs_get_tuning(nqs_ham h, nqs_tuning *out);
+
+/*
+ * Autotuner.  Times candidate tunings (threads x filter bits x blocks per
+ * CU) with HIP events on hip_stream, evaluating this batch (arguments as
+ * nqs_eloc_eval; eloc receives the last result), and keeps the fastest.  The
+ * choice is cached per shape class (mask words, sector-test form, log2 of
+ * the batch size and of the group count, precision) in a JSON file at
+ * cache_path (NULL: no cache); a cached class is applied without timing.
+ * The chosen tuning is set on the handle and returned in *best, with its
+ * time in *best_ms (-1 when it came from the cache).  Synchronises the
+ * stream.  Errors: as nqs_eloc_eval, plus NQS_E_STATE when the cache file
+ * cannot be written.
+ */
+int nqs_autotune(nqs_ham h, int64_t n, const uint64_t *samples, const double *log_amp,
+                 const double *phase, double *eloc, int precision, const char *cache_path,
+                 nqs_tuning *best, double *best_ms, void *hip_stream);
+
+/* ------------------------------------------------------------------ batched form
+ *
+ * Many Hamiltonians, each with its own uneven batch, in one pass: per-job
+ * hash builds run as one (tile, job) grid, and all lookup work is one list
+ * of (job, sample tile, group chunk) items drained by a single persistent
+ * kernel (blocks take items from an atomic counter until the list is
+ * empty).  Results equal those of nqs_eloc_eval with the same tunings.
+ */
+typedef struct {
+    nqs_ham ham;              /* distinct handles within one batch */
+    int64_t n;                /* samples of this job (0 allowed) */
+    const uint64_t *samples;  /* device [n][2] */
+    const int64_t *weights;   /* device [n] or NULL */
+    const double *log_amp;    /* device [n] */
+    const double *phase;      /* device [n] */
+    double *eloc;             /* device [n][2] output */
+} nqs_batch_item;
+
+typedef struct nqs_batch_s *nqs_batch; /* opaque, owned by the library */
+
+/*
+ * Plan a batch: grows each handle's scratch, builds and uploads the job
+ * descriptors and the work list (synchronously, on hip_stream).  The buffer
+ * pointers are recorded: later launches read whatever the buffers hold then.
+ * threads: lookup block size for the whole batch (0 = default).  Each job
+ * uses its handle's tuning for the filter size and chunking.  The handles
+ * must outlive the batch and must not be used elsewhere while it runs.
+ * Errors: NQS_E_ARG (no items, a repeated or invalid handle, bad sizes or
+ * pointers), NQS_E_NOMEM, NQS_E_DEVICE.
+ */
+int nqs_batch_create(nqs_batch *out, int n_items, const nqs_batch_item *items, int precision,
+                     int threads, void *hip_stream);
+/* Enqueue one evaluation of the whole batch (asynchronous; no allocation). */
+int nqs_batch_launch(nqs_batch b, void *hip_stream);
+/* Capture one evaluation into a HIP graph held by the batch.  hip_stream
+ * must not be the default (NULL) stream. */
+int nqs_batch_capture(nqs_batch b, void *hip_stream);
+/* Launch the captured graph (NQS_E_STATE if nothing was captured). */
+int nqs_batch_replay(nqs_batch b, void *hip_stream);
+/* Release the batch (waits for the device first).  NULL is accepted. */
+int nqs_batch_destroy(nqs_batch b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,7 +35,25 @@ _PRECISION = {"fp64": NQS_FP64, "fp32k": NQS_FP32_KAHAN, "fp32_kahan": NQS_FP32_
 # Every symbol include/nqs.h declares.
 EXPORTS = ("nqs_last_error", "nqs_version", "nqs_ham_create", "nqs_ham_info", "nqs_ham_destroy",
            "nqs_table_host", "nqs_eloc_eval", "nqs_energy", "nqs_sync", "nqs_eval_stats",
-           "nqs_debug_dump", "nqs_profile", "nqs_last_kernel_ms")
+           "nqs_debug_dump", "nqs_profile", "nqs_last_kernel_ms", "nqs_set_tuning",
+           "nqs_get_tuning", "nqs_autotune", "nqs_batch_create", "nqs_batch_launch",
+           "nqs_batch_capture", "nqs_batch_replay", "nqs_batch_destroy")
+
+
+class Tuning(ctypes.Structure):
+    """nqs_tuning: lookup block size, filter bits per sample, work items per CU."""
+    _fields_ = [("threads", ctypes.c_int32), ("filter_bits", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"threads": self.threads, "filter_bits": self.filter_bits,
+                "blocks_per_cu": self.blocks_per_cu}
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("ham", ctypes.c_void_p), ("n", ctypes.c_int64), ("samples", ctypes.c_void_p),
+                ("weights", ctypes.c_void_p), ("log_amp", ctypes.c_void_p),
+                ("phase", ctypes.c_void_p), ("eloc", ctypes.c_void_p)]
 
 
 class NQSError(RuntimeError):
@@ -71,6 +89,14 @@ def load_library(path: str = LIB_PATH):
         "nqs_debug_dump": (I, [P, I64, P, P, P, P, P, P, P]),
         "nqs_profile": (I, [P, I]),
         "nqs_last_kernel_ms": (I, [P, P]),
+        "nqs_set_tuning": (I, [P, P]),
+        "nqs_get_tuning": (I, [P, P]),
+        "nqs_autotune": (I, [P, I64, P, P, P, P, I, ctypes.c_char_p, P, P, P]),
+        "nqs_batch_create": (I, [P, I, P, I, I, P]),
+        "nqs_batch_launch": (I, [P, P]),
+        "nqs_batch_capture": (I, [P, P]),
+        "nqs_batch_replay": (I, [P, P]),
+        "nqs_batch_destroy": (I, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -212,6 +238,32 @@ class Hamiltonian:
         _check(load_library().nqs_last_kernel_ms(self._h, out))
         return tuple(out)
 
+    def set_tuning(self, threads=0, filter_bits=0, blocks_per_cu=0):
+        """nqs_set_tuning; all zeros restores the built-in plan."""
+        t = Tuning(threads, filter_bits, blocks_per_cu, 0)
+        _check(load_library().nqs_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(load_library().nqs_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, samples, log_amp, phase, out=None, precision="fp64", cache_path=None,
+                 stream=None):
+        """nqs_autotune: returns (tuning dict, best ms or -1 when cached); out holds E_loc."""
+        import torch
+        n = samples.shape[0]
+        if out is None:
+            out = torch.empty((n, 2), dtype=torch.float64, device=samples.device)
+        best = Tuning()
+        ms = ctypes.c_double()
+        cp = None if cache_path is None else str(cache_path).encode()
+        _check(load_library().nqs_autotune(
+            self._h, n, _dptr(samples, torch.int64, 2), _dptr(log_amp, torch.float64),
+            _dptr(phase, torch.float64), _dptr(out, torch.float64, 2), _PRECISION[precision], cp,
+            ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
+        return best.as_dict(), ms.value
+
     def debug_dump(self, samples, log_amp, phase, hit_idx=None, sign_bits=None, stream=None):
         """nqs_debug_dump: E_loc plus the recorded lookups / sign bits."""
         import torch
@@ -223,6 +275,56 @@ class Hamiltonian:
             self._h, n, _dptr(samples, torch.int64, 2), _dptr(log_amp, torch.float64),
             _dptr(phase, torch.float64), _dptr(out, torch.float64, 2), hp, sp, _stream(stream)))
         return torch.view_as_complex(out)
+
+
+class Batch:
+    """nqs_batch_*: many (Hamiltonian, batch) jobs in one persistent launch.
+
+    jobs: list of (Hamiltonian, samples, log_amp, phase, weights or None, out)
+    with device tensors; out is float64 [n, 2].  The buffers are recorded:
+    launch() and replay() read their current contents.
+    """
+
+    def __init__(self, jobs, precision="fp64", threads=0, stream=None):
+        import torch
+        arr = (BatchItem * len(jobs))()
+        self._keep = []
+        for k, (ham, S, la, ph, w, out) in enumerate(jobs):
+            n = S.shape[0]
+            arr[k].ham = ham.handle
+            arr[k].n = n
+            arr[k].samples = _dptr(S, torch.int64, 2).value if n else None
+            arr[k].weights = None if w is None else _dptr(w, torch.int64).value
+            arr[k].log_amp = _dptr(la, torch.float64).value if n else None
+            arr[k].phase = _dptr(ph, torch.float64).value if n else None
+            arr[k].eloc = _dptr(out, torch.float64, 2).value if n else None
+            self._keep.append((ham, S, la, ph, w, out))
+        b = ctypes.c_void_p()
+        _check(load_library().nqs_batch_create(ctypes.byref(b), len(jobs), arr,
+                                               _PRECISION[precision], int(threads),
+                                               _stream(stream)))
+        self._b = b
+
+    def launch(self, stream=None):
+        _check(load_library().nqs_batch_launch(self._b, _stream(stream)))
+
+    def capture(self, stream):
+        """Capture one evaluation into a HIP graph (stream must not be the default one)."""
+        _check(load_library().nqs_batch_capture(self._b, _stream(stream)))
+
+    def replay(self, stream=None):
+        _check(load_library().nqs_batch_replay(self._b, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            _check(load_library().nqs_batch_destroy(self._b))
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def energy(weights, eloc, stream=None):

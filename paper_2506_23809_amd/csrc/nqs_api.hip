@@ -1,7 +1,11 @@
 // C ABI of libnqs.so: handles, argument checks, scratch management, launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -62,6 +66,8 @@ struct nqs_ham_s {
     bool profiling = false;
     bool profiled = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // launch tuning (all-zero = built-in plan)
+    nqs::Tuning tune{0, 0, 0};
 };
 
 namespace {
@@ -134,7 +140,7 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
     if (n > (int64_t(1) << 30)) return fail(NQS_E_ARG, "batch larger than 2^30 samples");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool dump = hit_idx || sign_bits;
-    const nqs::EvalLaunch L = nqs::plan_eval(h->dt, n, dump);
+    const nqs::EvalLaunch L = nqs::plan_eval(h->dt, n, dump, &h->tune);
     int rc = ensure_scratch(h, n, L.n_chunks, st);
     if (rc) return rc;
     nqs::DevScratch sc = scratch_of(h);
@@ -424,6 +430,393 @@ int nqs_energy(int64_t n, const int64_t *weights, const double *eloc, double out
     NQS_HIP(hipStreamSynchronize(st));
     std::memcpy(out, es.host, sizeof(double) * 4);
     if (out[3] == 0.0) return fail(NQS_E_ARG, "sum of weights is zero");
+    return NQS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ tuning
+
+namespace {
+
+bool tuning_valid(const nqs_tuning &t) {
+    const bool th = t.threads == 0 || t.threads == 256 || t.threads == 512 || t.threads == 1024;
+    const bool fb = t.filter_bits == 0 || (t.filter_bits >= 4 && t.filter_bits <= 64);
+    const bool bc = t.blocks_per_cu == 0 || (t.blocks_per_cu >= 1 && t.blocks_per_cu <= 64);
+    return th && fb && bc && t.reserved == 0;
+}
+
+nqs_tuning filled(const nqs::Tuning &t) {
+    nqs_tuning o{};
+    o.threads = t.threads ? t.threads : 1024;
+    o.filter_bits = t.filter_bits ? t.filter_bits : 16;
+    o.blocks_per_cu = t.blocks_per_cu ? t.blocks_per_cu : 4;
+    return o;
+}
+
+std::string shape_key(nqs_ham h, int64_t n, int precision) {
+    const int lgn = n > 0 ? static_cast<int>(std::lround(std::log2(static_cast<double>(n)))) : 0;
+    const int lgg = h->dt.n_groups > 0
+                        ? static_cast<int>(std::lround(std::log2(static_cast<double>(h->dt.n_groups))))
+                        : 0;
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "w%d_sec%d_s32_%d_lgn%d_lgg%d_p%d", h->words,
+                  h->dt.sector_filter, h->dt.sector32, lgn, lgg, precision);
+    return buf;
+}
+
+struct CacheEntry {
+    nqs_tuning t;
+    double ms;
+};
+
+// The cache file is a JSON object with one entry per line:
+//   "key": {"threads": T, "filter_bits": F, "blocks_per_cu": B, "ms": X},
+std::map<std::string, CacheEntry> read_cache(const char *path) {
+    std::map<std::string, CacheEntry> m;
+    if (!path) return m;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return m;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        char key[128];
+        CacheEntry e{};
+        if (std::sscanf(line, " \"%127[^\"]\": {\"threads\": %d, \"filter_bits\": %d, "
+                              "\"blocks_per_cu\": %d, \"ms\": %lf",
+                        key, &e.t.threads, &e.t.filter_bits, &e.t.blocks_per_cu, &e.ms) == 5 &&
+            tuning_valid(e.t))
+            m[key] = e;
+    }
+    std::fclose(f);
+    return m;
+}
+
+bool write_cache(const char *path, const std::map<std::string, CacheEntry> &m) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\n");
+    size_t k = 0;
+    for (const auto &kv : m) {
+        std::fprintf(f, "  \"%s\": {\"threads\": %d, \"filter_bits\": %d, \"blocks_per_cu\": %d, "
+                        "\"ms\": %.6f}%s\n",
+                     kv.first.c_str(), kv.second.t.threads, kv.second.t.filter_bits,
+                     kv.second.t.blocks_per_cu, kv.second.ms, ++k < m.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+std::mutex g_cache_mutex;
+
+}  // namespace
+
+extern "C" {
+
+int nqs_set_tuning(nqs_ham h, const nqs_tuning *t) {
+    if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
+    if (!t) {
+        h->tune = nqs::Tuning{0, 0, 0};
+        return NQS_OK;
+    }
+    if (!tuning_valid(*t)) return fail(NQS_E_ARG, "tuning value out of range");
+    h->tune = nqs::Tuning{t->threads, t->filter_bits, t->blocks_per_cu};
+    return NQS_OK;
+}
+
+int nqs_get_tuning(nqs_ham h, nqs_tuning *out) {
+    if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
+    if (!out) return fail(NQS_E_ARG, "null output");
+    *out = filled(h->tune);
+    return NQS_OK;
+}
+
+int nqs_autotune(nqs_ham h, int64_t n, const uint64_t *samples, const double *log_amp,
+                 const double *phase, double *eloc, int precision, const char *cache_path,
+                 nqs_tuning *best, double *best_ms, void *hip_stream) {
+    if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
+    if (n <= 0) return fail(NQS_E_ARG, "autotuning needs a non-empty batch");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const std::string key = shape_key(h, n, precision);
+    {
+        std::lock_guard<std::mutex> lock(g_cache_mutex);
+        const auto cache = read_cache(cache_path);
+        const auto it = cache.find(key);
+        if (it != cache.end()) {
+            h->tune = nqs::Tuning{it->second.t.threads, it->second.t.filter_bits,
+                                  it->second.t.blocks_per_cu};
+            if (best) *best = filled(h->tune);
+            if (best_ms) *best_ms = -1.0;
+            return NQS_OK;
+        }
+    }
+    hipEvent_t e0, e1;
+    NQS_HIP(hipEventCreate(&e0));
+    NQS_HIP(hipEventCreate(&e1));
+    const nqs::Tuning saved = h->tune;
+    nqs::Tuning win{0, 0, 0};
+    double win_ms = 1e300;
+    int rc = NQS_OK;
+    const int threads[] = {256, 512, 1024};
+    const int fbits[] = {8, 16, 32};
+    const int bpc[] = {2, 4, 8};
+    for (int th : threads) {
+        for (int fb : fbits) {
+            for (int bc : bpc) {
+                h->tune = nqs::Tuning{th, fb, bc};
+                float best_run = 1e30f;
+                for (int rep = 0; rep < 4 && rc == NQS_OK; ++rep) {
+                    hipError_t e = hipEventRecord(e0, st);
+                    if (e == hipSuccess) {
+                        rc = eval_impl(h, n, samples, nullptr, log_amp, phase, eloc, precision,
+                                       nullptr, nullptr, st);
+                        if (rc) break;
+                        e = hipEventRecord(e1, st);
+                    }
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    if (e != hipSuccess) {
+                        rc = fail_hip(e, "timing a candidate tuning");
+                        break;
+                    }
+                    if (rep > 0) best_run = std::min(best_run, ms);  // first run warms up
+                }
+                if (rc) break;
+                if (best_run < win_ms) {
+                    win_ms = best_run;
+                    win = h->tune;
+                }
+            }
+            if (rc) break;
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        h->tune = saved;
+        return rc;
+    }
+    h->tune = win;
+    if (best) *best = filled(win);
+    if (best_ms) *best_ms = win_ms;
+    if (cache_path) {
+        std::lock_guard<std::mutex> lock(g_cache_mutex);
+        auto cache = read_cache(cache_path);
+        cache[key] = CacheEntry{filled(win), win_ms};
+        if (!write_cache(cache_path, cache))
+            return fail(NQS_E_STATE, std::string("cannot write tuning cache ") + cache_path);
+    }
+    // leave eloc holding the result of the chosen tuning
+    return eval_impl(h, n, samples, nullptr, log_amp, phase, eloc, precision, nullptr, nullptr, st);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batched form
+
+struct nqs_batch_s {
+    int precision = NQS_FP64;
+    std::vector<nqs_ham> hams;
+    std::vector<int64_t> ns;
+    nqs::JobDesc *d_jobs = nullptr;
+    nqs::WorkItem *d_items = nullptr;
+    unsigned *d_next = nullptr;
+    int n_jobs = 0;
+    int n_items = 0;
+    nqs::BatchShape shape{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void batch_free(nqs_batch b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_jobs) (void)hipFree(b->d_jobs);
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_next) (void)hipFree(b->d_next);
+    delete b;
+}
+
+void batch_mark(nqs_batch b) {
+    for (size_t k = 0; k < b->hams.size(); ++k) {
+        b->hams[k]->last_pairs = b->ns[k] * b->hams[k]->dt.n_groups;
+        b->hams[k]->ever_evaluated = true;
+        b->hams[k]->profiled = false;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int nqs_batch_create(nqs_batch *out, int n_items, const nqs_batch_item *items, int precision,
+                     int threads, void *hip_stream) {
+    if (!out) return fail(NQS_E_ARG, "null batch output");
+    *out = nullptr;
+    if (n_items <= 0 || !items) return fail(NQS_E_ARG, "a batch needs at least one item");
+    if (precision != NQS_FP64 && precision != NQS_FP32_KAHAN)
+        return fail(NQS_E_ARG, "unknown precision");
+    if (!(threads == 0 || threads == 256 || threads == 512 || threads == 1024))
+        return fail(NQS_E_ARG, "threads must be 0, 256, 512 or 1024");
+    const int th = threads ? threads : 1024;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    for (int k = 0; k < n_items; ++k) {
+        const nqs_batch_item &it = items[k];
+        if (!valid_handle(it.ham)) return fail(NQS_E_ARG, "invalid handle in batch item");
+        if (it.n < 0 || it.n > (int64_t(1) << 30)) return fail(NQS_E_ARG, "bad batch size");
+        if (it.n > 0 && (!it.samples || !it.log_amp || !it.phase || !it.eloc))
+            return fail(NQS_E_ARG, "null pointer in batch item");
+        for (int m = 0; m < k; ++m)
+            if (items[m].ham == it.ham) return fail(NQS_E_ARG, "a handle appears twice in a batch");
+    }
+    int dev = 0, n_cu = 0;
+    NQS_HIP(hipGetDevice(&dev));
+    NQS_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+
+    nqs_batch b = new (std::nothrow) nqs_batch_s();
+    if (!b) return fail(NQS_E_NOMEM, "host allocation failed");
+    b->precision = precision;
+    b->n_jobs = n_items;
+    std::vector<nqs::JobDesc> jobs(n_items);
+    std::vector<int64_t> cost(n_items);
+    nqs::BatchShape shape{};
+    shape.threads = th;
+    shape.max_filter_log2 = 7;
+    for (int k = 0; k < n_items; ++k) {
+        const nqs_batch_item &it = items[k];
+        nqs_ham h = it.ham;
+        nqs::Tuning t = h->tune;
+        t.threads = th;
+        const nqs::EvalLaunch L = nqs::plan_eval(h->dt, std::max<int64_t>(it.n, 1), false, &t);
+        int rc = ensure_scratch(h, std::max<int64_t>(it.n, 1), L.n_chunks, st);
+        if (rc) {
+            batch_free(b);
+            return rc;
+        }
+        nqs::JobDesc &J = jobs[k];
+        J.tab = h->dt;
+        J.sc = scratch_of(h);
+        J.sc.filter_log2 = L.filter_log2;
+        J.samples = it.samples;
+        J.weights = it.weights;
+        J.log_amp = it.log_amp;
+        J.phase = it.phase;
+        J.eloc = it.eloc;
+        J.n = it.n;
+        J.g_first = L.g_first;
+        J.chunk_len = L.chunk_len;
+        J.n_chunks = L.n_chunks;
+        const int w2 = h->words == 2 ? 1 : 0;
+        J.kind = !h->dt.sector_filter ? (w2 ? nqs::kJobW2Nosec : nqs::kJobW1Nosec)
+                 : h->dt.sector32     ? (w2 ? nqs::kJobW2S32 : nqs::kJobW1S32)
+                                      : (w2 ? nqs::kJobW2S64 : nqs::kJobW1S64);
+        J.capacity = h->slot_cap;
+        shape.max_filter_log2 = std::max(shape.max_filter_log2, L.filter_log2);
+        shape.max_n = std::max(shape.max_n, it.n);
+        shape.max_clear = std::max<int64_t>(shape.max_clear,
+                                            std::max<int64_t>(h->slot_cap, int64_t(1) << L.filter_log2));
+        cost[k] = it.n * (h->dt.n_groups - L.g_first);
+        b->hams.push_back(h);
+        b->ns.push_back(it.n);
+    }
+    // work list: largest jobs first (the persistent kernel drains it in order),
+    // chunk-major within a job so consecutive items share group records
+    std::vector<int> order(n_items);
+    for (int k = 0; k < n_items; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    std::vector<nqs::WorkItem> work;
+    for (int k : order) {
+        const nqs::JobDesc &J = jobs[k];
+        if (J.n == 0 || J.chunk_len == 0) continue;
+        const int64_t tiles = (J.n + th - 1) / th;
+        for (int64_t c = 0; c < J.n_chunks; ++c)
+            for (int64_t t = 0; t < tiles; ++t)
+                work.push_back(nqs::WorkItem{k, static_cast<int32_t>(c), static_cast<int32_t>(t), 0});
+    }
+    if (work.size() >= (size_t(1) << 31)) {
+        batch_free(b);
+        return fail(NQS_E_ARG, "work list too long");
+    }
+    b->n_items = static_cast<int>(work.size());
+    const size_t lds = nqs::batch_lds_bytes(th, shape.max_filter_log2);
+    const int per_cu_lds = static_cast<int>((160 * 1024) / lds);
+    const int per_cu_waves = (32 * 64) / th;
+    shape.lookup_blocks = static_cast<unsigned>(n_cu * std::max(1, std::min(per_cu_lds, per_cu_waves)));
+    b->shape = shape;
+    hipError_t e = hipMalloc(&b->d_jobs, sizeof(nqs::JobDesc) * n_items);
+    if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(nqs::WorkItem) * std::max<size_t>(work.size(), 1));
+    if (e == hipSuccess) e = hipMalloc(&b->d_next, sizeof(unsigned));
+    if (e != hipSuccess) {
+        batch_free(b);
+        return fail(NQS_E_NOMEM, "device allocation of the batch plan failed");
+    }
+    e = hipMemcpyAsync(b->d_jobs, jobs.data(), sizeof(nqs::JobDesc) * n_items, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !work.empty())
+        e = hipMemcpyAsync(b->d_items, work.data(), sizeof(nqs::WorkItem) * work.size(),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return fail_hip(e, "uploading the batch plan");
+    }
+    *out = b;
+    return NQS_OK;
+}
+
+int nqs_batch_launch(nqs_batch b, void *hip_stream) {
+    if (!b || !b->d_jobs) return fail(NQS_E_STATE, "invalid batch");
+    NQS_HIP(nqs::launch_batch(b->d_jobs, b->n_jobs, b->d_items, b->n_items, b->d_next, b->shape,
+                              b->precision, static_cast<hipStream_t>(hip_stream)));
+    batch_mark(b);
+    return NQS_OK;
+}
+
+int nqs_batch_capture(nqs_batch b, void *hip_stream) {
+    if (!b || !b->d_jobs) return fail(NQS_E_STATE, "invalid batch");
+    if (!hip_stream) return fail(NQS_E_ARG, "graph capture needs a non-default stream");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    // kernel attributes are set by one eager launch-free call before capture
+    NQS_HIP(nqs::prepare_batch_kernels());
+    NQS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const hipError_t le = nqs::launch_batch(b->d_jobs, b->n_jobs, b->d_items, b->n_items,
+                                            b->d_next, b->shape, b->precision, st);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(st, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail_hip(le, "launching the batch under capture");
+    }
+    if (ce != hipSuccess) return fail_hip(ce, "hipStreamEndCapture");
+    b->graph = g;
+    NQS_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return NQS_OK;
+}
+
+int nqs_batch_replay(nqs_batch b, void *hip_stream) {
+    if (!b || !b->exec) return fail(NQS_E_STATE, "no captured graph in this batch");
+    NQS_HIP(hipGraphLaunch(b->exec, static_cast<hipStream_t>(hip_stream)));
+    batch_mark(b);
+    return NQS_OK;
+}
+
+int nqs_batch_destroy(nqs_batch b) {
+    if (!b) return NQS_OK;
+    const hipError_t e = hipDeviceSynchronize();
+    batch_free(b);
+    if (e != hipSuccess) return fail_hip(e, "synchronising before batch destroy");
     return NQS_OK;
 }
 

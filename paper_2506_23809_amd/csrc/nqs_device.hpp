@@ -78,7 +78,16 @@ struct EvalStageEvents {
     hipEvent_t after_lookup;
 };
 
-EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump);
+// Launch parameters chosen by the autotuner; 0 means the built-in default
+// (1024 threads, 16 filter bits per sample, about 4 lookup blocks per CU's
+// worth of 1024-thread blocks).
+struct Tuning {
+    int threads;        // lookup block size: 256, 512 or 1024
+    int filter_bits;    // Bloom bits per sample (the bitmap is capped at 128 KB)
+    int blocks_per_cu;  // target (tile, chunk) items per CU
+};
+
+EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tune);
 hipError_t launch_reset(const DevScratch &sc, hipStream_t st);
 hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capacity,
                        const uint64_t *samples, const int64_t *weights, int64_t n,
@@ -91,5 +100,51 @@ hipError_t launch_energy(const int64_t *w, const double *e, int64_t n, double *p
                          double *result, double *out, hipStream_t st);
 constexpr int kEnergyPartDoubles = 3 * 256;
 constexpr int kCounters = 8;
+
+// ---- batched form
+
+// Lookup variant of a job: bit 0 = two mask words, then the sector test.
+enum JobKind : int {
+    kJobW1Nosec = 0, kJobW2Nosec = 1,
+    kJobW1S32 = 2, kJobW2S32 = 3,
+    kJobW1S64 = 4, kJobW2S64 = 5,
+};
+
+struct JobDesc {
+    DevTable tab;
+    DevScratch sc;
+    const uint64_t *samples;
+    const int64_t *weights;
+    const double *log_amp;
+    const double *phase;
+    double *eloc;
+    int64_t n;
+    int64_t g_first;
+    int64_t chunk_len;
+    int64_t n_chunks;
+    int kind;
+    uint32_t capacity;  // hash slots
+};
+
+struct WorkItem {
+    int32_t job;
+    int32_t chunk;
+    int32_t tile;
+    int32_t pad;
+};
+
+struct BatchShape {
+    int threads;          // lookup block size, shared by all jobs
+    int max_filter_log2;  // largest Bloom bitmap (sets the dynamic LDS)
+    int64_t max_n;        // largest batch
+    int64_t max_clear;    // largest of slot capacity and filter words
+    unsigned lookup_blocks;
+};
+
+hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_items, int n_items,
+                        unsigned *d_next, const BatchShape &shape, int precision, hipStream_t st);
+size_t batch_lds_bytes(int threads, int max_filter_log2);
+// Set the dynamic-LDS limit of the batch kernels (outside any graph capture).
+hipError_t prepare_batch_kernels();
 
 }  // namespace nqs

@@ -161,12 +161,10 @@ __global__ void hash_clear_kernel(int32_t *__restrict__ idx_words, int stride_wo
 // hash, Bloom bit, and insertion by CAS on the slot index.  A duplicate key
 // is found by comparing against the sample that owns the slot.
 template <int W>
-__global__ void hash_build_kernel(DevTable tab, DevScratch sc,
-                                  const uint64_t *__restrict__ samples,
-                                  const int64_t *__restrict__ weights, int64_t n) {
+__device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScratch &sc,
+                                               const uint64_t *__restrict__ samples,
+                                               const int64_t *__restrict__ weights, int64_t i) {
     using S = typename SlotT<W>::type;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const uint64_t w0 = samples[2 * i], w1 = samples[2 * i + 1];
     bool bad;
     const int nq = tab.n_qubits;
@@ -212,6 +210,14 @@ __global__ void hash_build_kernel(DevTable tab, DevScratch sc,
     }
 }
 
+template <int W>
+__global__ void hash_build_kernel(DevTable tab, DevScratch sc,
+                                  const uint64_t *__restrict__ samples,
+                                  const int64_t *__restrict__ weights, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) hash_build_one<W>(tab, sc, samples, weights, i);
+}
+
 // ------------------------------------------------------------------ E_loc
 
 constexpr int kLookupThreads = 1024;
@@ -220,6 +226,9 @@ constexpr int kQueueCap = 128;   // per-wave candidate queue (flushed at 64)
 constexpr int kUnroll = 4;       // groups tested per inner iteration
 constexpr uint32_t kPadKey = 0xFFFFFFFFu;  // stage padding: never a candidate
 static_assert(kStage % kUnroll == 0, "stage must hold whole unrolled iterations");
+// Largest dynamic LDS a lookup block asks for: 128 KB bitmap, 512 32-byte
+// records, 16 queues of 128 entries (152 KB; the CU has 160 KB).
+constexpr int kMaxLookupLds = (4 << 15) + kStage * 32 + 16 * kQueueCap * 4;
 
 template <bool S32>
 struct StageRec;
@@ -319,35 +328,37 @@ __device__ __forceinline__ void ratio_f32(double da, double dphi, float &rr, flo
     ri = mag * sn;
 }
 
-// Grid: (sample tiles of blockDim) x (group chunks).  Each lane walks the
-// groups of its chunk in order; hits are added to the owning lane in queue
-// order, which is group order, so the partial sums do not depend on
-// scheduling.  The X = 0 group is left to the finish kernel.
+// One (sample tile, group chunk) work item on one block.  Each lane walks the
+// groups of the chunk in order; hits are added to the owning lane in queue
+// order, which is group order, so the partial sum does not depend on
+// scheduling.  The X = 0 group is left to the finish kernel.  The caller
+// has synchronised the block; load_filter = false reuses the bitmap already
+// in LDS (same Hamiltonian and batch as the previous item).
 template <int W, bool S32, bool SEC, bool DUMP, int P>
-__global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
-    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
+__device__ __forceinline__ void lookup_item(
+    const DevTable &tab, const DevScratch &sc, const uint64_t *__restrict__ samples,
     const double *__restrict__ log_amp, const double *__restrict__ phase, int64_t n,
-    int64_t g_first, int64_t chunk_len, int32_t *__restrict__ hit_idx,
-    uint32_t *__restrict__ sign_bits, int64_t sign_words) {
+    int64_t tile, int64_t chunk, int64_t g_first, int64_t chunk_len, bool load_filter,
+    int32_t *__restrict__ hit_idx, uint32_t *__restrict__ sign_bits, int64_t sign_words,
+    uint4 *smem4) {
     using S = typename SlotT<W>::type;
     using Rec = StageRec<S32>;
-    extern __shared__ uint4 smem4[];
     const int fwords = 1 << sc.filter_log2;
     uint32_t *filt = reinterpret_cast<uint32_t *>(smem4);
     Rec *stage = reinterpret_cast<Rec *>(filt + fwords);
     const int lane = threadIdx.x & 63;
     uint32_t *queue = reinterpret_cast<uint32_t *>(stage + kStage) + (threadIdx.x >> 6) * kQueueCap;
 
-    const int64_t tile0 = static_cast<int64_t>(blockIdx.x) * blockDim.x;
+    const int64_t tile0 = tile * blockDim.x;
     const int64_t wave0 = tile0 + (threadIdx.x & ~63);
     const int64_t i = tile0 + threadIdx.x;
     const bool active = i < n;
-    const int64_t g0 = g_first + static_cast<int64_t>(blockIdx.y) * chunk_len;
+    const int64_t g0 = g_first + chunk * chunk_len;
     const int64_t g1 = min(g0 + chunk_len, tab.n_groups);
     const S *__restrict__ slots = static_cast<const S *>(sc.slots);
 
     // resident Bloom bitmap
-    {
+    if (load_filter) {
         const uint4 *gf = reinterpret_cast<const uint4 *>(sc.filter);
         for (int k = threadIdx.x; k < (fwords >> 2); k += blockDim.x) smem4[k] = gf[k];
     }
@@ -552,7 +563,7 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
     if (qn > 0) flush(qn);
 
     if (active) {
-        double *p = sc.part + 2 * (static_cast<int64_t>(blockIdx.y) * n + i);
+        double *p = sc.part + 2 * (chunk * n + i);
         if constexpr (P == NQS_FP64) {
             p[0] = acc_re;
             p[1] = acc_im;
@@ -574,13 +585,27 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
     }
 }
 
+// Grid form: (sample tiles of blockDim) x (group chunks), one item per block.
+template <int W, bool S32, bool SEC, bool DUMP, int P>
+__global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
+    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
+    const double *__restrict__ log_amp, const double *__restrict__ phase, int64_t n,
+    int64_t g_first, int64_t chunk_len, int32_t *__restrict__ hit_idx,
+    uint32_t *__restrict__ sign_bits, int64_t sign_words) {
+    extern __shared__ uint4 smem4[];
+    lookup_item<W, S32, SEC, DUMP, P>(tab, sc, samples, log_amp, phase, n, blockIdx.x, blockIdx.y,
+                                      g_first, chunk_len, true, hit_idx, sign_bits, sign_words,
+                                      smem4);
+}
+
 // E_loc(x) = diagonal group sum + sum of the chunk partials in chunk order.
 template <int W, bool DUMP, int P>
-__global__ __launch_bounds__(256) void eloc_finish_kernel(
-    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n,
-    int64_t n_chunks, double *__restrict__ eloc, int32_t *__restrict__ hit_idx,
-    uint32_t *__restrict__ sign_bits, int64_t sign_words) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch &sc,
+                                           const uint64_t *__restrict__ samples, int64_t n,
+                                           int64_t n_chunks, double *__restrict__ eloc,
+                                           int32_t *__restrict__ hit_idx,
+                                           uint32_t *__restrict__ sign_bits, int64_t sign_words,
+                                           int64_t i) {
     unsigned long long n_terms = 0;
     if (i < n) {
         const Key<W> x = load_key<W>(samples, i);
@@ -607,6 +632,149 @@ __global__ __launch_bounds__(256) void eloc_finish_kernel(
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) n_terms += __shfl_xor(n_terms, off);
     if ((threadIdx.x & 63) == 0 && n_terms) atomicAdd(&sc.counters[3], n_terms);
+}
+
+template <int W, bool DUMP, int P>
+__global__ __launch_bounds__(256) void eloc_finish_kernel(
+    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n,
+    int64_t n_chunks, double *__restrict__ eloc, int32_t *__restrict__ hit_idx,
+    uint32_t *__restrict__ sign_bits, int64_t sign_words) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    finish_one<W, DUMP, P>(tab, sc, samples, n, n_chunks, eloc, hit_idx, sign_bits, sign_words, i);
+}
+
+// ------------------------------------------------------------------ batched form
+//
+// Many Hamiltonians and uneven batches in one pass.  Small per-job kernels
+// run on a (tile, job) grid; the lookup work of all jobs is one list of
+// (job, tile, chunk) items drained by a persistent kernel: each block takes
+// the next item from one atomic counter until the list is empty, and
+// reloads the LDS Bloom bitmap only when the job changes.  Partials are
+// per item, so the result does not depend on which block ran which item.
+
+__global__ void batch_reset_kernel(const JobDesc *__restrict__ jobs, int n_jobs,
+                                   unsigned *__restrict__ next) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n_jobs) {
+        for (int k = 0; k < kCounters; ++k) jobs[j].sc.counters[k] = 0;
+        *jobs[j].sc.mixed = 0;
+    }
+    if (j == 0) *next = 0u;
+}
+
+__global__ void batch_clear_kernel(const JobDesc *__restrict__ jobs) {
+    const JobDesc &J = jobs[blockIdx.y];
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int words = (J.kind & 1) + 1;
+    if (s < J.capacity) {
+        if (words == 1)
+            static_cast<Slot1 *>(J.sc.slots)[s].idx = -1;
+        else
+            static_cast<Slot2 *>(J.sc.slots)[s].idx = -1;
+    }
+    if (s < (1u << J.sc.filter_log2)) J.sc.filter[s] = 0u;
+}
+
+__global__ void batch_build_kernel(const JobDesc *__restrict__ jobs) {
+    const JobDesc &J = jobs[blockIdx.y];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= J.n) return;
+    if ((J.kind & 1) == 0)
+        hash_build_one<1>(J.tab, J.sc, J.samples, J.weights, i);
+    else
+        hash_build_one<2>(J.tab, J.sc, J.samples, J.weights, i);
+}
+
+template <int P>
+__global__ __launch_bounds__(kLookupThreads) void batch_lookup_kernel(
+    const JobDesc *__restrict__ jobs, const WorkItem *__restrict__ items, int n_items,
+    unsigned *__restrict__ next) {
+    extern __shared__ uint4 smem4[];
+    __shared__ int cur;
+    int last_job = -1;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) cur = static_cast<int>(atomicAdd(next, 1u));
+        __syncthreads();
+        const int it = cur;
+        if (it >= n_items) break;  // every block reaches this once the list is drained
+        const WorkItem w = items[it];
+        const JobDesc &J = jobs[w.job];
+        const bool load = w.job != last_job;
+        last_job = w.job;
+#define NQS_ITEM(Wd, S, SE)                                                                    \
+    lookup_item<Wd, S, SE, false, P>(J.tab, J.sc, J.samples, J.log_amp, J.phase, J.n, w.tile, \
+                                     w.chunk, J.g_first, J.chunk_len, load, nullptr, nullptr, 0, \
+                                     smem4)
+        switch (J.kind) {
+            case kJobW1Nosec: NQS_ITEM(1, true, false); break;
+            case kJobW1S32: NQS_ITEM(1, true, true); break;
+            case kJobW1S64: NQS_ITEM(1, false, true); break;
+            case kJobW2Nosec: NQS_ITEM(2, true, false); break;
+            case kJobW2S32: NQS_ITEM(2, true, true); break;
+            default: NQS_ITEM(2, false, true); break;
+        }
+#undef NQS_ITEM
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void batch_finish_kernel(const JobDesc *__restrict__ jobs) {
+    const JobDesc &J = jobs[blockIdx.y];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (static_cast<int64_t>(blockIdx.x) * blockDim.x >= J.n) return;  // whole block past the end
+    const int64_t chunks = J.chunk_len > 0 ? J.n_chunks : 0;
+    if ((J.kind & 1) == 0)
+        finish_one<1, false, P>(J.tab, J.sc, J.samples, J.n, chunks, J.eloc, nullptr, nullptr, 0, i);
+    else
+        finish_one<2, false, P>(J.tab, J.sc, J.samples, J.n, chunks, J.eloc, nullptr, nullptr, 0, i);
+}
+
+size_t batch_lds_bytes(int threads, int max_filter_log2) {
+    return lookup_lds_bytes(false, max_filter_log2, threads);
+}
+
+hipError_t prepare_batch_kernels() {
+    static bool done = false;
+    if (done) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&batch_lookup_kernel<NQS_FP64>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLookupLds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_lookup_kernel<NQS_FP32_KAHAN>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLookupLds);
+    if (e == hipSuccess) done = true;
+    return e;
+}
+
+hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_items, int n_items,
+                        unsigned *d_next, const BatchShape &shape, int precision,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((n_jobs + 63) / 64), dim3(64), 0, st, d_jobs,
+                       n_jobs, d_next);
+    hipLaunchKernelGGL(batch_clear_kernel,
+                       dim3(static_cast<unsigned>((shape.max_clear + 255) / 256), n_jobs),
+                       dim3(256), 0, st, d_jobs);
+    hipLaunchKernelGGL(batch_build_kernel,
+                       dim3(static_cast<unsigned>((shape.max_n + 255) / 256), n_jobs), dim3(256),
+                       0, st, d_jobs);
+    const size_t lds = batch_lds_bytes(shape.threads, shape.max_filter_log2);
+    const hipError_t pe = prepare_batch_kernels();
+    if (pe != hipSuccess) return pe;
+    if (precision == NQS_FP32_KAHAN) {
+        hipLaunchKernelGGL(batch_lookup_kernel<NQS_FP32_KAHAN>, dim3(shape.lookup_blocks),
+                           dim3(shape.threads), lds, st, d_jobs, d_items, n_items, d_next);
+        hipLaunchKernelGGL(batch_finish_kernel<NQS_FP32_KAHAN>,
+                           dim3(static_cast<unsigned>((shape.max_n + 255) / 256), n_jobs),
+                           dim3(256), 0, st, d_jobs);
+    } else {
+        hipLaunchKernelGGL(batch_lookup_kernel<NQS_FP64>, dim3(shape.lookup_blocks),
+                           dim3(shape.threads), lds, st, d_jobs, d_items, n_items, d_next);
+        hipLaunchKernelGGL(batch_finish_kernel<NQS_FP64>,
+                           dim3(static_cast<unsigned>((shape.max_n + 255) / 256), n_jobs),
+                           dim3(256), 0, st, d_jobs);
+    }
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ energy (Eq. 1)
@@ -717,13 +885,14 @@ hipError_t launch_reset(const DevScratch &sc, hipStream_t st) {
     return hipGetLastError();
 }
 
-EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump) {
+EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tune) {
     EvalLaunch L;
     L.n = n;
-    L.threads = kLookupThreads;
-    // Bloom bitmap: about 16 bits per sample, 512 B .. 128 KB
+    L.threads = (tune && tune->threads) ? tune->threads : kLookupThreads;
+    // Bloom bitmap: about 16 bits per sample unless tuned, 512 B .. 128 KB
     int lg = 7;
-    while (lg < 15 && (int64_t(1) << (lg + 5)) < 16 * n) ++lg;
+    const int64_t bits_per_sample = (tune && tune->filter_bits) ? tune->filter_bits : 16;
+    while (lg < 15 && (int64_t(1) << (lg + 5)) < bits_per_sample * n) ++lg;
     L.filter_log2 = lg;
     L.lds_bytes = lookup_lds_bytes(tab.sector32 != 0, lg, L.threads);
     L.g_first = tab.has_diagonal ? 1 : 0;
@@ -731,7 +900,8 @@ EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump) {
     const int64_t tiles = (n + L.threads - 1) / L.threads;
     int64_t chunks = 1;
     if (!dump && g_eff > 0) {
-        const int64_t want = (1024 + tiles - 1) / tiles;  // ~4 blocks per CU
+        const int64_t target = (tune && tune->blocks_per_cu) ? tune->blocks_per_cu : 4;
+        const int64_t want = (target * 256 * 1024 / L.threads + tiles - 1) / tiles;
         const int64_t max_chunks = (g_eff + kStage - 1) / kStage;
         chunks = want < max_chunks ? want : max_chunks;
         if (chunks < 1) chunks = 1;
@@ -771,7 +941,7 @@ hipError_t launch_lookup(const DevTable &tab, const DevScratch &sc, const EvalLa
     if (!attr_set) {
         const hipError_t e = hipFuncSetAttribute(
             reinterpret_cast<const void *>(&eloc_lookup_kernel<W, S32, SEC, D, P>),
-            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLookupLds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
