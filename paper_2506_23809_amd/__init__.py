@@ -37,7 +37,15 @@ EXPORTS = ("nqs_last_error", "nqs_version", "nqs_ham_create", "nqs_ham_info", "n
            "nqs_table_host", "nqs_eloc_eval", "nqs_energy", "nqs_sync", "nqs_eval_stats",
            "nqs_debug_dump", "nqs_profile", "nqs_last_kernel_ms", "nqs_set_tuning",
            "nqs_get_tuning", "nqs_autotune", "nqs_batch_create", "nqs_batch_launch",
-           "nqs_batch_capture", "nqs_batch_replay", "nqs_batch_destroy")
+           "nqs_batch_capture", "nqs_batch_replay", "nqs_batch_destroy", "nqs_server_create",
+           "nqs_server_add_ham", "nqs_server_submit", "nqs_server_poll", "nqs_server_drain",
+           "nqs_server_stats", "nqs_server_destroy")
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("threads", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -97,6 +105,13 @@ def load_library(path: str = LIB_PATH):
         "nqs_batch_capture": (I, [P, P]),
         "nqs_batch_replay": (I, [P, P]),
         "nqs_batch_destroy": (I, [P]),
+        "nqs_server_create": (I, [P, P]),
+        "nqs_server_add_ham": (I, [P, P, I64]),
+        "nqs_server_submit": (I, [P, P, P]),
+        "nqs_server_poll": (I, [P, P, P, I, P]),
+        "nqs_server_drain": (I, [P, ctypes.c_double]),
+        "nqs_server_stats": (I, [P, P]),
+        "nqs_server_destroy": (I, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -319,6 +334,74 @@ class Batch:
         if getattr(self, "_b", None) is not None and self._b.value:
             _check(load_library().nqs_batch_destroy(self._b))
             self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _item(ham, S, la, ph, w, out):
+    import torch
+    n = S.shape[0]
+    it = BatchItem()
+    it.ham = ham.handle
+    it.n = n
+    it.samples = _dptr(S, torch.int64, 2).value if n else None
+    it.weights = None if w is None else _dptr(w, torch.int64).value
+    it.log_amp = _dptr(la, torch.float64).value if n else None
+    it.phase = _dptr(ph, torch.float64).value if n else None
+    it.eloc = _dptr(out, torch.float64, 2).value if n else None
+    return it
+
+
+class Server:
+    """nqs_server_*: request loop with continuous batching (see include/nqs.h)."""
+
+    def __init__(self, hbm_budget_bytes, streams=4, max_batch=64, precision="fp64", threads=0):
+        cfg = ServerConfig(int(hbm_budget_bytes), int(streams), int(max_batch),
+                           _PRECISION[precision], int(threads))
+        s = ctypes.c_void_p()
+        _check(load_library().nqs_server_create(ctypes.byref(s), ctypes.byref(cfg)))
+        self._s = s
+        self._keep = {}
+
+    def add(self, ham, max_samples):
+        _check(load_library().nqs_server_add_ham(self._s, ham.handle, int(max_samples)))
+
+    def submit(self, ham, S, la, ph, w, out):
+        """Enqueue one request; the tensors must stay alive until it finishes."""
+        it = _item(ham, S, la, ph, w, out)
+        t = ctypes.c_int64()
+        _check(load_library().nqs_server_submit(self._s, ctypes.byref(it), ctypes.byref(t)))
+        self._keep[t.value] = (S, la, ph, w, out)
+        return t.value
+
+    def poll(self, capacity=4096):
+        tk = (ctypes.c_int64 * capacity)()
+        lat = (ctypes.c_double * capacity)()
+        n = ctypes.c_int()
+        _check(load_library().nqs_server_poll(self._s, tk, lat, capacity, ctypes.byref(n)))
+        out = [(tk[k], lat[k]) for k in range(n.value)]
+        for t, _ in out:
+            self._keep.pop(t, None)
+        return out
+
+    def drain(self, timeout_s=120.0):
+        _check(load_library().nqs_server_drain(self._s, float(timeout_s)))
+
+    def stats(self):
+        o = (ctypes.c_int64 * 8)()
+        _check(load_library().nqs_server_stats(self._s, o))
+        keys = ("submitted", "completed", "rejected", "launches", "max_requests_in_flight",
+                "max_launches_in_flight", "peak_bytes", "resident_bytes")
+        return dict(zip(keys, list(o)))
+
+    def close(self):
+        if getattr(self, "_s", None) is not None and self._s.value:
+            _check(load_library().nqs_server_destroy(self._s))
+            self._s = None
 
     def __del__(self):
         try:

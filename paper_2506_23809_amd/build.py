@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnqs.so")
 
-SOURCES = ["nqs_api.hip", "nqs_kernels.hip", "nqs_table.cpp"]
+SOURCES = ["nqs_api.hip", "nqs_kernels.hip", "nqs_server.hip", "nqs_table.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -13,6 +13,7 @@
 
 #include "../../include/nqs.h"
 #include "nqs_device.hpp"
+#include "nqs_internal.hpp"
 #include "nqs_table.hpp"
 
 namespace {
@@ -658,96 +659,24 @@ int nqs_batch_create(nqs_batch *out, int n_items, const nqs_batch_item *items, i
                      int threads, void *hip_stream) {
     if (!out) return fail(NQS_E_ARG, "null batch output");
     *out = nullptr;
-    if (n_items <= 0 || !items) return fail(NQS_E_ARG, "a batch needs at least one item");
     if (precision != NQS_FP64 && precision != NQS_FP32_KAHAN)
         return fail(NQS_E_ARG, "unknown precision");
-    if (!(threads == 0 || threads == 256 || threads == 512 || threads == 1024))
-        return fail(NQS_E_ARG, "threads must be 0, 256, 512 or 1024");
-    const int th = threads ? threads : 1024;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    for (int k = 0; k < n_items; ++k) {
-        const nqs_batch_item &it = items[k];
-        if (!valid_handle(it.ham)) return fail(NQS_E_ARG, "invalid handle in batch item");
-        if (it.n < 0 || it.n > (int64_t(1) << 30)) return fail(NQS_E_ARG, "bad batch size");
-        if (it.n > 0 && (!it.samples || !it.log_amp || !it.phase || !it.eloc))
-            return fail(NQS_E_ARG, "null pointer in batch item");
-        for (int m = 0; m < k; ++m)
-            if (items[m].ham == it.ham) return fail(NQS_E_ARG, "a handle appears twice in a batch");
-    }
-    int dev = 0, n_cu = 0;
-    NQS_HIP(hipGetDevice(&dev));
-    NQS_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-
+    std::vector<nqs::JobDesc> jobs;
+    std::vector<nqs::WorkItem> work;
+    nqs::BatchShape shape{};
+    int rc = nqs::detail::plan_batch(items, n_items, threads, st, &jobs, &work, &shape);
+    if (rc) return rc;
     nqs_batch b = new (std::nothrow) nqs_batch_s();
     if (!b) return fail(NQS_E_NOMEM, "host allocation failed");
     b->precision = precision;
     b->n_jobs = n_items;
-    std::vector<nqs::JobDesc> jobs(n_items);
-    std::vector<int64_t> cost(n_items);
-    nqs::BatchShape shape{};
-    shape.threads = th;
-    shape.max_filter_log2 = 7;
-    for (int k = 0; k < n_items; ++k) {
-        const nqs_batch_item &it = items[k];
-        nqs_ham h = it.ham;
-        nqs::Tuning t = h->tune;
-        t.threads = th;
-        const nqs::EvalLaunch L = nqs::plan_eval(h->dt, std::max<int64_t>(it.n, 1), false, &t);
-        int rc = ensure_scratch(h, std::max<int64_t>(it.n, 1), L.n_chunks, st);
-        if (rc) {
-            batch_free(b);
-            return rc;
-        }
-        nqs::JobDesc &J = jobs[k];
-        J.tab = h->dt;
-        J.sc = scratch_of(h);
-        J.sc.filter_log2 = L.filter_log2;
-        J.samples = it.samples;
-        J.weights = it.weights;
-        J.log_amp = it.log_amp;
-        J.phase = it.phase;
-        J.eloc = it.eloc;
-        J.n = it.n;
-        J.g_first = L.g_first;
-        J.chunk_len = L.chunk_len;
-        J.n_chunks = L.n_chunks;
-        const int w2 = h->words == 2 ? 1 : 0;
-        J.kind = !h->dt.sector_filter ? (w2 ? nqs::kJobW2Nosec : nqs::kJobW1Nosec)
-                 : h->dt.sector32     ? (w2 ? nqs::kJobW2S32 : nqs::kJobW1S32)
-                                      : (w2 ? nqs::kJobW2S64 : nqs::kJobW1S64);
-        J.capacity = h->slot_cap;
-        shape.max_filter_log2 = std::max(shape.max_filter_log2, L.filter_log2);
-        shape.max_n = std::max(shape.max_n, it.n);
-        shape.max_clear = std::max<int64_t>(shape.max_clear,
-                                            std::max<int64_t>(h->slot_cap, int64_t(1) << L.filter_log2));
-        cost[k] = it.n * (h->dt.n_groups - L.g_first);
-        b->hams.push_back(h);
-        b->ns.push_back(it.n);
-    }
-    // work list: largest jobs first (the persistent kernel drains it in order),
-    // chunk-major within a job so consecutive items share group records
-    std::vector<int> order(n_items);
-    for (int k = 0; k < n_items; ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
-    std::vector<nqs::WorkItem> work;
-    for (int k : order) {
-        const nqs::JobDesc &J = jobs[k];
-        if (J.n == 0 || J.chunk_len == 0) continue;
-        const int64_t tiles = (J.n + th - 1) / th;
-        for (int64_t c = 0; c < J.n_chunks; ++c)
-            for (int64_t t = 0; t < tiles; ++t)
-                work.push_back(nqs::WorkItem{k, static_cast<int32_t>(c), static_cast<int32_t>(t), 0});
-    }
-    if (work.size() >= (size_t(1) << 31)) {
-        batch_free(b);
-        return fail(NQS_E_ARG, "work list too long");
-    }
     b->n_items = static_cast<int>(work.size());
-    const size_t lds = nqs::batch_lds_bytes(th, shape.max_filter_log2);
-    const int per_cu_lds = static_cast<int>((160 * 1024) / lds);
-    const int per_cu_waves = (32 * 64) / th;
-    shape.lookup_blocks = static_cast<unsigned>(n_cu * std::max(1, std::min(per_cu_lds, per_cu_waves)));
     b->shape = shape;
+    for (int k = 0; k < n_items; ++k) {
+        b->hams.push_back(items[k].ham);
+        b->ns.push_back(items[k].n);
+    }
     hipError_t e = hipMalloc(&b->d_jobs, sizeof(nqs::JobDesc) * n_items);
     if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(nqs::WorkItem) * std::max<size_t>(work.size(), 1));
     if (e == hipSuccess) e = hipMalloc(&b->d_next, sizeof(unsigned));
@@ -821,3 +750,123 @@ int nqs_batch_destroy(nqs_batch b) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ internals shared with the server
+
+namespace nqs {
+namespace detail {
+
+int fail(int code, const std::string &msg) { return ::fail(code, msg); }
+
+bool valid_handle(nqs_ham h) { return ::valid_handle(h); }
+
+int64_t table_bytes(nqs_ham h) { return h->table_bytes; }
+
+int64_t scratch_bytes(nqs_ham h) {
+    return static_cast<int64_t>(h->slot_bytes) + h->shx_cap * 4 + h->part_cap * 8 +
+           static_cast<int64_t>(kSmallBytes + kMaxFilterWords * 4);
+}
+
+int reserve(nqs_ham h, int64_t n, int threads, hipStream_t st) {
+    nqs::Tuning t = h->tune;
+    if (threads) t.threads = threads;
+    n = std::max<int64_t>(n, 1);
+    const nqs::EvalLaunch L = nqs::plan_eval(h->dt, n, false, &t);
+    // A batch of m <= n samples plans about (items per GPU) / tiles(m) chunks,
+    // so m * chunks(m) <= items * threads + m: size the partials for that.
+    const int64_t items = int64_t(t.blocks_per_cu ? t.blocks_per_cu : 4) * 256 * 1024 / L.threads;
+    const int64_t bound = (items * L.threads + n + n - 1) / n;
+    return ensure_scratch(h, n, std::max<int64_t>(L.n_chunks, bound), st);
+}
+
+void mark_evaluated(nqs_ham h, int64_t n) {
+    h->last_pairs = n * h->dt.n_groups;
+    h->ever_evaluated = true;
+    h->profiled = false;
+}
+
+int plan_batch(const nqs_batch_item *items, int n_items, int threads, hipStream_t st,
+               std::vector<JobDesc> *jobs_out, std::vector<WorkItem> *work_out,
+               BatchShape *shape_out) {
+    if (n_items <= 0 || !items) return fail(NQS_E_ARG, "a batch needs at least one item");
+    if (!(threads == 0 || threads == 256 || threads == 512 || threads == 1024))
+        return fail(NQS_E_ARG, "threads must be 0, 256, 512 or 1024");
+    const int th = threads ? threads : 1024;
+    for (int k = 0; k < n_items; ++k) {
+        const nqs_batch_item &it = items[k];
+        if (!::valid_handle(it.ham)) return fail(NQS_E_ARG, "invalid handle in batch item");
+        if (it.n < 0 || it.n > (int64_t(1) << 30)) return fail(NQS_E_ARG, "bad batch size");
+        if (it.n > 0 && (!it.samples || !it.log_amp || !it.phase || !it.eloc))
+            return fail(NQS_E_ARG, "null pointer in batch item");
+        for (int m = 0; m < k; ++m)
+            if (items[m].ham == it.ham) return fail(NQS_E_ARG, "a handle appears twice in a batch");
+    }
+    int dev = 0, n_cu = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he == hipSuccess) he = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (he != hipSuccess) return fail_hip(he, "querying the device");
+
+    std::vector<JobDesc> &jobs = *jobs_out;
+    std::vector<WorkItem> &work = *work_out;
+    jobs.assign(n_items, JobDesc{});
+    work.clear();
+    std::vector<int64_t> cost(n_items);
+    BatchShape shape{};
+    shape.threads = th;
+    shape.max_filter_log2 = 7;
+    for (int k = 0; k < n_items; ++k) {
+        const nqs_batch_item &it = items[k];
+        nqs_ham h = it.ham;
+        nqs::Tuning t = h->tune;
+        t.threads = th;
+        const EvalLaunch L = plan_eval(h->dt, std::max<int64_t>(it.n, 1), false, &t);
+        const int rc = ensure_scratch(h, std::max<int64_t>(it.n, 1), L.n_chunks, st);
+        if (rc) return rc;
+        JobDesc &J = jobs[k];
+        J.tab = h->dt;
+        J.sc = scratch_of(h);
+        J.sc.filter_log2 = L.filter_log2;
+        J.samples = it.samples;
+        J.weights = it.weights;
+        J.log_amp = it.log_amp;
+        J.phase = it.phase;
+        J.eloc = it.eloc;
+        J.n = it.n;
+        J.g_first = L.g_first;
+        J.chunk_len = L.chunk_len;
+        J.n_chunks = L.n_chunks;
+        const int w2 = h->words == 2 ? 1 : 0;
+        J.kind = !h->dt.sector_filter ? (w2 ? kJobW2Nosec : kJobW1Nosec)
+                 : h->dt.sector32     ? (w2 ? kJobW2S32 : kJobW1S32)
+                                      : (w2 ? kJobW2S64 : kJobW1S64);
+        J.capacity = h->slot_cap;
+        shape.max_filter_log2 = std::max(shape.max_filter_log2, L.filter_log2);
+        shape.max_n = std::max(shape.max_n, it.n);
+        shape.max_clear = std::max<int64_t>(shape.max_clear,
+                                            std::max<int64_t>(h->slot_cap, int64_t(1) << L.filter_log2));
+        cost[k] = it.n * (h->dt.n_groups - L.g_first);
+    }
+    // work list: largest jobs first (the persistent kernel drains it in order),
+    // chunk-major within a job so consecutive items share group records
+    std::vector<int> order(n_items);
+    for (int k = 0; k < n_items; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    for (int k : order) {
+        const JobDesc &J = jobs[k];
+        if (J.n == 0 || J.chunk_len == 0) continue;
+        const int64_t tiles = (J.n + th - 1) / th;
+        for (int64_t c = 0; c < J.n_chunks; ++c)
+            for (int64_t t = 0; t < tiles; ++t)
+                work.push_back(WorkItem{k, static_cast<int32_t>(c), static_cast<int32_t>(t), 0});
+    }
+    if (work.size() >= (size_t(1) << 31)) return fail(NQS_E_ARG, "work list too long");
+    const size_t lds = batch_lds_bytes(th, shape.max_filter_log2);
+    const int per_cu_lds = static_cast<int>((160 * 1024) / lds);
+    const int per_cu_waves = (32 * 64) / th;
+    shape.lookup_blocks = static_cast<unsigned>(n_cu * std::max(1, std::min(per_cu_lds, per_cu_waves)));
+    *shape_out = shape;
+    return NQS_OK;
+}
+
+}  // namespace detail
+}  // namespace nqs
