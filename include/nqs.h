@@ -94,6 +94,27 @@ int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *
                    const uint64_t *z_masks, const double *coeffs, const uint64_t *spin_masks,
                    void *hip_stream);
 
+/*
+ * Integral form (the paper's own evaluator, Slater-Condon rules of Sec.
+ * III-B): a handle whose matrix elements come from h_pq and the chemists'
+ * (pq|rs) instead of Pauli terms, for the ONV ordering of Sec. II-A (spin
+ * orbital (p, alpha) = qubit 2p, (p, beta) = qubit 2p + 1, n_qubits =
+ * 2 n_orbitals <= 126).  The Hamiltonian is
+ *   H = sum h_pq a+_{ps} a_{qs} + 1/2 sum (pq|rs) a+_{ps} a+_{rt} a_{st} a_{qs},
+ * and the table holds the X = 0 group and every spin-conserving single and
+ * double flip (the same groups as the Jordan-Wigner table of dense
+ * integrals).  (pq|rs) is stored once per 8-fold orbit, so the resident
+ * data are O(K^4 / 8) doubles instead of O(K^4) Pauli strings.
+ *   h1e: host [K][K] double, symmetric.   eri: host [K][K][K][K] double with
+ *   the 8-fold symmetry of real orbitals (checked to 1e-12 of the largest
+ *   integral).
+ * Evaluates in FP64 only (NQS_E_ARG for NQS_FP32_KAHAN); the debug dump
+ * records lookups but no sign bits.  Errors: NQS_E_ARG, NQS_E_RANGE,
+ * NQS_E_NOMEM, NQS_E_DEVICE.
+ */
+int nqs_ham_create_integrals(nqs_ham *out, int n_orbitals, const double *h1e, const double *eri,
+                             void *hip_stream);
+
 /* Group count G, merged term count T and device bytes held by the handle
  * (table plus scratch). */
 int nqs_ham_info(nqs_ham h, int64_t *n_groups, int64_t *n_terms, int64_t *device_bytes);

@@ -33,7 +33,8 @@ NQS_FP32_KAHAN = 1
 _PRECISION = {"fp64": NQS_FP64, "fp32k": NQS_FP32_KAHAN, "fp32_kahan": NQS_FP32_KAHAN}
 
 # Every symbol include/nqs.h declares.
-EXPORTS = ("nqs_last_error", "nqs_version", "nqs_ham_create", "nqs_ham_info", "nqs_ham_destroy",
+EXPORTS = ("nqs_last_error", "nqs_version", "nqs_ham_create", "nqs_ham_create_integrals",
+           "nqs_ham_info", "nqs_ham_destroy",
            "nqs_table_host", "nqs_eloc_eval", "nqs_energy", "nqs_sync", "nqs_eval_stats",
            "nqs_debug_dump", "nqs_profile", "nqs_last_kernel_ms", "nqs_set_tuning",
            "nqs_get_tuning", "nqs_autotune", "nqs_batch_create", "nqs_batch_launch",
@@ -87,6 +88,7 @@ def load_library(path: str = LIB_PATH):
         "nqs_last_error": (ctypes.c_char_p, []),
         "nqs_version": (I, []),
         "nqs_ham_create": (I, [P, I, I64, P, P, P, P, P]),
+        "nqs_ham_create_integrals": (I, [P, I, P, P, P]),
         "nqs_ham_info": (I, [P, P, P, P]),
         "nqs_ham_destroy": (I, [P]),
         "nqs_table_host": (I, [I, I64, P, P, P, P, P, P, P, P, P]),
@@ -195,6 +197,23 @@ class Hamiltonian:
             self.close()
         except Exception:
             pass
+
+    @classmethod
+    def from_integrals(cls, h1e, eri, stream=None):
+        """nqs_ham_create_integrals: the Slater-Condon form from h_pq and (pq|rs)."""
+        lib = load_library()
+        h1e = np.ascontiguousarray(np.asarray(h1e, dtype=np.float64))
+        eri = np.ascontiguousarray(np.asarray(eri, dtype=np.float64))
+        K = h1e.shape[0]
+        if h1e.shape != (K, K) or eri.shape != (K, K, K, K):
+            raise ValueError("h1e must be [K, K] and eri [K, K, K, K]")
+        h = ctypes.c_void_p()
+        _check(lib.nqs_ham_create_integrals(ctypes.byref(h), K, h1e.ctypes.data, eri.ctypes.data,
+                                            _stream(stream)))
+        self = cls.__new__(cls)
+        self._h = h
+        self.n_qubits = 2 * K
+        return self
 
     @property
     def handle(self):

@@ -135,6 +135,8 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
     if (n < 0) return fail(NQS_E_ARG, "n < 0");
     if (precision != NQS_FP64 && precision != NQS_FP32_KAHAN)
         return fail(NQS_E_ARG, "unknown precision");
+    if (h->dt.sc && precision != NQS_FP64)
+        return fail(NQS_E_ARG, "the integral form evaluates in FP64 only");
     if (n == 0) return NQS_OK;
     if (!samples || !log_amp || !phase || !eloc)
         return fail(NQS_E_ARG, "null sample, amplitude, phase or output pointer");
@@ -202,23 +204,15 @@ int nqs_table_host(int n_qubits, int64_t n_terms, const uint64_t *x_masks,
     return NQS_OK;
 }
 
-int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *x_masks,
-                   const uint64_t *z_masks, const double *coeffs, const uint64_t *spin_masks,
-                   void *hip_stream) {
-    if (!out) return fail(NQS_E_ARG, "null handle output");
-    *out = nullptr;
-    nqs::HostTable T;
-    std::string err;
-    int rc;
-    try {
-        rc = nqs::build_table(n_qubits, n_terms, x_masks, z_masks, coeffs, spin_masks, &T, &err);
-    } catch (const std::bad_alloc &) {
-        return fail(NQS_E_NOMEM, "host allocation failed");
-    }
-    if (rc) return fail(rc, err);
-    if (T.n_groups >= kMaxGroups) return fail(NQS_E_ARG, "more than 2^26 X groups");
-    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+}  // extern "C"
 
+namespace {
+
+// Upload a host table (and, for the integral form, h_pq and packed (pq|rs))
+// into one device allocation and make a handle of it.
+int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<double> *h1,
+                  const std::vector<double> *eri, int sc_k, hipStream_t st) {
+    if (T.n_groups >= kMaxGroups) return fail(NQS_E_ARG, "more than 2^26 X groups");
     const int64_t G = T.n_groups, Tn = T.n_terms;
     // one allocation holding every table array, each 256-byte aligned
     std::vector<float> tc32(2 * static_cast<size_t>(Tn));
@@ -244,6 +238,8 @@ int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *
         {T.tc.data(), sizeof(double) * T.tc.size(), 0},
         {tc32.data(), sizeof(float) * tc32.size(), 0},
         {lh.r, sizeof(lh.r), 0},
+        {h1 ? h1->data() : nullptr, h1 ? sizeof(double) * h1->size() : 0, 0},
+        {eri ? eri->data() : nullptr, eri ? sizeof(double) * eri->size() : 0, 0},
     };
     size_t total = 0;
     for (Piece &p : pieces) {
@@ -259,7 +255,7 @@ int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *
     }
     if (hipMalloc(&h->table_mem, total) != hipSuccess) {
         delete h;
-        return fail(NQS_E_NOMEM, "device allocation of the Pauli table failed");
+        return fail(NQS_E_NOMEM, "device allocation of the Hamiltonian table failed");
     }
     if (hipMalloc(&h->small, kSmallBytes) != hipSuccess ||
         hipMalloc(&h->filter, kMaxFilterWords * 4) != hipSuccess) {
@@ -281,7 +277,7 @@ int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *
         (void)hipFree(h->small);
         (void)hipFree(h->filter);
         delete h;
-        return fail_hip(e, "uploading the Pauli table");
+        return fail_hip(e, "uploading the Hamiltonian table");
     }
     h->table_bytes = static_cast<int64_t>(total);
     h->words = T.words;
@@ -294,9 +290,13 @@ int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *
     d.tc = reinterpret_cast<const double *>(base + pieces[5].off);
     d.tc32 = reinterpret_cast<const float *>(base + pieces[6].off);
     d.hr = reinterpret_cast<const uint32_t *>(base + pieces[7].off);
+    d.sc_h1 = h1 ? reinterpret_cast<const double *>(base + pieces[8].off) : nullptr;
+    d.sc_eri = eri ? reinterpret_cast<const double *>(base + pieces[9].off) : nullptr;
+    d.sc = h1 ? 1 : 0;
+    d.sc_k = sc_k;
     d.n_groups = G;
     d.n_terms = Tn;
-    d.n_qubits = n_qubits;
+    d.n_qubits = T.n_qubits;
     d.has_diagonal = T.has_diagonal ? 1 : 0;
     d.sector_filter = T.sector_filter ? 1 : 0;
     d.sector32 = T.sector32 ? 1 : 0;
@@ -306,6 +306,78 @@ int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *
     d.spin_b1 = T.spin[1][1];
     *out = h;
     return NQS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nqs_ham_create(nqs_ham *out, int n_qubits, int64_t n_terms, const uint64_t *x_masks,
+                   const uint64_t *z_masks, const double *coeffs, const uint64_t *spin_masks,
+                   void *hip_stream) {
+    if (!out) return fail(NQS_E_ARG, "null handle output");
+    *out = nullptr;
+    nqs::HostTable T;
+    std::string err;
+    int rc;
+    try {
+        rc = nqs::build_table(n_qubits, n_terms, x_masks, z_masks, coeffs, spin_masks, &T, &err);
+        if (rc) return fail(rc, err);
+        return create_handle(out, T, nullptr, nullptr, 0, static_cast<hipStream_t>(hip_stream));
+    } catch (const std::bad_alloc &) {
+        return fail(NQS_E_NOMEM, "host allocation failed");
+    }
+}
+
+int nqs_ham_create_integrals(nqs_ham *out, int n_orbitals, const double *h1e, const double *eri,
+                             void *hip_stream) {
+    if (!out) return fail(NQS_E_ARG, "null handle output");
+    *out = nullptr;
+    if (!h1e || !eri) return fail(NQS_E_ARG, "null integral arrays");
+    const int K = n_orbitals;
+    if (K < 1 || 2 * K > nqs::kMaxQubits) return fail(NQS_E_RANGE, "n_orbitals must be in [1, 63]");
+    try {
+        const size_t K2 = size_t(K) * K;
+        double scale = 0.0;
+        for (size_t k = 0; k < K2; ++k) {
+            if (!std::isfinite(h1e[k])) return fail(NQS_E_ARG, "non-finite h1e");
+            scale = std::max(scale, std::fabs(h1e[k]));
+        }
+        for (size_t k = 0; k < K2 * K2; ++k) {
+            if (!std::isfinite(eri[k])) return fail(NQS_E_ARG, "non-finite eri");
+            scale = std::max(scale, std::fabs(eri[k]));
+        }
+        const double tol = 1e-12 * std::max(scale, 1e-300);
+        auto E = [&](int p, int q, int r, int s) { return eri[((size_t(p) * K + q) * K + r) * K + s]; };
+        for (int p = 0; p < K; ++p)
+            for (int q = 0; q < K; ++q)
+                if (std::fabs(h1e[size_t(p) * K + q] - h1e[size_t(q) * K + p]) > tol)
+                    return fail(NQS_E_ARG, "h1e is not symmetric");
+        const int npair = K * (K + 1) / 2;
+        std::vector<double> packed(size_t(npair) * (npair + 1) / 2);
+        for (int p = 0; p < K; ++p)
+            for (int q = 0; q < K; ++q)
+                for (int r = 0; r < K; ++r)
+                    for (int s = 0; s < K; ++s) {
+                        const double v = E(p, q, r, s);
+                        // the 8-fold permutational symmetry of real orbitals
+                        if (std::fabs(v - E(q, p, r, s)) > tol || std::fabs(v - E(p, q, s, r)) > tol ||
+                            std::fabs(v - E(r, s, p, q)) > tol)
+                            return fail(NQS_E_ARG, "eri lacks the 8-fold symmetry of real orbitals");
+                        if (p >= q && r >= s) {
+                            const size_t pq = size_t(p) * (p + 1) / 2 + q, rs = size_t(r) * (r + 1) / 2 + s;
+                            if (pq >= rs) packed[pq * (pq + 1) / 2 + rs] = v;
+                        }
+                    }
+        std::vector<double> h1(h1e, h1e + K2);
+        nqs::HostTable T;
+        std::string err;
+        const int rc = nqs::build_flip_table(K, &T, &err);
+        if (rc) return fail(rc, err);
+        return create_handle(out, T, &h1, &packed, K, static_cast<hipStream_t>(hip_stream));
+    } catch (const std::bad_alloc &) {
+        return fail(NQS_E_NOMEM, "host allocation failed");
+    }
 }
 
 int nqs_ham_info(nqs_ham h, int64_t *n_groups, int64_t *n_terms, int64_t *device_bytes) {
@@ -839,6 +911,7 @@ int plan_batch(const nqs_batch_item *items, int n_items, int threads, hipStream_
         J.kind = !h->dt.sector_filter ? (w2 ? kJobW2Nosec : kJobW1Nosec)
                  : h->dt.sector32     ? (w2 ? kJobW2S32 : kJobW1S32)
                                       : (w2 ? kJobW2S64 : kJobW1S64);
+        if (h->dt.sc) J.kind += kJobIntegrals;
         J.capacity = h->slot_cap;
         shape.max_filter_log2 = std::max(shape.max_filter_log2, L.filter_log2);
         shape.max_n = std::max(shape.max_n, it.n);

@@ -17,6 +17,10 @@ struct DevTable {
     const double *tc;      // [T] folded coefficients
     const float *tc32;     // [T][2] coefficients as FP32 (hi, lo) pairs
     const uint32_t *hr;    // [128] linear-hash words
+    const double *sc_h1;   // integral form: h_pq [K][K]
+    const double *sc_eri;  // integral form: (pq|rs), 8-fold packed by compound index
+    int sc;                // 1: matrix elements from the integrals (no Pauli terms)
+    int sc_k;              // spatial orbitals of the integral form
     int64_t n_groups;
     int64_t n_terms;
     int n_qubits;
@@ -108,6 +112,7 @@ enum JobKind : int {
     kJobW1Nosec = 0, kJobW2Nosec = 1,
     kJobW1S32 = 2, kJobW2S32 = 3,
     kJobW1S64 = 4, kJobW2S64 = 5,
+    kJobIntegrals = 8,  // added to a sector kind: Slater-Condon elements
 };
 
 struct JobDesc {

@@ -268,6 +268,137 @@ __device__ __forceinline__ double group_sum(const DevTable &tab, int64_t g, cons
     return s;
 }
 
+// ---- integral form (Slater-Condon rules, the evaluator of Sec. III-B)
+//
+// <bra|H|ket> from h_pq and the chemists' (pq|rs) for determinants that
+// differ by at most two spin orbitals; ONV ordering, so a ladder operator on
+// spin orbital j carries (-1)^(occupied orbitals below j).
+
+template <int W>
+__device__ __forceinline__ int parity_below(const Key<W> &s, int j) {
+    int c;
+    if (j < 64) {
+        c = __popcll(s.w[0] & ((1ull << j) - 1ull));
+    } else {
+        c = __popcll(s.w[0]);
+        if constexpr (W == 2) c += __popcll(s.w[1] & ((1ull << (j - 64)) - 1ull));
+    }
+    return c & 1;
+}
+
+template <int W>
+__device__ __forceinline__ void flip_bit(Key<W> &s, int j) {
+    if (W == 1 || j < 64)
+        s.w[0] ^= 1ull << (j & 63);
+    else
+        s.w[W - 1] ^= 1ull << (j & 63);
+}
+
+template <int W>
+__device__ __forceinline__ int lowest(const Key<W> &s) {
+    if (s.w[0]) return __builtin_ctzll(s.w[0]);
+    if constexpr (W == 2) return 64 + __builtin_ctzll(s.w[1]);
+    return 127;
+}
+
+__device__ __forceinline__ double eri_at(const DevTable &tab, int p, int q, int r, int s) {
+    const int64_t pq = p > q ? int64_t(p) * (p + 1) / 2 + q : int64_t(q) * (q + 1) / 2 + p;
+    const int64_t rs = r > s ? int64_t(r) * (r + 1) / 2 + s : int64_t(s) * (s + 1) / 2 + r;
+    return tab.sc_eri[pq > rs ? pq * (pq + 1) / 2 + rs : rs * (rs + 1) / 2 + pq];
+}
+
+template <int W>
+__device__ __forceinline__ double sc_element(const DevTable &tab, const Key<W> &bra,
+                                             const Key<W> &ket) {
+    Key<W> A, I;
+    int na = 0, ni = 0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        A.w[q] = bra.w[q] & ~ket.w[q];  // created
+        I.w[q] = ket.w[q] & ~bra.w[q];  // annihilated
+        na += __popcll(A.w[q]);
+        ni += __popcll(I.w[q]);
+    }
+    if (na != ni) return 0.0;
+    const int K = tab.sc_k;
+    if (na == 1) {
+        const int i = lowest<W>(I), a = lowest<W>(A);
+        if ((i & 1) != (a & 1)) return 0.0;
+        Key<W> st = ket;
+        int sg = parity_below<W>(st, i);
+        flip_bit<W>(st, i);
+        sg ^= parity_below<W>(st, a);
+        const int as = a >> 1, is = i >> 1;
+        double v = tab.sc_h1[as * K + is];
+        // spectators: occupied in ket, except i
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            uint64_t m = ket.w[q] & ~I.w[q];
+            while (m) {
+                const int j = 64 * q + __builtin_ctzll(m);
+                m &= m - 1;
+                const int js = j >> 1;
+                v += eri_at(tab, as, is, js, js);
+                if ((j & 1) == (i & 1)) v -= eri_at(tab, as, js, js, is);
+            }
+        }
+        return sg ? -v : v;
+    }
+    if (na == 2) {
+        const int i = lowest<W>(I), a = lowest<W>(A);
+        Key<W> I2 = I, A2 = A;
+        flip_bit<W>(I2, i);
+        flip_bit<W>(A2, a);
+        const int j = lowest<W>(I2), b = lowest<W>(A2);
+        // |bra> = G a+_a a+_b a_j a_i |ket>
+        Key<W> st = ket;
+        int sg = parity_below<W>(st, i);
+        flip_bit<W>(st, i);
+        sg ^= parity_below<W>(st, j);
+        flip_bit<W>(st, j);
+        sg ^= parity_below<W>(st, b);
+        flip_bit<W>(st, b);
+        sg ^= parity_below<W>(st, a);
+        double v = 0.0;
+        if (((a ^ i) & 1) == 0 && ((b ^ j) & 1) == 0) v += eri_at(tab, a >> 1, i >> 1, b >> 1, j >> 1);
+        if (((a ^ j) & 1) == 0 && ((b ^ i) & 1) == 0) v -= eri_at(tab, a >> 1, j >> 1, b >> 1, i >> 1);
+        return sg ? -v : v;
+    }
+    return 0.0;
+}
+
+template <int W>
+__device__ __forceinline__ double sc_diagonal(const DevTable &tab, const Key<W> &x) {
+    const int K = tab.sc_k;
+    double d = 0.0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        uint64_t m = x.w[q];
+        while (m) {
+            const int i = 64 * q + __builtin_ctzll(m);
+            m &= m - 1;
+            const int is = i >> 1;
+            d += tab.sc_h1[is * K + is];
+            // partners above i
+            Key<W> rest;
+#pragma unroll
+            for (int r = 0; r < W; ++r) rest.w[r] = r < q ? 0ull : (r == q ? m : x.w[r]);
+#pragma unroll
+            for (int r = 0; r < W; ++r) {
+                uint64_t m2 = rest.w[r];
+                while (m2) {
+                    const int j = 64 * r + __builtin_ctzll(m2);
+                    m2 &= m2 - 1;
+                    const int js = j >> 1;
+                    d += eri_at(tab, is, is, js, js);
+                    if ((i & 1) == (j & 1)) d -= eri_at(tab, is, js, js, is);
+                }
+            }
+        }
+    }
+    return d;
+}
+
 // ---- FP32 form with compensation (precision NQS_FP32_KAHAN)
 //
 // Coefficients are stored as FP32 pairs hi + lo (lo = c - hi rounded), the
@@ -334,7 +465,7 @@ __device__ __forceinline__ void ratio_f32(double da, double dphi, float &rr, flo
 // scheduling.  The X = 0 group is left to the finish kernel.  The caller
 // has synchronised the block; load_filter = false reuses the bitmap already
 // in LDS (same Hamiltonian and batch as the previous item).
-template <int W, bool S32, bool SEC, bool DUMP, int P>
+template <int W, bool S32, bool SEC, bool DUMP, int P, bool SCV>
 __device__ __forceinline__ void lookup_item(
     const DevTable &tab, const DevScratch &sc, const uint64_t *__restrict__ samples,
     const double *__restrict__ log_amp, const double *__restrict__ phase, int64_t n,
@@ -419,7 +550,13 @@ __device__ __forceinline__ void lookup_item(
                 if constexpr (P == NQS_FP64) {
                     uint32_t *row =
                         (DUMP && sign_bits) ? sign_bits + (wave0 + l) * sign_words : nullptr;
-                    const double hsum = group_sum<W, DUMP>(tab, g, xl, row, &n_terms);
+                    double hsum;
+                    if constexpr (SCV) {
+                        (void)row;
+                        hsum = sc_element<W>(tab, xl, xp);
+                    } else {
+                        hsum = group_sum<W, DUMP>(tab, g, xl, row, &n_terms);
+                    }
                     double sn, cs;
                     sincos(phase[j] - phl, &sn, &cs);
                     const double mag = exp(log_amp[j] - lal);
@@ -586,20 +723,20 @@ __device__ __forceinline__ void lookup_item(
 }
 
 // Grid form: (sample tiles of blockDim) x (group chunks), one item per block.
-template <int W, bool S32, bool SEC, bool DUMP, int P>
+template <int W, bool S32, bool SEC, bool DUMP, int P, bool SCV>
 __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
     const double *__restrict__ log_amp, const double *__restrict__ phase, int64_t n,
     int64_t g_first, int64_t chunk_len, int32_t *__restrict__ hit_idx,
     uint32_t *__restrict__ sign_bits, int64_t sign_words) {
     extern __shared__ uint4 smem4[];
-    lookup_item<W, S32, SEC, DUMP, P>(tab, sc, samples, log_amp, phase, n, blockIdx.x, blockIdx.y,
+    lookup_item<W, S32, SEC, DUMP, P, SCV>(tab, sc, samples, log_amp, phase, n, blockIdx.x, blockIdx.y,
                                       g_first, chunk_len, true, hit_idx, sign_bits, sign_words,
                                       smem4);
 }
 
 // E_loc(x) = diagonal group sum + sum of the chunk partials in chunk order.
-template <int W, bool DUMP, int P>
+template <int W, bool DUMP, int P, bool SCV>
 __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch &sc,
                                            const uint64_t *__restrict__ samples, int64_t n,
                                            int64_t n_chunks, double *__restrict__ eloc,
@@ -611,7 +748,9 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
         const Key<W> x = load_key<W>(samples, i);
         double re = 0.0, im = 0.0;
         if (tab.has_diagonal) {
-            if constexpr (P == NQS_FP64) {
+            if constexpr (SCV) {
+                re = sc_diagonal<W>(tab, x);
+            } else if constexpr (P == NQS_FP64) {
                 uint32_t *row = (DUMP && sign_bits) ? sign_bits + i * sign_words : nullptr;
                 re = group_sum<W, DUMP>(tab, 0, x, row, &n_terms);
             } else {
@@ -634,13 +773,14 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
     if ((threadIdx.x & 63) == 0 && n_terms) atomicAdd(&sc.counters[3], n_terms);
 }
 
-template <int W, bool DUMP, int P>
+template <int W, bool DUMP, int P, bool SCV>
 __global__ __launch_bounds__(256) void eloc_finish_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n,
     int64_t n_chunks, double *__restrict__ eloc, int32_t *__restrict__ hit_idx,
     uint32_t *__restrict__ sign_bits, int64_t sign_words) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    finish_one<W, DUMP, P>(tab, sc, samples, n, n_chunks, eloc, hit_idx, sign_bits, sign_words, i);
+    finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, eloc, hit_idx, sign_bits, sign_words,
+                                i);
 }
 
 // ------------------------------------------------------------------ batched form
@@ -702,17 +842,21 @@ __global__ __launch_bounds__(kLookupThreads) void batch_lookup_kernel(
         const JobDesc &J = jobs[w.job];
         const bool load = w.job != last_job;
         last_job = w.job;
-#define NQS_ITEM(Wd, S, SE)                                                                    \
-    lookup_item<Wd, S, SE, false, P>(J.tab, J.sc, J.samples, J.log_amp, J.phase, J.n, w.tile, \
-                                     w.chunk, J.g_first, J.chunk_len, load, nullptr, nullptr, 0, \
-                                     smem4)
+#define NQS_ITEM(Wd, S, SE, SCI)                                                               \
+    lookup_item<Wd, S, SE, false, P, SCI>(J.tab, J.sc, J.samples, J.log_amp, J.phase, J.n, w.tile, \
+                                          w.chunk, J.g_first, J.chunk_len, load, nullptr, nullptr, \
+                                          0, smem4)
         switch (J.kind) {
-            case kJobW1Nosec: NQS_ITEM(1, true, false); break;
-            case kJobW1S32: NQS_ITEM(1, true, true); break;
-            case kJobW1S64: NQS_ITEM(1, false, true); break;
-            case kJobW2Nosec: NQS_ITEM(2, true, false); break;
-            case kJobW2S32: NQS_ITEM(2, true, true); break;
-            default: NQS_ITEM(2, false, true); break;
+            case kJobW1Nosec: NQS_ITEM(1, true, false, false); break;
+            case kJobW1S32: NQS_ITEM(1, true, true, false); break;
+            case kJobW1S64: NQS_ITEM(1, false, true, false); break;
+            case kJobW2Nosec: NQS_ITEM(2, true, false, false); break;
+            case kJobW2S32: NQS_ITEM(2, true, true, false); break;
+            case kJobW2S64: NQS_ITEM(2, false, true, false); break;
+            case kJobW1S32 + kJobIntegrals: NQS_ITEM(1, true, true, (P == NQS_FP64)); break;
+            case kJobW2S32 + kJobIntegrals: NQS_ITEM(2, true, true, (P == NQS_FP64)); break;
+            case kJobW2S64 + kJobIntegrals: NQS_ITEM(2, false, true, (P == NQS_FP64)); break;
+            default: break;
         }
 #undef NQS_ITEM
     }
@@ -724,10 +868,22 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(const JobDesc *__rest
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (static_cast<int64_t>(blockIdx.x) * blockDim.x >= J.n) return;  // whole block past the end
     const int64_t chunks = J.chunk_len > 0 ? J.n_chunks : 0;
-    if ((J.kind & 1) == 0)
-        finish_one<1, false, P>(J.tab, J.sc, J.samples, J.n, chunks, J.eloc, nullptr, nullptr, 0, i);
-    else
-        finish_one<2, false, P>(J.tab, J.sc, J.samples, J.n, chunks, J.eloc, nullptr, nullptr, 0, i);
+    const bool integrals = (J.kind & kJobIntegrals) != 0;
+    if ((J.kind & 1) == 0) {
+        if (integrals)
+            finish_one<1, false, NQS_FP64, true>(J.tab, J.sc, J.samples, J.n, chunks, J.eloc,
+                                                 nullptr, nullptr, 0, i);
+        else
+            finish_one<1, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, J.eloc, nullptr,
+                                           nullptr, 0, i);
+    } else {
+        if (integrals)
+            finish_one<2, false, NQS_FP64, true>(J.tab, J.sc, J.samples, J.n, chunks, J.eloc,
+                                                 nullptr, nullptr, 0, i);
+        else
+            finish_one<2, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, J.eloc, nullptr,
+                                           nullptr, 0, i);
+    }
 }
 
 size_t batch_lds_bytes(int threads, int max_filter_log2) {
@@ -932,7 +1088,7 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
     return hipGetLastError();
 }
 
-template <int W, bool S32, bool SEC, bool D, int P>
+template <int W, bool S32, bool SEC, bool D, int P, bool SCV>
 hipError_t launch_lookup(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
                          const uint64_t *samples, const double *log_amp, const double *phase,
                          int32_t *hit_idx, uint32_t *sign_bits, int64_t sign_words,
@@ -940,14 +1096,14 @@ hipError_t launch_lookup(const DevTable &tab, const DevScratch &sc, const EvalLa
     static bool attr_set = false;
     if (!attr_set) {
         const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&eloc_lookup_kernel<W, S32, SEC, D, P>),
+            reinterpret_cast<const void *>(&eloc_lookup_kernel<W, S32, SEC, D, P, SCV>),
             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLookupLds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const dim3 grid(static_cast<unsigned>((L.n + L.threads - 1) / L.threads),
                     static_cast<unsigned>(L.n_chunks));
-    hipLaunchKernelGGL((eloc_lookup_kernel<W, S32, SEC, D, P>), grid, dim3(L.threads), L.lds_bytes, st,
+    hipLaunchKernelGGL((eloc_lookup_kernel<W, S32, SEC, D, P, SCV>), grid, dim3(L.threads), L.lds_bytes, st,
                        tab, sc, samples, log_amp, phase, L.n, L.g_first, L.chunk_len, hit_idx,
                        sign_bits, sign_words);
     return hipGetLastError();
@@ -964,9 +1120,9 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
     const int64_t n = L.n;
     hipError_t e = hipSuccess;
     if (L.chunk_len > 0) {
-#define NQS_LOOKUP(Wd, S, SE, D, Pr)                                                             \
-    e = launch_lookup<Wd, S, SE, D, Pr>(tab, sc, L, samples, log_amp, phase, hit_idx, sign_bits, \
-                                        sign_words, st)
+#define NQS_LOOKUP(Wd, S, SE, D, Pr)                                                       \
+    e = launch_lookup<Wd, S, SE, D, Pr, false>(tab, sc, L, samples, log_amp, phase, hit_idx,  \
+                                               sign_bits, sign_words, st)
 #define NQS_LOOKUP_D(Wd, S, SE)                      \
     if (dump) NQS_LOOKUP(Wd, S, SE, true, NQS_FP64);  \
     else if (f32) NQS_LOOKUP(Wd, S, SE, false, NQS_FP32_KAHAN); \
@@ -974,7 +1130,19 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
         // the sector test needs spin masks (and, checked on the device, one
         // (N_alpha, N_beta) over the batch)
         const bool sec = tab.sector_filter != 0;
-        if (words == 1) {
+        if (tab.sc) {
+#define NQS_LOOKUP_SC(Wd, S, D) \
+    e = launch_lookup<Wd, S, true, D, NQS_FP64, true>(tab, sc, L, samples, log_amp, phase, \
+                                                     hit_idx, sign_bits, sign_words, st)
+            if (words == 1) {
+                if (dump) NQS_LOOKUP_SC(1, true, true); else NQS_LOOKUP_SC(1, true, false);
+            } else if (s32) {
+                if (dump) NQS_LOOKUP_SC(2, true, true); else NQS_LOOKUP_SC(2, true, false);
+            } else {
+                if (dump) NQS_LOOKUP_SC(2, false, true); else NQS_LOOKUP_SC(2, false, false);
+            }
+#undef NQS_LOOKUP_SC
+        } else if (words == 1) {
             if (!sec) { NQS_LOOKUP_D(1, true, false); }
             else if (s32) { NQS_LOOKUP_D(1, true, true); }
             else { NQS_LOOKUP_D(1, false, true); }
@@ -994,9 +1162,18 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
     const int64_t chunks = L.chunk_len > 0 ? L.n_chunks : 0;
     const dim3 fgrid(static_cast<unsigned>((n + 255) / 256));
 #define NQS_FINISH(Wd, D, Pr)                                                                 \
-    hipLaunchKernelGGL((eloc_finish_kernel<Wd, D, Pr>), fgrid, dim3(256), 0, st, tab, sc, samples, \
-                       n, chunks, eloc, hit_idx, sign_bits, sign_words)
-    if (words == 1) {
+    hipLaunchKernelGGL((eloc_finish_kernel<Wd, D, Pr, false>), fgrid, dim3(256), 0, st, tab, sc,  \
+                       samples, n, chunks, eloc, hit_idx, sign_bits, sign_words)
+#define NQS_FINISH_SC(Wd, D)                                                                     \
+    hipLaunchKernelGGL((eloc_finish_kernel<Wd, D, NQS_FP64, true>), fgrid, dim3(256), 0, st, tab, \
+                       sc, samples, n, chunks, eloc, hit_idx, sign_bits, sign_words)
+    if (tab.sc) {
+        if (words == 1) {
+            if (dump) NQS_FINISH_SC(1, true); else NQS_FINISH_SC(1, false);
+        } else {
+            if (dump) NQS_FINISH_SC(2, true); else NQS_FINISH_SC(2, false);
+        }
+    } else if (words == 1) {
         if (dump) NQS_FINISH(1, true, NQS_FP64);
         else if (f32) NQS_FINISH(1, false, NQS_FP32_KAHAN);
         else NQS_FINISH(1, false, NQS_FP64);
@@ -1006,6 +1183,7 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
         else NQS_FINISH(2, false, NQS_FP64);
     }
 #undef NQS_FINISH
+#undef NQS_FINISH_SC
     return hipGetLastError();
 }
 

@@ -193,4 +193,66 @@ int build_table(int n_qubits, int64_t n_terms, const uint64_t *x, const uint64_t
     return NQS_OK;
 }
 
+int build_flip_table(int K, HostTable *out, std::string *err) {
+    if (K < 1 || 2 * K > kMaxQubits) {
+        *err = "n_orbitals must be in [1, 63]";
+        return NQS_E_RANGE;
+    }
+    HostTable &T = *out;
+    T = HostTable();
+    const int nq = 2 * K;
+    T.n_qubits = nq;
+    T.words = nq <= 63 ? 1 : 2;
+    for (int p = 0; p < K; ++p) {
+        const int a = 2 * p, b = 2 * p + 1;
+        if (a < 64) T.spin[0][0] |= 1ull << a; else T.spin[0][1] |= 1ull << (a - 64);
+        if (b < 64) T.spin[1][0] |= 1ull << b; else T.spin[1][1] |= 1ull << (b - 64);
+    }
+    T.sector_filter = K <= 64;
+    T.sector32 = K <= 32;
+    struct M { uint64_t lo, hi; };
+    auto bit = [](int q) { return q < 64 ? M{1ull << q, 0} : M{0, 1ull << (q - 64)}; };
+    auto orr = [](M x, M y) { return M{x.lo | y.lo, x.hi | y.hi}; };
+    std::vector<M> flips;
+    flips.push_back(M{0, 0});
+    for (int s = 0; s < 2; ++s) {
+        for (int p = 0; p < K; ++p)
+            for (int q = p + 1; q < K; ++q) {
+                flips.push_back(orr(bit(2 * p + s), bit(2 * q + s)));
+                for (int r = q + 1; r < K; ++r)
+                    for (int t = r + 1; t < K; ++t)
+                        flips.push_back(orr(orr(bit(2 * p + s), bit(2 * q + s)),
+                                            orr(bit(2 * r + s), bit(2 * t + s))));
+            }
+    }
+    for (int p = 0; p < K; ++p)
+        for (int q = p + 1; q < K; ++q)
+            for (int r = 0; r < K; ++r)
+                for (int t = r + 1; t < K; ++t)
+                    flips.push_back(orr(orr(bit(2 * p), bit(2 * q)), orr(bit(2 * r + 1), bit(2 * t + 1))));
+    std::sort(flips.begin(), flips.end(), [](const M &x, const M &y) {
+        return x.hi != y.hi ? x.hi < y.hi : x.lo < y.lo;
+    });
+    const LinearHash lh;
+    T.n_groups = static_cast<int64_t>(flips.size());
+    T.n_terms = 0;
+    T.has_diagonal = true;
+    T.gx.resize(2 * T.n_groups);
+    T.gsec.resize(2 * T.n_groups);
+    T.ghm.resize(2 * T.n_groups);
+    T.goff.assign(T.n_groups + 1, 0);
+    for (int64_t g = 0; g < T.n_groups; ++g) {
+        const uint64_t x0 = flips[g].lo, x1 = flips[g].hi;
+        T.gx[2 * g] = x0;
+        T.gx[2 * g + 1] = x1;
+        const int pa = popc2(x0 & T.spin[0][0], x1 & T.spin[0][1]);
+        const int pb = popc2(x0 & T.spin[1][0], x1 & T.spin[1][1]);
+        T.gsec[2 * g] = compress_bits(x0, x1, T.spin[0][0], T.spin[0][1]);
+        T.gsec[2 * g + 1] = compress_bits(x0, x1, T.spin[1][0], T.spin[1][1]);
+        T.ghm[2 * g] = lh(x0, x1);
+        T.ghm[2 * g + 1] = static_cast<uint32_t>(pa / 2) | (static_cast<uint32_t>(pb / 2) << 8);
+    }
+    return NQS_OK;
+}
+
 }  // namespace nqs

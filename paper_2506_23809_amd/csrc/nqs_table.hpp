@@ -48,6 +48,12 @@ constexpr uint32_t kSectorNeverKey = 0xFFFFu;
 // Bits of w selected by mask, packed to the low end in mask order.
 uint64_t compress_bits(uint64_t w0, uint64_t w1, uint64_t m0, uint64_t m1);
 
+// Flip table of a molecular Hamiltonian in the ONV ordering (spin orbital
+// (p, alpha) = qubit 2p, (p, beta) = qubit 2p + 1): the X = 0 group and every
+// spin-conserving single and double flip, as groups without Pauli terms.
+// Matrix elements then come from the integrals (Slater-Condon rules).
+int build_flip_table(int n_orbitals, HostTable *out, std::string *err);
+
 // Returns 0 or a negative NQS_E_* code with *err describing it.
 int build_table(int n_qubits, int64_t n_terms, const uint64_t *x, const uint64_t *z,
                 const double *c, const uint64_t *spin_masks, HostTable *out, std::string *err);
