@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="nq40", choices=["nq12", "nq40", "nq100"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32k"])
+    ap.add_argument("--strategy", default="auto", choices=["auto", "stream", "enum"],
+                    help="lookup strategy: group streaming or flip enumeration (auto: "
+                         "enumeration where the table allows it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--mode", default="single", choices=["single", "batched", "serve"],
@@ -143,6 +146,8 @@ def main():
     ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t0) * 1e3
+    if args.strategy != "auto":
+        ham.set_tuning(strategy=args.strategy)
     G, T, table_bytes = ham.info()
     words = 1 if w.n_qubits <= 63 else 2
     log(f"table: {G} groups, {T} terms, {table_bytes / 1e6:.1f} MB, setup {setup_ms:.1f} ms")

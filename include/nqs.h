@@ -220,17 +220,31 @@ int nqs_debug_dump(nqs_ham h, int64_t n, const uint64_t *samples, const double *
 
 /* ------------------------------------------------------------------ tuning
  *
- * Launch parameters of the lookup kernel.  Zero fields take the built-in
+ * Launch parameters of the lookup stage.  Zero fields take the built-in
  * default.  They change speed only: results do not depend on threads or
- * filter_bits, and blocks_per_cu only moves the group-chunk boundaries, which
- * reorders FP sums within rounding.
+ * filter_bits, while blocks_per_cu (group-chunk boundaries) and strategy
+ * (the order in which a sample's hits are summed) reorder FP sums within
+ * rounding.
+ *
+ * Strategies (Eq. 5 evaluated two ways, same hits and matrix elements):
+ *   NQS_STRATEGY_STREAM: every X group passes every sample (exact sector
+ *     test, Bloom filter, hash probe); works for any table.
+ *   NQS_STRATEGY_ENUM: each sample's spin-conserving single and double
+ *     flips are enumerated from its occupied and virtual orbitals, and only
+ *     those are probed.  Needs spin masks covering every qubit and no group
+ *     flipping more than four qubits; a batch whose samples span several
+ *     sectors (or whose occupation does not fit the on-chip round) runs the
+ *     streaming kernel instead, decided on the device.
+ *   NQS_STRATEGY_AUTO (0): enumeration when the table allows it.
  */
+enum { NQS_STRATEGY_AUTO = 0, NQS_STRATEGY_STREAM = 1, NQS_STRATEGY_ENUM = 2 };
+
 typedef struct {
-    int32_t threads;       /* lookup block size: 256, 512 or 1024 (default 1024) */
+    int32_t threads;       /* streaming block size: 256, 512 or 1024 (default 1024) */
     int32_t filter_bits;   /* on-chip filter bits per sample, 4..64 (default 16; the
                               bitmap is capped at 128 KB) */
-    int32_t blocks_per_cu; /* target work items per compute unit, 1..64 (default 4) */
-    int32_t reserved;      /* must be 0 */
+    int32_t blocks_per_cu; /* streaming work items per compute unit, 1..64 (default 4) */
+    int32_t strategy;      /* NQS_STRATEGY_* (default AUTO) */
 } nqs_tuning;
 
 /* Set (t != NULL) or clear (t == NULL) the handle's tuning.  NQS_E_ARG on a
@@ -240,11 +254,13 @@ int nqs_set_tuning(nqs_ham h, const nqs_tuning *t);
 int nqs_get_tuning(nqs_ham h, nqs_tuning *out);
 
 /*
- * Autotuner.  Times candidate tunings (threads x filter bits x blocks per
- * CU) with HIP events on hip_stream, evaluating this batch (arguments as
+ * Autotuner.  Times candidate tunings (streaming: threads x filter bits x
+ * blocks per CU; enumeration, where allowed: filter bits) with HIP events on
+ * hip_stream, evaluating this batch (arguments as
  * nqs_eloc_eval; eloc receives the last result), and keeps the fastest.  The
- * choice is cached per shape class (mask words, sector-test form, log2 of
- * the batch size and of the group count, precision) in a JSON file at
+ * choice is cached per shape class (mask words, sector-test form, whether
+ * enumeration applies, log2 of the batch size and of the group count,
+ * precision) in a JSON file at
  * cache_path (NULL: no cache); a cached class is applied without timing.
  * The chosen tuning is set on the handle and returned in *best, with its
  * time in *best_ms (-1 when it came from the cache).  Synchronises the
@@ -261,7 +277,10 @@ int nqs_autotune(nqs_ham h, int64_t n, const uint64_t *samples, const double *lo
  * hash builds run as one (tile, job) grid, and all lookup work is one list
  * of (job, sample tile, group chunk) items drained by a single persistent
  * kernel (blocks take items from an atomic counter until the list is
- * empty).  Results equal those of nqs_eloc_eval with the same tunings.
+ * empty); enumeration jobs add items of sample rounds.  Results equal those
+ * of nqs_eloc_eval with the same tunings; a batch planned with threads other
+ * than 1024 runs every job with the streaming strategy.  Integral-form jobs
+ * (nqs_ham_create_integrals) evaluate in FP64 whatever the batch precision.
  */
 typedef struct {
     nqs_ham ham;              /* distinct handles within one batch */

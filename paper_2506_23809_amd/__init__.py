@@ -49,14 +49,20 @@ class ServerConfig(ctypes.Structure):
                 ("threads", ctypes.c_int32)]
 
 
+STRATEGIES = {"auto": 0, "stream": 1, "enum": 2}
+STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
+
+
 class Tuning(ctypes.Structure):
-    """nqs_tuning: lookup block size, filter bits per sample, work items per CU."""
+    """nqs_tuning: streaming block size, filter bits per sample, work items per CU,
+    lookup strategy (0 auto, 1 streaming, 2 enumeration)."""
     _fields_ = [("threads", ctypes.c_int32), ("filter_bits", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("strategy", ctypes.c_int32)]
 
     def as_dict(self):
         return {"threads": self.threads, "filter_bits": self.filter_bits,
-                "blocks_per_cu": self.blocks_per_cu}
+                "blocks_per_cu": self.blocks_per_cu,
+                "strategy": STRATEGY_NAMES.get(self.strategy, self.strategy)}
 
 
 class BatchItem(ctypes.Structure):
@@ -272,9 +278,10 @@ class Hamiltonian:
         _check(load_library().nqs_last_kernel_ms(self._h, out))
         return tuple(out)
 
-    def set_tuning(self, threads=0, filter_bits=0, blocks_per_cu=0):
-        """nqs_set_tuning; all zeros restores the built-in plan."""
-        t = Tuning(threads, filter_bits, blocks_per_cu, 0)
+    def set_tuning(self, threads=0, filter_bits=0, blocks_per_cu=0, strategy="auto"):
+        """nqs_set_tuning; all zeros (strategy "auto") restores the built-in plan.
+        strategy: "auto", "stream" or "enum"."""
+        t = Tuning(threads, filter_bits, blocks_per_cu, STRATEGIES[strategy])
         _check(load_library().nqs_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self):

@@ -68,7 +68,7 @@ struct nqs_ham_s {
     bool profiled = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // launch tuning (all-zero = built-in plan)
-    nqs::Tuning tune{0, 0, 0};
+    nqs::Tuning tune{0, 0, 0, 0};
 };
 
 namespace {
@@ -240,6 +240,8 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
         {lh.r, sizeof(lh.r), 0},
         {h1 ? h1->data() : nullptr, h1 ? sizeof(double) * h1->size() : 0, 0},
         {eri ? eri->data() : nullptr, eri ? sizeof(double) * eri->size() : 0, 0},
+        {T.spin_q, sizeof(T.spin_q), 0},
+        {T.gh.data(), sizeof(uint32_t) * T.gh.size(), 0},
     };
     size_t total = 0;
     for (Piece &p : pieces) {
@@ -304,6 +306,12 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
     d.spin_a1 = T.spin[0][1];
     d.spin_b0 = T.spin[1][0];
     d.spin_b1 = T.spin[1][1];
+    d.enum_ok = T.enum_ok ? 1 : 0;
+    d.k_alpha = T.k_alpha;
+    d.k_beta = T.k_beta;
+    d.spin_q = reinterpret_cast<const uint8_t *>(base + pieces[10].off);
+    d.gh = reinterpret_cast<const uint32_t *>(base + pieces[11].off);
+    d.gh_shift = T.gh_shift;
     *out = h;
     return NQS_OK;
 }
@@ -516,7 +524,8 @@ bool tuning_valid(const nqs_tuning &t) {
     const bool th = t.threads == 0 || t.threads == 256 || t.threads == 512 || t.threads == 1024;
     const bool fb = t.filter_bits == 0 || (t.filter_bits >= 4 && t.filter_bits <= 64);
     const bool bc = t.blocks_per_cu == 0 || (t.blocks_per_cu >= 1 && t.blocks_per_cu <= 64);
-    return th && fb && bc && t.reserved == 0;
+    const bool sg = t.strategy >= nqs::kStrategyAuto && t.strategy <= nqs::kStrategyEnum;
+    return th && fb && bc && sg;
 }
 
 nqs_tuning filled(const nqs::Tuning &t) {
@@ -524,6 +533,7 @@ nqs_tuning filled(const nqs::Tuning &t) {
     o.threads = t.threads ? t.threads : 1024;
     o.filter_bits = t.filter_bits ? t.filter_bits : 16;
     o.blocks_per_cu = t.blocks_per_cu ? t.blocks_per_cu : 4;
+    o.strategy = t.strategy;
     return o;
 }
 
@@ -533,8 +543,8 @@ std::string shape_key(nqs_ham h, int64_t n, int precision) {
                         ? static_cast<int>(std::lround(std::log2(static_cast<double>(h->dt.n_groups))))
                         : 0;
     char buf[96];
-    std::snprintf(buf, sizeof(buf), "w%d_sec%d_s32_%d_lgn%d_lgg%d_p%d", h->words,
-                  h->dt.sector_filter, h->dt.sector32, lgn, lgg, precision);
+    std::snprintf(buf, sizeof(buf), "w%d_sec%d_s32_%d_en%d_lgn%d_lgg%d_p%d", h->words,
+                  h->dt.sector_filter, h->dt.sector32, h->dt.enum_ok, lgn, lgg, precision);
     return buf;
 }
 
@@ -544,7 +554,7 @@ struct CacheEntry {
 };
 
 // The cache file is a JSON object with one entry per line:
-//   "key": {"threads": T, "filter_bits": F, "blocks_per_cu": B, "ms": X},
+//   "key": {"threads": T, "filter_bits": F, "blocks_per_cu": B, "strategy": S, "ms": X},
 std::map<std::string, CacheEntry> read_cache(const char *path) {
     std::map<std::string, CacheEntry> m;
     if (!path) return m;
@@ -555,8 +565,9 @@ std::map<std::string, CacheEntry> read_cache(const char *path) {
         char key[128];
         CacheEntry e{};
         if (std::sscanf(line, " \"%127[^\"]\": {\"threads\": %d, \"filter_bits\": %d, "
-                              "\"blocks_per_cu\": %d, \"ms\": %lf",
-                        key, &e.t.threads, &e.t.filter_bits, &e.t.blocks_per_cu, &e.ms) == 5 &&
+                              "\"blocks_per_cu\": %d, \"strategy\": %d, \"ms\": %lf",
+                        key, &e.t.threads, &e.t.filter_bits, &e.t.blocks_per_cu, &e.t.strategy,
+                        &e.ms) == 6 &&
             tuning_valid(e.t))
             m[key] = e;
     }
@@ -572,9 +583,10 @@ bool write_cache(const char *path, const std::map<std::string, CacheEntry> &m) {
     size_t k = 0;
     for (const auto &kv : m) {
         std::fprintf(f, "  \"%s\": {\"threads\": %d, \"filter_bits\": %d, \"blocks_per_cu\": %d, "
-                        "\"ms\": %.6f}%s\n",
+                        "\"strategy\": %d, \"ms\": %.6f}%s\n",
                      kv.first.c_str(), kv.second.t.threads, kv.second.t.filter_bits,
-                     kv.second.t.blocks_per_cu, kv.second.ms, ++k < m.size() ? "," : "");
+                     kv.second.t.blocks_per_cu, kv.second.t.strategy, kv.second.ms,
+                     ++k < m.size() ? "," : "");
     }
     std::fprintf(f, "}\n");
     const bool ok = std::fclose(f) == 0;
@@ -590,11 +602,11 @@ extern "C" {
 int nqs_set_tuning(nqs_ham h, const nqs_tuning *t) {
     if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
     if (!t) {
-        h->tune = nqs::Tuning{0, 0, 0};
+        h->tune = nqs::Tuning{0, 0, 0, 0};
         return NQS_OK;
     }
     if (!tuning_valid(*t)) return fail(NQS_E_ARG, "tuning value out of range");
-    h->tune = nqs::Tuning{t->threads, t->filter_bits, t->blocks_per_cu};
+    h->tune = nqs::Tuning{t->threads, t->filter_bits, t->blocks_per_cu, t->strategy};
     return NQS_OK;
 }
 
@@ -618,7 +630,7 @@ int nqs_autotune(nqs_ham h, int64_t n, const uint64_t *samples, const double *lo
         const auto it = cache.find(key);
         if (it != cache.end()) {
             h->tune = nqs::Tuning{it->second.t.threads, it->second.t.filter_bits,
-                                  it->second.t.blocks_per_cu};
+                                  it->second.t.blocks_per_cu, it->second.t.strategy};
             if (best) *best = filled(h->tune);
             if (best_ms) *best_ms = -1.0;
             return NQS_OK;
@@ -628,43 +640,42 @@ int nqs_autotune(nqs_ham h, int64_t n, const uint64_t *samples, const double *lo
     NQS_HIP(hipEventCreate(&e0));
     NQS_HIP(hipEventCreate(&e1));
     const nqs::Tuning saved = h->tune;
-    nqs::Tuning win{0, 0, 0};
+    nqs::Tuning win{0, 0, 0, 0};
     double win_ms = 1e300;
     int rc = NQS_OK;
-    const int threads[] = {256, 512, 1024};
-    const int fbits[] = {8, 16, 32};
-    const int bpc[] = {2, 4, 8};
-    for (int th : threads) {
-        for (int fb : fbits) {
-            for (int bc : bpc) {
-                h->tune = nqs::Tuning{th, fb, bc};
-                float best_run = 1e30f;
-                for (int rep = 0; rep < 4 && rc == NQS_OK; ++rep) {
-                    hipError_t e = hipEventRecord(e0, st);
-                    if (e == hipSuccess) {
-                        rc = eval_impl(h, n, samples, nullptr, log_amp, phase, eloc, precision,
-                                       nullptr, nullptr, st);
-                        if (rc) break;
-                        e = hipEventRecord(e1, st);
-                    }
-                    if (e == hipSuccess) e = hipEventSynchronize(e1);
-                    float ms = 0.f;
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                    if (e != hipSuccess) {
-                        rc = fail_hip(e, "timing a candidate tuning");
-                        break;
-                    }
-                    if (rep > 0) best_run = std::min(best_run, ms);  // first run warms up
-                }
+    // candidates: the streaming kernel's (threads, filter bits, items per
+    // CU) grid, and for tables that allow it the enumeration's filter sizes
+    std::vector<nqs::Tuning> cands;
+    for (int th : {256, 512, 1024})
+        for (int fb : {8, 16, 32})
+            for (int bc : {2, 4, 8}) cands.push_back(nqs::Tuning{th, fb, bc, nqs::kStrategyStream});
+    if (h->dt.enum_ok)
+        for (int fb : {8, 16, 32}) cands.push_back(nqs::Tuning{1024, fb, 4, nqs::kStrategyEnum});
+    for (const nqs::Tuning &cand : cands) {
+        h->tune = cand;
+        float best_run = 1e30f;
+        for (int rep = 0; rep < 4 && rc == NQS_OK; ++rep) {
+            hipError_t e = hipEventRecord(e0, st);
+            if (e == hipSuccess) {
+                rc = eval_impl(h, n, samples, nullptr, log_amp, phase, eloc, precision, nullptr,
+                               nullptr, st);
                 if (rc) break;
-                if (best_run < win_ms) {
-                    win_ms = best_run;
-                    win = h->tune;
-                }
+                e = hipEventRecord(e1, st);
             }
-            if (rc) break;
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = fail_hip(e, "timing a candidate tuning");
+                break;
+            }
+            if (rep > 0) best_run = std::min(best_run, ms);  // first run warms up
         }
         if (rc) break;
+        if (best_run < win_ms) {
+            win_ms = best_run;
+            win = h->tune;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -751,7 +762,7 @@ int nqs_batch_create(nqs_batch *out, int n_items, const nqs_batch_item *items, i
     }
     hipError_t e = hipMalloc(&b->d_jobs, sizeof(nqs::JobDesc) * n_items);
     if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(nqs::WorkItem) * std::max<size_t>(work.size(), 1));
-    if (e == hipSuccess) e = hipMalloc(&b->d_next, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMalloc(&b->d_next, nqs::kBatchCounters * sizeof(unsigned));
     if (e != hipSuccess) {
         batch_free(b);
         return fail(NQS_E_NOMEM, "device allocation of the batch plan failed");
@@ -891,7 +902,15 @@ int plan_batch(const nqs_batch_item *items, int n_items, int threads, hipStream_
         nqs_ham h = it.ham;
         nqs::Tuning t = h->tune;
         t.threads = th;
-        const EvalLaunch L = plan_eval(h->dt, std::max<int64_t>(it.n, 1), false, &t);
+        // enumeration rounds assume 1024-thread blocks
+        if (th != kEnumThreads) t.strategy = kStrategyStream;
+        EvalLaunch L = plan_eval(h->dt, std::max<int64_t>(it.n, 1), false, &t);
+        if (L.strategy == kStrategyEnum && L.chunk_len > 0) {
+            // the streaming items are only a fallback here (mixed sectors):
+            // one group chunk keeps their number small
+            L.n_chunks = 1;
+            L.chunk_len = h->dt.n_groups - L.g_first;
+        }
         const int rc = ensure_scratch(h, std::max<int64_t>(it.n, 1), L.n_chunks, st);
         if (rc) return rc;
         JobDesc &J = jobs[k];
@@ -913,6 +932,7 @@ int plan_batch(const nqs_batch_item *items, int n_items, int threads, hipStream_
                                       : (w2 ? kJobW2S64 : kJobW1S64);
         if (h->dt.sc) J.kind += kJobIntegrals;
         J.capacity = h->slot_cap;
+        J.strategy = L.strategy;
         shape.max_filter_log2 = std::max(shape.max_filter_log2, L.filter_log2);
         shape.max_n = std::max(shape.max_n, it.n);
         shape.max_clear = std::max<int64_t>(shape.max_clear,
@@ -924,6 +944,22 @@ int plan_batch(const nqs_batch_item *items, int n_items, int threads, hipStream_
     std::vector<int> order(n_items);
     for (int k = 0; k < n_items; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    // enumeration items first, grouped by variant (rounds q, q + S,
+    // q + 2 S, ... of a job; the round size is known on the device only),
+    // then the streaming items
+    for (int v = 0; v < kEnumVariants; ++v) {
+        shape.enum_begin[v] = static_cast<int>(work.size());
+        for (int k : order) {
+            const JobDesc &J = jobs[k];
+            if (J.n == 0 || J.strategy != kStrategyEnum) continue;
+            const int jv = (J.kind & 1) + ((J.kind & kJobIntegrals) ? 2 : 0);
+            if (jv != v) continue;
+            const int64_t S = std::min<int64_t>((J.n + 63) / 64, int64_t(1) << 20);
+            for (int64_t q = 0; q < S; ++q)
+                work.push_back(WorkItem{k, -1, static_cast<int32_t>(q), static_cast<int32_t>(S)});
+        }
+    }
+    shape.enum_begin[kEnumVariants] = static_cast<int>(work.size());
     for (int k : order) {
         const JobDesc &J = jobs[k];
         if (J.n == 0 || J.chunk_len == 0) continue;
@@ -937,6 +973,7 @@ int plan_batch(const nqs_batch_item *items, int n_items, int threads, hipStream_
     const int per_cu_lds = static_cast<int>((160 * 1024) / lds);
     const int per_cu_waves = (32 * 64) / th;
     shape.lookup_blocks = static_cast<unsigned>(n_cu * std::max(1, std::min(per_cu_lds, per_cu_waves)));
+    shape.enum_blocks = static_cast<unsigned>(n_cu);
     *shape_out = shape;
     return NQS_OK;
 }

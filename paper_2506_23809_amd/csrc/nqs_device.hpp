@@ -28,7 +28,51 @@ struct DevTable {
     int sector_filter;     // compressed sector test available
     int sector32;          // both compressed widths fit in 32 bits
     uint64_t spin_a0, spin_a1, spin_b0, spin_b1;
+    // flip enumeration
+    int enum_ok;           // every in-sector group is a single or double excitation
+    int k_alpha, k_beta;   // qubits per spin
+    const uint8_t *spin_q; // [128]: alpha qubits at [0, k_alpha), beta at [64, 64 + k_beta)
+    const uint32_t *gh;    // group index slots (0xFFFFFFFF = empty)
+    uint32_t gh_shift;     // 32 - log2(slots)
 };
+
+// ---- flip enumeration: shape of one round
+//
+// A block evaluates B samples per round.  Per sample it keeps in LDS a
+// 64-byte record, its occupied/virtual qubit lists (4 x 64 bytes), one
+// accumulator per wave (16 x 16 bytes) and the row lists of the three
+// products (8 bytes per row):
+//   A  = (beta singles + none) x (alpha singles + none), without (none, none)
+//   Ba = alpha occupied pairs x alpha virtual pairs
+//   Bb = beta occupied pairs x beta virtual pairs
+// B is the largest count (at most 16) whose records fit beside the filter.
+constexpr int kEnumThreads = 1024;
+constexpr int kEnumWaves = kEnumThreads / 64;
+constexpr int kEnumQueue = 64;     // (code, hash) entries per wave
+constexpr int kEnumMaxB = 16;
+// LDS of one CU (160 KB) less 64 bytes for the scalar variables of the
+// persistent batch kernel; every enumeration block takes all of it: a static
+// 128 KB filter (whatever its used size) and the dynamic rest
+constexpr int kEnumLds = 160 * 1024 - 64;
+constexpr int kEnumFilterWords = 1 << 15;
+constexpr int kEnumDynLds = kEnumLds - 4 * kEnumFilterWords;
+constexpr int kEnumScalars = 64;
+constexpr int kEnumRowPad = 32;    // rows may be read 3 entries past the end
+constexpr int kEnumDynFixed = 512 + kEnumWaves * kEnumQueue * 8 + kEnumScalars + kEnumRowPad;
+constexpr int kEnumPerSampleFixed = 64 + 256 + kEnumWaves * 16;
+
+__host__ __device__ inline int enum_pairs(int m) { return m * (m - 1) / 2; }
+
+__host__ __device__ inline int enum_rows(int ka, int kb, int na, int nb) {
+    return 1 + nb * (kb - nb) + enum_pairs(na) + enum_pairs(nb);
+}
+
+// Samples per round for the given occupation, 0 if one does not fit.
+__host__ __device__ inline int enum_round_size(int ka, int kb, int na, int nb) {
+    const int per = kEnumPerSampleFixed + 8 * enum_rows(ka, kb, na, nb);
+    const int b = (kEnumDynLds - kEnumDynFixed) / per;
+    return b < kEnumMaxB ? b : kEnumMaxB;
+}
 
 // Sector key of a group: (half popcount of its alpha flips) | (half popcount
 // of its beta flips) << 8.  A flip x -> x ^ X keeps (N_alpha, N_beta) iff
@@ -68,6 +112,8 @@ struct alignas(32) Slot2 {
 
 // Launch plan of one evaluation: sample tiles x group chunks.
 struct EvalLaunch {
+    int strategy;       // kStrategyStream or kStrategyEnum
+    unsigned enum_blocks;  // persistent blocks of the enumeration kernel
     int64_t n;
     int64_t n_chunks;
     int64_t chunk_len;
@@ -76,6 +122,8 @@ struct EvalLaunch {
     int filter_log2;    // filter words = 1 << filter_log2
     size_t lds_bytes;   // dynamic LDS of the lookup kernel
 };
+
+constexpr int kStrategyAuto = 0, kStrategyStream = 1, kStrategyEnum = 2;
 
 // Optional event recorded between the lookup and the finish kernels.
 struct EvalStageEvents {
@@ -89,6 +137,7 @@ struct Tuning {
     int threads;        // lookup block size: 256, 512 or 1024
     int filter_bits;    // Bloom bits per sample (the bitmap is capped at 128 KB)
     int blocks_per_cu;  // target (tile, chunk) items per CU
+    int strategy;       // kStrategyAuto: enumeration when the table allows it
 };
 
 EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tune);
@@ -129,14 +178,19 @@ struct JobDesc {
     int64_t n_chunks;
     int kind;
     uint32_t capacity;  // hash slots
+    int strategy;       // kStrategyEnum: enumeration rounds, streaming items only as fallback
+    int pad;
 };
 
 struct WorkItem {
     int32_t job;
-    int32_t chunk;
+    int32_t chunk;      // -1: enumeration rounds tile, tile + stride, ...
     int32_t tile;
-    int32_t pad;
+    int32_t stride;
 };
+
+constexpr int kEnumVariants = 4;
+constexpr int kBatchCounters = kEnumVariants + 1;
 
 struct BatchShape {
     int threads;          // lookup block size, shared by all jobs
@@ -144,8 +198,14 @@ struct BatchShape {
     int64_t max_n;        // largest batch
     int64_t max_clear;    // largest of slot capacity and filter words
     unsigned lookup_blocks;
+    unsigned enum_blocks;  // persistent blocks of the enumeration kernels
+    // the work list starts with the enumeration items, grouped by variant
+    // v = (words - 1) + 2 * integral form: group v is [enum_begin[v], enum_begin[v + 1])
+    int enum_begin[5];
 };
 
+// d_next: kBatchCounters counters (one per enumeration variant, then the
+// streaming items).
 hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_items, int n_items,
                         unsigned *d_next, const BatchShape &shape, int precision, hipStream_t st);
 size_t batch_lds_bytes(int threads, int max_filter_log2);

@@ -112,9 +112,23 @@ template <int W>
 __device__ __forceinline__ int32_t hash_find(const typename SlotT<W>::type *__restrict__ slots,
                                              uint32_t mask, uint32_t slot, const Key<W> &k) {
     for (uint32_t probe = 0; probe <= mask; ++probe) {
-        const typename SlotT<W>::type s = slots[slot];
-        if (s.idx < 0) return -1;
-        if (key_eq<W>(s, k)) return s.idx;
+        // the whole slot in one load: index and key together
+        const uint4 *p = reinterpret_cast<const uint4 *>(&slots[slot]);
+        const uint4 a = p[0];
+        const uint64_t k0 = (static_cast<uint64_t>(a.y) << 32) | a.x;
+        int32_t idx;
+        bool eq;
+        if constexpr (W == 1) {
+            idx = static_cast<int32_t>(a.z);
+            eq = k0 == k.w[0];
+        } else {
+            const uint4 b = p[1];
+            const uint64_t k1 = (static_cast<uint64_t>(a.w) << 32) | a.z;
+            idx = static_cast<int32_t>(b.x);
+            eq = k0 == k.w[0] && k1 == k.w[1];
+        }
+        if (idx < 0) return -1;
+        if (eq) return idx;
         slot = (slot + 1) & mask;
     }
     return -1;
@@ -722,14 +736,520 @@ __device__ __forceinline__ void lookup_item(
     }
 }
 
+// ------------------------------------------------------------------ flip enumeration
+//
+// The second lookup strategy, for tables whose in-sector groups are all
+// single and double excitations (molecular Hamiltonians, every qubit with a
+// spin).  Instead of passing every X group by every sample and discarding
+// the out-of-sector ones, a block builds each sample's occupied and virtual
+// orbital lists and enumerates exactly its spin-conserving flips:
+//   A  = (beta singles + none) x (alpha singles + none), without (none, none)
+//   Ba = alpha occupied pairs x alpha virtual pairs
+//   Bb = beta occupied pairs x beta virtual pairs
+// Each product is laid out as rows x columns: 64 columns sit in the lanes'
+// registers (their hash already XORed with h(x)), rows stream from LDS as
+// wave-uniform reads, so one probe is one XOR plus the Bloom test of the
+// streaming kernel.  Filter survivors go through the same per-wave queue
+// into the global sample hash; a hit finds its group through the group
+// index (or, in the integral form, evaluates Slater-Condon directly).
+// The result equals the streaming kernel's up to the order of the hit sums:
+// groups a sample cannot reach (sector test false) are never visited.
+//
+// Flip codes: four 7-bit qubit fields (0x7F = none), columns fill fields 0
+// and 1, rows fields 2 and 3, the round slot of the sample sits in bits 28+.
+
+// Base of the dynamic LDS of the running kernel.
+__device__ __forceinline__ char *dyn_lds() {
+    extern __shared__ uint4 nqs_dyn_lds[];
+    return reinterpret_cast<char *>(nqs_dyn_lds);
+}
+
+constexpr uint32_t kNoQubit = 0x7Fu;
+constexpr uint32_t kNoPair = kNoQubit | (kNoQubit << 7);
+constexpr int kEnumRowSeg = 32;  // rows per work unit
+
+struct alignas(16) EnumSample {
+    uint64_t x0, x1;
+    double la, ph;
+    int64_t idx;
+    uint32_t hx;
+    uint32_t pad[3];
+};
+static_assert(sizeof(EnumSample) == 64, "one 64-byte record per sample");
+
+struct EnumShape {
+    int B;               // samples per round, 0 = enumeration not usable
+    int na, nb, va, vb;  // occupied / virtual orbitals per spin
+    int ra, rba, rbb;    // rows of A, Ba, Bb
+    int ca, cba, cbb;    // columns of A, Ba, Bb
+    int rows;            // ra + rba + rbb
+    int ua, uba, ubb;    // work units of A, Ba, Bb
+};
+
+__device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Shape of the rounds of this batch, from the first sample's occupation.
+// Usable when the table allows it and the hash build found one sector.
+__device__ __forceinline__ EnumShape enum_shape(const DevTable &tab, const DevScratch &sc,
+                                                const uint64_t *__restrict__ samples, int64_t n) {
+    EnumShape s{};
+    if (!tab.enum_ok || n <= 0 || *sc.mixed != 0) return s;
+    const uint64_t w0 = samples[0], w1 = samples[1];
+    s.na = __popcll(w0 & tab.spin_a0) + __popcll(w1 & tab.spin_a1);
+    s.nb = __popcll(w0 & tab.spin_b0) + __popcll(w1 & tab.spin_b1);
+    s.va = tab.k_alpha - s.na;
+    s.vb = tab.k_beta - s.nb;
+    s.B = enum_round_size(tab.k_alpha, tab.k_beta, s.na, s.nb);
+    s.ra = 1 + s.nb * s.vb;
+    s.ca = 1 + s.na * s.va;
+    s.rba = enum_pairs(s.na);
+    s.cba = enum_pairs(s.va);
+    s.rbb = enum_pairs(s.nb);
+    s.cbb = enum_pairs(s.vb);
+    s.rows = s.ra + s.rba + s.rbb;
+    s.ua = ceil_div(s.ca, 64) * ceil_div(s.ra, kEnumRowSeg);
+    s.uba = (s.rba && s.cba) ? ceil_div(s.cba, 64) * ceil_div(s.rba, kEnumRowSeg) : 0;
+    s.ubb = (s.rbb && s.cbb) ? ceil_div(s.cbb, 64) * ceil_div(s.rbb, kEnumRowSeg) : 0;
+    return s;
+}
+
+// The shape as scalar values (its inputs may come through vector loads).
+__device__ __forceinline__ EnumShape uniform_shape(EnumShape s) {
+    int *f = reinterpret_cast<int *>(&s);
+#pragma unroll
+    for (int k = 0; k < static_cast<int>(sizeof(EnumShape) / sizeof(int)); ++k)
+        f[k] = __builtin_amdgcn_readfirstlane(f[k]);
+    return s;
+}
+
+// k-th pair (i < j) in the order (0,1), (0,2), (1,2), (0,3), ...
+__device__ __forceinline__ void pair_of(int k, int &i, int &j) {
+    int jj = static_cast<int>((1.0f + sqrtf(1.0f + 8.0f * static_cast<float>(k))) * 0.5f);
+    while (jj * (jj - 1) / 2 > k) --jj;
+    while ((jj + 1) * jj / 2 <= k) ++jj;
+    j = jj;
+    i = k - jj * (jj - 1) / 2;
+}
+
+// Index of the group with flip mask X, or -1 (the group index is keyed by
+// h(X), which the caller has: h(x') ^ h(x)).
+template <int W>
+__device__ __forceinline__ int64_t group_find(const DevTable &tab, uint32_t hX, const Key<W> &X) {
+    const uint32_t mask = 0xFFFFFFFFu >> tab.gh_shift;
+    uint32_t slot = slot_of(hX, tab.gh_shift);
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        const uint32_t g = tab.gh[slot];
+        if (g == 0xFFFFFFFFu) return -1;
+        bool eq = tab.gx[2 * static_cast<size_t>(g)] == X.w[0];
+        if constexpr (W == 2) eq = eq && tab.gx[2 * static_cast<size_t>(g) + 1] == X.w[1];
+        if (eq) return g;
+        slot = (slot + 1) & mask;
+    }
+    return -1;
+}
+
+struct EnumCounts {
+    unsigned long long probes = 0, cand = 0;  // wave-uniform
+    unsigned long long hits = 0, terms = 0;   // per lane
+};
+
+// One round: samples [round * B, round * B + B) of the batch.  The filter
+// is in LDS at offset 0 (load_filter = false reuses it).  Partial sums of
+// the hits go to sc.part[i] in a fixed order: per wave in queue order, then
+// over the waves in wave order.
+template <int W, bool DUMP, int P, bool SCV>
+__device__ __forceinline__ void enum_round(const uint32_t *filt, const DevTable &tab,
+                                           const DevScratch &sc, const EnumShape &S,
+                           const uint64_t *__restrict__ samples,
+                           const double *__restrict__ log_amp, const double *__restrict__ phase,
+                           int64_t n, int64_t round, int32_t *__restrict__ hit_idx,
+                           uint32_t *__restrict__ sign_bits, int64_t sign_words,
+                           EnumCounts &cnt) {
+    using Sl = typename SlotT<W>::type;
+    char *smem = dyn_lds();
+    const int lane = threadIdx.x & 63;
+    // wave-uniform (scalar) so that unit and row loops run on the scalar unit
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int fwords = 1 << sc.filter_log2;
+    uint32_t *hr = reinterpret_cast<uint32_t *>(smem);
+    uint2 *queue = reinterpret_cast<uint2 *>(smem + 512) + wave * kEnumQueue;
+    char *per = smem + kEnumDynFixed;
+    const int B = S.B;
+    EnumSample *smp = reinterpret_cast<EnumSample *>(per);
+    uint8_t *ov = reinterpret_cast<uint8_t *>(per + 64 * B);        // [B][4][64]
+    char *accb = per + 64 * B + 256 * B;                             // [B][16][16 B]
+    uint2 *rows = reinterpret_cast<uint2 *>(per + 64 * B + 256 * B + kEnumWaves * 16 * B);
+    const Sl *__restrict__ slots = static_cast<const Sl *>(sc.slots);
+
+    const int64_t s0 = round * B;
+    const int nb = static_cast<int>(min(static_cast<int64_t>(B), n - s0));
+    if (nb <= 0) return;
+
+    // stage 1: records and occupied / virtual lists, one wave per sample
+    for (int k = threadIdx.x; k < 128; k += blockDim.x) hr[k] = tab.hr[k];
+    for (int b = wave; b < nb; b += kEnumWaves) {
+        const int64_t i = s0 + b;
+        const uint64_t w0 = samples[2 * i], w1 = samples[2 * i + 1];
+        uint8_t *o = ov + 256 * b;
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+            const int kq = sp ? tab.k_beta : tab.k_alpha;
+            const bool in = lane < kq;
+            const int q = in ? tab.spin_q[64 * sp + lane] : 0;
+            const bool occ = in && (((q < 64 ? w0 : w1) >> (q & 63)) & 1ull);
+            const uint64_t mo = __ballot(occ), mv = __ballot(in && !occ);
+            if (occ) o[128 * sp + lanes_below(mo)] = static_cast<uint8_t>(q);
+            if (in && !occ) o[128 * sp + 64 + lanes_below(mv)] = static_cast<uint8_t>(q);
+        }
+        if (lane == 0) {
+            EnumSample r;
+            r.x0 = w0;
+            r.x1 = w1;
+            r.la = log_amp[i];
+            r.ph = phase[i];
+            r.idx = i;
+            r.hx = sc.shx[i];
+            r.pad[0] = r.pad[1] = r.pad[2] = 0;
+            smp[b] = r;
+        }
+        if (lane < kEnumWaves) reinterpret_cast<uint4 *>(accb + kEnumWaves * 16 * b)[lane] =
+            make_uint4(0u, 0u, 0u, 0u);
+    }
+    __syncthreads();
+
+    // stage 2: row lists (hash, code in fields 2 and 3)
+    const int R = S.rows;
+    for (int t = threadIdx.x; t < nb * R; t += blockDim.x) {
+        const int b = t / R, r = t - b * R;
+        const uint8_t *o = ov + 256 * b;
+        uint32_t qa, qb;
+        if (r < S.ra) {
+            if (r == 0) {
+                rows[t] = make_uint2(0u, kNoPair << 14);
+                continue;
+            }
+            const int e = r - 1;
+            const int ii = e / S.vb;
+            qa = o[128 + ii];
+            qb = o[192 + (e - ii * S.vb)];
+        } else if (r < S.ra + S.rba) {
+            int ii, jj;
+            pair_of(r - S.ra, ii, jj);
+            qa = o[ii];
+            qb = o[jj];
+        } else {
+            int ii, jj;
+            pair_of(r - S.ra - S.rba, ii, jj);
+            qa = o[128 + ii];
+            qb = o[128 + jj];
+        }
+        rows[t] = make_uint2(hr[qa] ^ hr[qb], (qa | (qb << 7)) << 14);
+    }
+    __syncthreads();
+
+    // stage 3: work units, round-robin over the waves
+    const uint32_t fbytes_mask = static_cast<uint32_t>(fwords - 1) << 2;
+    const char *filt_b = reinterpret_cast<const char *>(filt);
+    uint32_t qn = 0;
+
+    auto flush = [&](uint32_t m) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const uint2 e = lane < static_cast<int>(m) ? queue[lane] : make_uint2(0u, 0u);
+        const int b = static_cast<int>(e.x >> 28);
+        bool hit = false;
+        double cre = 0.0, cim = 0.0;
+        float pre = 0.f, ere = 0.f, pim = 0.f, eim = 0.f;
+        if (lane < static_cast<int>(m)) {
+            const EnumSample rec = smp[b];
+            Key<W> x, X;
+            x.w[0] = rec.x0;
+            if constexpr (W == 2) x.w[1] = rec.x1;
+#pragma unroll
+            for (int q = 0; q < W; ++q) X.w[q] = 0;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const uint32_t q = (e.x >> (7 * f)) & kNoQubit;
+                if (q != kNoQubit) {
+                    if constexpr (W == 1) {
+                        X.w[0] |= 1ull << q;
+                    } else {
+                        // constant indices keep X in registers
+                        const uint64_t bit = 1ull << (q & 63);
+                        if (q < 64) X.w[0] |= bit; else X.w[1] |= bit;
+                    }
+                }
+            }
+            Key<W> xp;
+#pragma unroll
+            for (int q = 0; q < W; ++q) xp.w[q] = x.w[q] ^ X.w[q];
+            const int32_t j = hash_find<W>(slots, sc.slot_mask, slot_of(e.y, sc.slot_shift), xp);
+            if (j >= 0) {
+                int64_t g = -1;
+                if (!SCV || DUMP) g = group_find<W>(tab, e.y ^ rec.hx, X);
+                if constexpr (DUMP) {
+                    if (hit_idx && g >= 0) hit_idx[rec.idx * tab.n_groups + g] = j;
+                }
+                if (SCV || g >= 0) {
+                    hit = true;
+                    ++cnt.hits;
+                    if constexpr (P == NQS_FP64) {
+                        uint32_t *row =
+                            (DUMP && sign_bits) ? sign_bits + rec.idx * sign_words : nullptr;
+                        double hsum;
+                        if constexpr (SCV) {
+                            (void)row;
+                            hsum = sc_element<W>(tab, x, xp);
+                        } else {
+                            hsum = group_sum<W, DUMP>(tab, g, x, row, &cnt.terms);
+                        }
+                        double sn, cs;
+                        sincos(phase[j] - rec.ph, &sn, &cs);
+                        const double mag = exp(log_amp[j] - rec.la);
+                        cre = hsum * (mag * cs);
+                        cim = hsum * (mag * sn);
+                    } else {
+                        const AccF32 hs = group_sum_f32<W>(tab, g, x, &cnt.terms);
+                        float rr, ri;
+                        ratio_f32(log_amp[j] - rec.la, phase[j] - rec.ph, rr, ri);
+                        pre = hs.s * rr;
+                        ere = fmaf(hs.s, rr, -pre) + hs.c * rr;
+                        pim = hs.s * ri;
+                        eim = fmaf(hs.s, ri, -pim) + hs.c * ri;
+                    }
+                }
+            }
+        }
+        uint64_t hm = __ballot(hit);
+        while (hm) {
+            const int q = __builtin_ctzll(hm);
+            hm &= hm - 1;
+            const int bq = __builtin_amdgcn_readlane(b, q);
+            char *slot = accb + kEnumWaves * 16 * bq + 16 * wave;
+            if constexpr (P == NQS_FP64) {
+                const double r = readlane_f64(cre, q);
+                const double im = readlane_f64(cim, q);
+                if (lane == 0) {
+                    double *a = reinterpret_cast<double *>(slot);
+                    a[0] += r;
+                    a[1] += im;
+                }
+            } else {
+                const float a0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pre), q));
+                const float a1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ere), q));
+                const float b0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pim), q));
+                const float b1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(eim), q));
+                if (lane == 0) {
+                    float *a = reinterpret_cast<float *>(slot);  // re.s, re.c, im.s, im.c
+                    AccF32 ar, ai;
+                    ar.s = a[0]; ar.c = a[1]; ai.s = a[2]; ai.c = a[3];
+                    ar.add(a0, a1);
+                    ai.add(b0, b1);
+                    a[0] = ar.s; a[1] = ar.c; a[2] = ai.s; a[3] = ai.c;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    };
+
+    const int U = S.ua + S.uba + S.ubb;
+    for (int u = wave; u < U * nb; u += kEnumWaves) {
+        const int l = u / nb, b = u - (u / nb) * nb;
+        const uint8_t *o = ov + 256 * b;
+        const EnumSample *rec = smp + b;
+        int ncol, row0, nrow, lu;
+        int prod;
+        if (l < S.ua) {
+            prod = 0; lu = l; ncol = S.ca; row0 = 0; nrow = S.ra;
+        } else if (l < S.ua + S.uba) {
+            prod = 1; lu = l - S.ua; ncol = S.cba; row0 = S.ra; nrow = S.rba;
+        } else {
+            prod = 2; lu = l - S.ua - S.uba; ncol = S.cbb; row0 = S.ra + S.rba; nrow = S.rbb;
+        }
+        const int nseg = ceil_div(nrow, kEnumRowSeg);
+        const int ch = lu / nseg, seg = lu - (lu / nseg) * nseg;
+        const int k = ch * 64 + lane;
+        const bool act = k < ncol;
+        // this lane's column: hash (with h(x)) and code in fields 0 and 1
+        uint32_t colh = 0, colc = kNoPair;
+        if (act) {
+            uint32_t qa = kNoQubit, qb = kNoQubit;
+            if (prod == 0) {
+                if (k > 0) {
+                    const int e = k - 1;
+                    const int ii = e / S.va;
+                    qa = o[ii];
+                    qb = o[64 + (e - ii * S.va)];
+                }
+            } else if (prod == 1) {
+                int ii, jj;
+                pair_of(k, ii, jj);
+                qa = o[64 + ii];
+                qb = o[64 + jj];
+            } else {
+                int ii, jj;
+                pair_of(k, ii, jj);
+                qa = o[192 + ii];
+                qb = o[192 + jj];
+            }
+            if (qa != kNoQubit) {
+                colh = hr[qa] ^ hr[qb];
+                colc = qa | (qb << 7);
+            }
+        }
+        colh ^= rec->hx;
+        colc |= static_cast<uint32_t>(b) << 28;
+        const uint64_t colmask = __ballot(act);
+        // (none, none) is x itself: never a probe
+        const bool excl0 = prod == 0 && ch == 0 && seg == 0;
+        const int r0 = seg * kEnumRowSeg;
+        const int nr = min(nrow - r0, kEnumRowSeg);
+        const uint2 *rw = rows + b * R + row0 + r0;
+        cnt.probes += static_cast<unsigned long long>(__popcll(colmask)) * nr - (excl0 ? 1ull : 0ull);
+        // probes: the filter bit of row r lands in bit nq - 1 - r of pm,
+        // nq = nr rounded up to whole groups of 4 (rows past nr are read
+        // from the padding or the next list and masked off below)
+        uint32_t pm = 0;
+        const int nq = (nr + 3) & ~3;
+        for (int r = 0; r < nr; r += 4) {
+            uint2 re[4];
+            uint32_t h[4], fw[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) re[v] = rw[r + v];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                h[v] = colh ^ re[v].x;
+                // word (h >> 5) of the bitmap, as a byte offset
+                fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + ((h[v] >> 3) & fbytes_mask));
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                pm = (pm << 1) | ((fw[v] >> (h[v] & 31)) & (fw[v] >> (h[v] >> 27)) & 1u);
+        }
+        // rows [0, nr) are bits (nq - 1 - nr, nq - 1]
+        uint32_t keep = (nr >= 32 ? 0xFFFFFFFFu : ((1u << nr) - 1u)) << (nq - nr);
+        if (!act) keep = 0u;
+        if (excl0 && lane == 0) keep &= ~(1u << (nq - 1));
+        pm &= keep;
+        // filter survivors into the queue
+        for (;;) {
+            const uint64_t any = __ballot(pm != 0u);
+            if (!any) break;
+            const bool has = pm != 0u;
+            const int rr = has ? nq - 1 - __builtin_ctz(pm) : 0;
+            pm &= pm - 1u;
+            const uint2 e = rw[rr];
+            const uint32_t c = static_cast<uint32_t>(__popcll(any));
+            cnt.cand += c;
+            if (qn + c > static_cast<uint32_t>(kEnumQueue)) {
+                flush(qn);
+                qn = 0;
+            }
+            if (has) queue[qn + lanes_below(any)] = make_uint2(colc | e.y, colh ^ e.x);
+            qn += c;
+        }
+    }
+    if (qn > 0) flush(qn);
+    __syncthreads();
+
+    // stage 4    if (qn > 0) flush(qn);
+    __syncthreads();
+
+    // stage 4: per-sample partial, waves in order
+    if (threadIdx.x < static_cast<unsigned>(nb)) {
+        const int b = threadIdx.x;
+        const char *a = accb + kEnumWaves * 16 * b;
+        double *p = sc.part + 2 * (s0 + b);
+        if constexpr (P == NQS_FP64) {
+            double re = 0.0, im = 0.0;
+            for (int w = 0; w < kEnumWaves; ++w) {
+                re += reinterpret_cast<const double *>(a + 16 * w)[0];
+                im += reinterpret_cast<const double *>(a + 16 * w)[1];
+            }
+            p[0] = re;
+            p[1] = im;
+        } else {
+            AccF32 ar, ai;
+            for (int w = 0; w < kEnumWaves; ++w) {
+                const float *f = reinterpret_cast<const float *>(a + 16 * w);
+                ar.add(f[0], f[1]);
+                ai.add(f[2], f[3]);
+            }
+            p[0] = ar.value();
+            p[1] = ai.value();
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void enum_flush_counts(const DevScratch &sc, EnumCounts &c) {
+    unsigned long long h = c.hits, t = c.terms;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        h += __shfl_xor(h, off);
+        t += __shfl_xor(t, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (c.probes) atomicAdd(&sc.counters[1], c.probes);
+        if (h) atomicAdd(&sc.counters[2], h);
+        if (t) atomicAdd(&sc.counters[3], t);
+        if (c.cand) atomicAdd(&sc.counters[4], c.cand);
+    }
+    c = EnumCounts{};
+}
+
+__device__ __forceinline__ void load_filter_lds(const DevScratch &sc, uint4 *smem4) {
+    // (also used with the static filter array of the enumeration kernels)
+    const uint4 *gf = reinterpret_cast<const uint4 *>(sc.filter);
+    const int n4 = (1 << sc.filter_log2) >> 2;
+    for (int k = threadIdx.x; k < n4; k += blockDim.x) smem4[k] = gf[k];
+}
+
+// Persistent form: blocks take rounds from counters[5] until none is left.
+template <int W, bool DUMP, int P, bool SCV>
+__global__ __launch_bounds__(kEnumThreads) void eloc_enum_kernel(
+    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
+    const double *__restrict__ log_amp, const double *__restrict__ phase, int64_t n,
+    int32_t *__restrict__ hit_idx, uint32_t *__restrict__ sign_bits, int64_t sign_words) {
+    // the filter at LDS address 0 (a static array: its address folds into
+    // the read); records, lists and queues in the dynamic rest
+    __shared__ uint4 s_filter[kEnumFilterWords / 4];
+    const EnumShape S = enum_shape(tab, sc, samples, n);
+    if (S.B <= 0) return;  // the streaming kernel of this launch does the work
+    int *cur = reinterpret_cast<int *>(dyn_lds() + 512 + kEnumWaves * kEnumQueue * 8);
+    const int64_t n_rounds = (n + S.B - 1) / S.B;
+    load_filter_lds(sc, s_filter);
+    EnumCounts cnt;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            *cur = static_cast<int>(atomicAdd(&sc.counters[5], 1ull));
+        __syncthreads();
+        const int64_t r = *cur;
+        if (r >= n_rounds) break;  // every block reaches this once the rounds are taken
+        enum_round<W, DUMP, P, SCV>(reinterpret_cast<const uint32_t *>(s_filter), tab, sc, S,
+                                    samples, log_amp, phase, n, r, hit_idx, sign_bits, sign_words,
+                                    cnt);
+    }
+    enum_flush_counts(sc, cnt);
+}
+
+// Marks every (sample, group) pair of a dump as "no candidate" before an
+// enumeration writes its hits.
+__global__ void fill_i32_kernel(int32_t *__restrict__ p, int64_t count, int32_t v) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < count) p[k] = v;
+}
+
 // Grid form: (sample tiles of blockDim) x (group chunks), one item per block.
 template <int W, bool S32, bool SEC, bool DUMP, int P, bool SCV>
 __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
     const double *__restrict__ log_amp, const double *__restrict__ phase, int64_t n,
     int64_t g_first, int64_t chunk_len, int32_t *__restrict__ hit_idx,
-    uint32_t *__restrict__ sign_bits, int64_t sign_words) {
+    uint32_t *__restrict__ sign_bits, int64_t sign_words, int fallback_only) {
     extern __shared__ uint4 smem4[];
+    // beside an enumeration launch this grid only runs when enumeration cannot
+    if (fallback_only && enum_shape(tab, sc, samples, n).B > 0) return;
     lookup_item<W, S32, SEC, DUMP, P, SCV>(tab, sc, samples, log_amp, phase, n, blockIdx.x, blockIdx.y,
                                       g_first, chunk_len, true, hit_idx, sign_bits, sign_words,
                                       smem4);
@@ -739,11 +1259,14 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
 template <int W, bool DUMP, int P, bool SCV>
 __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch &sc,
                                            const uint64_t *__restrict__ samples, int64_t n,
-                                           int64_t n_chunks, double *__restrict__ eloc,
+                                           int64_t n_chunks, bool enum_on,
+                                           double *__restrict__ eloc,
                                            int32_t *__restrict__ hit_idx,
                                            uint32_t *__restrict__ sign_bits, int64_t sign_words,
                                            int64_t i) {
     unsigned long long n_terms = 0;
+    // an enumeration leaves one partial per sample
+    if (enum_on && enum_shape(tab, sc, samples, n).B > 0) n_chunks = 1;
     if (i < n) {
         const Key<W> x = load_key<W>(samples, i);
         double re = 0.0, im = 0.0;
@@ -776,11 +1299,11 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
 template <int W, bool DUMP, int P, bool SCV>
 __global__ __launch_bounds__(256) void eloc_finish_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n,
-    int64_t n_chunks, double *__restrict__ eloc, int32_t *__restrict__ hit_idx,
+    int64_t n_chunks, int enum_on, double *__restrict__ eloc, int32_t *__restrict__ hit_idx,
     uint32_t *__restrict__ sign_bits, int64_t sign_words) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, eloc, hit_idx, sign_bits, sign_words,
-                                i);
+    finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc, hit_idx,
+                                sign_bits, sign_words, i);
 }
 
 // ------------------------------------------------------------------ batched form
@@ -799,7 +1322,8 @@ __global__ void batch_reset_kernel(const JobDesc *__restrict__ jobs, int n_jobs,
         for (int k = 0; k < kCounters; ++k) jobs[j].sc.counters[k] = 0;
         *jobs[j].sc.mixed = 0;
     }
-    if (j == 0) *next = 0u;
+    if (j == 0)
+        for (int k = 0; k < kBatchCounters; ++k) next[k] = 0u;
 }
 
 __global__ void batch_clear_kernel(const JobDesc *__restrict__ jobs) {
@@ -825,6 +1349,40 @@ __global__ void batch_build_kernel(const JobDesc *__restrict__ jobs) {
         hash_build_one<2>(J.tab, J.sc, J.samples, J.weights, i);
 }
 
+// Enumeration items: rounds tile, tile + stride, ... of one job.  One
+// persistent kernel per variant (mask words, evaluator) drains the items of
+// that variant; they run before the streaming kernel.
+template <int W, int P, bool SCV>
+__global__ __launch_bounds__(kEnumThreads) void batch_enum_kernel(
+    const JobDesc *__restrict__ jobs, const WorkItem *__restrict__ items, int n_items,
+    unsigned *__restrict__ next) {
+    __shared__ uint4 s_filter[kEnumFilterWords / 4];
+    __shared__ int cur;
+    int last_job = -1;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) cur = static_cast<int>(atomicAdd(next, 1u));
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(cur);
+        if (it >= n_items) break;  // every block reaches this once the list is drained
+        const WorkItem w = items[it];
+        const JobDesc &J = jobs[w.job];
+        const EnumShape S = uniform_shape(enum_shape(J.tab, J.sc, J.samples, J.n));
+        const int64_t n_rounds = S.B > 0 ? (J.n + S.B - 1) / S.B : 0;
+        if (w.tile >= n_rounds) continue;  // also: the streaming items do this job
+        if (w.job != last_job) load_filter_lds(J.sc, s_filter);
+        last_job = w.job;
+        EnumCounts cnt;
+        for (int64_t r = w.tile; r < n_rounds; r += w.stride)
+            enum_round<W, false, P, SCV>(reinterpret_cast<const uint32_t *>(s_filter), J.tab,
+                                         J.sc, S, J.samples, J.log_amp, J.phase, J.n, r,
+                                         nullptr, nullptr, 0, cnt);
+        enum_flush_counts(J.sc, cnt);
+    }
+}
+
+// Streaming items; those of a job that is enumerated return at once (they
+// run only when the job's samples span several sectors).
 template <int P>
 __global__ __launch_bounds__(kLookupThreads) void batch_lookup_kernel(
     const JobDesc *__restrict__ jobs, const WorkItem *__restrict__ items, int n_items,
@@ -836,26 +1394,30 @@ __global__ __launch_bounds__(kLookupThreads) void batch_lookup_kernel(
         __syncthreads();
         if (threadIdx.x == 0) cur = static_cast<int>(atomicAdd(next, 1u));
         __syncthreads();
-        const int it = cur;
+        // block-uniform: scalar loads of the item and its job descriptor
+        const int it = __builtin_amdgcn_readfirstlane(cur);
         if (it >= n_items) break;  // every block reaches this once the list is drained
         const WorkItem w = items[it];
         const JobDesc &J = jobs[w.job];
+        if (J.strategy == kStrategyEnum && enum_shape(J.tab, J.sc, J.samples, J.n).B > 0)
+            continue;  // enumerated instead
         const bool load = w.job != last_job;
         last_job = w.job;
-#define NQS_ITEM(Wd, S, SE, SCI)                                                               \
-    lookup_item<Wd, S, SE, false, P, SCI>(J.tab, J.sc, J.samples, J.log_amp, J.phase, J.n, w.tile, \
-                                          w.chunk, J.g_first, J.chunk_len, load, nullptr, nullptr, \
-                                          0, smem4)
+#define NQS_ITEM(Wd, S, SE, Pr, SCI)                                                          \
+    lookup_item<Wd, S, SE, false, Pr, SCI>(J.tab, J.sc, J.samples, J.log_amp, J.phase, J.n,      \
+                                           w.tile, w.chunk, J.g_first, J.chunk_len, load, nullptr, \
+                                           nullptr, 0, smem4)
+        // integral-form jobs evaluate in FP64 whatever the batch precision
         switch (J.kind) {
-            case kJobW1Nosec: NQS_ITEM(1, true, false, false); break;
-            case kJobW1S32: NQS_ITEM(1, true, true, false); break;
-            case kJobW1S64: NQS_ITEM(1, false, true, false); break;
-            case kJobW2Nosec: NQS_ITEM(2, true, false, false); break;
-            case kJobW2S32: NQS_ITEM(2, true, true, false); break;
-            case kJobW2S64: NQS_ITEM(2, false, true, false); break;
-            case kJobW1S32 + kJobIntegrals: NQS_ITEM(1, true, true, (P == NQS_FP64)); break;
-            case kJobW2S32 + kJobIntegrals: NQS_ITEM(2, true, true, (P == NQS_FP64)); break;
-            case kJobW2S64 + kJobIntegrals: NQS_ITEM(2, false, true, (P == NQS_FP64)); break;
+            case kJobW1Nosec: NQS_ITEM(1, true, false, P, false); break;
+            case kJobW1S32: NQS_ITEM(1, true, true, P, false); break;
+            case kJobW1S64: NQS_ITEM(1, false, true, P, false); break;
+            case kJobW2Nosec: NQS_ITEM(2, true, false, P, false); break;
+            case kJobW2S32: NQS_ITEM(2, true, true, P, false); break;
+            case kJobW2S64: NQS_ITEM(2, false, true, P, false); break;
+            case kJobW1S32 + kJobIntegrals: NQS_ITEM(1, true, true, NQS_FP64, true); break;
+            case kJobW2S32 + kJobIntegrals: NQS_ITEM(2, true, true, NQS_FP64, true); break;
+            case kJobW2S64 + kJobIntegrals: NQS_ITEM(2, false, true, NQS_FP64, true); break;
             default: break;
         }
 #undef NQS_ITEM
@@ -869,19 +1431,20 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(const JobDesc *__rest
     if (static_cast<int64_t>(blockIdx.x) * blockDim.x >= J.n) return;  // whole block past the end
     const int64_t chunks = J.chunk_len > 0 ? J.n_chunks : 0;
     const bool integrals = (J.kind & kJobIntegrals) != 0;
+    const bool en = J.strategy == kStrategyEnum;
     if ((J.kind & 1) == 0) {
         if (integrals)
-            finish_one<1, false, NQS_FP64, true>(J.tab, J.sc, J.samples, J.n, chunks, J.eloc,
+            finish_one<1, false, NQS_FP64, true>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc,
                                                  nullptr, nullptr, 0, i);
         else
-            finish_one<1, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, J.eloc, nullptr,
+            finish_one<1, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc, nullptr,
                                            nullptr, 0, i);
     } else {
         if (integrals)
-            finish_one<2, false, NQS_FP64, true>(J.tab, J.sc, J.samples, J.n, chunks, J.eloc,
+            finish_one<2, false, NQS_FP64, true>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc,
                                                  nullptr, nullptr, 0, i);
         else
-            finish_one<2, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, J.eloc, nullptr,
+            finish_one<2, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc, nullptr,
                                            nullptr, 0, i);
     }
 }
@@ -889,6 +1452,19 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(const JobDesc *__rest
 size_t batch_lds_bytes(int threads, int max_filter_log2) {
     return lookup_lds_bytes(false, max_filter_log2, threads);
 }
+
+namespace {
+// The enumeration kernel of variant v = (words - 1) + 2 * integral form.
+template <int P>
+const void *enum_variant(int v) {
+    switch (v) {
+        case 0: return reinterpret_cast<const void *>(&batch_enum_kernel<1, P, false>);
+        case 1: return reinterpret_cast<const void *>(&batch_enum_kernel<2, P, false>);
+        case 2: return reinterpret_cast<const void *>(&batch_enum_kernel<1, NQS_FP64, true>);
+        default: return reinterpret_cast<const void *>(&batch_enum_kernel<2, NQS_FP64, true>);
+    }
+}
+}  // namespace
 
 hipError_t prepare_batch_kernels() {
     static bool done = false;
@@ -899,6 +1475,13 @@ hipError_t prepare_batch_kernels() {
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_lookup_kernel<NQS_FP32_KAHAN>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLookupLds);
+    for (int v = 0; v < kEnumVariants && e == hipSuccess; ++v) {
+        e = hipFuncSetAttribute(enum_variant<NQS_FP64>(v),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kEnumDynLds);
+        if (e == hipSuccess && v < 2)
+            e = hipFuncSetAttribute(enum_variant<NQS_FP32_KAHAN>(v),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kEnumDynLds);
+    }
     if (e == hipSuccess) done = true;
     return e;
 }
@@ -917,18 +1500,41 @@ hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_ite
     const size_t lds = batch_lds_bytes(shape.threads, shape.max_filter_log2);
     const hipError_t pe = prepare_batch_kernels();
     if (pe != hipSuccess) return pe;
-    if (precision == NQS_FP32_KAHAN) {
-        hipLaunchKernelGGL(batch_lookup_kernel<NQS_FP32_KAHAN>, dim3(shape.lookup_blocks),
-                           dim3(shape.threads), lds, st, d_jobs, d_items, n_items, d_next);
-        hipLaunchKernelGGL(batch_finish_kernel<NQS_FP32_KAHAN>,
-                           dim3(static_cast<unsigned>((shape.max_n + 255) / 256), n_jobs),
-                           dim3(256), 0, st, d_jobs);
+    // items [enum_begin[v], enum_begin[v + 1]) are the enumeration rounds of
+    // variant v; the streaming items follow
+    const bool f32 = precision == NQS_FP32_KAHAN;
+    for (int v = 0; v < kEnumVariants; ++v) {
+        const int b0 = shape.enum_begin[v], cnt = shape.enum_begin[v + 1] - b0;
+        if (cnt <= 0) continue;
+        const WorkItem *it = d_items + b0;
+        unsigned *nx = d_next + v;
+#define NQS_EB(Wd, Pr, SCI)                                                                    \
+    hipLaunchKernelGGL((batch_enum_kernel<Wd, Pr, SCI>), dim3(shape.enum_blocks),               \
+                       dim3(kEnumThreads), kEnumDynLds, st, d_jobs, it, cnt, nx)
+        switch (v) {
+            case 0: if (f32) NQS_EB(1, NQS_FP32_KAHAN, false); else NQS_EB(1, NQS_FP64, false); break;
+            case 1: if (f32) NQS_EB(2, NQS_FP32_KAHAN, false); else NQS_EB(2, NQS_FP64, false); break;
+            case 2: NQS_EB(1, NQS_FP64, true); break;
+            default: NQS_EB(2, NQS_FP64, true); break;
+        }
+#undef NQS_EB
+    }
+    const int ne = shape.enum_begin[kEnumVariants];
+    const WorkItem *s_items = d_items + ne;
+    const int ns = n_items - ne;
+    const dim3 fgrid(static_cast<unsigned>((shape.max_n + 255) / 256), n_jobs);
+    if (f32) {
+        if (ns > 0)
+            hipLaunchKernelGGL(batch_lookup_kernel<NQS_FP32_KAHAN>, dim3(shape.lookup_blocks),
+                               dim3(shape.threads), lds, st, d_jobs, s_items, ns,
+                               d_next + kEnumVariants);
+        hipLaunchKernelGGL(batch_finish_kernel<NQS_FP32_KAHAN>, fgrid, dim3(256), 0, st, d_jobs);
     } else {
-        hipLaunchKernelGGL(batch_lookup_kernel<NQS_FP64>, dim3(shape.lookup_blocks),
-                           dim3(shape.threads), lds, st, d_jobs, d_items, n_items, d_next);
-        hipLaunchKernelGGL(batch_finish_kernel<NQS_FP64>,
-                           dim3(static_cast<unsigned>((shape.max_n + 255) / 256), n_jobs),
-                           dim3(256), 0, st, d_jobs);
+        if (ns > 0)
+            hipLaunchKernelGGL(batch_lookup_kernel<NQS_FP64>, dim3(shape.lookup_blocks),
+                               dim3(shape.threads), lds, st, d_jobs, s_items, ns,
+                               d_next + kEnumVariants);
+        hipLaunchKernelGGL(batch_finish_kernel<NQS_FP64>, fgrid, dim3(256), 0, st, d_jobs);
     }
     return hipGetLastError();
 }
@@ -1041,9 +1647,28 @@ hipError_t launch_reset(const DevScratch &sc, hipStream_t st) {
     return hipGetLastError();
 }
 
+namespace {
+int device_cus() {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v <= 0)
+            v = 256;
+        cus[dev] = v;
+    }
+    return cus[dev];
+}
+}  // namespace
+
 EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tune) {
     EvalLaunch L;
     L.n = n;
+    const int want = tune ? tune->strategy : kStrategyAuto;
+    L.strategy = (tab.enum_ok && want != kStrategyStream) ? kStrategyEnum : kStrategyStream;
+    L.enum_blocks = static_cast<unsigned>(device_cus());
     L.threads = (tune && tune->threads) ? tune->threads : kLookupThreads;
     // Bloom bitmap: about 16 bits per sample unless tuned, 512 B .. 128 KB
     int lg = 7;
@@ -1092,7 +1717,7 @@ template <int W, bool S32, bool SEC, bool D, int P, bool SCV>
 hipError_t launch_lookup(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
                          const uint64_t *samples, const double *log_amp, const double *phase,
                          int32_t *hit_idx, uint32_t *sign_bits, int64_t sign_words,
-                         hipStream_t st) {
+                         int fallback_only, hipStream_t st) {
     static bool attr_set = false;
     if (!attr_set) {
         const hipError_t e = hipFuncSetAttribute(
@@ -1105,7 +1730,25 @@ hipError_t launch_lookup(const DevTable &tab, const DevScratch &sc, const EvalLa
                     static_cast<unsigned>(L.n_chunks));
     hipLaunchKernelGGL((eloc_lookup_kernel<W, S32, SEC, D, P, SCV>), grid, dim3(L.threads), L.lds_bytes, st,
                        tab, sc, samples, log_amp, phase, L.n, L.g_first, L.chunk_len, hit_idx,
-                       sign_bits, sign_words);
+                       sign_bits, sign_words, fallback_only);
+    return hipGetLastError();
+}
+
+template <int W, bool D, int P, bool SCV>
+hipError_t launch_enum(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
+                       const uint64_t *samples, const double *log_amp, const double *phase,
+                       int32_t *hit_idx, uint32_t *sign_bits, int64_t sign_words, hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&eloc_enum_kernel<W, D, P, SCV>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, kEnumDynLds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((eloc_enum_kernel<W, D, P, SCV>), dim3(L.enum_blocks), dim3(kEnumThreads),
+                       kEnumDynLds, st, tab, sc, samples, log_amp, phase, L.n, hit_idx, sign_bits,
+                       sign_words);
     return hipGetLastError();
 }
 
@@ -1118,11 +1761,41 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
     const bool f32 = precision == NQS_FP32_KAHAN && !dump;
     const bool s32 = tab.sector32 != 0;
     const int64_t n = L.n;
+    const bool en = L.strategy == kStrategyEnum;
+    const int fb = en ? 1 : 0;
     hipError_t e = hipSuccess;
+    if (en) {
+        // a dump marks every pair first; the enumeration writes only its hits
+        if (hit_idx) {
+            const int64_t cnt = n * tab.n_groups;
+            hipLaunchKernelGGL(fill_i32_kernel, dim3(static_cast<unsigned>((cnt + 255) / 256)),
+                               dim3(256), 0, st, hit_idx, cnt, -1);
+        }
+#define NQS_ENUM(Wd, D, Pr, SCI) \
+    e = launch_enum<Wd, D, Pr, SCI>(tab, sc, L, samples, log_amp, phase, hit_idx, sign_bits, \
+                                    sign_words, st)
+        if (tab.sc) {
+            if (words == 1) {
+                if (dump) NQS_ENUM(1, true, NQS_FP64, true); else NQS_ENUM(1, false, NQS_FP64, true);
+            } else {
+                if (dump) NQS_ENUM(2, true, NQS_FP64, true); else NQS_ENUM(2, false, NQS_FP64, true);
+            }
+        } else if (words == 1) {
+            if (dump) NQS_ENUM(1, true, NQS_FP64, false);
+            else if (f32) NQS_ENUM(1, false, NQS_FP32_KAHAN, false);
+            else NQS_ENUM(1, false, NQS_FP64, false);
+        } else {
+            if (dump) NQS_ENUM(2, true, NQS_FP64, false);
+            else if (f32) NQS_ENUM(2, false, NQS_FP32_KAHAN, false);
+            else NQS_ENUM(2, false, NQS_FP64, false);
+        }
+#undef NQS_ENUM
+        if (e != hipSuccess) return e;
+    }
     if (L.chunk_len > 0) {
 #define NQS_LOOKUP(Wd, S, SE, D, Pr)                                                       \
     e = launch_lookup<Wd, S, SE, D, Pr, false>(tab, sc, L, samples, log_amp, phase, hit_idx,  \
-                                               sign_bits, sign_words, st)
+                                               sign_bits, sign_words, fb, st)
 #define NQS_LOOKUP_D(Wd, S, SE)                      \
     if (dump) NQS_LOOKUP(Wd, S, SE, true, NQS_FP64);  \
     else if (f32) NQS_LOOKUP(Wd, S, SE, false, NQS_FP32_KAHAN); \
@@ -1133,7 +1806,7 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
         if (tab.sc) {
 #define NQS_LOOKUP_SC(Wd, S, D) \
     e = launch_lookup<Wd, S, true, D, NQS_FP64, true>(tab, sc, L, samples, log_amp, phase, \
-                                                     hit_idx, sign_bits, sign_words, st)
+                                                     hit_idx, sign_bits, sign_words, fb, st)
             if (words == 1) {
                 if (dump) NQS_LOOKUP_SC(1, true, true); else NQS_LOOKUP_SC(1, true, false);
             } else if (s32) {
@@ -1163,10 +1836,10 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
     const dim3 fgrid(static_cast<unsigned>((n + 255) / 256));
 #define NQS_FINISH(Wd, D, Pr)                                                                 \
     hipLaunchKernelGGL((eloc_finish_kernel<Wd, D, Pr, false>), fgrid, dim3(256), 0, st, tab, sc,  \
-                       samples, n, chunks, eloc, hit_idx, sign_bits, sign_words)
+                       samples, n, chunks, fb, eloc, hit_idx, sign_bits, sign_words)
 #define NQS_FINISH_SC(Wd, D)                                                                     \
     hipLaunchKernelGGL((eloc_finish_kernel<Wd, D, NQS_FP64, true>), fgrid, dim3(256), 0, st, tab, \
-                       sc, samples, n, chunks, eloc, hit_idx, sign_bits, sign_words)
+                       sc, samples, n, chunks, fb, eloc, hit_idx, sign_bits, sign_words)
     if (tab.sc) {
         if (words == 1) {
             if (dump) NQS_FINISH_SC(1, true); else NQS_FINISH_SC(1, false);

@@ -280,7 +280,7 @@ int nqs_server_create(nqs_server *out, const nqs_server_config *cfg) {
     for (Slot &f : s->slots) {
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&f.st, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&f.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMalloc(&f.d_next, sizeof(unsigned));
+        if (e == hipSuccess) e = hipMalloc(&f.d_next, nqs::kBatchCounters * sizeof(unsigned));
         if (e == hipSuccess) e = ensure_slot(f, 64, size_t(1) << 16);
     }
     if (e == hipSuccess) e = nqs::prepare_batch_kernels();

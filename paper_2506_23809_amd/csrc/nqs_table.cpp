@@ -190,6 +190,7 @@ int build_table(int n_qubits, int64_t n_terms, const uint64_t *x, const uint64_t
         T.max_group_terms =
             std::max(T.max_group_terms, static_cast<int>(T.goff[g + 1] - T.goff[g]));
     }
+    build_enum_index(&T);
     return NQS_OK;
 }
 
@@ -252,7 +253,34 @@ int build_flip_table(int K, HostTable *out, std::string *err) {
         T.ghm[2 * g] = lh(x0, x1);
         T.ghm[2 * g + 1] = static_cast<uint32_t>(pa / 2) | (static_cast<uint32_t>(pb / 2) << 8);
     }
+    build_enum_index(&T);
     return NQS_OK;
+}
+
+void build_enum_index(HostTable *T) {
+    uint64_t cap = 64;
+    while (cap < 2 * static_cast<uint64_t>(T->n_groups)) cap <<= 1;
+    int lg = 0;
+    while ((uint64_t(1) << lg) < cap) ++lg;
+    T->gh.assign(cap, 0xFFFFFFFFu);
+    T->gh_shift = static_cast<uint32_t>(32 - lg);
+    T->max_flip = 0;
+    const uint32_t mask = static_cast<uint32_t>(cap - 1);
+    for (int64_t g = 0; g < T->n_groups; ++g) {
+        T->max_flip = std::max(T->max_flip, popc2(T->gx[2 * g], T->gx[2 * g + 1]));
+        uint32_t slot = (T->ghm[2 * g] * 0x9E3779B1u) >> T->gh_shift;
+        while (T->gh[slot] != 0xFFFFFFFFu) slot = (slot + 1) & mask;
+        T->gh[slot] = static_cast<uint32_t>(g);
+    }
+    T->k_alpha = T->k_beta = 0;
+    for (int q = 0; q < T->n_qubits; ++q) {
+        const int w = q >> 6;
+        const uint64_t b = 1ull << (q & 63);
+        if (T->spin[0][w] & b) T->spin_q[T->k_alpha++] = static_cast<uint8_t>(q);
+        else if (T->spin[1][w] & b) T->spin_q[64 + T->k_beta++] = static_cast<uint8_t>(q);
+    }
+    T->enum_ok = T->sector_filter && T->k_alpha + T->k_beta == T->n_qubits &&
+                 T->k_alpha <= 64 && T->k_beta <= 64 && T->max_flip <= 4;
 }
 
 }  // namespace nqs

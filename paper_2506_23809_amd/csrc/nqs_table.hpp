@@ -38,7 +38,22 @@ struct HostTable {
     std::vector<uint64_t> tz;      // [T][2]
     std::vector<double> tc;        // [T] c * (-1)^{ny/2}
     int max_group_terms = 0;
+    // flip enumeration (the alternative to streaming every group past each
+    // sample): valid when every qubit has a spin, the sector test applies and
+    // no group flips more than four qubits, so the in-sector groups of a
+    // sample are among its single and double excitations
+    int max_flip = 0;              // largest popc(X) over the groups
+    bool enum_ok = false;
+    int k_alpha = 0, k_beta = 0;   // qubits per spin
+    uint8_t spin_q[128] = {};      // alpha qubits at [0, k_alpha), beta qubits at [64, 64 + k_beta)
+    // group index by X: open addressing on (h(X) * golden) >> gh_shift,
+    // linear probing, 0xFFFFFFFF = empty; keys are compared through gx
+    std::vector<uint32_t> gh;
+    uint32_t gh_shift = 0;
 };
+
+// Fill max_flip, enum_ok, the spin qubit lists and the group index.
+void build_enum_index(HostTable *T);
 
 // Sector key: half of popc(X & alpha) | half of popc(X & beta) << 8, or
 // kSectorNeverKey when either popcount is odd (the flip always leaves the
