@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: int32 VALU lane-operations per second
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_23809_amd", "csrc", "nqs_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eloc_lookup_nq40.json")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash() -> str:
@@ -46,6 +46,15 @@ def algorithmic_bytes(n_s, words, n_groups, n_terms, probes, hits, hit_terms):
     wb = 8 * words
     return (n_s * (wb + 24 + 16) + probes * 32 + (n_groups + n_terms) * (wb + 8)
             + hits * 16 + hit_terms * (wb + 8))
+
+
+def algorithmic_ops_per_probe_enum():
+    """Integer work of the flip enumeration per probe (one spin-conserving
+    flip of one sample): one XOR forming h(x ^ X) from the row and column
+    hashes, the filter word offset (shift, mask), the two filter bits (a
+    shift by h, a shift of h, a shift by that) and their AND, and the shift-OR
+    that records the outcome in the lane's row mask."""
+    return 1 + 2 + 4 + 1
 
 
 def algorithmic_ops_per_pair(n_qubits, spin_bits):
@@ -190,16 +199,29 @@ def main():
     hit_terms = st["terms"] - w.n_samples * n_diag_terms
     b_alg = algorithmic_bytes(w.n_samples, words, G, T, st["probes"], st["hits"], max(hit_terms, 0))
     hbm_equiv = b_alg / (lookup_ms / 1e3) / 1e9
-    ops_pair = algorithmic_ops_per_pair(w.n_qubits, w.K)
-    achieved_ops = ops_pair * pairs / (lookup_ms / 1e3)
+    enumerated = st.get("enum_rounds", 0) > 0
+    if enumerated:
+        kernel_name = "eloc_enum_kernel"
+        ops_unit = algorithmic_ops_per_probe_enum()
+        units = st["probes"]
+        unit_name = "probe"
+    else:
+        kernel_name = "eloc_lookup_kernel"
+        ops_unit = algorithmic_ops_per_pair(w.n_qubits, w.K)
+        units = pairs
+        unit_name = "pair"
+    achieved_ops = ops_unit * units / (lookup_ms / 1e3)
 
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes of this
+    # kernel and workload, valid only for the kernel source they were taken on
+    traffic_file = os.path.join(PROFILES, f"traffic_{kernel_name}_{w.name}.json")
+    if os.path.exists(traffic_file):
         try:
-            with open(TRAFFIC_FILE) as f:
+            with open(traffic_file) as f:
                 tr = json.load(f)
             if tr.get("kernel_source_sha256_16") == kernel_source_hash() and \
-                    tr.get("workload") == w.name:
+                    tr.get("workload") == w.name and tr.get("kernel") == kernel_name:
                 traffic = tr.get("hbm_bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
@@ -225,15 +247,16 @@ def main():
             "precision": args.precision,
         },
         "roofline": {
-            "kernel": "eloc_lookup_kernel",
+            "kernel": kernel_name,
             "bound": "alu",
             "achieved": achieved_ops / 1e12,
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "Tops/s (int32 VALU lane-ops)",
             "frac": achieved_ops / VALU_PEAK_OPS,
             "traffic": traffic,
-            "algorithmic_ops_per_pair": ops_pair,
-            "pairs_per_launch": pairs,
+            "algorithmic_ops_per_unit": ops_unit,
+            "unit_of_work": unit_name,
+            "units_per_launch": units,
             "kernel_ms": lookup_ms,
             "hbm_equivalent": {
                 "algorithmic_bytes_per_launch": b_alg,
@@ -244,6 +267,7 @@ def main():
                         "are answered by the LDS filter and the L2-resident hash",
             },
         },
+        "strategy": "enumeration" if enumerated else "streaming",
         "kernel_ms": {"hash_build": hash_ms, "eloc_lookup": lookup_ms, "eloc_finish": finish_ms},
         "counts": st,
         "probes_per_s": st["probes"] / (ms_per_step / 1e3),

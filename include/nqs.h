@@ -184,8 +184,13 @@ int nqs_sync(nqs_ham h, void *hip_stream);
  *   out[3] terms      = Pauli terms evaluated (diagonal group plus hit groups)
  *   out[4] candidates = lookups that passed the on-chip filter and went to
  *                       the hash table in device memory
+ *   out[5] rounds     = sample rounds run by the flip enumeration (0 when
+ *                       the group-streaming kernel did the lookups)
+ * With the enumeration, probes counts every spin-conserving single and
+ * double flip of each sample, which equals the streaming count when the
+ * table holds a group for each of them.
  */
-int nqs_eval_stats(nqs_ham h, int64_t out[5]);
+int nqs_eval_stats(nqs_ham h, int64_t out[6]);
 
 /*
  * Kernel timing.  nqs_profile(h, 1) makes every later nqs_eloc_eval on h

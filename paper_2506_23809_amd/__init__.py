@@ -263,10 +263,10 @@ class Hamiltonian:
         _check(load_library().nqs_sync(self._h, _stream(stream)))
 
     def stats(self):
-        out = (ctypes.c_int64 * 5)()
+        out = (ctypes.c_int64 * 6)()
         _check(load_library().nqs_eval_stats(self._h, out))
         return {"pairs": out[0], "probes": out[1], "hits": out[2], "terms": out[3],
-                "candidates": out[4]}
+                "candidates": out[4], "enum_rounds": out[5]}
 
     def profile(self, enable=True):
         """Record HIP events around each kernel stage of later evaluations."""

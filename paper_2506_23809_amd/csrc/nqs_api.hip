@@ -40,6 +40,7 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 constexpr size_t kSmallBytes = 128;                  // counters, error latch, sector flag
 constexpr size_t kErrOffset = 8 * nqs::kCounters;    // after the counters
 constexpr size_t kMaxFilterWords = size_t(1) << 15;  // 128 KB Bloom bitmap
+constexpr size_t kMaxEFilterWords = kMaxFilterWords * nqs::kEnumMaxParts;
 constexpr int64_t kMaxGroups = int64_t(1) << 26;     // queue entries pack the group in 26 bits
 
 }  // namespace
@@ -59,6 +60,7 @@ struct nqs_ham_s {
     double *part = nullptr;
     int64_t part_cap = 0;  // doubles
     uint32_t *filter = nullptr;  // Bloom bitmap, kMaxFilterWords words
+    uint32_t *efilter = nullptr; // enumeration filter partitions (allocated when first needed)
     void *small = nullptr; // counters[8] u64, err, mixed
     int64_t last_pairs = 0;
     bool ever_evaluated = false;
@@ -90,16 +92,33 @@ nqs::DevScratch scratch_of(nqs_ham h) {
     return s;
 }
 
-// Grow the per-handle scratch to hold a batch of n samples.
-int ensure_scratch(nqs_ham h, int64_t n, int64_t n_chunks, hipStream_t st) {
+// Filter sizes of one evaluation plan.
+void set_filters(nqs::DevScratch *s, nqs_ham h, const nqs::EvalLaunch &L) {
+    s->filter_log2 = L.filter_log2;
+    s->eparts_log2 = L.eparts_log2;
+    s->efilter_log2 = L.efilter_log2;
+    s->efilter = L.eparts_log2 > 0 ? h->efilter : h->filter;
+}
+
+// Grow the per-handle scratch to hold a batch of n samples (and the
+// partitioned enumeration filter when the plan uses it).
+int ensure_scratch(nqs_ham h, int64_t n, int64_t n_chunks, hipStream_t st,
+                   bool efilter = false) {
     uint64_t want = 64;
     while (want < 2 * static_cast<uint64_t>(n)) want <<= 1;
     if (want > (1ull << 31)) return fail(NQS_E_ARG, "batch too large for the sample hash");
     const size_t slot_size = h->words == 1 ? sizeof(nqs::Slot1) : sizeof(nqs::Slot2);
     const int64_t part_need = 2 * n * (n_chunks > 0 ? n_chunks : 1);
-    const bool grow = want > h->slot_cap || n > h->shx_cap || part_need > h->part_cap;
+    const bool grow = want > h->slot_cap || n > h->shx_cap || part_need > h->part_cap ||
+                      (efilter && !h->efilter);
     if (grow) {
         NQS_HIP(hipStreamSynchronize(st));
+        if (efilter && !h->efilter) {
+            if (hipMalloc(&h->efilter, kMaxEFilterWords * 4) != hipSuccess) {
+                h->efilter = nullptr;
+                return fail(NQS_E_NOMEM, "device allocation of the filter partitions failed");
+            }
+        }
         if (want > h->slot_cap) {
             if (h->slots) NQS_HIP(hipFree(h->slots));
             h->slots = nullptr;
@@ -144,10 +163,10 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool dump = hit_idx || sign_bits;
     const nqs::EvalLaunch L = nqs::plan_eval(h->dt, n, dump, &h->tune);
-    int rc = ensure_scratch(h, n, L.n_chunks, st);
+    int rc = ensure_scratch(h, n, L.n_chunks, st, L.eparts_log2 > 0);
     if (rc) return rc;
     nqs::DevScratch sc = scratch_of(h);
-    sc.filter_log2 = L.filter_log2;
+    set_filters(&sc, h, L);
     NQS_HIP(nqs::launch_reset(sc, st));
     if (h->profiling) NQS_HIP(hipEventRecord(h->ev[0], st));
     NQS_HIP(nqs::launch_hash(h->dt, sc, h->slot_cap, samples, weights, n, st));
@@ -242,6 +261,7 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
         {eri ? eri->data() : nullptr, eri ? sizeof(double) * eri->size() : 0, 0},
         {T.spin_q, sizeof(T.spin_q), 0},
         {T.gh.data(), sizeof(uint32_t) * T.gh.size(), 0},
+        {T.qcls, sizeof(T.qcls), 0},
     };
     size_t total = 0;
     for (Piece &p : pieces) {
@@ -312,6 +332,7 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
     d.spin_q = reinterpret_cast<const uint8_t *>(base + pieces[10].off);
     d.gh = reinterpret_cast<const uint32_t *>(base + pieces[11].off);
     d.gh_shift = T.gh_shift;
+    d.qcls = reinterpret_cast<const uint8_t *>(base + pieces[12].off);
     *out = h;
     return NQS_OK;
 }
@@ -395,7 +416,8 @@ int nqs_ham_info(nqs_ham h, int64_t *n_groups, int64_t *n_terms, int64_t *device
     if (device_bytes)
         *device_bytes = h->table_bytes + static_cast<int64_t>(h->slot_bytes) +
                         h->shx_cap * 4 + h->part_cap * 8 + kSmallBytes +
-                        static_cast<int64_t>(kMaxFilterWords * 4);
+                        static_cast<int64_t>(kMaxFilterWords * 4) +
+                        (h->efilter ? static_cast<int64_t>(kMaxEFilterWords * 4) : 0);
     return NQS_OK;
 }
 
@@ -406,6 +428,7 @@ int nqs_ham_destroy(nqs_ham h) {
     if (h->table_mem) (void)hipFree(h->table_mem);
     if (h->small) (void)hipFree(h->small);
     if (h->filter) (void)hipFree(h->filter);
+    if (h->efilter) (void)hipFree(h->efilter);
     if (h->slots) (void)hipFree(h->slots);
     if (h->shx) (void)hipFree(h->shx);
     if (h->part) (void)hipFree(h->part);
@@ -471,7 +494,7 @@ int nqs_sync(nqs_ham h, void *hip_stream) {
     return NQS_OK;
 }
 
-int nqs_eval_stats(nqs_ham h, int64_t out[5]) {
+int nqs_eval_stats(nqs_ham h, int64_t out[6]) {
     if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
     if (!out) return fail(NQS_E_ARG, "null output");
     if (!h->ever_evaluated) return fail(NQS_E_STATE, "no evaluation on this handle yet");
@@ -479,6 +502,7 @@ int nqs_eval_stats(nqs_ham h, int64_t out[5]) {
     NQS_HIP(hipMemcpy(c, h->small, sizeof(c), hipMemcpyDeviceToHost));
     out[0] = h->last_pairs;
     for (int k = 1; k < 5; ++k) out[k] = static_cast<int64_t>(c[k]);
+    out[5] = static_cast<int64_t>(c[6]);
     return NQS_OK;
 }
 
@@ -847,7 +871,8 @@ int64_t table_bytes(nqs_ham h) { return h->table_bytes; }
 
 int64_t scratch_bytes(nqs_ham h) {
     return static_cast<int64_t>(h->slot_bytes) + h->shx_cap * 4 + h->part_cap * 8 +
-           static_cast<int64_t>(kSmallBytes + kMaxFilterWords * 4);
+           static_cast<int64_t>(kSmallBytes + kMaxFilterWords * 4) +
+           (h->efilter ? static_cast<int64_t>(kMaxEFilterWords * 4) : 0);
 }
 
 int reserve(nqs_ham h, int64_t n, int threads, hipStream_t st) {
@@ -859,7 +884,7 @@ int reserve(nqs_ham h, int64_t n, int threads, hipStream_t st) {
     // so m * chunks(m) <= items * threads + m: size the partials for that.
     const int64_t items = int64_t(t.blocks_per_cu ? t.blocks_per_cu : 4) * 256 * 1024 / L.threads;
     const int64_t bound = (items * L.threads + n + n - 1) / n;
-    return ensure_scratch(h, n, std::max<int64_t>(L.n_chunks, bound), st);
+    return ensure_scratch(h, n, std::max<int64_t>(L.n_chunks, bound), st, L.eparts_log2 > 0);
 }
 
 void mark_evaluated(nqs_ham h, int64_t n) {
@@ -911,12 +936,13 @@ int plan_batch(const nqs_batch_item *items, int n_items, int threads, hipStream_
             L.n_chunks = 1;
             L.chunk_len = h->dt.n_groups - L.g_first;
         }
-        const int rc = ensure_scratch(h, std::max<int64_t>(it.n, 1), L.n_chunks, st);
+        const int rc = ensure_scratch(h, std::max<int64_t>(it.n, 1), L.n_chunks, st,
+                                      L.eparts_log2 > 0);
         if (rc) return rc;
         JobDesc &J = jobs[k];
         J.tab = h->dt;
         J.sc = scratch_of(h);
-        J.sc.filter_log2 = L.filter_log2;
+        set_filters(&J.sc, h, L);
         J.samples = it.samples;
         J.weights = it.weights;
         J.log_amp = it.log_amp;
@@ -937,6 +963,9 @@ int plan_batch(const nqs_batch_item *items, int n_items, int threads, hipStream_
         shape.max_n = std::max(shape.max_n, it.n);
         shape.max_clear = std::max<int64_t>(shape.max_clear,
                                             std::max<int64_t>(h->slot_cap, int64_t(1) << L.filter_log2));
+        if (L.eparts_log2 > 0)
+            shape.max_clear = std::max<int64_t>(shape.max_clear,
+                                                int64_t(1) << (L.eparts_log2 + L.efilter_log2));
         cost[k] = it.n * (h->dt.n_groups - L.g_first);
     }
     // work list: largest jobs first (the persistent kernel drains it in order),

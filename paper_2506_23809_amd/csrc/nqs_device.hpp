@@ -34,22 +34,31 @@ struct DevTable {
     const uint8_t *spin_q; // [128]: alpha qubits at [0, k_alpha), beta at [64, 64 + k_beta)
     const uint32_t *gh;    // group index slots (0xFFFFFFFF = empty)
     uint32_t gh_shift;     // 32 - log2(slots)
+    const uint8_t *qcls;   // [128] class of each qubit (filter partitions)
 };
 
 // ---- flip enumeration: shape of one round
 //
 // A block evaluates B samples per round.  Per sample it keeps in LDS a
 // 64-byte record, its occupied/virtual qubit lists (4 x 64 bytes), one
-// accumulator per wave (16 x 16 bytes) and the row lists of the three
-// products (8 bytes per row):
+// accumulator per wave (16 x 16 bytes), 128 bytes of bucket counts and
+// offsets, and four lists of (hash u32, code u16) entries, each padded to a
+// multiple of 4 entries:
+//   rows of A  = beta singles + none      (sorted by class)
+//   rows of Ba = alpha occupied pairs
+//   rows of Bb = beta occupied pairs      (sorted by class)
+//   cols of Bb = beta virtual pairs       (sorted by class)
+// for the products
 //   A  = (beta singles + none) x (alpha singles + none), without (none, none)
 //   Ba = alpha occupied pairs x alpha virtual pairs
 //   Bb = beta occupied pairs x beta virtual pairs
-// B is the largest count (at most 16) whose records fit beside the filter.
+// (alpha columns are computed in registers).  B is the largest count (at
+// most 16) that fits beside the filter and the queues.
 constexpr int kEnumThreads = 1024;
 constexpr int kEnumWaves = kEnumThreads / 64;
 constexpr int kEnumQueue = 64;     // (code, hash) entries per wave
 constexpr int kEnumMaxB = 16;
+constexpr int kEnumMaxParts = 8;   // filter partitions (sample classes)
 // LDS of one CU (160 KB) less 64 bytes for the scalar variables of the
 // persistent batch kernel; every enumeration block takes all of it: a static
 // 128 KB filter (whatever its used size) and the dynamic rest
@@ -58,18 +67,25 @@ constexpr int kEnumFilterWords = 1 << 15;
 constexpr int kEnumDynLds = kEnumLds - 4 * kEnumFilterWords;
 constexpr int kEnumScalars = 64;
 constexpr int kEnumRowPad = 32;    // rows may be read 3 entries past the end
-constexpr int kEnumDynFixed = 512 + kEnumWaves * kEnumQueue * 8 + kEnumScalars + kEnumRowPad;
-constexpr int kEnumPerSampleFixed = 64 + 256 + kEnumWaves * 16;
+// dynamic LDS: hash words (512 B), qubit classes (128 B), queues, scalars,
+// padding, then the per-sample records
+constexpr int kEnumQueueOff = 512 + 128;
+constexpr int kEnumScalarOff = kEnumQueueOff + kEnumWaves * kEnumQueue * 8;
+constexpr int kEnumDynFixed = kEnumScalarOff + kEnumScalars + kEnumRowPad;
+constexpr int kEnumPerSampleFixed = 64 + 256 + kEnumWaves * 16 + 128;
 
 __host__ __device__ inline int enum_pairs(int m) { return m * (m - 1) / 2; }
+__host__ __device__ inline int enum_pad4(int m) { return (m + 3) & ~3; }
 
-__host__ __device__ inline int enum_rows(int ka, int kb, int na, int nb) {
-    return 1 + nb * (kb - nb) + enum_pairs(na) + enum_pairs(nb);
+// List entries per sample (padded): rows of A, Ba, Bb and columns of Bb.
+__host__ __device__ inline int enum_list_entries(int ka, int kb, int na, int nb) {
+    return enum_pad4(1 + nb * (kb - nb)) + enum_pad4(enum_pairs(na)) + enum_pad4(enum_pairs(nb)) +
+           enum_pad4(enum_pairs(kb - nb));
 }
 
 // Samples per round for the given occupation, 0 if one does not fit.
 __host__ __device__ inline int enum_round_size(int ka, int kb, int na, int nb) {
-    const int per = kEnumPerSampleFixed + 8 * enum_rows(ka, kb, na, nb);
+    const int per = kEnumPerSampleFixed + 6 * enum_list_entries(ka, kb, na, nb);
     const int b = (kEnumDynLds - kEnumDynFixed) / per;
     return b < kEnumMaxB ? b : kEnumMaxB;
 }
@@ -93,6 +109,11 @@ struct DevScratch {
     uint32_t slot_mask;     // capacity - 1 (capacity is a power of two)
     uint32_t slot_shift;    // 32 - log2(capacity)
     int filter_log2;        // log2 of the filter size in 32-bit words
+    // filter of the enumeration: 1 << eparts_log2 partitions (sample classes)
+    // of 1 << efilter_log2 words; with one partition it is the filter above
+    uint32_t *efilter;
+    int eparts_log2;
+    int efilter_log2;
 };
 
 constexpr uint32_t kGoldenMul = 0x9E3779B1u;
@@ -121,6 +142,8 @@ struct EvalLaunch {
     int threads;        // lookup kernel block size
     int filter_log2;    // filter words = 1 << filter_log2
     size_t lds_bytes;   // dynamic LDS of the lookup kernel
+    int eparts_log2;    // enumeration filter: partitions ...
+    int efilter_log2;   // ... of this many words (log2)
 };
 
 constexpr int kStrategyAuto = 0, kStrategyStream = 1, kStrategyEnum = 2;

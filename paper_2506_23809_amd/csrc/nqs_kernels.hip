@@ -165,10 +165,12 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 // Clears the slot indices (to -1) and the Bloom bitmap (to 0).
 __global__ void hash_clear_kernel(int32_t *__restrict__ idx_words, int stride_words,
                                   uint32_t capacity, uint32_t *__restrict__ filter,
-                                  uint32_t filter_words) {
+                                  uint32_t filter_words, uint32_t *__restrict__ efilter,
+                                  uint32_t efilter_words) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < capacity) idx_words[static_cast<size_t>(s) * stride_words] = -1;
     if (s < filter_words) filter[s] = 0u;
+    if (s < efilter_words) efilter[s] = 0u;
 }
 
 // One thread per sample: range check, sector uniformity, counts >= 0, linear
@@ -204,7 +206,25 @@ __device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScr
     const uint32_t h = linear_hash<W>(k, tab.hr);
     sc.shx[i] = h;
     const uint32_t fmask = (1u << sc.filter_log2) - 1u;
-    atomicOr(&sc.filter[(h >> 5) & fmask], (1u << (h & 31)) | (1u << (h >> 27)));
+    const uint32_t fbits = (1u << (h & 31)) | (1u << (h >> 27));
+    atomicOr(&sc.filter[(h >> 5) & fmask], fbits);
+    if (sc.eparts_log2 > 0) {
+        // the partition of the enumeration filter: class of x, the XOR of
+        // the classes of its occupied beta qubits
+        uint32_t c = 0;
+        uint64_t m0 = w0 & tab.spin_b0, m1 = w1 & tab.spin_b1;
+        while (m0) {
+            c ^= tab.qcls[__builtin_ctzll(m0)];
+            m0 &= m0 - 1;
+        }
+        while (m1) {
+            c ^= tab.qcls[64 + __builtin_ctzll(m1)];
+            m1 &= m1 - 1;
+        }
+        c &= (1u << sc.eparts_log2) - 1u;
+        const uint32_t emask = (1u << sc.efilter_log2) - 1u;
+        atomicOr(&sc.efilter[(c << sc.efilter_log2) + ((h >> 5) & emask)], fbits);
+    }
     S *slots = static_cast<S *>(sc.slots);
     uint32_t slot = slot_of(h, sc.slot_shift);
     for (uint32_t probe = 0; probe <= sc.slot_mask; ++probe) {
@@ -773,17 +793,34 @@ struct alignas(16) EnumSample {
     double la, ph;
     int64_t idx;
     uint32_t hx;
-    uint32_t pad[3];
+    uint32_t cx;     // class of x: the filter partition that holds it
+    uint32_t pad[2];
 };
 static_assert(sizeof(EnumSample) == 64, "one 64-byte record per sample");
 
+// Per-sample bucket counts and offsets (128 bytes): beta occupied / virtual
+// orbitals per class, and for each sorted list the start of each class
+// bucket (entry offsets within the list, kEnumMaxParts + 1 each), and the
+// work units of each partition.
+struct EnumMeta {
+    uint8_t nocc[kEnumMaxParts], nvir[kEnumMaxParts];
+    uint16_t offa[kEnumMaxParts + 1];   // rows of A
+    uint16_t offb[kEnumMaxParts + 1];   // rows of Bb
+    uint16_t offc[kEnumMaxParts + 1];   // columns of Bb
+    uint16_t units[kEnumMaxParts];      // work units of each partition
+    uint16_t pad[1];
+};
+static_assert(sizeof(EnumMeta) <= 128, "metadata fits its 128 bytes");
+
 struct EnumShape {
     int B;               // samples per round, 0 = enumeration not usable
+    int parts;           // filter partitions (sample classes)
     int na, nb, va, vb;  // occupied / virtual orbitals per spin
     int ra, rba, rbb;    // rows of A, Ba, Bb
-    int ca, cba, cbb;    // columns of A, Ba, Bb
-    int rows;            // ra + rba + rbb
-    int ua, uba, ubb;    // work units of A, Ba, Bb
+    int ca, cba, cbb;    // columns of A, Ba, Bb (cbb: the Bb column list)
+    int la, lba, lbb;    // list offsets (entries): rows of A at 0, Ba, Bb, then Bb columns
+    int lcb;
+    int L;               // padded list entries per sample
 };
 
 __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
@@ -800,16 +837,18 @@ __device__ __forceinline__ EnumShape enum_shape(const DevTable &tab, const DevSc
     s.va = tab.k_alpha - s.na;
     s.vb = tab.k_beta - s.nb;
     s.B = enum_round_size(tab.k_alpha, tab.k_beta, s.na, s.nb);
+    s.parts = 1 << sc.eparts_log2;
     s.ra = 1 + s.nb * s.vb;
     s.ca = 1 + s.na * s.va;
     s.rba = enum_pairs(s.na);
     s.cba = enum_pairs(s.va);
     s.rbb = enum_pairs(s.nb);
     s.cbb = enum_pairs(s.vb);
-    s.rows = s.ra + s.rba + s.rbb;
-    s.ua = ceil_div(s.ca, 64) * ceil_div(s.ra, kEnumRowSeg);
-    s.uba = (s.rba && s.cba) ? ceil_div(s.cba, 64) * ceil_div(s.rba, kEnumRowSeg) : 0;
-    s.ubb = (s.rbb && s.cbb) ? ceil_div(s.cbb, 64) * ceil_div(s.rbb, kEnumRowSeg) : 0;
+    s.la = 0;
+    s.lba = enum_pad4(s.ra);
+    s.lbb = s.lba + enum_pad4(s.rba);
+    s.lcb = s.lbb + enum_pad4(s.rbb);
+    s.L = s.lcb + enum_pad4(s.cbb);
     return s;
 }
 
@@ -849,57 +888,111 @@ __device__ __forceinline__ int64_t group_find(const DevTable &tab, uint32_t hX, 
 }
 
 struct EnumCounts {
-    unsigned long long probes = 0, cand = 0;  // wave-uniform
-    unsigned long long hits = 0, terms = 0;   // per lane
+    unsigned long long probes = 0, cand = 0, rounds = 0;  // wave-uniform
+    unsigned long long hits = 0, terms = 0;               // per lane
 };
 
-// One round: samples [round * B, round * B + B) of the batch.  The filter
-// is in LDS at offset 0 (load_filter = false reuses it).  Partial sums of
-// the hits go to sc.part[i] in a fixed order: per wave in queue order, then
-// over the waves in wave order.
+// Position of the pair (i < j) of a class-sorted orbital list in the pair
+// list sorted by pair class (u ^ w): bucket s holds the blocks of class
+// pairs (u, u ^ s), u <= u ^ s, in increasing u; pairs inside one class come
+// in pair_of order, pairs across two classes row-major.
+__device__ __forceinline__ int sorted_pair_pos(const uint8_t *cnt, const uint16_t *off, int parts,
+                                               int i, int j, int u, int w) {
+    int start_u = 0, start_w = 0;
+    for (int c = 0; c < parts; ++c) {
+        start_u += c < u ? cnt[c] : 0;
+        start_w += c < w ? cnt[c] : 0;
+    }
+    const int s = u ^ w;
+    int pre = 0;
+    for (int c = 0; c < u; ++c) {
+        const int d = c ^ s;
+        if (s == 0) pre += enum_pairs(cnt[c]);
+        else if (c < d) pre += cnt[c] * cnt[d];
+    }
+    const int il = i - start_u, jl = j - start_w;
+    const int loc = (s == 0) ? jl * (jl - 1) / 2 + il : il * cnt[w] + jl;
+    return off[s] + pre + loc;
+}
+
+// One round: samples [round * B, round * B + B) of the batch, all filter
+// partitions in turn (with one partition its filter is already in LDS).
+// Partial sums of the hits go to sc.part[i] in a fixed order: per wave in
+// queue order, then over the waves in wave order.
 template <int W, bool DUMP, int P, bool SCV>
-__device__ __forceinline__ void enum_round(const uint32_t *filt, const DevTable &tab,
+__device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
                                            const DevScratch &sc, const EnumShape &S,
-                           const uint64_t *__restrict__ samples,
-                           const double *__restrict__ log_amp, const double *__restrict__ phase,
-                           int64_t n, int64_t round, int32_t *__restrict__ hit_idx,
-                           uint32_t *__restrict__ sign_bits, int64_t sign_words,
-                           EnumCounts &cnt) {
+                                           const uint64_t *__restrict__ samples,
+                                           const double *__restrict__ log_amp,
+                                           const double *__restrict__ phase, int64_t n,
+                                           int64_t round, int32_t *__restrict__ hit_idx,
+                                           uint32_t *__restrict__ sign_bits, int64_t sign_words,
+                                           EnumCounts &cnt) {
     using Sl = typename SlotT<W>::type;
     char *smem = dyn_lds();
     const int lane = threadIdx.x & 63;
     // wave-uniform (scalar) so that unit and row loops run on the scalar unit
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int fwords = 1 << sc.filter_log2;
+    const int parts = S.parts;
     uint32_t *hr = reinterpret_cast<uint32_t *>(smem);
-    uint2 *queue = reinterpret_cast<uint2 *>(smem + 512) + wave * kEnumQueue;
+    uint8_t *qcl = reinterpret_cast<uint8_t *>(smem + 512);
+    uint2 *queue = reinterpret_cast<uint2 *>(smem + kEnumQueueOff) + wave * kEnumQueue;
     char *per = smem + kEnumDynFixed;
     const int B = S.B;
+    const int L = S.L;
     EnumSample *smp = reinterpret_cast<EnumSample *>(per);
-    uint8_t *ov = reinterpret_cast<uint8_t *>(per + 64 * B);        // [B][4][64]
-    char *accb = per + 64 * B + 256 * B;                             // [B][16][16 B]
-    uint2 *rows = reinterpret_cast<uint2 *>(per + 64 * B + 256 * B + kEnumWaves * 16 * B);
+    uint8_t *ov = reinterpret_cast<uint8_t *>(per + 64 * B);                      // [B][256]
+    char *accb = per + 320 * B;                                                    // [B][16][16 B]
+    EnumMeta *meta = reinterpret_cast<EnumMeta *>(per + 320 * B + kEnumWaves * 16 * B);  // [B]
+    uint32_t *lh = reinterpret_cast<uint32_t *>(per + kEnumPerSampleFixed * B);    // [B][L]
+    uint16_t *lc = reinterpret_cast<uint16_t *>(per + kEnumPerSampleFixed * B + 4 * L * B);
     const Sl *__restrict__ slots = static_cast<const Sl *>(sc.slots);
 
     const int64_t s0 = round * B;
     const int nb = static_cast<int>(min(static_cast<int64_t>(B), n - s0));
     if (nb <= 0) return;
+    ++cnt.rounds;
+    const uint32_t pmask = static_cast<uint32_t>(parts - 1);
 
-    // stage 1: records and occupied / virtual lists, one wave per sample
-    for (int k = threadIdx.x; k < 128; k += blockDim.x) hr[k] = tab.hr[k];
+    // stage 1: records, alpha lists, beta lists sorted by class (stable),
+    // class counts, bucket offsets and work units; one wave per sample
     for (int b = wave; b < nb; b += kEnumWaves) {
         const int64_t i = s0 + b;
         const uint64_t w0 = samples[2 * i], w1 = samples[2 * i + 1];
         uint8_t *o = ov + 256 * b;
-#pragma unroll
-        for (int sp = 0; sp < 2; ++sp) {
-            const int kq = sp ? tab.k_beta : tab.k_alpha;
-            const bool in = lane < kq;
-            const int q = in ? tab.spin_q[64 * sp + lane] : 0;
+        EnumMeta &m = meta[b];
+        uint32_t cx = 0;
+        {
+            const bool in = lane < tab.k_alpha;
+            const int q = in ? tab.spin_q[lane] : 0;
             const bool occ = in && (((q < 64 ? w0 : w1) >> (q & 63)) & 1ull);
             const uint64_t mo = __ballot(occ), mv = __ballot(in && !occ);
-            if (occ) o[128 * sp + lanes_below(mo)] = static_cast<uint8_t>(q);
-            if (in && !occ) o[128 * sp + 64 + lanes_below(mv)] = static_cast<uint8_t>(q);
+            if (occ) o[lanes_below(mo)] = static_cast<uint8_t>(q);
+            if (in && !occ) o[64 + lanes_below(mv)] = static_cast<uint8_t>(q);
+        }
+        {
+            const bool in = lane < tab.k_beta;
+            const int q = in ? tab.spin_q[64 + lane] : 0;
+            const bool occ = in && (((q < 64 ? w0 : w1) >> (q & 63)) & 1ull);
+            const uint32_t c = in ? (qcl[q] & pmask) : 0u;
+            int no = 0, nv = 0;
+            for (int u = 0; u < parts; ++u) {
+                const uint64_t mo = __ballot(occ && c == static_cast<uint32_t>(u));
+                const uint64_t mv = __ballot(in && !occ && c == static_cast<uint32_t>(u));
+                if (occ && c == static_cast<uint32_t>(u)) o[128 + no + lanes_below(mo)] = static_cast<uint8_t>(q);
+                if (in && !occ && c == static_cast<uint32_t>(u))
+                    o[192 + nv + lanes_below(mv)] = static_cast<uint8_t>(q);
+                if (lane == 0) {
+                    m.nocc[u] = static_cast<uint8_t>(__popcll(mo));
+                    m.nvir[u] = static_cast<uint8_t>(__popcll(mv));
+                }
+                no += __popcll(mo);
+                nv += __popcll(mv);
+            }
+            uint32_t v = occ ? c : 0u;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v ^= __shfl_xor(v, off);
+            cx = v;
         }
         if (lane == 0) {
             EnumSample r;
@@ -909,57 +1002,122 @@ __device__ __forceinline__ void enum_round(const uint32_t *filt, const DevTable 
             r.ph = phase[i];
             r.idx = i;
             r.hx = sc.shx[i];
-            r.pad[0] = r.pad[1] = r.pad[2] = 0;
+            r.cx = cx;
+            r.pad[0] = r.pad[1] = 0;
             smp[b] = r;
         }
         if (lane < kEnumWaves) reinterpret_cast<uint4 *>(accb + kEnumWaves * 16 * b)[lane] =
             make_uint4(0u, 0u, 0u, 0u);
+        if (lane == 0) {
+            int oa = 0, obb = 0, oc = 0;
+            for (int t = 0; t < parts; ++t) {
+                m.offa[t] = static_cast<uint16_t>(oa);
+                m.offb[t] = static_cast<uint16_t>(obb);
+                m.offc[t] = static_cast<uint16_t>(oc);
+                int sa = t == 0 ? 1 : 0, sb = 0, sc2 = 0;  // the none row opens bucket 0 of A
+                for (int u = 0; u < parts; ++u) {
+                    const int d = u ^ t;
+                    sa += m.nocc[u] * m.nvir[d];
+                    if (t == 0) {
+                        sb += enum_pairs(m.nocc[u]);
+                        sc2 += enum_pairs(m.nvir[u]);
+                    } else if (u < d) {
+                        sb += m.nocc[u] * m.nocc[d];
+                        sc2 += m.nvir[u] * m.nvir[d];
+                    }
+                }
+                oa += sa;
+                obb += sb;
+                oc += sc2;
+            }
+            m.offa[parts] = static_cast<uint16_t>(oa);
+            m.offb[parts] = static_cast<uint16_t>(obb);
+            m.offc[parts] = static_cast<uint16_t>(oc);
+            // cx: the class of this sample, computed above
+            const int cha = ceil_div(S.ca, 64);
+            const int uba = (S.rba && S.cba) ? ceil_div(S.cba, 64) * ceil_div(S.rba, kEnumRowSeg) : 0;
+            for (int p = 0; p < parts; ++p) {
+                const int t = p ^ static_cast<int>(cx);
+                int u = cha * ceil_div(m.offa[t + 1] - m.offa[t], kEnumRowSeg);
+                if (t == 0) u += uba;
+                for (int v = 0; v < parts; ++v) {
+                    const int nc = m.offc[v + 1] - m.offc[v];
+                    const int nr = m.offb[(t ^ v) + 1] - m.offb[t ^ v];
+                    u += ceil_div(nc, 64) * ceil_div(nr, kEnumRowSeg);
+                }
+                m.units[p] = static_cast<uint16_t>(u);
+            }
+        }
     }
     __syncthreads();
 
-    // stage 2: row lists (hash, code in fields 2 and 3)
-    const int R = S.rows;
-    for (int t = threadIdx.x; t < nb * R; t += blockDim.x) {
-        const int b = t / R, r = t - b * R;
+    // stage 3: list entries (hash, code) at their sorted positions
+    const int E = S.ra + S.rba + S.rbb + S.cbb;
+    for (int t = threadIdx.x; t < nb * E; t += blockDim.x) {
+        const int b = t / E;
+        int e = t - b * E;
         const uint8_t *o = ov + 256 * b;
+        const EnumMeta &m = meta[b];
         uint32_t qa, qb;
-        if (r < S.ra) {
-            if (r == 0) {
-                rows[t] = make_uint2(0u, kNoPair << 14);
+        int pos;
+        if (e < S.ra) {
+            if (e == 0) {
+                lh[b * L] = 0u;
+                lc[b * L] = static_cast<uint16_t>(kNoPair);
                 continue;
             }
-            const int e = r - 1;
-            const int ii = e / S.vb;
+            // beta single (occupied i -> virtual a), both in class order
+            const int k = e - 1;
+            const int ii = k / S.vb, aa = k - ii * S.vb;
             qa = o[128 + ii];
-            qb = o[192 + (e - ii * S.vb)];
-        } else if (r < S.ra + S.rba) {
+            qb = o[192 + aa];
+            const int u = qcl[qa] & pmask, d = qcl[qb] & pmask, tt = u ^ d;
+            int su = 0, sd = 0, pre = 0;
+            for (int c = 0; c < parts; ++c) {
+                su += c < u ? m.nocc[c] : 0;
+                sd += c < d ? m.nvir[c] : 0;
+                pre += c < u ? m.nocc[c] * m.nvir[c ^ tt] : 0;
+            }
+            pos = S.la + m.offa[tt] + (tt == 0 ? 1 : 0) + pre + (ii - su) * m.nvir[d] + (aa - sd);
+        } else if ((e -= S.ra) < S.rba) {
             int ii, jj;
-            pair_of(r - S.ra, ii, jj);
+            pair_of(e, ii, jj);
             qa = o[ii];
             qb = o[jj];
-        } else {
+            pos = S.lba + e;
+        } else if ((e -= S.rba) < S.rbb) {
             int ii, jj;
-            pair_of(r - S.ra - S.rba, ii, jj);
+            pair_of(e, ii, jj);
             qa = o[128 + ii];
             qb = o[128 + jj];
+            pos = S.lbb + sorted_pair_pos(m.nocc, m.offb, parts, ii, jj, qcl[qa] & pmask,
+                                          qcl[qb] & pmask);
+        } else {
+            e -= S.rbb;
+            int ii, jj;
+            pair_of(e, ii, jj);
+            qa = o[192 + ii];
+            qb = o[192 + jj];
+            pos = S.lcb + sorted_pair_pos(m.nvir, m.offc, parts, ii, jj, qcl[qa] & pmask,
+                                          qcl[qb] & pmask);
         }
-        rows[t] = make_uint2(hr[qa] ^ hr[qb], (qa | (qb << 7)) << 14);
+        lh[b * L + pos] = hr[qa] ^ hr[qb];
+        lc[b * L + pos] = static_cast<uint16_t>(qa | (qb << 7));
     }
     __syncthreads();
 
-    // stage 3: work units, round-robin over the waves
-    const uint32_t fbytes_mask = static_cast<uint32_t>(fwords - 1) << 2;
-    const char *filt_b = reinterpret_cast<const char *>(filt);
+    // stage 4: probes, partition by partition; work units round-robin over
+    // the waves
     uint32_t qn = 0;
 
-    auto flush = [&](uint32_t m) {
+    auto flush = [&](uint32_t mcount) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const uint2 e = lane < static_cast<int>(m) ? queue[lane] : make_uint2(0u, 0u);
+        const uint2 e = lane < static_cast<int>(mcount) ? queue[lane] : make_uint2(0u, 0u);
         const int b = static_cast<int>(e.x >> 28);
         bool hit = false;
         double cre = 0.0, cim = 0.0;
         float pre = 0.f, ere = 0.f, pim = 0.f, eim = 0.f;
-        if (lane < static_cast<int>(m)) {
+        if (lane < static_cast<int>(mcount)) {
             const EnumSample rec = smp[b];
             Key<W> x, X;
             x.w[0] = rec.x0;
@@ -1051,122 +1209,173 @@ __device__ __forceinline__ void enum_round(const uint32_t *filt, const DevTable 
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     };
 
-    const int U = S.ua + S.uba + S.ubb;
-    for (int u = wave; u < U * nb; u += kEnumWaves) {
-        const int l = u / nb, b = u - (u / nb) * nb;
-        const uint8_t *o = ov + 256 * b;
-        const EnumSample *rec = smp + b;
-        int ncol, row0, nrow, lu;
-        int prod;
-        if (l < S.ua) {
-            prod = 0; lu = l; ncol = S.ca; row0 = 0; nrow = S.ra;
-        } else if (l < S.ua + S.uba) {
-            prod = 1; lu = l - S.ua; ncol = S.cba; row0 = S.ra; nrow = S.rba;
-        } else {
-            prod = 2; lu = l - S.ua - S.uba; ncol = S.cbb; row0 = S.ra + S.rba; nrow = S.rbb;
+    const uint32_t fbytes_mask = ((1u << sc.efilter_log2) - 1u) << 2;
+    const char *filt_b = reinterpret_cast<const char *>(filt);
+    const int cha = ceil_div(S.ca, 64);
+    const int nseg_ba = ceil_div(S.rba, kEnumRowSeg);
+    const int uba = (S.rba && S.cba) ? ceil_div(S.cba, 64) * nseg_ba : 0;
+    for (int p = 0; p < parts; ++p) {
+        if (parts > 1) {
+            // partition p of the filter: samples of class p
+            __syncthreads();
+            const uint4 *gf = reinterpret_cast<const uint4 *>(
+                sc.efilter + (static_cast<size_t>(p) << sc.efilter_log2));
+            uint4 *f4 = reinterpret_cast<uint4 *>(filt);
+            for (int k = threadIdx.x; k < ((1 << sc.efilter_log2) >> 2); k += blockDim.x)
+                f4[k] = gf[k];
+            __syncthreads();
         }
-        const int nseg = ceil_div(nrow, kEnumRowSeg);
-        const int ch = lu / nseg, seg = lu - (lu / nseg) * nseg;
-        const int k = ch * 64 + lane;
-        const bool act = k < ncol;
-        // this lane's column: hash (with h(x)) and code in fields 0 and 1
-        uint32_t colh = 0, colc = kNoPair;
-        if (act) {
-            uint32_t qa = kNoQubit, qb = kNoQubit;
-            if (prod == 0) {
-                if (k > 0) {
-                    const int e = k - 1;
-                    const int ii = e / S.va;
-                    qa = o[ii];
-                    qb = o[64 + (e - ii * S.va)];
-                }
-            } else if (prod == 1) {
-                int ii, jj;
-                pair_of(k, ii, jj);
-                qa = o[64 + ii];
-                qb = o[64 + jj];
+        int U = 0;
+        for (int b = 0; b < nb; ++b) U += meta[b].units[p];
+        U = __builtin_amdgcn_readfirstlane(U);
+        int ub = 0, bb = 0;  // first unit of sample bb
+        for (int u = wave; u < U; u += kEnumWaves) {
+            // sample of unit u (units are sample-major)
+            while (u >= ub + meta[bb].units[p]) {
+                ub += meta[bb].units[p];
+                ++bb;
+            }
+            const int b = __builtin_amdgcn_readfirstlane(bb);
+            int l = u - __builtin_amdgcn_readfirstlane(ub);
+            const EnumMeta &m = meta[b];
+            const uint8_t *o = ov + 256 * b;
+            const int t = p ^ static_cast<int>(smp[b].cx);
+            // unit l of sample b: product, column chunk, row segment
+            int prod, ch, seg, ncol, col0 = 0, row0, nrow;
+            const int nra = m.offa[t + 1] - m.offa[t];
+            const int ua = cha * ceil_div(nra, kEnumRowSeg);
+            if (l < ua) {
+                prod = 0;
+                const int ns = ceil_div(nra, kEnumRowSeg);
+                ch = l / ns;
+                seg = l - ch * ns;
+                ncol = S.ca;
+                row0 = S.la + m.offa[t];
+                nrow = nra;
+            } else if (t == 0 && l < ua + uba) {
+                prod = 1;
+                l -= ua;
+                ch = l / nseg_ba;
+                seg = l - ch * nseg_ba;
+                ncol = S.cba;
+                row0 = S.lba;
+                nrow = S.rba;
             } else {
-                int ii, jj;
-                pair_of(k, ii, jj);
-                qa = o[192 + ii];
-                qb = o[192 + jj];
+                prod = 2;
+                l -= ua + (t == 0 ? uba : 0);
+                int v = 0, uv = 0, ns = 1;
+                for (; v < parts; ++v) {
+                    const int nc = m.offc[v + 1] - m.offc[v];
+                    nrow = m.offb[(t ^ v) + 1] - m.offb[t ^ v];
+                    ns = ceil_div(nrow, kEnumRowSeg);
+                    uv = ceil_div(nc, 64) * ns;
+                    if (l < uv) break;
+                    l -= uv;
+                }
+                ch = l / ns;
+                seg = l - ch * ns;
+                ncol = m.offc[v + 1] - m.offc[v];
+                col0 = S.lcb + m.offc[v];
+                row0 = S.lbb + m.offb[t ^ v];
             }
-            if (qa != kNoQubit) {
-                colh = hr[qa] ^ hr[qb];
-                colc = qa | (qb << 7);
+            const int k = ch * 64 + lane;
+            const bool act = k < ncol;
+            // this lane's column: hash (with h(x)) and code in fields 0 and 1
+            uint32_t colh = 0, colc = kNoPair;
+            if (act) {
+                if (prod == 2) {
+                    colh = lh[b * L + col0 + k];
+                    colc = lc[b * L + col0 + k];
+                } else {
+                    uint32_t qa = kNoQubit, qb = kNoQubit;
+                    if (prod == 0) {
+                        if (k > 0) {
+                            const int e = k - 1;
+                            const int ii = e / S.va;
+                            qa = o[ii];
+                            qb = o[64 + (e - ii * S.va)];
+                        }
+                    } else {
+                        int ii, jj;
+                        pair_of(k, ii, jj);
+                        qa = o[64 + ii];
+                        qb = o[64 + jj];
+                    }
+                    if (qa != kNoQubit) {
+                        colh = hr[qa] ^ hr[qb];
+                        colc = qa | (qb << 7);
+                    }
+                }
             }
-        }
-        colh ^= rec->hx;
-        colc |= static_cast<uint32_t>(b) << 28;
-        const uint64_t colmask = __ballot(act);
-        // (none, none) is x itself: never a probe
-        const bool excl0 = prod == 0 && ch == 0 && seg == 0;
-        const int r0 = seg * kEnumRowSeg;
-        const int nr = min(nrow - r0, kEnumRowSeg);
-        const uint2 *rw = rows + b * R + row0 + r0;
-        cnt.probes += static_cast<unsigned long long>(__popcll(colmask)) * nr - (excl0 ? 1ull : 0ull);
-        // probes: the filter bit of row r lands in bit nq - 1 - r of pm,
-        // nq = nr rounded up to whole groups of 4 (rows past nr are read
-        // from the padding or the next list and masked off below)
-        uint32_t pm = 0;
-        const int nq = (nr + 3) & ~3;
-        for (int r = 0; r < nr; r += 4) {
-            uint2 re[4];
-            uint32_t h[4], fw[4];
+            colh ^= smp[b].hx;
+            colc |= static_cast<uint32_t>(b) << 28;
+            const uint64_t colmask = __ballot(act);
+            // (none, none) is x itself: never a probe
+            const bool excl0 = prod == 0 && t == 0 && ch == 0 && seg == 0;
+            const int r0 = seg * kEnumRowSeg;
+            const int nr = min(nrow - r0, kEnumRowSeg);
+            const uint32_t *rw = lh + b * L + row0 + r0;
+            const uint16_t *rc = lc + b * L + row0 + r0;
+            cnt.probes += static_cast<unsigned long long>(__popcll(colmask)) * nr -
+                          (excl0 ? 1ull : 0ull);
+            // probes: the filter bit of row r lands in bit nq - 1 - r of pm,
+            // nq = nr rounded up to whole groups of 4 (rows past nr are read
+            // from the next list or the padding and masked off below)
+            uint32_t pm = 0;
+            const int nq = (nr + 3) & ~3;
+            for (int r = 0; r < nr; r += 4) {
+                uint32_t h[4], fw[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) re[v] = rw[r + v];
+                for (int v = 0; v < 4; ++v) h[v] = colh ^ rw[r + v];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                h[v] = colh ^ re[v].x;
-                // word (h >> 5) of the bitmap, as a byte offset
-                fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + ((h[v] >> 3) & fbytes_mask));
-            }
+                for (int v = 0; v < 4; ++v)
+                    // word (h >> 5) of the bitmap, as a byte offset
+                    fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + ((h[v] >> 3) & fbytes_mask));
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                pm = (pm << 1) | ((fw[v] >> (h[v] & 31)) & (fw[v] >> (h[v] >> 27)) & 1u);
-        }
-        // rows [0, nr) are bits (nq - 1 - nr, nq - 1]
-        uint32_t keep = (nr >= 32 ? 0xFFFFFFFFu : ((1u << nr) - 1u)) << (nq - nr);
-        if (!act) keep = 0u;
-        if (excl0 && lane == 0) keep &= ~(1u << (nq - 1));
-        pm &= keep;
-        // filter survivors into the queue
-        for (;;) {
-            const uint64_t any = __ballot(pm != 0u);
-            if (!any) break;
-            const bool has = pm != 0u;
-            const int rr = has ? nq - 1 - __builtin_ctz(pm) : 0;
-            pm &= pm - 1u;
-            const uint2 e = rw[rr];
-            const uint32_t c = static_cast<uint32_t>(__popcll(any));
-            cnt.cand += c;
-            if (qn + c > static_cast<uint32_t>(kEnumQueue)) {
-                flush(qn);
-                qn = 0;
+                for (int v = 0; v < 4; ++v)
+                    pm = (pm << 1) | ((fw[v] >> (h[v] & 31)) & (fw[v] >> (h[v] >> 27)) & 1u);
             }
-            if (has) queue[qn + lanes_below(any)] = make_uint2(colc | e.y, colh ^ e.x);
-            qn += c;
+            // rows [0, nr) are bits (nq - 1 - nr, nq - 1]
+            uint32_t keep = (nr >= 32 ? 0xFFFFFFFFu : ((1u << nr) - 1u)) << (nq - nr);
+            if (!act) keep = 0u;
+            if (excl0 && lane == 0) keep &= ~(1u << (nq - 1));
+            pm &= keep;
+            // filter survivors into the queue
+            for (;;) {
+                const uint64_t any = __ballot(pm != 0u);
+                if (!any) break;
+                const bool has = pm != 0u;
+                const int rr = has ? nq - 1 - __builtin_ctz(pm) : 0;
+                pm &= pm - 1u;
+                const uint32_t c = static_cast<uint32_t>(__popcll(any));
+                cnt.cand += c;
+                if (qn + c > static_cast<uint32_t>(kEnumQueue)) {
+                    flush(qn);
+                    qn = 0;
+                }
+                if (has)
+                    queue[qn + lanes_below(any)] =
+                        make_uint2(colc | (static_cast<uint32_t>(rc[rr]) << 14), colh ^ rw[rr]);
+                qn += c;
+            }
         }
     }
     if (qn > 0) flush(qn);
     __syncthreads();
 
-    // stage 4    if (qn > 0) flush(qn);
-    __syncthreads();
-
-    // stage 4: per-sample partial, waves in order
+    // stage 5: per-sample partial, waves in order
     if (threadIdx.x < static_cast<unsigned>(nb)) {
         const int b = threadIdx.x;
         const char *a = accb + kEnumWaves * 16 * b;
-        double *p = sc.part + 2 * (s0 + b);
+        double *pp = sc.part + 2 * (s0 + b);
         if constexpr (P == NQS_FP64) {
             double re = 0.0, im = 0.0;
             for (int w = 0; w < kEnumWaves; ++w) {
                 re += reinterpret_cast<const double *>(a + 16 * w)[0];
                 im += reinterpret_cast<const double *>(a + 16 * w)[1];
             }
-            p[0] = re;
-            p[1] = im;
+            pp[0] = re;
+            pp[1] = im;
         } else {
             AccF32 ar, ai;
             for (int w = 0; w < kEnumWaves; ++w) {
@@ -1174,8 +1383,8 @@ __device__ __forceinline__ void enum_round(const uint32_t *filt, const DevTable 
                 ar.add(f[0], f[1]);
                 ai.add(f[2], f[3]);
             }
-            p[0] = ar.value();
-            p[1] = ai.value();
+            pp[0] = ar.value();
+            pp[1] = ai.value();
         }
     }
     __syncthreads();
@@ -1193,8 +1402,21 @@ __device__ __forceinline__ void enum_flush_counts(const DevScratch &sc, EnumCoun
         if (h) atomicAdd(&sc.counters[2], h);
         if (t) atomicAdd(&sc.counters[3], t);
         if (c.cand) atomicAdd(&sc.counters[4], c.cand);
+        if (c.rounds && threadIdx.x == 0) atomicAdd(&sc.counters[6], c.rounds);
     }
     c = EnumCounts{};
+}
+
+// Hash words and qubit classes of a table into the enumeration's LDS (the
+// caller synchronises before the first round).
+__device__ __forceinline__ void load_enum_tables(const DevTable &tab) {
+    char *smem = dyn_lds();
+    uint32_t *hr = reinterpret_cast<uint32_t *>(smem);
+    uint8_t *qcl = reinterpret_cast<uint8_t *>(smem + 512);
+    for (int k = threadIdx.x; k < 128; k += blockDim.x) {
+        hr[k] = tab.hr[k];
+        qcl[k] = tab.qcls[k];
+    }
 }
 
 __device__ __forceinline__ void load_filter_lds(const DevScratch &sc, uint4 *smem4) {
@@ -1204,7 +1426,7 @@ __device__ __forceinline__ void load_filter_lds(const DevScratch &sc, uint4 *sme
     for (int k = threadIdx.x; k < n4; k += blockDim.x) smem4[k] = gf[k];
 }
 
-// Persistent form: blocks take rounds from counters[5] until none is left.
+// Persistent form: block b runs rounds b, b + grid, b + 2 grid, ...
 template <int W, bool DUMP, int P, bool SCV>
 __global__ __launch_bounds__(kEnumThreads) void eloc_enum_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
@@ -1215,21 +1437,15 @@ __global__ __launch_bounds__(kEnumThreads) void eloc_enum_kernel(
     __shared__ uint4 s_filter[kEnumFilterWords / 4];
     const EnumShape S = enum_shape(tab, sc, samples, n);
     if (S.B <= 0) return;  // the streaming kernel of this launch does the work
-    int *cur = reinterpret_cast<int *>(dyn_lds() + 512 + kEnumWaves * kEnumQueue * 8);
     const int64_t n_rounds = (n + S.B - 1) / S.B;
-    load_filter_lds(sc, s_filter);
+    if (S.parts == 1) load_filter_lds(sc, s_filter);  // else each round loads its partitions
+    load_enum_tables(tab);
+    __syncthreads();
     EnumCounts cnt;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0)
-            *cur = static_cast<int>(atomicAdd(&sc.counters[5], 1ull));
-        __syncthreads();
-        const int64_t r = *cur;
-        if (r >= n_rounds) break;  // every block reaches this once the rounds are taken
-        enum_round<W, DUMP, P, SCV>(reinterpret_cast<const uint32_t *>(s_filter), tab, sc, S,
-                                    samples, log_amp, phase, n, r, hit_idx, sign_bits, sign_words,
-                                    cnt);
-    }
+    // rounds blockIdx.x, blockIdx.x + gridDim.x, ...: no counter, no barrier
+    for (int64_t r = blockIdx.x; r < n_rounds; r += gridDim.x)
+        enum_round<W, DUMP, P, SCV>(reinterpret_cast<uint32_t *>(s_filter), tab, sc, S, samples,
+                                    log_amp, phase, n, r, hit_idx, sign_bits, sign_words, cnt);
     enum_flush_counts(sc, cnt);
 }
 
@@ -1337,6 +1553,8 @@ __global__ void batch_clear_kernel(const JobDesc *__restrict__ jobs) {
             static_cast<Slot2 *>(J.sc.slots)[s].idx = -1;
     }
     if (s < (1u << J.sc.filter_log2)) J.sc.filter[s] = 0u;
+    if (J.sc.eparts_log2 > 0 && s < (1u << (J.sc.eparts_log2 + J.sc.efilter_log2)))
+        J.sc.efilter[s] = 0u;
 }
 
 __global__ void batch_build_kernel(const JobDesc *__restrict__ jobs) {
@@ -1370,11 +1588,16 @@ __global__ __launch_bounds__(kEnumThreads) void batch_enum_kernel(
         const EnumShape S = uniform_shape(enum_shape(J.tab, J.sc, J.samples, J.n));
         const int64_t n_rounds = S.B > 0 ? (J.n + S.B - 1) / S.B : 0;
         if (w.tile >= n_rounds) continue;  // also: the streaming items do this job
-        if (w.job != last_job) load_filter_lds(J.sc, s_filter);
+        if (w.job != last_job) {
+            // (with several partitions each round loads the ones it needs)
+            if (S.parts == 1) load_filter_lds(J.sc, s_filter);
+            load_enum_tables(J.tab);
+            __syncthreads();
+        }
         last_job = w.job;
         EnumCounts cnt;
         for (int64_t r = w.tile; r < n_rounds; r += w.stride)
-            enum_round<W, false, P, SCV>(reinterpret_cast<const uint32_t *>(s_filter), J.tab,
+            enum_round<W, false, P, SCV>(reinterpret_cast<uint32_t *>(s_filter), J.tab,
                                          J.sc, S, J.samples, J.log_amp, J.phase, J.n, r,
                                          nullptr, nullptr, 0, cnt);
         enum_flush_counts(J.sc, cnt);
@@ -1675,6 +1898,19 @@ EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tu
     const int64_t bits_per_sample = (tune && tune->filter_bits) ? tune->filter_bits : 16;
     while (lg < 15 && (int64_t(1) << (lg + 5)) < bits_per_sample * n) ++lg;
     L.filter_log2 = lg;
+    // enumeration filter: up to kEnumMaxParts partitions (sample classes) of
+    // at most 128 KB each, so that every sample keeps its bits per sample
+    int lp = 0;
+    if (L.strategy == kStrategyEnum)
+        while ((1 << lp) < kEnumMaxParts && (int64_t(1) << (lp + 20)) < bits_per_sample * n) ++lp;
+    L.eparts_log2 = lp;
+    if (lp == 0) {
+        L.efilter_log2 = lg;
+    } else {
+        int le = 7;
+        while (le < 15 && (int64_t(1) << (le + 5 + lp)) < bits_per_sample * n) ++le;
+        L.efilter_log2 = le;
+    }
     L.lds_bytes = lookup_lds_bytes(tab.sector32 != 0, lg, L.threads);
     L.g_first = tab.has_diagonal ? 1 : 0;
     const int64_t g_eff = tab.n_groups - L.g_first;
@@ -1702,9 +1938,11 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
                                                 (words == 1 ? offsetof(Slot1, idx)
                                                             : offsetof(Slot2, idx)));
     const uint32_t fwords = 1u << sc.filter_log2;
-    const uint32_t span = capacity > fwords ? capacity : fwords;
+    const uint32_t efwords = sc.eparts_log2 > 0 ? (1u << (sc.eparts_log2 + sc.efilter_log2)) : 0u;
+    uint32_t span = capacity > fwords ? capacity : fwords;
+    span = span > efwords ? span : efwords;
     hipLaunchKernelGGL(hash_clear_kernel, dim3((span + 255) / 256), dim3(256), 0, st, idx0,
-                       stride, capacity, sc.filter, fwords);
+                       stride, capacity, sc.filter, fwords, sc.efilter, efwords);
     const dim3 grid(static_cast<unsigned>((n + 255) / 256));
     if (words == 1)
         hipLaunchKernelGGL(hash_build_kernel<1>, grid, dim3(256), 0, st, tab, sc, samples, weights, n);

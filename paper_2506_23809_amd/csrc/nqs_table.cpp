@@ -273,6 +273,12 @@ void build_enum_index(HostTable *T) {
         T->gh[slot] = static_cast<uint32_t>(g);
     }
     T->k_alpha = T->k_beta = 0;
+    uint64_t seed = 0x6e71735f636c6173ull;  // fixed: the partition of a sample is reproducible
+    for (int q = 0; q < 128; ++q) {
+        const uint8_t v = static_cast<uint8_t>(splitmix64(&seed) >> 61);
+        const int w = q >> 6;
+        T->qcls[q] = (q < T->n_qubits && (T->spin[1][w] >> (q & 63)) & 1ull) ? v : 0;
+    }
     for (int q = 0; q < T->n_qubits; ++q) {
         const int w = q >> 6;
         const uint64_t b = 1ull << (q & 63);

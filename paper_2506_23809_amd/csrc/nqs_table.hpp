@@ -46,6 +46,10 @@ struct HostTable {
     bool enum_ok = false;
     int k_alpha = 0, k_beta = 0;   // qubits per spin
     uint8_t spin_q[128] = {};      // alpha qubits at [0, k_alpha), beta qubits at [64, 64 + k_beta)
+    // class of each qubit (random 3-bit values on beta qubits, 0 on alpha):
+    // the class of a bit string, the XOR over its set qubits, picks the
+    // filter partition of a sample; alpha flips leave it unchanged
+    uint8_t qcls[128] = {};
     // group index by X: open addressing on (h(X) * golden) >> gh_shift,
     // linear probing, 0xFFFFFFFF = empty; keys are compared through gx
     std::vector<uint32_t> gh;

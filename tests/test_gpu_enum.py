@@ -75,6 +75,8 @@ def test_strategies_agree_with_the_oracle(torch_dev, name, n, workload_cache):
         e, st = _eval(torch_dev, ham, w.samples, w.log_amp, w.phase, strategy)
         _parity(e, ref, ab)
         assert st["hits"] == int(nc.sum()) - w.n_samples
+        # the device ran the strategy asked for
+        assert (st["enum_rounds"] > 0) == (strategy == "enum")
         out[strategy] = st
     G, _, conn = W.closed_form_counts(w.K, w.n_alpha)
     assert out["enum"]["probes"] == w.n_samples * conn
@@ -122,6 +124,37 @@ def test_closure_set_dump_and_values(torch_dev, workload_cache):
         ham.close()
 
 
+@pytest.mark.parametrize("filter_bits", [32, 64])
+def test_filter_partitions(torch_dev, filter_bits, workload_cache):
+    """More filter bits than one 128 KB bitmap holds: the samples are split
+    into classes (2 or 4 partitions at 65536 samples), each partition probed
+    by exactly its share of the flips."""
+    w = workload_cache(("workload", "nq40"))
+    ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
+    ham.set_tuning(filter_bits=filter_bits)
+    say(f"{w.name}: enumeration with {filter_bits} filter bits per sample")
+    S = nqs.to_device_samples(w.samples)
+    la = torch_dev.from_numpy(w.log_amp).cuda()
+    ph = torch_dev.from_numpy(w.phase).cuda()
+    e = ham.eloc(S, la, ph)
+    ham.sync()
+    st = ham.stats()
+    r = torch_dev.view_as_real(e).cpu().numpy()
+    e = r[:, 0] + 1j * r[:, 1]
+    ref, ab, nc = oracle.eloc(40, w.x, w.z, w.c, w.samples, w.log_amp, w.phase)
+    _parity(e, ref, ab)
+    _, _, conn = W.closed_form_counts(20, 10)
+    assert st["probes"] == w.n_samples * conn
+    assert st["hits"] == int(nc.sum()) - w.n_samples
+    assert st["enum_rounds"] > 0
+    # more bits per sample: fewer filter survivors than the one-bitmap run
+    ham.set_tuning(filter_bits=16)
+    ham.eloc(S, la, ph)
+    ham.sync()
+    assert st["candidates"] < ham.stats()["candidates"]
+    ham.close()
+
+
 # occupations (n_alpha, n_beta) of a 12-orbital register: empty and full
 # shells (no virtual or no occupied orbital in a spin), one electron or one
 # hole, unequal spins
@@ -154,6 +187,7 @@ def test_occupations(torch_dev, k12, na, nb):
         e, st = _eval(torch_dev, ham, S, la, ph, strategy)
         _parity(e, ref, ab)
         assert st["hits"] == int(nc.sum()) - n
+        assert (st["enum_rounds"] > 0) == (strategy == "enum")
     ham.close()
 
 
@@ -163,9 +197,10 @@ def test_batch_mixing_strategies(torch_dev, precision):
     same tunings, bit for bit."""
     torch = torch_dev
     jobs = []
+    # the 70000-sample job needs two filter partitions
     for j, (nq, n, strategy) in enumerate([(24, 1500, "enum"), (40, 3000, "stream"),
                                            (68, 2000, "enum"), (32, 900, "stream"),
-                                           (72, 1200, "enum")]):
+                                           (72, 1200, "enum"), (24, 70000, "enum")]):
         K = nq // 2
         w = W.molecule([7, 100 + j], K, K // 2, K - K // 2, n, L=4.0, log_sigma=1.5,
                        name=f"mix-{j}")

@@ -288,6 +288,8 @@ def test_mixed_sectors_switch_the_filter_off(torch_dev, workload_cache):
     assert_parity(e, ref, ab)
     G, _, _ = W.closed_form_counts(6, 3)
     assert st["probes"] == S.shape[0] * (G - 1)
+    # two sectors: the enumeration hands the batch to the streaming kernel
+    assert st["enum_rounds"] == 0
 
 
 def test_errors_are_latched_and_reported(torch_dev, nq12):

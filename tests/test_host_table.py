@@ -109,7 +109,7 @@ def test_api_argument_errors_without_device():
     assert lib.nqs_ham_info(None, None, None, None) == nqs.NQS_E_STATE
     assert lib.nqs_energy(0, None, None, None, None) == nqs.NQS_E_ARG
     assert lib.nqs_ham_destroy(None) == nqs.NQS_OK
-    out = (ctypes.c_int64 * 4)()
+    out = (ctypes.c_int64 * 6)()
     assert lib.nqs_eval_stats(None, out) == nqs.NQS_E_STATE
     h = ctypes.c_void_p()
     rc = lib.nqs_ham_create(ctypes.byref(h), 4, 1, np.array([1, 0], np.uint64).ctypes.data,
