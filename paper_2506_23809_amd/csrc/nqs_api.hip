@@ -88,7 +88,7 @@ nqs::DevScratch scratch_of(nqs_ham h) {
     s.slot_mask = cap - 1;
     int lg = 0;
     while ((1u << lg) < cap) ++lg;
-    s.slot_shift = 32 - lg;
+    s.slot_shift = 32 - (lg - nqs::bucket_log2(h->words));
     return s;
 }
 
@@ -105,7 +105,7 @@ void set_filters(nqs::DevScratch *s, nqs_ham h, const nqs::EvalLaunch &L) {
 int ensure_scratch(nqs_ham h, int64_t n, int64_t n_chunks, hipStream_t st,
                    bool efilter = false) {
     uint64_t want = 64;
-    while (want < 2 * static_cast<uint64_t>(n)) want <<= 1;
+    while (want < nqs::kSlotsPerSample * static_cast<uint64_t>(n)) want <<= 1;
     if (want > (1ull << 31)) return fail(NQS_E_ARG, "batch too large for the sample hash");
     const size_t slot_size = h->words == 1 ? sizeof(nqs::Slot1) : sizeof(nqs::Slot2);
     const int64_t part_need = 2 * n * (n_chunks > 0 ? n_chunks : 1);

@@ -118,6 +118,14 @@ struct DevScratch {
 
 constexpr uint32_t kGoldenMul = 0x9E3779B1u;
 
+// The sample hash is probed a bucket at a time: a key starts at the first
+// slot of bucket (h * golden) >> slot_shift and takes the first free slot
+// from there on, so the occupied slots of a bucket form a prefix and one
+// bucket load decides most lookups.  Buckets hold 8 one-word slots or 4
+// two-word slots (128 bytes); the table has at least 4 slots per sample.
+__host__ __device__ constexpr int bucket_log2(int words) { return words == 1 ? 3 : 2; }
+constexpr int kSlotsPerSample = 4;
+
 // Hash slots.  The claim protocol CASes idx from -1 to the sample index and
 // then stores the key; lookups run in a later kernel, so keys are visible.
 struct alignas(16) Slot1 {

@@ -110,26 +110,33 @@ __device__ __forceinline__ bool key_eq(const typename SlotT<W>::type &s, const K
 // 32-byte load holding both the key and its index.
 template <int W>
 __device__ __forceinline__ int32_t hash_find(const typename SlotT<W>::type *__restrict__ slots,
-                                             uint32_t mask, uint32_t slot, const Key<W> &k) {
-    for (uint32_t probe = 0; probe <= mask; ++probe) {
-        // the whole slot in one load: index and key together
-        const uint4 *p = reinterpret_cast<const uint4 *>(&slots[slot]);
-        const uint4 a = p[0];
-        const uint64_t k0 = (static_cast<uint64_t>(a.y) << 32) | a.x;
-        int32_t idx;
-        bool eq;
-        if constexpr (W == 1) {
-            idx = static_cast<int32_t>(a.z);
-            eq = k0 == k.w[0];
-        } else {
-            const uint4 b = p[1];
-            const uint64_t k1 = (static_cast<uint64_t>(a.w) << 32) | a.z;
-            idx = static_cast<int32_t>(b.x);
-            eq = k0 == k.w[0] && k1 == k.w[1];
+                                             uint32_t mask, uint32_t start, const Key<W> &k) {
+    constexpr int BK = 1 << bucket_log2(W);
+    for (uint32_t probe = 0; probe <= mask; probe += BK) {
+        // the whole bucket in independent loads: one memory latency per bucket
+        const uint4 *p = reinterpret_cast<const uint4 *>(&slots[start]);
+        int32_t found = -1;
+        bool empty = false;
+#pragma unroll
+        for (int s = 0; s < BK; ++s) {
+            int32_t idx;
+            bool eq;
+            if constexpr (W == 1) {
+                const uint4 a = p[s];
+                idx = static_cast<int32_t>(a.z);
+                eq = ((static_cast<uint64_t>(a.y) << 32) | a.x) == k.w[0];
+            } else {
+                const uint4 a = p[2 * s], b = p[2 * s + 1];
+                idx = static_cast<int32_t>(b.x);
+                eq = ((static_cast<uint64_t>(a.y) << 32) | a.x) == k.w[0] &&
+                     ((static_cast<uint64_t>(a.w) << 32) | a.z) == k.w[1];
+            }
+            if (idx >= 0 && eq) found = idx;
+            empty = empty || idx < 0;
         }
-        if (idx < 0) return -1;
-        if (eq) return idx;
-        slot = (slot + 1) & mask;
+        if (found >= 0) return found;
+        if (empty) return -1;
+        start = (start + BK) & mask;
     }
     return -1;
 }
@@ -226,7 +233,7 @@ __device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScr
         atomicOr(&sc.efilter[(c << sc.efilter_log2) + ((h >> 5) & emask)], fbits);
     }
     S *slots = static_cast<S *>(sc.slots);
-    uint32_t slot = slot_of(h, sc.slot_shift);
+    uint32_t slot = slot_of(h, sc.slot_shift) << bucket_log2(W);
     for (uint32_t probe = 0; probe <= sc.slot_mask; ++probe) {
         const int32_t old = atomicCAS(&slots[slot].idx, -1, static_cast<int32_t>(i));
         if (old == -1) {
@@ -574,7 +581,8 @@ __device__ __forceinline__ void lookup_item(
 #pragma unroll
             for (int q = 0; q < W; ++q) xp.w[q] = xl.w[q] ^ tab.gx[2 * g + q];
             const uint32_t h = hxl ^ tab.ghm[2 * g];
-            const int32_t j = hash_find<W>(slots, sc.slot_mask, slot_of(h, sc.slot_shift), xp);
+            const int32_t j = hash_find<W>(slots, sc.slot_mask,
+                                           slot_of(h, sc.slot_shift) << bucket_log2(W), xp);
             if constexpr (DUMP) {
                 if (hit_idx) hit_idx[(wave0 + l) * tab.n_groups + g] = j;
             }
@@ -861,13 +869,23 @@ __device__ __forceinline__ EnumShape uniform_shape(EnumShape s) {
     return s;
 }
 
-// k-th pair (i < j) in the order (0,1), (0,2), (1,2), (0,3), ...
+// k-th pair (i < j) in the order (0,1), (0,2), (1,2), (0,3), ... for
+// orbital lists of up to 64 entries, as a constant table (i | j << 8).
+constexpr int kPairTab = 64 * 63 / 2;
+struct PairTable {
+    uint16_t v[kPairTab];
+    constexpr PairTable() : v() {
+        int k = 0;
+        for (int j = 1; j < 64; ++j)
+            for (int i = 0; i < j; ++i) v[k++] = static_cast<uint16_t>(i | (j << 8));
+    }
+};
+__constant__ PairTable kPairs{};
+
 __device__ __forceinline__ void pair_of(int k, int &i, int &j) {
-    int jj = static_cast<int>((1.0f + sqrtf(1.0f + 8.0f * static_cast<float>(k))) * 0.5f);
-    while (jj * (jj - 1) / 2 > k) --jj;
-    while ((jj + 1) * jj / 2 <= k) ++jj;
-    j = jj;
-    i = k - jj * (jj - 1) / 2;
+    const uint32_t e = kPairs.v[k];
+    i = static_cast<int>(e & 0xFFu);
+    j = static_cast<int>(e >> 8);
 }
 
 // Index of the group with flip mask X, or -1 (the group index is keyed by
@@ -927,7 +945,7 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
                                            const double *__restrict__ phase, int64_t n,
                                            int64_t round, int32_t *__restrict__ hit_idx,
                                            uint32_t *__restrict__ sign_bits, int64_t sign_words,
-                                           EnumCounts &cnt) {
+                                           EnumCounts &cnt, int &loaded_part) {
     using Sl = typename SlotT<W>::type;
     char *smem = dyn_lds();
     const int lane = threadIdx.x & 63;
@@ -1140,7 +1158,8 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             Key<W> xp;
 #pragma unroll
             for (int q = 0; q < W; ++q) xp.w[q] = x.w[q] ^ X.w[q];
-            const int32_t j = hash_find<W>(slots, sc.slot_mask, slot_of(e.y, sc.slot_shift), xp);
+            const int32_t j = hash_find<W>(slots, sc.slot_mask,
+                                           slot_of(e.y, sc.slot_shift) << bucket_log2(W), xp);
             if (j >= 0) {
                 int64_t g = -1;
                 if (!SCV || DUMP) g = group_find<W>(tab, e.y ^ rec.hx, X);
@@ -1214,16 +1233,30 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
     const int cha = ceil_div(S.ca, 64);
     const int nseg_ba = ceil_div(S.rba, kEnumRowSeg);
     const int uba = (S.rba && S.cba) ? ceil_div(S.cba, 64) * nseg_ba : 0;
-    for (int p = 0; p < parts; ++p) {
-        if (parts > 1) {
+    for (int pi = 0; pi < parts; ++pi) {
+        // odd rounds walk the partitions backwards: a round starts with the
+        // partition the previous one ended with
+        const int p = (round & 1) ? parts - 1 - pi : pi;
+        if (parts > 1 && p != loaded_part) {
             // partition p of the filter: samples of class p
             __syncthreads();
             const uint4 *gf = reinterpret_cast<const uint4 *>(
                 sc.efilter + (static_cast<size_t>(p) << sc.efilter_log2));
             uint4 *f4 = reinterpret_cast<uint4 *>(filt);
-            for (int k = threadIdx.x; k < ((1 << sc.efilter_log2) >> 2); k += blockDim.x)
-                f4[k] = gf[k];
+            const int n4 = (1 << sc.efilter_log2) >> 2;
+            // four 16-byte loads in flight per thread
+            int k = static_cast<int>(threadIdx.x);
+            for (; k + 3 * kEnumThreads < n4; k += 4 * kEnumThreads) {
+                const uint4 a0 = gf[k], a1 = gf[k + kEnumThreads];
+                const uint4 a2 = gf[k + 2 * kEnumThreads], a3 = gf[k + 3 * kEnumThreads];
+                f4[k] = a0;
+                f4[k + kEnumThreads] = a1;
+                f4[k + 2 * kEnumThreads] = a2;
+                f4[k + 3 * kEnumThreads] = a3;
+            }
+            for (; k < n4; k += kEnumThreads) f4[k] = gf[k];
             __syncthreads();
+            loaded_part = p;
         }
         int U = 0;
         for (int b = 0; b < nb; ++b) U += meta[b].units[p];
@@ -1244,9 +1277,10 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             int prod, ch, seg, ncol, col0 = 0, row0, nrow;
             const int nra = m.offa[t + 1] - m.offa[t];
             const int ua = cha * ceil_div(nra, kEnumRowSeg);
+            int ns;
             if (l < ua) {
                 prod = 0;
-                const int ns = ceil_div(nra, kEnumRowSeg);
+                ns = ceil_div(nra, kEnumRowSeg);
                 ch = l / ns;
                 seg = l - ch * ns;
                 ncol = S.ca;
@@ -1255,6 +1289,7 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             } else if (t == 0 && l < ua + uba) {
                 prod = 1;
                 l -= ua;
+                ns = nseg_ba;
                 ch = l / nseg_ba;
                 seg = l - ch * nseg_ba;
                 ncol = S.cba;
@@ -1263,7 +1298,8 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             } else {
                 prod = 2;
                 l -= ua + (t == 0 ? uba : 0);
-                int v = 0, uv = 0, ns = 1;
+                int v = 0, uv = 0;
+                ns = 1;
                 for (; v < parts; ++v) {
                     const int nc = m.offc[v + 1] - m.offc[v];
                     nrow = m.offb[(t ^ v) + 1] - m.offb[t ^ v];
@@ -1312,8 +1348,10 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             const uint64_t colmask = __ballot(act);
             // (none, none) is x itself: never a probe
             const bool excl0 = prod == 0 && t == 0 && ch == 0 && seg == 0;
-            const int r0 = seg * kEnumRowSeg;
-            const int nr = min(nrow - r0, kEnumRowSeg);
+            // ns segments of equal length (a multiple of 4, at most 32)
+            const int sl = (ceil_div(nrow, ns) + 3) & ~3;
+            const int r0 = seg * sl;
+            const int nr = min(nrow - r0, sl);
             const uint32_t *rw = lh + b * L + row0 + r0;
             const uint16_t *rc = lc + b * L + row0 + r0;
             cnt.probes += static_cast<unsigned long long>(__popcll(colmask)) * nr -
@@ -1442,10 +1480,12 @@ __global__ __launch_bounds__(kEnumThreads) void eloc_enum_kernel(
     load_enum_tables(tab);
     __syncthreads();
     EnumCounts cnt;
+    int loaded_part = -1;
     // rounds blockIdx.x, blockIdx.x + gridDim.x, ...: no counter, no barrier
     for (int64_t r = blockIdx.x; r < n_rounds; r += gridDim.x)
         enum_round<W, DUMP, P, SCV>(reinterpret_cast<uint32_t *>(s_filter), tab, sc, S, samples,
-                                    log_amp, phase, n, r, hit_idx, sign_bits, sign_words, cnt);
+                                    log_amp, phase, n, r, hit_idx, sign_bits, sign_words, cnt,
+                                    loaded_part);
     enum_flush_counts(sc, cnt);
 }
 
@@ -1577,6 +1617,7 @@ __global__ __launch_bounds__(kEnumThreads) void batch_enum_kernel(
     __shared__ uint4 s_filter[kEnumFilterWords / 4];
     __shared__ int cur;
     int last_job = -1;
+    int loaded_part = -1;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) cur = static_cast<int>(atomicAdd(next, 1u));
@@ -1592,6 +1633,7 @@ __global__ __launch_bounds__(kEnumThreads) void batch_enum_kernel(
             // (with several partitions each round loads the ones it needs)
             if (S.parts == 1) load_filter_lds(J.sc, s_filter);
             load_enum_tables(J.tab);
+            loaded_part = -1;
             __syncthreads();
         }
         last_job = w.job;
@@ -1599,7 +1641,7 @@ __global__ __launch_bounds__(kEnumThreads) void batch_enum_kernel(
         for (int64_t r = w.tile; r < n_rounds; r += w.stride)
             enum_round<W, false, P, SCV>(reinterpret_cast<uint32_t *>(s_filter), J.tab,
                                          J.sc, S, J.samples, J.log_amp, J.phase, J.n, r,
-                                         nullptr, nullptr, 0, cnt);
+                                         nullptr, nullptr, 0, cnt, loaded_part);
         enum_flush_counts(J.sc, cnt);
     }
 }
