@@ -1519,7 +1519,8 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
                                            double *__restrict__ eloc,
                                            int32_t *__restrict__ hit_idx,
                                            uint32_t *__restrict__ sign_bits, int64_t sign_words,
-                                           int64_t i) {
+                                           int64_t i, const uint64_t *dz = nullptr,
+                                           const double *dc = nullptr, int nd = 0) {
     unsigned long long n_terms = 0;
     // an enumeration leaves one partial per sample
     if (enum_on && enum_shape(tab, sc, samples, n).B > 0) n_chunks = 1;
@@ -1529,6 +1530,28 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
         if (tab.has_diagonal) {
             if constexpr (SCV) {
                 re = sc_diagonal<W>(tab, x);
+            } else if (dz) {
+                // the X = 0 group staged in LDS by the caller (same order, same sums)
+                if constexpr (P == NQS_FP64) {
+                    double acc = 0.0;
+                    for (int t = 0; t < nd; ++t) {
+                        int par = __popcll(dz[2 * t] & x.w[0]);
+                        if constexpr (W == 2) par += __popcll(dz[2 * t + 1] & x.w[1]);
+                        acc += (par & 1) ? -dc[t] : dc[t];
+                    }
+                    re = acc;
+                } else {
+                    AccF32 a;
+                    const float2 *dc32 = reinterpret_cast<const float2 *>(dc);
+                    for (int t = 0; t < nd; ++t) {
+                        int par = __popcll(dz[2 * t] & x.w[0]);
+                        if constexpr (W == 2) par += __popcll(dz[2 * t + 1] & x.w[1]);
+                        const float2 cc = dc32[t];
+                        a.add(flip_sign(cc.x, par), flip_sign(cc.y, par));
+                    }
+                    re = a.value();
+                }
+                n_terms += static_cast<unsigned long long>(nd);
             } else if constexpr (P == NQS_FP64) {
                 uint32_t *row = (DUMP && sign_bits) ? sign_bits + i * sign_words : nullptr;
                 re = group_sum<W, DUMP>(tab, 0, x, row, &n_terms);
@@ -1552,12 +1575,50 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
     if ((threadIdx.x & 63) == 0 && n_terms) atomicAdd(&sc.counters[3], n_terms);
 }
 
+// Diagonal terms staged in LDS by the finish kernels (up to this many; a
+// larger X = 0 group is read from device memory).
+constexpr int kDiagLds = 1024;
+
+// Copy the X = 0 group's Z masks and coefficients (FP64, or the FP32 hi/lo
+// pair in the same 8 bytes) into LDS; returns the term count, or -1 when the
+// group does not fit.  Synchronises the block.
+template <int P>
+__device__ __forceinline__ int stage_diagonal(const DevTable &tab, uint64_t *dz, double *dc) {
+    if (!tab.has_diagonal) return -1;
+    const int t0 = static_cast<int>(tab.goff[0]);
+    const int nd = static_cast<int>(tab.goff[1]) - t0;
+    if (nd > kDiagLds) return -1;
+    for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+        dz[2 * k] = tab.tz[2 * static_cast<size_t>(t0 + k)];
+        dz[2 * k + 1] = tab.tz[2 * static_cast<size_t>(t0 + k) + 1];
+        if constexpr (P == NQS_FP64) {
+            dc[k] = tab.tc[t0 + k];
+        } else {
+            const float2 cc = make_float2(tab.tc32[2 * static_cast<size_t>(t0 + k)],
+                                          tab.tc32[2 * static_cast<size_t>(t0 + k) + 1]);
+            dc[k] = *reinterpret_cast<const double *>(&cc);
+        }
+    }
+    __syncthreads();
+    return nd;
+}
+
 template <int W, bool DUMP, int P, bool SCV>
 __global__ __launch_bounds__(256) void eloc_finish_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n,
     int64_t n_chunks, int enum_on, double *__restrict__ eloc, int32_t *__restrict__ hit_idx,
     uint32_t *__restrict__ sign_bits, int64_t sign_words) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if constexpr (!DUMP && !SCV) {
+        __shared__ uint64_t dz[2 * kDiagLds];
+        __shared__ double dc[kDiagLds];
+        const int nd = stage_diagonal<P>(tab, dz, dc);
+        if (nd >= 0) {
+            finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc,
+                                        hit_idx, sign_bits, sign_words, i, dz, dc, nd);
+            return;
+        }
+    }
     finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc, hit_idx,
                                 sign_bits, sign_words, i);
 }
@@ -1697,21 +1758,25 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(const JobDesc *__rest
     const int64_t chunks = J.chunk_len > 0 ? J.n_chunks : 0;
     const bool integrals = (J.kind & kJobIntegrals) != 0;
     const bool en = J.strategy == kStrategyEnum;
-    if ((J.kind & 1) == 0) {
-        if (integrals)
+    if (integrals) {
+        if ((J.kind & 1) == 0)
             finish_one<1, false, NQS_FP64, true>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc,
                                                  nullptr, nullptr, 0, i);
         else
-            finish_one<1, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc, nullptr,
-                                           nullptr, 0, i);
-    } else {
-        if (integrals)
             finish_one<2, false, NQS_FP64, true>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc,
                                                  nullptr, nullptr, 0, i);
-        else
-            finish_one<2, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc, nullptr,
-                                           nullptr, 0, i);
+        return;
     }
+    __shared__ uint64_t dz[2 * kDiagLds];
+    __shared__ double dc[kDiagLds];
+    const int nd = stage_diagonal<P>(J.tab, dz, dc);
+    const uint64_t *z = nd >= 0 ? dz : nullptr;
+    if ((J.kind & 1) == 0)
+        finish_one<1, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc, nullptr,
+                                       nullptr, 0, i, z, dc, nd);
+    else
+        finish_one<2, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc, nullptr,
+                                       nullptr, 0, i, z, dc, nd);
 }
 
 size_t batch_lds_bytes(int threads, int max_filter_log2) {
