@@ -104,14 +104,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="nq40", choices=["nq12", "nq40", "nq100"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32k"])
+    ap.add_argument("--filter-bits", type=int, default=0,
+                    help="on-chip filter bits per sample (0: the library's default)")
     ap.add_argument("--strategy", default="auto", choices=["auto", "stream", "enum"],
                     help="lookup strategy: group streaming or flip enumeration (auto: "
                          "enumeration where the table allows it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "serve"],
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "serve", "copy"],
                     help="single: the headline step; batched: 32 Hamiltonians in one "
-                         "persistent graph-captured launch; serve: continuous batching loop")
+                         "persistent graph-captured launch; serve: continuous batching loop; "
+                         "copy: a plain 1 GiB device copy, the calibration of the HBM byte "
+                         "counters")
     ap.add_argument("--jobs", type=int, default=32, help="Hamiltonians in the batched family")
     ap.add_argument("--requests", type=int, default=400, help="serve: requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: aggregate arrivals per second")
@@ -121,9 +125,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}, "
-              f"WORLD_SIZE {world}); multi-GPU sharding is described in DESIGN.md, not run.",
-              file=sys.stderr, flush=True)
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              f"the sharded path is not run.", file=sys.stderr, flush=True)
         sys.exit(2)
 
     import numpy as np
@@ -141,6 +144,8 @@ def main():
     if args.mode == "serve":
         import serve_bench
         return serve_bench.run(args, log)
+    if args.mode == "copy":
+        return run_copy(args, log)
 
     t0 = time.perf_counter()
     w = workloads.workload(args.workload)
@@ -155,8 +160,8 @@ def main():
     ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t0) * 1e3
-    if args.strategy != "auto":
-        ham.set_tuning(strategy=args.strategy)
+    if args.strategy != "auto" or args.filter_bits:
+        ham.set_tuning(filter_bits=args.filter_bits, strategy=args.strategy)
     G, T, table_bytes = ham.info()
     words = 1 if w.n_qubits <= 63 else 2
     log(f"table: {G} groups, {T} terms, {table_bytes / 1e6:.1f} MB, setup {setup_ms:.1f} ms")
@@ -292,6 +297,31 @@ def _family(n_jobs, log):
     log(f"family of {n_jobs}: qubits {[w.n_qubits for w in fam]}, samples "
         f"{[w.n_samples for w in fam]} ({time.perf_counter() - t0:.1f} s to generate)")
     return fam
+
+
+def run_copy(args, log):
+    """A plain device copy of known size (1 GiB read, 1 GiB written per step):
+    rocprofv3's FETCH_SIZE and WRITE_SIZE of this copy give the factor that
+    turns the counters of the E_loc kernels into bytes."""
+    import torch
+
+    n_bytes = 1 << 30
+    src = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    print(json.dumps({"metric": "device copy GB/s", "value": 2 * n_bytes / (ms / 1e3) / 1e9,
+                      "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "copy of 1 GiB (read 1 GiB, write 1 GiB)",
+                                 "bytes_read": n_bytes, "bytes_written": n_bytes}}), flush=True)
 
 
 def run_batched(args, log):

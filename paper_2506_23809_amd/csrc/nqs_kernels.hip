@@ -794,7 +794,7 @@ __device__ __forceinline__ char *dyn_lds() {
 
 constexpr uint32_t kNoQubit = 0x7Fu;
 constexpr uint32_t kNoPair = kNoQubit | (kNoQubit << 7);
-constexpr int kEnumRowSeg = 32;  // rows per work unit
+constexpr int kEnumRowSeg = 64;  // rows per work unit (two 32-row lane masks)
 
 struct alignas(16) EnumSample {
     uint64_t x0, x1;
@@ -1348,7 +1348,7 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             const uint64_t colmask = __ballot(act);
             // (none, none) is x itself: never a probe
             const bool excl0 = prod == 0 && t == 0 && ch == 0 && seg == 0;
-            // ns segments of equal length (a multiple of 4, at most 32)
+            // ns segments of equal length (a multiple of 4, at most 64)
             const int sl = (ceil_div(nrow, ns) + 3) & ~3;
             const int r0 = seg * sl;
             const int nr = min(nrow - r0, sl);
@@ -1356,12 +1356,14 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             const uint16_t *rc = lc + b * L + row0 + r0;
             cnt.probes += static_cast<unsigned long long>(__popcll(colmask)) * nr -
                           (excl0 ? 1ull : 0ull);
-            // probes: the filter bit of row r lands in bit nq - 1 - r of pm,
-            // nq = nr rounded up to whole groups of 4 (rows past nr are read
+            // probes: the filter bit of row r < 32 lands in bit nq0 - 1 - r of
+            // pm0, of row 32 + r in bit nq1 - 1 - r of pm1 (nq: the half's row
+            // count rounded up to whole groups of 4; rows past nr are read
             // from the next list or the padding and masked off below)
-            uint32_t pm = 0;
-            const int nq = (nr + 3) & ~3;
-            for (int r = 0; r < nr; r += 4) {
+            const int n0 = min(nr, 32), n1 = nr - n0;
+            const int nq0 = (n0 + 3) & ~3, nq1 = (n1 + 3) & ~3;
+            uint32_t pm0 = 0, pm1 = 0;
+            for (int r = 0; r < n0; r += 4) {
                 uint32_t h[4], fw[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) h[v] = colh ^ rw[r + v];
@@ -1371,20 +1373,33 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
                     fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + ((h[v] >> 3) & fbytes_mask));
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    pm = (pm << 1) | ((fw[v] >> (h[v] & 31)) & (fw[v] >> (h[v] >> 27)) & 1u);
+                    pm0 = (pm0 << 1) | ((fw[v] >> (h[v] & 31)) & (fw[v] >> (h[v] >> 27)) & 1u);
             }
-            // rows [0, nr) are bits (nq - 1 - nr, nq - 1]
-            uint32_t keep = (nr >= 32 ? 0xFFFFFFFFu : ((1u << nr) - 1u)) << (nq - nr);
-            if (!act) keep = 0u;
-            if (excl0 && lane == 0) keep &= ~(1u << (nq - 1));
-            pm &= keep;
+            for (int r = 32; r < nr; r += 4) {
+                uint32_t h[4], fw[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) h[v] = colh ^ rw[r + v];
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + ((h[v] >> 3) & fbytes_mask));
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    pm1 = (pm1 << 1) | ((fw[v] >> (h[v] & 31)) & (fw[v] >> (h[v] >> 27)) & 1u);
+            }
+            // rows [0, n0) are bits (nq0 - 1 - n0, nq0 - 1] of pm0, likewise pm1
+            uint32_t keep0 = (n0 >= 32 ? 0xFFFFFFFFu : ((1u << n0) - 1u)) << (nq0 - n0);
+            uint32_t keep1 = n1 > 0 ? ((n1 >= 32 ? 0xFFFFFFFFu : ((1u << n1) - 1u)) << (nq1 - n1)) : 0u;
+            if (!act) keep0 = keep1 = 0u;
+            if (excl0 && lane == 0) keep0 &= ~(1u << (nq0 - 1));
+            uint64_t pm = (static_cast<uint64_t>(pm1 & keep1) << 32) | (pm0 & keep0);
             // filter survivors into the queue
             for (;;) {
-                const uint64_t any = __ballot(pm != 0u);
+                const uint64_t any = __ballot(pm != 0ull);
                 if (!any) break;
-                const bool has = pm != 0u;
-                const int rr = has ? nq - 1 - __builtin_ctz(pm) : 0;
-                pm &= pm - 1u;
+                const bool has = pm != 0ull;
+                const int bit = has ? __builtin_ctzll(pm) : 0;
+                const int rr = bit < 32 ? nq0 - 1 - bit : 32 + nq1 - 1 - (bit - 32);
+                pm &= pm - 1ull;
                 const uint32_t c = static_cast<uint32_t>(__popcll(any));
                 cnt.cand += c;
                 if (qn + c > static_cast<uint32_t>(kEnumQueue)) {
@@ -2000,9 +2015,13 @@ EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tu
     L.strategy = (tab.enum_ok && want != kStrategyStream) ? kStrategyEnum : kStrategyStream;
     L.enum_blocks = static_cast<unsigned>(device_cus());
     L.threads = (tune && tune->threads) ? tune->threads : kLookupThreads;
-    // Bloom bitmap: about 16 bits per sample unless tuned, 512 B .. 128 KB
+    // Bloom bitmap: about 16 bits per sample unless tuned, 512 B .. 128 KB;
+    // an enumeration whose batch outgrows one bitmap takes 32 bits per
+    // sample in its class partitions
     int lg = 7;
-    const int64_t bits_per_sample = (tune && tune->filter_bits) ? tune->filter_bits : 16;
+    int64_t bits_per_sample = (tune && tune->filter_bits) ? tune->filter_bits : 16;
+    if (!(tune && tune->filter_bits) && L.strategy == kStrategyEnum && 16 * n > (int64_t(1) << 20))
+        bits_per_sample = 32;
     while (lg < 15 && (int64_t(1) << (lg + 5)) < bits_per_sample * n) ++lg;
     L.filter_log2 = lg;
     // enumeration filter: up to kEnumMaxParts partitions (sample classes) of

@@ -367,7 +367,7 @@ def test_edge_sizes_determinism_and_permutation(torch_dev, nq12):
 
 # ---------------------------------------------------------------- FP32 + compensation form
 
-FP32_TOL = 1e-6      # per sample, relative to A(x); see the design doc (FP32 error budget)
+FP32_TOL = 1e-6      # per sample, relative to A(x): a few FP32 roundings of each term and ratio
 ENERGY_TOL_HA = 1e-6  # absolute, on Re <E>
 
 
