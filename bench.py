@@ -66,8 +66,11 @@ def algorithmic_ops_per_pair(n_qubits, spin_bits):
     return 2 * (2 * words) + 2 + 1
 
 
-def cpu_baseline(w, threads, budget_s=20.0):
-    """The oracle as it stands, on the host cores, on a bounded sample."""
+def cpu_baseline(w, threads, e_loc_gpu=None, energies=None, budget_s=20.0):
+    """The oracle as it stands, on the host cores, on a bounded sample.  When
+    the whole batch fits in the budget, the oracle's local energies and Eq. 1
+    energy are also set beside the GPU's (e_loc_gpu: FP64 E_loc; energies:
+    (FP64, FP32-compensated) mean energies)."""
     import numpy as np
     import oracle
     n = w.n_samples
@@ -78,12 +81,21 @@ def cpu_baseline(w, threads, budget_s=20.0):
                      threads=threads)
     t_probe = time.perf_counter() - t0
     per_row = t_probe / len(rows)
+    check = None
     if per_row * n <= budget_s:
         t0 = time.perf_counter()
-        oracle.eloc(w.n_qubits, w.x, w.z, w.c, w.samples, w.log_amp, w.phase, threads=threads)
+        ref, ab, _ = oracle.eloc(w.n_qubits, w.x, w.z, w.c, w.samples, w.log_amp, w.phase,
+                                 threads=threads)
         dt = time.perf_counter() - t0
         done = n
         sample = f"all {n} samples (full S x S double loop)"
+        m_ref, _, _ = oracle.energy(w.weights, ref)
+        check = {"energy_re_oracle": m_ref.real}
+        if e_loc_gpu is not None:
+            check["max_err_eloc_fp64_rel_to_abs_sum"] = float(np.max(np.abs(e_loc_gpu - ref) / ab))
+        if energies is not None:
+            check["abs_err_re_energy_fp64_Ha"] = abs(energies[0].real - m_ref.real)
+            check["abs_err_re_energy_fp32k_Ha"] = abs(energies[1].real - m_ref.real)
     else:
         m = max(256, int(budget_s / per_row))
         sel = np.random.default_rng(0).choice(n, size=m, replace=False).astype(np.int64)
@@ -93,8 +105,11 @@ def cpu_baseline(w, threads, budget_s=20.0):
         dt = time.perf_counter() - t0
         done = m
         sample = f"{m} of {n} sample rows, each against all {n} samples"
-    return {"value": done * G / dt, "unit": "pair-evals/s", "cores": threads,
-            "kind": "oracle", "sample": sample, "seconds": round(dt, 3)}
+    res = {"value": done * G / dt, "unit": "pair-evals/s", "cores": threads,
+           "kind": "oracle", "sample": sample, "seconds": round(dt, 3)}
+    if check is not None:
+        res["check"] = check
+    return res
 
 
 def main():
@@ -172,28 +187,43 @@ def main():
     wt = torch.from_numpy(w.weights).to(dev)
     out = torch.empty((w.n_samples, 2), dtype=torch.float64, device=dev)
 
-    def step():
-        ham.eloc_into(out, S, la, ph, wt, precision=args.precision)
-        return nqs.energy(wt, out)
+    def timed(precision):
+        """Warm-up, then EXACTLY args.steps timed steps of one precision."""
+        def step():
+            ham.eloc_into(out, S, la, ph, wt, precision=precision)
+            return nqs.energy(wt, out)
 
-    for k in range(args.warmup):
-        step()
-        log(f"warmup {k + 1}/{args.warmup}")
-    ham.sync()
-    st = ham.stats()
-    ham.profile(True)
-    kms = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        mean, var, sw = step()          # nqs_energy synchronises the stream
-        kms.append(ham.last_kernel_ms())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ham.profile(False)
-    ham.sync()
-    ms_per_step = elapsed * 1e3 / args.steps
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, E = {mean.real:.10f}, var = {var:.4e}")
+        for k in range(args.warmup):
+            step()
+            log(f"{precision} warmup {k + 1}/{args.warmup}")
+        ham.sync()
+        st = ham.stats()
+        ham.profile(True)
+        kms = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            mean, var, sw = step()          # nqs_energy synchronises the stream
+            kms.append(ham.last_kernel_ms())
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        ham.profile(False)
+        ham.sync()
+        ms = elapsed * 1e3 / args.steps
+        log(f"{precision}: timed {args.steps} steps: {ms:.3f} ms/step, E = {mean.real:.10f}, "
+            f"var = {var:.4e}")
+        return ms, np.array(kms), mean, var, sw, st
+
+    other = "fp32k" if args.precision == "fp64" else "fp64"
+    ms_per_step, kms, mean, var, sw, st = timed(args.precision)
+    o_ms, o_kms, o_mean, o_var, _, _ = timed(other)
+    e_fp64 = mean if args.precision == "fp64" else o_mean
+    e_fp32k = o_mean if args.precision == "fp64" else mean
+    e_loc_fp64 = None
+    if args.precision == "fp64":
+        ham.eloc_into(out, S, la, ph, wt, precision="fp64")
+        ham.sync()
+        e_loc_fp64 = torch.view_as_complex(out).cpu().numpy()
 
     kms = np.array(kms)
     hash_ms, lookup_ms, finish_ms = (float(v) for v in kms.mean(axis=0))
@@ -259,6 +289,7 @@ def main():
             "unit": "Tops/s (int32 VALU lane-ops)",
             "frac": achieved_ops / VALU_PEAK_OPS,
             "traffic": traffic,
+            "traffic_GBps": (traffic / (lookup_ms / 1e3) / 1e9) if traffic else None,
             "algorithmic_ops_per_unit": ops_unit,
             "unit_of_work": unit_name,
             "units_per_launch": units,
@@ -278,11 +309,19 @@ def main():
         "probes_per_s": st["probes"] / (ms_per_step / 1e3),
         "setup_ms": setup_ms,
         "energy": {"re": mean.real, "im": mean.imag, "var": var, "sum_w": sw},
+        "compare": {
+            "precision": other,
+            "value": pairs / (o_ms / 1e3),
+            "ms_per_step": o_ms,
+            "kernel_ms": float(o_kms.mean(axis=0)[1]),
+            "energy_re": o_mean.real,
+            "abs_err_re_energy_fp32k_vs_fp64_Ha": abs(e_fp32k.real - e_fp64.real),
+        },
     }
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         log(f"cpu baseline: oracle on {threads} threads")
-        res["cpu_baseline"] = cpu_baseline(w, threads)
+        res["cpu_baseline"] = cpu_baseline(w, threads, e_loc_fp64, (e_fp64, e_fp32k))
         log(f"cpu baseline: {res['cpu_baseline']}")
     else:
         res["cpu_baseline"] = None
