@@ -90,6 +90,17 @@ __host__ __device__ inline int enum_round_size(int ka, int kb, int na, int nb) {
     return b < kEnumMaxB ? b : kEnumMaxB;
 }
 
+// Solo rounds, for occupations whose lists are small (at most 32 qubits per
+// spin and one filter partition): each wave evaluates its own samples, one at
+// a time, with no block barrier after the filter load.  Per wave it keeps its
+// sample's orbital lists (4 x 32 bytes) and the rows of A, Ba and Bb (hash
+// u32, then flip code u16; columns are computed in registers); the queue is
+// the wave's usual one.
+constexpr int kEnumSoloLists = 128;
+__host__ __device__ inline int enum_solo_bytes(int row_entries) {
+    return (kEnumSoloLists + 6 * row_entries + 15) & ~15;
+}
+
 // Sector key of a group: (half popcount of its alpha flips) | (half popcount
 // of its beta flips) << 8.  A flip x -> x ^ X keeps (N_alpha, N_beta) iff
 // popc(x & X_alpha) | popc(x & X_beta) << 8 equals the key.  Flips with an
@@ -221,7 +232,8 @@ struct WorkItem {
 };
 
 constexpr int kEnumVariants = 4;
-constexpr int kBatchCounters = kEnumVariants + 1;
+constexpr int kStreamCounter = 2 * kEnumVariants;  // after block- and solo-round counters
+constexpr int kBatchCounters = kStreamCounter + 1;
 
 struct BatchShape {
     int threads;          // lookup block size, shared by all jobs
@@ -235,8 +247,8 @@ struct BatchShape {
     int enum_begin[5];
 };
 
-// d_next: kBatchCounters counters (one per enumeration variant, then the
-// streaming items).
+// d_next: kBatchCounters counters (block and solo rounds of each
+// enumeration variant, then the streaming items).
 hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_items, int n_items,
                         unsigned *d_next, const BatchShape &shape, int precision, hipStream_t st);
 size_t batch_lds_bytes(int threads, int max_filter_log2);

@@ -167,6 +167,20 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
 }
 
+// Blocked Bloom filter of the sample hashes: a key with hash h sets two bits
+// of one 32-bit word, word (h >> 2) & (words - 1) and bits (h >> 17) & 31 and
+// h >> 27 (disjoint ranges of h for filters of up to 2^15 words).  The byte
+// offset of the word is then h & ((words - 1) << 2), one AND per probe.
+__device__ __forceinline__ uint32_t filter_word(uint32_t h, uint32_t wmask) {
+    return (h >> 2) & wmask;
+}
+__device__ __forceinline__ uint32_t filter_bits(uint32_t h) {
+    return (1u << ((h >> 17) & 31)) | (1u << (h >> 27));
+}
+__device__ __forceinline__ uint32_t filter_test(uint32_t fw, uint32_t h) {
+    return (fw >> ((h >> 17) & 31)) & (fw >> (h >> 27)) & 1u;
+}
+
 // ------------------------------------------------------------------ hash build
 
 // Clears the slot indices (to -1) and the Bloom bitmap (to 0).
@@ -213,8 +227,8 @@ __device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScr
     const uint32_t h = linear_hash<W>(k, tab.hr);
     sc.shx[i] = h;
     const uint32_t fmask = (1u << sc.filter_log2) - 1u;
-    const uint32_t fbits = (1u << (h & 31)) | (1u << (h >> 27));
-    atomicOr(&sc.filter[(h >> 5) & fmask], fbits);
+    const uint32_t fbits = filter_bits(h);
+    atomicOr(&sc.filter[filter_word(h, fmask)], fbits);
     if (sc.eparts_log2 > 0) {
         // the partition of the enumeration filter: class of x, the XOR of
         // the classes of its occupied beta qubits
@@ -230,7 +244,7 @@ __device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScr
         }
         c &= (1u << sc.eparts_log2) - 1u;
         const uint32_t emask = (1u << sc.efilter_log2) - 1u;
-        atomicOr(&sc.efilter[(c << sc.efilter_log2) + ((h >> 5) & emask)], fbits);
+        atomicOr(&sc.efilter[(c << sc.efilter_log2) + filter_word(h, emask)], fbits);
     }
     S *slots = static_cast<S *>(sc.slots);
     uint32_t slot = slot_of(h, sc.slot_shift) << bucket_log2(W);
@@ -683,7 +697,7 @@ __device__ __forceinline__ void lookup_item(
     #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
                     h[u] = hx ^ r[u].hx;
-                    fw[u] = filt[(h[u] >> 5) & fmask];
+                    fw[u] = filt[filter_word(h[u], fmask)];
                 }
                 // phase 3: sector test and filter bits
                 uint64_t ins_m[kUnroll], cand_m[kUnroll];
@@ -703,7 +717,7 @@ __device__ __forceinline__ void lookup_item(
                     } else {
                         ins = r[u].key != kPadKey;
                     }
-                    const bool bits = ((fw[u] >> (h[u] & 31)) & (fw[u] >> (h[u] >> 27)) & 1u) != 0u;
+                    const bool bits = filter_test(fw[u], h[u]) != 0u;
                     ins_m[u] = __ballot(ins) & amask;
                     cand_m[u] = __ballot(ins && bits) & amask;
                 }
@@ -829,6 +843,7 @@ struct EnumShape {
     int la, lba, lbb;    // list offsets (entries): rows of A at 0, Ba, Bb, then Bb columns
     int lcb;
     int L;               // padded list entries per sample
+    int solo;            // 1: solo rounds (one wave per sample)
 };
 
 __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
@@ -857,6 +872,9 @@ __device__ __forceinline__ EnumShape enum_shape(const DevTable &tab, const DevSc
     s.lbb = s.lba + enum_pad4(s.rba);
     s.lcb = s.lbb + enum_pad4(s.rbb);
     s.L = s.lcb + enum_pad4(s.cbb);
+    // solo rounds keep only the row lists (entries [0, lcb)) per wave
+    s.solo = (s.parts == 1 && tab.k_alpha <= 32 && tab.k_beta <= 32 &&
+              kEnumWaves * enum_solo_bytes(s.lcb) <= kEnumDynLds - kEnumDynFixed) ? 1 : 0;
     return s;
 }
 
@@ -869,23 +887,15 @@ __device__ __forceinline__ EnumShape uniform_shape(EnumShape s) {
     return s;
 }
 
-// k-th pair (i < j) in the order (0,1), (0,2), (1,2), (0,3), ... for
-// orbital lists of up to 64 entries, as a constant table (i | j << 8).
-constexpr int kPairTab = 64 * 63 / 2;
-struct PairTable {
-    uint16_t v[kPairTab];
-    constexpr PairTable() : v() {
-        int k = 0;
-        for (int j = 1; j < 64; ++j)
-            for (int i = 0; i < j; ++i) v[k++] = static_cast<uint16_t>(i | (j << 8));
-    }
-};
-__constant__ PairTable kPairs{};
-
+// k-th pair (i < j) in the order (0,1), (0,2), (1,2), (0,3), ...: j is the
+// largest with j (j - 1) / 2 <= k, from a float square root corrected by one
+// step each way (exact for the k < 2016 of orbital lists of up to 64).
 __device__ __forceinline__ void pair_of(int k, int &i, int &j) {
-    const uint32_t e = kPairs.v[k];
-    i = static_cast<int>(e & 0xFFu);
-    j = static_cast<int>(e >> 8);
+    int jj = static_cast<int>((1.0f + sqrtf(static_cast<float>(8 * k + 1))) * 0.5f);
+    if (jj * (jj - 1) / 2 > k) --jj;
+    if ((jj + 1) * jj / 2 <= k) ++jj;
+    j = jj;
+    i = k - jj * (jj - 1) / 2;
 }
 
 // Index of the group with flip mask X, or -1 (the group index is keyed by
@@ -910,6 +920,81 @@ struct EnumCounts {
     unsigned long long hits = 0, terms = 0;               // per lane
 };
 
+// Outcome of one queued candidate: whether x' is a sample with a group
+// (a hit), and its contribution H_xx' psi(x')/psi(x), in FP64 (re, im) or
+// in FP32 with the rounding errors kept (pre + ere, pim + eim).
+struct EnumHit {
+    bool hit = false;
+    double re = 0.0, im = 0.0;
+    float pre = 0.f, ere = 0.f, pim = 0.f, eim = 0.f;
+};
+
+// Candidate e = (flip code, h(x')) of sample x (hash hx, log amplitude la,
+// phase ph, index idx): look x' = x ^ X up in the sample hash and, on a hit,
+// find its group (or evaluate Slater-Condon) and the amplitude ratio; c is
+// left as it is (no hit) otherwise.
+template <int W, bool DUMP, int P, bool SCV>
+__device__ __forceinline__ void enum_candidate(
+    const DevTable &tab, const typename SlotT<W>::type *__restrict__ slots, const DevScratch &sc,
+    const Key<W> &x, uint32_t hx, double la, double ph, int64_t idx, uint2 e,
+    const double *__restrict__ log_amp, const double *__restrict__ phase,
+    int32_t *__restrict__ hit_idx, uint32_t *__restrict__ sign_bits, int64_t sign_words,
+    EnumCounts &cnt, EnumHit &c) {
+    Key<W> X;
+#pragma unroll
+    for (int q = 0; q < W; ++q) X.w[q] = 0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const uint32_t q = (e.x >> (7 * f)) & kNoQubit;
+        if (q != kNoQubit) {
+            if constexpr (W == 1) {
+                X.w[0] |= 1ull << q;
+            } else {
+                // constant indices keep X in registers
+                const uint64_t bit = 1ull << (q & 63);
+                if (q < 64) X.w[0] |= bit; else X.w[1] |= bit;
+            }
+        }
+    }
+    Key<W> xp;
+#pragma unroll
+    for (int q = 0; q < W; ++q) xp.w[q] = x.w[q] ^ X.w[q];
+    const int32_t j = hash_find<W>(slots, sc.slot_mask,
+                                   slot_of(e.y, sc.slot_shift) << bucket_log2(W), xp);
+    if (j < 0) return;
+    int64_t g = -1;
+    if (!SCV || DUMP) g = group_find<W>(tab, e.y ^ hx, X);
+    if constexpr (DUMP) {
+        if (hit_idx && g >= 0) hit_idx[idx * tab.n_groups + g] = j;
+    }
+    if (!SCV && g < 0) return;
+    c.hit = true;
+    ++cnt.hits;
+    if constexpr (P == NQS_FP64) {
+        uint32_t *row = (DUMP && sign_bits) ? sign_bits + idx * sign_words : nullptr;
+        double hsum;
+        if constexpr (SCV) {
+            (void)row;
+            hsum = sc_element<W>(tab, x, xp);
+        } else {
+            hsum = group_sum<W, DUMP>(tab, g, x, row, &cnt.terms);
+        }
+        double sn, cs;
+        sincos(phase[j] - ph, &sn, &cs);
+        const double mag = exp(log_amp[j] - la);
+        c.re = hsum * (mag * cs);
+        c.im = hsum * (mag * sn);
+    } else {
+        const AccF32 hs = group_sum_f32<W>(tab, g, x, &cnt.terms);
+        float rr, ri;
+        ratio_f32(log_amp[j] - la, phase[j] - ph, rr, ri);
+        c.pre = hs.s * rr;
+        c.ere = fmaf(hs.s, rr, -c.pre) + hs.c * rr;
+        c.pim = hs.s * ri;
+        c.eim = fmaf(hs.s, ri, -c.pim) + hs.c * ri;
+    }
+}
+
 // Position of the pair (i < j) of a class-sorted orbital list in the pair
 // list sorted by pair class (u ^ w): bucket s holds the blocks of class
 // pairs (u, u ^ s), u <= u ^ s, in increasing u; pairs inside one class come
@@ -931,6 +1016,68 @@ __device__ __forceinline__ int sorted_pair_pos(const uint8_t *cnt, const uint16_
     const int il = i - start_u, jl = j - start_w;
     const int loc = (s == 0) ? jl * (jl - 1) / 2 + il : il * cnt[w] + jl;
     return off[s] + pre + loc;
+}
+
+// Filter test of the rows [0, nr) of a work unit (nr <= 64, row hashes at
+// rw) against this lane's column hash (h(x) and the column's flips folded
+// in).  The outcome of row r < 32 lands in bit nq0 - 1 - r of the low word,
+// of row 32 + r in bit nq1 - 1 - r of the high word (nq: the half's row
+// count rounded up to whole groups of 4; rows past nr are read from the next
+// list or the padding and masked off).  Returns the survivors; excl drops
+// row 0 (the probe of x itself).  A16: rw is 16-byte aligned (one LDS read
+// per 4 rows).
+template <bool A16>
+__device__ __forceinline__ void rows4(const uint32_t *rw, int r, uint32_t colh, uint32_t h[4]) {
+    if constexpr (A16) {
+        const uint4 q = reinterpret_cast<const uint4 *>(rw)[r >> 2];
+        h[0] = colh ^ q.x;
+        h[1] = colh ^ q.y;
+        h[2] = colh ^ q.z;
+        h[3] = colh ^ q.w;
+    } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) h[v] = colh ^ rw[r + v];
+    }
+}
+
+template <bool A16>
+__device__ __forceinline__ uint64_t probe_rows(const char *filt_b, uint32_t fbytes_mask,
+                                               uint32_t colh, const uint32_t *rw, int nr,
+                                               bool act, bool excl, int &nq0, int &nq1) {
+    const int n0 = min(nr, 32), n1 = nr - n0;
+    nq0 = (n0 + 3) & ~3;
+    nq1 = (n1 + 3) & ~3;
+    uint32_t pm0 = 0, pm1 = 0;
+    for (int r = 0; r < n0; r += 4) {
+        uint32_t h[4], fw[4];
+        rows4<A16>(rw, r, colh, h);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            // the filter word of h, as a byte offset
+            fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + (h[v] & fbytes_mask));
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pm0 = (pm0 << 1) | filter_test(fw[v], h[v]);
+    }
+    for (int r = 32; r < nr; r += 4) {
+        uint32_t h[4], fw[4];
+        rows4<A16>(rw, r, colh, h);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + (h[v] & fbytes_mask));
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pm1 = (pm1 << 1) | filter_test(fw[v], h[v]);
+    }
+    // rows [0, n0) are bits (nq0 - 1 - n0, nq0 - 1] of pm0, likewise pm1
+    uint32_t keep0 = (n0 >= 32 ? 0xFFFFFFFFu : ((1u << n0) - 1u)) << (nq0 - n0);
+    uint32_t keep1 = n1 > 0 ? ((n1 >= 32 ? 0xFFFFFFFFu : ((1u << n1) - 1u)) << (nq1 - n1)) : 0u;
+    if (!act) keep0 = keep1 = 0u;
+    if (excl) keep0 &= ~(1u << (nq0 - 1));
+    return (static_cast<uint64_t>(pm1 & keep1) << 32) | (pm0 & keep0);
+}
+
+// Row of a survivor bit of probe_rows.
+__device__ __forceinline__ int row_of_bit(int bit, int nq0, int nq1) {
+    return bit < 32 ? nq0 - 1 - bit : 32 + nq1 - 1 - (bit - 32);
 }
 
 // One round: samples [round * B, round * B + B) of the batch, all filter
@@ -1132,70 +1279,19 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const uint2 e = lane < static_cast<int>(mcount) ? queue[lane] : make_uint2(0u, 0u);
         const int b = static_cast<int>(e.x >> 28);
-        bool hit = false;
-        double cre = 0.0, cim = 0.0;
-        float pre = 0.f, ere = 0.f, pim = 0.f, eim = 0.f;
+        EnumHit c;
         if (lane < static_cast<int>(mcount)) {
             const EnumSample rec = smp[b];
-            Key<W> x, X;
+            Key<W> x;
             x.w[0] = rec.x0;
             if constexpr (W == 2) x.w[1] = rec.x1;
-#pragma unroll
-            for (int q = 0; q < W; ++q) X.w[q] = 0;
-#pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                const uint32_t q = (e.x >> (7 * f)) & kNoQubit;
-                if (q != kNoQubit) {
-                    if constexpr (W == 1) {
-                        X.w[0] |= 1ull << q;
-                    } else {
-                        // constant indices keep X in registers
-                        const uint64_t bit = 1ull << (q & 63);
-                        if (q < 64) X.w[0] |= bit; else X.w[1] |= bit;
-                    }
-                }
-            }
-            Key<W> xp;
-#pragma unroll
-            for (int q = 0; q < W; ++q) xp.w[q] = x.w[q] ^ X.w[q];
-            const int32_t j = hash_find<W>(slots, sc.slot_mask,
-                                           slot_of(e.y, sc.slot_shift) << bucket_log2(W), xp);
-            if (j >= 0) {
-                int64_t g = -1;
-                if (!SCV || DUMP) g = group_find<W>(tab, e.y ^ rec.hx, X);
-                if constexpr (DUMP) {
-                    if (hit_idx && g >= 0) hit_idx[rec.idx * tab.n_groups + g] = j;
-                }
-                if (SCV || g >= 0) {
-                    hit = true;
-                    ++cnt.hits;
-                    if constexpr (P == NQS_FP64) {
-                        uint32_t *row =
-                            (DUMP && sign_bits) ? sign_bits + rec.idx * sign_words : nullptr;
-                        double hsum;
-                        if constexpr (SCV) {
-                            (void)row;
-                            hsum = sc_element<W>(tab, x, xp);
-                        } else {
-                            hsum = group_sum<W, DUMP>(tab, g, x, row, &cnt.terms);
-                        }
-                        double sn, cs;
-                        sincos(phase[j] - rec.ph, &sn, &cs);
-                        const double mag = exp(log_amp[j] - rec.la);
-                        cre = hsum * (mag * cs);
-                        cim = hsum * (mag * sn);
-                    } else {
-                        const AccF32 hs = group_sum_f32<W>(tab, g, x, &cnt.terms);
-                        float rr, ri;
-                        ratio_f32(log_amp[j] - rec.la, phase[j] - rec.ph, rr, ri);
-                        pre = hs.s * rr;
-                        ere = fmaf(hs.s, rr, -pre) + hs.c * rr;
-                        pim = hs.s * ri;
-                        eim = fmaf(hs.s, ri, -pim) + hs.c * ri;
-                    }
-                }
-            }
+            enum_candidate<W, DUMP, P, SCV>(tab, slots, sc, x, rec.hx, rec.la, rec.ph, rec.idx, e,
+                                            log_amp, phase, hit_idx, sign_bits, sign_words, cnt,
+                                            c);
         }
+        const bool hit = c.hit;
+        const double cre = c.re, cim = c.im;
+        const float pre = c.pre, ere = c.ere, pim = c.pim, eim = c.eim;
         uint64_t hm = __ballot(hit);
         while (hm) {
             const int q = __builtin_ctzll(hm);
@@ -1356,49 +1452,16 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             const uint16_t *rc = lc + b * L + row0 + r0;
             cnt.probes += static_cast<unsigned long long>(__popcll(colmask)) * nr -
                           (excl0 ? 1ull : 0ull);
-            // probes: the filter bit of row r < 32 lands in bit nq0 - 1 - r of
-            // pm0, of row 32 + r in bit nq1 - 1 - r of pm1 (nq: the half's row
-            // count rounded up to whole groups of 4; rows past nr are read
-            // from the next list or the padding and masked off below)
-            const int n0 = min(nr, 32), n1 = nr - n0;
-            const int nq0 = (n0 + 3) & ~3, nq1 = (n1 + 3) & ~3;
-            uint32_t pm0 = 0, pm1 = 0;
-            for (int r = 0; r < n0; r += 4) {
-                uint32_t h[4], fw[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) h[v] = colh ^ rw[r + v];
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    // word (h >> 5) of the bitmap, as a byte offset
-                    fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + ((h[v] >> 3) & fbytes_mask));
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    pm0 = (pm0 << 1) | ((fw[v] >> (h[v] & 31)) & (fw[v] >> (h[v] >> 27)) & 1u);
-            }
-            for (int r = 32; r < nr; r += 4) {
-                uint32_t h[4], fw[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) h[v] = colh ^ rw[r + v];
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + ((h[v] >> 3) & fbytes_mask));
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    pm1 = (pm1 << 1) | ((fw[v] >> (h[v] & 31)) & (fw[v] >> (h[v] >> 27)) & 1u);
-            }
-            // rows [0, n0) are bits (nq0 - 1 - n0, nq0 - 1] of pm0, likewise pm1
-            uint32_t keep0 = (n0 >= 32 ? 0xFFFFFFFFu : ((1u << n0) - 1u)) << (nq0 - n0);
-            uint32_t keep1 = n1 > 0 ? ((n1 >= 32 ? 0xFFFFFFFFu : ((1u << n1) - 1u)) << (nq1 - n1)) : 0u;
-            if (!act) keep0 = keep1 = 0u;
-            if (excl0 && lane == 0) keep0 &= ~(1u << (nq0 - 1));
-            uint64_t pm = (static_cast<uint64_t>(pm1 & keep1) << 32) | (pm0 & keep0);
+            int nq0, nq1;
+            uint64_t pm = probe_rows<false>(filt_b, fbytes_mask, colh, rw, nr, act,
+                                     excl0 && lane == 0, nq0, nq1);
             // filter survivors into the queue
             for (;;) {
                 const uint64_t any = __ballot(pm != 0ull);
                 if (!any) break;
                 const bool has = pm != 0ull;
                 const int bit = has ? __builtin_ctzll(pm) : 0;
-                const int rr = bit < 32 ? nq0 - 1 - bit : 32 + nq1 - 1 - (bit - 32);
+                const int rr = row_of_bit(bit, nq0, nq1);
                 pm &= pm - 1ull;
                 const uint32_t c = static_cast<uint32_t>(__popcll(any));
                 cnt.cand += c;
@@ -1441,6 +1504,221 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
         }
     }
     __syncthreads();
+}
+
+// floor(a / b) for 0 <= a < 4096 and 1 <= b <= 64, with inv = 1.0f / b: the
+// quotient (a + 1/2) / b lies at least 1 / 128 from an integer, far more
+// than the float rounding of the product.
+__device__ __forceinline__ int div_small(int a, float inv) {
+    return static_cast<int>((static_cast<float>(a) + 0.5f) * inv);
+}
+
+// Solo rounds: round r gives sample r * 16 + w to wave w, for r = first,
+// first + step, ...  Each wave builds its own sample's lists and runs the
+// products column chunk by column chunk (64 columns in the lanes, row
+// segments of up to 64 rows), adding its hits in queue order into registers:
+// there is no block barrier, so one wave's memory waits overlap the other
+// waves' probes.  The row lists of A, Ba and Bb (hash and flip code) sit in
+// the wave's LDS; columns are computed in registers.
+template <int W, bool DUMP, int P, bool SCV>
+__device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &tab,
+                                          const DevScratch &sc, const EnumShape &S,
+                                          const uint64_t *__restrict__ samples,
+                                          const double *__restrict__ log_amp,
+                                          const double *__restrict__ phase, int64_t n,
+                                          int64_t first, int64_t step,
+                                          int32_t *__restrict__ hit_idx,
+                                          uint32_t *__restrict__ sign_bits, int64_t sign_words,
+                                          EnumCounts &cnt) {
+    using Sl = typename SlotT<W>::type;
+    char *smem = dyn_lds();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t *hr = reinterpret_cast<const uint32_t *>(smem);
+    uint2 *queue = reinterpret_cast<uint2 *>(smem + kEnumQueueOff) + wave * kEnumQueue;
+    char *mine = smem + kEnumDynFixed + wave * enum_solo_bytes(S.lcb);
+    uint8_t *o = reinterpret_cast<uint8_t *>(mine);  // alpha occ, alpha vir, beta occ, beta vir
+    uint32_t *lh = reinterpret_cast<uint32_t *>(mine + kEnumSoloLists);
+    uint16_t *lc = reinterpret_cast<uint16_t *>(mine + kEnumSoloLists + 4 * S.lcb);
+    const Sl *__restrict__ slots = static_cast<const Sl *>(sc.slots);
+    const uint32_t fbytes_mask = ((1u << sc.efilter_log2) - 1u) << 2;
+    const char *filt_b = reinterpret_cast<const char *>(filt);
+    // this lane's alpha and beta qubit, for the whole loop
+    const bool ina = lane < tab.k_alpha, inb = lane < tab.k_beta;
+    const int qa_l = ina ? tab.spin_q[lane] : 0;
+    const int qb_l = inb ? tab.spin_q[64 + lane] : 0;
+    const float inv_va = 1.0f / static_cast<float>(max(S.va, 1));
+    const float inv_vb = 1.0f / static_cast<float>(max(S.vb, 1));
+    const int E = S.ra + S.rba + S.rbb;
+    const int s_ca = S.ca, s_cba = S.cba, s_cbb = S.cbb;
+    const int s_ra = S.ra, s_rba = S.rba, s_rbb = S.rbb;
+    const int s_lba = S.lba, s_lbb = S.lbb;
+    const int64_t n_rounds = (n + kEnumWaves - 1) / kEnumWaves;
+    for (int64_t r = first; r < n_rounds; r += step) {
+        const int64_t i = r * kEnumWaves + wave;
+        if (i >= n) break;  // later rounds only have larger indices
+        if (wave == 0) ++cnt.rounds;
+        Key<W> x;
+        x.w[0] = samples[2 * i];
+        if constexpr (W == 2) x.w[1] = samples[2 * i + 1];
+        const uint64_t x1 = W == 2 ? x.w[W - 1] : 0ull;
+        const double la = log_amp[i], ph = phase[i];
+        const uint32_t hx = sc.shx[i];
+
+        // orbital lists, in spin-qubit order
+        {
+            const bool oa = ina && (((qa_l < 64 ? x.w[0] : x1) >> (qa_l & 63)) & 1ull);
+            const bool ob = inb && (((qb_l < 64 ? x.w[0] : x1) >> (qb_l & 63)) & 1ull);
+            const uint64_t moa = __ballot(oa), mva = __ballot(ina && !oa);
+            const uint64_t mob = __ballot(ob), mvb = __ballot(inb && !ob);
+            if (oa) o[lanes_below(moa)] = static_cast<uint8_t>(qa_l);
+            if (ina && !oa) o[32 + lanes_below(mva)] = static_cast<uint8_t>(qa_l);
+            if (ob) o[64 + lanes_below(mob)] = static_cast<uint8_t>(qb_l);
+            if (inb && !ob) o[96 + lanes_below(mvb)] = static_cast<uint8_t>(qb_l);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // row lists (hash, flip code): A rows (the none row, then beta
+        // singles), alpha occupied pairs, beta occupied pairs
+        for (int e0 = 0; e0 < E; e0 += 64) {
+            int e = e0 + lane;
+            if (e >= E) break;
+            uint32_t qa = kNoQubit, qb = kNoQubit;
+            int pos;
+            if (e < S.ra) {
+                pos = e;
+                if (e > 0) {
+                    const int kk = e - 1, ii = div_small(kk, inv_vb);
+                    qa = o[64 + ii];
+                    qb = o[96 + kk - ii * S.vb];
+                }
+            } else if ((e -= S.ra) < S.rba) {
+                int ii, jj;
+                pair_of(e, ii, jj);
+                qa = o[ii];
+                qb = o[jj];
+                pos = S.lba + e;
+            } else {
+                e -= S.rba;
+                int ii, jj;
+                pair_of(e, ii, jj);
+                qa = o[64 + ii];
+                qb = o[64 + jj];
+                pos = S.lbb + e;
+            }
+            lh[pos] = qa == kNoQubit ? 0u : (hr[qa] ^ hr[qb]);
+            lc[pos] = static_cast<uint16_t>(qa | (qb << 7));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+
+        double acc_re = 0.0, acc_im = 0.0;
+        AccF32 acc_r, acc_i;
+        uint32_t qn = 0;
+        auto flush = [&](uint32_t mcount) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            EnumHit c;
+            if (lane < static_cast<int>(mcount))
+                enum_candidate<W, DUMP, P, SCV>(tab, slots, sc, x, hx, la, ph, i, queue[lane],
+                                                log_amp, phase, hit_idx, sign_bits, sign_words,
+                                                cnt, c);
+            uint64_t hm = __ballot(c.hit);
+            while (hm) {
+                const int q = __builtin_ctzll(hm);
+                hm &= hm - 1;
+                if constexpr (P == NQS_FP64) {
+                    acc_re += readlane_f64(c.re, q);
+                    acc_im += readlane_f64(c.im, q);
+                } else {
+                    acc_r.add(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.pre), q)),
+                              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.ere), q)));
+                    acc_i.add(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.pim), q)),
+                              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.eim), q)));
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        };
+
+        for (int prod = 0; prod < 3; ++prod) {
+            // product: columns, rows and their list (selects of values: a
+            // select of field addresses would keep the shape in memory)
+            const int ncol = prod == 0 ? s_ca : (prod == 1 ? s_cba : s_cbb);
+            const int nrow = prod == 0 ? s_ra : (prod == 1 ? s_rba : s_rbb);
+            const int row0 = prod == 0 ? 0 : (prod == 1 ? s_lba : s_lbb);
+            if (ncol == 0 || nrow == 0) continue;
+            const int ns = ceil_div(nrow, kEnumRowSeg);
+            // ns segments of equal length (a multiple of 4, at most 64)
+            const int sl = (ceil_div(nrow, ns) + 3) & ~3;
+            for (int ch = 0; ch * 64 < ncol; ++ch) {
+                // this lane's column: alpha single (or none), alpha virtual
+                // pair or beta virtual pair
+                const int k = ch * 64 + lane;
+                const bool act = k < ncol;
+                uint32_t colh = 0u, colc = kNoPair;
+                if (act) {
+                    uint32_t qa = kNoQubit, qb = kNoQubit;
+                    if (prod == 0) {
+                        if (k > 0) {
+                            const int kk = k - 1, ii = div_small(kk, inv_va);
+                            qa = o[ii];
+                            qb = o[32 + kk - ii * S.va];
+                        }
+                    } else {
+                        int ii, jj;
+                        pair_of(k, ii, jj);
+                        const int base = prod == 1 ? 32 : 96;
+                        qa = o[base + ii];
+                        qb = o[base + jj];
+                    }
+                    if (qa != kNoQubit) {
+                        colh = hr[qa] ^ hr[qb];
+                        colc = qa | (qb << 7);
+                    }
+                }
+                colh ^= hx;
+                const uint64_t colmask = __ballot(act);
+                for (int seg = 0; seg < ns; ++seg) {
+                    const bool excl0 = prod == 0 && ch == 0 && seg == 0;  // (none, none) is x
+                    const int r0 = seg * sl;
+                    const int nr = min(nrow - r0, sl);
+                    const uint32_t *rw = lh + row0 + r0;
+                    const uint16_t *rc = lc + row0 + r0;
+                    cnt.probes += static_cast<unsigned long long>(__popcll(colmask)) * nr -
+                                  (excl0 ? 1ull : 0ull);
+                    int nq0, nq1;
+                    uint64_t pm = probe_rows<true>(filt_b, fbytes_mask, colh, rw, nr, act,
+                                                   excl0 && lane == 0, nq0, nq1);
+                    for (;;) {
+                        const uint64_t any = __ballot(pm != 0ull);
+                        if (!any) break;
+                        const bool has = pm != 0ull;
+                        const int bit = has ? __builtin_ctzll(pm) : 0;
+                        const int rr = row_of_bit(bit, nq0, nq1);
+                        pm &= pm - 1ull;
+                        const uint32_t c = static_cast<uint32_t>(__popcll(any));
+                        cnt.cand += c;
+                        if (qn + c > static_cast<uint32_t>(kEnumQueue)) {
+                            flush(qn);
+                            qn = 0;
+                        }
+                        if (has)
+                            queue[qn + lanes_below(any)] = make_uint2(
+                                colc | (static_cast<uint32_t>(rc[rr]) << 14), colh ^ rw[rr]);
+                        qn += c;
+                    }
+                }
+            }
+        }
+        if (qn > 0) flush(qn);
+        if (lane == 0) {
+            double *pp = sc.part + 2 * i;
+            if constexpr (P == NQS_FP64) {
+                pp[0] = acc_re;
+                pp[1] = acc_im;
+            } else {
+                pp[0] = acc_r.value();
+                pp[1] = acc_i.value();
+            }
+        }
+    }
 }
 
 __device__ __forceinline__ void enum_flush_counts(const DevScratch &sc, EnumCounts &c) {
@@ -1497,10 +1775,16 @@ __global__ __launch_bounds__(kEnumThreads) void eloc_enum_kernel(
     EnumCounts cnt;
     int loaded_part = -1;
     // rounds blockIdx.x, blockIdx.x + gridDim.x, ...: no counter, no barrier
-    for (int64_t r = blockIdx.x; r < n_rounds; r += gridDim.x)
-        enum_round<W, DUMP, P, SCV>(reinterpret_cast<uint32_t *>(s_filter), tab, sc, S, samples,
-                                    log_amp, phase, n, r, hit_idx, sign_bits, sign_words, cnt,
-                                    loaded_part);
+    if (S.solo) {
+        enum_solo<W, DUMP, P, SCV>(reinterpret_cast<uint32_t *>(s_filter), tab, sc, S, samples,
+                                   log_amp, phase, n, blockIdx.x, gridDim.x, hit_idx, sign_bits,
+                                   sign_words, cnt);
+    } else {
+        for (int64_t r = blockIdx.x; r < n_rounds; r += gridDim.x)
+            enum_round<W, DUMP, P, SCV>(reinterpret_cast<uint32_t *>(s_filter), tab, sc, S,
+                                        samples, log_amp, phase, n, r, hit_idx, sign_bits,
+                                        sign_words, cnt, loaded_part);
+    }
     enum_flush_counts(sc, cnt);
 }
 
@@ -1683,10 +1967,13 @@ __global__ void batch_build_kernel(const JobDesc *__restrict__ jobs) {
         hash_build_one<2>(J.tab, J.sc, J.samples, J.weights, i);
 }
 
-// Enumeration items: rounds tile, tile + stride, ... of one job.  One
-// persistent kernel per variant (mask words, evaluator) drains the items of
-// that variant; they run before the streaming kernel.
-template <int W, int P, bool SCV>
+// Enumeration items: rounds tile, tile + stride, ... of one job.  Two
+// persistent kernels per variant (mask words, evaluator) drain the items of
+// that variant, each with its own counter: one runs the jobs whose shape
+// takes block rounds, the other the jobs that take solo rounds (the shape is
+// known on the device only), so that a job is evaluated exactly as a single
+// launch would.  They run before the streaming kernel.
+template <int W, int P, bool SCV, bool SOLO>
 __global__ __launch_bounds__(kEnumThreads) void batch_enum_kernel(
     const JobDesc *__restrict__ jobs, const WorkItem *__restrict__ items, int n_items,
     unsigned *__restrict__ next) {
@@ -1703,8 +1990,9 @@ __global__ __launch_bounds__(kEnumThreads) void batch_enum_kernel(
         const WorkItem w = items[it];
         const JobDesc &J = jobs[w.job];
         const EnumShape S = uniform_shape(enum_shape(J.tab, J.sc, J.samples, J.n));
-        const int64_t n_rounds = S.B > 0 ? (J.n + S.B - 1) / S.B : 0;
-        if (w.tile >= n_rounds) continue;  // also: the streaming items do this job
+        if (S.B <= 0 || (S.solo != 0) != SOLO) continue;  // the streaming items or the other kernel
+        const int64_t n_rounds = (J.n + (SOLO ? kEnumWaves : S.B) - 1) / (SOLO ? kEnumWaves : S.B);
+        if (w.tile >= n_rounds) continue;
         if (w.job != last_job) {
             // (with several partitions each round loads the ones it needs)
             if (S.parts == 1) load_filter_lds(J.sc, s_filter);
@@ -1714,10 +2002,16 @@ __global__ __launch_bounds__(kEnumThreads) void batch_enum_kernel(
         }
         last_job = w.job;
         EnumCounts cnt;
-        for (int64_t r = w.tile; r < n_rounds; r += w.stride)
-            enum_round<W, false, P, SCV>(reinterpret_cast<uint32_t *>(s_filter), J.tab,
-                                         J.sc, S, J.samples, J.log_amp, J.phase, J.n, r,
-                                         nullptr, nullptr, 0, cnt, loaded_part);
+        if constexpr (SOLO) {
+            enum_solo<W, false, P, SCV>(reinterpret_cast<uint32_t *>(s_filter), J.tab, J.sc, S,
+                                        J.samples, J.log_amp, J.phase, J.n, w.tile, w.stride,
+                                        nullptr, nullptr, 0, cnt);
+        } else {
+            for (int64_t r = w.tile; r < n_rounds; r += w.stride)
+                enum_round<W, false, P, SCV>(reinterpret_cast<uint32_t *>(s_filter), J.tab,
+                                             J.sc, S, J.samples, J.log_amp, J.phase, J.n, r,
+                                             nullptr, nullptr, 0, cnt, loaded_part);
+        }
         enum_flush_counts(J.sc, cnt);
     }
 }
@@ -1799,14 +2093,15 @@ size_t batch_lds_bytes(int threads, int max_filter_log2) {
 }
 
 namespace {
-// The enumeration kernel of variant v = (words - 1) + 2 * integral form.
-template <int P>
+// The enumeration kernel of variant v = (words - 1) + 2 * integral form,
+// block rounds or solo rounds.
+template <int P, bool SOLO>
 const void *enum_variant(int v) {
     switch (v) {
-        case 0: return reinterpret_cast<const void *>(&batch_enum_kernel<1, P, false>);
-        case 1: return reinterpret_cast<const void *>(&batch_enum_kernel<2, P, false>);
-        case 2: return reinterpret_cast<const void *>(&batch_enum_kernel<1, NQS_FP64, true>);
-        default: return reinterpret_cast<const void *>(&batch_enum_kernel<2, NQS_FP64, true>);
+        case 0: return reinterpret_cast<const void *>(&batch_enum_kernel<1, P, false, SOLO>);
+        case 1: return reinterpret_cast<const void *>(&batch_enum_kernel<2, P, false, SOLO>);
+        case 2: return reinterpret_cast<const void *>(&batch_enum_kernel<1, NQS_FP64, true, SOLO>);
+        default: return reinterpret_cast<const void *>(&batch_enum_kernel<2, NQS_FP64, true, SOLO>);
     }
 }
 }  // namespace
@@ -1821,10 +2116,16 @@ hipError_t prepare_batch_kernels() {
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_lookup_kernel<NQS_FP32_KAHAN>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLookupLds);
     for (int v = 0; v < kEnumVariants && e == hipSuccess; ++v) {
-        e = hipFuncSetAttribute(enum_variant<NQS_FP64>(v),
+        e = hipFuncSetAttribute(enum_variant<NQS_FP64, false>(v),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kEnumDynLds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(enum_variant<NQS_FP64, true>(v),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kEnumDynLds);
         if (e == hipSuccess && v < 2)
-            e = hipFuncSetAttribute(enum_variant<NQS_FP32_KAHAN>(v),
+            e = hipFuncSetAttribute(enum_variant<NQS_FP32_KAHAN, false>(v),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kEnumDynLds);
+        if (e == hipSuccess && v < 2)
+            e = hipFuncSetAttribute(enum_variant<NQS_FP32_KAHAN, true>(v),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, kEnumDynLds);
     }
     if (e == hipSuccess) done = true;
@@ -1846,23 +2147,32 @@ hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_ite
     const hipError_t pe = prepare_batch_kernels();
     if (pe != hipSuccess) return pe;
     // items [enum_begin[v], enum_begin[v + 1]) are the enumeration rounds of
-    // variant v; the streaming items follow
+    // variant v (drained twice: block rounds with counter 2 v, solo rounds
+    // with counter 2 v + 1); the streaming items follow
     const bool f32 = precision == NQS_FP32_KAHAN;
     for (int v = 0; v < kEnumVariants; ++v) {
         const int b0 = shape.enum_begin[v], cnt = shape.enum_begin[v + 1] - b0;
         if (cnt <= 0) continue;
         const WorkItem *it = d_items + b0;
-        unsigned *nx = d_next + v;
+        for (int solo = 0; solo < 2; ++solo) {
+            unsigned *nx = d_next + 2 * v + solo;
 #define NQS_EB(Wd, Pr, SCI)                                                                    \
-    hipLaunchKernelGGL((batch_enum_kernel<Wd, Pr, SCI>), dim3(shape.enum_blocks),               \
-                       dim3(kEnumThreads), kEnumDynLds, st, d_jobs, it, cnt, nx)
-        switch (v) {
-            case 0: if (f32) NQS_EB(1, NQS_FP32_KAHAN, false); else NQS_EB(1, NQS_FP64, false); break;
-            case 1: if (f32) NQS_EB(2, NQS_FP32_KAHAN, false); else NQS_EB(2, NQS_FP64, false); break;
-            case 2: NQS_EB(1, NQS_FP64, true); break;
-            default: NQS_EB(2, NQS_FP64, true); break;
-        }
+    do {                                                                                       \
+        if (solo)                                                                              \
+            hipLaunchKernelGGL((batch_enum_kernel<Wd, Pr, SCI, true>), dim3(shape.enum_blocks), \
+                               dim3(kEnumThreads), kEnumDynLds, st, d_jobs, it, cnt, nx);      \
+        else                                                                                   \
+            hipLaunchKernelGGL((batch_enum_kernel<Wd, Pr, SCI, false>), dim3(shape.enum_blocks), \
+                               dim3(kEnumThreads), kEnumDynLds, st, d_jobs, it, cnt, nx);      \
+    } while (0)
+            switch (v) {
+                case 0: if (f32) NQS_EB(1, NQS_FP32_KAHAN, false); else NQS_EB(1, NQS_FP64, false); break;
+                case 1: if (f32) NQS_EB(2, NQS_FP32_KAHAN, false); else NQS_EB(2, NQS_FP64, false); break;
+                case 2: NQS_EB(1, NQS_FP64, true); break;
+                default: NQS_EB(2, NQS_FP64, true); break;
+            }
 #undef NQS_EB
+        }
     }
     const int ne = shape.enum_begin[kEnumVariants];
     const WorkItem *s_items = d_items + ne;
@@ -1872,13 +2182,13 @@ hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_ite
         if (ns > 0)
             hipLaunchKernelGGL(batch_lookup_kernel<NQS_FP32_KAHAN>, dim3(shape.lookup_blocks),
                                dim3(shape.threads), lds, st, d_jobs, s_items, ns,
-                               d_next + kEnumVariants);
+                               d_next + kStreamCounter);
         hipLaunchKernelGGL(batch_finish_kernel<NQS_FP32_KAHAN>, fgrid, dim3(256), 0, st, d_jobs);
     } else {
         if (ns > 0)
             hipLaunchKernelGGL(batch_lookup_kernel<NQS_FP64>, dim3(shape.lookup_blocks),
                                dim3(shape.threads), lds, st, d_jobs, s_items, ns,
-                               d_next + kEnumVariants);
+                               d_next + kStreamCounter);
         hipLaunchKernelGGL(batch_finish_kernel<NQS_FP64>, fgrid, dim3(256), 0, st, d_jobs);
     }
     return hipGetLastError();
