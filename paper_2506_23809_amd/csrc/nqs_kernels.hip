@@ -169,16 +169,18 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 
 // Blocked Bloom filter of the sample hashes: a key with hash h sets two bits
 // of one 32-bit word, word (h >> 2) & (words - 1) and bits (h >> 17) & 31 and
-// h >> 27 (disjoint ranges of h for filters of up to 2^15 words).  The byte
-// offset of the word is then h & ((words - 1) << 2), one AND per probe.
+// (h >> 24) & 31 (disjoint ranges of h for filters of up to 2^15 words).  The
+// byte offset of the word is h & ((words - 1) << 2), which folds into the
+// XOR forming h; the shift by (h >> 24) reads byte 3 of h in place (a
+// sub-dword operand), so a probe costs one shift less.
 __device__ __forceinline__ uint32_t filter_word(uint32_t h, uint32_t wmask) {
     return (h >> 2) & wmask;
 }
 __device__ __forceinline__ uint32_t filter_bits(uint32_t h) {
-    return (1u << ((h >> 17) & 31)) | (1u << (h >> 27));
+    return (1u << ((h >> 17) & 31)) | (1u << ((h >> 24) & 31));
 }
 __device__ __forceinline__ uint32_t filter_test(uint32_t fw, uint32_t h) {
-    return (fw >> ((h >> 17) & 31)) & (fw >> (h >> 27)) & 1u;
+    return (fw >> ((h >> 17) & 31)) & (fw >> ((h >> 24) & 31)) & 1u;
 }
 
 // ------------------------------------------------------------------ hash build
@@ -874,7 +876,8 @@ __device__ __forceinline__ EnumShape enum_shape(const DevTable &tab, const DevSc
     s.L = s.lcb + enum_pad4(s.cbb);
     // solo rounds keep only the row lists (entries [0, lcb)) per wave
     s.solo = (s.parts == 1 && tab.k_alpha <= 32 && tab.k_beta <= 32 &&
-              kEnumWaves * enum_solo_bytes(s.lcb) <= kEnumDynLds - kEnumDynFixed) ? 1 : 0;
+              kEnumWaves * enum_solo_bytes(s.lcb) + 2 * kEnumSoloPairs <=
+                  kEnumDynLds - kEnumDynFixed) ? 1 : 0;
     return s;
 }
 
@@ -1018,14 +1021,14 @@ __device__ __forceinline__ int sorted_pair_pos(const uint8_t *cnt, const uint16_
     return off[s] + pre + loc;
 }
 
-// Filter test of the rows [0, nr) of a work unit (nr <= 64, row hashes at
-// rw) against this lane's column hash (h(x) and the column's flips folded
-// in).  The outcome of row r < 32 lands in bit nq0 - 1 - r of the low word,
-// of row 32 + r in bit nq1 - 1 - r of the high word (nq: the half's row
-// count rounded up to whole groups of 4; rows past nr are read from the next
-// list or the padding and masked off).  Returns the survivors; excl drops
-// row 0 (the probe of x itself).  A16: rw is 16-byte aligned (one LDS read
-// per 4 rows).
+// Filter test of the rows [0, nrl) of a work unit (nrl <= 64, row hashes at
+// rw, this lane's own rows [0, nr)) against this lane's column hash (h(x)
+// and the column's flips folded in).  The outcome of row r < 32 lands in
+// bit nq0 - 1 - r of the low word, of row 32 + r in bit nq1 - 1 - r of the
+// high word (nq: the half's row count rounded up to whole groups of 4; rows
+// past nr are read from the next list or the padding and masked off).
+// Returns the survivors; excl drops row 0 (the probe of x itself).  A16: rw
+// is 16-byte aligned (one LDS read per 4 rows).
 template <bool A16>
 __device__ __forceinline__ void rows4(const uint32_t *rw, int r, uint32_t colh, uint32_t h[4]) {
     if constexpr (A16) {
@@ -1042,13 +1045,15 @@ __device__ __forceinline__ void rows4(const uint32_t *rw, int r, uint32_t colh, 
 
 template <bool A16>
 __device__ __forceinline__ uint64_t probe_rows(const char *filt_b, uint32_t fbytes_mask,
-                                               uint32_t colh, const uint32_t *rw, int nr,
+                                               uint32_t colh, const uint32_t *rw, int nrl, int nr,
                                                bool act, bool excl, int &nq0, int &nq1) {
+    // nrl (wave-uniform) rows are read, the lane's first nr are kept
+    const int m0 = min(nrl, 32);
+    nq0 = (m0 + 3) & ~3;
+    nq1 = (nrl - m0 + 3) & ~3;
     const int n0 = min(nr, 32), n1 = nr - n0;
-    nq0 = (n0 + 3) & ~3;
-    nq1 = (n1 + 3) & ~3;
     uint32_t pm0 = 0, pm1 = 0;
-    for (int r = 0; r < n0; r += 4) {
+    for (int r = 0; r < m0; r += 4) {
         uint32_t h[4], fw[4];
         rows4<A16>(rw, r, colh, h);
 #pragma unroll
@@ -1058,7 +1063,7 @@ __device__ __forceinline__ uint64_t probe_rows(const char *filt_b, uint32_t fbyt
 #pragma unroll
         for (int v = 0; v < 4; ++v) pm0 = (pm0 << 1) | filter_test(fw[v], h[v]);
     }
-    for (int r = 32; r < nr; r += 4) {
+    for (int r = 32; r < nrl; r += 4) {
         uint32_t h[4], fw[4];
         rows4<A16>(rw, r, colh, h);
 #pragma unroll
@@ -1453,7 +1458,7 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             cnt.probes += static_cast<unsigned long long>(__popcll(colmask)) * nr -
                           (excl0 ? 1ull : 0ull);
             int nq0, nq1;
-            uint64_t pm = probe_rows<false>(filt_b, fbytes_mask, colh, rw, nr, act,
+            uint64_t pm = probe_rows<false>(filt_b, fbytes_mask, colh, rw, nr, nr, act,
                                      excl0 && lane == 0, nq0, nq1);
             // filter survivors into the queue
             for (;;) {
@@ -1506,20 +1511,24 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
     __syncthreads();
 }
 
-// floor(a / b) for 0 <= a < 4096 and 1 <= b <= 64, with inv = 1.0f / b: the
-// quotient (a + 1/2) / b lies at least 1 / 128 from an integer, far more
-// than the float rounding of the product.
+// floor(a / b) for 0 <= a < 2^22 and b >= 1, with inv = 1.0f / b: the
+// quotient (a + 1/2) / b lies at least 1 / (2 b) from an integer, more than
+// the two float roundings of the product (at most (a + 1/2) / b * 2^-23).
 __device__ __forceinline__ int div_small(int a, float inv) {
     return static_cast<int>((static_cast<float>(a) + 0.5f) * inv);
 }
 
 // Solo rounds: round r gives sample r * 16 + w to wave w, for r = first,
-// first + step, ...  Each wave builds its own sample's lists and runs the
-// products column chunk by column chunk (64 columns in the lanes, row
-// segments of up to 64 rows), adding its hits in queue order into registers:
-// there is no block barrier, so one wave's memory waits overlap the other
-// waves' probes.  The row lists of A, Ba and Bb (hash and flip code) sit in
-// the wave's LDS; columns are computed in registers.
+// first + step, ...  Each wave builds its own sample's lists and probes its
+// products as tasks (product, row segment of at most 64 rows, column), 64
+// tasks at a time, one per lane: a chunk may mix products, so that lanes are
+// not left idle by column counts short of a multiple of 64.  Hits are added
+// in queue order into registers; there is no block barrier, so one wave's
+// memory waits overlap the other waves' probes.  The row lists of A, Ba and
+// Bb (hash and flip code) sit in the wave's LDS, columns are computed in
+// registers.  A lane reads its segment's rows; reads past them (up to the
+// chunk's longest segment) stay inside the block's LDS (the next wave's area
+// or the pair table) and are masked off.
 template <int W, bool DUMP, int P, bool SCV>
 __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &tab,
                                           const DevScratch &sc, const EnumShape &S,
@@ -1547,12 +1556,35 @@ __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &
     const bool ina = lane < tab.k_alpha, inb = lane < tab.k_beta;
     const int qa_l = ina ? tab.spin_q[lane] : 0;
     const int qb_l = inb ? tab.spin_q[64 + lane] : 0;
+    const uint16_t *pt = reinterpret_cast<const uint16_t *>(
+        smem + kEnumDynFixed + kEnumWaves * enum_solo_bytes(S.lcb));
+    auto pair_lds = [&](int q, int &ii, int &jj) {
+        const uint32_t v = pt[q];
+        ii = static_cast<int>(v & 0xFFu);
+        jj = static_cast<int>(v >> 8);
+    };
     const float inv_va = 1.0f / static_cast<float>(max(S.va, 1));
     const float inv_vb = 1.0f / static_cast<float>(max(S.vb, 1));
     const int E = S.ra + S.rba + S.rbb;
     const int s_ca = S.ca, s_cba = S.cba, s_cbb = S.cbb;
     const int s_ra = S.ra, s_rba = S.rba, s_rbb = S.rbb;
     const int s_lba = S.lba, s_lbb = S.lbb;
+    // per product: row segments of at most 64 rows, of equal length (a
+    // multiple of 4), and the tasks (segment, column) they make
+    const int ns_a = ceil_div(s_ra, kEnumRowSeg), ns_ba = ceil_div(s_rba, kEnumRowSeg);
+    const int ns_bb = ceil_div(s_rbb, kEnumRowSeg);
+    const int sl_a = ns_a ? (ceil_div(s_ra, ns_a) + 3) & ~3 : 0;
+    const int sl_ba = ns_ba ? (ceil_div(s_rba, ns_ba) + 3) & ~3 : 0;
+    const int sl_bb = ns_bb ? (ceil_div(s_rbb, ns_bb) + 3) & ~3 : 0;
+    const int t_a = ns_a * s_ca, t_ba = ns_ba * s_cba, t_bb = ns_bb * s_cbb;
+    const int n_task = t_a + t_ba + t_bb;
+    const float inv_ca = 1.0f / static_cast<float>(max(s_ca, 1));
+    const float inv_cba = 1.0f / static_cast<float>(max(s_cba, 1));
+    const float inv_cbb = 1.0f / static_cast<float>(max(s_cbb, 1));
+    // every flip but (none, none)
+    const unsigned long long n_probe = static_cast<unsigned long long>(s_ra) * s_ca +
+                                       static_cast<unsigned long long>(s_rba) * s_cba +
+                                       static_cast<unsigned long long>(s_rbb) * s_cbb - 1ull;
     const int64_t n_rounds = (n + kEnumWaves - 1) / kEnumWaves;
     for (int64_t r = first; r < n_rounds; r += step) {
         const int64_t i = r * kEnumWaves + wave;
@@ -1593,14 +1625,14 @@ __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &
                 }
             } else if ((e -= S.ra) < S.rba) {
                 int ii, jj;
-                pair_of(e, ii, jj);
+                pair_lds(e, ii, jj);
                 qa = o[ii];
                 qb = o[jj];
                 pos = S.lba + e;
             } else {
                 e -= S.rba;
                 int ii, jj;
-                pair_of(e, ii, jj);
+                pair_lds(e, ii, jj);
                 qa = o[64 + ii];
                 qb = o[64 + jj];
                 pos = S.lbb + e;
@@ -1637,74 +1669,79 @@ __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         };
 
-        for (int prod = 0; prod < 3; ++prod) {
-            // product: columns, rows and their list (selects of values: a
-            // select of field addresses would keep the shape in memory)
-            const int ncol = prod == 0 ? s_ca : (prod == 1 ? s_cba : s_cbb);
-            const int nrow = prod == 0 ? s_ra : (prod == 1 ? s_rba : s_rbb);
-            const int row0 = prod == 0 ? 0 : (prod == 1 ? s_lba : s_lbb);
-            if (ncol == 0 || nrow == 0) continue;
-            const int ns = ceil_div(nrow, kEnumRowSeg);
-            // ns segments of equal length (a multiple of 4, at most 64)
-            const int sl = (ceil_div(nrow, ns) + 3) & ~3;
-            for (int ch = 0; ch * 64 < ncol; ++ch) {
-                // this lane's column: alpha single (or none), alpha virtual
-                // pair or beta virtual pair
-                const int k = ch * 64 + lane;
-                const bool act = k < ncol;
-                uint32_t colh = 0u, colc = kNoPair;
-                if (act) {
-                    uint32_t qa = kNoQubit, qb = kNoQubit;
-                    if (prod == 0) {
-                        if (k > 0) {
-                            const int kk = k - 1, ii = div_small(kk, inv_va);
-                            qa = o[ii];
-                            qb = o[32 + kk - ii * S.va];
-                        }
-                    } else {
-                        int ii, jj;
-                        pair_of(k, ii, jj);
-                        const int base = prod == 1 ? 32 : 96;
-                        qa = o[base + ii];
-                        qb = o[base + jj];
+        // lanes take (product, row segment, column) tasks, products and
+        // segments in order: a chunk of 64 tasks may mix products, each lane
+        // reading its own segment's rows (16-byte aligned)
+        cnt.probes += n_probe;
+        for (int c0 = 0; c0 < n_task; c0 += 64) {
+            const int t = c0 + lane;
+            const bool act = t < n_task;
+            const int p = t < t_a ? 0 : (t < t_a + t_ba ? 1 : 2);
+            const int u = t - (p == 0 ? 0 : (p == 1 ? t_a : t_a + t_ba));
+            const int ncol = p == 0 ? s_ca : (p == 1 ? s_cba : s_cbb);
+            const float inv = p == 0 ? inv_ca : (p == 1 ? inv_cba : inv_cbb);
+            const int sl = p == 0 ? sl_a : (p == 1 ? sl_ba : sl_bb);
+            const int nrow = p == 0 ? s_ra : (p == 1 ? s_rba : s_rbb);
+            const int row0 = p == 0 ? 0 : (p == 1 ? s_lba : s_lbb);
+            const int seg = div_small(u, inv), k = u - seg * ncol;
+            const int r0 = seg * sl;
+            const int nr = act ? min(nrow - r0, sl) : 0;
+            const int rb = act ? row0 + r0 : 0;
+            // this lane's column: alpha single (or none), alpha virtual pair
+            // or beta virtual pair
+            uint32_t colh = 0u, colc = kNoPair;
+            if (act) {
+                uint32_t qa = kNoQubit, qb = kNoQubit;
+                if (p == 0) {
+                    if (k > 0) {
+                        const int kk = k - 1, ii = div_small(kk, inv_va);
+                        qa = o[ii];
+                        qb = o[32 + kk - ii * S.va];
                     }
-                    if (qa != kNoQubit) {
-                        colh = hr[qa] ^ hr[qb];
-                        colc = qa | (qb << 7);
-                    }
+                } else {
+                    int ii, jj;
+                    pair_lds(k, ii, jj);
+                    const int base = p == 1 ? 32 : 96;
+                    qa = o[base + ii];
+                    qb = o[base + jj];
                 }
-                colh ^= hx;
-                const uint64_t colmask = __ballot(act);
-                for (int seg = 0; seg < ns; ++seg) {
-                    const bool excl0 = prod == 0 && ch == 0 && seg == 0;  // (none, none) is x
-                    const int r0 = seg * sl;
-                    const int nr = min(nrow - r0, sl);
-                    const uint32_t *rw = lh + row0 + r0;
-                    const uint16_t *rc = lc + row0 + r0;
-                    cnt.probes += static_cast<unsigned long long>(__popcll(colmask)) * nr -
-                                  (excl0 ? 1ull : 0ull);
-                    int nq0, nq1;
-                    uint64_t pm = probe_rows<true>(filt_b, fbytes_mask, colh, rw, nr, act,
-                                                   excl0 && lane == 0, nq0, nq1);
-                    for (;;) {
-                        const uint64_t any = __ballot(pm != 0ull);
-                        if (!any) break;
-                        const bool has = pm != 0ull;
-                        const int bit = has ? __builtin_ctzll(pm) : 0;
-                        const int rr = row_of_bit(bit, nq0, nq1);
-                        pm &= pm - 1ull;
-                        const uint32_t c = static_cast<uint32_t>(__popcll(any));
-                        cnt.cand += c;
-                        if (qn + c > static_cast<uint32_t>(kEnumQueue)) {
-                            flush(qn);
-                            qn = 0;
-                        }
-                        if (has)
-                            queue[qn + lanes_below(any)] = make_uint2(
-                                colc | (static_cast<uint32_t>(rc[rr]) << 14), colh ^ rw[rr]);
-                        qn += c;
-                    }
+                if (qa != kNoQubit) {
+                    colh = hr[qa] ^ hr[qb];
+                    colc = qa | (qb << 7);
                 }
+            }
+            colh ^= hx;
+            // rows read by the chunk: the longest segment among its products
+            const int tl = min(c0 + 63, n_task - 1);
+            const int pf = c0 < t_a ? 0 : (c0 < t_a + t_ba ? 1 : 2);
+            const int pl = tl < t_a ? 0 : (tl < t_a + t_ba ? 1 : 2);
+            int nrl = 0;
+            if (pf <= 0 && 0 <= pl) nrl = max(nrl, sl_a);
+            if (pf <= 1 && 1 <= pl) nrl = max(nrl, sl_ba);
+            if (pf <= 2 && 2 <= pl) nrl = max(nrl, sl_bb);
+            const uint32_t *rw = lh + rb;
+            const uint16_t *rc = lc + rb;
+            int nq0, nq1;
+            // task 0 is (A, first segment, none column): its row 0 is x
+            uint64_t pm = probe_rows<true>(filt_b, fbytes_mask, colh, rw, nrl, nr, act,
+                                           c0 == 0 && lane == 0, nq0, nq1);
+            for (;;) {
+                const uint64_t any = __ballot(pm != 0ull);
+                if (!any) break;
+                const bool has = pm != 0ull;
+                const int bit = has ? __builtin_ctzll(pm) : 0;
+                const int rr = row_of_bit(bit, nq0, nq1);
+                pm &= pm - 1ull;
+                const uint32_t c = static_cast<uint32_t>(__popcll(any));
+                cnt.cand += c;
+                if (qn + c > static_cast<uint32_t>(kEnumQueue)) {
+                    flush(qn);
+                    qn = 0;
+                }
+                if (has)
+                    queue[qn + lanes_below(any)] = make_uint2(
+                        colc | (static_cast<uint32_t>(rc[rr]) << 14), colh ^ rw[rr]);
+                qn += c;
             }
         }
         if (qn > 0) flush(qn);
@@ -1750,6 +1787,17 @@ __device__ __forceinline__ void load_enum_tables(const DevTable &tab) {
     }
 }
 
+// Pair table of the solo rounds (the caller synchronises before use).
+__device__ __forceinline__ void load_solo_pairs(const EnumShape &S) {
+    uint16_t *pt = reinterpret_cast<uint16_t *>(dyn_lds() + kEnumDynFixed +
+                                                kEnumWaves * enum_solo_bytes(S.lcb));
+    for (int q = threadIdx.x; q < kEnumSoloPairs; q += blockDim.x) {
+        int i, j;
+        pair_of(q, i, j);
+        pt[q] = static_cast<uint16_t>(i | (j << 8));
+    }
+}
+
 __device__ __forceinline__ void load_filter_lds(const DevScratch &sc, uint4 *smem4) {
     // (also used with the static filter array of the enumeration kernels)
     const uint4 *gf = reinterpret_cast<const uint4 *>(sc.filter);
@@ -1771,6 +1819,7 @@ __global__ __launch_bounds__(kEnumThreads) void eloc_enum_kernel(
     const int64_t n_rounds = (n + S.B - 1) / S.B;
     if (S.parts == 1) load_filter_lds(sc, s_filter);  // else each round loads its partitions
     load_enum_tables(tab);
+    if (S.solo) load_solo_pairs(S);
     __syncthreads();
     EnumCounts cnt;
     int loaded_part = -1;
@@ -1997,6 +2046,7 @@ __global__ __launch_bounds__(kEnumThreads) void batch_enum_kernel(
             // (with several partitions each round loads the ones it needs)
             if (S.parts == 1) load_filter_lds(J.sc, s_filter);
             load_enum_tables(J.tab);
+            if (SOLO) load_solo_pairs(S);
             loaded_part = -1;
             __syncthreads();
         }
