@@ -1023,12 +1023,10 @@ __device__ __forceinline__ int sorted_pair_pos(const uint8_t *cnt, const uint16_
 
 // Filter test of the rows [0, nrl) of a work unit (nrl <= 64, row hashes at
 // rw, this lane's own rows [0, nr)) against this lane's column hash (h(x)
-// and the column's flips folded in).  The outcome of row r < 32 lands in
-// bit nq0 - 1 - r of the low word, of row 32 + r in bit nq1 - 1 - r of the
-// high word (nq: the half's row count rounded up to whole groups of 4; rows
-// past nr are read from the next list or the padding and masked off).
-// Returns the survivors; excl drops row 0 (the probe of x itself).  A16: rw
-// is 16-byte aligned (one LDS read per 4 rows).
+// and the column's flips folded in): bit r of the result is the outcome of
+// row r, rows past nr (read from the next list or the padding) masked off.
+// excl drops row 0 (the probe of x itself).  A16: rw is 16-byte aligned
+// (one LDS read per 4 rows).
 template <bool A16>
 __device__ __forceinline__ void rows4(const uint32_t *rw, int r, uint32_t colh, uint32_t h[4]) {
     if constexpr (A16) {
@@ -1046,12 +1044,8 @@ __device__ __forceinline__ void rows4(const uint32_t *rw, int r, uint32_t colh, 
 template <bool A16>
 __device__ __forceinline__ uint64_t probe_rows(const char *filt_b, uint32_t fbytes_mask,
                                                uint32_t colh, const uint32_t *rw, int nrl, int nr,
-                                               bool act, bool excl, int &nq0, int &nq1) {
-    // nrl (wave-uniform) rows are read, the lane's first nr are kept
+                                               bool act, bool excl) {
     const int m0 = min(nrl, 32);
-    nq0 = (m0 + 3) & ~3;
-    nq1 = (nrl - m0 + 3) & ~3;
-    const int n0 = min(nr, 32), n1 = nr - n0;
     uint32_t pm0 = 0, pm1 = 0;
     for (int r = 0; r < m0; r += 4) {
         uint32_t h[4], fw[4];
@@ -1061,7 +1055,7 @@ __device__ __forceinline__ uint64_t probe_rows(const char *filt_b, uint32_t fbyt
             // the filter word of h, as a byte offset
             fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + (h[v] & fbytes_mask));
 #pragma unroll
-        for (int v = 0; v < 4; ++v) pm0 = (pm0 << 1) | filter_test(fw[v], h[v]);
+        for (int v = 0; v < 4; ++v) pm0 |= filter_test(fw[v], h[v]) << (r + v);
     }
     for (int r = 32; r < nrl; r += 4) {
         uint32_t h[4], fw[4];
@@ -1070,20 +1064,16 @@ __device__ __forceinline__ uint64_t probe_rows(const char *filt_b, uint32_t fbyt
         for (int v = 0; v < 4; ++v)
             fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + (h[v] & fbytes_mask));
 #pragma unroll
-        for (int v = 0; v < 4; ++v) pm1 = (pm1 << 1) | filter_test(fw[v], h[v]);
+        for (int v = 0; v < 4; ++v) pm1 |= filter_test(fw[v], h[v]) << (r - 32 + v);
     }
-    // rows [0, n0) are bits (nq0 - 1 - n0, nq0 - 1] of pm0, likewise pm1
-    uint32_t keep0 = (n0 >= 32 ? 0xFFFFFFFFu : ((1u << n0) - 1u)) << (nq0 - n0);
-    uint32_t keep1 = n1 > 0 ? ((n1 >= 32 ? 0xFFFFFFFFu : ((1u << n1) - 1u)) << (nq1 - n1)) : 0u;
+    const int n0 = min(nr, 32), n1 = nr - n0;
+    uint32_t keep0 = n0 >= 32 ? 0xFFFFFFFFu : ((1u << n0) - 1u);
+    uint32_t keep1 = n1 >= 32 ? 0xFFFFFFFFu : ((1u << n1) - 1u);
     if (!act) keep0 = keep1 = 0u;
-    if (excl) keep0 &= ~(1u << (nq0 - 1));
+    if (excl) keep0 &= ~1u;
     return (static_cast<uint64_t>(pm1 & keep1) << 32) | (pm0 & keep0);
 }
 
-// Row of a survivor bit of probe_rows.
-__device__ __forceinline__ int row_of_bit(int bit, int nq0, int nq1) {
-    return bit < 32 ? nq0 - 1 - bit : 32 + nq1 - 1 - (bit - 32);
-}
 
 // One round: samples [round * B, round * B + B) of the batch, all filter
 // partitions in turn (with one partition its filter is already in LDS).
@@ -1457,16 +1447,15 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             const uint16_t *rc = lc + b * L + row0 + r0;
             cnt.probes += static_cast<unsigned long long>(__popcll(colmask)) * nr -
                           (excl0 ? 1ull : 0ull);
-            int nq0, nq1;
             uint64_t pm = probe_rows<false>(filt_b, fbytes_mask, colh, rw, nr, nr, act,
-                                     excl0 && lane == 0, nq0, nq1);
+                                            excl0 && lane == 0);
             // filter survivors into the queue
             for (;;) {
                 const uint64_t any = __ballot(pm != 0ull);
                 if (!any) break;
                 const bool has = pm != 0ull;
                 const int bit = has ? __builtin_ctzll(pm) : 0;
-                const int rr = row_of_bit(bit, nq0, nq1);
+                const int rr = bit;
                 pm &= pm - 1ull;
                 const uint32_t c = static_cast<uint32_t>(__popcll(any));
                 cnt.cand += c;
@@ -1721,16 +1710,15 @@ __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &
             if (pf <= 2 && 2 <= pl) nrl = max(nrl, sl_bb);
             const uint32_t *rw = lh + rb;
             const uint16_t *rc = lc + rb;
-            int nq0, nq1;
             // task 0 is (A, first segment, none column): its row 0 is x
             uint64_t pm = probe_rows<true>(filt_b, fbytes_mask, colh, rw, nrl, nr, act,
-                                           c0 == 0 && lane == 0, nq0, nq1);
+                                           c0 == 0 && lane == 0);
             for (;;) {
                 const uint64_t any = __ballot(pm != 0ull);
                 if (!any) break;
                 const bool has = pm != 0ull;
                 const int bit = has ? __builtin_ctzll(pm) : 0;
-                const int rr = row_of_bit(bit, nq0, nq1);
+                const int rr = bit;
                 pm &= pm - 1ull;
                 const uint32_t c = static_cast<uint32_t>(__popcll(any));
                 cnt.cand += c;
