@@ -240,6 +240,12 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
         tc32[2 * t] = hi;
         tc32[2 * t + 1] = static_cast<float>(T.tc[t] - static_cast<double>(hi));
     }
+    std::vector<float> diag32(2 * T.diag.size());
+    for (size_t k = 0; k < T.diag.size(); ++k) {
+        const float hi = static_cast<float>(T.diag[k]);
+        diag32[2 * k] = hi;
+        diag32[2 * k + 1] = static_cast<float>(T.diag[k] - static_cast<double>(hi));
+    }
     std::vector<uint32_t> goff32(T.goff.size());
     for (size_t k = 0; k < T.goff.size(); ++k) goff32[k] = static_cast<uint32_t>(T.goff[k]);
     const nqs::LinearHash lh;
@@ -262,6 +268,8 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
         {T.spin_q, sizeof(T.spin_q), 0},
         {T.gh.data(), sizeof(uint32_t) * T.gh.size(), 0},
         {T.qcls, sizeof(T.qcls), 0},
+        {T.diag.data(), sizeof(double) * T.diag.size(), 0},
+        {diag32.data(), sizeof(float) * diag32.size(), 0},
     };
     size_t total = 0;
     for (Piece &p : pieces) {
@@ -333,6 +341,9 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
     d.gh = reinterpret_cast<const uint32_t *>(base + pieces[11].off);
     d.gh_shift = T.gh_shift;
     d.qcls = reinterpret_cast<const uint8_t *>(base + pieces[12].off);
+    d.diag_occ = T.diag_occ ? 1 : 0;
+    d.diag = T.diag_occ ? reinterpret_cast<const double *>(base + pieces[13].off) : nullptr;
+    d.diag32 = T.diag_occ ? reinterpret_cast<const float *>(base + pieces[14].off) : nullptr;
     *out = h;
     return NQS_OK;
 }

@@ -35,6 +35,12 @@ struct DevTable {
     const uint32_t *gh;    // group index slots (0xFFFFFFFF = empty)
     uint32_t gh_shift;     // 32 - log2(slots)
     const uint8_t *qcls;   // [128] class of each qubit (filter partitions)
+    // the X = 0 group in occupation form (when its Z strings have at most two
+    // qubits): d[0], d[1 + j], d[1 + nq + j (j - 1) / 2 + i] for i < j; FP64
+    // and FP32 (hi, lo) pairs
+    int diag_occ;
+    const double *diag;
+    const float *diag32;
 };
 
 // ---- flip enumeration: shape of one round

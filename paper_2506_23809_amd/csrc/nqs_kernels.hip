@@ -1847,6 +1847,63 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
                                       smem4);
 }
 
+// <x|H_diag|x> from the occupation form of the X = 0 group: d[0] plus, for
+// each occupied qubit j in increasing order, d[1 + j] and the pair terms
+// d[1 + nq + j (j - 1) / 2 + i] of the occupied i < j (d: FP64 values, or
+// FP32 (hi, lo) pairs in the same 8 bytes for the compensated form).
+template <int W, int P>
+__device__ __forceinline__ double diag_occ_sum(const double *d, int nq, const Key<W> &x) {
+    const double *d2 = d + 1 + nq;
+    if constexpr (P == NQS_FP64) {
+        double acc = d[0];
+#pragma unroll
+        for (int qw = 0; qw < W; ++qw) {
+            uint64_t m = x.w[qw];
+            while (m) {
+                const int j = 64 * qw + __builtin_ctzll(m);
+                m &= m - 1;
+                const double *row = d2 + j * (j - 1) / 2;
+                double t = d[1 + j];
+#pragma unroll
+                for (int qi = 0; qi <= qw; ++qi) {
+                    uint64_t mi = x.w[qi] & (qi < qw ? ~0ull : ((1ull << (j & 63)) - 1ull));
+                    while (mi) {
+                        t += row[64 * qi + __builtin_ctzll(mi)];
+                        mi &= mi - 1;
+                    }
+                }
+                acc += t;
+            }
+        }
+        return acc;
+    } else {
+        const float2 *f = reinterpret_cast<const float2 *>(d);
+        const float2 *f2 = f + 1 + nq;
+        AccF32 a;
+        a.add(f[0].x, f[0].y);
+#pragma unroll
+        for (int qw = 0; qw < W; ++qw) {
+            uint64_t m = x.w[qw];
+            while (m) {
+                const int j = 64 * qw + __builtin_ctzll(m);
+                m &= m - 1;
+                const float2 *row = f2 + j * (j - 1) / 2;
+                a.add(f[1 + j].x, f[1 + j].y);
+#pragma unroll
+                for (int qi = 0; qi <= qw; ++qi) {
+                    uint64_t mi = x.w[qi] & (qi < qw ? ~0ull : ((1ull << (j & 63)) - 1ull));
+                    while (mi) {
+                        const float2 v = row[64 * qi + __builtin_ctzll(mi)];
+                        a.add(v.x, v.y);
+                        mi &= mi - 1;
+                    }
+                }
+            }
+        }
+        return a.value();
+    }
+}
+
 // E_loc(x) = diagonal group sum + sum of the chunk partials in chunk order.
 template <int W, bool DUMP, int P, bool SCV>
 __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch &sc,
@@ -1856,7 +1913,8 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
                                            int32_t *__restrict__ hit_idx,
                                            uint32_t *__restrict__ sign_bits, int64_t sign_words,
                                            int64_t i, const uint64_t *dz = nullptr,
-                                           const double *dc = nullptr, int nd = 0) {
+                                           const double *dc = nullptr, int nd = 0,
+                                           const double *dq = nullptr) {
     unsigned long long n_terms = 0;
     // an enumeration leaves one partial per sample
     if (enum_on && enum_shape(tab, sc, samples, n).B > 0) n_chunks = 1;
@@ -1866,6 +1924,11 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
         if (tab.has_diagonal) {
             if constexpr (SCV) {
                 re = sc_diagonal<W>(tab, x);
+            } else if (dq) {
+                // occupation form (the caller passes it staged or in place);
+                // counted as the X = 0 group's terms it stands for
+                re = diag_occ_sum<W, P>(dq, tab.n_qubits, x);
+                n_terms += static_cast<unsigned long long>(tab.goff[1] - tab.goff[0]);
             } else if (dz) {
                 // the X = 0 group staged in LDS by the caller (same order, same sums)
                 if constexpr (P == NQS_FP64) {
@@ -1939,6 +2002,21 @@ __device__ __forceinline__ int stage_diagonal(const DevTable &tab, uint64_t *dz,
     return nd;
 }
 
+// The occupation form of the diagonal (its 1 + nq + nq (nq - 1) / 2 entries)
+// in LDS when it fits the staging area of the term form, else in place;
+// nullptr when the table has no such form.  Synchronises the block.
+template <int P>
+__device__ __forceinline__ const double *stage_diag_occ(const DevTable &tab, double *buf) {
+    if (!tab.diag_occ) return nullptr;
+    const int nq = tab.n_qubits;
+    const int cnt = 1 + nq + nq * (nq - 1) / 2;
+    const double *src = P == NQS_FP64 ? tab.diag : reinterpret_cast<const double *>(tab.diag32);
+    if (cnt > 3 * kDiagLds) return src;
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) buf[k] = src[k];
+    __syncthreads();
+    return buf;
+}
+
 template <int W, bool DUMP, int P, bool SCV>
 __global__ __launch_bounds__(256) void eloc_finish_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n,
@@ -1946,8 +2024,18 @@ __global__ __launch_bounds__(256) void eloc_finish_kernel(
     uint32_t *__restrict__ sign_bits, int64_t sign_words) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if constexpr (!DUMP && !SCV) {
-        __shared__ uint64_t dz[2 * kDiagLds];
-        __shared__ double dc[kDiagLds];
+        // staging area: the diagonal's Z masks and coefficients, or its
+        // occupation form
+        __shared__ double stage[3 * kDiagLds];
+        const double *dq = stage_diag_occ<P>(tab, stage);
+        if (dq) {
+            finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc,
+                                        hit_idx, sign_bits, sign_words, i, nullptr, nullptr, 0,
+                                        dq);
+            return;
+        }
+        uint64_t *dz = reinterpret_cast<uint64_t *>(stage);
+        double *dc = stage + 2 * kDiagLds;
         const int nd = stage_diagonal<P>(tab, dz, dc);
         if (nd >= 0) {
             finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc,
@@ -2114,16 +2202,19 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(const JobDesc *__rest
                                                  nullptr, nullptr, 0, i);
         return;
     }
-    __shared__ uint64_t dz[2 * kDiagLds];
-    __shared__ double dc[kDiagLds];
-    const int nd = stage_diagonal<P>(J.tab, dz, dc);
+    // the same diagonal evaluation as the single-launch finish kernel
+    __shared__ double stage[3 * kDiagLds];
+    const double *dq = stage_diag_occ<P>(J.tab, stage);
+    uint64_t *dz = reinterpret_cast<uint64_t *>(stage);
+    double *dc = stage + 2 * kDiagLds;
+    const int nd = dq ? -1 : stage_diagonal<P>(J.tab, dz, dc);
     const uint64_t *z = nd >= 0 ? dz : nullptr;
     if ((J.kind & 1) == 0)
         finish_one<1, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc, nullptr,
-                                       nullptr, 0, i, z, dc, nd);
+                                       nullptr, 0, i, z, dc, nd, dq);
     else
         finish_one<2, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc, nullptr,
-                                       nullptr, 0, i, z, dc, nd);
+                                       nullptr, 0, i, z, dc, nd, dq);
 }
 
 size_t batch_lds_bytes(int threads, int max_filter_log2) {

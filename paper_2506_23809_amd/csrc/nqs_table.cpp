@@ -191,6 +191,7 @@ int build_table(int n_qubits, int64_t n_terms, const uint64_t *x, const uint64_t
             std::max(T.max_group_terms, static_cast<int>(T.goff[g + 1] - T.goff[g]));
     }
     build_enum_index(&T);
+    build_diag_occ(&T);
     return NQS_OK;
 }
 
@@ -287,6 +288,34 @@ void build_enum_index(HostTable *T) {
     }
     T->enum_ok = T->sector_filter && T->k_alpha + T->k_beta == T->n_qubits &&
                  T->k_alpha <= 64 && T->k_beta <= 64 && T->max_flip <= 4;
+}
+
+void build_diag_occ(HostTable *T) {
+    T->diag_occ = false;
+    T->diag.clear();
+    if (!T->has_diagonal) return;
+    const int nq = T->n_qubits;
+    std::vector<double> d(1 + nq + static_cast<size_t>(nq) * (nq - 1) / 2, 0.0);
+    for (int64_t t = T->goff[0]; t < T->goff[1]; ++t) {
+        const uint64_t z0 = T->tz[2 * t], z1 = T->tz[2 * t + 1];
+        const double c = T->tc[t];
+        int q[2], w = 0;
+        for (int b = 0; b < 128 && w <= 2; ++b) {
+            if (((b < 64 ? z0 >> b : z1 >> (b - 64)) & 1ull) == 0) continue;
+            if (w < 2) q[w] = b;
+            ++w;
+        }
+        if (w > 2) return;  // a Z string on three or more qubits: keep the term form
+        // c Z_i Z_j = c (1 - 2 n_i)(1 - 2 n_j), c Z_i = c (1 - 2 n_i)
+        d[0] += c;
+        if (w >= 1) d[1 + q[0]] -= 2.0 * c;
+        if (w == 2) {
+            d[1 + q[1]] -= 2.0 * c;
+            d[1 + nq + static_cast<size_t>(q[1]) * (q[1] - 1) / 2 + q[0]] += 4.0 * c;
+        }
+    }
+    T->diag = std::move(d);
+    T->diag_occ = true;
 }
 
 }  // namespace nqs

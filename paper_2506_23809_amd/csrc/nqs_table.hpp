@@ -54,10 +54,18 @@ struct HostTable {
     // linear probing, 0xFFFFFFFF = empty; keys are compared through gx
     std::vector<uint32_t> gh;
     uint32_t gh_shift = 0;
+    // the X = 0 group in occupation form, when all its Z strings have at
+    // most two qubits (Z_i = 1 - 2 n_i):
+    //   <x|H_diag|x> = d[0] + sum_{j occ} (d[1 + j] + sum_{i occ, i < j} d[1 + nq + j (j - 1) / 2 + i])
+    bool diag_occ = false;
+    std::vector<double> diag;
 };
 
 // Fill max_flip, enum_ok, the spin qubit lists and the group index.
 void build_enum_index(HostTable *T);
+
+// Fill diag_occ and diag from the X = 0 group.
+void build_diag_occ(HostTable *T);
 
 // Sector key: half of popc(X & alpha) | half of popc(X & beta) << 8, or
 // kSectorNeverKey when either popcount is odd (the flip always leaves the
