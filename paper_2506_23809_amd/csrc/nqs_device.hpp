@@ -119,7 +119,8 @@ constexpr uint32_t kSectorNever = 0xFFFFu;
 
 // Per-handle scratch for one batch.
 struct DevScratch {
-    void *slots;            // hash slots (layout depends on the word count)
+    uint64_t *skey;         // [capacity][words] sample keys (kFreeKey in the last word: free)
+    int32_t *sidx;          // [capacity] sample index of each claimed slot (-1: free)
     uint32_t *shx;          // [n] linear hash of each sample
     uint32_t *filter;       // [1 << filter_log2 words] Bloom bitmap of sample hashes
     double *part;           // [n_chunks][n][2] partial E_loc per group chunk
@@ -141,23 +142,15 @@ constexpr uint32_t kGoldenMul = 0x9E3779B1u;
 // The sample hash is probed a bucket at a time: a key starts at the first
 // slot of bucket (h * golden) >> slot_shift and takes the first free slot
 // from there on, so the occupied slots of a bucket form a prefix and one
-// bucket load decides most lookups.  Buckets hold 8 one-word slots or 4
-// two-word slots (128 bytes); the table has at least 4 slots per sample.
+// bucket load decides most lookups.  Keys and sample indices are separate
+// arrays: a bucket is 64 bytes of keys (8 one-word or 4 two-word keys), the
+// index is read only on a hit.  The table has at least 4 slots per sample.
 __host__ __device__ constexpr int bucket_log2(int words) { return words == 1 ? 3 : 2; }
 constexpr int kSlotsPerSample = 4;
-
-// Hash slots.  The claim protocol CASes idx from -1 to the sample index and
-// then stores the key; lookups run in a later kernel, so keys are visible.
-struct alignas(16) Slot1 {
-    uint64_t k0;
-    int32_t idx;
-    int32_t pad;
-};
-struct alignas(32) Slot2 {
-    uint64_t k0, k1;
-    int32_t idx;
-    int32_t pad[3];
-};
+// A free slot holds all ones in its key's last word: bit 63 of that word is
+// qubit 63 (one word, at most 63 qubits) or qubit 127 (two words, at most
+// 127 qubits), never set in a sample.
+constexpr uint64_t kFreeKey = ~0ull;
 
 // Launch plan of one evaluation: sample tiles x group chunks.
 struct EvalLaunch {

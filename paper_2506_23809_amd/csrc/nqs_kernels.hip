@@ -86,55 +86,39 @@ __device__ __forceinline__ uint32_t slot_of(uint32_t h, uint32_t shift) {
     return (h * kGoldenMul) >> shift;
 }
 
+// Index of key in the sample hash, or -1.  One bucket is four independent
+// 16-byte loads of keys (one memory latency); the index array is read only
+// for the slot that holds the key.
 template <int W>
-struct SlotT;
-template <>
-struct SlotT<1> {
-    using type = Slot1;
-};
-template <>
-struct SlotT<2> {
-    using type = Slot2;
-};
-
-template <int W>
-__device__ __forceinline__ bool key_eq(const typename SlotT<W>::type &s, const Key<W> &k) {
-    if constexpr (W == 1) {
-        return s.k0 == k.w[0];
-    } else {
-        return s.k0 == k.w[0] && s.k1 == k.w[1];
-    }
-}
-
-// Index of key in the sample hash, or -1.  One slot is one aligned 16- or
-// 32-byte load holding both the key and its index.
-template <int W>
-__device__ __forceinline__ int32_t hash_find(const typename SlotT<W>::type *__restrict__ slots,
-                                             uint32_t mask, uint32_t start, const Key<W> &k) {
+__device__ __forceinline__ int32_t hash_find(const uint64_t *__restrict__ skey,
+                                             const int32_t *__restrict__ sidx, uint32_t mask,
+                                             uint32_t start, const Key<W> &k) {
     constexpr int BK = 1 << bucket_log2(W);
     for (uint32_t probe = 0; probe <= mask; probe += BK) {
-        // the whole bucket in independent loads: one memory latency per bucket
-        const uint4 *p = reinterpret_cast<const uint4 *>(&slots[start]);
-        int32_t found = -1;
+        const uint4 *p = reinterpret_cast<const uint4 *>(skey + static_cast<size_t>(start) * W);
+        const uint4 q[4] = {p[0], p[1], p[2], p[3]};
+        int found = -1;
         bool empty = false;
 #pragma unroll
         for (int s = 0; s < BK; ++s) {
-            int32_t idx;
-            bool eq;
+            bool eq, fr;
             if constexpr (W == 1) {
-                const uint4 a = p[s];
-                idx = static_cast<int32_t>(a.z);
-                eq = ((static_cast<uint64_t>(a.y) << 32) | a.x) == k.w[0];
+                const uint4 &v = q[s >> 1];
+                const uint64_t key = (s & 1) ? ((static_cast<uint64_t>(v.w) << 32) | v.z)
+                                             : ((static_cast<uint64_t>(v.y) << 32) | v.x);
+                eq = key == k.w[0];
+                fr = key == kFreeKey;
             } else {
-                const uint4 a = p[2 * s], b = p[2 * s + 1];
-                idx = static_cast<int32_t>(b.x);
-                eq = ((static_cast<uint64_t>(a.y) << 32) | a.x) == k.w[0] &&
-                     ((static_cast<uint64_t>(a.w) << 32) | a.z) == k.w[1];
+                const uint4 &v = q[s];
+                const uint64_t k0 = (static_cast<uint64_t>(v.y) << 32) | v.x;
+                const uint64_t k1 = (static_cast<uint64_t>(v.w) << 32) | v.z;
+                eq = k0 == k.w[0] && k1 == k.w[1];
+                fr = k1 == kFreeKey;
             }
-            if (idx >= 0 && eq) found = idx;
-            empty = empty || idx < 0;
+            if (eq && found < 0) found = s;
+            empty = empty || fr;
         }
-        if (found >= 0) return found;
+        if (found >= 0) return sidx[(start + static_cast<uint32_t>(found)) & mask];
         if (empty) return -1;
         start = (start + BK) & mask;
     }
@@ -185,13 +169,17 @@ __device__ __forceinline__ uint32_t filter_test(uint32_t fw, uint32_t h) {
 
 // ------------------------------------------------------------------ hash build
 
-// Clears the slot indices (to -1) and the Bloom bitmap (to 0).
-__global__ void hash_clear_kernel(int32_t *__restrict__ idx_words, int stride_words,
-                                  uint32_t capacity, uint32_t *__restrict__ filter,
+// Frees every slot (index -1, key's last word kFreeKey) and clears the
+// Bloom bitmaps.
+__global__ void hash_clear_kernel(uint64_t *__restrict__ skey, int32_t *__restrict__ sidx,
+                                  int words, uint32_t capacity, uint32_t *__restrict__ filter,
                                   uint32_t filter_words, uint32_t *__restrict__ efilter,
                                   uint32_t efilter_words) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < capacity) idx_words[static_cast<size_t>(s) * stride_words] = -1;
+    if (s < capacity) {
+        sidx[s] = -1;
+        skey[static_cast<size_t>(s) * words + words - 1] = kFreeKey;
+    }
     if (s < filter_words) filter[s] = 0u;
     if (s < efilter_words) efilter[s] = 0u;
 }
@@ -203,7 +191,6 @@ template <int W>
 __device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScratch &sc,
                                                const uint64_t *__restrict__ samples,
                                                const int64_t *__restrict__ weights, int64_t i) {
-    using S = typename SlotT<W>::type;
     const uint64_t w0 = samples[2 * i], w1 = samples[2 * i + 1];
     bool bad;
     const int nq = tab.n_qubits;
@@ -248,13 +235,12 @@ __device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScr
         const uint32_t emask = (1u << sc.efilter_log2) - 1u;
         atomicOr(&sc.efilter[(c << sc.efilter_log2) + filter_word(h, emask)], fbits);
     }
-    S *slots = static_cast<S *>(sc.slots);
     uint32_t slot = slot_of(h, sc.slot_shift) << bucket_log2(W);
     for (uint32_t probe = 0; probe <= sc.slot_mask; ++probe) {
-        const int32_t old = atomicCAS(&slots[slot].idx, -1, static_cast<int32_t>(i));
+        const int32_t old = atomicCAS(&sc.sidx[slot], -1, static_cast<int32_t>(i));
         if (old == -1) {
-            slots[slot].k0 = w0;
-            if constexpr (W == 2) slots[slot].k1 = w1;
+            sc.skey[static_cast<size_t>(slot) * W] = w0;
+            if constexpr (W == 2) sc.skey[static_cast<size_t>(slot) * W + 1] = w1;
             return;
         }
         bool same = samples[2 * old] == w0;
@@ -529,7 +515,6 @@ __device__ __forceinline__ void lookup_item(
     int64_t tile, int64_t chunk, int64_t g_first, int64_t chunk_len, bool load_filter,
     int32_t *__restrict__ hit_idx, uint32_t *__restrict__ sign_bits, int64_t sign_words,
     uint4 *smem4) {
-    using S = typename SlotT<W>::type;
     using Rec = StageRec<S32>;
     const int fwords = 1 << sc.filter_log2;
     uint32_t *filt = reinterpret_cast<uint32_t *>(smem4);
@@ -543,7 +528,6 @@ __device__ __forceinline__ void lookup_item(
     const bool active = i < n;
     const int64_t g0 = g_first + chunk * chunk_len;
     const int64_t g1 = min(g0 + chunk_len, tab.n_groups);
-    const S *__restrict__ slots = static_cast<const S *>(sc.slots);
 
     // resident Bloom bitmap
     if (load_filter) {
@@ -597,7 +581,7 @@ __device__ __forceinline__ void lookup_item(
 #pragma unroll
             for (int q = 0; q < W; ++q) xp.w[q] = xl.w[q] ^ tab.gx[2 * g + q];
             const uint32_t h = hxl ^ tab.ghm[2 * g];
-            const int32_t j = hash_find<W>(slots, sc.slot_mask,
+            const int32_t j = hash_find<W>(sc.skey, sc.sidx, sc.slot_mask,
                                            slot_of(h, sc.slot_shift) << bucket_log2(W), xp);
             if constexpr (DUMP) {
                 if (hit_idx) hit_idx[(wave0 + l) * tab.n_groups + g] = j;
@@ -938,7 +922,7 @@ struct EnumHit {
 // left as it is (no hit) otherwise.
 template <int W, bool DUMP, int P, bool SCV>
 __device__ __forceinline__ void enum_candidate(
-    const DevTable &tab, const typename SlotT<W>::type *__restrict__ slots, const DevScratch &sc,
+    const DevTable &tab, const DevScratch &sc,
     const Key<W> &x, uint32_t hx, double la, double ph, int64_t idx, uint2 e,
     const double *__restrict__ log_amp, const double *__restrict__ phase,
     int32_t *__restrict__ hit_idx, uint32_t *__restrict__ sign_bits, int64_t sign_words,
@@ -962,7 +946,7 @@ __device__ __forceinline__ void enum_candidate(
     Key<W> xp;
 #pragma unroll
     for (int q = 0; q < W; ++q) xp.w[q] = x.w[q] ^ X.w[q];
-    const int32_t j = hash_find<W>(slots, sc.slot_mask,
+    const int32_t j = hash_find<W>(sc.skey, sc.sidx, sc.slot_mask,
                                    slot_of(e.y, sc.slot_shift) << bucket_log2(W), xp);
     if (j < 0) return;
     int64_t g = -1;
@@ -1088,7 +1072,6 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
                                            int64_t round, int32_t *__restrict__ hit_idx,
                                            uint32_t *__restrict__ sign_bits, int64_t sign_words,
                                            EnumCounts &cnt, int &loaded_part) {
-    using Sl = typename SlotT<W>::type;
     char *smem = dyn_lds();
     const int lane = threadIdx.x & 63;
     // wave-uniform (scalar) so that unit and row loops run on the scalar unit
@@ -1106,7 +1089,6 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
     EnumMeta *meta = reinterpret_cast<EnumMeta *>(per + 320 * B + kEnumWaves * 16 * B);  // [B]
     uint32_t *lh = reinterpret_cast<uint32_t *>(per + kEnumPerSampleFixed * B);    // [B][L]
     uint16_t *lc = reinterpret_cast<uint16_t *>(per + kEnumPerSampleFixed * B + 4 * L * B);
-    const Sl *__restrict__ slots = static_cast<const Sl *>(sc.slots);
 
     const int64_t s0 = round * B;
     const int nb = static_cast<int>(min(static_cast<int64_t>(B), n - s0));
@@ -1280,7 +1262,7 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             Key<W> x;
             x.w[0] = rec.x0;
             if constexpr (W == 2) x.w[1] = rec.x1;
-            enum_candidate<W, DUMP, P, SCV>(tab, slots, sc, x, rec.hx, rec.la, rec.ph, rec.idx, e,
+            enum_candidate<W, DUMP, P, SCV>(tab, sc, x, rec.hx, rec.la, rec.ph, rec.idx, e,
                                             log_amp, phase, hit_idx, sign_bits, sign_words, cnt,
                                             c);
         }
@@ -1528,7 +1510,6 @@ __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &
                                           int32_t *__restrict__ hit_idx,
                                           uint32_t *__restrict__ sign_bits, int64_t sign_words,
                                           EnumCounts &cnt) {
-    using Sl = typename SlotT<W>::type;
     char *smem = dyn_lds();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1538,7 +1519,6 @@ __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &
     uint8_t *o = reinterpret_cast<uint8_t *>(mine);  // alpha occ, alpha vir, beta occ, beta vir
     uint32_t *lh = reinterpret_cast<uint32_t *>(mine + kEnumSoloLists);
     uint16_t *lc = reinterpret_cast<uint16_t *>(mine + kEnumSoloLists + 4 * S.lcb);
-    const Sl *__restrict__ slots = static_cast<const Sl *>(sc.slots);
     const uint32_t fbytes_mask = ((1u << sc.efilter_log2) - 1u) << 2;
     const char *filt_b = reinterpret_cast<const char *>(filt);
     // this lane's alpha and beta qubit, for the whole loop
@@ -1638,7 +1618,7 @@ __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             EnumHit c;
             if (lane < static_cast<int>(mcount))
-                enum_candidate<W, DUMP, P, SCV>(tab, slots, sc, x, hx, la, ph, i, queue[lane],
+                enum_candidate<W, DUMP, P, SCV>(tab, sc, x, hx, la, ph, i, queue[lane],
                                                 log_amp, phase, hit_idx, sign_bits, sign_words,
                                                 cnt, c);
             uint64_t hm = __ballot(c.hit);
@@ -2072,10 +2052,8 @@ __global__ void batch_clear_kernel(const JobDesc *__restrict__ jobs) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     const int words = (J.kind & 1) + 1;
     if (s < J.capacity) {
-        if (words == 1)
-            static_cast<Slot1 *>(J.sc.slots)[s].idx = -1;
-        else
-            static_cast<Slot2 *>(J.sc.slots)[s].idx = -1;
+        J.sc.sidx[s] = -1;
+        J.sc.skey[static_cast<size_t>(s) * words + words - 1] = kFreeKey;
     }
     if (s < (1u << J.sc.filter_log2)) J.sc.filter[s] = 0u;
     if (J.sc.eparts_log2 > 0 && s < (1u << (J.sc.eparts_log2 + J.sc.efilter_log2)))
@@ -2498,16 +2476,12 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
                        const uint64_t *samples, const int64_t *weights, int64_t n,
                        hipStream_t st) {
     const int words = tab.n_qubits <= 63 ? 1 : 2;
-    const int stride = words == 1 ? sizeof(Slot1) / 4 : sizeof(Slot2) / 4;
-    int32_t *idx0 = reinterpret_cast<int32_t *>(static_cast<char *>(sc.slots) +
-                                                (words == 1 ? offsetof(Slot1, idx)
-                                                            : offsetof(Slot2, idx)));
     const uint32_t fwords = 1u << sc.filter_log2;
     const uint32_t efwords = sc.eparts_log2 > 0 ? (1u << (sc.eparts_log2 + sc.efilter_log2)) : 0u;
     uint32_t span = capacity > fwords ? capacity : fwords;
     span = span > efwords ? span : efwords;
-    hipLaunchKernelGGL(hash_clear_kernel, dim3((span + 255) / 256), dim3(256), 0, st, idx0,
-                       stride, capacity, sc.filter, fwords, sc.efilter, efwords);
+    hipLaunchKernelGGL(hash_clear_kernel, dim3((span + 255) / 256), dim3(256), 0, st, sc.skey,
+                       sc.sidx, words, capacity, sc.filter, fwords, sc.efilter, efwords);
     const dim3 grid(static_cast<unsigned>((n + 255) / 256));
     if (words == 1)
         hipLaunchKernelGGL(hash_build_kernel<1>, grid, dim3(256), 0, st, tab, sc, samples, weights, n);
