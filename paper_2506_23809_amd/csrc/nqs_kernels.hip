@@ -86,43 +86,72 @@ __device__ __forceinline__ uint32_t slot_of(uint32_t h, uint32_t shift) {
     return (h * kGoldenMul) >> shift;
 }
 
-// Index of key in the sample hash, or -1.  One bucket is four independent
-// 16-byte loads of keys (one memory latency); the index array is read only
-// for the slot that holds the key.
+// One bucket of the sample hash: 64 bytes of keys (8 one-word or 4
+// two-word), four independent 16-byte loads.
+struct Bucket {
+    uint4 q0, q1, q2, q3;
+};
+
+template <int W>
+__device__ __forceinline__ Bucket bucket_load(const uint64_t *__restrict__ skey, uint32_t start) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(skey + static_cast<size_t>(start) * W);
+    return Bucket{p[0], p[1], p[2], p[3]};
+}
+
+// First slot of the bucket holding k (or -1), and whether the bucket has a
+// free slot.
+template <int W>
+__device__ __forceinline__ int bucket_scan(const Bucket &b, const Key<W> &k, bool &empty) {
+    constexpr int BK = 1 << bucket_log2(W);
+    int found = -1;
+    empty = false;
+#pragma unroll
+    for (int s = 0; s < BK; ++s) {
+        const uint4 &v = (W == 1 ? s >> 1 : s) == 0 ? b.q0
+                         : (W == 1 ? s >> 1 : s) == 1 ? b.q1
+                         : (W == 1 ? s >> 1 : s) == 2 ? b.q2 : b.q3;
+        bool eq, fr;
+        if constexpr (W == 1) {
+            const uint64_t key = (s & 1) ? ((static_cast<uint64_t>(v.w) << 32) | v.z)
+                                         : ((static_cast<uint64_t>(v.y) << 32) | v.x);
+            eq = key == k.w[0];
+            fr = key == kFreeKey;
+        } else {
+            const uint64_t k0 = (static_cast<uint64_t>(v.y) << 32) | v.x;
+            const uint64_t k1 = (static_cast<uint64_t>(v.w) << 32) | v.z;
+            eq = k0 == k.w[0] && k1 == k.w[1];
+            fr = k1 == kFreeKey;
+        }
+        if (eq && found < 0) found = s;
+        empty = empty || fr;
+    }
+    return found;
+}
+
+// Index of key k in the sample hash, or -1, with the bucket at start already
+// loaded (b); the index array is read only for the slot that holds the key.
+template <int W>
+__device__ __forceinline__ int32_t hash_find_from(const uint64_t *__restrict__ skey,
+                                                  const int32_t *__restrict__ sidx, uint32_t mask,
+                                                  uint32_t start, const Key<W> &k, Bucket b) {
+    constexpr int BK = 1 << bucket_log2(W);
+    for (uint32_t probe = 0; probe <= mask; probe += BK) {
+        bool empty;
+        const int found = bucket_scan<W>(b, k, empty);
+        if (found >= 0) return sidx[(start + static_cast<uint32_t>(found)) & mask];
+        if (empty) return -1;
+        start = (start + BK) & mask;
+        b = bucket_load<W>(skey, start);
+    }
+    return -1;
+}
+
+// Index of key in the sample hash, or -1 (one memory round trip per bucket).
 template <int W>
 __device__ __forceinline__ int32_t hash_find(const uint64_t *__restrict__ skey,
                                              const int32_t *__restrict__ sidx, uint32_t mask,
                                              uint32_t start, const Key<W> &k) {
-    constexpr int BK = 1 << bucket_log2(W);
-    for (uint32_t probe = 0; probe <= mask; probe += BK) {
-        const uint4 *p = reinterpret_cast<const uint4 *>(skey + static_cast<size_t>(start) * W);
-        const uint4 q[4] = {p[0], p[1], p[2], p[3]};
-        int found = -1;
-        bool empty = false;
-#pragma unroll
-        for (int s = 0; s < BK; ++s) {
-            bool eq, fr;
-            if constexpr (W == 1) {
-                const uint4 &v = q[s >> 1];
-                const uint64_t key = (s & 1) ? ((static_cast<uint64_t>(v.w) << 32) | v.z)
-                                             : ((static_cast<uint64_t>(v.y) << 32) | v.x);
-                eq = key == k.w[0];
-                fr = key == kFreeKey;
-            } else {
-                const uint4 &v = q[s];
-                const uint64_t k0 = (static_cast<uint64_t>(v.y) << 32) | v.x;
-                const uint64_t k1 = (static_cast<uint64_t>(v.w) << 32) | v.z;
-                eq = k0 == k.w[0] && k1 == k.w[1];
-                fr = k1 == kFreeKey;
-            }
-            if (eq && found < 0) found = s;
-            empty = empty || fr;
-        }
-        if (found >= 0) return sidx[(start + static_cast<uint32_t>(found)) & mask];
-        if (empty) return -1;
-        start = (start + BK) & mask;
-    }
-    return -1;
+    return hash_find_from<W>(skey, sidx, mask, start, k, bucket_load<W>(skey, start));
 }
 
 __device__ __forceinline__ void latch(int *err, int code) { atomicCAS(err, 0, code); }
@@ -917,13 +946,20 @@ struct EnumHit {
 };
 
 // Candidate e = (flip code, h(x')) of sample x (hash hx, log amplitude la,
-// phase ph, index idx): look x' = x ^ X up in the sample hash and, on a hit,
-// find its group (or evaluate Slater-Condon) and the amplitude ratio; c is
-// left as it is (no hit) otherwise.
+// phase ph, index idx), the first bucket of x' already loaded (b0): look
+// x' = x ^ X up in the sample hash and, on a hit, find its group (or
+// evaluate Slater-Condon) and the amplitude ratio; c is left as it is (no
+// hit) otherwise.
+// The first bucket of a candidate's x' (loaded ahead of its lookup).
+template <int W>
+__device__ __forceinline__ Bucket enum_candidate_bucket(const DevScratch &sc, uint2 e) {
+    return bucket_load<W>(sc.skey, slot_of(e.y, sc.slot_shift) << bucket_log2(W));
+}
+
 template <int W, bool DUMP, int P, bool SCV>
 __device__ __forceinline__ void enum_candidate(
     const DevTable &tab, const DevScratch &sc,
-    const Key<W> &x, uint32_t hx, double la, double ph, int64_t idx, uint2 e,
+    const Key<W> &x, uint32_t hx, double la, double ph, int64_t idx, uint2 e, const Bucket &b0,
     const double *__restrict__ log_amp, const double *__restrict__ phase,
     int32_t *__restrict__ hit_idx, uint32_t *__restrict__ sign_bits, int64_t sign_words,
     EnumCounts &cnt, EnumHit &c) {
@@ -946,8 +982,8 @@ __device__ __forceinline__ void enum_candidate(
     Key<W> xp;
 #pragma unroll
     for (int q = 0; q < W; ++q) xp.w[q] = x.w[q] ^ X.w[q];
-    const int32_t j = hash_find<W>(sc.skey, sc.sidx, sc.slot_mask,
-                                   slot_of(e.y, sc.slot_shift) << bucket_log2(W), xp);
+    const int32_t j = hash_find_from<W>(sc.skey, sc.sidx, sc.slot_mask,
+                                        slot_of(e.y, sc.slot_shift) << bucket_log2(W), xp, b0);
     if (j < 0) return;
     int64_t g = -1;
     if (!SCV || DUMP) g = group_find<W>(tab, e.y ^ hx, X);
@@ -1263,8 +1299,8 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             x.w[0] = rec.x0;
             if constexpr (W == 2) x.w[1] = rec.x1;
             enum_candidate<W, DUMP, P, SCV>(tab, sc, x, rec.hx, rec.la, rec.ph, rec.idx, e,
-                                            log_amp, phase, hit_idx, sign_bits, sign_words, cnt,
-                                            c);
+                                            enum_candidate_bucket<W>(sc, e), log_amp, phase,
+                                            hit_idx, sign_bits, sign_words, cnt, c);
         }
         const bool hit = c.hit;
         const double cre = c.re, cim = c.im;
@@ -1317,15 +1353,22 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
                 sc.efilter + (static_cast<size_t>(p) << sc.efilter_log2));
             uint4 *f4 = reinterpret_cast<uint4 *>(filt);
             const int n4 = (1 << sc.efilter_log2) >> 2;
-            // four 16-byte loads in flight per thread
+            // eight 16-byte loads in flight per thread: a whole 128 KB
+            // partition in one memory round trip
             int k = static_cast<int>(threadIdx.x);
-            for (; k + 3 * kEnumThreads < n4; k += 4 * kEnumThreads) {
+            for (; k + 7 * kEnumThreads < n4; k += 8 * kEnumThreads) {
                 const uint4 a0 = gf[k], a1 = gf[k + kEnumThreads];
                 const uint4 a2 = gf[k + 2 * kEnumThreads], a3 = gf[k + 3 * kEnumThreads];
+                const uint4 a4 = gf[k + 4 * kEnumThreads], a5 = gf[k + 5 * kEnumThreads];
+                const uint4 a6 = gf[k + 6 * kEnumThreads], a7 = gf[k + 7 * kEnumThreads];
                 f4[k] = a0;
                 f4[k + kEnumThreads] = a1;
                 f4[k + 2 * kEnumThreads] = a2;
                 f4[k + 3 * kEnumThreads] = a3;
+                f4[k + 4 * kEnumThreads] = a4;
+                f4[k + 5 * kEnumThreads] = a5;
+                f4[k + 6 * kEnumThreads] = a6;
+                f4[k + 7 * kEnumThreads] = a7;
             }
             for (; k < n4; k += kEnumThreads) f4[k] = gf[k];
             __syncthreads();
@@ -1617,10 +1660,12 @@ __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &
         auto flush = [&](uint32_t mcount) {
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             EnumHit c;
-            if (lane < static_cast<int>(mcount))
-                enum_candidate<W, DUMP, P, SCV>(tab, sc, x, hx, la, ph, i, queue[lane],
-                                                log_amp, phase, hit_idx, sign_bits, sign_words,
-                                                cnt, c);
+            if (lane < static_cast<int>(mcount)) {
+                const uint2 e = queue[lane];
+                enum_candidate<W, DUMP, P, SCV>(tab, sc, x, hx, la, ph, i, e,
+                                                enum_candidate_bucket<W>(sc, e), log_amp, phase,
+                                                hit_idx, sign_bits, sign_words, cnt, c);
+            }
             uint64_t hm = __ballot(c.hit);
             while (hm) {
                 const int q = __builtin_ctzll(hm);
