@@ -234,7 +234,7 @@ struct WorkItem {
 };
 
 constexpr int kEnumVariants = 4;
-constexpr int kStreamCounter = 2 * kEnumVariants;  // after block- and solo-round counters
+constexpr int kStreamCounter = kEnumVariants;  // after the enumeration counters
 constexpr int kBatchCounters = kStreamCounter + 1;
 
 struct BatchShape {
@@ -249,8 +249,8 @@ struct BatchShape {
     int enum_begin[5];
 };
 
-// d_next: kBatchCounters counters (block and solo rounds of each
-// enumeration variant, then the streaming items).
+// d_next: kBatchCounters counters (one per enumeration variant, then the
+// streaming items).
 hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_items, int n_items,
                         unsigned *d_next, const BatchShape &shape, int precision, hipStream_t st);
 size_t batch_lds_bytes(int threads, int max_filter_log2);

@@ -2115,13 +2115,12 @@ __global__ void batch_build_kernel(const JobDesc *__restrict__ jobs) {
         hash_build_one<2>(J.tab, J.sc, J.samples, J.weights, i);
 }
 
-// Enumeration items: rounds tile, tile + stride, ... of one job.  Two
-// persistent kernels per variant (mask words, evaluator) drain the items of
-// that variant, each with its own counter: one runs the jobs whose shape
-// takes block rounds, the other the jobs that take solo rounds (the shape is
-// known on the device only), so that a job is evaluated exactly as a single
+// Enumeration items: rounds tile, tile + stride, ... of one job.  One
+// persistent kernel per variant (mask words, evaluator) drains the items of
+// that variant; each job runs block rounds or solo rounds as its shape
+// decides (the shape is known on the device only), exactly as a single
 // launch would.  They run before the streaming kernel.
-template <int W, int P, bool SCV, bool SOLO>
+template <int W, int P, bool SCV>
 __global__ __launch_bounds__(kEnumThreads) void batch_enum_kernel(
     const JobDesc *__restrict__ jobs, const WorkItem *__restrict__ items, int n_items,
     unsigned *__restrict__ next) {
@@ -2138,20 +2137,21 @@ __global__ __launch_bounds__(kEnumThreads) void batch_enum_kernel(
         const WorkItem w = items[it];
         const JobDesc &J = jobs[w.job];
         const EnumShape S = uniform_shape(enum_shape(J.tab, J.sc, J.samples, J.n));
-        if (S.B <= 0 || (S.solo != 0) != SOLO) continue;  // the streaming items or the other kernel
-        const int64_t n_rounds = (J.n + (SOLO ? kEnumWaves : S.B) - 1) / (SOLO ? kEnumWaves : S.B);
+        if (S.B <= 0) continue;  // the streaming items do this job
+        const int per_round = S.solo ? kEnumWaves : S.B;
+        const int64_t n_rounds = (J.n + per_round - 1) / per_round;
         if (w.tile >= n_rounds) continue;
         if (w.job != last_job) {
             // (with several partitions each round loads the ones it needs)
             if (S.parts == 1) load_filter_lds(J.sc, s_filter);
             load_enum_tables(J.tab);
-            if (SOLO) load_solo_pairs(S);
+            if (S.solo) load_solo_pairs(S);
             loaded_part = -1;
             __syncthreads();
         }
         last_job = w.job;
         EnumCounts cnt;
-        if constexpr (SOLO) {
+        if (S.solo) {
             enum_solo<W, false, P, SCV>(reinterpret_cast<uint32_t *>(s_filter), J.tab, J.sc, S,
                                         J.samples, J.log_amp, J.phase, J.n, w.tile, w.stride,
                                         nullptr, nullptr, 0, cnt);
@@ -2245,15 +2245,14 @@ size_t batch_lds_bytes(int threads, int max_filter_log2) {
 }
 
 namespace {
-// The enumeration kernel of variant v = (words - 1) + 2 * integral form,
-// block rounds or solo rounds.
-template <int P, bool SOLO>
+// The enumeration kernel of variant v = (words - 1) + 2 * integral form.
+template <int P>
 const void *enum_variant(int v) {
     switch (v) {
-        case 0: return reinterpret_cast<const void *>(&batch_enum_kernel<1, P, false, SOLO>);
-        case 1: return reinterpret_cast<const void *>(&batch_enum_kernel<2, P, false, SOLO>);
-        case 2: return reinterpret_cast<const void *>(&batch_enum_kernel<1, NQS_FP64, true, SOLO>);
-        default: return reinterpret_cast<const void *>(&batch_enum_kernel<2, NQS_FP64, true, SOLO>);
+        case 0: return reinterpret_cast<const void *>(&batch_enum_kernel<1, P, false>);
+        case 1: return reinterpret_cast<const void *>(&batch_enum_kernel<2, P, false>);
+        case 2: return reinterpret_cast<const void *>(&batch_enum_kernel<1, NQS_FP64, true>);
+        default: return reinterpret_cast<const void *>(&batch_enum_kernel<2, NQS_FP64, true>);
     }
 }
 }  // namespace
@@ -2268,16 +2267,10 @@ hipError_t prepare_batch_kernels() {
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_lookup_kernel<NQS_FP32_KAHAN>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLookupLds);
     for (int v = 0; v < kEnumVariants && e == hipSuccess; ++v) {
-        e = hipFuncSetAttribute(enum_variant<NQS_FP64, false>(v),
+        e = hipFuncSetAttribute(enum_variant<NQS_FP64>(v),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kEnumDynLds);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(enum_variant<NQS_FP64, true>(v),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, kEnumDynLds);
         if (e == hipSuccess && v < 2)
-            e = hipFuncSetAttribute(enum_variant<NQS_FP32_KAHAN, false>(v),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, kEnumDynLds);
-        if (e == hipSuccess && v < 2)
-            e = hipFuncSetAttribute(enum_variant<NQS_FP32_KAHAN, true>(v),
+            e = hipFuncSetAttribute(enum_variant<NQS_FP32_KAHAN>(v),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, kEnumDynLds);
     }
     if (e == hipSuccess) done = true;
@@ -2299,32 +2292,23 @@ hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_ite
     const hipError_t pe = prepare_batch_kernels();
     if (pe != hipSuccess) return pe;
     // items [enum_begin[v], enum_begin[v + 1]) are the enumeration rounds of
-    // variant v (drained twice: block rounds with counter 2 v, solo rounds
-    // with counter 2 v + 1); the streaming items follow
+    // variant v; the streaming items follow
     const bool f32 = precision == NQS_FP32_KAHAN;
     for (int v = 0; v < kEnumVariants; ++v) {
         const int b0 = shape.enum_begin[v], cnt = shape.enum_begin[v + 1] - b0;
         if (cnt <= 0) continue;
         const WorkItem *it = d_items + b0;
-        for (int solo = 0; solo < 2; ++solo) {
-            unsigned *nx = d_next + 2 * v + solo;
+        unsigned *nx = d_next + v;
 #define NQS_EB(Wd, Pr, SCI)                                                                    \
-    do {                                                                                       \
-        if (solo)                                                                              \
-            hipLaunchKernelGGL((batch_enum_kernel<Wd, Pr, SCI, true>), dim3(shape.enum_blocks), \
-                               dim3(kEnumThreads), kEnumDynLds, st, d_jobs, it, cnt, nx);      \
-        else                                                                                   \
-            hipLaunchKernelGGL((batch_enum_kernel<Wd, Pr, SCI, false>), dim3(shape.enum_blocks), \
-                               dim3(kEnumThreads), kEnumDynLds, st, d_jobs, it, cnt, nx);      \
-    } while (0)
-            switch (v) {
-                case 0: if (f32) NQS_EB(1, NQS_FP32_KAHAN, false); else NQS_EB(1, NQS_FP64, false); break;
-                case 1: if (f32) NQS_EB(2, NQS_FP32_KAHAN, false); else NQS_EB(2, NQS_FP64, false); break;
-                case 2: NQS_EB(1, NQS_FP64, true); break;
-                default: NQS_EB(2, NQS_FP64, true); break;
-            }
-#undef NQS_EB
+    hipLaunchKernelGGL((batch_enum_kernel<Wd, Pr, SCI>), dim3(shape.enum_blocks),               \
+                       dim3(kEnumThreads), kEnumDynLds, st, d_jobs, it, cnt, nx)
+        switch (v) {
+            case 0: if (f32) NQS_EB(1, NQS_FP32_KAHAN, false); else NQS_EB(1, NQS_FP64, false); break;
+            case 1: if (f32) NQS_EB(2, NQS_FP32_KAHAN, false); else NQS_EB(2, NQS_FP64, false); break;
+            case 2: NQS_EB(1, NQS_FP64, true); break;
+            default: NQS_EB(2, NQS_FP64, true); break;
         }
+#undef NQS_EB
     }
     const int ne = shape.enum_begin[kEnumVariants];
     const WorkItem *s_items = d_items + ne;
