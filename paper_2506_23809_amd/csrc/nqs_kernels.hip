@@ -825,6 +825,13 @@ constexpr uint32_t kNoQubit = 0x7Fu;
 constexpr uint32_t kNoPair = kNoQubit | (kNoQubit << 7);
 constexpr int kEnumRowSeg = 64;  // rows per work unit (two 32-row lane masks)
 
+// Row segments of a product of nrow rows: at most 64 rows each, of equal
+// length rounded up to a multiple of 4.
+__device__ __forceinline__ int seg_len(int nrow) {
+    const int ns = (nrow + kEnumRowSeg - 1) / kEnumRowSeg;
+    return ns ? (((nrow + ns - 1) / ns) + 3) & ~3 : 0;
+}
+
 struct alignas(16) EnumSample {
     uint64_t x0, x1;
     double la, ph;
@@ -858,6 +865,7 @@ struct EnumShape {
     int la, lba, lbb;    // list offsets (entries): rows of A at 0, Ba, Bb, then Bb columns
     int lcb;
     int L;               // padded list entries per sample
+    int n_task;          // solo rounds: (product, row segment, column) tasks per sample
     int solo;            // 1: solo rounds (one wave per sample)
 };
 
@@ -887,9 +895,13 @@ __device__ __forceinline__ EnumShape enum_shape(const DevTable &tab, const DevSc
     s.lbb = s.lba + enum_pad4(s.rba);
     s.lcb = s.lbb + enum_pad4(s.rbb);
     s.L = s.lcb + enum_pad4(s.cbb);
-    // solo rounds keep only the row lists (entries [0, lcb)) per wave
+    // solo rounds keep only the row lists (entries [0, lcb)) per wave, then
+    // the block's pair table and task table
+    s.n_task = ceil_div(s.ra, kEnumRowSeg) * s.ca + ceil_div(s.rba, kEnumRowSeg) * s.cba +
+               ceil_div(s.rbb, kEnumRowSeg) * s.cbb;
     s.solo = (s.parts == 1 && tab.k_alpha <= 32 && tab.k_beta <= 32 &&
-              kEnumWaves * enum_solo_bytes(s.lcb) + 2 * kEnumSoloPairs <=
+              kEnumWaves * enum_solo_bytes(s.lcb) + 2 * kEnumSoloPairs +
+                      4 * 64 * ceil_div(s.n_task, 64) <=
                   kEnumDynLds - kEnumDynFixed) ? 1 : 0;
     return s;
 }
@@ -1570,29 +1582,22 @@ __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &
     const int qb_l = inb ? tab.spin_q[64 + lane] : 0;
     const uint16_t *pt = reinterpret_cast<const uint16_t *>(
         smem + kEnumDynFixed + kEnumWaves * enum_solo_bytes(S.lcb));
+    const uint32_t *tasks = reinterpret_cast<const uint32_t *>(pt + kEnumSoloPairs);
     auto pair_lds = [&](int q, int &ii, int &jj) {
         const uint32_t v = pt[q];
         ii = static_cast<int>(v & 0xFFu);
         jj = static_cast<int>(v >> 8);
     };
-    const float inv_va = 1.0f / static_cast<float>(max(S.va, 1));
     const float inv_vb = 1.0f / static_cast<float>(max(S.vb, 1));
     const int E = S.ra + S.rba + S.rbb;
     const int s_ca = S.ca, s_cba = S.cba, s_cbb = S.cbb;
     const int s_ra = S.ra, s_rba = S.rba, s_rbb = S.rbb;
-    const int s_lba = S.lba, s_lbb = S.lbb;
     // per product: row segments of at most 64 rows, of equal length (a
     // multiple of 4), and the tasks (segment, column) they make
     const int ns_a = ceil_div(s_ra, kEnumRowSeg), ns_ba = ceil_div(s_rba, kEnumRowSeg);
-    const int ns_bb = ceil_div(s_rbb, kEnumRowSeg);
-    const int sl_a = ns_a ? (ceil_div(s_ra, ns_a) + 3) & ~3 : 0;
-    const int sl_ba = ns_ba ? (ceil_div(s_rba, ns_ba) + 3) & ~3 : 0;
-    const int sl_bb = ns_bb ? (ceil_div(s_rbb, ns_bb) + 3) & ~3 : 0;
-    const int t_a = ns_a * s_ca, t_ba = ns_ba * s_cba, t_bb = ns_bb * s_cbb;
-    const int n_task = t_a + t_ba + t_bb;
-    const float inv_ca = 1.0f / static_cast<float>(max(s_ca, 1));
-    const float inv_cba = 1.0f / static_cast<float>(max(s_cba, 1));
-    const float inv_cbb = 1.0f / static_cast<float>(max(s_cbb, 1));
+    const int sl_a = seg_len(s_ra), sl_ba = seg_len(s_rba), sl_bb = seg_len(s_rbb);
+    const int t_a = ns_a * s_ca, t_ba = ns_ba * s_cba;
+    const int n_task = S.n_task;
     // every flip but (none, none)
     const unsigned long long n_probe = static_cast<unsigned long long>(s_ra) * s_ca +
                                        static_cast<unsigned long long>(s_rba) * s_cba +
@@ -1688,41 +1693,18 @@ __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &
         // reading its own segment's rows (16-byte aligned)
         cnt.probes += n_probe;
         for (int c0 = 0; c0 < n_task; c0 += 64) {
-            const int t = c0 + lane;
-            const bool act = t < n_task;
-            const int p = t < t_a ? 0 : (t < t_a + t_ba ? 1 : 2);
-            const int u = t - (p == 0 ? 0 : (p == 1 ? t_a : t_a + t_ba));
-            const int ncol = p == 0 ? s_ca : (p == 1 ? s_cba : s_cbb);
-            const float inv = p == 0 ? inv_ca : (p == 1 ? inv_cba : inv_cbb);
-            const int sl = p == 0 ? sl_a : (p == 1 ? sl_ba : sl_bb);
-            const int nrow = p == 0 ? s_ra : (p == 1 ? s_rba : s_rbb);
-            const int row0 = p == 0 ? 0 : (p == 1 ? s_lba : s_lbb);
-            const int seg = div_small(u, inv), k = u - seg * ncol;
-            const int r0 = seg * sl;
-            const int nr = act ? min(nrow - r0, sl) : 0;
-            const int rb = act ? row0 + r0 : 0;
-            // this lane's column: alpha single (or none), alpha virtual pair
-            // or beta virtual pair
+            // this lane's task: rows [rb, rb + nr) of its product's list and
+            // its column (alpha single or none, alpha or beta virtual pair)
+            const uint32_t tv = tasks[c0 + lane];
+            const int rb = static_cast<int>(tv & 0x7FFu);
+            const int nr = static_cast<int>((tv >> 11) & 0x7Fu);
+            const uint32_t ia = (tv >> 18) & kNoQubit, ib = tv >> 25;
+            const bool act = nr > 0;
             uint32_t colh = 0u, colc = kNoPair;
-            if (act) {
-                uint32_t qa = kNoQubit, qb = kNoQubit;
-                if (p == 0) {
-                    if (k > 0) {
-                        const int kk = k - 1, ii = div_small(kk, inv_va);
-                        qa = o[ii];
-                        qb = o[32 + kk - ii * S.va];
-                    }
-                } else {
-                    int ii, jj;
-                    pair_lds(k, ii, jj);
-                    const int base = p == 1 ? 32 : 96;
-                    qa = o[base + ii];
-                    qb = o[base + jj];
-                }
-                if (qa != kNoQubit) {
-                    colh = hr[qa] ^ hr[qb];
-                    colc = qa | (qb << 7);
-                }
+            if (ia != kNoQubit) {
+                const uint32_t qa = o[ia], qb = o[ib];
+                colh = hr[qa] ^ hr[qb];
+                colc = qa | (qb << 7);
             }
             colh ^= hx;
             // rows read by the chunk: the longest segment among its products
@@ -1800,14 +1782,53 @@ __device__ __forceinline__ void load_enum_tables(const DevTable &tab) {
     }
 }
 
-// Pair table of the solo rounds (the caller synchronises before use).
-__device__ __forceinline__ void load_solo_pairs(const EnumShape &S) {
-    uint16_t *pt = reinterpret_cast<uint16_t *>(dyn_lds() + kEnumDynFixed +
-                                                kEnumWaves * enum_solo_bytes(S.lcb));
+// Pair table and task table of the solo rounds (the caller synchronises
+// before use).  Task t of a sample, products and row segments in order:
+// A = (none + alpha singles) columns x (none + beta singles) rows, then Ba,
+// then Bb; its word holds the first row (11 bits, entries of the wave's row
+// lists), the row count (7 bits) and the column's two qubits as indices into
+// the wave's orbital lists (7 bits each, 0x7F: none).  Padding tasks up to
+// a whole chunk have no rows and no qubits.
+__device__ __forceinline__ void load_solo_tables(const EnumShape &S) {
+    char *base = dyn_lds() + kEnumDynFixed + kEnumWaves * enum_solo_bytes(S.lcb);
+    uint16_t *pt = reinterpret_cast<uint16_t *>(base);
     for (int q = threadIdx.x; q < kEnumSoloPairs; q += blockDim.x) {
         int i, j;
         pair_of(q, i, j);
         pt[q] = static_cast<uint16_t>(i | (j << 8));
+    }
+    uint32_t *tt = reinterpret_cast<uint32_t *>(base + 2 * kEnumSoloPairs);
+    const int ns_a = ceil_div(S.ra, kEnumRowSeg), ns_ba = ceil_div(S.rba, kEnumRowSeg);
+    const int t_a = ns_a * S.ca, t_ba = ns_ba * S.cba;
+    const int sl_a = seg_len(S.ra), sl_ba = seg_len(S.rba), sl_bb = seg_len(S.rbb);
+    const int n_pad = 64 * ceil_div(S.n_task, 64);
+    for (int t = threadIdx.x; t < n_pad; t += blockDim.x) {
+        uint32_t rb = 0, nr = 0, ia = kNoQubit, ib = kNoQubit;
+        if (t < S.n_task) {
+            const int p = t < t_a ? 0 : (t < t_a + t_ba ? 1 : 2);
+            const int u = t - (p == 0 ? 0 : (p == 1 ? t_a : t_a + t_ba));
+            const int ncol = p == 0 ? S.ca : (p == 1 ? S.cba : S.cbb);
+            const int sl = p == 0 ? sl_a : (p == 1 ? sl_ba : sl_bb);
+            const int nrow = p == 0 ? S.ra : (p == 1 ? S.rba : S.rbb);
+            const int row0 = p == 0 ? 0 : (p == 1 ? S.lba : S.lbb);
+            const int seg = u / ncol, col = u - seg * ncol;
+            rb = static_cast<uint32_t>(row0 + seg * sl);
+            nr = static_cast<uint32_t>(min(nrow - seg * sl, sl));
+            if (p == 0) {
+                if (col > 0) {
+                    const int kk = col - 1, ii = kk / S.va;
+                    ia = static_cast<uint32_t>(ii);                  // alpha occupied
+                    ib = static_cast<uint32_t>(32 + kk - ii * S.va);  // alpha virtual
+                }
+            } else {
+                int ii, jj;
+                pair_of(col, ii, jj);
+                const int lb = p == 1 ? 32 : 96;                     // alpha / beta virtual
+                ia = static_cast<uint32_t>(lb + ii);
+                ib = static_cast<uint32_t>(lb + jj);
+            }
+        }
+        tt[t] = rb | (nr << 11) | (ia << 18) | (ib << 25);
     }
 }
 
@@ -1832,7 +1853,7 @@ __global__ __launch_bounds__(kEnumThreads) void eloc_enum_kernel(
     const int64_t n_rounds = (n + S.B - 1) / S.B;
     if (S.parts == 1) load_filter_lds(sc, s_filter);  // else each round loads its partitions
     load_enum_tables(tab);
-    if (S.solo) load_solo_pairs(S);
+    if (S.solo) load_solo_tables(S);
     __syncthreads();
     EnumCounts cnt;
     int loaded_part = -1;
@@ -2145,7 +2166,7 @@ __global__ __launch_bounds__(kEnumThreads) void batch_enum_kernel(
             // (with several partitions each round loads the ones it needs)
             if (S.parts == 1) load_filter_lds(J.sc, s_filter);
             load_enum_tables(J.tab);
-            if (S.solo) load_solo_pairs(S);
+            if (S.solo) load_solo_tables(S);
             loaded_part = -1;
             __syncthreads();
         }
