@@ -98,33 +98,40 @@ __device__ __forceinline__ Bucket bucket_load(const uint64_t *__restrict__ skey,
     return Bucket{p[0], p[1], p[2], p[3]};
 }
 
-// First slot of the bucket holding k (or -1), and whether the bucket has a
-// free slot.
+// Slot of the bucket holding k (or -1), and whether the bucket has a free
+// slot.  Occupied slots form a prefix of a bucket (a key takes the first
+// free slot from its start on, and nothing is removed), so the bucket is
+// open iff its last slot is free; a key is stored once, so any slot that
+// matches is the one.  The common case (no match) costs one XOR-OR per key
+// word and a minimum.
+template <int W>
+__device__ __forceinline__ uint32_t slot_diff(const Bucket &b, int s, const Key<W> &k) {
+    // zero iff slot s holds k (s a compile-time constant after unrolling)
+    const uint32_t k0l = static_cast<uint32_t>(k.w[0]), k0h = static_cast<uint32_t>(k.w[0] >> 32);
+    if constexpr (W == 1) {
+        const uint4 &v = (s >> 1) == 0 ? b.q0 : (s >> 1) == 1 ? b.q1 : (s >> 1) == 2 ? b.q2 : b.q3;
+        return (s & 1) ? ((v.z ^ k0l) | (v.w ^ k0h)) : ((v.x ^ k0l) | (v.y ^ k0h));
+    } else {
+        const uint32_t k1l = static_cast<uint32_t>(k.w[1]), k1h = static_cast<uint32_t>(k.w[1] >> 32);
+        const uint4 &v = s == 0 ? b.q0 : s == 1 ? b.q1 : s == 2 ? b.q2 : b.q3;
+        return (v.x ^ k0l) | (v.y ^ k0h) | (v.z ^ k1l) | (v.w ^ k1h);
+    }
+}
+
 template <int W>
 __device__ __forceinline__ int bucket_scan(const Bucket &b, const Key<W> &k, bool &empty) {
     constexpr int BK = 1 << bucket_log2(W);
-    int found = -1;
-    empty = false;
+    // the last slot's key (its last word) is the bucket's last word
+    empty = (b.q3.z & b.q3.w) == 0xFFFFFFFFu;
+    uint32_t m = slot_diff<W>(b, 0, k);
 #pragma unroll
-    for (int s = 0; s < BK; ++s) {
-        const uint4 &v = (W == 1 ? s >> 1 : s) == 0 ? b.q0
-                         : (W == 1 ? s >> 1 : s) == 1 ? b.q1
-                         : (W == 1 ? s >> 1 : s) == 2 ? b.q2 : b.q3;
-        bool eq, fr;
-        if constexpr (W == 1) {
-            const uint64_t key = (s & 1) ? ((static_cast<uint64_t>(v.w) << 32) | v.z)
-                                         : ((static_cast<uint64_t>(v.y) << 32) | v.x);
-            eq = key == k.w[0];
-            fr = key == kFreeKey;
-        } else {
-            const uint64_t k0 = (static_cast<uint64_t>(v.y) << 32) | v.x;
-            const uint64_t k1 = (static_cast<uint64_t>(v.w) << 32) | v.z;
-            eq = k0 == k.w[0] && k1 == k.w[1];
-            fr = k1 == kFreeKey;
-        }
-        if (eq && found < 0) found = s;
-        empty = empty || fr;
-    }
+    for (int s = 1; s < BK; ++s) m = min(m, slot_diff<W>(b, s, k));
+    if (m != 0u) return -1;
+    // a match (rare): which slot
+    int found = 0;
+#pragma unroll
+    for (int s = BK - 1; s > 0; --s)
+        if (slot_diff<W>(b, s, k) == 0u) found = s;
     return found;
 }
 
