@@ -106,9 +106,14 @@ constexpr int kEnumSoloLists = 128;
 __host__ __device__ inline int enum_solo_bytes(int row_entries) {
     return (kEnumSoloLists + 6 * row_entries + 15) & ~15;
 }
-// After the waves' areas: the pair table (i | j << 8 of the k-th pair of a
-// list of up to 32 orbitals), shared by the block.
-constexpr int kEnumSoloPairs = 32 * 31 / 2;
+// After the waves' areas, shared by the block: the entry table (u16 per row
+// list position) and the task table (u32 per lane and chunk).
+__host__ __device__ inline int enum_solo_entry_off(int row_entries) {
+    return kEnumDynFixed + kEnumWaves * enum_solo_bytes(row_entries);
+}
+__host__ __device__ inline int enum_solo_task_off(int row_entries) {
+    return enum_solo_entry_off(row_entries) + ((2 * row_entries + 15) & ~15);
+}
 
 // Sector key of a group: (half popcount of its alpha flips) | (half popcount
 // of its beta flips) << 8.  A flip x -> x ^ X keeps (N_alpha, N_beta) iff

@@ -907,9 +907,7 @@ __device__ __forceinline__ EnumShape enum_shape(const DevTable &tab, const DevSc
     s.n_task = ceil_div(s.ra, kEnumRowSeg) * s.ca + ceil_div(s.rba, kEnumRowSeg) * s.cba +
                ceil_div(s.rbb, kEnumRowSeg) * s.cbb;
     s.solo = (s.parts == 1 && tab.k_alpha <= 32 && tab.k_beta <= 32 &&
-              kEnumWaves * enum_solo_bytes(s.lcb) + 2 * kEnumSoloPairs +
-                      4 * 64 * ceil_div(s.n_task, 64) <=
-                  kEnumDynLds - kEnumDynFixed) ? 1 : 0;
+              enum_solo_task_off(s.lcb) + 4 * 64 * ceil_div(s.n_task, 64) <= kEnumDynLds) ? 1 : 0;
     return s;
 }
 
@@ -1561,7 +1559,7 @@ __device__ __forceinline__ int div_small(int a, float inv) {
 // Bb (hash and flip code) sit in the wave's LDS, columns are computed in
 // registers.  A lane reads its segment's rows; reads past them (up to the
 // chunk's longest segment) stay inside the block's LDS (the next wave's area
-// or the pair table) and are masked off.
+// or the block's tables) and are masked off.
 template <int W, bool DUMP, int P, bool SCV>
 __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &tab,
                                           const DevScratch &sc, const EnumShape &S,
@@ -1587,16 +1585,9 @@ __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &
     const bool ina = lane < tab.k_alpha, inb = lane < tab.k_beta;
     const int qa_l = ina ? tab.spin_q[lane] : 0;
     const int qb_l = inb ? tab.spin_q[64 + lane] : 0;
-    const uint16_t *pt = reinterpret_cast<const uint16_t *>(
-        smem + kEnumDynFixed + kEnumWaves * enum_solo_bytes(S.lcb));
-    const uint32_t *tasks = reinterpret_cast<const uint32_t *>(pt + kEnumSoloPairs);
-    auto pair_lds = [&](int q, int &ii, int &jj) {
-        const uint32_t v = pt[q];
-        ii = static_cast<int>(v & 0xFFu);
-        jj = static_cast<int>(v >> 8);
-    };
-    const float inv_vb = 1.0f / static_cast<float>(max(S.vb, 1));
-    const int E = S.ra + S.rba + S.rbb;
+    const uint16_t *et = reinterpret_cast<const uint16_t *>(smem + enum_solo_entry_off(S.lcb));
+    const uint32_t *tasks = reinterpret_cast<const uint32_t *>(smem + enum_solo_task_off(S.lcb));
+    const int lcb = S.lcb;
     const int s_ca = S.ca, s_cba = S.cba, s_cbb = S.cbb;
     const int s_ra = S.ra, s_rba = S.rba, s_rbb = S.rbb;
     // per product: row segments of at most 64 rows, of equal length (a
@@ -1633,36 +1624,19 @@ __device__ __forceinline__ void enum_solo(const uint32_t *filt, const DevTable &
             if (inb && !ob) o[96 + lanes_below(mvb)] = static_cast<uint8_t>(qb_l);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // row lists (hash, flip code): A rows (the none row, then beta
-        // singles), alpha occupied pairs, beta occupied pairs
-        for (int e0 = 0; e0 < E; e0 += 64) {
-            int e = e0 + lane;
-            if (e >= E) break;
-            uint32_t qa = kNoQubit, qb = kNoQubit;
-            int pos;
-            if (e < S.ra) {
-                pos = e;
-                if (e > 0) {
-                    const int kk = e - 1, ii = div_small(kk, inv_vb);
-                    qa = o[64 + ii];
-                    qb = o[96 + kk - ii * S.vb];
-                }
-            } else if ((e -= S.ra) < S.rba) {
-                int ii, jj;
-                pair_lds(e, ii, jj);
-                qa = o[ii];
-                qb = o[jj];
-                pos = S.lba + e;
-            } else {
-                e -= S.rba;
-                int ii, jj;
-                pair_lds(e, ii, jj);
-                qa = o[64 + ii];
-                qb = o[64 + jj];
-                pos = S.lbb + e;
+        // row lists (hash, flip code) from the entry table: A rows (the none
+        // row, then beta singles), alpha occupied pairs, beta occupied pairs
+        for (int pos = lane; pos < lcb; pos += 64) {
+            const uint32_t v = et[pos];
+            const uint32_t ia = v & kNoQubit, ib = v >> 7;
+            uint32_t h = 0u, c = kNoPair;
+            if (ia != kNoQubit) {
+                const uint32_t qa = o[ia], qb = o[ib];
+                h = hr[qa] ^ hr[qb];
+                c = qa | (qb << 7);
             }
-            lh[pos] = qa == kNoQubit ? 0u : (hr[qa] ^ hr[qb]);
-            lc[pos] = static_cast<uint16_t>(qa | (qb << 7));
+            lh[pos] = h;
+            lc[pos] = static_cast<uint16_t>(c);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
@@ -1789,22 +1763,40 @@ __device__ __forceinline__ void load_enum_tables(const DevTable &tab) {
     }
 }
 
-// Pair table and task table of the solo rounds (the caller synchronises
-// before use).  Task t of a sample, products and row segments in order:
-// A = (none + alpha singles) columns x (none + beta singles) rows, then Ba,
-// then Bb; its word holds the first row (11 bits, entries of the wave's row
-// lists), the row count (7 bits) and the column's two qubits as indices into
-// the wave's orbital lists (7 bits each, 0x7F: none).  Padding tasks up to
-// a whole chunk have no rows and no qubits.
+// Entry table and task table of the solo rounds (the caller synchronises
+// before use).  Entry table: for each position of a wave's row lists, the
+// row's two qubits as indices into the wave's orbital lists (7 bits each,
+// 0x7F: none, also for the padding): A rows (the none row, then beta
+// occupied x beta virtual), alpha occupied pairs, beta occupied pairs.
+// Task t of a sample, products and row segments in order: A = (none + alpha
+// singles) columns x A rows, then Ba, then Bb; its word holds the first row
+// (11 bits), the row count (7 bits) and the column's two qubits as orbital
+// list indices (7 bits each, 0x7F: none).  Padding tasks up to a whole
+// chunk have no rows and no qubits.
 __device__ __forceinline__ void load_solo_tables(const EnumShape &S) {
-    char *base = dyn_lds() + kEnumDynFixed + kEnumWaves * enum_solo_bytes(S.lcb);
-    uint16_t *pt = reinterpret_cast<uint16_t *>(base);
-    for (int q = threadIdx.x; q < kEnumSoloPairs; q += blockDim.x) {
-        int i, j;
-        pair_of(q, i, j);
-        pt[q] = static_cast<uint16_t>(i | (j << 8));
+    uint16_t *et = reinterpret_cast<uint16_t *>(dyn_lds() + enum_solo_entry_off(S.lcb));
+    for (int pos = threadIdx.x; pos < S.lcb; pos += blockDim.x) {
+        uint32_t ia = kNoQubit, ib = kNoQubit;
+        if (pos < S.ra) {
+            if (pos > 0) {
+                const int kk = pos - 1, ii = kk / S.vb;
+                ia = static_cast<uint32_t>(64 + ii);                // beta occupied
+                ib = static_cast<uint32_t>(96 + kk - ii * S.vb);    // beta virtual
+            }
+        } else if (pos >= S.lba && pos < S.lba + S.rba) {
+            int ii, jj;
+            pair_of(pos - S.lba, ii, jj);                           // alpha occupied pair
+            ia = static_cast<uint32_t>(ii);
+            ib = static_cast<uint32_t>(jj);
+        } else if (pos >= S.lbb && pos < S.lbb + S.rbb) {
+            int ii, jj;
+            pair_of(pos - S.lbb, ii, jj);                           // beta occupied pair
+            ia = static_cast<uint32_t>(64 + ii);
+            ib = static_cast<uint32_t>(64 + jj);
+        }
+        et[pos] = static_cast<uint16_t>(ia | (ib << 7));
     }
-    uint32_t *tt = reinterpret_cast<uint32_t *>(base + 2 * kEnumSoloPairs);
+    uint32_t *tt = reinterpret_cast<uint32_t *>(dyn_lds() + enum_solo_task_off(S.lcb));
     const int ns_a = ceil_div(S.ra, kEnumRowSeg), ns_ba = ceil_div(S.rba, kEnumRowSeg);
     const int t_a = ns_a * S.ca, t_ba = ns_ba * S.cba;
     const int sl_a = seg_len(S.ra), sl_ba = seg_len(S.rba), sl_bb = seg_len(S.rbb);
