@@ -1157,6 +1157,7 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
         uint8_t *o = ov + 256 * b;
         EnumMeta &m = meta[b];
         uint32_t cx = 0;
+        int my_no = 0, my_nv = 0;
         {
             const bool in = lane < tab.k_alpha;
             const int q = in ? tab.spin_q[lane] : 0;
@@ -1177,9 +1178,12 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
                 if (occ && c == static_cast<uint32_t>(u)) o[128 + no + lanes_below(mo)] = static_cast<uint8_t>(q);
                 if (in && !occ && c == static_cast<uint32_t>(u))
                     o[192 + nv + lanes_below(mv)] = static_cast<uint8_t>(q);
-                if (lane == 0) {
-                    m.nocc[u] = static_cast<uint8_t>(__popcll(mo));
-                    m.nvir[u] = static_cast<uint8_t>(__popcll(mv));
+                if (lane == u) {
+                    // lane u keeps the class-u counts
+                    my_no = __popcll(mo);
+                    my_nv = __popcll(mv);
+                    m.nocc[u] = static_cast<uint8_t>(my_no);
+                    m.nvir[u] = static_cast<uint8_t>(my_nv);
                 }
                 no += __popcll(mo);
                 nv += __popcll(mv);
@@ -1203,44 +1207,70 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
         }
         if (lane < kEnumWaves) reinterpret_cast<uint4 *>(accb + kEnumWaves * 16 * b)[lane] =
             make_uint4(0u, 0u, 0u, 0u);
-        if (lane == 0) {
-            int oa = 0, obb = 0, oc = 0;
-            for (int t = 0; t < parts; ++t) {
-                m.offa[t] = static_cast<uint16_t>(oa);
-                m.offb[t] = static_cast<uint16_t>(obb);
-                m.offc[t] = static_cast<uint16_t>(oc);
-                int sa = t == 0 ? 1 : 0, sb = 0, sc2 = 0;  // the none row opens bucket 0 of A
-                for (int u = 0; u < parts; ++u) {
-                    const int d = u ^ t;
-                    sa += m.nocc[u] * m.nvir[d];
-                    if (t == 0) {
-                        sb += enum_pairs(m.nocc[u]);
-                        sc2 += enum_pairs(m.nvir[u]);
-                    } else if (u < d) {
-                        sb += m.nocc[u] * m.nocc[d];
-                        sc2 += m.nvir[u] * m.nvir[d];
-                    }
+        // bucket sizes, offsets and work units, one lane per (t, u) pair of
+        // classes: lane 8 t + u
+        {
+            const int gt = lane >> 3, gu = lane & 7;
+            const bool gin = gt < parts && gu < parts;
+            const int gd = (gu ^ gt) & 7;
+            const int no_u = __shfl(my_no, gu), nv_u = __shfl(my_nv, gu);
+            const int no_d = __shfl(my_no, gd), nv_d = __shfl(my_nv, gd);
+            // bucket t of A rows: beta singles u -> u ^ t; of Bb rows / columns:
+            // occupied / virtual pairs of classes (u, u ^ t)
+            int sa = gin ? no_u * nv_d : 0, sb = 0, scc = 0;
+            if (gin) {
+                if (gt == 0) {
+                    sb = enum_pairs(no_u);
+                    scc = enum_pairs(nv_u);
+                } else if (gu < gd) {
+                    sb = no_u * no_d;
+                    scc = nv_u * nv_d;
                 }
-                oa += sa;
-                obb += sb;
-                oc += sc2;
             }
-            m.offa[parts] = static_cast<uint16_t>(oa);
-            m.offb[parts] = static_cast<uint16_t>(obb);
-            m.offc[parts] = static_cast<uint16_t>(oc);
-            // cx: the class of this sample, computed above
-            const int cha = ceil_div(S.ca, 64);
-            const int uba = (S.rba && S.cba) ? ceil_div(S.cba, 64) * ceil_div(S.rba, kEnumRowSeg) : 0;
-            for (int p = 0; p < parts; ++p) {
-                const int t = p ^ static_cast<int>(cx);
-                int u = cha * ceil_div(m.offa[t + 1] - m.offa[t], kEnumRowSeg);
-                if (t == 0) u += uba;
-                for (int v = 0; v < parts; ++v) {
-                    const int nc = m.offc[v + 1] - m.offc[v];
-                    const int nr = m.offb[(t ^ v) + 1] - m.offb[t ^ v];
-                    u += ceil_div(nc, 64) * ceil_div(nr, kEnumRowSeg);
+#pragma unroll
+            for (int off = 1; off < 8; off <<= 1) {
+                sa += __shfl_xor(sa, off);
+                sb += __shfl_xor(sb, off);
+                scc += __shfl_xor(scc, off);
+            }
+            if (gt == 0) sa += 1;  // the none row opens bucket 0 of A
+            // every lane of group t holds the sizes of bucket t; offsets are
+            // the sums over the buckets before t
+            const int sa_u = __shfl(sa, 8 * gu), sb_u = __shfl(sb, 8 * gu), sc_u = __shfl(scc, 8 * gu);
+            int pa = (gu < gt && gu < parts) ? sa_u : 0;
+            int pb = (gu < gt && gu < parts) ? sb_u : 0;
+            int pc = (gu < gt && gu < parts) ? sc_u : 0;
+#pragma unroll
+            for (int off = 1; off < 8; off <<= 1) {
+                pa += __shfl_xor(pa, off);
+                pb += __shfl_xor(pb, off);
+                pc += __shfl_xor(pc, off);
+            }
+            if (gu == 0 && gt < parts) {
+                m.offa[gt] = static_cast<uint16_t>(pa);
+                m.offb[gt] = static_cast<uint16_t>(pb);
+                m.offc[gt] = static_cast<uint16_t>(pc);
+                if (gt == parts - 1) {
+                    m.offa[parts] = static_cast<uint16_t>(pa + sa);
+                    m.offb[parts] = static_cast<uint16_t>(pb + sb);
+                    m.offc[parts] = static_cast<uint16_t>(pc + scc);
                 }
-                m.units[p] = static_cast<uint16_t>(u);
+            }
+            // work units of partition p (lane group p): A rows of bucket t =
+            // p ^ cx against all alpha columns, Ba when t = 0, and Bb column
+            // bucket v against row bucket t ^ v
+            const int t = (gt ^ static_cast<int>(cx)) & 7;
+            const int sc_v = __shfl(scc, 8 * gu), sb_tv = __shfl(sb, 8 * ((t ^ gu) & 7));
+            const int sa_t = __shfl(sa, 8 * t);
+            int un = gin ? ceil_div(sc_v, 64) * ceil_div(sb_tv, kEnumRowSeg) : 0;
+#pragma unroll
+            for (int off = 1; off < 8; off <<= 1) un += __shfl_xor(un, off);
+            if (gu == 0 && gt < parts) {
+                const int cha = ceil_div(S.ca, 64);
+                const int uba =
+                    (S.rba && S.cba) ? ceil_div(S.cba, 64) * ceil_div(S.rba, kEnumRowSeg) : 0;
+                un += cha * ceil_div(sa_t, kEnumRowSeg) + (t == 0 ? uba : 0);
+                m.units[gt] = static_cast<uint16_t>(un);
             }
         }
     }
