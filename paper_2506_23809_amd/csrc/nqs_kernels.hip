@@ -1058,6 +1058,72 @@ __device__ __forceinline__ int sorted_pair_pos(const uint8_t *cnt, const uint16_
     return off[s] + pre + loc;
 }
 
+// Rows [0, m) of rw (m at most 32) against the column hash, in groups of
+// four (rows past m are probed too and left to the caller's mask): bit r of
+// the result is the filter outcome of row r.  Each outcome is funnelled in at
+// bit 31 (one alignbit per row, no masking of the shifted filter word), so
+// the word ends up shifted by 32 less the rows probed.  Rows go two groups
+// of four at a time: eight filter reads in flight per lane.
+template <bool A16>
+__device__ __forceinline__ uint4 row_group(const uint32_t *rw, int r) {
+    if constexpr (A16) {
+        return reinterpret_cast<const uint4 *>(rw)[r >> 2];
+    } else {
+        return make_uint4(rw[r], rw[r + 1], rw[r + 2], rw[r + 3]);
+    }
+}
+
+__device__ __forceinline__ void filter_words(const char *filt_b, uint32_t fbytes_mask,
+                                             const uint32_t h[4], uint32_t fw[4]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        // the filter word of h, as a byte offset
+        fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + (h[v] & fbytes_mask));
+}
+
+__device__ __forceinline__ uint32_t filter_funnel(uint32_t pm, const uint32_t h[4],
+                                                  const uint32_t fw[4]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        pm = __builtin_amdgcn_alignbit((fw[v] >> ((h[v] >> 17) & 31)) &
+                                           (fw[v] >> ((h[v] >> 24) & 31)),
+                                       pm, 1u);
+    return pm;
+}
+
+template <bool A16>
+__device__ __forceinline__ void row_hashes(const uint32_t *rw, int r, uint32_t colh, uint32_t h[4]) {
+    const uint4 q = row_group<A16>(rw, r);
+    h[0] = colh ^ q.x;
+    h[1] = colh ^ q.y;
+    h[2] = colh ^ q.z;
+    h[3] = colh ^ q.w;
+}
+
+template <bool A16>
+__device__ __forceinline__ uint32_t probe_half(const char *filt_b, uint32_t fbytes_mask,
+                                               uint32_t colh, const uint32_t *rw, int m) {
+    uint32_t pm = 0;
+    int r = 0;
+    for (; r + 8 <= m; r += 8) {
+        uint32_t ha[4], hb[4], fa[4], fb[4];
+        row_hashes<A16>(rw, r, colh, ha);
+        row_hashes<A16>(rw, r + 4, colh, hb);
+        filter_words(filt_b, fbytes_mask, ha, fa);
+        filter_words(filt_b, fbytes_mask, hb, fb);
+        pm = filter_funnel(pm, ha, fa);
+        pm = filter_funnel(pm, hb, fb);
+    }
+    for (; r < m; r += 4) {
+        uint32_t ha[4], fa[4];
+        row_hashes<A16>(rw, r, colh, ha);
+        filter_words(filt_b, fbytes_mask, ha, fa);
+        pm = filter_funnel(pm, ha, fa);
+    }
+    // r rows went in (m rounded up to 4)
+    return r > 0 ? pm >> (32 - r) : 0u;
+}
+
 // Filter test of the rows [0, nrl) of a work unit (nrl <= 64, row hashes at
 // rw, this lane's own rows [0, nr)) against this lane's column hash (h(x)
 // and the column's flips folded in): bit r of the result is the outcome of
@@ -1065,44 +1131,12 @@ __device__ __forceinline__ int sorted_pair_pos(const uint8_t *cnt, const uint16_
 // excl drops row 0 (the probe of x itself).  A16: rw is 16-byte aligned
 // (one LDS read per 4 rows).
 template <bool A16>
-__device__ __forceinline__ void rows4(const uint32_t *rw, int r, uint32_t colh, uint32_t h[4]) {
-    if constexpr (A16) {
-        const uint4 q = reinterpret_cast<const uint4 *>(rw)[r >> 2];
-        h[0] = colh ^ q.x;
-        h[1] = colh ^ q.y;
-        h[2] = colh ^ q.z;
-        h[3] = colh ^ q.w;
-    } else {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) h[v] = colh ^ rw[r + v];
-    }
-}
-
-template <bool A16>
 __device__ __forceinline__ uint64_t probe_rows(const char *filt_b, uint32_t fbytes_mask,
                                                uint32_t colh, const uint32_t *rw, int nrl, int nr,
                                                bool act, bool excl) {
     const int m0 = min(nrl, 32);
-    uint32_t pm0 = 0, pm1 = 0;
-    for (int r = 0; r < m0; r += 4) {
-        uint32_t h[4], fw[4];
-        rows4<A16>(rw, r, colh, h);
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            // the filter word of h, as a byte offset
-            fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + (h[v] & fbytes_mask));
-#pragma unroll
-        for (int v = 0; v < 4; ++v) pm0 |= filter_test(fw[v], h[v]) << (r + v);
-    }
-    for (int r = 32; r < nrl; r += 4) {
-        uint32_t h[4], fw[4];
-        rows4<A16>(rw, r, colh, h);
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            fw[v] = *reinterpret_cast<const uint32_t *>(filt_b + (h[v] & fbytes_mask));
-#pragma unroll
-        for (int v = 0; v < 4; ++v) pm1 |= filter_test(fw[v], h[v]) << (r - 32 + v);
-    }
+    const uint32_t pm0 = probe_half<A16>(filt_b, fbytes_mask, colh, rw, m0);
+    const uint32_t pm1 = probe_half<A16>(filt_b, fbytes_mask, colh, rw + 32, nrl - m0);
     const int n0 = min(nr, 32), n1 = nr - n0;
     uint32_t keep0 = n0 >= 32 ? 0xFFFFFFFFu : ((1u << n0) - 1u);
     uint32_t keep1 = n1 >= 32 ? 0xFFFFFFFFu : ((1u << n1) - 1u);
