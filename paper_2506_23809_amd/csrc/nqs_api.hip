@@ -77,11 +77,12 @@ namespace {
 
 nqs::DevScratch scratch_of(nqs_ham h) {
     nqs::DevScratch s{};
-    // keys first, then the slot indices
+    // keys first, then the slot indices, then the slot fingerprints
     s.skey = static_cast<uint64_t *>(h->slots);
     s.sidx = h->slots ? reinterpret_cast<int32_t *>(static_cast<char *>(h->slots) +
                                                     sizeof(uint64_t) * h->words * h->slot_cap)
                       : nullptr;
+    s.sfp = h->slots ? reinterpret_cast<uint32_t *>(s.sidx + h->slot_cap) : nullptr;
     s.shx = h->shx;
     s.part = h->part;
     s.filter = h->filter;
@@ -111,7 +112,8 @@ int ensure_scratch(nqs_ham h, int64_t n, int64_t n_chunks, hipStream_t st,
     uint64_t want = 64;
     while (want < nqs::kSlotsPerSample * static_cast<uint64_t>(n)) want <<= 1;
     if (want > (1ull << 31)) return fail(NQS_E_ARG, "batch too large for the sample hash");
-    const size_t slot_size = sizeof(uint64_t) * h->words + sizeof(int32_t);  // key + index
+    // key + index + fingerprint
+    const size_t slot_size = sizeof(uint64_t) * h->words + sizeof(int32_t) + sizeof(uint32_t);
     const int64_t part_need = 2 * n * (n_chunks > 0 ? n_chunks : 1);
     const bool grow = want > h->slot_cap || n > h->shx_cap || part_need > h->part_cap ||
                       (efilter && !h->efilter);

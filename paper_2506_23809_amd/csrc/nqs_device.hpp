@@ -126,6 +126,7 @@ constexpr uint32_t kSectorNever = 0xFFFFu;
 struct DevScratch {
     uint64_t *skey;         // [capacity][words] sample keys (kFreeKey in the last word: free)
     int32_t *sidx;          // [capacity] sample index of each claimed slot (-1: free)
+    uint32_t *sfp;          // [capacity] fingerprint h(key) | 1 of each claimed slot (0: free)
     uint32_t *shx;          // [n] linear hash of each sample
     uint32_t *filter;       // [1 << filter_log2 words] Bloom bitmap of sample hashes
     double *part;           // [n_chunks][n][2] partial E_loc per group chunk
@@ -150,6 +151,10 @@ constexpr uint32_t kGoldenMul = 0x9E3779B1u;
 // bucket load decides most lookups.  Keys and sample indices are separate
 // arrays: a bucket is 64 bytes of keys (8 one-word or 4 two-word keys), the
 // index is read only on a hit.  The table has at least 4 slots per sample.
+// A third array holds a 4-byte fingerprint per slot, the key's linear hash
+// with bit 0 set (0: free): a lookup whose hash matches no fingerprint of an
+// open bucket is a miss without reading keys (the enumeration's candidates,
+// nearly all misses, decide this from 32 or 16 bytes).
 __host__ __device__ constexpr int bucket_log2(int words) { return words == 1 ? 3 : 2; }
 constexpr int kSlotsPerSample = 4;
 // A free slot holds all ones in its key's last word: bit 63 of that word is

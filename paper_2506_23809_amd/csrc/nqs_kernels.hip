@@ -205,15 +205,17 @@ __device__ __forceinline__ uint32_t filter_test(uint32_t fw, uint32_t h) {
 
 // ------------------------------------------------------------------ hash build
 
-// Frees every slot (index -1, key's last word kFreeKey) and clears the
+// Frees every slot (index -1, fingerprint 0, key's last word kFreeKey) and clears the
 // Bloom bitmaps.
 __global__ void hash_clear_kernel(uint64_t *__restrict__ skey, int32_t *__restrict__ sidx,
+                                  uint32_t *__restrict__ sfp,
                                   int words, uint32_t capacity, uint32_t *__restrict__ filter,
                                   uint32_t filter_words, uint32_t *__restrict__ efilter,
                                   uint32_t efilter_words) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < capacity) {
         sidx[s] = -1;
+        sfp[s] = 0u;
         skey[static_cast<size_t>(s) * words + words - 1] = kFreeKey;
     }
     if (s < filter_words) filter[s] = 0u;
@@ -277,6 +279,7 @@ __device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScr
         if (old == -1) {
             sc.skey[static_cast<size_t>(slot) * W] = w0;
             if constexpr (W == 2) sc.skey[static_cast<size_t>(slot) * W + 1] = w1;
+            sc.sfp[slot] = h | 1u;
             return;
         }
         bool same = samples[2 * old] == w0;
@@ -962,24 +965,54 @@ struct EnumHit {
     float pre = 0.f, ere = 0.f, pim = 0.f, eim = 0.f;
 };
 
-// Candidate e = (flip code, h(x')) of sample x (hash hx, log amplitude la,
-// phase ph, index idx), the first bucket of x' already loaded (b0): look
-// x' = x ^ X up in the sample hash and, on a hit, find its group (or
-// evaluate Slater-Condon) and the amplitude ratio; c is left as it is (no
-// hit) otherwise.
-// The first bucket of a candidate's x' (loaded ahead of its lookup).
+// Fingerprints of one bucket: 8 (one-word keys, a and b) or 4 (two-word
+// keys, a only).  The candidates load those of the first bucket of x' ahead
+// of their lookups.
+struct FpBucket {
+    uint4 a, b;
+};
+
 template <int W>
-__device__ __forceinline__ Bucket enum_candidate_bucket(const DevScratch &sc, uint2 e) {
-    return bucket_load<W>(sc.skey, slot_of(e.y, sc.slot_shift) << bucket_log2(W));
+__device__ __forceinline__ FpBucket enum_candidate_bucket(const DevScratch &sc, uint2 e) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(
+        sc.sfp + (slot_of(e.y, sc.slot_shift) << bucket_log2(W)));
+    FpBucket f;
+    f.a = p[0];
+    if constexpr (W == 1) f.b = p[1];
+    else f.b = make_uint4(0u, 0u, 0u, 0u);
+    return f;
 }
 
+// Whether a key of hash h may sit in the bucket (a fingerprint equals
+// h | 1), and whether the bucket is open (its last slot free): a key that is
+// present sits in its first bucket unless that bucket is full.
+template <int W>
+__device__ __forceinline__ bool fp_settles_miss(const FpBucket &f, uint32_t h) {
+    const uint32_t w = h | 1u;
+    uint32_t d = min(min(f.a.x ^ w, f.a.y ^ w), min(f.a.z ^ w, f.a.w ^ w));
+    uint32_t last = f.a.w;
+    if constexpr (W == 1) {
+        d = min(d, min(min(f.b.x ^ w, f.b.y ^ w), min(f.b.z ^ w, f.b.w ^ w)));
+        last = f.b.w;
+    }
+    return d != 0u && last == 0u;
+}
+
+// Candidate e = (flip code, h(x')) of sample x (hash hx, log amplitude la,
+// phase ph, index idx), the fingerprints of the first bucket of x' already
+// loaded (f0): look x' = x ^ X up in the sample hash and, on a hit, find its
+// group (or evaluate Slater-Condon) and the amplitude ratio; c is left as it
+// is (no hit) otherwise.
 template <int W, bool DUMP, int P, bool SCV>
 __device__ __forceinline__ void enum_candidate(
     const DevTable &tab, const DevScratch &sc,
-    const Key<W> &x, uint32_t hx, double la, double ph, int64_t idx, uint2 e, const Bucket &b0,
+    const Key<W> &x, uint32_t hx, double la, double ph, int64_t idx, uint2 e, const FpBucket &f0,
     const double *__restrict__ log_amp, const double *__restrict__ phase,
     int32_t *__restrict__ hit_idx, uint32_t *__restrict__ sign_bits, int64_t sign_words,
     EnumCounts &cnt, EnumHit &c) {
+    // nearly every candidate is a filter false positive: its fingerprints
+    // settle it before the flips are decoded or any key is read
+    if (fp_settles_miss<W>(f0, e.y)) return;
     Key<W> X;
 #pragma unroll
     for (int q = 0; q < W; ++q) X.w[q] = 0;
@@ -999,8 +1032,8 @@ __device__ __forceinline__ void enum_candidate(
     Key<W> xp;
 #pragma unroll
     for (int q = 0; q < W; ++q) xp.w[q] = x.w[q] ^ X.w[q];
-    const int32_t j = hash_find_from<W>(sc.skey, sc.sidx, sc.slot_mask,
-                                        slot_of(e.y, sc.slot_shift) << bucket_log2(W), xp, b0);
+    const int32_t j = hash_find<W>(sc.skey, sc.sidx, sc.slot_mask,
+                                   slot_of(e.y, sc.slot_shift) << bucket_log2(W), xp);
     if (j < 0) return;
     int64_t g = -1;
     if (!SCV || DUMP) g = group_find<W>(tab, e.y ^ hx, X);
@@ -2182,6 +2215,7 @@ __global__ void batch_clear_kernel(const JobDesc *__restrict__ jobs) {
     const int words = (J.kind & 1) + 1;
     if (s < J.capacity) {
         J.sc.sidx[s] = -1;
+        J.sc.sfp[s] = 0u;
         J.sc.skey[static_cast<size_t>(s) * words + words - 1] = kFreeKey;
     }
     if (s < (1u << J.sc.filter_log2)) J.sc.filter[s] = 0u;
@@ -2594,7 +2628,7 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
     uint32_t span = capacity > fwords ? capacity : fwords;
     span = span > efwords ? span : efwords;
     hipLaunchKernelGGL(hash_clear_kernel, dim3((span + 255) / 256), dim3(256), 0, st, sc.skey,
-                       sc.sidx, words, capacity, sc.filter, fwords, sc.efilter, efwords);
+                       sc.sidx, sc.sfp, words, capacity, sc.filter, fwords, sc.efilter, efwords);
     const dim3 grid(static_cast<unsigned>((n + 255) / 256));
     if (words == 1)
         hipLaunchKernelGGL(hash_build_kernel<1>, grid, dim3(256), 0, st, tab, sc, samples, weights, n);
