@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -71,6 +72,14 @@ struct nqs_ham_s {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // launch tuning (all-zero = built-in plan)
     nqs::Tuning tune{0, 0, 0, 0};
+    // replay of a repeated evaluation: the launch sequence of the last call,
+    // captured on a private stream once the same arguments come twice in a
+    // row, and launched as one graph while they keep coming
+    bool graphs = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t eval_exec = nullptr;
+    bool have_key = false;
+    unsigned char eval_key[256] = {};
 };
 
 namespace {
@@ -153,6 +162,63 @@ int ensure_scratch(nqs_ham h, int64_t n, int64_t n_chunks, hipStream_t st,
 
 bool valid_handle(nqs_ham h) { return h && h->table_mem && h->small; }
 
+// Everything the launches of one evaluation depend on besides the table.
+struct EvalKey {
+    int64_t n;
+    const void *samples, *weights, *log_amp, *phase, *eloc;
+    int precision;
+    int profiling;
+    int strategy;
+    unsigned enum_blocks;
+    int64_t n_chunks, chunk_len, g_first;
+    int threads, filter_log2;
+    size_t lds_bytes;
+    int eparts_log2, efilter_log2;
+    const void *slots, *shx, *part, *filter, *efilter, *small;
+    uint32_t slot_cap;
+};
+static_assert(sizeof(EvalKey) <= sizeof(nqs_ham_s::eval_key), "key fits");
+
+// The launches of one evaluation on stream s.
+hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunch &L, int64_t n,
+                      const uint64_t *samples, const int64_t *weights, const double *log_amp,
+                      const double *phase, double *eloc, int precision, int32_t *hit_idx,
+                      uint32_t *sign_bits, hipStream_t s) {
+    hipError_t e;
+    if ((e = nqs::launch_reset(sc, s)) != hipSuccess) return e;
+    if (h->profiling && (e = hipEventRecord(h->ev[0], s)) != hipSuccess) return e;
+    if ((e = nqs::launch_hash(h->dt, sc, h->slot_cap, samples, weights, n, s)) != hipSuccess)
+        return e;
+    if (h->profiling && (e = hipEventRecord(h->ev[1], s)) != hipSuccess) return e;
+    const int64_t sign_words = (h->dt.n_terms + 31) / 32;
+    nqs::EvalStageEvents stages{h->profiling ? h->ev[2] : nullptr};
+    if ((e = nqs::launch_eloc(h->dt, sc, L, samples, log_amp, phase, eloc, precision, hit_idx,
+                              sign_bits, sign_words, stages, s)) != hipSuccess)
+        return e;
+    if (h->profiling && (e = hipEventRecord(h->ev[3], s)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// Capture the launches of one evaluation into a graph (on the handle's own
+// stream: the caller's may be the null stream, which cannot be captured).
+hipError_t capture_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunch &L, int64_t n,
+                        const uint64_t *samples, const int64_t *weights, const double *log_amp,
+                        const double *phase, double *eloc, int precision, hipGraphExec_t *out) {
+    hipError_t e = hipSuccess;
+    if (!h->cap_stream) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t e1 = issue_eval(h, sc, L, n, samples, weights, log_amp, phase, eloc,
+                                     precision, nullptr, nullptr, h->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+    e = e1 != hipSuccess ? e1 : e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
 int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weights,
               const double *log_amp, const double *phase, double *eloc, int precision,
               int32_t *hit_idx, uint32_t *sign_bits, void *stream) {
@@ -173,18 +239,67 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
     if (rc) return rc;
     nqs::DevScratch sc = scratch_of(h);
     set_filters(&sc, h, L);
-    NQS_HIP(nqs::launch_reset(sc, st));
-    if (h->profiling) NQS_HIP(hipEventRecord(h->ev[0], st));
-    NQS_HIP(nqs::launch_hash(h->dt, sc, h->slot_cap, samples, weights, n, st));
-    if (h->profiling) NQS_HIP(hipEventRecord(h->ev[1], st));
-    const int64_t sign_words = (h->dt.n_terms + 31) / 32;
-    nqs::EvalStageEvents stages{h->profiling ? h->ev[2] : nullptr};
-    NQS_HIP(nqs::launch_eloc(h->dt, sc, L, samples, log_amp, phase, eloc, precision, hit_idx,
-                             sign_bits, sign_words, stages, st));
-    if (h->profiling) {
-        NQS_HIP(hipEventRecord(h->ev[3], st));
-        h->profiled = true;
+    bool done = false;
+    if (h->graphs && !dump) {
+        EvalKey key;
+        std::memset(&key, 0, sizeof key);
+        key.n = n;
+        key.samples = samples;
+        key.weights = weights;
+        key.log_amp = log_amp;
+        key.phase = phase;
+        key.eloc = eloc;
+        key.precision = precision;
+        key.profiling = h->profiling ? 1 : 0;
+        key.strategy = L.strategy;
+        key.enum_blocks = L.enum_blocks;
+        key.n_chunks = L.n_chunks;
+        key.chunk_len = L.chunk_len;
+        key.g_first = L.g_first;
+        key.threads = L.threads;
+        key.filter_log2 = L.filter_log2;
+        key.lds_bytes = L.lds_bytes;
+        key.eparts_log2 = L.eparts_log2;
+        key.efilter_log2 = L.efilter_log2;
+        key.slots = h->slots;
+        key.shx = h->shx;
+        key.part = h->part;
+        key.filter = h->filter;
+        key.efilter = h->efilter;
+        key.small = h->small;
+        key.slot_cap = h->slot_cap;
+        const bool same = h->have_key && std::memcmp(h->eval_key, &key, sizeof key) == 0;
+        if (!same) {
+            // a new argument set: run it eagerly, remember it
+            if (h->eval_exec) {
+                (void)hipGraphExecDestroy(h->eval_exec);
+                h->eval_exec = nullptr;
+            }
+            std::memcpy(h->eval_key, &key, sizeof key);
+            h->have_key = true;
+        } else {
+            if (!h->eval_exec) {
+                hipGraphExec_t ex = nullptr;
+                if (capture_eval(h, sc, L, n, samples, weights, log_amp, phase, eloc, precision,
+                                 &ex) == hipSuccess) {
+                    h->eval_exec = ex;
+                } else {
+                    // graphs unavailable: stay eager from now on
+                    (void)hipGetLastError();
+                    if (ex) (void)hipGraphExecDestroy(ex);
+                    h->graphs = false;
+                }
+            }
+            if (h->eval_exec) {
+                NQS_HIP(hipGraphLaunch(h->eval_exec, st));
+                done = true;
+            }
+        }
     }
+    if (!done)
+        NQS_HIP(issue_eval(h, sc, L, n, samples, weights, log_amp, phase, eloc, precision, hit_idx,
+                           sign_bits, st));
+    if (h->profiling) h->profiled = true;
     h->last_pairs = n * h->dt.n_groups;
     h->ever_evaluated = true;
     return NQS_OK;
@@ -284,6 +399,8 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
     }
     nqs_ham h = new (std::nothrow) nqs_ham_s();
     if (!h) return fail(NQS_E_NOMEM, "host allocation failed");
+    // NQS_EVAL_GRAPHS=0 keeps every evaluation eager
+    if (const char *g = std::getenv("NQS_EVAL_GRAPHS")) h->graphs = std::strcmp(g, "0") != 0;
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {
         delete h;
@@ -451,6 +568,8 @@ int nqs_ham_destroy(nqs_ham h) {
     if (h->part) (void)hipFree(h->part);
     for (hipEvent_t e : h->ev)
         if (e) (void)hipEventDestroy(e);
+    if (h->eval_exec) (void)hipGraphExecDestroy(h->eval_exec);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
     return rc;
 }
