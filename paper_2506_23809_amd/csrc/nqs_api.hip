@@ -167,7 +167,6 @@ struct EvalKey {
     int64_t n;
     const void *samples, *weights, *log_amp, *phase, *eloc;
     int precision;
-    int profiling;
     int strategy;
     unsigned enum_blocks;
     int64_t n_chunks, chunk_len, g_first;
@@ -201,6 +200,7 @@ hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunc
 
 // Capture the launches of one evaluation into a graph (on the handle's own
 // stream: the caller's may be the null stream, which cannot be captured).
+// Never with profiling on (its events are recorded eagerly).
 hipError_t capture_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunch &L, int64_t n,
                         const uint64_t *samples, const int64_t *weights, const double *log_amp,
                         const double *phase, double *eloc, int precision, hipGraphExec_t *out) {
@@ -240,7 +240,8 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
     nqs::DevScratch sc = scratch_of(h);
     set_filters(&sc, h, L);
     bool done = false;
-    if (h->graphs && !dump) {
+    // profiling stays eager: its events time each kernel of every call
+    if (h->graphs && !dump && !h->profiling) {
         EvalKey key;
         std::memset(&key, 0, sizeof key);
         key.n = n;
@@ -250,7 +251,6 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
         key.phase = phase;
         key.eloc = eloc;
         key.precision = precision;
-        key.profiling = h->profiling ? 1 : 0;
         key.strategy = L.strategy;
         key.enum_blocks = L.enum_blocks;
         key.n_chunks = L.n_chunks;
