@@ -62,6 +62,10 @@ struct nqs_ham_s {
     int64_t part_cap = 0;  // doubles
     uint32_t *filter = nullptr;  // Bloom bitmap, kMaxFilterWords words
     uint32_t *efilter = nullptr; // enumeration filter partitions (allocated when first needed)
+    // the enumeration blocks' areas of device scratch (one per CU)
+    char *eblk = nullptr;
+    int64_t eblk_stride = 0;
+    uint32_t eblk_blocks = 0;
     void *small = nullptr; // counters[8] u64, err, mixed
     int64_t last_pairs = 0;
     bool ever_evaluated = false;
@@ -95,6 +99,9 @@ nqs::DevScratch scratch_of(nqs_ham h) {
     s.shx = h->shx;
     s.part = h->part;
     s.filter = h->filter;
+    s.eblk = h->eblk;
+    s.eblk_stride = h->eblk_stride;
+    s.eblk_blocks = h->eblk_blocks;
     s.counters = static_cast<unsigned long long *>(h->small);
     s.err = reinterpret_cast<int *>(static_cast<char *>(h->small) + kErrOffset);
     s.mixed = reinterpret_cast<int *>(static_cast<char *>(h->small) + kErrOffset + 4);
@@ -116,6 +123,17 @@ void set_filters(nqs::DevScratch *s, nqs_ham h, const nqs::EvalLaunch &L) {
 
 // Grow the per-handle scratch to hold a batch of n samples (and the
 // partitioned enumeration filter when the plan uses it).
+// Bytes of one enumeration block's area for this table: the most any
+// occupation of its spin orbitals needs.
+int64_t enum_blk_stride(const nqs::DevTable &t) {
+    if (!t.enum_ok) return 0;
+    int64_t m = 0;
+    for (int na = 0; na <= t.k_alpha; ++na)
+        for (int nb = 0; nb <= t.k_beta; ++nb)
+            m = std::max(m, nqs::enum_blk_bytes(t.k_alpha, t.k_beta, na, nb));
+    return (m + 255) & ~static_cast<int64_t>(255);
+}
+
 int ensure_scratch(nqs_ham h, int64_t n, int64_t n_chunks, hipStream_t st,
                    bool efilter = false) {
     uint64_t want = 64;
@@ -124,10 +142,29 @@ int ensure_scratch(nqs_ham h, int64_t n, int64_t n_chunks, hipStream_t st,
     // key + index + fingerprint
     const size_t slot_size = sizeof(uint64_t) * h->words + sizeof(int32_t) + sizeof(uint32_t);
     const int64_t part_need = 2 * n * (n_chunks > 0 ? n_chunks : 1);
+    // the block areas: allocated once, one per CU of the handle's device
+    int n_cu = 0;
+    int64_t blk_stride = 0;
+    if (!h->eblk && h->dt.enum_ok) {
+        NQS_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device));
+        blk_stride = enum_blk_stride(h->dt);
+    }
+    const bool blk_grow = blk_stride > 0 && n_cu > 0;
     const bool grow = want > h->slot_cap || n > h->shx_cap || part_need > h->part_cap ||
-                      (efilter && !h->efilter);
+                      (efilter && !h->efilter) || blk_grow;
     if (grow) {
         NQS_HIP(hipStreamSynchronize(st));
+        if (blk_grow) {
+            if (h->eblk) NQS_HIP(hipFree(h->eblk));
+            h->eblk = nullptr;
+            h->eblk_blocks = 0;
+            if (hipMalloc(&h->eblk, blk_stride * n_cu) != hipSuccess) {
+                h->eblk = nullptr;
+                return fail(NQS_E_NOMEM, "device allocation of the enumeration block areas failed");
+            }
+            h->eblk_stride = blk_stride;
+            h->eblk_blocks = static_cast<uint32_t>(n_cu);
+        }
         if (efilter && !h->efilter) {
             if (hipMalloc(&h->efilter, kMaxEFilterWords * 4) != hipSuccess) {
                 h->efilter = nullptr;
@@ -173,7 +210,7 @@ struct EvalKey {
     int threads, filter_log2;
     size_t lds_bytes;
     int eparts_log2, efilter_log2;
-    const void *slots, *shx, *part, *filter, *efilter, *small;
+    const void *slots, *shx, *part, *filter, *efilter, *small, *eblk;
     uint32_t slot_cap;
 };
 static_assert(sizeof(EvalKey) <= sizeof(nqs_ham_s::eval_key), "key fits");
@@ -267,6 +304,7 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
         key.filter = h->filter;
         key.efilter = h->efilter;
         key.small = h->small;
+        key.eblk = h->eblk;
         key.slot_cap = h->slot_cap;
         const bool same = h->have_key && std::memcmp(h->eval_key, &key, sizeof key) == 0;
         if (!same) {
@@ -551,7 +589,8 @@ int nqs_ham_info(nqs_ham h, int64_t *n_groups, int64_t *n_terms, int64_t *device
         *device_bytes = h->table_bytes + static_cast<int64_t>(h->slot_bytes) +
                         h->shx_cap * 4 + h->part_cap * 8 + kSmallBytes +
                         static_cast<int64_t>(kMaxFilterWords * 4) +
-                        (h->efilter ? static_cast<int64_t>(kMaxEFilterWords * 4) : 0);
+                        (h->efilter ? static_cast<int64_t>(kMaxEFilterWords * 4) : 0) +
+                        h->eblk_stride * h->eblk_blocks;
     return NQS_OK;
 }
 
@@ -563,6 +602,7 @@ int nqs_ham_destroy(nqs_ham h) {
     if (h->small) (void)hipFree(h->small);
     if (h->filter) (void)hipFree(h->filter);
     if (h->efilter) (void)hipFree(h->efilter);
+    if (h->eblk) (void)hipFree(h->eblk);
     if (h->slots) (void)hipFree(h->slots);
     if (h->shx) (void)hipFree(h->shx);
     if (h->part) (void)hipFree(h->part);
@@ -1008,7 +1048,8 @@ int64_t table_bytes(nqs_ham h) { return h->table_bytes; }
 int64_t scratch_bytes(nqs_ham h) {
     return static_cast<int64_t>(h->slot_bytes) + h->shx_cap * 4 + h->part_cap * 8 +
            static_cast<int64_t>(kSmallBytes + kMaxFilterWords * 4) +
-           (h->efilter ? static_cast<int64_t>(kMaxEFilterWords * 4) : 0);
+           (h->efilter ? static_cast<int64_t>(kMaxEFilterWords * 4) : 0) +
+           h->eblk_stride * h->eblk_blocks;
 }
 
 int reserve(nqs_ham h, int64_t n, int threads, hipStream_t st) {

@@ -48,13 +48,16 @@ struct DevTable {
 // A block evaluates B samples per round.  Per sample it keeps in LDS a
 // 64-byte record, its occupied/virtual qubit lists (4 x 64 bytes), one
 // accumulator per wave (16 x 16 bytes), 128 bytes of bucket counts and
-// offsets, and four lists of (hash u32, code u16) entries, each padded to a
-// multiple of 4 entries:
+// offsets, and the row hashes (u32) of three lists, each padded to a multiple
+// of 4 entries:
 //   rows of A  = beta singles + none      (sorted by class)
 //   rows of Ba = alpha occupied pairs
 //   rows of Bb = beta occupied pairs      (sorted by class)
+// and, in the block's area of device scratch, the flip codes (u16) of those
+// rows and of the fourth list, whose hashes (u32) sit there too:
 //   cols of Bb = beta virtual pairs       (sorted by class)
-// for the products
+// (a column is read once per work unit, a row code only for a candidate its
+// fingerprints do not settle).  The products are
 //   A  = (beta singles + none) x (alpha singles + none), without (none, none)
 //   Ba = alpha occupied pairs x alpha virtual pairs
 //   Bb = beta occupied pairs x beta virtual pairs
@@ -83,17 +86,36 @@ constexpr int kEnumPerSampleFixed = 64 + 256 + kEnumWaves * 16 + 128;
 __host__ __device__ inline int enum_pairs(int m) { return m * (m - 1) / 2; }
 __host__ __device__ inline int enum_pad4(int m) { return (m + 3) & ~3; }
 
-// List entries per sample (padded): rows of A, Ba, Bb and columns of Bb.
-__host__ __device__ inline int enum_list_entries(int ka, int kb, int na, int nb) {
-    return enum_pad4(1 + nb * (kb - nb)) + enum_pad4(enum_pairs(na)) + enum_pad4(enum_pairs(nb)) +
-           enum_pad4(enum_pairs(kb - nb));
+// Row entries per sample (padded): rows of A, Ba and Bb.
+__host__ __device__ inline int enum_row_entries(int ka, int kb, int na, int nb) {
+    (void)ka;
+    return enum_pad4(1 + nb * (kb - nb)) + enum_pad4(enum_pairs(na)) + enum_pad4(enum_pairs(nb));
 }
 
-// Samples per round for the given occupation, 0 if one does not fit.
+// List entries per sample (padded): rows of A, Ba, Bb and columns of Bb.
+__host__ __device__ inline int enum_list_entries(int ka, int kb, int na, int nb) {
+    return enum_row_entries(ka, kb, na, nb) + enum_pad4(enum_pairs(kb - nb));
+}
+
+// Samples per round for the given occupation, 0 if one does not fit (16
+// bytes stay free after the last sample: rows are read up to 3 entries past
+// a list's end).
 __host__ __device__ inline int enum_round_size(int ka, int kb, int na, int nb) {
-    const int per = kEnumPerSampleFixed + 6 * enum_list_entries(ka, kb, na, nb);
-    const int b = (kEnumDynLds - kEnumDynFixed) / per;
+    const int per = kEnumPerSampleFixed + 4 * enum_row_entries(ka, kb, na, nb);
+    const int b = (kEnumDynLds - kEnumDynFixed - 16) / per;
     return b < kEnumMaxB ? b : kEnumMaxB;
+}
+
+// Device scratch of one block in its rounds: B x L flip codes (u16), then,
+// 16-byte aligned, B x (Bb columns) hashes (u32).
+__host__ __device__ inline int64_t enum_blk_codes_bytes(int B, int L) {
+    return (2 * static_cast<int64_t>(B) * L + 15) & ~static_cast<int64_t>(15);
+}
+__host__ __device__ inline int64_t enum_blk_bytes(int ka, int kb, int na, int nb) {
+    const int B = enum_round_size(ka, kb, na, nb);
+    if (B <= 0) return 0;
+    return enum_blk_codes_bytes(B, enum_list_entries(ka, kb, na, nb)) +
+           4 * static_cast<int64_t>(B) * enum_pad4(enum_pairs(kb - nb));
 }
 
 // Solo rounds, for occupations whose lists are small (at most 32 qubits per
@@ -141,6 +163,11 @@ struct DevScratch {
     uint32_t *efilter;
     int eparts_log2;
     int efilter_log2;
+    // the enumeration blocks' areas (codes and Bb columns of their rounds):
+    // eblk_blocks areas of eblk_stride bytes
+    char *eblk;
+    int64_t eblk_stride;
+    uint32_t eblk_blocks;
 };
 
 constexpr uint32_t kGoldenMul = 0x9E3779B1u;

@@ -1207,12 +1207,22 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
     uint8_t *ov = reinterpret_cast<uint8_t *>(per + 64 * B);                      // [B][256]
     char *accb = per + 320 * B;                                                    // [B][16][16 B]
     EnumMeta *meta = reinterpret_cast<EnumMeta *>(per + 320 * B + kEnumWaves * 16 * B);  // [B]
-    uint32_t *lh = reinterpret_cast<uint32_t *>(per + kEnumPerSampleFixed * B);    // [B][L]
-    uint16_t *lc = reinterpret_cast<uint16_t *>(per + kEnumPerSampleFixed * B + 4 * L * B);
+    // row hashes in LDS [B][Lr]; in the block's device area the flip codes
+    // of all four lists [B][L] and the Bb column hashes [B][Lc]
+    const int Lr = S.lcb, Lc = L - S.lcb;
+    uint32_t *lh = reinterpret_cast<uint32_t *>(per + kEnumPerSampleFixed * B);
+    char *blk = sc.eblk + static_cast<int64_t>(blockIdx.x) * sc.eblk_stride;
+    uint16_t *lc = reinterpret_cast<uint16_t *>(blk);
+    uint32_t *lch = reinterpret_cast<uint32_t *>(blk + enum_blk_codes_bytes(B, L));
 
     const int64_t s0 = round * B;
     const int nb = static_cast<int>(min(static_cast<int64_t>(B), n - s0));
     if (nb <= 0) return;
+    if (blockIdx.x >= sc.eblk_blocks) {
+        // no device area for this block (the grids have one block per CU)
+        if (threadIdx.x == 0) latch(sc.err, NQS_E_STATE);
+        return;
+    }
     ++cnt.rounds;
     const uint32_t pmask = static_cast<uint32_t>(parts - 1);
 
@@ -1354,7 +1364,7 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
         int pos;
         if (e < S.ra) {
             if (e == 0) {
-                lh[b * L] = 0u;
+                lh[b * Lr] = 0u;
                 lc[b * L] = static_cast<uint16_t>(kNoPair);
                 continue;
             }
@@ -1393,7 +1403,9 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             pos = S.lcb + sorted_pair_pos(m.nvir, m.offc, parts, ii, jj, qcl[qa] & pmask,
                                           qcl[qb] & pmask);
         }
-        lh[b * L + pos] = hr[qa] ^ hr[qb];
+        const uint32_t hv = hr[qa] ^ hr[qb];
+        if (pos < Lr) lh[b * Lr + pos] = hv;
+        else lch[b * Lc + pos - Lr] = hv;
         lc[b * L + pos] = static_cast<uint16_t>(qa | (qb << 7));
     }
     __syncthreads();
@@ -1408,13 +1420,20 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
         const int b = static_cast<int>(e.x >> 28);
         EnumHit c;
         if (lane < static_cast<int>(mcount)) {
-            const EnumSample rec = smp[b];
-            Key<W> x;
-            x.w[0] = rec.x0;
-            if constexpr (W == 2) x.w[1] = rec.x1;
-            enum_candidate<W, DUMP, P, SCV>(tab, sc, x, rec.hx, rec.la, rec.ph, rec.idx, e,
-                                            enum_candidate_bucket<W>(sc, e), log_amp, phase,
-                                            hit_idx, sign_bits, sign_words, cnt, c);
+            const FpBucket f = enum_candidate_bucket<W>(sc, e);
+            if (!fp_settles_miss<W>(f, e.y)) {
+                // the row's code from its list position
+                const uint32_t pos = (e.x >> 14) & 0x3FFFu;
+                const uint32_t rc = lc[b * L + static_cast<int>(pos)];
+                const uint2 ef = make_uint2((e.x & 0xF0003FFFu) | (rc << 14), e.y);
+                const EnumSample rec = smp[b];
+                Key<W> x;
+                x.w[0] = rec.x0;
+                if constexpr (W == 2) x.w[1] = rec.x1;
+                enum_candidate<W, DUMP, P, SCV>(tab, sc, x, rec.hx, rec.la, rec.ph, rec.idx, ef, f,
+                                                log_amp, phase, hit_idx, sign_bits, sign_words,
+                                                cnt, c);
+            }
         }
         const bool hit = c.hit;
         const double cre = c.re, cim = c.im;
@@ -1550,7 +1569,7 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             uint32_t colh = 0, colc = kNoPair;
             if (act) {
                 if (prod == 2) {
-                    colh = lh[b * L + col0 + k];
+                    colh = lch[b * Lc + col0 - Lr + k];
                     colc = lc[b * L + col0 + k];
                 } else {
                     uint32_t qa = kNoQubit, qb = kNoQubit;
@@ -1582,8 +1601,9 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
             const int sl = (ceil_div(nrow, ns) + 3) & ~3;
             const int r0 = seg * sl;
             const int nr = min(nrow - r0, sl);
-            const uint32_t *rw = lh + b * L + row0 + r0;
-            const uint16_t *rc = lc + b * L + row0 + r0;
+            const uint32_t *rw = lh + b * Lr + row0 + r0;
+            // queue entry of row rr: its list position in place of its code
+            const uint32_t colq = colc | (static_cast<uint32_t>(row0 + r0) << 14);
             cnt.probes += static_cast<unsigned long long>(__popcll(colmask)) * nr -
                           (excl0 ? 1ull : 0ull);
             uint64_t pm = probe_rows<false>(filt_b, fbytes_mask, colh, rw, nr, nr, act,
@@ -1604,7 +1624,7 @@ __device__ __forceinline__ void enum_round(uint32_t *filt, const DevTable &tab,
                 }
                 if (has)
                     queue[qn + lanes_below(any)] =
-                        make_uint2(colc | (static_cast<uint32_t>(rc[rr]) << 14), colh ^ rw[rr]);
+                        make_uint2(colq + (static_cast<uint32_t>(rr) << 14), colh ^ rw[rr]);
                 qn += c;
             }
         }
