@@ -151,7 +151,12 @@ int nqs_table_host(int n_qubits, int64_t n_terms, const uint64_t *x_masks,
  *
  * Asynchronous on hip_stream (no host synchronisation).  The handle's
  * scratch (sample hash, partial sums) is reused; a handle may be used from
- * one stream at a time.  n = 0 is a no-op.  Errors: NQS_E_ARG, NQS_E_STATE
+ * one stream at a time.  n = 0 is a no-op.  A call whose arguments (n,
+ * pointers, precision) repeat the previous call's, with the same launch plan
+ * and profiling off, is issued as one replay of a HIP graph captured on the
+ * second such call (the buffers' contents are read at run time, as for an
+ * eager call); the environment variable NQS_EVAL_GRAPHS=0, read when a
+ * handle is created, keeps every call eager.  Errors: NQS_E_ARG, NQS_E_STATE
  * (bad handle), NQS_E_NOMEM, NQS_E_DEVICE synchronously; NQS_E_DUPLICATE and
  * NQS_E_RANGE (sample bits, negative counts) from the next nqs_sync().
  */
