@@ -221,7 +221,6 @@ hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunc
                       const double *phase, double *eloc, int precision, int32_t *hit_idx,
                       uint32_t *sign_bits, hipStream_t s) {
     hipError_t e;
-    if ((e = nqs::launch_reset(sc, s)) != hipSuccess) return e;
     if (h->profiling && (e = hipEventRecord(h->ev[0], s)) != hipSuccess) return e;
     if ((e = nqs::launch_hash(h->dt, sc, h->slot_cap, samples, weights, n, s)) != hipSuccess)
         return e;

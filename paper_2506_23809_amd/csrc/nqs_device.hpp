@@ -222,7 +222,6 @@ struct Tuning {
 };
 
 EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tune);
-hipError_t launch_reset(const DevScratch &sc, hipStream_t st);
 hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capacity,
                        const uint64_t *samples, const int64_t *weights, int64_t n,
                        hipStream_t st);
@@ -232,7 +231,7 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
                        int64_t sign_words, EvalStageEvents ev, hipStream_t st);
 hipError_t launch_energy(const int64_t *w, const double *e, int64_t n, double *part,
                          double *result, double *out, hipStream_t st);
-constexpr int kEnergyPartDoubles = 3 * 256;
+constexpr int kEnergyPartDoubles = 4 * 256;  // pass-1 (3 per block), then pass-2 partials
 constexpr int kCounters = 8;
 
 // ---- batched form

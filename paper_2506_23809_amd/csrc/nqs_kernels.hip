@@ -211,8 +211,12 @@ __global__ void hash_clear_kernel(uint64_t *__restrict__ skey, int32_t *__restri
                                   uint32_t *__restrict__ sfp,
                                   int words, uint32_t capacity, uint32_t *__restrict__ filter,
                                   uint32_t filter_words, uint32_t *__restrict__ efilter,
-                                  uint32_t efilter_words) {
+                                  uint32_t efilter_words, unsigned long long *__restrict__ counters,
+                                  int *__restrict__ mixed) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    // the batch's counters and sector flag start at zero as well
+    if (s < static_cast<uint32_t>(kCounters)) counters[s] = 0;
+    if (s == 0) *mixed = 0;
     if (s < capacity) {
         sidx[s] = -1;
         sfp[s] = 0u;
@@ -2508,34 +2512,38 @@ __global__ __launch_bounds__(kRedThreads) void energy_pass1_kernel(
     }
 }
 
-// Single block: combine pass-1 partials in block order; result[0..2] =
-// sum w, mean re, mean im.
-__global__ __launch_bounds__(kRedThreads) void energy_mean_kernel(const double *__restrict__ part,
-                                                                  int nparts,
-                                                                  double *__restrict__ result) {
-    __shared__ double lds[kRedThreads];
-    double sw = 0.0, sr = 0.0, si = 0.0;
+// The pass-1 partials combined in block order (every block of pass 2 does
+// this the same way, to the same bits): sum w, mean re, mean im.
+__device__ __forceinline__ void energy_mean(const double *__restrict__ part1, int nparts,
+                                            double *lds, double &sw, double &mr, double &mi) {
+    double sr = 0.0, si = 0.0;
+    sw = 0.0;
     for (int b = threadIdx.x; b < nparts; b += kRedThreads) {
-        sw += part[3 * b];
-        sr += part[3 * b + 1];
-        si += part[3 * b + 2];
+        sw += part1[3 * b];
+        sr += part1[3 * b + 1];
+        si += part1[3 * b + 2];
     }
     sw = block_sum(sw, lds);
     sr = block_sum(sr, lds);
     si = block_sum(si, lds);
-    if (threadIdx.x == 0) {
-        result[0] = sw;
-        result[1] = sw != 0.0 ? sr / sw : 0.0;
-        result[2] = sw != 0.0 ? si / sw : 0.0;
-    }
+    mr = sw != 0.0 ? sr / sw : 0.0;
+    mi = sw != 0.0 ? si / sw : 0.0;
 }
 
-// Pass 2: per-block sum w |E - mean|^2.
+// Pass 2: the mean from the pass-1 partials (block 0 keeps it in result[0..2]
+// = sum w, mean re, mean im), then per-block sum w |E - mean|^2.
 __global__ __launch_bounds__(kRedThreads) void energy_pass2_kernel(
     const int64_t *__restrict__ w, const double *__restrict__ e, int64_t n,
-    const double *__restrict__ result, double *__restrict__ part) {
+    const double *__restrict__ part1, int nparts, double *__restrict__ result,
+    double *__restrict__ part) {
     __shared__ double lds[kRedThreads];
-    const double mr = result[1], mi = result[2];
+    double sw, mr, mi;
+    energy_mean(part1, nparts, lds, sw, mr, mi);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        result[0] = sw;
+        result[1] = mr;
+        result[2] = mi;
+    }
     double sv = 0.0;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRedThreads + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * kRedThreads) {
@@ -2566,15 +2574,7 @@ __global__ __launch_bounds__(kRedThreads) void energy_var_kernel(const double *_
 
 // ------------------------------------------------------------------ launchers
 
-__global__ void reset_kernel(unsigned long long *counters, int *mixed) {
-    if (threadIdx.x < kCounters) counters[threadIdx.x] = 0;
-    if (threadIdx.x == 0) *mixed = 0;
-}
 
-hipError_t launch_reset(const DevScratch &sc, hipStream_t st) {
-    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, st, sc.counters, sc.mixed);
-    return hipGetLastError();
-}
 
 namespace {
 int device_cus() {
@@ -2648,7 +2648,8 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
     uint32_t span = capacity > fwords ? capacity : fwords;
     span = span > efwords ? span : efwords;
     hipLaunchKernelGGL(hash_clear_kernel, dim3((span + 255) / 256), dim3(256), 0, st, sc.skey,
-                       sc.sidx, sc.sfp, words, capacity, sc.filter, fwords, sc.efilter, efwords);
+                       sc.sidx, sc.sfp, words, capacity, sc.filter, fwords, sc.efilter, efwords,
+                       sc.counters, sc.mixed);
     const dim3 grid(static_cast<unsigned>((n + 255) / 256));
     if (words == 1)
         hipLaunchKernelGGL(hash_build_kernel<1>, grid, dim3(256), 0, st, tab, sc, samples, weights, n);
@@ -2809,12 +2810,13 @@ hipError_t launch_energy(const int64_t *w, const double *e, int64_t n, double *p
     int64_t blocks = (n + kRedThreads - 1) / kRedThreads;
     if (blocks > kRedBlocks) blocks = kRedBlocks;
     if (blocks < 1) blocks = 1;
+    // pass-1 partials, then (apart: pass 2 still reads those) pass-2 partials
+    double *part2 = part + 3 * kRedBlocks;
+    static_assert(4 * kRedBlocks <= kEnergyPartDoubles, "both partial sets fit");
     hipLaunchKernelGGL(energy_pass1_kernel, dim3(blocks), dim3(kRedThreads), 0, st, w, e, n, part);
-    hipLaunchKernelGGL(energy_mean_kernel, dim3(1), dim3(kRedThreads), 0, st, part,
-                       static_cast<int>(blocks), result);
     hipLaunchKernelGGL(energy_pass2_kernel, dim3(blocks), dim3(kRedThreads), 0, st, w, e, n,
-                       result, part);
-    hipLaunchKernelGGL(energy_var_kernel, dim3(1), dim3(kRedThreads), 0, st, part,
+                       part, static_cast<int>(blocks), result, part2);
+    hipLaunchKernelGGL(energy_var_kernel, dim3(1), dim3(kRedThreads), 0, st, part2,
                        static_cast<int>(blocks), result, out);
     return hipGetLastError();
 }
