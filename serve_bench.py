@@ -91,9 +91,6 @@ def run(args, log):
     hams, payloads, pairs = [], [], []
     for j, w in enumerate(jobs):
         h = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
-        if args.tuning_cache:
-            # tuned plans from the cache when present (no timing here)
-            pass
         hams.append(h)
         s2, la2, ph2 = second_batch(w, j)
         p = []
