@@ -7,9 +7,12 @@ the weighted energy/variance reduction (nqs_energy, which synchronises).  The
 Pauli table is built and uploaded once before the timed region (it is
 resident across VMC steps); its setup time is reported separately.
 
-Default workload: 40 qubits (20 orbitals, 10 alpha + 10 beta), full
-Jordan-Wigner table (46,171 X groups, 233,001 terms), 65,536 unique sector
-samples with geometric counts, log|psi| ~ N(0, 2), phase ~ U[0, 2 pi), FP64.
+Default workload: 100 qubits (50 orbitals, 25 alpha + 25 beta, integral
+decay length 6), full Jordan-Wigner table (1,963,674 X groups, 9,256,243
+terms), 262,144 unique sector samples with geometric counts, log|psi| ~
+N(0, 2), phase ~ U[0, 2 pi), FP64; the FP32-with-compensation form is timed
+beside it.  Secondary lines: the 40-qubit batch (65,536 samples) and the
+latency of the 12-qubit batch (400 samples) in microseconds.
 
 Prints ONE JSON line.  Metric: E_loc pair-evaluations per second, where a
 pair is one (unique sample, X group) combination, N_s * G per batch.
@@ -30,6 +33,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: int32 VALU lane-operations per second
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# FP64 adds per second: one v_add_f64 per lane per clock (78.6 TFLOP/s counts
+# an FMA as two)
+FP64_PEAK_ADDS = 256 * 4 * 16 * 2.4e9
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_23809_amd", "csrc", "nqs_kernels.hip")
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -55,6 +61,22 @@ def algorithmic_ops_per_probe_enum():
     shift by h, a shift of h, a shift by that) and their AND, and the shift-OR
     that records the outcome in the lane's row mask."""
     return 1 + 2 + 4 + 1
+
+
+def algorithmic_ops_per_candidate_join(words):
+    """Integer work of the pair join per candidate (an ordered pair of samples
+    sharing a bucket): the XOR of the two bit strings and its popcount (one
+    32-bit operation per half word each), and the compare against the
+    largest flip."""
+    return 2 * words + 2 * words + 1
+
+
+def algorithmic_ops_per_entry_join(words):
+    """Integer work of the join's grouping per entry (sample, block): the
+    block's hash (one XOR per occupied qubit, about a fifth of 2 * 32 * words
+    bits set) and its bucket (multiply, shift), the count, the scatter and
+    the place in its sorted bucket (one atomic and a few moves each)."""
+    return (2 * 32 * words) // 10 + 2 + 6
 
 
 def algorithmic_ops_per_pair(n_qubits, spin_bits):
@@ -106,7 +128,8 @@ def cpu_baseline(w, threads, e_loc_gpu=None, energies=None, budget_s=20.0):
         done = m
         sample = f"{m} of {n} sample rows, each against all {n} samples"
     res = {"value": done * G / dt, "unit": "pair-evals/s", "cores": threads,
-           "kind": "oracle", "sample": sample, "seconds": round(dt, 3)}
+           "kind": "oracle", "sample": sample, "seconds": round(dt, 3),
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
     if check is not None:
         res["check"] = check
     return res
@@ -117,7 +140,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="nq40", choices=["nq12", "nq40", "nq100"])
+    ap.add_argument("--workload", default="nq100", choices=["nq12", "nq40", "nq100"])
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 40-qubit and 12-qubit secondary measurements")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32k"])
     ap.add_argument("--filter-bits", type=int, default=0,
                     help="on-chip filter bits per sample (0: the library's default)")
@@ -200,10 +225,13 @@ def main():
         st = ham.stats()
         ham.profile(True)
         kms = []
+        per_step = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
+            ts = time.perf_counter()
             mean, var, sw = step()          # nqs_energy synchronises the stream
+            per_step.append((time.perf_counter() - ts) * 1e3)
             kms.append(ham.last_kernel_ms())
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
@@ -212,8 +240,10 @@ def main():
         ms = elapsed * 1e3 / args.steps
         log(f"{precision}: timed {args.steps} steps: {ms:.3f} ms/step, E = {mean.real:.10f}, "
             f"var = {var:.4e}")
+        timed.per_step[precision] = per_step
         return ms, np.array(kms), mean, var, sw, st
 
+    timed.per_step = {}
     other = "fp32k" if args.precision == "fp64" else "fp64"
     ms_per_step, kms, mean, var, sw, st = timed(args.precision)
     o_ms, o_kms, o_mean, o_var, _, _ = timed(other)
@@ -234,18 +264,52 @@ def main():
     hit_terms = st["terms"] - w.n_samples * n_diag_terms
     b_alg = algorithmic_bytes(w.n_samples, words, G, T, st["probes"], st["hits"], max(hit_terms, 0))
     hbm_equiv = b_alg / (lookup_ms / 1e3) / 1e9
+    plan = ham.plan()
+    joined = plan.get("join_ran") == 1
     enumerated = st.get("enum_rounds", 0) > 0
-    if enumerated:
+    strategy = "pair join" if joined else ("enumeration" if enumerated else "streaming")
+    stage_ms = {"grouping": hash_ms, "pairs": lookup_ms, "finish": finish_ms}
+    if joined:
+        # the stage that dominates the step carries the roofline
+        dominant = max(stage_ms, key=stage_ms.get)
+    else:
+        dominant = "pairs"
+    peak = VALU_PEAK_OPS
+    peak_unit = "Tops/s (int32 VALU lane-ops)"
+    if dominant == "finish":
+        n_occ = w.n_alpha + w.n_beta
+        kernel_name = "eloc_finish_kernel"
+        ops_unit = 1
+        units = w.n_samples * (1 + n_occ + n_occ * (n_occ - 1) // 2)
+        unit_name = "diagonal term (one FP64 add of the occupation form)"
+        kernel_ms = finish_ms
+        peak = FP64_PEAK_ADDS
+        peak_unit = "T FP64 adds/s"
+    elif dominant == "grouping":
+        kernel_name = "join grouping (count, scan, scatter, sort) + hash build"
+        ops_unit = algorithmic_ops_per_entry_join(words)
+        units = plan["join_blocks"] * w.n_samples
+        unit_name = "join entry (sample, block)"
+        kernel_ms = hash_ms
+    elif joined:
+        kernel_name = "join_pair_kernel"
+        ops_unit = algorithmic_ops_per_candidate_join(words)
+        units = st["candidates"]
+        unit_name = "candidate pair (ordered pair sharing a bucket)"
+        kernel_ms = lookup_ms
+    elif enumerated:
         kernel_name = "eloc_enum_kernel"
         ops_unit = algorithmic_ops_per_probe_enum()
         units = st["probes"]
         unit_name = "probe"
+        kernel_ms = lookup_ms
     else:
         kernel_name = "eloc_lookup_kernel"
         ops_unit = algorithmic_ops_per_pair(w.n_qubits, w.K)
         units = pairs
         unit_name = "pair"
-    achieved_ops = ops_unit * units / (lookup_ms / 1e3)
+        kernel_ms = lookup_ms
+    achieved_ops = ops_unit * units / (kernel_ms / 1e3)
 
     traffic = None
     # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes of this
@@ -269,6 +333,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_median": float(np.median(timed.per_step[args.precision])),
+        "ms_per_step_min": float(np.min(timed.per_step[args.precision])),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -285,15 +351,15 @@ def main():
             "kernel": kernel_name,
             "bound": "alu",
             "achieved": achieved_ops / 1e12,
-            "peak": VALU_PEAK_OPS / 1e12,
-            "unit": "Tops/s (int32 VALU lane-ops)",
-            "frac": achieved_ops / VALU_PEAK_OPS,
+            "peak": peak / 1e12,
+            "unit": peak_unit,
+            "frac": achieved_ops / peak,
             "traffic": traffic,
             "traffic_GBps": (traffic / (lookup_ms / 1e3) / 1e9) if traffic else None,
             "algorithmic_ops_per_unit": ops_unit,
             "unit_of_work": unit_name,
             "units_per_launch": units,
-            "kernel_ms": lookup_ms,
+            "kernel_ms": kernel_ms,
             "hbm_equivalent": {
                 "algorithmic_bytes_per_launch": b_alg,
                 "achieved_GBps": hbm_equiv,
@@ -303,8 +369,10 @@ def main():
                         "are answered by the LDS filter and the L2-resident hash",
             },
         },
-        "strategy": "enumeration" if enumerated else "streaming",
-        "kernel_ms": {"hash_build": hash_ms, "eloc_lookup": lookup_ms, "eloc_finish": finish_ms},
+        "strategy": strategy,
+        "plan": plan,
+        "kernel_ms": {"hash_build_and_join_grouping": hash_ms, "pairs_or_lookup": lookup_ms,
+                      "eloc_finish": finish_ms},
         "counts": st,
         "probes_per_s": st["probes"] / (ms_per_step / 1e3),
         "setup_ms": setup_ms,
@@ -313,11 +381,18 @@ def main():
             "precision": other,
             "value": pairs / (o_ms / 1e3),
             "ms_per_step": o_ms,
+            "ms_per_step_median": float(np.median(timed.per_step[other])),
+            "ms_per_step_min": float(np.min(timed.per_step[other])),
             "kernel_ms": float(o_kms.mean(axis=0)[1]),
             "energy_re": o_mean.real,
             "abs_err_re_energy_fp32k_vs_fp64_Ha": abs(e_fp32k.real - e_fp64.real),
         },
     }
+    if joined and ham.plan().get("join_ran") == 1:
+        res["compare_strategy"] = compare_enumeration(ham, out, S, la, ph, wt, args, log, pairs)
+    ham.close()
+    if not args.no_secondary:
+        res["secondary"] = secondary(args, log, dev)
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         log(f"cpu baseline: oracle on {threads} threads")
@@ -325,8 +400,101 @@ def main():
         log(f"cpu baseline: {res['cpu_baseline']}")
     else:
         res["cpu_baseline"] = None
-    ham.close()
     print(json.dumps(res), flush=True)
+
+
+def compare_enumeration(ham, out, S, la, ph, wt, args, log, pairs):
+    """The same FP64 step with the flip enumeration forced (the strategy the
+    device declines here): its time and its kernel's VALU roofline."""
+    import numpy as np
+
+    import paper_2506_23809_amd as nqs
+    ham.set_tuning(strategy="enum")
+    for _ in range(args.warmup):
+        ham.eloc_into(out, S, la, ph, wt)
+        nqs.energy(wt, out)
+    ham.sync()
+    ham.profile(True)
+    per, kms = [], []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        ham.eloc_into(out, S, la, ph, wt)
+        nqs.energy(wt, out)
+        per.append((time.perf_counter() - t0) * 1e3)
+        kms.append(ham.last_kernel_ms())
+    ham.profile(False)
+    ham.sync()
+    st = ham.stats()
+    ham.set_tuning(strategy="auto")
+    k_ms = float(np.mean([k[1] for k in kms]))
+    achieved = algorithmic_ops_per_probe_enum() * st["probes"] / (k_ms / 1e3)
+    ms = float(np.mean(per))
+    log(f"enumeration forced: {ms:.3f} ms/step, kernel {k_ms:.3f} ms")
+    return {"strategy": "enumeration", "ms_per_step": ms,
+            "ms_per_step_median": float(np.median(per)), "ms_per_step_min": float(np.min(per)),
+            "value": pairs / (ms / 1e3), "kernel": "eloc_enum_kernel", "kernel_ms": k_ms,
+            "roofline_frac": achieved / VALU_PEAK_OPS, "achieved_Tops": achieved / 1e12,
+            "probes": st["probes"], "hits": st["hits"]}
+
+
+def secondary(args, log, dev):
+    """The other single-GPU workloads, timed the same way (not the headline):
+    the 40-qubit batch's throughput and the 12-qubit batch's latency."""
+    import numpy as np
+    import torch
+
+    import paper_2506_23809_amd as nqs
+    import workloads
+
+    out = {}
+    for name in ("nq40", "nq12"):
+        if name == args.workload:
+            continue
+        w = workloads.workload(name)
+        ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
+        S = nqs.to_device_samples(w.samples, dev)
+        la = torch.from_numpy(w.log_amp).to(dev)
+        ph = torch.from_numpy(w.phase).to(dev)
+        wt = torch.from_numpy(w.weights).to(dev)
+        e = torch.empty((w.n_samples, 2), dtype=torch.float64, device=dev)
+        steps = max(args.steps, 50) if name == "nq12" else args.steps
+        for _ in range(args.warmup):
+            ham.eloc_into(e, S, la, ph, wt)
+            nqs.energy(wt, e)
+        ham.sync()
+        per = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            ham.eloc_into(e, S, la, ph, wt)
+            nqs.energy(wt, e)
+            per.append((time.perf_counter() - t0) * 1e3)
+        ham.sync()
+        st = ham.stats()
+        pairs = st["pairs"]
+        ms = float(np.mean(per))
+        plan = ham.plan()
+        strategy = ("pair join" if plan["join_ran"] == 1 else
+                    ("enumeration" if st["enum_rounds"] > 0 else "streaming"))
+        out[w.name] = {"pair_evals_per_s": pairs / (ms / 1e3), "ms_per_step": ms,
+                       "ms_per_step_median": float(np.median(per)),
+                       "ms_per_step_min": float(np.min(per)), "steps": steps,
+                       "latency_us_median": float(np.median(per)) * 1e3,
+                       "strategy": strategy, "counts": st}
+        log(f"secondary {w.name}: {ms:.3f} ms/step (median {np.median(per):.3f})")
+        ham.close()
+    return out
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (what lscpu prints), from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _family(n_jobs, log):

@@ -198,6 +198,36 @@ int nqs_sync(nqs_ham h, void *hip_stream);
 int nqs_eval_stats(nqs_ham h, int64_t out[6]);
 
 /*
+ * Launch plan of the last nqs_eloc_eval on this
+ * handle; out[0..6] are host-side and valid as soon as the call has
+ * returned, out[7] after nqs_sync:
+ *   out[0] strategy planned besides the pair join: NQS_STRATEGY_STREAM or
+ *          NQS_STRATEGY_ENUM
+ *   out[1] filter partitions (sample classes) of the enumeration filter:
+ *          1, 2, 4 or 8 (0 when streaming is planned)
+ *   out[2] 32-bit words per enumeration filter partition
+ *   out[3] group chunks of the streaming kernel (0: no streaming launch)
+ *   out[4] samples of the batch
+ *   out[5] 32-bit words of the streaming kernel's Bloom bitmap
+ *   out[6] qubit blocks of the pair join, 0 when no join was launched
+ *   out[7] whether the device ran the pair join: 1, 0, or -1 (not launched)
+ * Which of the others ran is in nqs_eval_stats (rounds > 0: enumeration).
+ * Errors: NQS_E_STATE (bad handle, nothing evaluated yet), NQS_E_ARG,
+ * NQS_E_DEVICE.
+ */
+int nqs_eval_plan(nqs_ham h, int64_t out[8]);
+
+/*
+ * Test hook: the k-th device allocation of evaluation scratch from now on
+ * (block areas, filter partitions, sample hash, sample hashes, partial sums,
+ * in that order within one growth) fails once as if the device were out of
+ * memory, so the error path can be exercised: that evaluation returns
+ * NQS_E_NOMEM and the handle stays usable (a later call allocates again).
+ * k = 0 switches the hook off.  Process-wide.  Errors: NQS_E_ARG (k < 0).
+ */
+int nqs_debug_fail_allocs(int k);
+
+/*
  * Kernel timing.  nqs_profile(h, 1) makes every later nqs_eloc_eval on h
  * record HIP events on its stream around each kernel stage; after the
  * stream has completed, nqs_last_kernel_ms(h, out) returns the durations in
@@ -245,9 +275,25 @@ int nqs_debug_dump(nqs_ham h, int64_t n, const uint64_t *samples, const double *
  *     flipping more than four qubits; a batch whose samples span several
  *     sectors (or whose occupation does not fit the on-chip round) runs the
  *     streaming kernel instead, decided on the device.
- *   NQS_STRATEGY_AUTO (0): enumeration when the table allows it.
+ *   NQS_STRATEGY_JOIN: the pair join.  Every group of the table flips at
+ *     most m qubits (m = 4 for molecular tables), so two samples a term
+ *     connects agree on at least one of m + 1 disjoint qubit blocks; the
+ *     samples are bucketed by the contents of each block, and only pairs of
+ *     samples sharing a bucket are tested (Hamming distance, then the group
+ *     index).  Its cost is the sum of squared bucket sizes, independent of
+ *     the table's size: for samples spread over a large sector it is far
+ *     below both others.  Needs m + 1 <= 8 and at most 8192 samples in one
+ *     bucket; otherwise (decided on the device) the enumeration or streaming
+ *     strategy runs instead.
+ *   NQS_STRATEGY_AUTO (0): the pair join is launched beside the enumeration
+ *     (where the table allows it) or streaming, and the device runs the
+ *     join when its counted cost (sum of squared bucket sizes plus a term
+ *     per entry and bucket) is below the other strategy's (the
+ *     enumeration's lookups, or half the sample-group pairs of streaming).
+ *     Batches (nqs_batch_*) and the server never run the pair join.
  */
-enum { NQS_STRATEGY_AUTO = 0, NQS_STRATEGY_STREAM = 1, NQS_STRATEGY_ENUM = 2 };
+enum { NQS_STRATEGY_AUTO = 0, NQS_STRATEGY_STREAM = 1, NQS_STRATEGY_ENUM = 2,
+       NQS_STRATEGY_JOIN = 3 };
 
 typedef struct {
     int32_t threads;       /* streaming block size: 256, 512 or 1024 (default 1024) */

@@ -17,7 +17,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libnqs.so")
+# NQS_LIBRARY names another build of the library (the host-only sanitizer
+# build of the table builder, which exports only its host entry points)
+LIB_PATH = os.environ.get("NQS_LIBRARY") or os.path.join(_HERE, "libnqs.so")
 
 NQS_OK = 0
 NQS_E_ARG = -1
@@ -36,6 +38,7 @@ _PRECISION = {"fp64": NQS_FP64, "fp32k": NQS_FP32_KAHAN, "fp32_kahan": NQS_FP32_
 EXPORTS = ("nqs_last_error", "nqs_version", "nqs_ham_create", "nqs_ham_create_integrals",
            "nqs_ham_info", "nqs_ham_destroy",
            "nqs_table_host", "nqs_eloc_eval", "nqs_energy", "nqs_sync", "nqs_eval_stats",
+           "nqs_eval_plan", "nqs_debug_fail_allocs",
            "nqs_debug_dump", "nqs_profile", "nqs_last_kernel_ms", "nqs_set_tuning",
            "nqs_get_tuning", "nqs_autotune", "nqs_batch_create", "nqs_batch_launch",
            "nqs_batch_capture", "nqs_batch_replay", "nqs_batch_destroy", "nqs_server_create",
@@ -49,13 +52,13 @@ class ServerConfig(ctypes.Structure):
                 ("threads", ctypes.c_int32)]
 
 
-STRATEGIES = {"auto": 0, "stream": 1, "enum": 2}
+STRATEGIES = {"auto": 0, "stream": 1, "enum": 2, "join": 3}
 STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
 
 
 class Tuning(ctypes.Structure):
     """nqs_tuning: streaming block size, filter bits per sample, work items per CU,
-    lookup strategy (0 auto, 1 streaming, 2 enumeration)."""
+    lookup strategy (0 auto, 1 streaming, 2 enumeration, 3 pair join)."""
     _fields_ = [("threads", ctypes.c_int32), ("filter_bits", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("strategy", ctypes.c_int32)]
 
@@ -102,6 +105,8 @@ def load_library(path: str = LIB_PATH):
         "nqs_energy": (I, [I64, P, P, P, P]),
         "nqs_sync": (I, [P, P]),
         "nqs_eval_stats": (I, [P, P]),
+        "nqs_eval_plan": (I, [P, P]),
+        "nqs_debug_fail_allocs": (I, [I]),
         "nqs_debug_dump": (I, [P, I64, P, P, P, P, P, P, P]),
         "nqs_profile": (I, [P, I]),
         "nqs_last_kernel_ms": (I, [P, P]),
@@ -122,7 +127,12 @@ def load_library(path: str = LIB_PATH):
         "nqs_server_destroy": (I, [P]),
     }
     for name, (res, args) in sig.items():
-        fn = getattr(lib, name)
+        # a host-only build lacks the device entry points: those stay unbound
+        # (calling one raises AttributeError); the export test checks that
+        # the full library has every one
+        fn = getattr(lib, name, None)
+        if fn is None:
+            continue
         fn.restype = res
         fn.argtypes = args
     _lib = lib
@@ -268,6 +278,14 @@ class Hamiltonian:
         return {"pairs": out[0], "probes": out[1], "hits": out[2], "terms": out[3],
                 "candidates": out[4], "enum_rounds": out[5]}
 
+    def plan(self):
+        """nqs_eval_plan: the launch plan of the last evaluation."""
+        out = (ctypes.c_int64 * 8)()
+        _check(load_library().nqs_eval_plan(self._h, out))
+        return {"strategy": STRATEGY_NAMES.get(out[0], out[0]), "filter_partitions": out[1],
+                "partition_words": out[2], "stream_chunks": out[3], "n": out[4],
+                "filter_words": out[5], "join_blocks": out[6], "join_ran": out[7]}
+
     def profile(self, enable=True):
         """Record HIP events around each kernel stage of later evaluations."""
         _check(load_library().nqs_profile(self._h, 1 if enable else 0))
@@ -280,7 +298,7 @@ class Hamiltonian:
 
     def set_tuning(self, threads=0, filter_bits=0, blocks_per_cu=0, strategy="auto"):
         """nqs_set_tuning; all zeros (strategy "auto") restores the built-in plan.
-        strategy: "auto", "stream" or "enum"."""
+        strategy: "auto", "stream", "enum" or "join"."""
         t = Tuning(threads, filter_bits, blocks_per_cu, STRATEGIES[strategy])
         _check(load_library().nqs_set_tuning(self._h, ctypes.byref(t)))
 
@@ -434,6 +452,11 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def debug_fail_allocs(k):
+    """Test hook: the k-th scratch allocation from now fails once (0: off)."""
+    _check(load_library().nqs_debug_fail_allocs(int(k)))
 
 
 def energy(weights, eloc, stream=None):

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -19,12 +20,7 @@
 
 namespace {
 
-thread_local std::string g_last_error;
-
-int fail(int code, const std::string &msg) {
-    g_last_error = msg;
-    return code;
-}
+int fail(int code, const std::string &msg) { return nqs::detail::fail(code, msg); }
 
 int fail_hip(hipError_t e, const char *what) {
     return fail(NQS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -38,8 +34,9 @@ int fail_hip(hipError_t e, const char *what) {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-constexpr size_t kSmallBytes = 128;                  // counters, error latch, sector flag
-constexpr size_t kErrOffset = 8 * nqs::kCounters;    // after the counters
+// counters (kCounterSlots copies), error latch, sector flag
+constexpr size_t kErrOffset = 8 * nqs::kCounters * nqs::kCounterSlots;
+constexpr size_t kSmallBytes = kErrOffset + 64;
 constexpr size_t kMaxFilterWords = size_t(1) << 15;  // 128 KB Bloom bitmap
 constexpr size_t kMaxEFilterWords = kMaxFilterWords * nqs::kEnumMaxParts;
 constexpr int64_t kMaxGroups = int64_t(1) << 26;     // queue entries pack the group in 26 bits
@@ -66,9 +63,13 @@ struct nqs_ham_s {
     char *eblk = nullptr;
     int64_t eblk_stride = 0;
     uint32_t eblk_blocks = 0;
+    void *jmem = nullptr;  // the pair join's buckets and entries
+    size_t jmem_bytes = 0;
     void *small = nullptr; // counters[8] u64, err, mixed
     int64_t last_pairs = 0;
     bool ever_evaluated = false;
+    nqs::EvalLaunch last_plan{};  // launch plan of the last evaluation
+    unsigned long long *last_jctl = nullptr;  // its pair-join control words (device)
     // optional per-stage events: hash start, hash end / lookup start,
     // lookup end / finish start, finish end
     bool profiling = false;
@@ -88,14 +89,28 @@ struct nqs_ham_s {
 
 namespace {
 
+// Slot arrays of a sample hash of cap slots (a power of two) at base: keys
+// first, then the slot indices, then the slot fingerprints.
+void set_slots(nqs::DevScratch *s, void *base, uint32_t cap, int words) {
+    s->skey = static_cast<uint64_t *>(base);
+    s->sidx = base ? reinterpret_cast<int32_t *>(static_cast<char *>(base) +
+                                                 sizeof(uint64_t) * words * cap)
+                   : nullptr;
+    s->sfp = base ? reinterpret_cast<uint32_t *>(s->sidx + cap) : nullptr;
+    s->slot_mask = cap - 1;
+    int lg = 0;
+    while ((1u << lg) < cap) ++lg;
+    s->slot_shift = 32 - (lg - nqs::bucket_log2(words));
+}
+
+// Bytes of a sample hash of cap slots.
+size_t slot_array_bytes(uint32_t cap, int words) {
+    return static_cast<size_t>(cap) * (sizeof(uint64_t) * words + sizeof(int32_t) + sizeof(uint32_t));
+}
+
 nqs::DevScratch scratch_of(nqs_ham h) {
     nqs::DevScratch s{};
-    // keys first, then the slot indices, then the slot fingerprints
-    s.skey = static_cast<uint64_t *>(h->slots);
-    s.sidx = h->slots ? reinterpret_cast<int32_t *>(static_cast<char *>(h->slots) +
-                                                    sizeof(uint64_t) * h->words * h->slot_cap)
-                      : nullptr;
-    s.sfp = h->slots ? reinterpret_cast<uint32_t *>(s.sidx + h->slot_cap) : nullptr;
+    set_slots(&s, h->slots, h->slot_cap, h->words);
     s.shx = h->shx;
     s.part = h->part;
     s.filter = h->filter;
@@ -105,11 +120,6 @@ nqs::DevScratch scratch_of(nqs_ham h) {
     s.counters = static_cast<unsigned long long *>(h->small);
     s.err = reinterpret_cast<int *>(static_cast<char *>(h->small) + kErrOffset);
     s.mixed = reinterpret_cast<int *>(static_cast<char *>(h->small) + kErrOffset + 4);
-    uint32_t cap = h->slot_cap;
-    s.slot_mask = cap - 1;
-    int lg = 0;
-    while ((1u << lg) < cap) ++lg;
-    s.slot_shift = 32 - (lg - nqs::bucket_log2(h->words));
     return s;
 }
 
@@ -119,6 +129,22 @@ void set_filters(nqs::DevScratch *s, nqs_ham h, const nqs::EvalLaunch &L) {
     s->eparts_log2 = L.eparts_log2;
     s->efilter_log2 = L.efilter_log2;
     s->efilter = L.eparts_log2 > 0 ? h->efilter : h->filter;
+    if (L.join && h->jmem) {
+        nqs::join_scratch_layout(h->dt, L.n, L.join_log2m, static_cast<char *>(h->jmem), s);
+        s->join_force = L.join_force;
+    }
+}
+
+// Partial-sum slots per sample a plan needs: its group chunks, or one per
+// join block when the pair join may run.
+int64_t plan_chunks(const nqs_ham h, const nqs::EvalLaunch &L) {
+    const int64_t c = L.n_chunks > 0 ? L.n_chunks : 1;
+    return L.join ? std::max<int64_t>(c, h->dt.join_blocks) : c;
+}
+
+// Bytes of the pair join's scratch for a plan (0: none planned).
+size_t plan_join_bytes(const nqs_ham h, const nqs::EvalLaunch &L) {
+    return L.join ? nqs::join_scratch_bytes(h->dt, L.n, L.join_log2m) : 0;
 }
 
 // Grow the per-handle scratch to hold a batch of n samples (and the
@@ -134,8 +160,49 @@ int64_t enum_blk_stride(const nqs::DevTable &t) {
     return (m + 255) & ~static_cast<int64_t>(255);
 }
 
+// Test hook (nqs_debug_fail_allocs): the g_fail_at-th scratch allocation
+// from the time it was set reports out-of-memory without allocating (once).
+std::atomic<int> g_fail_at{0};
+
+hipError_t scratch_malloc(void **p, size_t bytes) {
+    int left = g_fail_at.load();
+    while (left > 0) {
+        if (g_fail_at.compare_exchange_weak(left, left - 1)) {
+            if (left == 1) {
+                *p = nullptr;
+                return hipErrorOutOfMemory;
+            }
+            break;
+        }
+    }
+    return hipMalloc(p, bytes);
+}
+
+// Replace a scratch buffer by one of `bytes`: the old one is released and
+// its recorded capacity zeroed first, so a failed allocation leaves an empty
+// buffer (capacity 0) that the next call grows again, never a stale
+// capacity over a null pointer.
+template <typename T, typename C>
+int regrow(T **buf, C *cap, C new_cap, size_t bytes, const char *what) {
+    if (*buf) {
+        const hipError_t e = hipFree(*buf);
+        *buf = nullptr;
+        *cap = 0;
+        if (e != hipSuccess) return fail_hip(e, "hipFree of scratch");
+    }
+    *cap = 0;
+    void *p = nullptr;
+    if (scratch_malloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(NQS_E_NOMEM, std::string("device allocation of ") + what + " failed");
+    }
+    *buf = static_cast<T *>(p);
+    *cap = new_cap;
+    return NQS_OK;
+}
+
 int ensure_scratch(nqs_ham h, int64_t n, int64_t n_chunks, hipStream_t st,
-                   bool efilter = false) {
+                   bool efilter = false, size_t join_bytes = 0) {
     uint64_t want = 64;
     while (want < nqs::kSlotsPerSample * static_cast<uint64_t>(n)) want <<= 1;
     if (want > (1ull << 31)) return fail(NQS_E_ARG, "batch too large for the sample hash");
@@ -151,50 +218,57 @@ int ensure_scratch(nqs_ham h, int64_t n, int64_t n_chunks, hipStream_t st,
     }
     const bool blk_grow = blk_stride > 0 && n_cu > 0;
     const bool grow = want > h->slot_cap || n > h->shx_cap || part_need > h->part_cap ||
-                      (efilter && !h->efilter) || blk_grow;
-    if (grow) {
-        NQS_HIP(hipStreamSynchronize(st));
-        if (blk_grow) {
-            if (h->eblk) NQS_HIP(hipFree(h->eblk));
-            h->eblk = nullptr;
-            h->eblk_blocks = 0;
-            if (hipMalloc(&h->eblk, blk_stride * n_cu) != hipSuccess) {
-                h->eblk = nullptr;
-                return fail(NQS_E_NOMEM, "device allocation of the enumeration block areas failed");
-            }
-            h->eblk_stride = blk_stride;
-            h->eblk_blocks = static_cast<uint32_t>(n_cu);
-        }
-        if (efilter && !h->efilter) {
-            if (hipMalloc(&h->efilter, kMaxEFilterWords * 4) != hipSuccess) {
-                h->efilter = nullptr;
-                return fail(NQS_E_NOMEM, "device allocation of the filter partitions failed");
-            }
-        }
-        if (want > h->slot_cap) {
-            if (h->slots) NQS_HIP(hipFree(h->slots));
-            h->slots = nullptr;
-            if (hipMalloc(&h->slots, want * slot_size) != hipSuccess)
-                return fail(NQS_E_NOMEM, "device allocation of the sample hash failed");
-            h->slot_cap = static_cast<uint32_t>(want);
-            h->slot_bytes = want * slot_size;
-        }
-        if (n > h->shx_cap) {
-            if (h->shx) NQS_HIP(hipFree(h->shx));
-            h->shx = nullptr;
-            if (hipMalloc(&h->shx, sizeof(uint32_t) * n) != hipSuccess)
-                return fail(NQS_E_NOMEM, "device allocation of sample hashes failed");
-            h->shx_cap = n;
-        }
-        if (part_need > h->part_cap) {
-            if (h->part) NQS_HIP(hipFree(h->part));
-            h->part = nullptr;
-            if (hipMalloc(&h->part, sizeof(double) * part_need) != hipSuccess)
-                return fail(NQS_E_NOMEM, "device allocation of partial sums failed");
-            h->part_cap = part_need;
-        }
+                      (efilter && !h->efilter) || blk_grow || join_bytes > h->jmem_bytes;
+    if (!grow) return NQS_OK;
+    NQS_HIP(hipStreamSynchronize(st));
+    int rc = NQS_OK;
+    if (blk_grow) {
+        uint32_t blocks = 0;
+        rc = regrow(&h->eblk, &blocks, static_cast<uint32_t>(n_cu),
+                    static_cast<size_t>(blk_stride) * n_cu, "the enumeration block areas");
+        h->eblk_blocks = blocks;
+        h->eblk_stride = h->eblk ? blk_stride : 0;
+        if (rc) return rc;
+    }
+    if (efilter && !h->efilter) {
+        int have = 0;
+        rc = regrow(&h->efilter, &have, 1, kMaxEFilterWords * 4, "the filter partitions");
+        if (rc) return rc;
+    }
+    if (want > h->slot_cap) {
+        uint32_t cap = h->slot_cap;
+        h->slot_bytes = 0;
+        rc = regrow(&h->slots, &cap, static_cast<uint32_t>(want),
+                    want * slot_size, "the sample hash");
+        h->slot_cap = cap;
+        if (rc) return rc;
+        h->slot_bytes = want * slot_size;
+    }
+    if (n > h->shx_cap) {
+        rc = regrow(&h->shx, &h->shx_cap, n, sizeof(uint32_t) * n, "sample hashes");
+        if (rc) return rc;
+    }
+    if (part_need > h->part_cap) {
+        rc = regrow(&h->part, &h->part_cap, part_need, sizeof(double) * part_need,
+                    "partial sums");
+        if (rc) return rc;
+    }
+    if (join_bytes > h->jmem_bytes) {
+        rc = regrow(&h->jmem, &h->jmem_bytes, join_bytes, join_bytes, "the pair join's buckets");
+        if (rc) return rc;
     }
     return NQS_OK;
+}
+
+// Whether the scratch a plan needs is all present (a failed growth leaves
+// a buffer empty; nothing may be launched over it).
+int scratch_ready(nqs_ham h, const nqs::EvalLaunch &L) {
+    const bool ok = h->slots && h->slot_cap >= 64 && h->shx && h->part && h->filter && h->small &&
+                    (L.eparts_log2 == 0 || h->efilter) &&
+                    (L.strategy != nqs::kStrategyEnum || !h->dt.enum_ok || h->eblk) &&
+                    (!L.join || (h->jmem && h->jmem_bytes >= plan_join_bytes(h, L))) &&
+                    h->part_cap >= 2 * L.n * plan_chunks(h, L);
+    return ok ? NQS_OK : fail(NQS_E_STATE, "scratch buffers missing after a failed allocation");
 }
 
 bool valid_handle(nqs_ham h) { return h && h->table_mem && h->small; }
@@ -210,7 +284,8 @@ struct EvalKey {
     int threads, filter_log2;
     size_t lds_bytes;
     int eparts_log2, efilter_log2;
-    const void *slots, *shx, *part, *filter, *efilter, *small, *eblk;
+    int join, join_force, join_log2m;
+    const void *slots, *shx, *part, *filter, *efilter, *small, *eblk, *jmem;
     uint32_t slot_cap;
 };
 static_assert(sizeof(EvalKey) <= sizeof(nqs_ham_s::eval_key), "key fits");
@@ -222,7 +297,7 @@ hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunc
                       uint32_t *sign_bits, hipStream_t s) {
     hipError_t e;
     if (h->profiling && (e = hipEventRecord(h->ev[0], s)) != hipSuccess) return e;
-    if ((e = nqs::launch_hash(h->dt, sc, h->slot_cap, samples, weights, n, s)) != hipSuccess)
+    if ((e = nqs::launch_hash(h->dt, sc, sc.slot_mask + 1u, samples, weights, n, s)) != hipSuccess)
         return e;
     if (h->profiling && (e = hipEventRecord(h->ev[1], s)) != hipSuccess) return e;
     const int64_t sign_words = (h->dt.n_terms + 31) / 32;
@@ -271,7 +346,8 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool dump = hit_idx || sign_bits;
     const nqs::EvalLaunch L = nqs::plan_eval(h->dt, n, dump, &h->tune);
-    int rc = ensure_scratch(h, n, L.n_chunks, st, L.eparts_log2 > 0);
+    int rc = ensure_scratch(h, n, plan_chunks(h, L), st, L.eparts_log2 > 0, plan_join_bytes(h, L));
+    if (!rc) rc = scratch_ready(h, L);
     if (rc) return rc;
     nqs::DevScratch sc = scratch_of(h);
     set_filters(&sc, h, L);
@@ -297,6 +373,10 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
         key.lds_bytes = L.lds_bytes;
         key.eparts_log2 = L.eparts_log2;
         key.efilter_log2 = L.efilter_log2;
+        key.join = L.join;
+        key.join_force = L.join_force;
+        key.join_log2m = L.join_log2m;
+        key.jmem = h->jmem;
         key.slots = h->slots;
         key.shx = h->shx;
         key.part = h->part;
@@ -338,6 +418,8 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
                            sign_bits, st));
     if (h->profiling) h->profiled = true;
     h->last_pairs = n * h->dt.n_groups;
+    h->last_plan = L;
+    h->last_jctl = sc.jctl;
     h->ever_evaluated = true;
     return NQS_OK;
 }
@@ -351,37 +433,6 @@ std::mutex g_energy_mutex;
 std::unordered_map<int, EnergyScratch> g_energy;
 
 }  // namespace
-
-extern "C" {
-
-const char *nqs_last_error(void) { return g_last_error.c_str(); }
-
-int nqs_version(void) { return 100; }
-
-int nqs_table_host(int n_qubits, int64_t n_terms, const uint64_t *x_masks,
-                   const uint64_t *z_masks, const double *coeffs, int64_t *n_groups,
-                   int64_t *n_merged, uint64_t *group_x, int64_t *group_off, uint64_t *term_z,
-                   double *term_c) {
-    if (!n_groups || !n_merged) return fail(NQS_E_ARG, "null count outputs");
-    nqs::HostTable T;
-    std::string err;
-    int rc;
-    try {
-        rc = nqs::build_table(n_qubits, n_terms, x_masks, z_masks, coeffs, nullptr, &T, &err);
-    } catch (const std::bad_alloc &) {
-        return fail(NQS_E_NOMEM, "host allocation failed");
-    }
-    if (rc) return fail(rc, err);
-    *n_groups = T.n_groups;
-    *n_merged = T.n_terms;
-    if (group_x) std::memcpy(group_x, T.gx.data(), sizeof(uint64_t) * T.gx.size());
-    if (group_off) std::memcpy(group_off, T.goff.data(), sizeof(int64_t) * T.goff.size());
-    if (term_z) std::memcpy(term_z, T.tz.data(), sizeof(uint64_t) * T.tz.size());
-    if (term_c) std::memcpy(term_c, T.tc.data(), sizeof(double) * T.tc.size());
-    return NQS_OK;
-}
-
-}  // extern "C"
 
 namespace {
 
@@ -501,6 +552,15 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
     d.gh = reinterpret_cast<const uint32_t *>(base + pieces[11].off);
     d.gh_shift = T.gh_shift;
     d.qcls = reinterpret_cast<const uint8_t *>(base + pieces[12].off);
+    d.max_flip = T.max_flip;
+    d.join_blocks = T.max_flip + 1 <= nqs::kJoinMaxBlocks ? T.max_flip + 1 : 0;
+    for (int b = 0; b < nqs::kJoinMaxBlocks; ++b) {
+        d.jmask[b][0] = d.jmask[b][1] = 0;
+        if (b >= d.join_blocks) continue;
+        // block b: qubits [b nq / B, (b + 1) nq / B)
+        const int q0 = b * T.n_qubits / d.join_blocks, q1 = (b + 1) * T.n_qubits / d.join_blocks;
+        for (int q = q0; q < q1; ++q) d.jmask[b][q >> 6] |= 1ull << (q & 63);
+    }
     d.diag_occ = T.diag_occ ? 1 : 0;
     d.diag = T.diag_occ ? reinterpret_cast<const double *>(base + pieces[13].off) : nullptr;
     d.diag32 = T.diag_occ ? reinterpret_cast<const float *>(base + pieces[14].off) : nullptr;
@@ -589,7 +649,7 @@ int nqs_ham_info(nqs_ham h, int64_t *n_groups, int64_t *n_terms, int64_t *device
                         h->shx_cap * 4 + h->part_cap * 8 + kSmallBytes +
                         static_cast<int64_t>(kMaxFilterWords * 4) +
                         (h->efilter ? static_cast<int64_t>(kMaxEFilterWords * 4) : 0) +
-                        h->eblk_stride * h->eblk_blocks;
+                        h->eblk_stride * h->eblk_blocks + static_cast<int64_t>(h->jmem_bytes);
     return NQS_OK;
 }
 
@@ -605,6 +665,7 @@ int nqs_ham_destroy(nqs_ham h) {
     if (h->slots) (void)hipFree(h->slots);
     if (h->shx) (void)hipFree(h->shx);
     if (h->part) (void)hipFree(h->part);
+    if (h->jmem) (void)hipFree(h->jmem);
     for (hipEvent_t e : h->ev)
         if (e) (void)hipEventDestroy(e);
     if (h->eval_exec) (void)hipGraphExecDestroy(h->eval_exec);
@@ -673,11 +734,43 @@ int nqs_eval_stats(nqs_ham h, int64_t out[6]) {
     if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
     if (!out) return fail(NQS_E_ARG, "null output");
     if (!h->ever_evaluated) return fail(NQS_E_STATE, "no evaluation on this handle yet");
-    unsigned long long c[nqs::kCounters];
-    NQS_HIP(hipMemcpy(c, h->small, sizeof(c), hipMemcpyDeviceToHost));
+    unsigned long long slots[nqs::kCounters * nqs::kCounterSlots];
+    NQS_HIP(hipMemcpy(slots, h->small, sizeof(slots), hipMemcpyDeviceToHost));
+    unsigned long long c[nqs::kCounters] = {};
+    for (int s = 0; s < nqs::kCounterSlots; ++s)
+        for (int k = 0; k < nqs::kCounters; ++k) c[k] += slots[s * nqs::kCounters + k];
     out[0] = h->last_pairs;
     for (int k = 1; k < 5; ++k) out[k] = static_cast<int64_t>(c[k]);
     out[5] = static_cast<int64_t>(c[6]);
+    return NQS_OK;
+}
+
+int nqs_eval_plan(nqs_ham h, int64_t out[8]) {
+    if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
+    if (!out) return fail(NQS_E_ARG, "null output");
+    if (!h->ever_evaluated) return fail(NQS_E_STATE, "no evaluation on this handle yet");
+    const nqs::EvalLaunch &L = h->last_plan;
+    out[0] = L.strategy;
+    out[1] = L.strategy == nqs::kStrategyEnum ? (int64_t(1) << L.eparts_log2) : 0;
+    out[2] = int64_t(1) << (L.eparts_log2 > 0 ? L.efilter_log2 : L.filter_log2);
+    out[3] = L.chunk_len > 0 ? L.n_chunks : 0;
+    out[4] = L.n;
+    out[5] = int64_t(1) << L.filter_log2;
+    out[6] = L.join ? h->dt.join_blocks : 0;
+    out[7] = -1;
+    if (L.join && h->last_jctl) {
+        // the device's decision, in the control words of the join scratch
+        unsigned long long chosen = 0;
+        NQS_HIP(hipMemcpy(&chosen, h->last_jctl + nqs::kJoinCtlChosen, sizeof(chosen),
+                          hipMemcpyDeviceToHost));
+        out[7] = chosen ? 1 : 0;
+    }
+    return NQS_OK;
+}
+
+int nqs_debug_fail_allocs(int k) {
+    if (k < 0) return fail(NQS_E_ARG, "k < 0");
+    g_fail_at.store(k);
     return NQS_OK;
 }
 
@@ -723,7 +816,7 @@ bool tuning_valid(const nqs_tuning &t) {
     const bool th = t.threads == 0 || t.threads == 256 || t.threads == 512 || t.threads == 1024;
     const bool fb = t.filter_bits == 0 || (t.filter_bits >= 4 && t.filter_bits <= 64);
     const bool bc = t.blocks_per_cu == 0 || (t.blocks_per_cu >= 1 && t.blocks_per_cu <= 64);
-    const bool sg = t.strategy >= nqs::kStrategyAuto && t.strategy <= nqs::kStrategyEnum;
+    const bool sg = t.strategy >= nqs::kStrategyAuto && t.strategy <= nqs::kStrategyJoin;
     return th && fb && bc && sg;
 }
 
@@ -850,6 +943,7 @@ int nqs_autotune(nqs_ham h, int64_t n, const uint64_t *samples, const double *lo
             for (int bc : {2, 4, 8}) cands.push_back(nqs::Tuning{th, fb, bc, nqs::kStrategyStream});
     if (h->dt.enum_ok)
         for (int fb : {8, 16, 32}) cands.push_back(nqs::Tuning{1024, fb, 4, nqs::kStrategyEnum});
+    if (h->dt.join_blocks > 0) cands.push_back(nqs::Tuning{1024, 16, 4, nqs::kStrategyJoin});
     for (const nqs::Tuning &cand : cands) {
         h->tune = cand;
         float best_run = 1e30f;
@@ -1038,8 +1132,6 @@ int nqs_batch_destroy(nqs_batch b) {
 namespace nqs {
 namespace detail {
 
-int fail(int code, const std::string &msg) { return ::fail(code, msg); }
-
 bool valid_handle(nqs_ham h) { return ::valid_handle(h); }
 
 int64_t table_bytes(nqs_ham h) { return h->table_bytes; }
@@ -1048,14 +1140,15 @@ int64_t scratch_bytes(nqs_ham h) {
     return static_cast<int64_t>(h->slot_bytes) + h->shx_cap * 4 + h->part_cap * 8 +
            static_cast<int64_t>(kSmallBytes + kMaxFilterWords * 4) +
            (h->efilter ? static_cast<int64_t>(kMaxEFilterWords * 4) : 0) +
-           h->eblk_stride * h->eblk_blocks;
+           h->eblk_stride * h->eblk_blocks + static_cast<int64_t>(h->jmem_bytes);
 }
 
 int reserve(nqs_ham h, int64_t n, int threads, hipStream_t st) {
     nqs::Tuning t = h->tune;
     if (threads) t.threads = threads;
     n = std::max<int64_t>(n, 1);
-    const nqs::EvalLaunch L = nqs::plan_eval(h->dt, n, false, &t);
+    nqs::EvalLaunch L = nqs::plan_eval(h->dt, n, false, &t);
+    L.join = 0;  // batches (and so the server) do not run the pair join
     // A batch of m <= n samples plans about (items per GPU) / tiles(m) chunks,
     // so m * chunks(m) <= items * threads + m: size the partials for that.
     const int64_t items = int64_t(t.blocks_per_cu ? t.blocks_per_cu : 4) * 256 * 1024 / L.threads;
@@ -1106,14 +1199,16 @@ int plan_batch(const nqs_batch_item *items, int n_items, int threads, hipStream_
         // enumeration rounds assume 1024-thread blocks
         if (th != kEnumThreads) t.strategy = kStrategyStream;
         EvalLaunch L = plan_eval(h->dt, std::max<int64_t>(it.n, 1), false, &t);
+        L.join = 0;  // batches run the enumeration or streaming items only
         if (L.strategy == kStrategyEnum && L.chunk_len > 0) {
             // the streaming items are only a fallback here (mixed sectors):
             // one group chunk keeps their number small
             L.n_chunks = 1;
             L.chunk_len = h->dt.n_groups - L.g_first;
         }
-        const int rc = ensure_scratch(h, std::max<int64_t>(it.n, 1), L.n_chunks, st,
-                                      L.eparts_log2 > 0);
+        int rc = ensure_scratch(h, std::max<int64_t>(it.n, 1), L.n_chunks, st,
+                                L.eparts_log2 > 0);
+        if (!rc) rc = scratch_ready(h, L);
         if (rc) return rc;
         JobDesc &J = jobs[k];
         J.tab = h->dt;

@@ -7,6 +7,10 @@
 
 namespace nqs {
 
+// Pair join: at most this many qubit blocks (a table whose groups flip up to
+// kJoinMaxBlocks - 1 qubits).
+constexpr int kJoinMaxBlocks = 8;
+
 // Resident Pauli table (structure of arrays, all device pointers).
 struct DevTable {
     const uint64_t *gx;    // [G][2] flip masks
@@ -41,6 +45,13 @@ struct DevTable {
     int diag_occ;
     const double *diag;
     const float *diag32;
+    // pair join: the qubits split into join_blocks disjoint blocks (jmask);
+    // two bit strings at Hamming distance at most max_flip < join_blocks
+    // agree on at least one block (pigeonhole), so every connected pair of
+    // samples shares the contents of some block
+    int max_flip;          // largest popc(X) over the groups
+    int join_blocks;       // max_flip + 1, or 0 when that exceeds kJoinMaxBlocks
+    uint64_t jmask[kJoinMaxBlocks][2];
 };
 
 // ---- flip enumeration: shape of one round
@@ -168,7 +179,35 @@ struct DevScratch {
     char *eblk;
     int64_t eblk_stride;
     uint32_t eblk_blocks;
+    // pair join (all null when the launch plans none): buckets of samples
+    // by block contents, join_blocks << join_log2m of them, block-major
+    uint32_t *jcnt;             // [buckets] counts -> start offsets -> bucket ends
+    uint32_t *jkey;             // [blocks][n] bucket of each (block, sample)
+    uint32_t *jent;             // [blocks * n] entries (sample index), by bucket, ascending
+    uint2 *jrange;              // [blocks * n] [start, end) of each entry's bucket
+    uint64_t *jkeys;            // [blocks * n][2] bit string of each entry
+    uint32_t *jbig;             // [blocks * n] buckets left to the block sorter
+    unsigned long long *jscan;  // [3][scan blocks] count, sum of squares, largest
+    unsigned long long *jctl;   // [kJoinCtl] see kJoinCtl*
+    int join_log2m;
+    int join_force;             // 1: join whenever it can run, 0: when cheaper
 };
+
+// Pair-join control words (jctl): the enumeration's probe count, the join's
+// ordered candidate pairs (sum of squared bucket sizes), the largest bucket,
+// buckets for the block sorter, and the decision (1: the join runs).
+enum { kJoinCtlProbes = 0, kJoinCtlCost = 1, kJoinCtlMax = 2, kJoinCtlBig = 3,
+       kJoinCtlChosen = 4, kJoinCtlProbeSlots = 8, kJoinCtl = 8 + 64 };
+// Counters per scan block of the bucket counts (1024 threads x 4).
+constexpr int kJoinScanItems = 4096;
+// Largest bucket the block sorter takes (entries in LDS); a larger one
+// leaves the batch to the other strategies.
+constexpr int kJoinMaxBucket = 8192;
+
+// Whether the pair join was chosen for this launch (device side).
+__device__ __forceinline__ bool join_chosen(const DevScratch &sc) {
+    return sc.jctl != nullptr && sc.jctl[kJoinCtlChosen] != 0ull;
+}
 
 constexpr uint32_t kGoldenMul = 0x9E3779B1u;
 
@@ -202,9 +241,28 @@ struct EvalLaunch {
     size_t lds_bytes;   // dynamic LDS of the lookup kernel
     int eparts_log2;    // enumeration filter: partitions ...
     int efilter_log2;   // ... of this many words (log2)
+    int join;           // 1: the pair join is launched (the device decides whether it runs)
+    int join_force;     // 1: it runs whenever it can (tuning asked for it)
+    int join_log2m;     // log2 of the buckets per block
 };
 
-constexpr int kStrategyAuto = 0, kStrategyStream = 1, kStrategyEnum = 2;
+// Bytes of the pair join's scratch for n samples and the table's blocks
+// (0 when the table has none).
+size_t join_scratch_bytes(const DevTable &tab, int64_t n, int log2m);
+// Bucket count per block for n samples: the power of two at or above n.
+int join_log2m_for(int64_t n);
+// Lay the join scratch out from base (256-byte aligned pieces).
+void join_scratch_layout(const DevTable &tab, int64_t n, int log2m, char *base, DevScratch *sc);
+// The join's grouping (counts, scan, decision, scatter, sort) between the
+// hash clear and the hash build, and its pair kernel.
+hipError_t launch_join_prep(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
+                            int64_t n, int64_t g_eff, hipStream_t st);
+hipError_t launch_join_pairs(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
+                             const double *log_amp, const double *phase, int64_t n, int precision,
+                             int32_t *hit_idx, uint32_t *sign_bits, int64_t sign_words,
+                             hipStream_t st);
+
+constexpr int kStrategyAuto = 0, kStrategyStream = 1, kStrategyEnum = 2, kStrategyJoin = 3;
 
 // Optional event recorded between the lookup and the finish kernels.
 struct EvalStageEvents {
@@ -233,6 +291,15 @@ hipError_t launch_energy(const int64_t *w, const double *e, int64_t n, double *p
                          double *result, double *out, hipStream_t st);
 constexpr int kEnergyPartDoubles = 4 * 256;  // pass-1 (3 per block), then pass-2 partials
 constexpr int kCounters = 8;
+// The counters are kept in kCounterSlots copies, one 64-byte line each; a
+// block adds to copy (blockIdx.x % kCounterSlots), so the device's atomics
+// on them spread over that many lines (thousands of waves adding to one
+// address serialise), and a reader sums the copies.
+constexpr int kCounterSlots = 64;
+__device__ __forceinline__ void count_add(unsigned long long *counters, int k,
+                                          unsigned long long v) {
+    if (v) atomicAdd(&counters[(blockIdx.x % kCounterSlots) * kCounters + k], v);
+}
 
 // ---- batched form
 

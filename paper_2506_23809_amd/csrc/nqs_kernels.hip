@@ -30,178 +30,9 @@
 
 #include "../../include/nqs.h"
 #include "nqs_device.hpp"
+#include "nqs_dev_common.hpp"
 
 namespace nqs {
-
-// ------------------------------------------------------------------ helpers
-
-template <int W>
-struct Key {
-    uint64_t w[W];
-};
-
-template <int W>
-__device__ __forceinline__ Key<W> load_key(const uint64_t *__restrict__ p, int64_t i) {
-    Key<W> k;
-#pragma unroll
-    for (int q = 0; q < W; ++q) k.w[q] = p[2 * i + q];
-    return k;
-}
-
-template <int W>
-__device__ __forceinline__ uint32_t linear_hash(const Key<W> &k, const uint32_t *__restrict__ hr) {
-    uint32_t h = 0;
-#pragma unroll
-    for (int q = 0; q < W; ++q) {
-        uint64_t v = k.w[q];
-        while (v) {
-            h ^= hr[64 * q + __builtin_ctzll(v)];
-            v &= v - 1;
-        }
-    }
-    return h;
-}
-
-// Bits of x selected by (m0, m1), packed to the low end in mask order.
-template <int W>
-__device__ __forceinline__ uint64_t compress(const Key<W> &x, uint64_t m0, uint64_t m1) {
-    uint64_t r = 0;
-    int k = 0;
-    while (m0) {
-        const int b = __builtin_ctzll(m0);
-        r |= ((x.w[0] >> b) & 1ull) << k++;
-        m0 &= m0 - 1;
-    }
-    if constexpr (W == 2) {
-        while (m1) {
-            const int b = __builtin_ctzll(m1);
-            r |= ((x.w[1] >> b) & 1ull) << k++;
-            m1 &= m1 - 1;
-        }
-    }
-    return r;
-}
-
-__device__ __forceinline__ uint32_t slot_of(uint32_t h, uint32_t shift) {
-    return (h * kGoldenMul) >> shift;
-}
-
-// One bucket of the sample hash: 64 bytes of keys (8 one-word or 4
-// two-word), four independent 16-byte loads.
-struct Bucket {
-    uint4 q0, q1, q2, q3;
-};
-
-template <int W>
-__device__ __forceinline__ Bucket bucket_load(const uint64_t *__restrict__ skey, uint32_t start) {
-    const uint4 *p = reinterpret_cast<const uint4 *>(skey + static_cast<size_t>(start) * W);
-    return Bucket{p[0], p[1], p[2], p[3]};
-}
-
-// Slot of the bucket holding k (or -1), and whether the bucket has a free
-// slot.  Occupied slots form a prefix of a bucket (a key takes the first
-// free slot from its start on, and nothing is removed), so the bucket is
-// open iff its last slot is free; a key is stored once, so any slot that
-// matches is the one.  The common case (no match) costs one XOR-OR per key
-// word and a minimum.
-template <int W>
-__device__ __forceinline__ uint32_t slot_diff(const Bucket &b, int s, const Key<W> &k) {
-    // zero iff slot s holds k (s a compile-time constant after unrolling)
-    const uint32_t k0l = static_cast<uint32_t>(k.w[0]), k0h = static_cast<uint32_t>(k.w[0] >> 32);
-    if constexpr (W == 1) {
-        const uint4 &v = (s >> 1) == 0 ? b.q0 : (s >> 1) == 1 ? b.q1 : (s >> 1) == 2 ? b.q2 : b.q3;
-        return (s & 1) ? ((v.z ^ k0l) | (v.w ^ k0h)) : ((v.x ^ k0l) | (v.y ^ k0h));
-    } else {
-        const uint32_t k1l = static_cast<uint32_t>(k.w[1]), k1h = static_cast<uint32_t>(k.w[1] >> 32);
-        const uint4 &v = s == 0 ? b.q0 : s == 1 ? b.q1 : s == 2 ? b.q2 : b.q3;
-        return (v.x ^ k0l) | (v.y ^ k0h) | (v.z ^ k1l) | (v.w ^ k1h);
-    }
-}
-
-template <int W>
-__device__ __forceinline__ int bucket_scan(const Bucket &b, const Key<W> &k, bool &empty) {
-    constexpr int BK = 1 << bucket_log2(W);
-    // the last slot's key (its last word) is the bucket's last word
-    empty = (b.q3.z & b.q3.w) == 0xFFFFFFFFu;
-    uint32_t m = slot_diff<W>(b, 0, k);
-#pragma unroll
-    for (int s = 1; s < BK; ++s) m = min(m, slot_diff<W>(b, s, k));
-    if (m != 0u) return -1;
-    // a match (rare): which slot
-    int found = 0;
-#pragma unroll
-    for (int s = BK - 1; s > 0; --s)
-        if (slot_diff<W>(b, s, k) == 0u) found = s;
-    return found;
-}
-
-// Index of key k in the sample hash, or -1, with the bucket at start already
-// loaded (b); the index array is read only for the slot that holds the key.
-template <int W>
-__device__ __forceinline__ int32_t hash_find_from(const uint64_t *__restrict__ skey,
-                                                  const int32_t *__restrict__ sidx, uint32_t mask,
-                                                  uint32_t start, const Key<W> &k, Bucket b) {
-    constexpr int BK = 1 << bucket_log2(W);
-    for (uint32_t probe = 0; probe <= mask; probe += BK) {
-        bool empty;
-        const int found = bucket_scan<W>(b, k, empty);
-        if (found >= 0) return sidx[(start + static_cast<uint32_t>(found)) & mask];
-        if (empty) return -1;
-        start = (start + BK) & mask;
-        b = bucket_load<W>(skey, start);
-    }
-    return -1;
-}
-
-// Index of key in the sample hash, or -1 (one memory round trip per bucket).
-template <int W>
-__device__ __forceinline__ int32_t hash_find(const uint64_t *__restrict__ skey,
-                                             const int32_t *__restrict__ sidx, uint32_t mask,
-                                             uint32_t start, const Key<W> &k) {
-    return hash_find_from<W>(skey, sidx, mask, start, k, bucket_load<W>(skey, start));
-}
-
-__device__ __forceinline__ void latch(int *err, int code) { atomicCAS(err, 0, code); }
-
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-    const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
-    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(u), lane);
-    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(u >> 32), lane);
-    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
-}
-
-__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int lane) {
-    const uint32_t lo = __shfl(static_cast<uint32_t>(v), lane);
-    const uint32_t hi = __shfl(static_cast<uint32_t>(v >> 32), lane);
-    return (static_cast<uint64_t>(hi) << 32) | lo;
-}
-
-__device__ __forceinline__ double shfl_f64(double v, int lane) {
-    return __longlong_as_double(static_cast<long long>(
-        shfl_u64(static_cast<uint64_t>(__double_as_longlong(v)), lane)));
-}
-
-// Number of set bits of mask below this lane.
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
-}
-
-// Blocked Bloom filter of the sample hashes: a key with hash h sets two bits
-// of one 32-bit word, word (h >> 2) & (words - 1) and bits (h >> 17) & 31 and
-// (h >> 24) & 31 (disjoint ranges of h for filters of up to 2^15 words).  The
-// byte offset of the word is h & ((words - 1) << 2), which folds into the
-// XOR forming h; the shift by (h >> 24) reads byte 3 of h in place (a
-// sub-dword operand), so a probe costs one shift less.
-__device__ __forceinline__ uint32_t filter_word(uint32_t h, uint32_t wmask) {
-    return (h >> 2) & wmask;
-}
-__device__ __forceinline__ uint32_t filter_bits(uint32_t h) {
-    return (1u << ((h >> 17) & 31)) | (1u << ((h >> 24) & 31));
-}
-__device__ __forceinline__ uint32_t filter_test(uint32_t fw, uint32_t h) {
-    return (fw >> ((h >> 17) & 31)) & (fw >> ((h >> 24) & 31)) & 1u;
-}
 
 // ------------------------------------------------------------------ hash build
 
@@ -212,11 +43,15 @@ __global__ void hash_clear_kernel(uint64_t *__restrict__ skey, int32_t *__restri
                                   int words, uint32_t capacity, uint32_t *__restrict__ filter,
                                   uint32_t filter_words, uint32_t *__restrict__ efilter,
                                   uint32_t efilter_words, unsigned long long *__restrict__ counters,
-                                  int *__restrict__ mixed) {
+                                  int *__restrict__ mixed, uint32_t *__restrict__ jcnt,
+                                  uint32_t jbuckets, unsigned long long *__restrict__ jctl) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    // the batch's counters and sector flag start at zero as well
-    if (s < static_cast<uint32_t>(kCounters)) counters[s] = 0;
+    // the batch's counters and sector flag start at zero as well, and so do
+    // the pair join's bucket counts and control words
+    if (s < static_cast<uint32_t>(kCounters * kCounterSlots)) counters[s] = 0;
     if (s == 0) *mixed = 0;
+    if (jctl && s < static_cast<uint32_t>(kJoinCtl)) jctl[s] = 0;
+    if (s < jbuckets) jcnt[s] = 0u;
     if (s < capacity) {
         sidx[s] = -1;
         sfp[s] = 0u;
@@ -251,7 +86,8 @@ __device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScr
         const int rb = __popcll(s0 & tab.spin_b0) + __popcll(s1 & tab.spin_b1);
         if (na != ra || nb != rb) atomicOr(sc.mixed, 1);
     }
-    if (bad) return;
+    // the pair join, when it runs, needs neither the hash nor the filters
+    if (bad || join_chosen(sc)) return;
     Key<W> k;
     k.w[0] = w0;
     if constexpr (W == 2) k.w[1] = w1;
@@ -334,217 +170,6 @@ size_t lookup_lds_bytes(bool s32, int filter_log2, int threads) {
 }
 
 // Sum of one group's terms for bra x: sum_t c~_t (-1)^{popc(Z_t & x)}.
-template <int W, bool DUMP>
-__device__ __forceinline__ double group_sum(const DevTable &tab, int64_t g, const Key<W> &x,
-                                            uint32_t *__restrict__ sign_row,
-                                            unsigned long long *terms) {
-    const uint32_t t0 = tab.goff[g], t1 = tab.goff[g + 1];
-    double s = 0.0;
-    for (uint32_t t = t0; t < t1; ++t) {
-        int par = 0;
-#pragma unroll
-        for (int q = 0; q < W; ++q) par += __popcll(tab.tz[2 * static_cast<size_t>(t) + q] & x.w[q]);
-        const double c = tab.tc[t];
-        s += (par & 1) ? -c : c;
-        if constexpr (DUMP) {
-            if (sign_row && (par & 1)) atomicOr(&sign_row[t >> 5], 1u << (t & 31));
-        }
-    }
-    *terms += t1 - t0;
-    return s;
-}
-
-// ---- integral form (Slater-Condon rules, the evaluator of Sec. III-B)
-//
-// <bra|H|ket> from h_pq and the chemists' (pq|rs) for determinants that
-// differ by at most two spin orbitals; ONV ordering, so a ladder operator on
-// spin orbital j carries (-1)^(occupied orbitals below j).
-
-template <int W>
-__device__ __forceinline__ int parity_below(const Key<W> &s, int j) {
-    int c;
-    if (j < 64) {
-        c = __popcll(s.w[0] & ((1ull << j) - 1ull));
-    } else {
-        c = __popcll(s.w[0]);
-        if constexpr (W == 2) c += __popcll(s.w[1] & ((1ull << (j - 64)) - 1ull));
-    }
-    return c & 1;
-}
-
-template <int W>
-__device__ __forceinline__ void flip_bit(Key<W> &s, int j) {
-    if (W == 1 || j < 64)
-        s.w[0] ^= 1ull << (j & 63);
-    else
-        s.w[W - 1] ^= 1ull << (j & 63);
-}
-
-template <int W>
-__device__ __forceinline__ int lowest(const Key<W> &s) {
-    if (s.w[0]) return __builtin_ctzll(s.w[0]);
-    if constexpr (W == 2) return 64 + __builtin_ctzll(s.w[1]);
-    return 127;
-}
-
-__device__ __forceinline__ double eri_at(const DevTable &tab, int p, int q, int r, int s) {
-    const int64_t pq = p > q ? int64_t(p) * (p + 1) / 2 + q : int64_t(q) * (q + 1) / 2 + p;
-    const int64_t rs = r > s ? int64_t(r) * (r + 1) / 2 + s : int64_t(s) * (s + 1) / 2 + r;
-    return tab.sc_eri[pq > rs ? pq * (pq + 1) / 2 + rs : rs * (rs + 1) / 2 + pq];
-}
-
-template <int W>
-__device__ __forceinline__ double sc_element(const DevTable &tab, const Key<W> &bra,
-                                             const Key<W> &ket) {
-    Key<W> A, I;
-    int na = 0, ni = 0;
-#pragma unroll
-    for (int q = 0; q < W; ++q) {
-        A.w[q] = bra.w[q] & ~ket.w[q];  // created
-        I.w[q] = ket.w[q] & ~bra.w[q];  // annihilated
-        na += __popcll(A.w[q]);
-        ni += __popcll(I.w[q]);
-    }
-    if (na != ni) return 0.0;
-    const int K = tab.sc_k;
-    if (na == 1) {
-        const int i = lowest<W>(I), a = lowest<W>(A);
-        if ((i & 1) != (a & 1)) return 0.0;
-        Key<W> st = ket;
-        int sg = parity_below<W>(st, i);
-        flip_bit<W>(st, i);
-        sg ^= parity_below<W>(st, a);
-        const int as = a >> 1, is = i >> 1;
-        double v = tab.sc_h1[as * K + is];
-        // spectators: occupied in ket, except i
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-            uint64_t m = ket.w[q] & ~I.w[q];
-            while (m) {
-                const int j = 64 * q + __builtin_ctzll(m);
-                m &= m - 1;
-                const int js = j >> 1;
-                v += eri_at(tab, as, is, js, js);
-                if ((j & 1) == (i & 1)) v -= eri_at(tab, as, js, js, is);
-            }
-        }
-        return sg ? -v : v;
-    }
-    if (na == 2) {
-        const int i = lowest<W>(I), a = lowest<W>(A);
-        Key<W> I2 = I, A2 = A;
-        flip_bit<W>(I2, i);
-        flip_bit<W>(A2, a);
-        const int j = lowest<W>(I2), b = lowest<W>(A2);
-        // |bra> = G a+_a a+_b a_j a_i |ket>
-        Key<W> st = ket;
-        int sg = parity_below<W>(st, i);
-        flip_bit<W>(st, i);
-        sg ^= parity_below<W>(st, j);
-        flip_bit<W>(st, j);
-        sg ^= parity_below<W>(st, b);
-        flip_bit<W>(st, b);
-        sg ^= parity_below<W>(st, a);
-        double v = 0.0;
-        if (((a ^ i) & 1) == 0 && ((b ^ j) & 1) == 0) v += eri_at(tab, a >> 1, i >> 1, b >> 1, j >> 1);
-        if (((a ^ j) & 1) == 0 && ((b ^ i) & 1) == 0) v -= eri_at(tab, a >> 1, j >> 1, b >> 1, i >> 1);
-        return sg ? -v : v;
-    }
-    return 0.0;
-}
-
-template <int W>
-__device__ __forceinline__ double sc_diagonal(const DevTable &tab, const Key<W> &x) {
-    const int K = tab.sc_k;
-    double d = 0.0;
-#pragma unroll
-    for (int q = 0; q < W; ++q) {
-        uint64_t m = x.w[q];
-        while (m) {
-            const int i = 64 * q + __builtin_ctzll(m);
-            m &= m - 1;
-            const int is = i >> 1;
-            d += tab.sc_h1[is * K + is];
-            // partners above i
-            Key<W> rest;
-#pragma unroll
-            for (int r = 0; r < W; ++r) rest.w[r] = r < q ? 0ull : (r == q ? m : x.w[r]);
-#pragma unroll
-            for (int r = 0; r < W; ++r) {
-                uint64_t m2 = rest.w[r];
-                while (m2) {
-                    const int j = 64 * r + __builtin_ctzll(m2);
-                    m2 &= m2 - 1;
-                    const int js = j >> 1;
-                    d += eri_at(tab, is, is, js, js);
-                    if ((i & 1) == (j & 1)) d -= eri_at(tab, is, js, js, is);
-                }
-            }
-        }
-    }
-    return d;
-}
-
-// ---- FP32 form with compensation (precision NQS_FP32_KAHAN)
-//
-// Coefficients are stored as FP32 pairs hi + lo (lo = c - hi rounded), the
-// sign (-1)^{popc(Z & x)} is applied by flipping sign bits, the hi parts
-// are added with Knuth's error-free TwoSum and the lo parts and the TwoSum
-// errors go into a compensation term; a product H * r keeps its rounding
-// error through fma.  The per-sample value s + c is widened to FP64 only
-// when it leaves the lane.
-
-__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
-    s = a + b;
-    const float bp = s - a;
-    e = (a - (s - bp)) + (b - bp);
-}
-
-__device__ __forceinline__ float flip_sign(float v, int par) {
-    return __uint_as_float(__float_as_uint(v) ^ (static_cast<uint32_t>(par & 1) << 31));
-}
-
-struct AccF32 {
-    float s = 0.f, c = 0.f;
-    __device__ __forceinline__ void add(float v, float err) {
-        float t, e;
-        two_sum(s, v, t, e);
-        s = t;
-        c += e + err;
-    }
-    __device__ __forceinline__ double value() const {
-        return static_cast<double>(s) + static_cast<double>(c);
-    }
-};
-
-template <int W>
-__device__ __forceinline__ AccF32 group_sum_f32(const DevTable &tab, int64_t g, const Key<W> &x,
-                                                unsigned long long *terms) {
-    const uint32_t t0 = tab.goff[g], t1 = tab.goff[g + 1];
-    AccF32 a;
-    for (uint32_t t = t0; t < t1; ++t) {
-        int par = 0;
-#pragma unroll
-        for (int q = 0; q < W; ++q) par += __popcll(tab.tz[2 * static_cast<size_t>(t) + q] & x.w[q]);
-        a.add(flip_sign(tab.tc32[2 * static_cast<size_t>(t)], par),
-              flip_sign(tab.tc32[2 * static_cast<size_t>(t) + 1], par));
-    }
-    *terms += t1 - t0;
-    return a;
-}
-
-// psi(x') / psi(x) in FP32 from the FP64 log-psi difference; the phase
-// difference is reduced to (-pi, pi] in FP64 before rounding.
-__device__ __forceinline__ void ratio_f32(double da, double dphi, float &rr, float &ri) {
-    constexpr double kTwoPi = 6.283185307179586476925286766559;
-    dphi -= kTwoPi * rint(dphi / kTwoPi);
-    const float mag = expf(static_cast<float>(da));
-    float sn, cs;
-    sincosf(static_cast<float>(dphi), &sn, &cs);
-    rr = mag * cs;
-    ri = mag * sn;
-}
-
 // One (sample tile, group chunk) work item on one block.  Each lane walks the
 // groups of the chunk in order; hits are added to the owning lane in queue
 // order, which is group order, so the partial sum does not depend on
@@ -800,10 +425,10 @@ __device__ __forceinline__ void lookup_item(
         n_terms += __shfl_xor(n_terms, off);
     }
     if (lane == 0) {
-        atomicAdd(&sc.counters[1], w_probe);
-        atomicAdd(&sc.counters[2], n_hit);
-        atomicAdd(&sc.counters[3], n_terms);
-        atomicAdd(&sc.counters[4], w_cand);
+        count_add(sc.counters, 1, w_probe);
+        count_add(sc.counters, 2, n_hit);
+        count_add(sc.counters, 3, n_terms);
+        count_add(sc.counters, 4, w_cand);
     }
 }
 
@@ -936,23 +561,6 @@ __device__ __forceinline__ void pair_of(int k, int &i, int &j) {
     if ((jj + 1) * jj / 2 <= k) ++jj;
     j = jj;
     i = k - jj * (jj - 1) / 2;
-}
-
-// Index of the group with flip mask X, or -1 (the group index is keyed by
-// h(X), which the caller has: h(x') ^ h(x)).
-template <int W>
-__device__ __forceinline__ int64_t group_find(const DevTable &tab, uint32_t hX, const Key<W> &X) {
-    const uint32_t mask = 0xFFFFFFFFu >> tab.gh_shift;
-    uint32_t slot = slot_of(hX, tab.gh_shift);
-    for (uint32_t probe = 0; probe <= mask; ++probe) {
-        const uint32_t g = tab.gh[slot];
-        if (g == 0xFFFFFFFFu) return -1;
-        bool eq = tab.gx[2 * static_cast<size_t>(g)] == X.w[0];
-        if constexpr (W == 2) eq = eq && tab.gx[2 * static_cast<size_t>(g) + 1] == X.w[1];
-        if (eq) return g;
-        slot = (slot + 1) & mask;
-    }
-    return -1;
 }
 
 struct EnumCounts {
@@ -1863,11 +1471,11 @@ __device__ __forceinline__ void enum_flush_counts(const DevScratch &sc, EnumCoun
         t += __shfl_xor(t, off);
     }
     if ((threadIdx.x & 63) == 0) {
-        if (c.probes) atomicAdd(&sc.counters[1], c.probes);
-        if (h) atomicAdd(&sc.counters[2], h);
-        if (t) atomicAdd(&sc.counters[3], t);
-        if (c.cand) atomicAdd(&sc.counters[4], c.cand);
-        if (c.rounds && threadIdx.x == 0) atomicAdd(&sc.counters[6], c.rounds);
+        count_add(sc.counters, 1, c.probes);
+        count_add(sc.counters, 2, h);
+        count_add(sc.counters, 3, t);
+        count_add(sc.counters, 4, c.cand);
+        if (threadIdx.x == 0) count_add(sc.counters, 6, c.rounds);
     }
     c = EnumCounts{};
 }
@@ -1968,6 +1576,7 @@ __global__ __launch_bounds__(kEnumThreads) void eloc_enum_kernel(
     // the filter at LDS address 0 (a static array: its address folds into
     // the read); records, lists and queues in the dynamic rest
     __shared__ uint4 s_filter[kEnumFilterWords / 4];
+    if (join_chosen(sc)) return;  // the pair join of this launch does the work
     const EnumShape S = enum_shape(tab, sc, samples, n);
     if (S.B <= 0) return;  // the streaming kernel of this launch does the work
     const int64_t n_rounds = (n + S.B - 1) / S.B;
@@ -2006,6 +1615,7 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
     int64_t g_first, int64_t chunk_len, int32_t *__restrict__ hit_idx,
     uint32_t *__restrict__ sign_bits, int64_t sign_words, int fallback_only) {
     extern __shared__ uint4 smem4[];
+    if (join_chosen(sc)) return;  // the pair join of this launch does the work
     // beside an enumeration launch this grid only runs when enumeration cannot
     if (fallback_only && enum_shape(tab, sc, samples, n).B > 0) return;
     lookup_item<W, S32, SEC, DUMP, P, SCV>(tab, sc, samples, log_amp, phase, n, blockIdx.x, blockIdx.y,
@@ -2017,29 +1627,41 @@ __global__ __launch_bounds__(kLookupThreads) void eloc_lookup_kernel(
 // each occupied qubit j in increasing order, d[1 + j] and the pair terms
 // d[1 + nq + j (j - 1) / 2 + i] of the occupied i < j (d: FP64 values, or
 // FP32 (hi, lo) pairs in the same 8 bytes for the compensated form).
+// The next set bit of (lo, hi) in increasing order (lo first), cleared.
+// Selects instead of branches: lanes whose sets have equally many bits run
+// the same number of steps whichever words the bits sit in.
+__device__ __forceinline__ int pop_lowest(uint64_t &lo, uint64_t &hi) {
+    const bool in_lo = lo != 0ull;
+    const uint64_t m = in_lo ? lo : hi;
+    const int q = (in_lo ? 0 : 64) + __builtin_ctzll(m);
+    const uint64_t cleared = m & (m - 1);
+    lo = in_lo ? cleared : lo;
+    hi = in_lo ? hi : cleared;
+    return q;
+}
+
+// <x|H_diag|x> from the occupation form of the X = 0 group: d[0] plus, for
+// each occupied qubit j in increasing order, d[1 + j] and the pair terms
+// d[1 + nq + j (j - 1) / 2 + i] of the occupied i < j in increasing order
+// (d: FP64 values, or FP32 (hi, lo) pairs in the same 8 bytes for the
+// compensated form).  Every sample of a one-sector batch takes the same
+// number of steps in both loops (the k-th occupied qubit has k below it).
 template <int W, int P>
 __device__ __forceinline__ double diag_occ_sum(const double *d, int nq, const Key<W> &x) {
     const double *d2 = d + 1 + nq;
+    const uint64_t x0 = x.w[0], x1 = W == 2 ? x.w[W - 1] : 0ull;
+    uint64_t a0 = x0, a1 = x1;
     if constexpr (P == NQS_FP64) {
         double acc = d[0];
-#pragma unroll
-        for (int qw = 0; qw < W; ++qw) {
-            uint64_t m = x.w[qw];
-            while (m) {
-                const int j = 64 * qw + __builtin_ctzll(m);
-                m &= m - 1;
-                const double *row = d2 + j * (j - 1) / 2;
-                double t = d[1 + j];
-#pragma unroll
-                for (int qi = 0; qi <= qw; ++qi) {
-                    uint64_t mi = x.w[qi] & (qi < qw ? ~0ull : ((1ull << (j & 63)) - 1ull));
-                    while (mi) {
-                        t += row[64 * qi + __builtin_ctzll(mi)];
-                        mi &= mi - 1;
-                    }
-                }
-                acc += t;
-            }
+        while (a0 | a1) {
+            const int j = pop_lowest(a0, a1);
+            const double *row = d2 + j * (j - 1) / 2;
+            double t = d[1 + j];
+            // the occupied qubits below j
+            uint64_t b0 = j >= 64 ? x0 : (x0 & ((1ull << j) - 1ull));
+            uint64_t b1 = j >= 64 ? (x1 & ((1ull << (j & 63)) - 1ull)) : 0ull;
+            while (b0 | b1) t += row[pop_lowest(b0, b1)];
+            acc += t;
         }
         return acc;
     } else {
@@ -2047,23 +1669,80 @@ __device__ __forceinline__ double diag_occ_sum(const double *d, int nq, const Ke
         const float2 *f2 = f + 1 + nq;
         AccF32 a;
         a.add(f[0].x, f[0].y);
-#pragma unroll
-        for (int qw = 0; qw < W; ++qw) {
-            uint64_t m = x.w[qw];
-            while (m) {
-                const int j = 64 * qw + __builtin_ctzll(m);
-                m &= m - 1;
-                const float2 *row = f2 + j * (j - 1) / 2;
-                a.add(f[1 + j].x, f[1 + j].y);
-#pragma unroll
-                for (int qi = 0; qi <= qw; ++qi) {
-                    uint64_t mi = x.w[qi] & (qi < qw ? ~0ull : ((1ull << (j & 63)) - 1ull));
-                    while (mi) {
-                        const float2 v = row[64 * qi + __builtin_ctzll(mi)];
-                        a.add(v.x, v.y);
-                        mi &= mi - 1;
-                    }
-                }
+        while (a0 | a1) {
+            const int j = pop_lowest(a0, a1);
+            const float2 *row = f2 + j * (j - 1) / 2;
+            a.add(f[1 + j].x, f[1 + j].y);
+            uint64_t b0 = j >= 64 ? x0 : (x0 & ((1ull << j) - 1ull));
+            uint64_t b1 = j >= 64 ? (x1 & ((1ull << (j & 63)) - 1ull)) : 0ull;
+            while (b0 | b1) {
+                const float2 v = row[pop_lowest(b0, b1)];
+                a.add(v.x, v.y);
+            }
+        }
+        return a.value();
+    }
+}
+
+// The same sum from a staged occupation form, with the occupied qubits first
+// written, in increasing order, as bytes into the lane's list in LDS
+// (interleaved across the block: entries 4w..4w+3 of this lane are the word
+// lst[w * stride]).  Four row entries are read per step, independently of
+// each other (the bit scan of the loop above makes every read wait for the
+// last), and added in the same order: the bits of the result are the same.
+template <int W, int P>
+__device__ __forceinline__ double diag_occ_sum_list(const double *d, int nq, const Key<W> &x,
+                                                    uint32_t *lst, int stride) {
+    uint64_t a0 = x.w[0], a1 = W == 2 ? x.w[W - 1] : 0ull;
+    int cnt = 0;
+    uint32_t word = 0;
+    while (a0 | a1) {
+        const int q = pop_lowest(a0, a1);
+        word |= static_cast<uint32_t>(q) << (8 * (cnt & 3));
+        if ((cnt & 3) == 3) {
+            lst[(cnt >> 2) * stride] = word;
+            word = 0;
+        }
+        ++cnt;
+    }
+    // the last word's unused bytes are 0 (a valid row index, never added)
+    if (cnt & 3) lst[(cnt >> 2) * stride] = word;
+    if constexpr (P == NQS_FP64) {
+        const double *d2 = d + 1 + nq;
+        double acc = d[0];
+        for (int k = 0; k < cnt; ++k) {
+            const int j = static_cast<int>((lst[(k >> 2) * stride] >> (8 * (k & 3))) & 0xFFu);
+            const double *row = d2 + j * (j - 1) / 2;
+            double t = d[1 + j];
+            for (int m = 0; m < k; m += 4) {
+                const uint32_t iw = lst[(m >> 2) * stride];
+                const double r0 = row[iw & 0xFFu], r1 = row[(iw >> 8) & 0xFFu];
+                const double r2 = row[(iw >> 16) & 0xFFu], r3 = row[iw >> 24];
+                t += r0;
+                if (m + 1 < k) t += r1;
+                if (m + 2 < k) t += r2;
+                if (m + 3 < k) t += r3;
+            }
+            acc += t;
+        }
+        return acc;
+    } else {
+        const float2 *f = reinterpret_cast<const float2 *>(d);
+        const float2 *f2 = f + 1 + nq;
+        AccF32 a;
+        a.add(f[0].x, f[0].y);
+        for (int k = 0; k < cnt; ++k) {
+            const int j = static_cast<int>((lst[(k >> 2) * stride] >> (8 * (k & 3))) & 0xFFu);
+            const float2 *row = f2 + j * (j - 1) / 2;
+            a.add(f[1 + j].x, f[1 + j].y);
+            for (int m = 0; m < k; m += 4) {
+                const uint32_t iw = lst[(m >> 2) * stride];
+                const float2 r0 = row[iw & 0xFFu], r1 = row[(iw >> 8) & 0xFFu];
+                const float2 r2 = row[(iw >> 16) & 0xFFu], r3 = row[iw >> 24];
+                a.add(r0.x, r0.y);
+                if (m + 1 < k) a.add(r1.x, r1.y);
+                if (m + 2 < k) a.add(r2.x, r2.y);
+                if (m + 3 < k) a.add(r3.x, r3.y);
             }
         }
         return a.value();
@@ -2080,10 +1759,14 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
                                            uint32_t *__restrict__ sign_bits, int64_t sign_words,
                                            int64_t i, const uint64_t *dz = nullptr,
                                            const double *dc = nullptr, int nd = 0,
-                                           const double *dq = nullptr) {
+                                           const double *dq = nullptr,
+                                           uint32_t *olist = nullptr) {
     unsigned long long n_terms = 0;
-    // an enumeration leaves one partial per sample
-    if (enum_on && enum_shape(tab, sc, samples, n).B > 0) n_chunks = 1;
+    // the pair join leaves one partial per block, an enumeration one per sample
+    if (join_chosen(sc))
+        n_chunks = tab.join_blocks;
+    else if (enum_on && enum_shape(tab, sc, samples, n).B > 0)
+        n_chunks = 1;
     if (i < n) {
         const Key<W> x = load_key<W>(samples, i);
         double re = 0.0, im = 0.0;
@@ -2093,7 +1776,9 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
             } else if (dq) {
                 // occupation form (the caller passes it staged or in place);
                 // counted as the X = 0 group's terms it stands for
-                re = diag_occ_sum<W, P>(dq, tab.n_qubits, x);
+                re = olist ? diag_occ_sum_list<W, P>(dq, tab.n_qubits, x, olist + threadIdx.x,
+                                                     static_cast<int>(blockDim.x))
+                           : diag_occ_sum<W, P>(dq, tab.n_qubits, x);
                 n_terms += static_cast<unsigned long long>(tab.goff[1] - tab.goff[0]);
             } else if (dz) {
                 // the X = 0 group staged in LDS by the caller (same order, same sums)
@@ -2135,9 +1820,11 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
         eloc[2 * i] = re;
         eloc[2 * i + 1] = im;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) n_terms += __shfl_xor(n_terms, off);
-    if ((threadIdx.x & 63) == 0 && n_terms) atomicAdd(&sc.counters[3], n_terms);
+    // every sample sums the whole X = 0 group: one count for the batch
+    (void)n_terms;
+    if (!SCV && tab.has_diagonal && blockIdx.x == 0 && threadIdx.x == 0)
+        count_add(sc.counters, 3,
+                  static_cast<unsigned long long>(n) * (tab.goff[1] - tab.goff[0]));
 }
 
 // Diagonal terms staged in LDS by the finish kernels (up to this many; a
@@ -2172,12 +1859,13 @@ __device__ __forceinline__ int stage_diagonal(const DevTable &tab, uint64_t *dz,
 // in LDS when it fits the staging area of the term form, else in place;
 // nullptr when the table has no such form.  Synchronises the block.
 template <int P>
-__device__ __forceinline__ const double *stage_diag_occ(const DevTable &tab, double *buf) {
+__device__ __forceinline__ const double *stage_diag_occ(const DevTable &tab, double *buf,
+                                                        int cap = 3 * kDiagLds) {
     if (!tab.diag_occ) return nullptr;
     const int nq = tab.n_qubits;
     const int cnt = 1 + nq + nq * (nq - 1) / 2;
     const double *src = P == NQS_FP64 ? tab.diag : reinterpret_cast<const double *>(tab.diag32);
-    if (cnt > 3 * kDiagLds) return src;
+    if (cnt > cap) return src;
     for (int k = threadIdx.x; k < cnt; k += blockDim.x) buf[k] = src[k];
     __syncthreads();
     return buf;
@@ -2187,17 +1875,23 @@ template <int W, bool DUMP, int P, bool SCV>
 __global__ __launch_bounds__(256) void eloc_finish_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n,
     int64_t n_chunks, int enum_on, double *__restrict__ eloc, int32_t *__restrict__ hit_idx,
-    uint32_t *__restrict__ sign_bits, int64_t sign_words) {
+    uint32_t *__restrict__ sign_bits, int64_t sign_words, int stage_cap, int list_words) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if constexpr (!DUMP && !SCV) {
-        // staging area: the diagonal's Z masks and coefficients, or its
+        // staging area (dynamic LDS of stage_cap doubles, at least
+        // 3 kDiagLds): the diagonal's Z masks and coefficients, or its
         // occupation form
-        __shared__ double stage[3 * kDiagLds];
-        const double *dq = stage_diag_occ<P>(tab, stage);
+        double *stage = reinterpret_cast<double *>(dyn_lds());
+        const double *dq = stage_diag_occ<P>(tab, stage, stage_cap);
         if (dq) {
+            // staged: the occupied-qubit lists follow the stage (list_words
+            // words per thread)
+            uint32_t *olist = (dq == stage && list_words > 0)
+                                  ? reinterpret_cast<uint32_t *>(stage + stage_cap)
+                                  : nullptr;
             finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc,
                                         hit_idx, sign_bits, sign_words, i, nullptr, nullptr, 0,
-                                        dq);
+                                        dq, olist);
             return;
         }
         uint64_t *dz = reinterpret_cast<uint64_t *>(stage);
@@ -2226,7 +1920,7 @@ __global__ void batch_reset_kernel(const JobDesc *__restrict__ jobs, int n_jobs,
                                    unsigned *__restrict__ next) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < n_jobs) {
-        for (int k = 0; k < kCounters; ++k) jobs[j].sc.counters[k] = 0;
+        for (int k = 0; k < kCounters * kCounterSlots; ++k) jobs[j].sc.counters[k] = 0;
         *jobs[j].sc.mixed = 0;
     }
     if (j == 0)
@@ -2636,6 +2330,17 @@ EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tu
     }
     L.n_chunks = chunks;
     L.chunk_len = g_eff > 0 ? (g_eff + chunks - 1) / chunks : 0;
+    // the pair join is launched beside the other strategy and decides on the
+    // device whether it runs (entries must fit 32-bit offsets)
+    L.join = 0;
+    L.join_force = 0;
+    L.join_log2m = 0;
+    if (tab.join_blocks > 0 && (want == kStrategyAuto || want == kStrategyJoin) &&
+        static_cast<int64_t>(tab.join_blocks) * n < (int64_t(1) << 31)) {
+        L.join = 1;
+        L.join_force = want == kStrategyJoin ? 1 : 0;
+        L.join_log2m = join_log2m_for(n);
+    }
     return L;
 }
 
@@ -2645,11 +2350,23 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
     const int words = tab.n_qubits <= 63 ? 1 : 2;
     const uint32_t fwords = 1u << sc.filter_log2;
     const uint32_t efwords = sc.eparts_log2 > 0 ? (1u << (sc.eparts_log2 + sc.efilter_log2)) : 0u;
+    const uint32_t jbuckets =
+        sc.jctl ? static_cast<uint32_t>(static_cast<int64_t>(tab.join_blocks) << sc.join_log2m) : 0u;
     uint32_t span = capacity > fwords ? capacity : fwords;
     span = span > efwords ? span : efwords;
+    span = span > jbuckets ? span : jbuckets;
+    const uint32_t n_counters = static_cast<uint32_t>(kCounters * kCounterSlots);
+    span = span > n_counters ? span : n_counters;
     hipLaunchKernelGGL(hash_clear_kernel, dim3((span + 255) / 256), dim3(256), 0, st, sc.skey,
                        sc.sidx, sc.sfp, words, capacity, sc.filter, fwords, sc.efilter, efwords,
-                       sc.counters, sc.mixed);
+                       sc.counters, sc.mixed, sc.jcnt, jbuckets, sc.jctl);
+    if (sc.jctl) {
+        // the pair join's grouping and decision come before the build, which
+        // skips its insertion when the join runs
+        const hipError_t e = launch_join_prep(tab, sc, samples, n,
+                                              tab.n_groups - (tab.has_diagonal ? 1 : 0), st);
+        if (e != hipSuccess) return e;
+    }
     const dim3 grid(static_cast<unsigned>((n + 255) / 256));
     if (words == 1)
         hipLaunchKernelGGL(hash_build_kernel<1>, grid, dim3(256), 0, st, tab, sc, samples, weights, n);
@@ -2697,6 +2414,19 @@ hipError_t launch_enum(const DevTable &tab, const DevScratch &sc, const EvalLaun
     return hipGetLastError();
 }
 
+// The finish kernel's dynamic LDS may pass 64 KB (a staged occupation form
+// plus the threads' occupied-qubit lists): raise its limit once.
+template <int W, bool D, int P>
+hipError_t allow_finish_lds() {
+    static bool done = false;
+    if (done) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&eloc_finish_kernel<W, D, P, false>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    if (e == hipSuccess) done = true;
+    return e;
+}
+
 hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
                        const uint64_t *samples, const double *log_amp, const double *phase,
                        double *eloc, int precision, int32_t *hit_idx, uint32_t *sign_bits,
@@ -2709,9 +2439,22 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
     const bool en = L.strategy == kStrategyEnum;
     const int fb = en ? 1 : 0;
     hipError_t e = hipSuccess;
+    if (sc.jctl) {
+        // a dump marks every pair first; the join (or the enumeration) writes
+        // only its hits
+        if (hit_idx) {
+            const int64_t cnt = n * tab.n_groups;
+            hipLaunchKernelGGL(fill_i32_kernel, dim3(static_cast<unsigned>((cnt + 255) / 256)),
+                               dim3(256), 0, st, hit_idx, cnt, -1);
+        }
+        e = launch_join_pairs(tab, sc, samples, log_amp, phase, n, precision, hit_idx, sign_bits,
+                              sign_words, st);
+        if (e != hipSuccess) return e;
+    }
     if (en) {
         // a dump marks every pair first; the enumeration writes only its hits
-        if (hit_idx) {
+        // (done above when a join was launched too)
+        if (hit_idx && !sc.jctl) {
             const int64_t cnt = n * tab.n_groups;
             hipLaunchKernelGGL(fill_i32_kernel, dim3(static_cast<unsigned>((cnt + 255) / 256)),
                                dim3(256), 0, st, hit_idx, cnt, -1);
@@ -2779,12 +2522,24 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
     }
     const int64_t chunks = L.chunk_len > 0 ? L.n_chunks : 0;
     const dim3 fgrid(static_cast<unsigned>((n + 255) / 256));
+    // the occupation form staged whole when it fits 64 KB (100 qubits: 40 KB)
+    const int occ_cnt = 1 + tab.n_qubits + tab.n_qubits * (tab.n_qubits - 1) / 2;
+    const int stage_cap = (tab.diag_occ && occ_cnt > 3 * kDiagLds && occ_cnt * 8 <= 65536)
+                              ? occ_cnt : 3 * kDiagLds;
+    // and, after it, each thread's list of occupied qubits (bytes, 4 a word)
+    const int list_words = tab.diag_occ ? (tab.n_qubits + 3) / 4 : 0;
+    const size_t stage_bytes =
+        (dump || tab.sc) ? 0 : sizeof(double) * stage_cap + size_t(256) * 4 * list_words;
 #define NQS_FINISH(Wd, D, Pr)                                                                 \
-    hipLaunchKernelGGL((eloc_finish_kernel<Wd, D, Pr, false>), fgrid, dim3(256), 0, st, tab, sc,  \
-                       samples, n, chunks, fb, eloc, hit_idx, sign_bits, sign_words)
+    do {                                                                                      \
+        if ((e = allow_finish_lds<Wd, D, Pr>()) != hipSuccess) return e;                     \
+        hipLaunchKernelGGL((eloc_finish_kernel<Wd, D, Pr, false>), fgrid, dim3(256),          \
+                           stage_bytes, st, tab, sc, samples, n, chunks, fb, eloc, hit_idx,   \
+                           sign_bits, sign_words, stage_cap, list_words);                     \
+    } while (0)
 #define NQS_FINISH_SC(Wd, D)                                                                     \
     hipLaunchKernelGGL((eloc_finish_kernel<Wd, D, NQS_FP64, true>), fgrid, dim3(256), 0, st, tab, \
-                       sc, samples, n, chunks, fb, eloc, hit_idx, sign_bits, sign_words)
+                       sc, samples, n, chunks, fb, eloc, hit_idx, sign_bits, sign_words, 0, 0)
     if (tab.sc) {
         if (words == 1) {
             if (dump) NQS_FINISH_SC(1, true); else NQS_FINISH_SC(1, false);

@@ -7,6 +7,11 @@
 
 namespace nqs {
 
+namespace detail {
+// Record msg as the calling thread's last error and return code (nqs_host.cpp).
+int fail(int code, const std::string &msg);
+}  // namespace detail
+
 // Maximum supported register width: samples and masks are two 64-bit words.
 constexpr int kMaxQubits = 127;
 

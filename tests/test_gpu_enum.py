@@ -131,7 +131,7 @@ def test_filter_partitions(torch_dev, filter_bits, workload_cache):
     by exactly its share of the flips."""
     w = workload_cache(("workload", "nq40"))
     ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
-    ham.set_tuning(filter_bits=filter_bits)
+    ham.set_tuning(filter_bits=filter_bits, strategy="enum")
     say(f"{w.name}: enumeration with {filter_bits} filter bits per sample")
     S = nqs.to_device_samples(w.samples)
     la = torch_dev.from_numpy(w.log_amp).cuda()
@@ -148,7 +148,7 @@ def test_filter_partitions(torch_dev, filter_bits, workload_cache):
     assert st["hits"] == int(nc.sum()) - w.n_samples
     assert st["enum_rounds"] > 0
     # more bits per sample: fewer filter survivors than the one-bitmap run
-    ham.set_tuning(filter_bits=16)
+    ham.set_tuning(filter_bits=16, strategy="enum")
     ham.eloc(S, la, ph)
     ham.sync()
     assert st["candidates"] < ham.stats()["candidates"]

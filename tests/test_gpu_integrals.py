@@ -126,6 +126,7 @@ def test_batch_mixes_both_forms(torch_dev, workload_cache):
     b.launch()
     torch.cuda.synchronize()
     for h, S, la, ph, _, out in jobs:
+        h.set_tuning(strategy="enum")  # the strategy a batch runs
         single = torch.view_as_real(h.eloc(S, la, ph)).cpu().numpy()
         h.sync()
         assert np.array_equal(single.view(np.uint64), out.cpu().numpy().view(np.uint64))

@@ -45,7 +45,7 @@ def upload(torch, samples, la, ph, weights=None):
 
 
 def gpu_eloc(torch, w, samples=None, la=None, ph=None, weights=None, spin=True,
-             precision="fp64", ham=None):
+             precision="fp64", ham=None, strategy="auto"):
     samples = w.samples if samples is None else samples
     la = w.log_amp if la is None else la
     ph = w.phase if ph is None else ph
@@ -53,6 +53,7 @@ def gpu_eloc(torch, w, samples=None, la=None, ph=None, weights=None, spin=True,
     own = ham is None
     if own:
         ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks if spin else None)
+    ham.set_tuning(strategy=strategy)
     S, la_t, ph_t, w_t = upload(torch, samples, la, ph, weights)
     e = ham.eloc(S, la_t, ph_t, w_t, precision=precision)
     ham.sync()
@@ -77,7 +78,7 @@ def nq12(workload_cache):
 
 def test_nq12_random_psi(torch_dev, nq12):
     say("nq12 random psi, 12 qubits, 400 samples")
-    e, st = gpu_eloc(torch_dev, nq12)
+    e, st = gpu_eloc(torch_dev, nq12, strategy="enum")
     ref, ab, nc = oracle.eloc(12, nq12.x, nq12.z, nq12.c, nq12.samples, nq12.log_amp, nq12.phase)
     assert_parity(e, ref, ab)
     G, T, conn = W.closed_form_counts(6, 3)
@@ -163,7 +164,7 @@ def test_nq12_lookups_and_signs_bit_exact(torch_dev, nq12):
 def test_nq40_reduced_full_parity(torch_dev, workload_cache):
     w = workload_cache(("workload", "nq40", 4096))
     say("nq40 40 qubits, 4096 samples, full parity")
-    e, st = gpu_eloc(torch_dev, w)
+    e, st = gpu_eloc(torch_dev, w, strategy="enum")
     ref, ab, nc = oracle.eloc(40, w.x, w.z, w.c, w.samples, w.log_amp, w.phase)
     assert_parity(e, ref, ab)
     G, T, conn = W.closed_form_counts(20, 10)
@@ -174,7 +175,7 @@ def test_nq40_reduced_full_parity(torch_dev, workload_cache):
 def test_nq40_full_size(torch_dev, workload_cache):
     w = workload_cache(("workload", "nq40"))
     say("nq40 40 qubits, 65536 samples, full oracle")
-    e, st = gpu_eloc(torch_dev, w)
+    e, st = gpu_eloc(torch_dev, w, strategy="enum")
     ref, ab, nc = oracle.eloc(40, w.x, w.z, w.c, w.samples, w.log_amp, w.phase)
     assert_parity(e, ref, ab)
     G, T, conn = W.closed_form_counts(20, 10)
@@ -195,7 +196,7 @@ def test_nq100_reduced_full_parity(torch_dev, workload_cache):
 def test_nq100_full_size_sampled_rows(torch_dev, workload_cache):
     w = workload_cache(("workload", "nq100"))
     say("nq100 100 qubits, 262144 samples, 192 sampled rows")
-    e, st = gpu_eloc(torch_dev, w)
+    e, st = gpu_eloc(torch_dev, w, strategy="enum")
     rows = np.sort(np.random.default_rng(9).choice(w.n_samples, 192, replace=False))
     rows[0], rows[-1] = 0, w.n_samples - 1
     ref, ab, _ = oracle.eloc_rows(100, w.x, w.z, w.c, w.samples, w.log_amp, w.phase, rows)
@@ -283,7 +284,8 @@ def test_mixed_sectors_switch_the_filter_off(torch_dev, workload_cache):
     rng = np.random.default_rng(8)
     la, ph = rng.normal(0, 1, S.shape[0]), rng.uniform(0, 2 * math.pi, S.shape[0])
     say("mixed sectors")
-    e, st = gpu_eloc(torch_dev, w, samples=S, la=la, ph=ph, weights=np.ones(S.shape[0], np.int64))
+    e, st = gpu_eloc(torch_dev, w, samples=S, la=la, ph=ph, weights=np.ones(S.shape[0], np.int64),
+                     strategy="enum")
     ref, ab, _ = oracle.eloc(12, w.x, w.z, w.c, S, la, ph)
     assert_parity(e, ref, ab)
     G, _, _ = W.closed_form_counts(6, 3)
@@ -404,3 +406,49 @@ def test_fp32_kahan_closure_set(torch_dev, workload_cache):
     m_ref, _, _ = oracle.energy(ones, ref)
     m32, _, _ = oracle.energy(ones, e32)
     assert abs(m32.real - m_ref.real) <= ENERGY_TOL_HA
+
+
+def test_failed_scratch_allocation_leaves_the_handle_usable(torch_dev, workload_cache):
+    """A scratch allocation that fails returns NQS_E_NOMEM; the buffer it
+    freed is recorded as empty, so a later, smaller batch allocates again and
+    evaluates correctly (no launch over a released buffer)."""
+    torch = torch_dev
+    w = workload_cache(("workload", "nq40", 4096))
+
+    def run(ham, n):
+        S, la, ph, _ = upload(torch, w.samples[:n], w.log_amp[:n], w.phase[:n])
+        e = ham.eloc(S, la, ph)
+        ham.sync()
+        return e.cpu().numpy()
+
+    def check(e, n):
+        ref, ab, _ = oracle.eloc(40, w.x, w.z, w.c, w.samples[:n], w.log_amp[:n], w.phase[:n])
+        assert_parity(e, ref, ab)
+
+    try:
+        ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
+        say("allocation failure: first evaluation of a fresh handle")
+        nqs.debug_fail_allocs(1)
+        with pytest.raises(nqs.NQSError) as ex:
+            run(ham, 1024)
+        assert ex.value.code == nqs.NQS_E_NOMEM
+        nqs.debug_fail_allocs(0)
+        check(run(ham, 512), 512)
+        ham.close()
+        # growth from 512 to 4096 samples reallocates the sample hash, the
+        # sample hashes, the partial sums and the pair join's buckets, in that
+        # order: each failure in turn, on a fresh handle
+        for k in (1, 2, 3, 4):
+            say(f"allocation failure: growth to 4096 samples, allocation {k} fails")
+            ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
+            run(ham, 512)
+            nqs.debug_fail_allocs(k)
+            with pytest.raises(nqs.NQSError) as ex:
+                run(ham, 4096)
+            assert ex.value.code == nqs.NQS_E_NOMEM
+            nqs.debug_fail_allocs(0)
+            check(run(ham, 256), 256)
+            check(run(ham, 4096), 4096)
+            ham.close()
+    finally:
+        nqs.debug_fail_allocs(0)

@@ -1,10 +1,12 @@
 """Serving loop: continuous batching, admission by HBM footprint, and the same
-result alone and in the mix (through the C ABI)."""
+result alone and in the mix (through the C ABI); served rows against the
+CPU oracle (Eq. 5 over each request's sample set)."""
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 import paper_2506_23809_amd as nqs
 import workloads as W
 
@@ -29,13 +31,13 @@ def torch_dev():
 @pytest.fixture(scope="module")
 def setup(torch_dev):
     torch = torch_dev
-    hams, payloads = [], []
+    hams, payloads, host = [], [], []
     for j, (nq, n) in enumerate(JOBS):
         K = nq // 2
         w = W.molecule([5, 100 + j], K, K // 2, K - K // 2, n, L=4.0, log_sigma=1.5,
                        name=f"serve-{j}")
         h = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
-        ps = []
+        ps, hs = [], []
         for r in range(3):
             rng = np.random.default_rng([5, 100 + j, 20 + r])
             s = W.sector_samples(rng, K, w.n_alpha, w.n_beta, n)
@@ -44,9 +46,11 @@ def setup(torch_dev):
             ps.append((nqs.to_device_samples(s), torch.from_numpy(la).cuda(),
                        torch.from_numpy(ph).cuda(), torch.from_numpy(w.weights).cuda(),
                        torch.zeros((n, 2), dtype=torch.float64, device="cuda")))
+            hs.append((s, la, ph))
         hams.append(h)
         payloads.append(ps)
-    yield hams, payloads
+        host.append((w, hs))
+    yield hams, payloads, host
     for h in hams:
         h.close()
 
@@ -61,7 +65,7 @@ def _alone(torch, h, p):
 @pytest.mark.parametrize("precision", ["fp64", "fp32k"])
 def test_each_result_same_alone_and_in_the_mix(torch_dev, setup, precision):
     torch = torch_dev
-    hams, payloads = setup
+    hams, payloads, host = setup
     srv = nqs.Server(8 * 1024 ** 3, streams=3, max_batch=8, precision=precision)
     for h, (nq, n) in zip(hams, JOBS):
         srv.add(h, n)
@@ -82,15 +86,28 @@ def test_each_result_same_alone_and_in_the_mix(torch_dev, setup, precision):
     srv.close()
     for (j, r), e_mix in served.items():
         S, la, ph, wt, _ = payloads[j][r]
+        # the server runs batches, which take the enumeration (never the pair
+        # join): alone means the single launch with that strategy
+        hams[j].set_tuning(strategy="enum")
         e = hams[j].eloc(S, la, ph, wt, precision=precision)
         hams[j].sync()
+        hams[j].set_tuning(strategy="auto")
         e_alone = torch.view_as_real(e).cpu().numpy()
         assert np.array_equal(e_alone.view(np.uint64), e_mix.view(np.uint64)), (j, r)
+        # and against the oracle on 32 sampled rows of every served request
+        w, hs = host[j]
+        s_np, la_np, ph_np = hs[r]
+        rows = np.sort(np.random.default_rng([j, r]).choice(s_np.shape[0], 32, replace=False))
+        ref, ab, _ = oracle.eloc_rows(w.n_qubits, w.x, w.z, w.c, s_np, la_np, ph_np, rows)
+        got = e_mix[rows, 0] + 1j * e_mix[rows, 1]
+        tol = 1e-12 if precision == "fp64" else 1e-6
+        err = np.abs(got - ref)
+        assert np.all(err <= tol * ab), (j, r, float(np.max(err / ab)))
 
 
 def test_admission_respects_the_budget(torch_dev, setup):
     torch = torch_dev
-    hams, payloads = setup
+    hams, payloads, _ = setup
     # tables of all handles are resident; leave room for exactly one request
     probe = nqs.Server(1 << 40, streams=1, max_batch=1)
     resident = []

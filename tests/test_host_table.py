@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(nqs.EXPORTS)
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.nqs_version() == 100
+    assert lib.nqs_version() == 101
 
 
 def _ny(x, z):

@@ -295,6 +295,56 @@ def test_oracle_matches_slater_condon_on_closure_sets(K, n, L, workload_cache):
         assert abs(el[k] - ref_el) <= 1e-12 * ab[k]
 
 
+def _absum_from_terms(x, c, S, la):
+    """A(x) written out from its definition, in numpy: the diagonal group's
+    sum of |c_t|, plus, for every other x' in S reached by some X_t = x ^ x',
+    |psi(x') / psi(x)| = exp(a(x') - a(x)) times the sum of |c_t| over the
+    terms with that X."""
+    groups = {}
+    for (a, b), cc in zip(x.tolist(), np.abs(c).tolist()):
+        groups.setdefault((a, b), []).append(cc)
+    gsum = {k: math.fsum(v) for k, v in groups.items()}
+    maxpop = max(int(np.bitwise_count(np.uint64(a))) + int(np.bitwise_count(np.uint64(b)))
+                 for a, b in groups)
+    n = S.shape[0]
+    A = np.zeros(n)
+    for i in range(n):
+        d0 = S[i, 0] ^ S[:, 0]
+        d1 = S[i, 1] ^ S[:, 1]
+        near = np.nonzero(np.bitwise_count(d0).astype(int) + np.bitwise_count(d1) <= maxpop)[0]
+        parts = []
+        for j in near.tolist():
+            g = gsum.get((int(d0[j]), int(d1[j])))
+            if g is not None:
+                parts.append(math.exp(la[j] - la[i]) * g)
+        A[i] = math.fsum(parts)
+    return A
+
+
+@pytest.mark.parametrize("case", ["nq12", "closure100"])
+def test_oracle_absum_equals_its_definition(case, nq12, workload_cache):
+    """The scale A(x) that every floating-point tolerance is taken against is
+    what its definition says: an inflated A(x) (a doubled group, a ratio
+    taken the wrong way round) would loosen every parity check silently."""
+    if case == "nq12":
+        x, z, c, S = nq12.x, nq12.z, nq12.c, nq12.samples
+        la, ph = _random_psi(np.random.default_rng(31), S.shape[0], 1.0)
+        nq = 12
+    else:
+        def make():
+            h, eri = W.integrals(np.random.default_rng([2, 0]), 50, 6.0)
+            x_, z_, c_ = W.jw_terms(h, eri)
+            return h, eri, x_, z_, c_
+        _, _, x, z, c = workload_cache(("ham", 50), make)
+        S = closure_set(50, 25, 2, 150, seed=50)
+        la, ph = _random_psi(np.random.default_rng(32), S.shape[0], 1.0)
+        nq = 100
+    _, ab, nc = oracle.eloc(nq, x, z, c, S, la, ph)
+    A = _absum_from_terms(x, c, S, la)
+    assert (nc > 1).sum() > S.shape[0] // 2
+    assert np.all(np.abs(ab - A) <= 1e-13 * A), np.max(np.abs(ab - A) / A)
+
+
 # ---------------------------------------------------------------- energy
 
 

@@ -216,6 +216,61 @@ def sector_samples(rng: np.random.Generator, K: int, na: int, nb: int, n_samples
     return np.array(kept, dtype=np.uint64).reshape(n_samples, 2)
 
 
+def planted_samples(rng: np.random.Generator, K: int, na: int, nb: int, n_base: int,
+                    n_total: int, per_kind: int = 3) -> np.ndarray:
+    """A uniform sector batch with planted neighbours (hit-heavy rows inside a
+    hit-sparse batch).
+
+    n_base uniform sector states each bring per_kind alpha singles, beta
+    singles, alpha-alpha, beta-beta and alpha-beta doubles of themselves
+    (occupied orbitals emptied, virtual ones filled, same spin counts); the
+    rest of the batch is uniform sector draws.  Unique, shuffled, n_total
+    states in all.
+    """
+    nq = 2 * K
+    base = sector_samples(rng, K, na, nb, n_base)
+    out = {}
+    for w in base:
+        out[(int(w[0]), int(w[1]))] = w
+    bits = unpack_bits(base, nq)
+    planted = []
+    for row in bits:
+        occ = [np.nonzero(row[s::2])[0] for s in (0, 1)]
+        vir = [np.nonzero(~row[s::2])[0] for s in (0, 1)]
+        kinds = ((1, 0), (0, 1), (2, 0), (0, 2), (1, 1))  # excitations per spin
+        for ea, eb in kinds:
+            for _ in range(per_kind):
+                r = row.copy()
+                ok = True
+                for spin, e in ((0, ea), (1, eb)):
+                    if e == 0:
+                        continue
+                    if len(occ[spin]) < e or len(vir[spin]) < e:
+                        ok = False
+                        break
+                    i = rng.choice(occ[spin], e, replace=False)
+                    a = rng.choice(vir[spin], e, replace=False)
+                    r[2 * i + spin] = False
+                    r[2 * a + spin] = True
+                if ok:
+                    planted.append(r)
+    if planted:
+        for w in pack_bits(np.array(planted)):
+            out.setdefault((int(w[0]), int(w[1])), w)
+    rest = n_total - len(out)
+    if rest < 0:
+        raise ValueError("n_total smaller than the planted set")
+    extra = sector_samples(rng, K, na, nb, rest + len(out))
+    for w in extra:
+        if len(out) == n_total:
+            break
+        out.setdefault((int(w[0]), int(w[1])), w)
+    if len(out) < n_total:
+        raise ValueError("sector too small for n_total unique states")
+    arr = np.array(list(out.values()), dtype=np.uint64).reshape(-1, 2)
+    return arr[rng.permutation(arr.shape[0])]
+
+
 def geometric_weights(rng: np.random.Generator, n: int) -> np.ndarray:
     """w = 1 + G with P(G = k) = 0.3 * 0.7^k (numpy's geometric(0.3), support >= 1)."""
     return rng.geometric(0.3, size=n).astype(np.int64)
