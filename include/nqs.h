@@ -165,6 +165,31 @@ int nqs_eloc_eval(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *
                   void *hip_stream);
 
 /*
+ * nqs_eloc_eval for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results as nqs_eloc_eval (bit for bit, same launch
+ * plan), but the evaluation scratch comes from one array of
+ * NQS_NOALLOC_SCRATCH_BYTES held by the library on every device it runs on
+ * for the life of the process, and the call makes no allocation of any kind
+ * (it also never captures or replays a graph).
+ *
+ * The array is shared by every call on a device and keeps the last call's
+ * contents; whatever must start cleared is cleared on the stream by the
+ * call's own kernels.  Two calls that overlap on one device (different
+ * streams, threads or handles) race on it and give undefined results: the
+ * caller serialises them.  The scratch needed grows with n (at 100 qubits
+ * and 262,144 samples about 126 MB, the pair join's buckets included): a
+ * batch that needs more than the array holds returns NQS_E_ARG before
+ * anything is launched.  Arguments, other
+ * errors and asynchrony as nqs_eloc_eval; NQS_E_STATE also when the
+ * handle's device is not the current one.
+ */
+#define NQS_NOALLOC_SCRATCH_BYTES (160ull << 20)
+int nqs_eloc_eval_noalloc(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weights,
+                          const double *log_amp, const double *phase, double *eloc, int precision,
+                          void *hip_stream);
+
+/*
  * Count-weighted energy of Eq. 1 over unique samples:
  *   out[0] = Re E, out[1] = Im E with E = sum w E_loc / sum w,
  *   out[2] = sum w |E_loc - E|^2 / sum w (population variance, second pass),
@@ -198,7 +223,7 @@ int nqs_sync(nqs_ham h, void *hip_stream);
 int nqs_eval_stats(nqs_ham h, int64_t out[6]);
 
 /*
- * Launch plan of the last nqs_eloc_eval on this
+ * Launch plan of the last nqs_eloc_eval (or nqs_eloc_eval_noalloc) on this
  * handle; out[0..6] are host-side and valid as soon as the call has
  * returned, out[7] after nqs_sync:
  *   out[0] strategy planned besides the pair join: NQS_STRATEGY_STREAM or

@@ -32,13 +32,14 @@ NQS_E_STATE = -7
 
 NQS_FP64 = 0
 NQS_FP32_KAHAN = 1
+NOALLOC_SCRATCH_BYTES = 160 << 20  # NQS_NOALLOC_SCRATCH_BYTES
 _PRECISION = {"fp64": NQS_FP64, "fp32k": NQS_FP32_KAHAN, "fp32_kahan": NQS_FP32_KAHAN}
 
 # Every symbol include/nqs.h declares.
 EXPORTS = ("nqs_last_error", "nqs_version", "nqs_ham_create", "nqs_ham_create_integrals",
            "nqs_ham_info", "nqs_ham_destroy",
            "nqs_table_host", "nqs_eloc_eval", "nqs_energy", "nqs_sync", "nqs_eval_stats",
-           "nqs_eval_plan", "nqs_debug_fail_allocs",
+           "nqs_eval_plan", "nqs_debug_fail_allocs", "nqs_eloc_eval_noalloc",
            "nqs_debug_dump", "nqs_profile", "nqs_last_kernel_ms", "nqs_set_tuning",
            "nqs_get_tuning", "nqs_autotune", "nqs_batch_create", "nqs_batch_launch",
            "nqs_batch_capture", "nqs_batch_replay", "nqs_batch_destroy", "nqs_server_create",
@@ -102,6 +103,7 @@ def load_library(path: str = LIB_PATH):
         "nqs_ham_destroy": (I, [P]),
         "nqs_table_host": (I, [I, I64, P, P, P, P, P, P, P, P, P]),
         "nqs_eloc_eval": (I, [P, I64, P, P, P, P, P, I, P]),
+        "nqs_eloc_eval_noalloc": (I, [P, I64, P, P, P, P, P, I, P]),
         "nqs_energy": (I, [I64, P, P, P, P]),
         "nqs_sync": (I, [P, P]),
         "nqs_eval_stats": (I, [P, P]),
@@ -256,6 +258,20 @@ class Hamiltonian:
         n = samples.shape[0]
         wp = None if weights is None else _dptr(weights, torch.int64)
         _check(load_library().nqs_eloc_eval(
+            self._h, n, _dptr(samples, torch.int64, 2), wp, _dptr(log_amp, torch.float64),
+            _dptr(phase, torch.float64), _dptr(out, torch.float64, 2), _PRECISION[precision],
+            _stream(stream)))
+        return out
+
+    def eloc_noalloc_into(self, out, samples, log_amp, phase, weights=None, precision="fp64",
+                          stream=None):
+        """nqs_eloc_eval_noalloc: as eloc_into, with the library's fixed
+        scratch array instead of allocated scratch (calls on one device must
+        not overlap)."""
+        import torch
+        n = samples.shape[0]
+        wp = None if weights is None else _dptr(weights, torch.int64)
+        _check(load_library().nqs_eloc_eval_noalloc(
             self._h, n, _dptr(samples, torch.int64, 2), wp, _dptr(log_amp, torch.float64),
             _dptr(phase, torch.float64), _dptr(out, torch.float64, 2), _PRECISION[precision],
             _stream(stream)))

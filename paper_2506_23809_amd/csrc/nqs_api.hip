@@ -18,6 +18,11 @@
 #include "nqs_internal.hpp"
 #include "nqs_table.hpp"
 
+// Scratch of nqs_eloc_eval_noalloc (one copy per device, in the library's
+// code object).  Its name is a host-side stand-in: host code takes the
+// device address with hipGetSymbolAddress and uses only that.
+static __device__ __align__(256) unsigned char scratch[NQS_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 int fail(int code, const std::string &msg) { return nqs::detail::fail(code, msg); }
@@ -424,6 +429,119 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
     return NQS_OK;
 }
 
+// ---- the entry point that allocates nothing (nqs_eloc_eval_noalloc)
+//
+// Its evaluation scratch (sample hash, sample hashes, partial sums, filters,
+// the enumeration's block areas) is carved out of one file-scope device
+// array, resident on every device the library runs on for the life of the
+// process.  Host code never uses the array's name as an address: the
+// device address is taken once per device with hipGetSymbolAddress and kept.
+constexpr size_t kNoAllocBytes = static_cast<size_t>(NQS_NOALLOC_SCRATCH_BYTES);
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mutex;
+void *g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (looked up on first use,
+// with the device current).
+int noalloc_base(int dev, char **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(NQS_E_DEVICE, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail_hip(e, "hipGetSymbolAddress of the scratch array");
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = static_cast<char *>(g_noalloc_ptr[dev]);
+    return NQS_OK;
+}
+
+// Lay the scratch of one evaluation out from base (256-byte aligned pieces):
+// slots, sample hashes, partial sums, filter, filter partitions, block
+// areas.  Returns the bytes it needs; fills *sc only when they fit in cap.
+size_t layout_scratch(nqs_ham h, const nqs::EvalLaunch &L, int64_t n, int n_cu, char *base,
+                      size_t cap, nqs::DevScratch *sc) {
+    uint64_t slots = 64;
+    while (slots < nqs::kSlotsPerSample * static_cast<uint64_t>(n)) slots <<= 1;
+    const int64_t chunks = plan_chunks(h, L);
+    const size_t sizes[7] = {
+        slot_array_bytes(static_cast<uint32_t>(slots), h->words),
+        sizeof(uint32_t) * static_cast<size_t>(n),
+        sizeof(double) * 2 * static_cast<size_t>(n) * chunks,
+        kMaxFilterWords * 4,
+        L.eparts_log2 > 0 ? kMaxEFilterWords * 4 : 0,
+        h->dt.enum_ok ? static_cast<size_t>(enum_blk_stride(h->dt)) * n_cu : 0,
+        plan_join_bytes(h, L),
+    };
+    size_t off[7];
+    size_t total = 0;
+    for (int k = 0; k < 7; ++k) {
+        off[k] = total;
+        total = align_up(total + sizes[k], 256);
+    }
+    if (slots > (1ull << 31) || total > cap) return total;
+    set_slots(sc, base + off[0], static_cast<uint32_t>(slots), h->words);
+    sc->shx = reinterpret_cast<uint32_t *>(base + off[1]);
+    sc->part = reinterpret_cast<double *>(base + off[2]);
+    sc->filter = reinterpret_cast<uint32_t *>(base + off[3]);
+    sc->efilter = L.eparts_log2 > 0 ? reinterpret_cast<uint32_t *>(base + off[4]) : sc->filter;
+    sc->eblk = h->dt.enum_ok ? base + off[5] : nullptr;
+    sc->eblk_stride = h->dt.enum_ok ? enum_blk_stride(h->dt) : 0;
+    sc->eblk_blocks = h->dt.enum_ok ? static_cast<uint32_t>(n_cu) : 0;
+    sc->counters = static_cast<unsigned long long *>(h->small);
+    sc->err = reinterpret_cast<int *>(static_cast<char *>(h->small) + kErrOffset);
+    sc->mixed = reinterpret_cast<int *>(static_cast<char *>(h->small) + kErrOffset + 4);
+    sc->filter_log2 = L.filter_log2;
+    sc->eparts_log2 = L.eparts_log2;
+    sc->efilter_log2 = L.efilter_log2;
+    if (L.join) {
+        nqs::join_scratch_layout(h->dt, n, L.join_log2m, base + off[6], sc);
+        sc->join_force = L.join_force;
+    }
+    return total;
+}
+
+int eval_noalloc(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weights,
+                 const double *log_amp, const double *phase, double *eloc, int precision,
+                 void *stream) {
+    if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
+    if (n < 0) return fail(NQS_E_ARG, "n < 0");
+    if (precision != NQS_FP64 && precision != NQS_FP32_KAHAN)
+        return fail(NQS_E_ARG, "unknown precision");
+    if (h->dt.sc && precision != NQS_FP64)
+        return fail(NQS_E_ARG, "the integral form evaluates in FP64 only");
+    if (n == 0) return NQS_OK;
+    if (!samples || !log_amp || !phase || !eloc)
+        return fail(NQS_E_ARG, "null sample, amplitude, phase or output pointer");
+    if (n > (int64_t(1) << 30)) return fail(NQS_E_ARG, "batch larger than 2^30 samples");
+    int dev = -1;
+    NQS_HIP(hipGetDevice(&dev));
+    if (dev != h->device) return fail(NQS_E_STATE, "the handle's device is not current");
+    int n_cu = 0;
+    NQS_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const nqs::EvalLaunch L = nqs::plan_eval(h->dt, n, false, &h->tune);
+    nqs::DevScratch sc{};
+    const size_t need = layout_scratch(h, L, n, n_cu, nullptr, 0, &sc);
+    if (need > kNoAllocBytes)
+        return fail(NQS_E_ARG, "batch needs " + std::to_string(need) +
+                                   " bytes of scratch, more than the " +
+                                   std::to_string(kNoAllocBytes) +
+                                   " the allocation-free entry point holds");
+    char *base = nullptr;
+    int rc = noalloc_base(dev, &base);
+    if (rc) return rc;
+    layout_scratch(h, L, n, n_cu, base, kNoAllocBytes, &sc);
+    NQS_HIP(issue_eval(h, sc, L, n, samples, weights, log_amp, phase, eloc, precision, nullptr,
+                       nullptr, static_cast<hipStream_t>(stream)));
+    if (h->profiling) h->profiled = true;
+    h->last_pairs = n * h->dt.n_groups;
+    h->last_plan = L;
+    h->last_jctl = sc.jctl;
+    h->ever_evaluated = true;
+    return NQS_OK;
+}
+
 // Process-wide scratch of nqs_energy, one per device, used under a lock.
 struct EnergyScratch {
     double *dev = nullptr;   // part[3*256] | result[3] | out[4]
@@ -679,6 +797,12 @@ int nqs_eloc_eval(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *
                   void *hip_stream) {
     return eval_impl(h, n, samples, weights, log_amp, phase, eloc, precision, nullptr, nullptr,
                      hip_stream);
+}
+
+int nqs_eloc_eval_noalloc(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weights,
+                          const double *log_amp, const double *phase, double *eloc, int precision,
+                          void *hip_stream) {
+    return eval_noalloc(h, n, samples, weights, log_amp, phase, eloc, precision, hip_stream);
 }
 
 int nqs_profile(nqs_ham h, int enable) {
