@@ -146,9 +146,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32k"])
     ap.add_argument("--filter-bits", type=int, default=0,
                     help="on-chip filter bits per sample (0: the library's default)")
-    ap.add_argument("--strategy", default="auto", choices=["auto", "stream", "enum"],
-                    help="lookup strategy: group streaming or flip enumeration (auto: "
-                         "enumeration where the table allows it)")
+    ap.add_argument("--strategy", default="auto", choices=["auto", "stream", "enum", "join"],
+                    help="lookup strategy: group streaming, flip enumeration or pair join "
+                         "(auto: the device picks by counted cost)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--mode", default="single", choices=["single", "batched", "serve", "copy"],
@@ -157,8 +157,10 @@ def main():
                          "copy: a plain 1 GiB device copy, the calibration of the HBM byte "
                          "counters")
     ap.add_argument("--jobs", type=int, default=32, help="Hamiltonians in the batched family")
-    ap.add_argument("--requests", type=int, default=400, help="serve: requests in the trace")
-    ap.add_argument("--rate", type=float, default=200.0, help="serve: aggregate arrivals per second")
+    ap.add_argument("--requests", type=int, default=2000,
+                    help="serve: requests per point of the sweep")
+    ap.add_argument("--rates", default="200,1000,2000,3000,4000,inf",
+                    help="serve: aggregate arrival rates per second to sweep (inf: all at once)")
     ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_2506_23809_amd",
                                                            "tuning_mi355x.json"))
     args = ap.parse_args()

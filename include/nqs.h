@@ -400,55 +400,63 @@ int nqs_batch_destroy(nqs_batch b);
 /* ------------------------------------------------------------------ serving
  *
  * A request loop with continuous batching.  Hamiltonians are registered
- * once (their tables stay resident, their scratch is sized for the largest
- * request they will see).  nqs_server_submit enqueues an E_loc request
+ * once (their tables stay resident).  The device is divided into lanes
+ * (streams, 1..8): each lane owns evaluation scratch (sample hash, partial
+ * sums, filters, pair-join buckets) sized for the largest request any
+ * registered handle will send, plus its own counters and error latch, all
+ * allocated at registration.  nqs_server_submit enqueues an E_loc request
  * (nqs_batch_item: handle, batch, amplitudes, output) and returns at once.
- * A dispatcher thread admits pending requests in arrival order whenever a
- * stream slot is free and the request's handle is not already running;
- * admission also requires that the resident tables plus the footprint of
- * every request on the device stay within hbm_budget_bytes.  The admitted
- * requests are evaluated together as one batched launch on that stream,
- * so batches on different streams overlap on the device, and requests that
- * arrive while others run join the next launch as slots free up.  A
- * request's result is the same as its nqs_eloc_eval result (same kernels,
- * same per-handle plan).
+ * A dispatcher thread admits pending requests in arrival order into free
+ * lanes, as long as the resident data plus the footprint of every request
+ * on the device stays within hbm_budget_bytes, and launches each on its
+ * lane with the plan nqs_eloc_eval would take (the device picks the pair
+ * join, the enumeration or streaming).  Lanes run concurrently, so requests
+ * that arrive while others run join the device's work as lanes free up,
+ * whatever handle they use (two requests for one handle overlap on two
+ * lanes); each request completes on its own lane event.  A request's result
+ * is the same as its nqs_eloc_eval result, bit for bit (same kernels, same
+ * plan).
  *
  * Footprint of a request: 56 bytes per sample (samples, log_amp, phase,
- * counts, output) plus the handle's scratch.  Requests whose footprint plus
- * the resident tables exceed the budget are rejected at submission
- * (NQS_E_NOMEM).  Device-detected errors of a request (duplicates, bits out
- * of range) stay latched on its handle until nqs_sync.
+ * counts, output).  Resident: the tables and the lanes' scratch.  Requests
+ * whose footprint plus the resident data exceed the budget are rejected at
+ * submission (NQS_E_NOMEM).  Device-detected errors of a request
+ * (duplicates, bits out of range) are latched on its handle and returned by
+ * the next nqs_sync on that handle; the server goes on serving.
  */
 typedef struct {
     int64_t hbm_budget_bytes; /* admission budget (> 0) */
-    int32_t streams;          /* batches in flight at once, 1..8 (0 = 4) */
-    int32_t max_batch;        /* requests per launch, 1..256 (0 = 64) */
+    int32_t streams;          /* lanes: requests on the device at once, 1..8 (0 = 4) */
     int32_t precision;        /* NQS_FP64 or NQS_FP32_KAHAN */
-    int32_t threads;          /* lookup block size (0 = default) */
 } nqs_server_config;
 
 typedef struct nqs_server_s *nqs_server; /* opaque, owned by the library */
 
 /* Start a server (and its dispatcher thread) on the current device. */
 int nqs_server_create(nqs_server *out, const nqs_server_config *cfg);
-/* Register a handle: its table counts as resident; its scratch is grown for
- * max_samples.  NQS_E_NOMEM if the resident total would exceed the budget. */
+/* Register a handle: its table counts as resident, and every lane's scratch
+ * is grown (when no request runs) to hold a request of max_samples for it.
+ * NQS_E_NOMEM if the resident total would exceed the budget or the lanes'
+ * scratch cannot be allocated; NQS_E_STATE if the lanes must grow while
+ * requests run. */
 int nqs_server_add_ham(nqs_server s, nqs_ham h, int64_t max_samples);
 /* Enqueue a request (thread-safe).  *ticket identifies it in nqs_server_poll.
- * Errors: NQS_E_ARG (unregistered handle, bad item), NQS_E_NOMEM (can never
- * fit the budget), NQS_E_STATE (server stopping or failed). */
+ * Errors: NQS_E_ARG (unregistered handle, more samples than its registered
+ * max_samples, bad item), NQS_E_NOMEM (can never fit the budget),
+ * NQS_E_STATE (server stopping or failed). */
 int nqs_server_submit(nqs_server s, const nqs_batch_item *req, int64_t *ticket);
 /* Move up to capacity finished requests out: their tickets and their
- * latencies in microseconds (submission to completion of their launch);
+ * latencies in microseconds (submission to completion on its lane);
  * *n_out receives the count.  Returns the dispatcher's error, if any. */
 int nqs_server_poll(nqs_server s, int64_t *tickets, double *latency_us, int capacity,
                     int *n_out);
 /* Wait until every submitted request has finished, or timeout_s elapses
  * (NQS_E_STATE). */
 int nqs_server_drain(nqs_server s, double timeout_s);
-/* out[0] submitted, [1] completed, [2] rejected, [3] launches,
- * [4] most requests in flight at once, [5] most launches in flight at once,
- * [6] peak admitted bytes (resident + in flight), [7] resident bytes. */
+/* out[0] submitted, [1] completed, [2] rejected, [3] launches (one per
+ * request), [4] most requests in flight at once, [5] the same (lanes busy at
+ * once), [6] peak admitted bytes (resident + in flight), [7] resident bytes
+ * (tables and lane scratch). */
 int nqs_server_stats(nqs_server s, int64_t out[8]);
 /* Finish outstanding requests, stop the dispatcher and release everything.
  * NULL is accepted. */

@@ -49,8 +49,7 @@ EXPORTS = ("nqs_last_error", "nqs_version", "nqs_ham_create", "nqs_ham_create_in
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("threads", ctypes.c_int32)]
+                ("precision", ctypes.c_int32)]
 
 
 STRATEGIES = {"auto": 0, "stream": 1, "enum": 2, "join": 3}
@@ -417,11 +416,11 @@ def _item(ham, S, la, ph, w, out):
 
 
 class Server:
-    """nqs_server_*: request loop with continuous batching (see include/nqs.h)."""
+    """nqs_server_*: request loop with continuous batching over lanes (streams
+    with their own scratch); see include/nqs.h."""
 
-    def __init__(self, hbm_budget_bytes, streams=4, max_batch=64, precision="fp64", threads=0):
-        cfg = ServerConfig(int(hbm_budget_bytes), int(streams), int(max_batch),
-                           _PRECISION[precision], int(threads))
+    def __init__(self, hbm_budget_bytes, streams=4, precision="fp64"):
+        cfg = ServerConfig(int(hbm_budget_bytes), int(streams), _PRECISION[precision])
         s = ctypes.c_void_p()
         _check(load_library().nqs_server_create(ctypes.byref(s), ctypes.byref(cfg)))
         self._s = s

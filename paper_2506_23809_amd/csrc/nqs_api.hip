@@ -71,6 +71,9 @@ struct nqs_ham_s {
     void *jmem = nullptr;  // the pair join's buckets and entries
     size_t jmem_bytes = 0;
     void *small = nullptr; // counters[8] u64, err, mixed
+    // an error a server lane saw for one of this handle's requests, reported
+    // by the next nqs_sync like a latched device error
+    std::atomic<int> host_err{0};
     int64_t last_pairs = 0;
     bool ever_evaluated = false;
     nqs::EvalLaunch last_plan{};  // launch plan of the last evaluation
@@ -299,18 +302,19 @@ static_assert(sizeof(EvalKey) <= sizeof(nqs_ham_s::eval_key), "key fits");
 hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunch &L, int64_t n,
                       const uint64_t *samples, const int64_t *weights, const double *log_amp,
                       const double *phase, double *eloc, int precision, int32_t *hit_idx,
-                      uint32_t *sign_bits, hipStream_t s) {
+                      uint32_t *sign_bits, hipStream_t s, bool may_profile = true) {
     hipError_t e;
-    if (h->profiling && (e = hipEventRecord(h->ev[0], s)) != hipSuccess) return e;
+    const bool prof = h->profiling && may_profile;
+    if (prof && (e = hipEventRecord(h->ev[0], s)) != hipSuccess) return e;
     if ((e = nqs::launch_hash(h->dt, sc, sc.slot_mask + 1u, samples, weights, n, s)) != hipSuccess)
         return e;
-    if (h->profiling && (e = hipEventRecord(h->ev[1], s)) != hipSuccess) return e;
+    if (prof && (e = hipEventRecord(h->ev[1], s)) != hipSuccess) return e;
     const int64_t sign_words = (h->dt.n_terms + 31) / 32;
-    nqs::EvalStageEvents stages{h->profiling ? h->ev[2] : nullptr};
+    nqs::EvalStageEvents stages{prof ? h->ev[2] : nullptr};
     if ((e = nqs::launch_eloc(h->dt, sc, L, samples, log_amp, phase, eloc, precision, hit_idx,
                               sign_bits, sign_words, stages, s)) != hipSuccess)
         return e;
-    if (h->profiling && (e = hipEventRecord(h->ev[3], s)) != hipSuccess) return e;
+    if (prof && (e = hipEventRecord(h->ev[3], s)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -461,7 +465,8 @@ int noalloc_base(int dev, char **out) {
 // slots, sample hashes, partial sums, filter, filter partitions, block
 // areas.  Returns the bytes it needs; fills *sc only when they fit in cap.
 size_t layout_scratch(nqs_ham h, const nqs::EvalLaunch &L, int64_t n, int n_cu, char *base,
-                      size_t cap, nqs::DevScratch *sc) {
+                      size_t cap, nqs::DevScratch *sc, void *small = nullptr) {
+    if (!small) small = h->small;
     uint64_t slots = 64;
     while (slots < nqs::kSlotsPerSample * static_cast<uint64_t>(n)) slots <<= 1;
     const int64_t chunks = plan_chunks(h, L);
@@ -489,9 +494,9 @@ size_t layout_scratch(nqs_ham h, const nqs::EvalLaunch &L, int64_t n, int n_cu, 
     sc->eblk = h->dt.enum_ok ? base + off[5] : nullptr;
     sc->eblk_stride = h->dt.enum_ok ? enum_blk_stride(h->dt) : 0;
     sc->eblk_blocks = h->dt.enum_ok ? static_cast<uint32_t>(n_cu) : 0;
-    sc->counters = static_cast<unsigned long long *>(h->small);
-    sc->err = reinterpret_cast<int *>(static_cast<char *>(h->small) + kErrOffset);
-    sc->mixed = reinterpret_cast<int *>(static_cast<char *>(h->small) + kErrOffset + 4);
+    sc->counters = static_cast<unsigned long long *>(small);
+    sc->err = reinterpret_cast<int *>(static_cast<char *>(small) + kErrOffset);
+    sc->mixed = reinterpret_cast<int *>(static_cast<char *>(small) + kErrOffset + 4);
     sc->filter_log2 = L.filter_log2;
     sc->eparts_log2 = L.eparts_log2;
     sc->efilter_log2 = L.efilter_log2;
@@ -573,6 +578,21 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
         diag32[2 * k] = hi;
         diag32[2 * k + 1] = static_cast<float>(T.diag[k] - static_cast<double>(hi));
     }
+    // the pair terms of the occupation form as a zero-padded 128 x 128
+    // triangle (row j, column i < j) and the single terms padded to 128, for
+    // the dense diagonal sum
+    std::vector<double> diag_u, diag_d1;
+    if (T.diag_occ) {
+        const int nq = T.n_qubits;
+        diag_u.assign(size_t(nqs::kDiagPad) * nqs::kDiagPad, 0.0);
+        diag_d1.assign(nqs::kDiagPad, 0.0);
+        for (int j = 0; j < nq; ++j) {
+            diag_d1[j] = T.diag[1 + j];
+            for (int i = 0; i < j; ++i)
+                diag_u[size_t(j) * nqs::kDiagPad + i] =
+                    T.diag[1 + nq + size_t(j) * (j - 1) / 2 + i];
+        }
+    }
     std::vector<uint32_t> goff32(T.goff.size());
     for (size_t k = 0; k < T.goff.size(); ++k) goff32[k] = static_cast<uint32_t>(T.goff[k]);
     const nqs::LinearHash lh;
@@ -597,6 +617,8 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
         {T.qcls, sizeof(T.qcls), 0},
         {T.diag.data(), sizeof(double) * T.diag.size(), 0},
         {diag32.data(), sizeof(float) * diag32.size(), 0},
+        {diag_u.data(), sizeof(double) * diag_u.size(), 0},
+        {diag_d1.data(), sizeof(double) * diag_d1.size(), 0},
     };
     size_t total = 0;
     for (Piece &p : pieces) {
@@ -682,6 +704,8 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
     d.diag_occ = T.diag_occ ? 1 : 0;
     d.diag = T.diag_occ ? reinterpret_cast<const double *>(base + pieces[13].off) : nullptr;
     d.diag32 = T.diag_occ ? reinterpret_cast<const float *>(base + pieces[14].off) : nullptr;
+    d.diag_u = T.diag_occ ? reinterpret_cast<const double *>(base + pieces[15].off) : nullptr;
+    d.diag_d1 = T.diag_occ ? reinterpret_cast<const double *>(base + pieces[16].off) : nullptr;
     *out = h;
     return NQS_OK;
 }
@@ -838,13 +862,17 @@ int nqs_sync(nqs_ham h, void *hip_stream) {
     if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     NQS_HIP(hipStreamSynchronize(st));
-    int err = 0;
+    int err = h->host_err.exchange(0);
+    if (err == 0) {
     NQS_HIP(hipMemcpy(&err, static_cast<char *>(h->small) + kErrOffset, sizeof(int),
                       hipMemcpyDeviceToHost));
     if (err != 0) {
         const int zero = 0;
         NQS_HIP(hipMemcpy(static_cast<char *>(h->small) + kErrOffset, &zero, sizeof(int),
                           hipMemcpyHostToDevice));
+    }
+    }
+    if (err != 0) {
         switch (err) {
             case NQS_E_DUPLICATE: return fail(err, "a sample occurs more than once in the batch");
             case NQS_E_RANGE: return fail(err, "a sample has bits at or above n_qubits, or a count is negative");
@@ -1278,6 +1306,43 @@ int reserve(nqs_ham h, int64_t n, int threads, hipStream_t st) {
     const int64_t items = int64_t(t.blocks_per_cu ? t.blocks_per_cu : 4) * 256 * 1024 / L.threads;
     const int64_t bound = (items * L.threads + n + n - 1) / n;
     return ensure_scratch(h, n, std::max<int64_t>(L.n_chunks, bound), st, L.eparts_log2 > 0);
+}
+
+size_t request_scratch_bytes(nqs_ham h, int64_t n) {
+    n = std::max<int64_t>(n, 1);
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess)
+        n_cu = 256;
+    const nqs::EvalLaunch L = nqs::plan_eval(h->dt, n, false, &h->tune);
+    nqs::DevScratch sc{};
+    return layout_scratch(h, L, n, n_cu, nullptr, 0, &sc);
+}
+
+size_t small_bytes() { return kSmallBytes; }
+size_t small_err_offset() { return kErrOffset; }
+
+int eval_in(nqs_ham h, const nqs_batch_item &it, int precision, char *ctx, size_t ctx_bytes,
+            void *small, hipStream_t st) {
+    if (!::valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
+    if (it.n <= 0) return NQS_OK;
+    if (h->dt.sc) precision = NQS_FP64;  // the integral form evaluates in FP64 only
+    int n_cu = 0;
+    hipError_t e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+    if (e != hipSuccess) return fail_hip(e, "querying the device");
+    const nqs::EvalLaunch L = nqs::plan_eval(h->dt, it.n, false, &h->tune);
+    nqs::DevScratch sc{};
+    const size_t need = layout_scratch(h, L, it.n, n_cu, nullptr, 0, &sc);
+    if (need > ctx_bytes) return fail(NQS_E_ARG, "request larger than its lane's scratch");
+    layout_scratch(h, L, it.n, n_cu, ctx, ctx_bytes, &sc, small);
+    e = issue_eval(h, sc, L, it.n, it.samples, it.weights, it.log_amp, it.phase, it.eloc,
+                   precision, nullptr, nullptr, st, false);
+    if (e != hipSuccess) return fail_hip(e, "launching a served request");
+    return NQS_OK;
+}
+
+void latch_host_error(nqs_ham h, int code) {
+    int expected = 0;
+    h->host_err.compare_exchange_strong(expected, code);
 }
 
 void mark_evaluated(nqs_ham h, int64_t n) {

@@ -7,6 +7,9 @@
 
 namespace nqs {
 
+// Rows of the padded diagonal triangle (at least the largest register).
+constexpr int kDiagPad = 128;
+
 // Pair join: at most this many qubit blocks (a table whose groups flip up to
 // kJoinMaxBlocks - 1 qubits).
 constexpr int kJoinMaxBlocks = 8;
@@ -45,6 +48,11 @@ struct DevTable {
     int diag_occ;
     const double *diag;
     const float *diag32;
+    // the same form for the dense FP64 sum: the pair terms as a zero-padded
+    // kDiagPad x kDiagPad triangle (row j, column i < j) and the single terms
+    // d[1 + j] padded to kDiagPad
+    const double *diag_u;
+    const double *diag_d1;
     // pair join: the qubits split into join_blocks disjoint blocks (jmask);
     // two bit strings at Hamming distance at most max_flip < join_blocks
     // agree on at least one block (pigeonhole), so every connected pair of
@@ -182,10 +190,14 @@ struct DevScratch {
     // pair join (all null when the launch plans none): buckets of samples
     // by block contents, join_blocks << join_log2m of them, block-major
     uint32_t *jcnt;             // [buckets] counts -> start offsets -> bucket ends
+    uint32_t *jsize;            // [buckets] bucket sizes
     uint32_t *jkey;             // [blocks][n] bucket of each (block, sample)
-    uint32_t *jent;             // [blocks * n] entries (sample index), by bucket, ascending
-    uint2 *jrange;              // [blocks * n] [start, end) of each entry's bucket
-    uint64_t *jkeys;            // [blocks * n][2] bit string of each entry
+    // entries of the buckets that hold two samples or more (a sample alone
+    // in its bucket has no partner there and takes no entry):
+    uint32_t *jent;             // [<= blocks * n] sample index, by bucket, ascending
+    uint2 *jrange;              // [<= blocks * n] [start, end) of each entry's bucket
+    uint64_t *jkeys;            // [<= blocks * n][2] bit string of each entry
+    uint8_t *jblk;              // [<= blocks * n] block of each entry
     uint32_t *jbig;             // [blocks * n] buckets left to the block sorter
     unsigned long long *jscan;  // [3][scan blocks] count, sum of squares, largest
     unsigned long long *jctl;   // [kJoinCtl] see kJoinCtl*
@@ -197,7 +209,7 @@ struct DevScratch {
 // ordered candidate pairs (sum of squared bucket sizes), the largest bucket,
 // buckets for the block sorter, and the decision (1: the join runs).
 enum { kJoinCtlProbes = 0, kJoinCtlCost = 1, kJoinCtlMax = 2, kJoinCtlBig = 3,
-       kJoinCtlChosen = 4, kJoinCtlProbeSlots = 8, kJoinCtl = 8 + 64 };
+       kJoinCtlChosen = 4, kJoinCtlEntries = 5, kJoinCtlProbeSlots = 8, kJoinCtl = 8 + 64 };
 // Counters per scan block of the bucket counts (1024 threads x 4).
 constexpr int kJoinScanItems = 4096;
 // Largest bucket the block sorter takes (entries in LDS); a larger one

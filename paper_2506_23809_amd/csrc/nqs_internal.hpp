@@ -23,6 +23,18 @@ int64_t scratch_bytes(nqs_ham h);
 int reserve(nqs_ham h, int64_t n, int threads, hipStream_t st);
 // Bookkeeping of nqs_eval_stats after a launch that evaluated n samples.
 void mark_evaluated(nqs_ham h, int64_t n);
+// Server lanes: the evaluation scratch a request of n samples needs (the
+// plan nqs_eloc_eval would take), and one evaluation of a request with its
+// scratch carved from ctx (ctx_bytes) and its counters, error latch and
+// sector flag in small (small_bytes(), the error word at
+// small_err_offset()), on st, without allocating.
+size_t request_scratch_bytes(nqs_ham h, int64_t n);
+size_t small_bytes();
+size_t small_err_offset();
+int eval_in(nqs_ham h, const nqs_batch_item &it, int precision, char *ctx, size_t ctx_bytes,
+            void *small, hipStream_t st);
+// Latch an error seen for one of h's requests (the next nqs_sync reports it).
+void latch_host_error(nqs_ham h, int code);
 // Validate batch items, grow scratch, and build the job descriptors, the
 // work list and the launch shape (host side only; no upload).
 int plan_batch(const nqs_batch_item *items, int n_items, int threads, hipStream_t st,

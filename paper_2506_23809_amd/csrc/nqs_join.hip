@@ -132,26 +132,29 @@ __device__ __forceinline__ void bitonic_regs(uint32_t (&v)[N]) {
     }
 }
 
-// Entry p of the sorted bucket [s, e): sample j, its bit string, the range.
+// Entry p of the sorted bucket [s, e) of block b: sample j, its bit
+// string, the range, the block.
 __device__ __forceinline__ void join_put(const DevScratch &sc, const uint64_t *__restrict__ samples,
-                                         uint32_t p, uint32_t j, uint32_t s, uint32_t e) {
+                                         uint32_t p, uint32_t j, uint32_t s, uint32_t e,
+                                         uint32_t b) {
     sc.jent[p] = j;
     const uint4 key = reinterpret_cast<const uint4 *>(samples)[j];
     reinterpret_cast<uint4 *>(sc.jkeys)[p] = key;
     sc.jrange[p] = make_uint2(s, e);
+    sc.jblk[p] = static_cast<uint8_t>(b);
 }
 
 template <int N>
 __device__ __forceinline__ void join_sort_put(const DevScratch &sc,
                                               const uint64_t *__restrict__ samples, uint32_t s,
-                                              uint32_t m) {
+                                              uint32_t m, uint32_t b) {
     uint32_t v[N];
 #pragma unroll
     for (int t = 0; t < N; ++t) v[t] = static_cast<uint32_t>(t) < m ? sc.jent[s + t] : 0xFFFFFFFFu;
     bitonic_regs<N>(v);
 #pragma unroll
     for (int t = 0; t < N; ++t)
-        if (static_cast<uint32_t>(t) < m) join_put(sc, samples, s + t, v[t], s, s + m);
+        if (static_cast<uint32_t>(t) < m) join_put(sc, samples, s + t, v[t], s, s + m, b);
 }
 
 // ---- kernels
@@ -193,8 +196,9 @@ __global__ __launch_bounds__(kJoinThreads) void join_count_kernel(DevTable tab, 
         atomicAdd(&sc.jctl[kJoinCtlProbeSlots + blockIdx.x % 64], probes);
 }
 
-// Per scan block of kJoinScanItems bucket counts: their sum, the sum of
-// their squares and the largest.
+// Per scan block of kJoinScanItems bucket counts: the entries they take
+// (buckets of two samples or more), the sum of their squares and the
+// largest.
 __global__ __launch_bounds__(kJoinScanThreads) void join_scan_sums_kernel(DevScratch sc,
                                                                           int64_t buckets) {
     __shared__ unsigned long long part[3][kJoinScanThreads / 64];
@@ -203,7 +207,7 @@ __global__ __launch_bounds__(kJoinScanThreads) void join_scan_sums_kernel(DevScr
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const unsigned long long v = base + t < buckets ? sc.jcnt[base + t] : 0u;
-        s += v;
+        s += v >= 2 ? v : 0;
         q += v * v;
         m = v > m ? v : m;
     }
@@ -292,6 +296,7 @@ __global__ __launch_bounds__(1024) void join_decide_kernel(DevTable tab, DevScra
     const bool chosen = fits && (sc.join_force != 0 || cost < alt);
     sc.jctl[kJoinCtlCost] = Q;
     sc.jctl[kJoinCtlMax] = M;
+    sc.jctl[kJoinCtlEntries] = carry;
     sc.jctl[kJoinCtlChosen] = chosen ? 1ull : 0ull;
 }
 
@@ -306,19 +311,24 @@ __global__ __launch_bounds__(kJoinScanThreads) void join_offsets_kernel(DevScrat
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         v[t] = base + t < buckets ? sc.jcnt[base + t] : 0u;
-        own += v[t];
+        own += v[t] >= 2 ? v[t] : 0u;
     }
     unsigned long long total;
     unsigned long long off = sc.jscan[blockIdx.x] + block_exclusive_scan(own, &total);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        if (base + t < buckets) sc.jcnt[base + t] = static_cast<uint32_t>(off);
-        off += v[t];
+        if (base + t < buckets) {
+            sc.jcnt[base + t] = static_cast<uint32_t>(off);
+            sc.jsize[base + t] = v[t];
+        }
+        off += v[t] >= 2 ? v[t] : 0u;
     }
 }
 
 // Entries into their buckets (any order; sorted next).  Afterwards jcnt[k]
-// holds the end of bucket k, whose start is jcnt[k - 1] (0 for k = 0).
+// holds the end of bucket k, whose start is that less jsize[k].  A sample
+// alone in its bucket has no partner in that block: its partial is zero,
+// written here, and it takes no entry.
 __global__ __launch_bounds__(kJoinThreads) void join_scatter_kernel(DevTable tab, DevScratch sc,
                                                                     int64_t n) {
     if (!join_chosen(sc)) return;
@@ -326,6 +336,12 @@ __global__ __launch_bounds__(kJoinThreads) void join_scatter_kernel(DevTable tab
     if (i >= n) return;
     for (int b = 0; b < tab.join_blocks; ++b) {
         const uint32_t k = sc.jkey[static_cast<int64_t>(b) * n + i];
+        if (sc.jsize[k] < 2u) {
+            double *out = sc.part + 2 * (static_cast<int64_t>(b) * n + i);
+            out[0] = 0.0;
+            out[1] = 0.0;
+            continue;
+        }
         const uint32_t pos = atomicAdd(&sc.jcnt[k], 1u);
         sc.jent[pos] = static_cast<uint32_t>(i);
     }
@@ -339,23 +355,22 @@ __global__ __launch_bounds__(kJoinThreads) void join_sort_small_kernel(
     if (!join_chosen(sc)) return;
     const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= buckets) return;
-    const uint32_t s = k ? sc.jcnt[k - 1] : 0u, e = sc.jcnt[k];
-    const uint32_t m = e - s;
-    if (m == 0) return;
-    if (m == 1) {
-        join_put(sc, samples, s, sc.jent[s], s, e);
-    } else if (m == 2) {
+    const uint32_t m = sc.jsize[k];
+    if (m < 2) return;  // no entry
+    const uint32_t e = sc.jcnt[k], s = e - m;
+    const uint32_t blk = static_cast<uint32_t>(k >> sc.join_log2m);
+    if (m == 2) {
         const uint32_t a = sc.jent[s], b = sc.jent[s + 1];
-        join_put(sc, samples, s, a < b ? a : b, s, e);
-        join_put(sc, samples, s + 1, a < b ? b : a, s, e);
+        join_put(sc, samples, s, a < b ? a : b, s, e, blk);
+        join_put(sc, samples, s + 1, a < b ? b : a, s, e, blk);
     } else if (m <= 4) {
-        join_sort_put<4>(sc, samples, s, m);
+        join_sort_put<4>(sc, samples, s, m, blk);
     } else if (m <= 8) {
-        join_sort_put<8>(sc, samples, s, m);
+        join_sort_put<8>(sc, samples, s, m, blk);
     } else if (m <= 16) {
-        join_sort_put<16>(sc, samples, s, m);
+        join_sort_put<16>(sc, samples, s, m, blk);
     } else if (m <= static_cast<uint32_t>(kJoinSmallSort)) {
-        join_sort_put<32>(sc, samples, s, m);
+        join_sort_put<32>(sc, samples, s, m, blk);
     } else {
         const unsigned long long t = atomicAdd(&sc.jctl[kJoinCtlBig], 1ull);
         sc.jbig[t] = static_cast<uint32_t>(k);
@@ -372,8 +387,9 @@ __global__ __launch_bounds__(kJoinSortThreads) void join_sort_big_kernel(
     const unsigned long long nbig = sc.jctl[kJoinCtlBig];
     for (unsigned long long t = blockIdx.x; t < nbig; t += gridDim.x) {
         const uint32_t k = sc.jbig[t];
-        const uint32_t s = k ? sc.jcnt[k - 1] : 0u, e = sc.jcnt[k];
-        const uint32_t m = e - s;
+        const uint32_t m = sc.jsize[k];
+        const uint32_t e = sc.jcnt[k], s = e - m;
+        const uint32_t blk = k >> sc.join_log2m;
         uint32_t P = 64;
         while (P < m) P <<= 1;
         for (uint32_t u = threadIdx.x; u < P; u += blockDim.x)
@@ -395,7 +411,8 @@ __global__ __launch_bounds__(kJoinSortThreads) void join_sort_big_kernel(
                 __syncthreads();
             }
         }
-        for (uint32_t u = threadIdx.x; u < m; u += blockDim.x) join_put(sc, samples, s + u, buf[u], s, e);
+        for (uint32_t u = threadIdx.x; u < m; u += blockDim.x)
+            join_put(sc, samples, s + u, buf[u], s, e, blk);
         __syncthreads();
     }
 }
@@ -452,11 +469,12 @@ __global__ __launch_bounds__(kJoinThreads) void join_pair_kernel(
     const double *__restrict__ phase, int64_t n, int32_t *__restrict__ hit_idx,
     uint32_t *__restrict__ sign_bits, int64_t sign_words) {
     if (!join_chosen(sc)) return;
-    const int64_t total = static_cast<int64_t>(tab.join_blocks) * n;
+    // the entries of buckets of two samples or more
+    const int64_t total = static_cast<int64_t>(sc.jctl[kJoinCtlEntries]);
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     unsigned long long n_cand = 0, n_probe = 0, n_hit = 0, n_term = 0;
     if (p < total) {
-        const int b = static_cast<int>(p / n);
+        const int b = sc.jblk[p];
         const int64_t i = sc.jent[p];
         const uint4 xk = reinterpret_cast<const uint4 *>(sc.jkeys)[p];
         Key<W> x;
@@ -595,7 +613,8 @@ int join_log2m_for(int64_t n) {
 namespace {
 
 // Byte sizes of the join's pieces, in layout order.
-void join_sizes(const DevTable &tab, int64_t n, int log2m, size_t sizes[7]) {
+constexpr int kJoinPieces = 9;
+void join_sizes(const DevTable &tab, int64_t n, int log2m, size_t sizes[kJoinPieces]) {
     const size_t B = static_cast<size_t>(tab.join_blocks);
     const size_t buckets = B << log2m;
     const size_t entries = B * static_cast<size_t>(n);
@@ -607,13 +626,15 @@ void join_sizes(const DevTable &tab, int64_t n, int log2m, size_t sizes[7]) {
     sizes[4] = 16 * entries;                   // jkeys
     sizes[5] = 8 * 3 * nscan;                  // jscan
     sizes[6] = 8 * static_cast<size_t>(kJoinCtl);  // jctl
+    sizes[7] = 4 * buckets;                    // jsize
+    sizes[8] = entries;                        // jblk
 }
 
 }  // namespace
 
 size_t join_scratch_bytes(const DevTable &tab, int64_t n, int log2m) {
     if (tab.join_blocks <= 0 || n <= 0) return 0;
-    size_t sizes[7];
+    size_t sizes[kJoinPieces];
     join_sizes(tab, n, log2m, sizes);
     size_t total = 0;
     for (size_t s : sizes) total = align256(total + s);
@@ -621,11 +642,11 @@ size_t join_scratch_bytes(const DevTable &tab, int64_t n, int log2m) {
 }
 
 void join_scratch_layout(const DevTable &tab, int64_t n, int log2m, char *base, DevScratch *sc) {
-    size_t sizes[7];
+    size_t sizes[kJoinPieces];
     join_sizes(tab, n, log2m, sizes);
-    size_t off[7];
+    size_t off[kJoinPieces];
     size_t total = 0;
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < kJoinPieces; ++k) {
         off[k] = total;
         total = align256(total + sizes[k]);
     }
@@ -637,6 +658,8 @@ void join_scratch_layout(const DevTable &tab, int64_t n, int log2m, char *base, 
     sc->jkeys = reinterpret_cast<uint64_t *>(base + off[4]);
     sc->jscan = reinterpret_cast<unsigned long long *>(base + off[5]);
     sc->jctl = reinterpret_cast<unsigned long long *>(base + off[6]);
+    sc->jsize = reinterpret_cast<uint32_t *>(base + off[7]);
+    sc->jblk = reinterpret_cast<uint8_t *>(base + off[8]);
     sc->join_log2m = log2m;
 }
 

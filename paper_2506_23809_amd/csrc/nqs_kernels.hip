@@ -1684,6 +1684,52 @@ __device__ __forceinline__ double diag_occ_sum(const double *d, int nq, const Ke
     }
 }
 
+// Bits [16 c, 16 c + 16) of x.
+template <int W>
+__device__ __forceinline__ uint32_t chunk16(const Key<W> &x, int c) {
+    const int w = c >> 2;
+    uint64_t v = x.w[0];
+    if constexpr (W == 2) v = w ? x.w[W - 1] : v;
+    return w < W ? static_cast<uint32_t>(v >> (16 * (c & 3))) & 0xFFFFu : 0u;
+}
+
+// The FP64 occupation-form sum without gathers: with n_i in {0, 1} as a
+// double, t_j = d_j + sum_{i < j} n_i d_ij and the result d0 + sum_j n_j t_j
+// are formed tile by tile (16 j, 16 i) with FMAs whose d_ij are the same for
+// every lane (scalar loads of the padded triangle U, zero where i >= j).  An
+// unoccupied term adds an exact zero, and the occupied ones are added in the
+// order of the sparse sum above (i ascending from d_j, then j ascending), so
+// the result has the same bits; the work is nq^2 / 2 FMAs in place of
+// n_occ^2 / 2 gathers, all issue-bound.
+template <int W>
+__device__ __forceinline__ double diag_occ_dense(const DevTable &tab, const Key<W> &x) {
+    const double *__restrict__ U = tab.diag_u;
+    const double *__restrict__ d1 = tab.diag_d1;
+    double acc = tab.diag[0];
+    const int jtiles = (tab.n_qubits + 15) >> 4;
+    for (int jt = 0; jt < jtiles; ++jt) {
+        double t[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) t[jj] = d1[16 * jt + jj];
+        for (int it = 0; it <= jt; ++it) {
+            const uint32_t bi = chunk16<W>(x, it);
+            double f[16];
+#pragma unroll
+            for (int ii = 0; ii < 16; ++ii) f[ii] = static_cast<double>((bi >> ii) & 1u);
+            const double *Ut = U + static_cast<size_t>(16 * jt) * kDiagPad + 16 * it;
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+#pragma unroll
+                for (int ii = 0; ii < 16; ++ii) t[jj] = fma(f[ii], Ut[jj * kDiagPad + ii], t[jj]);
+            }
+        }
+        const uint32_t bj = chunk16<W>(x, jt);
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) acc = fma(static_cast<double>((bj >> jj) & 1u), t[jj], acc);
+    }
+    return acc;
+}
+
 // The same sum from a staged occupation form, with the occupied qubits first
 // written, in increasing order, as bytes into the lane's list in LDS
 // (interleaved across the block: entries 4w..4w+3 of this lane are the word
@@ -1776,9 +1822,13 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
             } else if (dq) {
                 // occupation form (the caller passes it staged or in place);
                 // counted as the X = 0 group's terms it stands for
-                re = olist ? diag_occ_sum_list<W, P>(dq, tab.n_qubits, x, olist + threadIdx.x,
-                                                     static_cast<int>(blockDim.x))
-                           : diag_occ_sum<W, P>(dq, tab.n_qubits, x);
+                if constexpr (P == NQS_FP64)
+                    re = diag_occ_dense<W>(tab, x);
+                else
+                    re = olist ? diag_occ_sum_list<W, P>(dq, tab.n_qubits, x,
+                                                         olist + threadIdx.x,
+                                                         static_cast<int>(blockDim.x))
+                               : diag_occ_sum<W, P>(dq, tab.n_qubits, x);
                 n_terms += static_cast<unsigned long long>(tab.goff[1] - tab.goff[0]);
             } else if (dz) {
                 // the X = 0 group staged in LDS by the caller (same order, same sums)
@@ -1881,6 +1931,15 @@ __global__ __launch_bounds__(256) void eloc_finish_kernel(
         // staging area (dynamic LDS of stage_cap doubles, at least
         // 3 kDiagLds): the diagonal's Z masks and coefficients, or its
         // occupation form
+        if constexpr (P == NQS_FP64) {
+            // the dense sum reads the padded triangle in place (scalar loads)
+            if (tab.diag_occ) {
+                finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc,
+                                            hit_idx, sign_bits, sign_words, i, nullptr, nullptr,
+                                            0, tab.diag);
+                return;
+            }
+        }
         double *stage = reinterpret_cast<double *>(dyn_lds());
         const double *dq = stage_diag_occ<P>(tab, stage, stage_cap);
         if (dq) {
@@ -2529,7 +2588,9 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
     // and, after it, each thread's list of occupied qubits (bytes, 4 a word)
     const int list_words = tab.diag_occ ? (tab.n_qubits + 3) / 4 : 0;
     const size_t stage_bytes =
-        (dump || tab.sc) ? 0 : sizeof(double) * stage_cap + size_t(256) * 4 * list_words;
+        (dump || tab.sc || (!f32 && tab.diag_occ))
+            ? 0
+            : sizeof(double) * stage_cap + (f32 ? size_t(256) * 4 * list_words : 0);
 #define NQS_FINISH(Wd, D, Pr)                                                                 \
     do {                                                                                      \
         if ((e = allow_finish_lds<Wd, D, Pr>()) != hipSuccess) return e;                     \

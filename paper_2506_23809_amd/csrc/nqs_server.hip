@@ -1,15 +1,20 @@
 // Serving runtime: a request loop with continuous batching over resident
 // Pauli tables.
 //
-// One dispatcher thread owns the device work.  Pending requests wait in
-// arrival order; whenever a stream slot is free the dispatcher admits every
-// request it can (handle not already running, footprint within the HBM
-// budget, at most max_batch), plans them as one batched launch into the
-// slot's preallocated descriptor buffers, uploads the plan from pinned
-// staging and launches on the slot's stream.  Completion is seen with
-// hipEventQuery, so slots refill as soon as their launch ends while other
-// slots keep running.  Nothing in the loop allocates device memory once a
-// slot's buffers have reached their working size.
+// One dispatcher thread owns the device work.  The device is divided into
+// lanes: each lane is a stream with its own evaluation scratch (sample
+// hash, partial sums, filters, enumeration areas, pair-join buckets) and its
+// own counters and error latch, all allocated when handles are registered.
+// Pending requests wait in arrival order; whenever a lane is free the
+// dispatcher admits the oldest request whose footprint fits the HBM budget
+// and launches it on that lane, with the plan nqs_eloc_eval would take (so
+// the device picks the pair join, the enumeration or streaming per
+// request).  Lanes run concurrently, so requests that arrive while others
+// run join the device's work as soon as a lane frees up, whatever
+// Hamiltonian they use (two requests for one handle overlap on two lanes).
+// Each request completes on its own lane event, seen with hipEventQuery; a
+// small request never waits for a large one that started with it.  Nothing
+// in the loop allocates device memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,7 +27,6 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
-#include <unordered_set>
 #include <utility>
 #include <vector>
 
@@ -42,20 +46,20 @@ struct SrvRequest {
     Clock::time_point t_submit;
 };
 
-struct Slot {
+struct Lane {
     hipStream_t st = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
-    std::vector<SrvRequest> reqs;
-    int64_t bytes = 0;
-    // device plan buffers and their pinned staging
-    nqs::JobDesc *d_jobs = nullptr;
-    nqs::WorkItem *d_items = nullptr;
-    unsigned *d_next = nullptr;
-    nqs::JobDesc *h_jobs = nullptr;
-    nqs::WorkItem *h_items = nullptr;
-    size_t jobs_cap = 0;
-    size_t items_cap = 0;
+    SrvRequest req{};
+    char *ctx = nullptr;  // evaluation scratch
+    size_t ctx_bytes = 0;
+    void *small = nullptr;  // counters, error latch, sector flag
+    int *h_err = nullptr;   // pinned copy of the lane's error latch after a request
+};
+
+struct Registered {
+    int64_t table_bytes;
+    int64_t max_samples;
 };
 
 }  // namespace
@@ -68,11 +72,11 @@ struct nqs_server_s {
     std::condition_variable done_cv;  // wakes drain()
     std::deque<SrvRequest> pending;
     std::vector<std::pair<int64_t, double>> finished;
-    std::unordered_map<nqs_ham, int64_t> resident;  // handle -> bytes counted as resident
-    std::unordered_set<nqs_ham> running;
-    int64_t resident_bytes = 0;
+    std::unordered_map<nqs_ham, Registered> resident;
+    int64_t resident_bytes = 0;  // tables plus the lanes' scratch
+    int64_t lane_bytes = 0;      // scratch of all lanes
     int64_t inflight_bytes = 0;
-    std::vector<Slot> slots;
+    std::vector<Lane> lanes;
     std::thread worker;
     bool stop = false;
     int error = 0;
@@ -81,120 +85,80 @@ struct nqs_server_s {
     // statistics
     int64_t submitted = 0, completed = 0, rejected = 0, launches = 0;
     int64_t max_reqs_inflight = 0, max_launches_inflight = 0, peak_bytes = 0;
-    int64_t reqs_inflight = 0, launches_inflight = 0;
+    int64_t reqs_inflight = 0;
 };
 
 namespace {
 
 int fail(int code, const std::string &msg) { return nqs::detail::fail(code, msg); }
 
-void free_slot(Slot &f) {
-    if (f.done) (void)hipEventDestroy(f.done);
-    if (f.st) (void)hipStreamDestroy(f.st);
-    if (f.d_jobs) (void)hipFree(f.d_jobs);
-    if (f.d_items) (void)hipFree(f.d_items);
-    if (f.d_next) (void)hipFree(f.d_next);
-    if (f.h_jobs) (void)hipHostFree(f.h_jobs);
-    if (f.h_items) (void)hipHostFree(f.h_items);
-    f = Slot{};
+void free_lane(Lane &l) {
+    if (l.done) (void)hipEventDestroy(l.done);
+    if (l.st) (void)hipStreamDestroy(l.st);
+    if (l.ctx) (void)hipFree(l.ctx);
+    if (l.small) (void)hipFree(l.small);
+    if (l.h_err) (void)hipHostFree(l.h_err);
+    l = Lane{};
 }
 
-// Grow a slot's plan buffers (rare: only past the largest plan seen so far).
-hipError_t ensure_slot(Slot &f, size_t jobs, size_t items) {
-    hipError_t e = hipSuccess;
-    if (jobs > f.jobs_cap) {
-        if (f.d_jobs) (void)hipFree(f.d_jobs);
-        if (f.h_jobs) (void)hipHostFree(f.h_jobs);
-        f.d_jobs = nullptr;
-        f.h_jobs = nullptr;
-        const size_t cap = std::max<size_t>(jobs, 64);
-        e = hipMalloc(&f.d_jobs, cap * sizeof(nqs::JobDesc));
-        if (e == hipSuccess) e = hipHostMalloc(&f.h_jobs, cap * sizeof(nqs::JobDesc), hipHostMallocDefault);
-        if (e != hipSuccess) return e;
-        f.jobs_cap = cap;
-    }
-    if (items > f.items_cap) {
-        if (f.d_items) (void)hipFree(f.d_items);
-        if (f.h_items) (void)hipHostFree(f.h_items);
-        f.d_items = nullptr;
-        f.h_items = nullptr;
-        const size_t cap = std::max<size_t>(items, size_t(1) << 16);
-        e = hipMalloc(&f.d_items, cap * sizeof(nqs::WorkItem));
-        if (e == hipSuccess) e = hipHostMalloc(&f.h_items, cap * sizeof(nqs::WorkItem), hipHostMallocDefault);
-        if (e != hipSuccess) return e;
-        f.items_cap = cap;
-    }
-    return e;
-}
-
-// Plan and launch the slot's requests (called without the server lock).
-int launch_slot(nqs_server s, Slot &f) {
-    std::vector<nqs_batch_item> items;
-    items.reserve(f.reqs.size());
-    for (const SrvRequest &r : f.reqs) items.push_back(r.item);
-    std::vector<nqs::JobDesc> jobs;
-    std::vector<nqs::WorkItem> work;
-    nqs::BatchShape shape{};
-    int rc = nqs::detail::plan_batch(items.data(), static_cast<int>(items.size()), s->cfg.threads,
-                                     f.st, &jobs, &work, &shape);
+// Launch the lane's request (called without the server lock).  After the
+// evaluation the lane's error word is copied to pinned memory, then the
+// lane's event is recorded: the request is done when the event is.
+int launch_lane(nqs_server s, Lane &l) {
+    const nqs_batch_item &it = l.req.item;
+    int rc = nqs::detail::eval_in(it.ham, it, s->cfg.precision, l.ctx, l.ctx_bytes, l.small, l.st);
     if (rc) return rc;
-    hipError_t e = ensure_slot(f, jobs.size(), std::max<size_t>(work.size(), 1));
-    if (e != hipSuccess) return fail(NQS_E_NOMEM, "allocating a serving slot's plan buffers");
-    std::memcpy(f.h_jobs, jobs.data(), jobs.size() * sizeof(nqs::JobDesc));
-    if (!work.empty()) std::memcpy(f.h_items, work.data(), work.size() * sizeof(nqs::WorkItem));
-    e = hipMemcpyAsync(f.d_jobs, f.h_jobs, jobs.size() * sizeof(nqs::JobDesc), hipMemcpyHostToDevice, f.st);
-    if (e == hipSuccess && !work.empty())
-        e = hipMemcpyAsync(f.d_items, f.h_items, work.size() * sizeof(nqs::WorkItem),
-                           hipMemcpyHostToDevice, f.st);
-    if (e == hipSuccess)
-        e = nqs::launch_batch(f.d_jobs, static_cast<int>(jobs.size()), f.d_items,
-                              static_cast<int>(work.size()), f.d_next, shape, s->cfg.precision, f.st);
-    if (e == hipSuccess) e = hipEventRecord(f.done, f.st);
+    hipError_t e = hipMemcpyAsync(l.h_err, static_cast<char *>(l.small) + nqs::detail::small_err_offset(),
+                                  sizeof(int), hipMemcpyDeviceToHost, l.st);
+    if (e == hipSuccess) e = hipEventRecord(l.done, l.st);
     if (e != hipSuccess) return fail(NQS_E_DEVICE, std::string("serving launch: ") + hipGetErrorString(e));
-    for (const SrvRequest &r : f.reqs) nqs::detail::mark_evaluated(r.item.ham, r.item.n);
+    nqs::detail::mark_evaluated(it.ham, it.n);
     return NQS_OK;
 }
 
-// Called with the lock held once a slot's launch has completed.
-void retire_slot(nqs_server s, Slot &f, const Clock::time_point now, bool ok) {
-    for (const SrvRequest &r : f.reqs) {
-        const double us =
-            ok ? std::chrono::duration<double, std::micro>(now - r.t_submit).count() : -1.0;
-        s->finished.emplace_back(r.ticket, us);
-        s->running.erase(r.item.ham);
+// Called with the lock held once a lane's request has completed.
+void retire_lane(nqs_server s, Lane &l, const Clock::time_point now, bool ok) {
+    const double us =
+        ok ? std::chrono::duration<double, std::micro>(now - l.req.t_submit).count() : -1.0;
+    if (ok && *l.h_err != 0) {
+        // a device-detected error of this request (duplicate samples, bits
+        // out of range): latched on its handle for nqs_sync; the lane's latch
+        // is cleared on its stream before the lane's next request
+        nqs::detail::latch_host_error(l.req.item.ham, *l.h_err);
+        *l.h_err = 0;
+        (void)hipMemsetAsync(static_cast<char *>(l.small) + nqs::detail::small_err_offset(), 0,
+                             sizeof(int), l.st);
     }
-    s->completed += static_cast<int64_t>(f.reqs.size());
-    s->reqs_inflight -= static_cast<int64_t>(f.reqs.size());
-    s->launches_inflight -= 1;
-    s->inflight_bytes -= f.bytes;
-    f.reqs.clear();
-    f.bytes = 0;
-    f.busy = false;
+    s->finished.emplace_back(l.req.ticket, us);
+    s->completed += 1;
+    s->reqs_inflight -= 1;
+    s->inflight_bytes -= l.req.bytes;
+    l.busy = false;
 }
 
 void dispatcher(nqs_server s) {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        // 1. retire finished launches
+        // 1. retire finished requests
         const Clock::time_point now = Clock::now();
         bool retired = false;
-        for (Slot &f : s->slots) {
-            if (!f.busy) continue;
-            const hipError_t q = hipEventQuery(f.done);
+        for (Lane &l : s->lanes) {
+            if (!l.busy) continue;
+            const hipError_t q = hipEventQuery(l.done);
             if (q == hipSuccess) {
-                retire_slot(s, f, now, true);
+                retire_lane(s, l, now, true);
                 retired = true;
             } else if (q != hipErrorNotReady) {
                 s->error = NQS_E_DEVICE;
                 s->error_msg = std::string("serving launch failed: ") + hipGetErrorString(q);
-                retire_slot(s, f, now, false);
+                retire_lane(s, l, now, false);
                 retired = true;
             }
         }
         if (retired) s->done_cv.notify_all();
         bool any_busy = false;
-        for (const Slot &f : s->slots) any_busy = any_busy || f.busy;
+        for (const Lane &l : s->lanes) any_busy = any_busy || l.busy;
         if (s->error && !s->pending.empty()) {
             // after a failed launch nothing more is admitted: fail the queue
             for (const SrvRequest &r : s->pending) s->finished.emplace_back(r.ticket, -1.0);
@@ -204,53 +168,37 @@ void dispatcher(nqs_server s) {
         }
         if (s->stop && s->pending.empty() && !any_busy) break;
 
-        // 2. admit pending requests into free slots
+        // 2. admit the oldest request that fits into each free lane
         bool launched = false;
-        for (Slot &f : s->slots) {
-            if (f.busy || s->pending.empty() || s->error) continue;
-            std::vector<SrvRequest> pick;
-            std::unordered_set<nqs_ham> in_pick;
-            int64_t bytes = 0;
-            for (auto it = s->pending.begin();
-                 it != s->pending.end() && static_cast<int>(pick.size()) < s->cfg.max_batch;) {
-                const nqs_ham h = it->item.ham;
-                const bool free_handle = !s->running.count(h) && !in_pick.count(h);
-                const bool fits = s->resident_bytes + s->inflight_bytes + bytes + it->bytes <=
-                                  s->cfg.hbm_budget_bytes;
-                if (free_handle && fits) {
-                    bytes += it->bytes;
-                    in_pick.insert(h);
-                    pick.push_back(*it);
-                    it = s->pending.erase(it);
-                } else {
-                    ++it;
-                }
-            }
-            if (pick.empty()) break;
-            for (const SrvRequest &r : pick) s->running.insert(r.item.ham);
-            f.reqs = std::move(pick);
-            f.bytes = bytes;
-            f.busy = true;
-            s->inflight_bytes += bytes;
-            s->reqs_inflight += static_cast<int64_t>(f.reqs.size());
-            s->launches_inflight += 1;
+        for (Lane &l : s->lanes) {
+            if (l.busy || s->pending.empty() || s->error) continue;
+            auto it = s->pending.begin();
+            while (it != s->pending.end() &&
+                   s->resident_bytes + s->inflight_bytes + it->bytes > s->cfg.hbm_budget_bytes)
+                ++it;
+            if (it == s->pending.end()) break;
+            l.req = *it;
+            s->pending.erase(it);
+            l.busy = true;
+            s->inflight_bytes += l.req.bytes;
+            s->reqs_inflight += 1;
             s->launches += 1;
             s->max_reqs_inflight = std::max(s->max_reqs_inflight, s->reqs_inflight);
-            s->max_launches_inflight = std::max(s->max_launches_inflight, s->launches_inflight);
+            s->max_launches_inflight = s->max_reqs_inflight;
             s->peak_bytes = std::max(s->peak_bytes, s->resident_bytes + s->inflight_bytes);
             lk.unlock();
-            const int rc = launch_slot(s, f);
+            const int rc = launch_lane(s, l);
             lk.lock();
             if (rc) {
                 s->error = rc;
                 s->error_msg = "serving launch could not be planned or enqueued";
-                retire_slot(s, f, Clock::now(), false);
+                retire_lane(s, l, Clock::now(), false);
                 s->done_cv.notify_all();
             }
             launched = true;
         }
         if (launched) continue;
-        // 3. wait: poll completions while launches run, sleep when idle
+        // 3. wait: poll completions while requests run, sleep when idle
         if (any_busy)
             s->cv.wait_for(lk, std::chrono::microseconds(20));
         else
@@ -267,28 +215,30 @@ int nqs_server_create(nqs_server *out, const nqs_server_config *cfg) {
     *out = nullptr;
     nqs_server_config c = *cfg;
     if (c.streams == 0) c.streams = 4;
-    if (c.max_batch == 0) c.max_batch = 64;
-    if (c.hbm_budget_bytes <= 0 || c.streams < 1 || c.streams > 8 || c.max_batch < 1 ||
-        c.max_batch > 256 || (c.precision != NQS_FP64 && c.precision != NQS_FP32_KAHAN) ||
-        !(c.threads == 0 || c.threads == 256 || c.threads == 512 || c.threads == 1024))
+    if (c.hbm_budget_bytes <= 0 || c.streams < 1 || c.streams > 8 ||
+        (c.precision != NQS_FP64 && c.precision != NQS_FP32_KAHAN))
         return fail(NQS_E_ARG, "server configuration out of range");
     nqs_server s = new (std::nothrow) nqs_server_s();
     if (!s) return fail(NQS_E_NOMEM, "host allocation failed");
     s->cfg = c;
     hipError_t e = hipGetDevice(&s->device);
-    s->slots.resize(c.streams);
-    for (Slot &f : s->slots) {
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&f.st, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&f.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMalloc(&f.d_next, nqs::kBatchCounters * sizeof(unsigned));
-        if (e == hipSuccess) e = ensure_slot(f, 64, size_t(1) << 16);
+    s->lanes.resize(c.streams);
+    for (Lane &l : s->lanes) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&l.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMalloc(&l.small, nqs::detail::small_bytes());
+        if (e == hipSuccess) e = hipMemset(l.small, 0, nqs::detail::small_bytes());
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&l.h_err), sizeof(int), hipHostMallocDefault);
+        if (e == hipSuccess) *l.h_err = 0;
     }
-    if (e == hipSuccess) e = nqs::prepare_batch_kernels();
     if (e != hipSuccess) {
-        for (Slot &f : s->slots) free_slot(f);
+        for (Lane &l : s->lanes) free_lane(l);
         delete s;
         return fail(NQS_E_DEVICE, std::string("creating the server: ") + hipGetErrorString(e));
     }
+    s->lane_bytes = static_cast<int64_t>(nqs::detail::small_bytes()) * c.streams;
+    s->resident_bytes = s->lane_bytes;
     s->worker = std::thread(dispatcher, s);
     *out = s;
     return NQS_OK;
@@ -298,25 +248,48 @@ int nqs_server_add_ham(nqs_server s, nqs_ham h, int64_t max_samples) {
     if (!s) return fail(NQS_E_STATE, "invalid server");
     if (!nqs::detail::valid_handle(h)) return fail(NQS_E_ARG, "invalid handle");
     if (max_samples < 1) return fail(NQS_E_ARG, "max_samples must be positive");
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (s->resident.count(h)) return fail(NQS_E_ARG, "handle already registered");
-        if (s->running.count(h)) return fail(NQS_E_STATE, "handle is running");
-    }
-    // scratch is sized now so that the serving loop does not allocate
-    hipStream_t st = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-    if (e != hipSuccess) return fail(NQS_E_DEVICE, "creating a stream");
-    int rc = nqs::detail::reserve(h, max_samples, s->cfg.threads, st);
-    (void)hipStreamSynchronize(st);
-    (void)hipStreamDestroy(st);
-    if (rc) return rc;
-    const int64_t bytes = nqs::detail::table_bytes(h);
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->resident_bytes + bytes > s->cfg.hbm_budget_bytes)
-        return fail(NQS_E_NOMEM, "resident tables would exceed the HBM budget");
-    s->resident[h] = bytes;
-    s->resident_bytes += bytes;
+    if (s->resident.count(h)) return fail(NQS_E_ARG, "handle already registered");
+    const int64_t table = nqs::detail::table_bytes(h);
+    const int64_t small = static_cast<int64_t>(nqs::detail::small_bytes()) * s->cfg.streams;
+    // every lane must hold this handle's largest request
+    const size_t need = nqs::detail::request_scratch_bytes(h, max_samples);
+    const size_t have = s->lanes[0].ctx_bytes;
+    const int64_t lanes_after =
+        small + static_cast<int64_t>(std::max(need, have)) * s->cfg.streams;
+    if (s->resident_bytes - s->lane_bytes + lanes_after + table > s->cfg.hbm_budget_bytes)
+        return fail(NQS_E_NOMEM, "resident tables and lane scratch would exceed the HBM budget");
+    if (need > have) {
+        for (const Lane &l : s->lanes)
+            if (l.busy) return fail(NQS_E_STATE, "lanes are running: register handles first");
+        bool ok = true;
+        for (Lane &l : s->lanes) {
+            if (l.ctx) (void)hipFree(l.ctx);
+            l.ctx = nullptr;
+            l.ctx_bytes = 0;
+            if (ok && hipMalloc(reinterpret_cast<void **>(&l.ctx), need) == hipSuccess)
+                l.ctx_bytes = need;
+            else
+                ok = false;
+        }
+        if (!ok) {
+            // no lane keeps scratch it cannot use: all empty, nothing admitted
+            // until a registration succeeds
+            for (Lane &l : s->lanes) {
+                if (l.ctx) (void)hipFree(l.ctx);
+                l.ctx = nullptr;
+                l.ctx_bytes = 0;
+            }
+            s->resident_bytes += small - s->lane_bytes;
+            s->lane_bytes = small;
+            for (auto &kv : s->resident) kv.second.max_samples = 0;
+            return fail(NQS_E_NOMEM, "allocating the lanes' scratch");
+        }
+        s->resident_bytes += lanes_after - s->lane_bytes;
+        s->lane_bytes = lanes_after;
+    }
+    s->resident[h] = Registered{table, max_samples};
+    s->resident_bytes += table;
     return NQS_OK;
 }
 
@@ -329,11 +302,14 @@ int nqs_server_submit(nqs_server s, const nqs_batch_item *req, int64_t *ticket) 
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return fail(NQS_E_STATE, "server is stopping");
     if (s->error) return fail(NQS_E_STATE, "server failed: " + s->error_msg);
-    if (!s->resident.count(req->ham)) return fail(NQS_E_ARG, "handle not registered with the server");
+    const auto reg = s->resident.find(req->ham);
+    if (reg == s->resident.end()) return fail(NQS_E_ARG, "handle not registered with the server");
+    if (req->n > reg->second.max_samples)
+        return fail(NQS_E_ARG, "request larger than the handle's registered max_samples");
     SrvRequest r;
     r.ticket = s->next_ticket++;
     r.item = *req;
-    r.bytes = kBytesPerSample * req->n + nqs::detail::scratch_bytes(req->ham);
+    r.bytes = kBytesPerSample * req->n;
     r.t_submit = Clock::now();
     if (s->resident_bytes + r.bytes > s->cfg.hbm_budget_bytes) {
         s->rejected += 1;
@@ -400,9 +376,9 @@ int nqs_server_destroy(nqs_server s) {
     }
     s->cv.notify_all();
     if (s->worker.joinable()) s->worker.join();
-    for (Slot &f : s->slots) {
-        if (f.st) (void)hipStreamSynchronize(f.st);
-        free_slot(f);
+    for (Lane &l : s->lanes) {
+        if (l.st) (void)hipStreamSynchronize(l.st);
+        free_lane(l);
     }
     const int err = s->error;
     delete s;

@@ -3,17 +3,19 @@
 64 jobs are drawn from the batched-family distribution (qubits 24..80 at
 half filling, samples log-uniform in [1e3, 2e5]); each keeps its Hamiltonian
 resident and alternates between two sample batches (with their psi values).
-Requests arrive as a Poisson process (200 per second in aggregate by
-default), each for a uniformly chosen job.  The same arrival trace is
-replayed through three server configurations:
+Requests arrive as a Poisson process, each for a uniformly chosen job.  The
+same arrival trace is replayed through three server configurations:
 
-* serial FP64: one stream, one request per launch (plain FP64 launches in
-  arrival order);
-* continuous FP64 and continuous FP32+compensation: four streams, up to 64
-  requests per launch, admission by HBM footprint (64 GB budget).
+* serial FP64: one lane (one request on the device at a time, in arrival
+  order: plain FP64 launches one after another);
+* continuous FP64 and continuous FP32+compensation: four lanes, requests
+  admitted as lanes free up and HBM allows (64 GB budget), overlapping on
+  the device.
 
-Reported: completed requests per second, pair-evaluations per second and
-the p50 / p99 latency from submission to completion.
+A sweep replays traces at increasing aggregate rates, the last submitting
+every request at once (saturation: the throughput ceiling).  Reported per
+point: completed requests per second, pair-evaluations per second and the
+p50 / p99 latency from submission to completion.
 """
 from __future__ import annotations
 
@@ -77,14 +79,18 @@ def replay(server, hams, payloads, arrivals, job_of):
     return np.array(sorted(lat.values())), wall
 
 
+MODES = (("serial_fp64", 1, "fp64"), ("continuous_fp64", 4, "fp64"),
+         ("continuous_fp32k", 4, "fp32k"))
+
+
 def run(args, log):
     import torch
 
     import paper_2506_23809_amd as nqs
 
     n_jobs = 64
-    n_req = getattr(args, "requests", 0) or 400
-    rate = getattr(args, "rate", 0.0) or 200.0
+    n_req = getattr(args, "requests", 0) or 2000
+    rates = [float(r) for r in str(getattr(args, "rates", "") or "200,1000,2000,3000,4000,inf").split(",")]
     jobs = make_jobs(n_jobs, log)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -101,15 +107,9 @@ def run(args, log):
         payloads.append(p)
         pairs.append(h.n_groups * w.n_samples)
     torch.cuda.synchronize()
-    arrivals, job_of = poisson_trace(n_req, rate, n_jobs)
-    req_pairs = float(sum(pairs[j] for j in job_of))
-    log(f"trace: {n_req} requests at {rate:.0f}/s over {arrivals[-1]:.2f} s, "
-        f"{req_pairs:.3e} pair-evaluations")
-    results = {}
-    for name, streams, max_batch, prec in (("serial_fp64", 1, 1, "fp64"),
-                                           ("continuous_fp64", 4, 64, "fp64"),
-                                           ("continuous_fp32k", 4, 64, "fp32k")):
-        srv = nqs.Server(HBM_BUDGET, streams=streams, max_batch=max_batch, precision=prec)
+    servers = {}
+    for name, lanes, prec in MODES:
+        srv = nqs.Server(HBM_BUDGET, streams=lanes, precision=prec)
         for h, w in zip(hams, jobs):
             srv.add(h, w.n_samples)
         # warm-up: one request per job
@@ -117,29 +117,42 @@ def run(args, log):
             srv.submit(h, *p[0])
         srv.drain(600.0)
         srv.poll()
-        lat, wall = replay(srv, hams, payloads, arrivals, job_of)
-        st = srv.stats()
+        servers[name] = srv
+    sweep = []
+    for rate in rates:
+        arrivals, job_of = poisson_trace(n_req, rate if math.isfinite(rate) else 1e12, n_jobs)
+        if not math.isfinite(rate):
+            arrivals = np.zeros_like(arrivals)
+        req_pairs = float(sum(pairs[j] for j in job_of))
+        point = {"rate_per_s": rate if math.isfinite(rate) else "saturation",
+                 "requests": n_req, "pair_evaluations": req_pairs}
+        for name, lanes, prec in MODES:
+            srv = servers[name]
+            before = srv.stats()
+            lat, wall = replay(srv, hams, payloads, arrivals, job_of)
+            st = srv.stats()
+            point[name] = {
+                "requests_per_s": n_req / wall,
+                "pair_evals_per_s": req_pairs / wall,
+                "p50_ms": float(np.percentile(lat, 50)) / 1e3,
+                "p99_ms": float(np.percentile(lat, 99)) / 1e3,
+                "mean_ms": float(lat.mean()) / 1e3,
+                "wall_s": wall,
+                "requests_above_p99": int(np.sum(lat > np.percentile(lat, 99))),
+                "launches": st["launches"] - before["launches"],
+                "max_requests_in_flight": st["max_requests_in_flight"],
+            }
+            log(f"rate {point['rate_per_s']}: {name}: "
+                f"{point[name]['requests_per_s']:.1f} req/s, p50 {point[name]['p50_ms']:.2f} ms, "
+                f"p99 {point[name]['p99_ms']:.2f} ms")
+        sweep.append(point)
+    for srv in servers.values():
         srv.close()
-        results[name] = {
-            "requests_per_s": n_req / wall,
-            "pair_evals_per_s": req_pairs / wall,
-            "p50_ms": float(np.percentile(lat, 50)) / 1e3,
-            "p99_ms": float(np.percentile(lat, 99)) / 1e3,
-            "mean_ms": float(lat.mean()) / 1e3,
-            "wall_s": wall,
-            "launches": st["launches"] - n_jobs if max_batch == 1 else st["launches"],
-            "max_requests_in_flight": st["max_requests_in_flight"],
-            "max_launches_in_flight": st["max_launches_in_flight"],
-            "peak_admitted_GB": st["peak_bytes"] / 1e9,
-        }
-        log(f"{name}: {results[name]['requests_per_s']:.1f} req/s, p50 "
-            f"{results[name]['p50_ms']:.1f} ms, p99 {results[name]['p99_ms']:.1f} ms, "
-            f"in flight up to {st['max_requests_in_flight']} requests / "
-            f"{st['max_launches_in_flight']} launches")
     for h in hams:
         h.sync()
         h.close()
-    best = results["continuous_fp32k"]
+    sat = sweep[-1]
+    best = sat["continuous_fp32k"]
     out = {
         "metric": "served E_loc requests/s with p50/p99 latency",
         "value": best["requests_per_s"],
@@ -148,10 +161,12 @@ def run(args, log):
         "ms_per_step": 1e3 / best["requests_per_s"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+kahan/f64", "data": "synthetic",
         "config": {"workload": f"{n_jobs} synthetic VMC jobs (qubits 24..80, samples 1e3..2e5), "
-                               f"Poisson arrivals {rate:.0f}/s, {n_req} requests, 64 GB budget",
-                   "pair_evaluations": req_pairs},
+                               f"Poisson arrivals at {rates} per s, {n_req} requests per point, "
+                               f"64 GB budget, 4 lanes"},
         "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"],
-        "modes": results,
-        "throughput_vs_serial_fp64": best["requests_per_s"] / results["serial_fp64"]["requests_per_s"],
+        "sweep": sweep,
+        "saturation_throughput_vs_serial_fp64": {
+            name: sat[name]["requests_per_s"] / sat["serial_fp64"]["requests_per_s"]
+            for name, _, _ in MODES},
     }
     print(json.dumps(out), flush=True)

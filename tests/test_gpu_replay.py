@@ -69,7 +69,7 @@ def test_replays_equal_eager(torch_dev, workload_cache, name, n, precision):
             # profiled calls run eagerly: every call times its own kernels
             ms = ham.last_kernel_ms()
             assert ms[1] > 0.0, ms
-            profiled.append(ms[1])
+            profiled.append(tuple(ms))
         e = ref.eloc(S, la, ph, wt, precision=precision)
         ref.sync()
         want = torch.view_as_real(e).cpu().numpy()
@@ -78,7 +78,9 @@ def test_replays_equal_eager(torch_dev, workload_cache, name, n, precision):
         m_want = nqs.energy(wt, torch.view_as_real(e).contiguous())
         assert m_got[0] == m_want[0] and m_got[1] == m_want[1], (m_got, m_want)
     ham.profile(False)
-    # three calls, three measurements (not one replayed timestamp pair)
+    # three calls, three measurements (not one replayed set of timestamps);
+    # a single stage of a small batch can repeat its duration to the tick, so
+    # the stages are compared together
     assert len(set(profiled)) > 1, profiled
     # a different batch size in between: eager again, then replays again
     k = n // 2
