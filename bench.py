@@ -150,6 +150,8 @@ def main():
                     help="lookup strategy: group streaming, flip enumeration or pair join "
                          "(auto: the device picks by counted cost)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-strategy-compare", action="store_true",
+                    help="skip the forced-enumeration comparison run (profiler passes)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--mode", default="single", choices=["single", "batched", "serve", "copy"],
                     help="single: the headline step; batched: 32 Hamiltonians in one "
@@ -390,7 +392,7 @@ def main():
             "abs_err_re_energy_fp32k_vs_fp64_Ha": abs(e_fp32k.real - e_fp64.real),
         },
     }
-    if joined and ham.plan().get("join_ran") == 1:
+    if joined and ham.plan().get("join_ran") == 1 and not args.no_strategy_compare:
         res["compare_strategy"] = compare_enumeration(ham, out, S, la, ph, wt, args, log, pairs)
     ham.close()
     if not args.no_secondary:

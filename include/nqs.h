@@ -139,6 +139,27 @@ int nqs_table_host(int n_qubits, int64_t n_terms, const uint64_t *x_masks,
                    double *term_c);
 
 /*
+ * Host-only form of the occupation-form diagonal that the finish kernel
+ * evaluates on the matrix cores (no device needed).  For a table whose X = 0
+ * group has only Z strings of at most two qubits, Z_i = 1 - 2 n_i turns the
+ * group into d0 + sum_{i <= j} n_i n_j U[j][i]; the U are stored as 64-bit
+ * fixed point (U 2^S rounded, S the largest integer keeping every |U| 2^S
+ * below 2^62) in eight balanced base-256 int8 digits, least significant
+ * first, as 16 x 16 x 64 int8 MFMA operand tiles: for column tile jt (j in
+ * [16 jt, 16 jt + 16), ceil(n_qubits / 16) of them) its k-blocks kb of 64
+ * rows i (one for jt < 4, two after), then per digit 64 lanes x 16 bytes,
+ * lane L byte b holding the digit of U[16 jt + L % 16][64 kb + 16 (L / 16)
+ * + b] (zero where i > j or outside the register).  Call with tiles NULL to
+ * obtain *n_bytes (0: the table has no such form), then with a buffer of
+ * that size.  *d0 receives d0 and *scale 2^-S.  Same arguments, validation
+ * and errors as nqs_ham_create.
+ */
+int nqs_diag_tiles_host(int n_qubits, int64_t n_terms, const uint64_t *x_masks,
+                        const uint64_t *z_masks, const double *coeffs,
+                        const uint64_t *spin_masks, int64_t *n_bytes, int8_t *tiles,
+                        double *d0, double *scale);
+
+/*
  * Local energies of one batch (Eq. 5 over S, Alg. 3's per-sample outer loop).
  *
  *   samples : device, [n][2] uint64, unique bit strings, bits >= n_qubits zero.
@@ -178,7 +199,7 @@ int nqs_eloc_eval(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *
  * call's own kernels.  Two calls that overlap on one device (different
  * streams, threads or handles) race on it and give undefined results: the
  * caller serialises them.  The scratch needed grows with n (at 100 qubits
- * and 262,144 samples about 126 MB, the pair join's buckets included): a
+ * and 262,144 samples about 125 MB, the pair join's entries included): a
  * batch that needs more than the array holds returns NQS_E_ARG before
  * anything is launched.  Arguments, other
  * errors and asynchrony as nqs_eloc_eval; NQS_E_STATE also when the
@@ -307,13 +328,15 @@ int nqs_debug_dump(nqs_ham h, int64_t n, const uint64_t *samples, const double *
  *     samples sharing a bucket are tested (Hamming distance, then the group
  *     index).  Its cost is the sum of squared bucket sizes, independent of
  *     the table's size: for samples spread over a large sector it is far
- *     below both others.  Needs m + 1 <= 8 and at most 8192 samples in one
- *     bucket; otherwise (decided on the device) the enumeration or streaming
+ *     below both others.  Needs m + 1 <= 8, at most 2^21 samples, and at
+ *     most 8192 entries in one partition of 2^10 buckets (a hash range of
+ *     the bucket keys; about a thousand entries each on average);
+ *     otherwise (decided on the device) the enumeration or streaming
  *     strategy runs instead.
  *   NQS_STRATEGY_AUTO (0): the pair join is launched beside the enumeration
  *     (where the table allows it) or streaming, and the device runs the
  *     join when its counted cost (sum of squared bucket sizes plus a term
- *     per entry and bucket) is below the other strategy's (the
+ *     per entry) is below the other strategy's (the
  *     enumeration's lookups, or half the sample-group pairs of streaming).
  *     Batches (nqs_batch_*) and the server never run the pair join.
  */

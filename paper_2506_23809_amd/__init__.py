@@ -38,7 +38,7 @@ _PRECISION = {"fp64": NQS_FP64, "fp32k": NQS_FP32_KAHAN, "fp32_kahan": NQS_FP32_
 # Every symbol include/nqs.h declares.
 EXPORTS = ("nqs_last_error", "nqs_version", "nqs_ham_create", "nqs_ham_create_integrals",
            "nqs_ham_info", "nqs_ham_destroy",
-           "nqs_table_host", "nqs_eloc_eval", "nqs_energy", "nqs_sync", "nqs_eval_stats",
+           "nqs_table_host", "nqs_diag_tiles_host", "nqs_eloc_eval", "nqs_energy", "nqs_sync", "nqs_eval_stats",
            "nqs_eval_plan", "nqs_debug_fail_allocs", "nqs_eloc_eval_noalloc",
            "nqs_debug_dump", "nqs_profile", "nqs_last_kernel_ms", "nqs_set_tuning",
            "nqs_get_tuning", "nqs_autotune", "nqs_batch_create", "nqs_batch_launch",
@@ -101,6 +101,7 @@ def load_library(path: str = LIB_PATH):
         "nqs_ham_info": (I, [P, P, P, P]),
         "nqs_ham_destroy": (I, [P]),
         "nqs_table_host": (I, [I, I64, P, P, P, P, P, P, P, P, P]),
+        "nqs_diag_tiles_host": (I, [I, I64, P, P, P, P, P, P, P, P]),
         "nqs_eloc_eval": (I, [P, I64, P, P, P, P, P, I, P]),
         "nqs_eloc_eval_noalloc": (I, [P, I64, P, P, P, P, P, I, P]),
         "nqs_energy": (I, [I64, P, P, P, P]),
@@ -185,6 +186,26 @@ def table_host(n_qubits, x, z, c):
     _check(lib.nqs_table_host(*args, ctypes.byref(G), ctypes.byref(T), gx.ctypes.data,
                               go.ctypes.data, tz.ctypes.data, tc.ctypes.data))
     return gx, go, tz, tc
+
+
+def diag_tiles_host(n_qubits, x, z, c, spin_masks=None):
+    """Host-only digit tiles of the occupation-form diagonal
+    (nqs_diag_tiles_host): (tiles int8 array, d0, scale); tiles is empty when
+    the table has no occupation form."""
+    lib = load_library()
+    x, z = _np_u64(x), _np_u64(z)
+    c = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+    sm = None if spin_masks is None else _np_u64(spin_masks)
+    nb = ctypes.c_int64()
+    d0 = ctypes.c_double()
+    sc = ctypes.c_double()
+    args = (int(n_qubits), x.shape[0], x.ctypes.data, z.ctypes.data, c.ctypes.data,
+            None if sm is None else sm.ctypes.data)
+    _check(lib.nqs_diag_tiles_host(*args, ctypes.byref(nb), None, None, None))
+    tiles = np.zeros(nb.value, np.int8)
+    _check(lib.nqs_diag_tiles_host(*args, ctypes.byref(nb), tiles.ctypes.data if nb.value else None,
+                                   ctypes.byref(d0), ctypes.byref(sc)))
+    return tiles, d0.value, sc.value
 
 
 class Hamiltonian:

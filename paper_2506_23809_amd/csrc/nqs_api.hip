@@ -578,21 +578,11 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
         diag32[2 * k] = hi;
         diag32[2 * k + 1] = static_cast<float>(T.diag[k] - static_cast<double>(hi));
     }
-    // the pair terms of the occupation form as a zero-padded 128 x 128
-    // triangle (row j, column i < j) and the single terms padded to 128, for
-    // the dense diagonal sum
-    std::vector<double> diag_u, diag_d1;
-    if (T.diag_occ) {
-        const int nq = T.n_qubits;
-        diag_u.assign(size_t(nqs::kDiagPad) * nqs::kDiagPad, 0.0);
-        diag_d1.assign(nqs::kDiagPad, 0.0);
-        for (int j = 0; j < nq; ++j) {
-            diag_d1[j] = T.diag[1 + j];
-            for (int i = 0; i < j; ++i)
-                diag_u[size_t(j) * nqs::kDiagPad + i] =
-                    T.diag[1 + nq + size_t(j) * (j - 1) / 2 + i];
-        }
-    }
+    // the occupation form as int8 digit tiles for the matrix cores
+    std::vector<int8_t> diag_q8;
+    double diag_scale = 1.0;
+    const int diag_jtiles = T.diag_occ ? (T.n_qubits + 15) / 16 : 0;
+    if (T.diag_occ) nqs::build_diag_tiles(T, &diag_q8, &diag_scale);
     std::vector<uint32_t> goff32(T.goff.size());
     for (size_t k = 0; k < T.goff.size(); ++k) goff32[k] = static_cast<uint32_t>(T.goff[k]);
     const nqs::LinearHash lh;
@@ -617,8 +607,7 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
         {T.qcls, sizeof(T.qcls), 0},
         {T.diag.data(), sizeof(double) * T.diag.size(), 0},
         {diag32.data(), sizeof(float) * diag32.size(), 0},
-        {diag_u.data(), sizeof(double) * diag_u.size(), 0},
-        {diag_d1.data(), sizeof(double) * diag_d1.size(), 0},
+        {diag_q8.data(), diag_q8.size(), 0},
     };
     size_t total = 0;
     for (Piece &p : pieces) {
@@ -704,8 +693,9 @@ int create_handle(nqs_ham *out, const nqs::HostTable &T, const std::vector<doubl
     d.diag_occ = T.diag_occ ? 1 : 0;
     d.diag = T.diag_occ ? reinterpret_cast<const double *>(base + pieces[13].off) : nullptr;
     d.diag32 = T.diag_occ ? reinterpret_cast<const float *>(base + pieces[14].off) : nullptr;
-    d.diag_u = T.diag_occ ? reinterpret_cast<const double *>(base + pieces[15].off) : nullptr;
-    d.diag_d1 = T.diag_occ ? reinterpret_cast<const double *>(base + pieces[16].off) : nullptr;
+    d.diag_q8 = T.diag_occ ? reinterpret_cast<const int8_t *>(base + pieces[15].off) : nullptr;
+    d.diag_scale = diag_scale;
+    d.diag_jtiles = diag_jtiles;
     *out = h;
     return NQS_OK;
 }

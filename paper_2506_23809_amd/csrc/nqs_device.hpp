@@ -5,10 +5,18 @@
 
 #include <cstdint>
 
+#include "nqs_table.hpp"
+
 namespace nqs {
 
-// Rows of the padded diagonal triangle (at least the largest register).
-constexpr int kDiagPad = 128;
+// The occupation-form diagonal for the matrix cores: digit tiles of the
+// 16 x 16 x 64 int8 MFMA (64 lanes x 16 bytes each, kDiagLimbs digits; see
+// build_diag_tiles).  Column tile jt (qubits j in [16 jt, 16 jt + 16))
+// needs the rows i <= j: one k-block of 64 rows for jt < 4, two after.
+constexpr int kDiagTileBytes = 64 * 16;
+__host__ __device__ constexpr int diag_mfma_tiles(int jtiles) {
+    return jtiles <= 4 ? jtiles : 4 + 2 * (jtiles - 4);
+}
 
 // Pair join: at most this many qubit blocks (a table whose groups flip up to
 // kJoinMaxBlocks - 1 qubits).
@@ -48,11 +56,12 @@ struct DevTable {
     int diag_occ;
     const double *diag;
     const float *diag32;
-    // the same form for the dense FP64 sum: the pair terms as a zero-padded
-    // kDiagPad x kDiagPad triangle (row j, column i < j) and the single terms
-    // d[1 + j] padded to kDiagPad
-    const double *diag_u;
-    const double *diag_d1;
+    // the same form for the matrix cores (see kDiagLimbs): digit tiles
+    // [diag_mfma_tiles(diag_jtiles)][kDiagLimbs][64][16], 2^-S, and the
+    // column tiles (ceil(n_qubits / 16); 0 without the form)
+    const int8_t *diag_q8;
+    double diag_scale;
+    int diag_jtiles;
     // pair join: the qubits split into join_blocks disjoint blocks (jmask);
     // two bit strings at Hamming distance at most max_flip < join_blocks
     // agree on at least one block (pigeonhole), so every connected pair of
@@ -187,34 +196,41 @@ struct DevScratch {
     char *eblk;
     int64_t eblk_stride;
     uint32_t eblk_blocks;
-    // pair join (all null when the launch plans none): buckets of samples
-    // by block contents, join_blocks << join_log2m of them, block-major
-    uint32_t *jcnt;             // [buckets] counts -> start offsets -> bucket ends
-    uint32_t *jsize;            // [buckets] bucket sizes
-    uint32_t *jkey;             // [blocks][n] bucket of each (block, sample)
-    // entries of the buckets that hold two samples or more (a sample alone
-    // in its bucket has no partner there and takes no entry):
-    uint32_t *jent;             // [<= blocks * n] sample index, by bucket, ascending
-    uint2 *jrange;              // [<= blocks * n] [start, end) of each entry's bucket
-    uint64_t *jkeys;            // [<= blocks * n][2] bit string of each entry
-    uint8_t *jblk;              // [<= blocks * n] block of each entry
-    uint32_t *jbig;             // [blocks * n] buckets left to the block sorter
-    unsigned long long *jscan;  // [3][scan blocks] count, sum of squares, largest
+    // pair join (all null when the launch plans none).  A bucket is
+    // (block b, slot of the hash of x's contents on b), key (b << join_log2m)
+    // | slot; a partition is the buckets of one key prefix,
+    // key >> join_lshift, join_parts of them
+    uint32_t *jcnt;             // [parts] entries per partition
+    uint32_t *jkey;             // [blocks][n] bucket key of each (block, sample)
+    uint32_t *jtbase;           // [tiles][parts] each tile's first slot in a partition
+    uint32_t *jpoff;            // [parts + 1] first entry of each partition
+    // entries by partition, then bucket, then sample index
+    unsigned long long *jent;   // [blocks * n] (key & (2^join_lshift - 1)) << 32 | sample
+    unsigned long long *jrange; // [blocks * n] first entry of the entry's bucket |
+                                // bucket size << 32 | block << 48
+    uint64_t *jkeys;            // [blocks * n][2] the entry's bit string
+    unsigned long long *jstat;  // [parts][2] sum of squared bucket sizes, largest bucket
     unsigned long long *jctl;   // [kJoinCtl] see kJoinCtl*
     int join_log2m;
+    int join_lshift;
+    int join_parts;
+    int join_tile;              // samples per tile of the grouping kernels
+    int join_tiles;
     int join_force;             // 1: join whenever it can run, 0: when cheaper
 };
 
 // Pair-join control words (jctl): the enumeration's probe count, the join's
 // ordered candidate pairs (sum of squared bucket sizes), the largest bucket,
-// buckets for the block sorter, and the decision (1: the join runs).
-enum { kJoinCtlProbes = 0, kJoinCtlCost = 1, kJoinCtlMax = 2, kJoinCtlBig = 3,
-       kJoinCtlChosen = 4, kJoinCtlEntries = 5, kJoinCtlProbeSlots = 8, kJoinCtl = 8 + 64 };
-// Counters per scan block of the bucket counts (1024 threads x 4).
-constexpr int kJoinScanItems = 4096;
-// Largest bucket the block sorter takes (entries in LDS); a larger one
+// whether a partition exceeded kJoinPartCap, and the decision (1: the join
+// runs); then 64 slots of the probe count.
+enum { kJoinCtlProbes = 0, kJoinCtlCost = 1, kJoinCtlMax = 2, kJoinCtlOver = 3,
+       kJoinCtlChosen = 4, kJoinCtlProbeSlots = 8, kJoinCtl = 8 + 64 };
+// Largest partition the per-partition sorter holds in LDS; a larger one
 // leaves the batch to the other strategies.
-constexpr int kJoinMaxBucket = 8192;
+constexpr int kJoinPartCap = 8192;
+// Largest batch the join is planned for: its partitions then have at most
+// 2^11 buckets (the sorter's bucket counts in LDS).
+constexpr int64_t kJoinMaxSamples = int64_t(1) << 21;
 
 // Whether the pair join was chosen for this launch (device side).
 __device__ __forceinline__ bool join_chosen(const DevScratch &sc) {

@@ -60,4 +60,29 @@ int nqs_table_host(int n_qubits, int64_t n_terms, const uint64_t *x_masks,
     return NQS_OK;
 }
 
+int nqs_diag_tiles_host(int n_qubits, int64_t n_terms, const uint64_t *x_masks,
+                        const uint64_t *z_masks, const double *coeffs,
+                        const uint64_t *spin_masks, int64_t *n_bytes, int8_t *tiles,
+                        double *d0, double *scale) {
+    using nqs::detail::fail;
+    if (!n_bytes) return fail(NQS_E_ARG, "null size output");
+    nqs::HostTable T;
+    std::string err;
+    std::vector<int8_t> q8;
+    double sc = 1.0;
+    int rc;
+    try {
+        rc = nqs::build_table(n_qubits, n_terms, x_masks, z_masks, coeffs, spin_masks, &T, &err);
+        if (rc == 0) nqs::build_diag_tiles(T, &q8, &sc);
+    } catch (const std::bad_alloc &) {
+        return fail(NQS_E_NOMEM, "host allocation failed");
+    }
+    if (rc) return fail(rc, err);
+    *n_bytes = static_cast<int64_t>(q8.size());
+    if (tiles && !q8.empty()) std::memcpy(tiles, q8.data(), q8.size());
+    if (d0) *d0 = T.diag_occ ? T.diag[0] : 0.0;
+    if (scale) *scale = sc;
+    return NQS_OK;
+}
+
 }  // extern "C"

@@ -14,19 +14,26 @@
 // X = x ^ x' exists, and a hit adds <x|H|x'> psi(x')/psi(x) with the same
 // sums as the other strategies.
 //
+// Grouping without global atomics per entry: the bucket keys are split into
+// partitions by their high bits (about a thousand entries each).  A tile of
+// samples counts its entries per partition in LDS and reserves its share
+// of each partition with one atomic; the entries are then placed, each
+// partition is sorted in LDS by (bucket, sample), and its bucket starts and
+// sizes are written beside the entries.  The pair kernel then takes one
+// lane per entry.
+//
 // Cost: the ordered pairs inside buckets, the sum of squared bucket sizes.
 // For samples spread over a large sector this is far below the
 // enumeration's N x (connected states per sample) lookups.  The decision is
 // taken on the device from the bucket sizes, between the hash clear and the
 // hash build: when the join is cheaper it runs, and the hash build's
 // insertion, the enumeration and the streaming kernels of the same launch
-// stand down; otherwise those run and the join's later kernels return at
-// once.
+// stand down; otherwise those run and the pair kernel returns at once.
 //
-// Determinism: the entries of a bucket are sorted by sample index before the
-// pair kernel runs, so each sample's hits are added in a fixed order (one
-// partial per block, partners in index order), and the finish kernel adds
-// the block partials in block order.
+// Determinism: a partition is sorted by sample index within each bucket, so
+// each sample's hits are added in a fixed order (one partial per block,
+// partners in index order), and the finish kernel adds the block partials
+// in block order.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -39,28 +46,28 @@ namespace nqs {
 
 namespace {
 
-constexpr int kJoinThreads = 256;
-constexpr int kJoinScanThreads = kJoinScanItems / 4;
-constexpr int kJoinSmallSort = 32;  // buckets up to this size are sorted in registers
-constexpr int kJoinSortThreads = 1024;
+constexpr int kJoinGroupThreads = 1024;  // tile kernels, sorter, decision
+constexpr int kJoinPairThreads = 256;
+constexpr int kJoinSortThreads = 512;
+constexpr int kJoinMaxParts = 8192;      // partitions of any planned launch
+constexpr int kJoinMaxLocal = 2048;      // buckets per partition (2^join_lshift)
+constexpr int kJoinTiles = 128;          // tiles of the grouping kernels, at most
 
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
-// Bucket of block b of x: the block index in the top bits, a hash of the
-// block's contents below (equal contents, equal bucket).
+// Bucket key of block b of x: the block index in the top bits, a hash of
+// the block's contents below (equal contents, equal bucket).  The hash is a
+// 64-bit multiply-xorshift mix of the masked words (any hash serves: only
+// equal contents must meet).
 template <int W>
 __device__ __forceinline__ uint32_t join_bucket(const DevTable &tab, const Key<W> &x, int b,
                                                 int log2m) {
-    uint32_t h = 0;
-#pragma unroll
-    for (int q = 0; q < W; ++q) {
-        uint64_t v = x.w[q] & tab.jmask[b][q];
-        while (v) {
-            h ^= tab.hr[64 * q + __builtin_ctzll(v)];
-            v &= v - 1;
-        }
-    }
-    const uint32_t slot = log2m > 0 ? (h * kGoldenMul) >> (32 - log2m) : 0u;
+    uint64_t z = x.w[0] & tab.jmask[b][0];
+    if constexpr (W == 2) z ^= (x.w[W - 1] & tab.jmask[b][1]) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const uint32_t slot = static_cast<uint32_t>(z >> (64 - log2m));
     return (static_cast<uint32_t>(b) << log2m) | slot;
 }
 
@@ -111,69 +118,54 @@ __device__ __forceinline__ unsigned long long block_exclusive_scan(unsigned long
     return before + inc - v;
 }
 
-// In-register bitonic sort of N values (N a power of two; constant indices).
-template <int N>
-__device__ __forceinline__ void bitonic_regs(uint32_t (&v)[N]) {
-#pragma unroll
-    for (int k = 2; k <= N; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint32_t a = v[i], b = v[l];
-                    const bool sw = ((i & k) == 0) ? (a > b) : (a < b);
-                    v[i] = sw ? b : a;
-                    v[l] = sw ? a : b;
-                }
-            }
-        }
+// Sum and maximum over the block (blockDim.x a multiple of 64, at most
+// 1024 threads), valid in thread 0.  Synchronises.
+__device__ __forceinline__ void block_sum_max(unsigned long long &s, unsigned long long &m) {
+    __shared__ unsigned long long red[2][16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    s = wave_sum(s);
+    m = wave_max(m);
+    if (lane == 0) {
+        red[0][wave] = s;
+        red[1][wave] = m;
     }
-}
-
-// Entry p of the sorted bucket [s, e) of block b: sample j, its bit
-// string, the range, the block.
-__device__ __forceinline__ void join_put(const DevScratch &sc, const uint64_t *__restrict__ samples,
-                                         uint32_t p, uint32_t j, uint32_t s, uint32_t e,
-                                         uint32_t b) {
-    sc.jent[p] = j;
-    const uint4 key = reinterpret_cast<const uint4 *>(samples)[j];
-    reinterpret_cast<uint4 *>(sc.jkeys)[p] = key;
-    sc.jrange[p] = make_uint2(s, e);
-    sc.jblk[p] = static_cast<uint8_t>(b);
-}
-
-template <int N>
-__device__ __forceinline__ void join_sort_put(const DevScratch &sc,
-                                              const uint64_t *__restrict__ samples, uint32_t s,
-                                              uint32_t m, uint32_t b) {
-    uint32_t v[N];
-#pragma unroll
-    for (int t = 0; t < N; ++t) v[t] = static_cast<uint32_t>(t) < m ? sc.jent[s + t] : 0xFFFFFFFFu;
-    bitonic_regs<N>(v);
-#pragma unroll
-    for (int t = 0; t < N; ++t)
-        if (static_cast<uint32_t>(t) < m) join_put(sc, samples, s + t, v[t], s, s + m, b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long S = 0, M = 0;
+        for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
+            S += red[0][w];
+            M = red[1][w] > M ? red[1][w] : M;
+        }
+        s = S;
+        m = M;
+    }
+    __syncthreads();
 }
 
 // ---- kernels
 
-// Per sample: its bucket in every block (counted), whether the batch spans
-// several (N_alpha, N_beta) sectors, and the enumeration's lookups for it
-// (its spin-conserving singles and doubles), summed for the decision.
+// One block per tile of samples: the bucket key of every (block, sample),
+// the tile's entries per partition (LDS) and its reserved range in each
+// partition (one global atomic per partition it touches); also whether the
+// batch spans several (N_alpha, N_beta) sectors and the enumeration's
+// lookups for it (its spin-conserving singles and doubles), summed for the
+// decision.
 template <int W>
-__global__ __launch_bounds__(kJoinThreads) void join_count_kernel(DevTable tab, DevScratch sc,
-                                                                  const uint64_t *__restrict__ samples,
-                                                                  int64_t n) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kJoinGroupThreads) void join_hist_kernel(
+    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n) {
+    __shared__ uint32_t hist[kJoinMaxParts];
+    const int parts = sc.join_parts, lshift = sc.join_lshift, log2m = sc.join_log2m;
+    for (int p = threadIdx.x; p < parts; p += blockDim.x) hist[p] = 0u;
+    __syncthreads();
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * sc.join_tile;
+    const int64_t t1 = t0 + sc.join_tile < n ? t0 + sc.join_tile : n;
     unsigned long long probes = 0;
-    if (i < n) {
+    for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
         const Key<W> x = load_key<W>(samples, i);
         for (int b = 0; b < tab.join_blocks; ++b) {
-            const uint32_t k = join_bucket<W>(tab, x, b, sc.join_log2m);
+            const uint32_t k = join_bucket<W>(tab, x, b, log2m);
             sc.jkey[static_cast<int64_t>(b) * n + i] = k;
-            atomicAdd(&sc.jcnt[k], 1u);
+            atomicAdd(&hist[k >> lshift], 1u);
         }
         if (tab.sector_filter) {
             const uint64_t w0 = x.w[0], w1 = W == 2 ? x.w[W - 1] : 0ull;
@@ -186,91 +178,152 @@ __global__ __launch_bounds__(kJoinThreads) void join_count_kernel(DevTable tab, 
             if (tab.enum_ok) {
                 const unsigned long long va = tab.k_alpha - na, vb = tab.k_beta - nb;
                 const unsigned long long a = na, bb = nb;
-                probes = a * va + bb * vb + (a * (a - 1) / 2) * (va * (va - 1) / 2) +
-                         (bb * (bb - 1) / 2) * (vb * (vb - 1) / 2) + a * va * bb * vb;
+                probes += a * va + bb * vb + (a * (a - 1) / 2) * (va * (va - 1) / 2) +
+                          (bb * (bb - 1) / 2) * (vb * (vb - 1) / 2) + a * va * bb * vb;
             }
         }
     }
+    __syncthreads();
+    uint32_t *tbase = sc.jtbase + static_cast<int64_t>(blockIdx.x) * parts;
+    for (int p = threadIdx.x; p < parts; p += blockDim.x) {
+        const uint32_t c = hist[p];
+        if (c) tbase[p] = atomicAdd(&sc.jcnt[p], c);
+    }
     probes = wave_sum(probes);
     if ((threadIdx.x & 63) == 0 && probes)
-        atomicAdd(&sc.jctl[kJoinCtlProbeSlots + blockIdx.x % 64], probes);
+        atomicAdd(&sc.jctl[kJoinCtlProbeSlots + (blockIdx.x * 16 + (threadIdx.x >> 6)) % 64],
+                  probes);
 }
 
-// Per scan block of kJoinScanItems bucket counts: the entries they take
-// (buckets of two samples or more), the sum of their squares and the
-// largest.
-__global__ __launch_bounds__(kJoinScanThreads) void join_scan_sums_kernel(DevScratch sc,
-                                                                          int64_t buckets) {
-    __shared__ unsigned long long part[3][kJoinScanThreads / 64];
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * kJoinScanItems + 4 * threadIdx.x;
-    unsigned long long s = 0, q = 0, m = 0;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const unsigned long long v = base + t < buckets ? sc.jcnt[base + t] : 0u;
-        s += v >= 2 ? v : 0;
-        q += v * v;
-        m = v > m ? v : m;
+// One block per tile: the partition starts (every block scans the
+// partition counts itself; block 0 stores them), then each entry of the
+// tile goes to the next free place of its partition's range for the tile.
+__global__ __launch_bounds__(kJoinGroupThreads) void join_place_kernel(DevTable tab, DevScratch sc,
+                                                                       int64_t n) {
+    __shared__ uint32_t base[kJoinMaxParts];
+    const int parts = sc.join_parts, lshift = sc.join_lshift;
+    const int per = (parts + blockDim.x - 1) / blockDim.x;
+    const int p0 = threadIdx.x * per;
+    unsigned long long own = 0;
+    for (int p = p0; p < p0 + per && p < parts; ++p) own += sc.jcnt[p];
+    unsigned long long total;
+    unsigned long long run = block_exclusive_scan(own, &total);
+    const uint32_t *tbase = sc.jtbase + static_cast<int64_t>(blockIdx.x) * parts;
+    for (int p = p0; p < p0 + per && p < parts; ++p) {
+        if (blockIdx.x == 0) sc.jpoff[p] = static_cast<uint32_t>(run);
+        // a partition this tile has no entry in is never looked up
+        base[p] = static_cast<uint32_t>(run) + tbase[p];
+        run += sc.jcnt[p];
     }
-    s = wave_sum(s);
-    q = wave_sum(q);
-    m = wave_max(m);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        part[0][wave] = s;
-        part[1][wave] = q;
-        part[2][wave] = m;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc.jpoff[parts] = static_cast<uint32_t>(total);
+    __syncthreads();
+    const uint32_t lmask = (1u << lshift) - 1u;
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * sc.join_tile;
+    const int64_t t1 = t0 + sc.join_tile < n ? t0 + sc.join_tile : n;
+    for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
+        for (int b = 0; b < tab.join_blocks; ++b) {
+            const uint32_t k = sc.jkey[static_cast<int64_t>(b) * n + i];
+            const uint32_t pos = atomicAdd(&base[k >> lshift], 1u);
+            sc.jent[pos] = (static_cast<unsigned long long>(k & lmask) << 32) |
+                           static_cast<unsigned long long>(i);
+        }
+    }
+}
+
+// One block per partition: its entries ordered by (bucket, sample) and
+// written back, each with its bucket's range and block and its bit string;
+// the partition's sum of squared bucket sizes and largest bucket.  A
+// counting sort by bucket (LDS counts, their scan, then each entry at its
+// bucket's start plus a second atomic count) groups the buckets; an
+// entry's place inside its bucket is then the number of members with a
+// smaller sample index (a pass over the bucket, as long as the pair
+// kernel's).  LDS holds 4 bytes per entry (bucket << 21 | sample), so that
+// several blocks share a CU.  A partition of more than kJoinPartCap entries
+// is only flagged (the join then does not run).
+__global__ __launch_bounds__(kJoinSortThreads) void join_sort_kernel(
+    DevScratch sc, const uint64_t *__restrict__ samples) {
+    __shared__ uint32_t buf[kJoinPartCap];
+    __shared__ uint32_t cnt[kJoinMaxLocal];
+    __shared__ uint32_t fill[kJoinMaxLocal];
+    const int p = blockIdx.x;
+    const uint32_t c = sc.jcnt[p];
+    const uint32_t s0 = sc.jpoff[p];
+    if (c > static_cast<uint32_t>(kJoinPartCap)) {
+        if (threadIdx.x == 0) {
+            sc.jstat[2 * p] = static_cast<unsigned long long>(c) * c;
+            sc.jstat[2 * p + 1] = c;
+            sc.jctl[kJoinCtlOver] = 1ull;
+        }
+        return;
+    }
+    const int L = 1 << sc.join_lshift;
+    for (int u = threadIdx.x; u < L; u += blockDim.x) {
+        cnt[u] = 0u;
+        fill[u] = 0u;
     }
     __syncthreads();
+    for (uint32_t u = threadIdx.x; u < c; u += blockDim.x)
+        atomicAdd(&cnt[static_cast<uint32_t>(sc.jent[s0 + u] >> 32)], 1u);
+    __syncthreads();
+    // bucket starts (exclusive scan of the counts), packed with the sizes
+    const int per = (L + blockDim.x - 1) / blockDim.x;
+    const int u0 = threadIdx.x * per;
+    unsigned long long own = 0, sq = 0, mx = 0;
+    for (int u = u0; u < u0 + per && u < L; ++u) {
+        const unsigned long long v = cnt[u];
+        own += v;
+        sq += v * v;
+        mx = v > mx ? v : mx;
+    }
+    unsigned long long total;
+    unsigned long long run = block_exclusive_scan(own, &total);
+    for (int u = u0; u < u0 + per && u < L; ++u) {
+        const uint32_t v = cnt[u];
+        cnt[u] = static_cast<uint32_t>(run) | (v << 16);
+        run += v;
+    }
+    __syncthreads();
+    for (uint32_t u = threadIdx.x; u < c; u += blockDim.x) {
+        const unsigned long long e = sc.jent[s0 + u];
+        const uint32_t loc = static_cast<uint32_t>(e >> 32);
+        const uint32_t at = (cnt[loc] & 0xFFFFu) + atomicAdd(&fill[loc], 1u);
+        buf[at] = (loc << 21) | static_cast<uint32_t>(e);
+    }
+    __syncthreads();
+    const unsigned long long blk =
+        static_cast<unsigned long long>(p >> (sc.join_log2m - sc.join_lshift));
+    uint4 *keys = reinterpret_cast<uint4 *>(sc.jkeys);
+    for (uint32_t u = threadIdx.x; u < c; u += blockDim.x) {
+        const uint32_t v = buf[u];
+        const uint32_t loc = v >> 21, me = v & 0x1FFFFFu;
+        const uint32_t r = cnt[loc];
+        const uint32_t bs = r & 0xFFFFu, m = r >> 16;
+        uint32_t rank = 0;
+        for (uint32_t q = bs; q < bs + m; ++q) rank += (buf[q] & 0x1FFFFFu) < me ? 1u : 0u;
+        const uint32_t dst = s0 + bs + rank;
+        sc.jent[dst] = (static_cast<unsigned long long>(loc) << 32) | me;
+        sc.jrange[dst] = (s0 + bs) | (static_cast<unsigned long long>(m) << 32) | (blk << 48);
+        keys[dst] = reinterpret_cast<const uint4 *>(samples)[me];
+    }
+    block_sum_max(sq, mx);
     if (threadIdx.x == 0) {
-        unsigned long long S = 0, Q = 0, M = 0;
-        for (int w = 0; w < kJoinScanThreads / 64; ++w) {
-            S += part[0][w];
-            Q += part[1][w];
-            M = part[2][w] > M ? part[2][w] : M;
-        }
-        const int64_t nb = gridDim.x;
-        sc.jscan[blockIdx.x] = S;
-        sc.jscan[nb + blockIdx.x] = Q;
-        sc.jscan[2 * nb + blockIdx.x] = M;
+        sc.jstat[2 * p] = sq;
+        sc.jstat[2 * p + 1] = mx;
     }
 }
 
-// One block: the exclusive scan of the scan blocks' sums (in place), the
-// join's cost and largest bucket, and the decision.
-__global__ __launch_bounds__(1024) void join_decide_kernel(DevTable tab, DevScratch sc,
-                                                           const uint64_t *__restrict__ samples,
-                                                           int64_t n, int64_t nscan,
-                                                           int64_t g_eff) {
-    __shared__ unsigned long long red[2][16];
-    unsigned long long carry = 0, q = 0, m = 0;
-    for (int64_t c0 = 0; c0 < nscan; c0 += blockDim.x) {
-        const int64_t t = c0 + threadIdx.x;
-        unsigned long long v = 0;
-        if (t < nscan) {
-            v = sc.jscan[t];
-            q += sc.jscan[nscan + t];
-            const unsigned long long mm = sc.jscan[2 * nscan + t];
-            m = mm > m ? mm : m;
-        }
-        unsigned long long total;
-        const unsigned long long ex = block_exclusive_scan(v, &total);
-        if (t < nscan) sc.jscan[t] = carry + ex;
-        carry += total;
+// One block: the join's cost and largest bucket over the partitions, and
+// the decision.
+__global__ __launch_bounds__(kJoinGroupThreads) void join_decide_kernel(
+    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n, int64_t g_eff) {
+    unsigned long long q = 0, m = 0;
+    for (int p = threadIdx.x; p < sc.join_parts; p += blockDim.x) {
+        q += sc.jstat[2 * p];
+        const unsigned long long mm = sc.jstat[2 * p + 1];
+        m = mm > m ? mm : m;
     }
-    q = wave_sum(q);
-    m = wave_max(m);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[0][wave] = q;
-        red[1][wave] = m;
-    }
-    __syncthreads();
+    block_sum_max(q, m);
     if (threadIdx.x != 0) return;
-    unsigned long long Q = 0, M = 0;
-    for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
-        Q += red[0][w];
-        M = red[1][w] > M ? red[1][w] : M;
-    }
     // the alternative: the enumeration's lookups when it can take this batch
     // (one sector, an occupation whose round fits on chip), else streaming
     // every group past every sample (cheaper per pair)
@@ -286,135 +339,14 @@ __global__ __launch_bounds__(1024) void join_decide_kernel(DevTable tab, DevScra
     sc.jctl[kJoinCtlProbes] = probes;
     const double alt = enum_usable ? static_cast<double>(probes)
                                    : 0.5 * static_cast<double>(n) * static_cast<double>(g_eff);
-    // the join's own fixed work: counting, scanning, scattering and sorting
-    // the entries and buckets
-    const double buckets = static_cast<double>(static_cast<int64_t>(tab.join_blocks)
-                                               << sc.join_log2m);
+    // the join's own fixed work: keys, placing and sorting the entries
     const double entries = static_cast<double>(tab.join_blocks) * static_cast<double>(n);
-    const double cost = static_cast<double>(Q) + 4.0 * entries + 0.5 * buckets;
-    const bool fits = M <= static_cast<unsigned long long>(kJoinMaxBucket);
+    const double cost = static_cast<double>(q) + 4.0 * entries;
+    const bool fits = sc.jctl[kJoinCtlOver] == 0ull;
     const bool chosen = fits && (sc.join_force != 0 || cost < alt);
-    sc.jctl[kJoinCtlCost] = Q;
-    sc.jctl[kJoinCtlMax] = M;
-    sc.jctl[kJoinCtlEntries] = carry;
+    sc.jctl[kJoinCtlCost] = q;
+    sc.jctl[kJoinCtlMax] = m;
     sc.jctl[kJoinCtlChosen] = chosen ? 1ull : 0ull;
-}
-
-// Bucket start offsets: each scan block rescans its counts from the block's
-// exclusive offset.
-__global__ __launch_bounds__(kJoinScanThreads) void join_offsets_kernel(DevScratch sc,
-                                                                        int64_t buckets) {
-    if (!join_chosen(sc)) return;
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * kJoinScanItems + 4 * threadIdx.x;
-    uint32_t v[4];
-    unsigned long long own = 0;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        v[t] = base + t < buckets ? sc.jcnt[base + t] : 0u;
-        own += v[t] >= 2 ? v[t] : 0u;
-    }
-    unsigned long long total;
-    unsigned long long off = sc.jscan[blockIdx.x] + block_exclusive_scan(own, &total);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        if (base + t < buckets) {
-            sc.jcnt[base + t] = static_cast<uint32_t>(off);
-            sc.jsize[base + t] = v[t];
-        }
-        off += v[t] >= 2 ? v[t] : 0u;
-    }
-}
-
-// Entries into their buckets (any order; sorted next).  Afterwards jcnt[k]
-// holds the end of bucket k, whose start is that less jsize[k].  A sample
-// alone in its bucket has no partner in that block: its partial is zero,
-// written here, and it takes no entry.
-__global__ __launch_bounds__(kJoinThreads) void join_scatter_kernel(DevTable tab, DevScratch sc,
-                                                                    int64_t n) {
-    if (!join_chosen(sc)) return;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int b = 0; b < tab.join_blocks; ++b) {
-        const uint32_t k = sc.jkey[static_cast<int64_t>(b) * n + i];
-        if (sc.jsize[k] < 2u) {
-            double *out = sc.part + 2 * (static_cast<int64_t>(b) * n + i);
-            out[0] = 0.0;
-            out[1] = 0.0;
-            continue;
-        }
-        const uint32_t pos = atomicAdd(&sc.jcnt[k], 1u);
-        sc.jent[pos] = static_cast<uint32_t>(i);
-    }
-}
-
-// One thread per bucket: a bucket of up to kJoinSmallSort entries is sorted
-// in registers and written out with its keys and range; a larger one goes to
-// the block sorter's list.
-__global__ __launch_bounds__(kJoinThreads) void join_sort_small_kernel(
-    DevScratch sc, const uint64_t *__restrict__ samples, int64_t buckets) {
-    if (!join_chosen(sc)) return;
-    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= buckets) return;
-    const uint32_t m = sc.jsize[k];
-    if (m < 2) return;  // no entry
-    const uint32_t e = sc.jcnt[k], s = e - m;
-    const uint32_t blk = static_cast<uint32_t>(k >> sc.join_log2m);
-    if (m == 2) {
-        const uint32_t a = sc.jent[s], b = sc.jent[s + 1];
-        join_put(sc, samples, s, a < b ? a : b, s, e, blk);
-        join_put(sc, samples, s + 1, a < b ? b : a, s, e, blk);
-    } else if (m <= 4) {
-        join_sort_put<4>(sc, samples, s, m, blk);
-    } else if (m <= 8) {
-        join_sort_put<8>(sc, samples, s, m, blk);
-    } else if (m <= 16) {
-        join_sort_put<16>(sc, samples, s, m, blk);
-    } else if (m <= static_cast<uint32_t>(kJoinSmallSort)) {
-        join_sort_put<32>(sc, samples, s, m, blk);
-    } else {
-        const unsigned long long t = atomicAdd(&sc.jctl[kJoinCtlBig], 1ull);
-        sc.jbig[t] = static_cast<uint32_t>(k);
-    }
-}
-
-// The listed buckets (more than kJoinSmallSort entries, at most
-// kJoinMaxBucket: the decision guarantees it), one block each at a time:
-// bitonic sort in LDS, then written out.
-__global__ __launch_bounds__(kJoinSortThreads) void join_sort_big_kernel(
-    DevScratch sc, const uint64_t *__restrict__ samples) {
-    if (!join_chosen(sc)) return;
-    __shared__ uint32_t buf[kJoinMaxBucket];
-    const unsigned long long nbig = sc.jctl[kJoinCtlBig];
-    for (unsigned long long t = blockIdx.x; t < nbig; t += gridDim.x) {
-        const uint32_t k = sc.jbig[t];
-        const uint32_t m = sc.jsize[k];
-        const uint32_t e = sc.jcnt[k], s = e - m;
-        const uint32_t blk = k >> sc.join_log2m;
-        uint32_t P = 64;
-        while (P < m) P <<= 1;
-        for (uint32_t u = threadIdx.x; u < P; u += blockDim.x)
-            buf[u] = u < m ? sc.jent[s + u] : 0xFFFFFFFFu;
-        __syncthreads();
-        for (uint32_t kk = 2; kk <= P; kk <<= 1) {
-            for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-                for (uint32_t u = threadIdx.x; u < P; u += blockDim.x) {
-                    const uint32_t l = u ^ j;
-                    if (l > u) {
-                        const uint32_t a = buf[u], b = buf[l];
-                        const bool sw = ((u & kk) == 0) ? (a > b) : (a < b);
-                        if (sw) {
-                            buf[u] = b;
-                            buf[l] = a;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        for (uint32_t u = threadIdx.x; u < m; u += blockDim.x)
-            join_put(sc, samples, s + u, buf[u], s, e, blk);
-        __syncthreads();
-    }
 }
 
 // The contribution of partner j (bit string y = x ^ d) to E_loc(x), or no
@@ -461,91 +393,82 @@ __device__ __forceinline__ bool join_hit(const DevTable &tab, const Key<W> &x, c
     return true;
 }
 
-// One lane per entry (block b, sample i): the partners of i in its bucket of
-// block b, in index order; its partial sum goes to part[b][i].
+// One lane per entry (block b, sample i): the partners of i in its bucket,
+// in index order; its partial sum goes to part[b][i] (zero for a sample
+// alone in its bucket).
 template <int W, bool DUMP, int P, bool SCV>
-__global__ __launch_bounds__(kJoinThreads) void join_pair_kernel(
-    DevTable tab, DevScratch sc, const double *__restrict__ log_amp,
-    const double *__restrict__ phase, int64_t n, int32_t *__restrict__ hit_idx,
-    uint32_t *__restrict__ sign_bits, int64_t sign_words) {
+__global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
+    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
+    const double *__restrict__ log_amp, const double *__restrict__ phase, int64_t n,
+    int32_t *__restrict__ hit_idx, uint32_t *__restrict__ sign_bits, int64_t sign_words) {
     if (!join_chosen(sc)) return;
-    // the entries of buckets of two samples or more
-    const int64_t total = static_cast<int64_t>(sc.jctl[kJoinCtlEntries]);
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const unsigned long long *__restrict__ ent = sc.jent;
+    const int maxf = tab.max_flip;
     unsigned long long n_cand = 0, n_probe = 0, n_hit = 0, n_term = 0;
-    if (p < total) {
-        const int b = sc.jblk[p];
-        const int64_t i = sc.jent[p];
-        const uint4 xk = reinterpret_cast<const uint4 *>(sc.jkeys)[p];
-        Key<W> x;
-        x.w[0] = (static_cast<uint64_t>(xk.y) << 32) | xk.x;
-        if constexpr (W == 2) x.w[W - 1] = (static_cast<uint64_t>(xk.w) << 32) | xk.z;
-        const uint2 r = sc.jrange[p];
-        double re = 0.0, im = 0.0, la = 0.0, ph = 0.0;
-        bool have_psi = false;
-        AccF32 ar, ai;
-        const int maxf = tab.max_flip;
-        const uint4 *keys = reinterpret_cast<const uint4 *>(sc.jkeys);
-        auto visit = [&](uint32_t q, uint4 yk) {
-            Key<W> d;
-            d.w[0] = x.w[0] ^ ((static_cast<uint64_t>(yk.y) << 32) | yk.x);
-            int pop = __popcll(d.w[0]);
-            if constexpr (W == 2) {
-                d.w[W - 1] = x.w[W - 1] ^ ((static_cast<uint64_t>(yk.w) << 32) | yk.z);
-                pop += __popcll(d.w[W - 1]);
-            }
-            if (pop > maxf || q == static_cast<uint32_t>(p)) return;
-            // the first block on which x and y agree must be this one
-            int first = tab.join_blocks;
-#pragma unroll
-            for (int c = kJoinMaxBlocks - 1; c >= 0; --c) {
-                if (c < tab.join_blocks) {
-                    uint64_t v = d.w[0] & tab.jmask[c][0];
-                    if constexpr (W == 2) v |= d.w[W - 1] & tab.jmask[c][1];
-                    if (v == 0ull) first = c;
-                }
-            }
-            if (first != b) return;
-            if (pop == 0) {
-                latch(sc.err, NQS_E_DUPLICATE);
-                return;
-            }
-            ++n_probe;
-            if (!have_psi) {
-                la = log_amp[i];
-                ph = phase[i];
-                have_psi = true;
-            }
-            Key<W> y;
-#pragma unroll
-            for (int w = 0; w < W; ++w) y.w[w] = x.w[w] ^ d.w[w];
-            const int32_t j = static_cast<int32_t>(sc.jent[q]);
-            if (join_hit<W, DUMP, P, SCV>(tab, x, y, d, i, j, la, ph, log_amp, phase, hit_idx,
-                                          sign_bits, sign_words, &n_term, re, im, ar, ai))
-                ++n_hit;
-        };
-        uint32_t q = r.x;
-        // four partner keys in flight per step
-        for (; q + 4 <= r.y; q += 4) {
-            const uint4 k0 = keys[q], k1 = keys[q + 1], k2 = keys[q + 2], k3 = keys[q + 3];
-            visit(q, k0);
-            visit(q + 1, k1);
-            visit(q + 2, k2);
-            visit(q + 3, k3);
-        }
-        for (; q < r.y; ++q) visit(q, keys[q]);
-        n_cand = r.y - r.x - 1;
+    if (p < static_cast<int64_t>(tab.join_blocks) * n) {
+        const int64_t i = static_cast<uint32_t>(ent[p]);
+        const unsigned long long r = sc.jrange[p];
+        const uint32_t bs = static_cast<uint32_t>(r), m = static_cast<uint32_t>(r >> 32) & 0xFFFFu;
+        const int b = static_cast<int>(r >> 48);
         double *out = sc.part + 2 * (static_cast<int64_t>(b) * n + i);
-        if constexpr (P == NQS_FP64) {
-            out[0] = re;
-            out[1] = im;
+        if (m < 2) {
+            out[0] = 0.0;
+            out[1] = 0.0;
         } else {
-            out[0] = ar.value();
-            out[1] = ai.value();
+            const Key<W> x = load_key<W>(sc.jkeys, p);
+            double re = 0.0, im = 0.0, la = 0.0, ph = 0.0;
+            bool have_psi = false;
+            AccF32 ar, ai;
+            for (uint32_t q = bs; q < bs + m; ++q) {
+                if (q == static_cast<uint32_t>(p)) continue;
+                const Key<W> y = load_key<W>(sc.jkeys, q);
+                Key<W> d;
+                int pop = 0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    d.w[w] = x.w[w] ^ y.w[w];
+                    pop += __popcll(d.w[w]);
+                }
+                if (pop > maxf) continue;
+                // the first block on which x and y agree must be this one
+                int first = tab.join_blocks;
+#pragma unroll
+                for (int cb = kJoinMaxBlocks - 1; cb >= 0; --cb) {
+                    if (cb < tab.join_blocks) {
+                        uint64_t v = d.w[0] & tab.jmask[cb][0];
+                        if constexpr (W == 2) v |= d.w[W - 1] & tab.jmask[cb][1];
+                        if (v == 0ull) first = cb;
+                    }
+                }
+                if (first != b) continue;
+                if (pop == 0) {
+                    latch(sc.err, NQS_E_DUPLICATE);
+                    continue;
+                }
+                const int32_t j = static_cast<int32_t>(static_cast<uint32_t>(ent[q]));
+                ++n_probe;
+                if (!have_psi) {
+                    la = log_amp[i];
+                    ph = phase[i];
+                    have_psi = true;
+                }
+                if (join_hit<W, DUMP, P, SCV>(tab, x, y, d, i, j, la, ph, log_amp, phase, hit_idx,
+                                              sign_bits, sign_words, &n_term, re, im, ar, ai))
+                    ++n_hit;
+            }
+            n_cand = m - 1;
+            if constexpr (P == NQS_FP64) {
+                out[0] = re;
+                out[1] = im;
+            } else {
+                out[0] = ar.value();
+                out[1] = ai.value();
+            }
         }
     }
     // one set of counter atomics per block
-    __shared__ unsigned long long cnt[4][kJoinThreads / 64];
+    __shared__ unsigned long long cnt[4][kJoinPairThreads / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     n_cand = wave_sum(n_cand);
     n_probe = wave_sum(n_probe);
@@ -560,46 +483,55 @@ __global__ __launch_bounds__(kJoinThreads) void join_pair_kernel(
     __syncthreads();
     if (threadIdx.x < 4) {
         unsigned long long v = 0;
-        for (int w = 0; w < kJoinThreads / 64; ++w) v += cnt[threadIdx.x][w];
+        for (int w = 0; w < kJoinPairThreads / 64; ++w) v += cnt[threadIdx.x][w];
         const int slot[4] = {4, 1, 2, 3};
-        count_add(sc.counters, slot[threadIdx.x], v);
+        if (v) count_add(sc.counters, slot[threadIdx.x], v);
     }
 }
 
 template <int W>
 hipError_t launch_join_prep_w(const DevTable &tab, const DevScratch &sc,
                               const uint64_t *samples, int64_t n, int64_t g_eff, hipStream_t st) {
-    const int64_t buckets = static_cast<int64_t>(tab.join_blocks) << sc.join_log2m;
-    const int64_t nscan = (buckets + kJoinScanItems - 1) / kJoinScanItems;
-    const dim3 sgrid(static_cast<unsigned>((n + kJoinThreads - 1) / kJoinThreads));
-    hipLaunchKernelGGL(join_count_kernel<W>, sgrid, dim3(kJoinThreads), 0, st, tab, sc, samples, n);
-    hipLaunchKernelGGL(join_scan_sums_kernel, dim3(static_cast<unsigned>(nscan)),
-                       dim3(kJoinScanThreads), 0, st, sc, buckets);
-    hipLaunchKernelGGL(join_decide_kernel, dim3(1), dim3(1024), 0, st, tab, sc, samples, n, nscan,
-                       g_eff);
-    hipLaunchKernelGGL(join_offsets_kernel, dim3(static_cast<unsigned>(nscan)),
-                       dim3(kJoinScanThreads), 0, st, sc, buckets);
-    hipLaunchKernelGGL(join_scatter_kernel, sgrid, dim3(kJoinThreads), 0, st, tab, sc, n);
-    hipLaunchKernelGGL(join_sort_small_kernel,
-                       dim3(static_cast<unsigned>((buckets + kJoinThreads - 1) / kJoinThreads)),
-                       dim3(kJoinThreads), 0, st, sc, samples, buckets);
-    // the listed buckets number at most entries / (kJoinSmallSort + 1)
-    const int64_t max_big = static_cast<int64_t>(tab.join_blocks) * n / (kJoinSmallSort + 1);
-    const int64_t big_grid = max_big < 1 ? 1 : (max_big < 2048 ? max_big : 2048);
-    hipLaunchKernelGGL(join_sort_big_kernel, dim3(static_cast<unsigned>(big_grid)),
+    const dim3 tiles(static_cast<unsigned>(sc.join_tiles));
+    const dim3 blk(kJoinGroupThreads);
+    hipLaunchKernelGGL(join_hist_kernel<W>, tiles, blk, 0, st, tab, sc, samples, n);
+    hipLaunchKernelGGL(join_place_kernel, tiles, blk, 0, st, tab, sc, n);
+    hipLaunchKernelGGL(join_sort_kernel, dim3(static_cast<unsigned>(sc.join_parts)),
                        dim3(kJoinSortThreads), 0, st, sc, samples);
+    hipLaunchKernelGGL(join_decide_kernel, dim3(1), blk, 0, st, tab, sc, samples, n, g_eff);
     return hipGetLastError();
 }
 
 template <int W, bool D, int P, bool SCV>
-hipError_t launch_pairs_w(const DevTable &tab, const DevScratch &sc, const double *log_amp,
-                          const double *phase, int64_t n, int32_t *hit_idx, uint32_t *sign_bits,
-                          int64_t sign_words, hipStream_t st) {
-    const int64_t total = static_cast<int64_t>(tab.join_blocks) * n;
-    const dim3 grid(static_cast<unsigned>((total + kJoinThreads - 1) / kJoinThreads));
-    hipLaunchKernelGGL((join_pair_kernel<W, D, P, SCV>), grid, dim3(kJoinThreads), 0, st, tab, sc,
-                       log_amp, phase, n, hit_idx, sign_bits, sign_words);
+hipError_t launch_pairs_w(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
+                          const double *log_amp, const double *phase, int64_t n,
+                          int32_t *hit_idx, uint32_t *sign_bits, int64_t sign_words,
+                          hipStream_t st) {
+    const int64_t entries = static_cast<int64_t>(tab.join_blocks) * n;
+    const dim3 grid(static_cast<unsigned>((entries + kJoinPairThreads - 1) / kJoinPairThreads));
+    hipLaunchKernelGGL((join_pair_kernel<W, D, P, SCV>), grid, dim3(kJoinPairThreads), 0, st, tab,
+                       sc, samples, log_amp, phase, n, hit_idx, sign_bits, sign_words);
     return hipGetLastError();
+}
+
+// Partitions and tiles of a launch of n samples with 2^log2m buckets per
+// block: a partition covers 2^lshift buckets (1024, fewer for a small batch,
+// 2048 at the largest), about as many entries; the grouping kernels take at
+// most kJoinTiles tiles of a multiple of 1024 samples.
+struct JoinGeometry {
+    int lshift, parts, tile, tiles;
+};
+
+JoinGeometry join_geometry(const DevTable &tab, int64_t n, int log2m) {
+    JoinGeometry g;
+    g.lshift = log2m <= 10 ? log2m : (log2m <= 20 ? 10 : log2m - 10);
+    g.parts = tab.join_blocks << (log2m - g.lshift);
+    const int64_t per = (n + int64_t(kJoinTiles) * kJoinGroupThreads - 1) /
+                        (int64_t(kJoinTiles) * kJoinGroupThreads);
+    g.tile = static_cast<int>((per < 1 ? 1 : per) * kJoinGroupThreads);
+    g.tiles = static_cast<int>((n + g.tile - 1) / g.tile);
+    if (g.tiles < 1) g.tiles = 1;
+    return g;
 }
 
 }  // namespace
@@ -615,19 +547,18 @@ namespace {
 // Byte sizes of the join's pieces, in layout order.
 constexpr int kJoinPieces = 9;
 void join_sizes(const DevTable &tab, int64_t n, int log2m, size_t sizes[kJoinPieces]) {
-    const size_t B = static_cast<size_t>(tab.join_blocks);
-    const size_t buckets = B << log2m;
-    const size_t entries = B * static_cast<size_t>(n);
-    const size_t nscan = (buckets + kJoinScanItems - 1) / kJoinScanItems;
-    sizes[0] = 4 * buckets;                    // jcnt
-    sizes[1] = 4 * entries;                    // jkey, then the block sorter's list
-    sizes[2] = 4 * entries;                    // jent
-    sizes[3] = 8 * entries;                    // jrange
-    sizes[4] = 16 * entries;                   // jkeys
-    sizes[5] = 8 * 3 * nscan;                  // jscan
-    sizes[6] = 8 * static_cast<size_t>(kJoinCtl);  // jctl
-    sizes[7] = 4 * buckets;                    // jsize
-    sizes[8] = entries;                        // jblk
+    const JoinGeometry g = join_geometry(tab, n, log2m);
+    const size_t entries = static_cast<size_t>(tab.join_blocks) * static_cast<size_t>(n);
+    const size_t parts = static_cast<size_t>(g.parts);
+    sizes[0] = 4 * parts;                                 // jcnt
+    sizes[1] = 4 * entries;                               // jkey
+    sizes[2] = 4 * parts * static_cast<size_t>(g.tiles);  // jtbase
+    sizes[3] = 4 * (parts + 1);                           // jpoff
+    sizes[4] = 8 * entries;                               // jent
+    sizes[5] = 8 * entries;                               // jrange
+    sizes[6] = 16 * parts;                                // jstat
+    sizes[7] = 8 * static_cast<size_t>(kJoinCtl);         // jctl
+    sizes[8] = 16 * entries;                              // jkeys
 }
 
 }  // namespace
@@ -650,17 +581,21 @@ void join_scratch_layout(const DevTable &tab, int64_t n, int log2m, char *base, 
         off[k] = total;
         total = align256(total + sizes[k]);
     }
+    const JoinGeometry g = join_geometry(tab, n, log2m);
     sc->jcnt = reinterpret_cast<uint32_t *>(base + off[0]);
     sc->jkey = reinterpret_cast<uint32_t *>(base + off[1]);
-    sc->jbig = sc->jkey;  // the bucket keys are dead once the entries are scattered
-    sc->jent = reinterpret_cast<uint32_t *>(base + off[2]);
-    sc->jrange = reinterpret_cast<uint2 *>(base + off[3]);
-    sc->jkeys = reinterpret_cast<uint64_t *>(base + off[4]);
-    sc->jscan = reinterpret_cast<unsigned long long *>(base + off[5]);
-    sc->jctl = reinterpret_cast<unsigned long long *>(base + off[6]);
-    sc->jsize = reinterpret_cast<uint32_t *>(base + off[7]);
-    sc->jblk = reinterpret_cast<uint8_t *>(base + off[8]);
+    sc->jtbase = reinterpret_cast<uint32_t *>(base + off[2]);
+    sc->jpoff = reinterpret_cast<uint32_t *>(base + off[3]);
+    sc->jent = reinterpret_cast<unsigned long long *>(base + off[4]);
+    sc->jrange = reinterpret_cast<unsigned long long *>(base + off[5]);
+    sc->jstat = reinterpret_cast<unsigned long long *>(base + off[6]);
+    sc->jctl = reinterpret_cast<unsigned long long *>(base + off[7]);
+    sc->jkeys = reinterpret_cast<uint64_t *>(base + off[8]);
     sc->join_log2m = log2m;
+    sc->join_lshift = g.lshift;
+    sc->join_parts = g.parts;
+    sc->join_tile = g.tile;
+    sc->join_tiles = g.tiles;
 }
 
 hipError_t launch_join_prep(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
@@ -673,12 +608,12 @@ hipError_t launch_join_pairs(const DevTable &tab, const DevScratch &sc, const ui
                              const double *log_amp, const double *phase, int64_t n, int precision,
                              int32_t *hit_idx, uint32_t *sign_bits, int64_t sign_words,
                              hipStream_t st) {
-    (void)samples;
     const bool dump = hit_idx || sign_bits;
     const bool f32 = precision == NQS_FP32_KAHAN && !dump && !tab.sc;
     const bool w1 = tab.n_qubits <= 63;
 #define NQS_PAIRS(Wd, D, Pr, SCI) \
-    return launch_pairs_w<Wd, D, Pr, SCI>(tab, sc, log_amp, phase, n, hit_idx, sign_bits, sign_words, st)
+    return launch_pairs_w<Wd, D, Pr, SCI>(tab, sc, samples, log_amp, phase, n, hit_idx, sign_bits, \
+                                          sign_words, st)
     if (tab.sc) {
         if (w1) {
             if (dump) NQS_PAIRS(1, true, NQS_FP64, true);

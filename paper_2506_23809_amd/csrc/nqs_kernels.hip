@@ -44,14 +44,14 @@ __global__ void hash_clear_kernel(uint64_t *__restrict__ skey, int32_t *__restri
                                   uint32_t filter_words, uint32_t *__restrict__ efilter,
                                   uint32_t efilter_words, unsigned long long *__restrict__ counters,
                                   int *__restrict__ mixed, uint32_t *__restrict__ jcnt,
-                                  uint32_t jbuckets, unsigned long long *__restrict__ jctl) {
+                                  uint32_t jparts, unsigned long long *__restrict__ jctl) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     // the batch's counters and sector flag start at zero as well, and so do
-    // the pair join's bucket counts and control words
+    // the pair join's partition counts and control words
     if (s < static_cast<uint32_t>(kCounters * kCounterSlots)) counters[s] = 0;
     if (s == 0) *mixed = 0;
     if (jctl && s < static_cast<uint32_t>(kJoinCtl)) jctl[s] = 0;
-    if (s < jbuckets) jcnt[s] = 0u;
+    if (s < jparts) jcnt[s] = 0u;
     if (s < capacity) {
         sidx[s] = -1;
         sfp[s] = 0u;
@@ -1684,50 +1684,131 @@ __device__ __forceinline__ double diag_occ_sum(const double *d, int nq, const Ke
     }
 }
 
-// Bits [16 c, 16 c + 16) of x.
-template <int W>
-__device__ __forceinline__ uint32_t chunk16(const Key<W> &x, int c) {
-    const int w = c >> 2;
-    uint64_t v = x.w[0];
-    if constexpr (W == 2) v = w ? x.w[W - 1] : v;
-    return w < W ? static_cast<uint32_t>(v >> (16 * (c & 3))) & 0xFFFFu : 0u;
+typedef int diag_v4i __attribute__((ext_vector_type(4)));
+
+// Bits b of a 16-bit value as 16 bytes of 0 or 1 (byte b = bit b): each
+// nibble times 0x00204081 puts its bits 7 apart, one in each byte's bit 0.
+__device__ __forceinline__ diag_v4i spread_bits16(uint32_t v) {
+    diag_v4i r;
+    r[0] = static_cast<int>(((v & 0xFu) * 0x00204081u) & 0x01010101u);
+    r[1] = static_cast<int>((((v >> 4) & 0xFu) * 0x00204081u) & 0x01010101u);
+    r[2] = static_cast<int>((((v >> 8) & 0xFu) * 0x00204081u) & 0x01010101u);
+    r[3] = static_cast<int>((((v >> 12) & 0xFu) * 0x00204081u) & 0x01010101u);
+    return r;
 }
 
-// The FP64 occupation-form sum without gathers: with n_i in {0, 1} as a
-// double, t_j = d_j + sum_{i < j} n_i d_ij and the result d0 + sum_j n_j t_j
-// are formed tile by tile (16 j, 16 i) with FMAs whose d_ij are the same for
-// every lane (scalar loads of the padded triangle U, zero where i >= j).  An
-// unoccupied term adds an exact zero, and the occupied ones are added in the
-// order of the sparse sum above (i ascending from d_j, then j ascending), so
-// the result has the same bits; the work is nq^2 / 2 FMAs in place of
-// n_occ^2 / 2 gathers, all issue-bound.
-template <int W>
-__device__ __forceinline__ double diag_occ_dense(const DevTable &tab, const Key<W> &x) {
-    const double *__restrict__ U = tab.diag_u;
-    const double *__restrict__ d1 = tab.diag_d1;
-    double acc = tab.diag[0];
-    const int jtiles = (tab.n_qubits + 15) >> 4;
-    for (int jt = 0; jt < jtiles; ++jt) {
-        double t[16];
+// The occupation-form diagonal of the 64 samples of a wave (each lane's x;
+// zero for a lane without a sample) on the matrix cores, called by every
+// lane of the wave together.  With n the 0/1 occupations and Q the
+// fixed-point terms (see kDiagLimbs), the value is
+//   d0 + 2^-S sum_j n_j sum_{i <= j} n_i Q[j][i].
+// Per digit l, column tile jt and group of 16 samples: C = D_l N (16 x 16
+// x 64 int8 products; D_l the digit tile, rows j, k = i; N the samples'
+// bits, k = i, one column per sample), so C[j][s] = sum_i D_l[j][i] n_s[i];
+// each lane masks its four C[j][s] by n_s[j] and adds them to its digit
+// sum.  All of it is exact integer arithmetic (|C| <= 2^14, a digit sum
+// below 2^21), the digits are recombined in 64-bit integers and the total
+// is rounded once to FP64, so the result does not depend on any order of
+// summation.  B holds the digit tiles (LDS or global memory).
+//
+// Lane layout of the instruction: lane L holds row L % 16 of A and column
+// L % 16 of B, with k in [16 (L / 16), +16) of the 64-wide k-block (byte
+// b = k); C row 4 (L / 16) + r, column L % 16 in its r-th value.  The digit
+// tiles are stored in that A layout.
+// One column tile jt of diag_occ_mfma for H groups of 16 samples: the
+// digit tiles at B + t (KB k-blocks), the samples' bit operands N, their
+// words m0/m1 for the row masks, the digit sums T.
+template <int H, int KB>
+__device__ __forceinline__ void diag_mfma_tile(const diag_v4i *__restrict__ B, int t, int jt,
+                                               int lane, int g, const diag_v4i (&N)[H][2],
+                                               const uint64_t (&m0)[H], const uint64_t (&m1)[H],
+                                               int (&T)[H][kDiagLimbs]) {
+    const diag_v4i zero = {0, 0, 0, 0};
+    // n_s[j] for the lane's rows j = 16 jt + 4 g + r, r = 0..3, as 0/1
+    // multipliers (hidden from the optimiser, so that each masked add stays
+    // a 24-bit multiply and an add)
+    const int j0 = 16 * jt + 4 * g;
+    int bit[H][4];
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) t[jj] = d1[16 * jt + jj];
-        for (int it = 0; it <= jt; ++it) {
-            const uint32_t bi = chunk16<W>(x, it);
-            double f[16];
+    for (int h = 0; h < H; ++h) {
+        const uint32_t nib =
+            static_cast<uint32_t>(((j0 < 64 ? m0[h] : m1[h]) >> (j0 & 63)) & 0xFull);
 #pragma unroll
-            for (int ii = 0; ii < 16; ++ii) f[ii] = static_cast<double>((bi >> ii) & 1u);
-            const double *Ut = U + static_cast<size_t>(16 * jt) * kDiagPad + 16 * it;
-#pragma unroll
-            for (int jj = 0; jj < 16; ++jj) {
-#pragma unroll
-                for (int ii = 0; ii < 16; ++ii) t[jj] = fma(f[ii], Ut[jj * kDiagPad + ii], t[jj]);
-            }
+        for (int r = 0; r < 4; ++r) {
+            bit[h][r] = static_cast<int>((nib >> r) & 1u);
+            asm("" : "+v"(bit[h][r]));
         }
-        const uint32_t bj = chunk16<W>(x, jt);
-#pragma unroll
-        for (int jj = 0; jj < 16; ++jj) acc = fma(static_cast<double>((bj >> jj) & 1u), t[jj], acc);
     }
-    return acc;
+#pragma unroll
+    for (int l = 0; l < kDiagLimbs; ++l) {
+        diag_v4i a[KB];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) a[kb] = B[((t + kb) * kDiagLimbs + l) * 64 + lane];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            diag_v4i acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0], N[h][0], zero, 0, 0, 0);
+            if constexpr (KB == 2)
+                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[1], N[h][1], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) T[h][l] = __mul24(acc[r], bit[h][r]) + T[h][l];
+        }
+    }
+}
+
+template <int W>
+__device__ __forceinline__ double diag_occ_mfma(const DevTable &tab, const Key<W> &x,
+                                                const diag_v4i *__restrict__ B) {
+    // groups of 16 samples per pass over the digit tiles (two passes: the
+    // registers of four groups at once would spill)
+    constexpr int H = 2;
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+    const uint64_t w0 = x.w[0], w1 = W == 2 ? x.w[W - 1] : 0ull;
+    const int jtiles = tab.diag_jtiles;
+    double mine = 0.0;
+    for (int pass = 0; pass < 4 / H; ++pass) {
+        // the column samples 16 (H pass + h) + c: their bits as the B
+        // operands of both k-blocks, and their words for the masks
+        diag_v4i N[H][2];
+        uint64_t m0[H], m1[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const int src = 16 * (H * pass + h) + c;
+            m0[h] = __shfl(w0, src);
+            m1[h] = __shfl(w1, src);
+            N[h][0] = spread_bits16(static_cast<uint32_t>(m0[h] >> (16 * g)) & 0xFFFFu);
+            N[h][1] = spread_bits16(static_cast<uint32_t>(m1[h] >> (16 * g)) & 0xFFFFu);
+        }
+        int T[H][kDiagLimbs];
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int l = 0; l < kDiagLimbs; ++l) T[h][l] = 0;
+        // column tiles 0..3 reach rows i < 64 (one k-block), later ones two
+        const int j1 = jtiles < 4 ? jtiles : 4;
+        for (int jt = 0; jt < j1; ++jt) diag_mfma_tile<H, 1>(B, jt, jt, lane, g, N, m0, m1, T);
+        for (int jt = 4; jt < jtiles; ++jt)
+            diag_mfma_tile<H, 2>(B, 4 + 2 * (jt - 4), jt, lane, g, N, m0, m1, T);
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            // digits 0..3 and 4..7 recombined (each below 2^46 in magnitude),
+            // then summed over the four row groups of the lane's column
+            long long lo = 0, hi = 0;
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                lo += static_cast<long long>(T[h][l]) << (8 * l);
+                hi += static_cast<long long>(T[h][l + 4]) << (8 * l);
+            }
+            lo += __shfl_xor(lo, 16);
+            hi += __shfl_xor(hi, 16);
+            lo += __shfl_xor(lo, 32);
+            hi += __shfl_xor(hi, 32);
+            // both terms exact in FP64, one rounding of the exact total; the
+            // lane of sample 16 (H pass + h) + c (row group H pass + h) keeps it
+            const double v = static_cast<double>(lo) + static_cast<double>(hi) * 4294967296.0;
+            if (g == H * pass + h) mine = v;
+        }
+    }
+    return tab.diag[0] + mine * tab.diag_scale;
 }
 
 // The same sum from a staged occupation form, with the occupied qubits first
@@ -1806,7 +1887,8 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
                                            int64_t i, const uint64_t *dz = nullptr,
                                            const double *dc = nullptr, int nd = 0,
                                            const double *dq = nullptr,
-                                           uint32_t *olist = nullptr) {
+                                           uint32_t *olist = nullptr, bool have_d = false,
+                                           double dval = 0.0) {
     unsigned long long n_terms = 0;
     // the pair join leaves one partial per block, an enumeration one per sample
     if (join_chosen(sc))
@@ -1819,16 +1901,16 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
         if (tab.has_diagonal) {
             if constexpr (SCV) {
                 re = sc_diagonal<W>(tab, x);
+            } else if (have_d) {
+                // the occupation form on the matrix cores (computed by the
+                // caller for the whole wave)
+                re = dval;
             } else if (dq) {
                 // occupation form (the caller passes it staged or in place);
                 // counted as the X = 0 group's terms it stands for
-                if constexpr (P == NQS_FP64)
-                    re = diag_occ_dense<W>(tab, x);
-                else
-                    re = olist ? diag_occ_sum_list<W, P>(dq, tab.n_qubits, x,
-                                                         olist + threadIdx.x,
-                                                         static_cast<int>(blockDim.x))
-                               : diag_occ_sum<W, P>(dq, tab.n_qubits, x);
+                re = olist ? diag_occ_sum_list<W, P>(dq, tab.n_qubits, x, olist + threadIdx.x,
+                                                     static_cast<int>(blockDim.x))
+                           : diag_occ_sum<W, P>(dq, tab.n_qubits, x);
                 n_terms += static_cast<unsigned long long>(tab.goff[1] - tab.goff[0]);
             } else if (dz) {
                 // the X = 0 group staged in LDS by the caller (same order, same sums)
@@ -1931,15 +2013,6 @@ __global__ __launch_bounds__(256) void eloc_finish_kernel(
         // staging area (dynamic LDS of stage_cap doubles, at least
         // 3 kDiagLds): the diagonal's Z masks and coefficients, or its
         // occupation form
-        if constexpr (P == NQS_FP64) {
-            // the dense sum reads the padded triangle in place (scalar loads)
-            if (tab.diag_occ) {
-                finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc,
-                                            hit_idx, sign_bits, sign_words, i, nullptr, nullptr,
-                                            0, tab.diag);
-                return;
-            }
-        }
         double *stage = reinterpret_cast<double *>(dyn_lds());
         const double *dq = stage_diag_occ<P>(tab, stage, stage_cap);
         if (dq) {
@@ -1964,6 +2037,31 @@ __global__ __launch_bounds__(256) void eloc_finish_kernel(
     }
     finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc, hit_idx,
                                 sign_bits, sign_words, i);
+}
+
+// The finish kernel of tables with the occupation-form diagonal (no debug
+// dump, Pauli form): the digit tiles staged in LDS once per block, the
+// diagonal of each wave's 64 samples on the matrix cores, then the partials.
+constexpr int kFinishMfmaThreads = 1024;
+constexpr int kDiagMaxTiles = diag_mfma_tiles(8);
+
+template <int W, int P>
+__global__ __launch_bounds__(kFinishMfmaThreads) void eloc_finish_mfma_kernel(
+    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n,
+    int64_t n_chunks, int enum_on, double *__restrict__ eloc) {
+    __shared__ diag_v4i tiles[kDiagMaxTiles * kDiagLimbs * 64];
+    const int words = diag_mfma_tiles(tab.diag_jtiles) * kDiagLimbs * 64;
+    const diag_v4i *src = reinterpret_cast<const diag_v4i *>(tab.diag_q8);
+    for (int k = threadIdx.x; k < words; k += blockDim.x) tiles[k] = src[k];
+    __syncthreads();
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    Key<W> x;
+#pragma unroll
+    for (int w = 0; w < W; ++w) x.w[w] = 0ull;
+    if (i < n) x = load_key<W>(samples, i);
+    const double d = diag_occ_mfma<W>(tab, x, tiles);
+    finish_one<W, false, P, false>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc, nullptr,
+                                   nullptr, 0, i, nullptr, nullptr, 0, nullptr, nullptr, true, d);
 }
 
 // ------------------------------------------------------------------ batched form
@@ -2120,7 +2218,27 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(const JobDesc *__rest
                                                  nullptr, nullptr, 0, i);
         return;
     }
-    // the same diagonal evaluation as the single-launch finish kernel
+    // the same diagonal evaluation as the single-launch finish kernels
+    if (J.tab.diag_jtiles > 0) {
+        const diag_v4i *tiles = reinterpret_cast<const diag_v4i *>(J.tab.diag_q8);
+        if ((J.kind & 1) == 0) {
+            Key<1> x;
+            x.w[0] = i < J.n ? J.samples[2 * i] : 0ull;
+            const double d = diag_occ_mfma<1>(J.tab, x, tiles);
+            finish_one<1, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc,
+                                           nullptr, nullptr, 0, i, nullptr, nullptr, 0, nullptr,
+                                           nullptr, true, d);
+        } else {
+            Key<2> x;
+            x.w[0] = i < J.n ? J.samples[2 * i] : 0ull;
+            x.w[1] = i < J.n ? J.samples[2 * i + 1] : 0ull;
+            const double d = diag_occ_mfma<2>(J.tab, x, tiles);
+            finish_one<2, false, P, false>(J.tab, J.sc, J.samples, J.n, chunks, en, J.eloc,
+                                           nullptr, nullptr, 0, i, nullptr, nullptr, 0, nullptr,
+                                           nullptr, true, d);
+        }
+        return;
+    }
     __shared__ double stage[3 * kDiagLds];
     const double *dq = stage_diag_occ<P>(J.tab, stage);
     uint64_t *dz = reinterpret_cast<uint64_t *>(stage);
@@ -2390,12 +2508,12 @@ EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tu
     L.n_chunks = chunks;
     L.chunk_len = g_eff > 0 ? (g_eff + chunks - 1) / chunks : 0;
     // the pair join is launched beside the other strategy and decides on the
-    // device whether it runs (entries must fit 32-bit offsets)
+    // device whether it runs
     L.join = 0;
     L.join_force = 0;
     L.join_log2m = 0;
     if (tab.join_blocks > 0 && (want == kStrategyAuto || want == kStrategyJoin) &&
-        static_cast<int64_t>(tab.join_blocks) * n < (int64_t(1) << 31)) {
+        n <= kJoinMaxSamples) {
         L.join = 1;
         L.join_force = want == kStrategyJoin ? 1 : 0;
         L.join_log2m = join_log2m_for(n);
@@ -2409,16 +2527,15 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
     const int words = tab.n_qubits <= 63 ? 1 : 2;
     const uint32_t fwords = 1u << sc.filter_log2;
     const uint32_t efwords = sc.eparts_log2 > 0 ? (1u << (sc.eparts_log2 + sc.efilter_log2)) : 0u;
-    const uint32_t jbuckets =
-        sc.jctl ? static_cast<uint32_t>(static_cast<int64_t>(tab.join_blocks) << sc.join_log2m) : 0u;
+    const uint32_t jparts = sc.jctl ? static_cast<uint32_t>(sc.join_parts) : 0u;
     uint32_t span = capacity > fwords ? capacity : fwords;
     span = span > efwords ? span : efwords;
-    span = span > jbuckets ? span : jbuckets;
+    span = span > jparts ? span : jparts;
     const uint32_t n_counters = static_cast<uint32_t>(kCounters * kCounterSlots);
     span = span > n_counters ? span : n_counters;
     hipLaunchKernelGGL(hash_clear_kernel, dim3((span + 255) / 256), dim3(256), 0, st, sc.skey,
                        sc.sidx, sc.sfp, words, capacity, sc.filter, fwords, sc.efilter, efwords,
-                       sc.counters, sc.mixed, sc.jcnt, jbuckets, sc.jctl);
+                       sc.counters, sc.mixed, sc.jcnt, jparts, sc.jctl);
     if (sc.jctl) {
         // the pair join's grouping and decision come before the build, which
         // skips its insertion when the join runs
@@ -2588,9 +2705,29 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
     // and, after it, each thread's list of occupied qubits (bytes, 4 a word)
     const int list_words = tab.diag_occ ? (tab.n_qubits + 3) / 4 : 0;
     const size_t stage_bytes =
-        (dump || tab.sc || (!f32 && tab.diag_occ))
-            ? 0
-            : sizeof(double) * stage_cap + (f32 ? size_t(256) * 4 * list_words : 0);
+        (dump || tab.sc) ? 0
+                         : sizeof(double) * stage_cap + (f32 ? size_t(256) * 4 * list_words : 0);
+    if (!dump && !tab.sc && tab.diag_jtiles > 0) {
+        // the occupation-form diagonal on the matrix cores
+        const dim3 mgrid(static_cast<unsigned>((n + kFinishMfmaThreads - 1) / kFinishMfmaThreads));
+        const dim3 mblk(kFinishMfmaThreads);
+        if (words == 1) {
+            if (f32)
+                hipLaunchKernelGGL((eloc_finish_mfma_kernel<1, NQS_FP32_KAHAN>), mgrid, mblk, 0,
+                                   st, tab, sc, samples, n, chunks, fb, eloc);
+            else
+                hipLaunchKernelGGL((eloc_finish_mfma_kernel<1, NQS_FP64>), mgrid, mblk, 0, st, tab,
+                                   sc, samples, n, chunks, fb, eloc);
+        } else {
+            if (f32)
+                hipLaunchKernelGGL((eloc_finish_mfma_kernel<2, NQS_FP32_KAHAN>), mgrid, mblk, 0,
+                                   st, tab, sc, samples, n, chunks, fb, eloc);
+            else
+                hipLaunchKernelGGL((eloc_finish_mfma_kernel<2, NQS_FP64>), mgrid, mblk, 0, st, tab,
+                                   sc, samples, n, chunks, fb, eloc);
+        }
+        return hipGetLastError();
+    }
 #define NQS_FINISH(Wd, D, Pr)                                                                 \
     do {                                                                                      \
         if ((e = allow_finish_lds<Wd, D, Pr>()) != hipSuccess) return e;                     \

@@ -318,4 +318,44 @@ void build_diag_occ(HostTable *T) {
     T->diag_occ = true;
 }
 
+void build_diag_tiles(const HostTable &T, std::vector<int8_t> *out, double *scale) {
+    out->clear();
+    *scale = 1.0;
+    if (!T.diag_occ) return;
+    const int nq = T.n_qubits;
+    const int jtiles = (nq + 15) / 16;
+    auto u = [&](int j, int i) -> double {
+        if (j >= nq || i > j) return 0.0;
+        return i == j ? T.diag[1 + j] : T.diag[1 + nq + size_t(j) * (j - 1) / 2 + i];
+    };
+    double maxabs = 0.0;
+    for (int j = 0; j < nq; ++j)
+        for (int i = 0; i <= j; ++i) maxabs = std::max(maxabs, std::fabs(u(j, i)));
+    int e = 0;
+    if (maxabs > 0.0) std::frexp(maxabs, &e);  // maxabs < 2^e
+    const int S = maxabs > 0.0 ? 62 - e : 0;
+    *scale = std::ldexp(1.0, -S);
+    const int tiles = jtiles <= 4 ? jtiles : 4 + 2 * (jtiles - 4);
+    out->assign(size_t(tiles) * kDiagLimbs * 64 * 16, 0);
+    int t = 0;
+    for (int jt = 0; jt < jtiles; ++jt) {
+        const int nkb = jt < 4 ? 1 : 2;
+        for (int kb = 0; kb < nkb; ++kb, ++t) {
+            for (int L = 0; L < 64; ++L) {
+                for (int b = 0; b < 16; ++b) {
+                    const int j = 16 * jt + L % 16, i = 64 * kb + 16 * (L / 16) + b;
+                    int64_t q = std::llround(std::ldexp(u(j, i), S));
+                    for (int l = 0; l < kDiagLimbs; ++l) {
+                        int d = static_cast<int>(q & 0xFF);
+                        if (d >= 128) d -= 256;
+                        q = (q - d) / 256;
+                        (*out)[((size_t(t) * kDiagLimbs + l) * 64 + L) * 16 + b] =
+                            static_cast<int8_t>(d);
+                    }
+                }
+            }
+        }
+    }
+}
+
 }  // namespace nqs

@@ -72,6 +72,19 @@ void build_enum_index(HostTable *T);
 // Fill diag_occ and diag from the X = 0 group.
 void build_diag_occ(HostTable *T);
 
+// The occupation form as the digit tiles of the matrix-core diagonal: the
+// terms U[j][i] (i <= j < nq; i == j: d[1 + j], the single terms; i < j:
+// the pair terms) times 2^S, with S the largest integer keeping every
+// |U| 2^S below 2^62, rounded to 64-bit integers and split into kDiagLimbs
+// balanced base-256 digits (in [-128, 127], least significant first).
+// Tiles: for column tile jt (j in [16 jt, 16 jt + 16), ceil(nq / 16) of
+// them) the k-blocks kb of 64 rows i (one for jt < 4, two after), in that
+// order; per tile and digit, lane L holds in byte b the digit of
+// U[16 jt + L % 16][64 kb + 16 (L / 16) + b] (the A-operand layout of the
+// 16 x 16 x 64 int8 MFMA).  *scale = 2^-S.  Empty without the form.
+constexpr int kDiagLimbs = 8;
+void build_diag_tiles(const HostTable &T, std::vector<int8_t> *out, double *scale);
+
 // Sector key: half of popc(X & alpha) | half of popc(X & beta) << 8, or
 // kSectorNeverKey when either popcount is odd (the flip always leaves the
 // sector).
