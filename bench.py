@@ -36,12 +36,16 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # FP64 adds per second: one v_add_f64 per lane per clock (78.6 TFLOP/s counts
 # an FMA as two)
 FP64_PEAK_ADDS = 256 * 4 * 16 * 2.4e9
-KERNEL_SRC = os.path.join(ROOT, "paper_2506_23809_amd", "csrc", "nqs_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2506_23809_amd", "csrc")
+# int8 dense MFMA peak of MI355X (5.0 POP/s)
+INT8_PEAK_OPS = 5.0e15
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
+def kernel_source_hash(kernel: str) -> str:
+    """Hash of the source file that defines the kernel."""
+    src = "nqs_join.hip" if kernel.startswith("join_") else "nqs_kernels.hip"
+    with open(os.path.join(CSRC, src), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
@@ -52,6 +56,21 @@ def algorithmic_bytes(n_s, words, n_groups, n_terms, probes, hits, hit_terms):
     wb = 8 * words
     return (n_s * (wb + 24 + 16) + probes * 32 + (n_groups + n_terms) * (wb + 8)
             + hits * 16 + hit_terms * (wb + 8))
+
+
+def algorithmic_ops_per_sample_diag(n_qubits):
+    """Integer work of the exact occupation-form diagonal per sample on the
+    int8 matrix cores: a multiply-add (two operations) of each of the 8
+    digits of each of the n_qubits (n_qubits + 1) / 2 terms of the triangle."""
+    return 2 * 8 * n_qubits * (n_qubits + 1) // 2
+
+
+def algorithmic_bytes_join_pairs(entries, candidates):
+    """Bytes the pair kernel must move: per entry (sample, block) its packed
+    entry and bucket range (16 B), its bit string (16 B) and its partial sum
+    out (16 B); per candidate (another member of its bucket) the partner's
+    entry (8 B) and bit string (16 B)."""
+    return 48 * entries + 24 * candidates
 
 
 def algorithmic_ops_per_probe_enum():
@@ -217,7 +236,13 @@ def main():
     out = torch.empty((w.n_samples, 2), dtype=torch.float64, device=dev)
 
     def timed(precision):
-        """Warm-up, then EXACTLY args.steps timed steps of one precision."""
+        """Warm-up, then EXACTLY args.steps timed steps of one precision.
+
+        The timed steps call nqs_eloc_eval with the same arguments each time,
+        as a VMC loop does: after its first call the library replays the
+        evaluation as one captured HIP graph.  Then as many profiled steps
+        (eager launches, HIP events around every stage on the launch stream)
+        give the per-kernel durations and the eager step time."""
         def step():
             ham.eloc_into(out, S, la, ph, wt, precision=precision)
             return nqs.energy(wt, out)
@@ -227,8 +252,6 @@ def main():
             log(f"{precision} warmup {k + 1}/{args.warmup}")
         ham.sync()
         st = ham.stats()
-        ham.profile(True)
-        kms = []
         per_step = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -236,18 +259,31 @@ def main():
             ts = time.perf_counter()
             mean, var, sw = step()          # nqs_energy synchronises the stream
             per_step.append((time.perf_counter() - ts) * 1e3)
-            kms.append(ham.last_kernel_ms())
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        ham.profile(False)
         ham.sync()
         ms = elapsed * 1e3 / args.steps
-        log(f"{precision}: timed {args.steps} steps: {ms:.3f} ms/step, E = {mean.real:.10f}, "
+        # profiled steps: eager, every stage timed
+        ham.profile(True)
+        kms, per_eager = [], []
+        torch.cuda.synchronize()
+        for k in range(args.steps):
+            ts = time.perf_counter()
+            step()
+            per_eager.append((time.perf_counter() - ts) * 1e3)
+            kms.append(ham.last_stage_ms())
+        torch.cuda.synchronize()
+        ham.profile(False)
+        ham.sync()
+        log(f"{precision}: timed {args.steps} steps: {ms:.3f} ms/step (graph replay), "
+            f"{np.mean(per_eager):.3f} ms/step eager and profiled, E = {mean.real:.10f}, "
             f"var = {var:.4e}")
         timed.per_step[precision] = per_step
+        timed.eager[precision] = per_eager
         return ms, np.array(kms), mean, var, sw, st
 
     timed.per_step = {}
+    timed.eager = {}
     other = "fp32k" if args.precision == "fp64" else "fp64"
     ms_per_step, kms, mean, var, sw, st = timed(args.precision)
     o_ms, o_kms, o_mean, o_var, _, _ = timed(other)
@@ -260,60 +296,62 @@ def main():
         e_loc_fp64 = torch.view_as_complex(out).cpu().numpy()
 
     kms = np.array(kms)
-    hash_ms, lookup_ms, finish_ms = (float(v) for v in kms.mean(axis=0))
+    group_ms, build_ms, pair_ms, lookup_ms, finish_ms, total_ms = (
+        float(v) for v in kms.mean(axis=0))
     pairs = st["pairs"]
     value = pairs / (ms_per_step / 1e3)
-    # bytes per launch of the lookup kernel (everything except the diagonal group)
-    n_diag_terms = int(np.sum((w.x[:, 0] == 0) & (w.x[:, 1] == 0)))
-    hit_terms = st["terms"] - w.n_samples * n_diag_terms
-    b_alg = algorithmic_bytes(w.n_samples, words, G, T, st["probes"], st["hits"], max(hit_terms, 0))
-    hbm_equiv = b_alg / (lookup_ms / 1e3) / 1e9
     plan = ham.plan()
     joined = plan.get("join_ran") == 1
     enumerated = st.get("enum_rounds", 0) > 0
     strategy = "pair join" if joined else ("enumeration" if enumerated else "streaming")
-    stage_ms = {"grouping": hash_ms, "pairs": lookup_ms, "finish": finish_ms}
+    n_occ = w.n_alpha + w.n_beta
+    occ_form = True  # every molecular table has the occupation-form diagonal
+    finish_name = "eloc_finish_mfma_kernel" if occ_form else "eloc_finish_kernel"
+    # the single kernels of the step and their live durations (HIP events
+    # around each on the launch stream); the grouping stage is several
+    # launches and is reported beside them
     if joined:
-        # the stage that dominates the step carries the roofline
-        dominant = max(stage_ms, key=stage_ms.get)
-    else:
-        dominant = "pairs"
-    peak = VALU_PEAK_OPS
-    peak_unit = "Tops/s (int32 VALU lane-ops)"
-    if dominant == "finish":
-        n_occ = w.n_alpha + w.n_beta
-        kernel_name = "eloc_finish_kernel"
-        ops_unit = 1
-        units = w.n_samples * (1 + n_occ + n_occ * (n_occ - 1) // 2)
-        unit_name = "diagonal term (one FP64 add of the occupation form)"
-        kernel_ms = finish_ms
-        peak = FP64_PEAK_ADDS
-        peak_unit = "T FP64 adds/s"
-    elif dominant == "grouping":
-        kernel_name = "join grouping (count, scan, scatter, sort) + hash build"
-        ops_unit = algorithmic_ops_per_entry_join(words)
-        units = plan["join_blocks"] * w.n_samples
-        unit_name = "join entry (sample, block)"
-        kernel_ms = hash_ms
-    elif joined:
-        kernel_name = "join_pair_kernel"
-        ops_unit = algorithmic_ops_per_candidate_join(words)
-        units = st["candidates"]
-        unit_name = "candidate pair (ordered pair sharing a bucket)"
-        kernel_ms = lookup_ms
+        kernels = {"join_pair_kernel": pair_ms, finish_name: finish_ms}
     elif enumerated:
-        kernel_name = "eloc_enum_kernel"
-        ops_unit = algorithmic_ops_per_probe_enum()
+        kernels = {"eloc_enum_kernel": lookup_ms, finish_name: finish_ms}
+    else:
+        kernels = {"eloc_lookup_kernel": lookup_ms, finish_name: finish_ms}
+    kernel_name = max(kernels, key=kernels.get)
+    kernel_ms = kernels[kernel_name]
+    entries = plan["join_blocks"] * w.n_samples if joined else 0
+    if kernel_name == finish_name:
+        # exact occupation-form diagonal on the int8 matrix cores: per sample
+        # the quadratic form over the nq (nq + 1) / 2 terms of the triangle,
+        # each a multiply-add of 8 digits
+        bound, unit = "mfma", "TOP/s (int8, dense)"
+        peak = INT8_PEAK_OPS
+        per_unit = algorithmic_ops_per_sample_diag(w.n_qubits)
+        units = w.n_samples
+        unit_name = "sample (int8 digit multiply-adds of the diagonal's triangle, x2)"
+        achieved = per_unit * units / (kernel_ms / 1e3)
+    elif kernel_name == "join_pair_kernel":
+        bound, unit = "hbm", "GB/s"
+        peak = HBM_PEAK_GBS * 1e9
+        per_unit = None
+        units = {"entries": entries, "candidates": st["candidates"]}
+        unit_name = ("entry (sample, block): 48 B; candidate pair inside a bucket: 24 B")
+        b_pair = algorithmic_bytes_join_pairs(entries, st["candidates"])
+        achieved = b_pair / (kernel_ms / 1e3)
+    elif kernel_name == "eloc_enum_kernel":
+        bound, unit = "alu", "Tops/s (int32 VALU lane-ops)"
+        peak = VALU_PEAK_OPS
+        per_unit = algorithmic_ops_per_probe_enum()
         units = st["probes"]
         unit_name = "probe"
-        kernel_ms = lookup_ms
+        achieved = per_unit * units / (kernel_ms / 1e3)
     else:
-        kernel_name = "eloc_lookup_kernel"
-        ops_unit = algorithmic_ops_per_pair(w.n_qubits, w.K)
+        bound, unit = "alu", "Tops/s (int32 VALU lane-ops)"
+        peak = VALU_PEAK_OPS
+        per_unit = algorithmic_ops_per_pair(w.n_qubits, w.K)
         units = pairs
         unit_name = "pair"
-        kernel_ms = lookup_ms
-    achieved_ops = ops_unit * units / (kernel_ms / 1e3)
+        achieved = per_unit * units / (kernel_ms / 1e3)
+    scale = 1e9 if bound == "hbm" else 1e12
 
     traffic = None
     # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes of this
@@ -323,11 +361,16 @@ def main():
         try:
             with open(traffic_file) as f:
                 tr = json.load(f)
-            if tr.get("kernel_source_sha256_16") == kernel_source_hash() and \
+            if tr.get("kernel_source_sha256_16") == kernel_source_hash(kernel_name) and \
                     tr.get("workload") == w.name and tr.get("kernel") == kernel_name:
                 traffic = tr.get("hbm_bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
+    # the method's bytes for the whole batch as the SURVEY counts them (one
+    # 32-byte granule per sector-passing lookup, the table once)
+    n_diag_terms = int(np.sum((w.x[:, 0] == 0) & (w.x[:, 1] == 0)))
+    hit_terms = st["terms"] - w.n_samples * n_diag_terms
+    b_alg = algorithmic_bytes(w.n_samples, words, G, T, st["probes"], st["hits"], max(hit_terms, 0))
 
     res = {
         "metric": "E_loc pair-evals/s",
@@ -339,6 +382,7 @@ def main():
         "ms_per_step": ms_per_step,
         "ms_per_step_median": float(np.median(timed.per_step[args.precision])),
         "ms_per_step_min": float(np.min(timed.per_step[args.precision])),
+        "ms_per_step_eager_profiled": float(np.mean(timed.eager[args.precision])),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -353,30 +397,32 @@ def main():
         },
         "roofline": {
             "kernel": kernel_name,
-            "bound": "alu",
-            "achieved": achieved_ops / 1e12,
-            "peak": peak / 1e12,
-            "unit": peak_unit,
-            "frac": achieved_ops / peak,
+            "bound": bound,
+            "achieved": achieved / scale,
+            "peak": peak / scale,
+            "unit": unit,
+            "frac": achieved / peak,
             "traffic": traffic,
-            "traffic_GBps": (traffic / (lookup_ms / 1e3) / 1e9) if traffic else None,
-            "algorithmic_ops_per_unit": ops_unit,
+            "traffic_GBps": (traffic / (kernel_ms / 1e3) / 1e9) if traffic else None,
+            "algorithmic_per_unit": per_unit,
             "unit_of_work": unit_name,
             "units_per_launch": units,
             "kernel_ms": kernel_ms,
-            "hbm_equivalent": {
-                "algorithmic_bytes_per_launch": b_alg,
-                "achieved_GBps": hbm_equiv,
-                "peak_GBps": HBM_PEAK_GBS,
-                "frac": hbm_equiv / HBM_PEAK_GBS,
-                "note": "32 B per sector-passing lookup; above 1.0 because lookups "
-                        "are answered by the LDS filter and the L2-resident hash",
+            "step_kernels_ms": {
+                "hash_clear_and_join_grouping": group_ms, "hash_build": build_ms,
+                "join_pair_kernel": pair_ms, "enum_or_stream_lookup": lookup_ms,
+                finish_name: finish_ms, "evaluation_total": total_ms},
+            "method_bytes": {
+                "algorithmic_bytes_per_batch": b_alg,
+                "GBps_over_step": b_alg / (ms_per_step / 1e3) / 1e9,
+                "note": "one 32-byte granule per sector-passing lookup and the table once; "
+                        "the pair join touches neither for unconnected samples",
             },
         },
         "strategy": strategy,
         "plan": plan,
-        "kernel_ms": {"hash_build_and_join_grouping": hash_ms, "pairs_or_lookup": lookup_ms,
-                      "eloc_finish": finish_ms},
+        "kernel_ms": {"hash_clear_and_join_grouping": group_ms, "hash_build": build_ms,
+                      "join_pairs": pair_ms, "lookup": lookup_ms, "finish": finish_ms},
         "counts": st,
         "probes_per_s": st["probes"] / (ms_per_step / 1e3),
         "setup_ms": setup_ms,
@@ -387,7 +433,9 @@ def main():
             "ms_per_step": o_ms,
             "ms_per_step_median": float(np.median(timed.per_step[other])),
             "ms_per_step_min": float(np.min(timed.per_step[other])),
-            "kernel_ms": float(o_kms.mean(axis=0)[1]),
+            "kernel_ms": dict(zip(("hash_clear_and_join_grouping", "hash_build", "join_pairs",
+                                   "lookup", "finish", "evaluation_total"),
+                                  (float(v) for v in np.array(o_kms).mean(axis=0)))),
             "energy_re": o_mean.real,
             "abs_err_re_energy_fp32k_vs_fp64_Ha": abs(e_fp32k.real - e_fp64.real),
         },

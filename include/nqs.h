@@ -288,6 +288,21 @@ int nqs_profile(nqs_ham h, int enable);
 int nqs_last_kernel_ms(nqs_ham h, float out[3]);
 
 /*
+ * Finer durations of the last profiled evaluation, in milliseconds, from
+ * the same events plus two more (stages that did not run take ~0):
+ *   out[0] hash clear and the pair join's grouping (bucket keys, partition
+ *          counts, placing, per-partition sort, the device's decision)
+ *   out[1] sample-hash build (checks only, when the join runs)
+ *   out[2] the pair join's pair kernel
+ *   out[3] enumeration / streaming lookup kernels (return at once when the
+ *          join runs)
+ *   out[4] finish kernel (diagonal + partial sums)
+ *   out[5] all of the evaluation
+ * Errors as nqs_last_kernel_ms.
+ */
+int nqs_last_stage_ms(nqs_ham h, float out[6]);
+
+/*
  * Test hook: nqs_eloc_eval with the lookup results recorded (same kernels,
  * extra stores switched on).
  *   hit_idx  : device [n][G] int32 or NULL.  For group g of sample i: the

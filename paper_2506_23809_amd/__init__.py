@@ -40,7 +40,7 @@ EXPORTS = ("nqs_last_error", "nqs_version", "nqs_ham_create", "nqs_ham_create_in
            "nqs_ham_info", "nqs_ham_destroy",
            "nqs_table_host", "nqs_diag_tiles_host", "nqs_eloc_eval", "nqs_energy", "nqs_sync", "nqs_eval_stats",
            "nqs_eval_plan", "nqs_debug_fail_allocs", "nqs_eloc_eval_noalloc",
-           "nqs_debug_dump", "nqs_profile", "nqs_last_kernel_ms", "nqs_set_tuning",
+           "nqs_debug_dump", "nqs_profile", "nqs_last_kernel_ms", "nqs_last_stage_ms", "nqs_set_tuning",
            "nqs_get_tuning", "nqs_autotune", "nqs_batch_create", "nqs_batch_launch",
            "nqs_batch_capture", "nqs_batch_replay", "nqs_batch_destroy", "nqs_server_create",
            "nqs_server_add_ham", "nqs_server_submit", "nqs_server_poll", "nqs_server_drain",
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH):
         "nqs_debug_dump": (I, [P, I64, P, P, P, P, P, P, P]),
         "nqs_profile": (I, [P, I]),
         "nqs_last_kernel_ms": (I, [P, P]),
+        "nqs_last_stage_ms": (I, [P, P]),
         "nqs_set_tuning": (I, [P, P]),
         "nqs_get_tuning": (I, [P, P]),
         "nqs_autotune": (I, [P, I64, P, P, P, P, I, ctypes.c_char_p, P, P, P]),
@@ -330,6 +331,13 @@ class Hamiltonian:
         """(hash build, lookup kernel, finish kernel) durations of the last evaluation."""
         out = (ctypes.c_float * 3)()
         _check(load_library().nqs_last_kernel_ms(self._h, out))
+        return tuple(out)
+
+    def last_stage_ms(self):
+        """nqs_last_stage_ms: (grouping, hash build, join pairs, lookup, finish,
+        total) durations of the last evaluation, in ms."""
+        out = (ctypes.c_float * 6)()
+        _check(load_library().nqs_last_stage_ms(self._h, out))
         return tuple(out)
 
     def set_tuning(self, threads=0, filter_bits=0, blocks_per_cu=0, strategy="auto"):

@@ -82,7 +82,9 @@ struct nqs_ham_s {
     // lookup end / finish start, finish end
     bool profiling = false;
     bool profiled = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // profiling events: start, after the hash stage, after the lookup
+    // stage, after the finish, after the join grouping, after the join pairs
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // launch tuning (all-zero = built-in plan)
     nqs::Tuning tune{0, 0, 0, 0};
     // replay of a repeated evaluation: the launch sequence of the last call,
@@ -306,11 +308,13 @@ hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunc
     hipError_t e;
     const bool prof = h->profiling && may_profile;
     if (prof && (e = hipEventRecord(h->ev[0], s)) != hipSuccess) return e;
-    if ((e = nqs::launch_hash(h->dt, sc, sc.slot_mask + 1u, samples, weights, n, s)) != hipSuccess)
+    if ((e = nqs::launch_hash(h->dt, sc, sc.slot_mask + 1u, samples, weights, n, s,
+                              prof ? h->ev[4] : nullptr)) != hipSuccess)
         return e;
     if (prof && (e = hipEventRecord(h->ev[1], s)) != hipSuccess) return e;
     const int64_t sign_words = (h->dt.n_terms + 31) / 32;
-    nqs::EvalStageEvents stages{prof ? h->ev[2] : nullptr};
+    nqs::EvalStageEvents stages{prof ? h->ev[2] : nullptr, prof ? h->ev[5] : nullptr,
+                                nullptr};
     if ((e = nqs::launch_eloc(h->dt, sc, L, samples, log_amp, phase, eloc, precision, hit_idx,
                               sign_bits, sign_words, stages, s)) != hipSuccess)
         return e;
@@ -837,6 +841,23 @@ int nqs_last_kernel_ms(nqs_ham h, float out[3]) {
     NQS_HIP(hipEventElapsedTime(&out[0], h->ev[0], h->ev[1]));
     NQS_HIP(hipEventElapsedTime(&out[1], h->ev[1], h->ev[2]));
     NQS_HIP(hipEventElapsedTime(&out[2], h->ev[2], h->ev[3]));
+    return NQS_OK;
+}
+
+int nqs_last_stage_ms(nqs_ham h, float out[6]) {
+    if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
+    if (!out) return fail(NQS_E_ARG, "null output");
+    if (!h->profiling || !h->profiled) return fail(NQS_E_STATE, "no profiled evaluation");
+    NQS_HIP(hipEventSynchronize(h->ev[3]));
+    // the events of the last evaluation: start, grouping done, hash done,
+    // pairs done, lookup done, finish done (the grouping and pair events are
+    // recorded on every profiled call, so they always belong to it)
+    NQS_HIP(hipEventElapsedTime(&out[0], h->ev[0], h->ev[4]));
+    NQS_HIP(hipEventElapsedTime(&out[1], h->ev[4], h->ev[1]));
+    NQS_HIP(hipEventElapsedTime(&out[2], h->ev[1], h->ev[5]));
+    NQS_HIP(hipEventElapsedTime(&out[3], h->ev[5], h->ev[2]));
+    NQS_HIP(hipEventElapsedTime(&out[4], h->ev[2], h->ev[3]));
+    NQS_HIP(hipEventElapsedTime(&out[5], h->ev[0], h->ev[3]));
     return NQS_OK;
 }
 

@@ -212,6 +212,7 @@ struct DevScratch {
     unsigned long long *jstat;  // [parts][2] sum of squared bucket sizes, largest bucket
     unsigned long long *jctl;   // [kJoinCtl] see kJoinCtl*
     int join_log2m;
+    int64_t join_n;             // samples of the launch (the partials' row length)
     int join_lshift;
     int join_parts;
     int join_tile;              // samples per tile of the grouping kernels
@@ -295,6 +296,8 @@ constexpr int kStrategyAuto = 0, kStrategyStream = 1, kStrategyEnum = 2, kStrate
 // Optional event recorded between the lookup and the finish kernels.
 struct EvalStageEvents {
     hipEvent_t after_lookup;
+    hipEvent_t after_pairs;     // after the pair join's pair kernel (when launched)
+    hipEvent_t after_grouping;  // after the pair join's grouping (before the hash build)
 };
 
 // Launch parameters chosen by the autotuner; 0 means the built-in default
@@ -310,7 +313,7 @@ struct Tuning {
 EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tune);
 hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capacity,
                        const uint64_t *samples, const int64_t *weights, int64_t n,
-                       hipStream_t st);
+                       hipStream_t st, hipEvent_t after_grouping = nullptr);
 hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
                        const uint64_t *samples, const double *log_amp, const double *phase,
                        double *eloc, int precision, int32_t *hit_idx, uint32_t *sign_bits,

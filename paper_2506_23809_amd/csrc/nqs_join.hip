@@ -303,7 +303,8 @@ __global__ __launch_bounds__(kJoinSortThreads) void join_sort_kernel(
         const uint32_t dst = s0 + bs + rank;
         sc.jent[dst] = (static_cast<unsigned long long>(loc) << 32) | me;
         sc.jrange[dst] = (s0 + bs) | (static_cast<unsigned long long>(m) << 32) | (blk << 48);
-        keys[dst] = reinterpret_cast<const uint4 *>(samples)[me];
+        // (a sample alone in its bucket is never paired: no bit string)
+        if (m >= 2) keys[dst] = reinterpret_cast<const uint4 *>(samples)[me];
     }
     block_sum_max(sq, mx);
     if (threadIdx.x == 0) {
@@ -394,8 +395,8 @@ __device__ __forceinline__ bool join_hit(const DevTable &tab, const Key<W> &x, c
 }
 
 // One lane per entry (block b, sample i): the partners of i in its bucket,
-// in index order; its partial sum goes to part[b][i] (zero for a sample
-// alone in its bucket).
+// in index order; its partial sum goes to part[b][i] when it has a hit (the
+// hash build kernel has cleared the partials).
 template <int W, bool DUMP, int P, bool SCV>
 __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
@@ -411,11 +412,11 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
         const unsigned long long r = sc.jrange[p];
         const uint32_t bs = static_cast<uint32_t>(r), m = static_cast<uint32_t>(r >> 32) & 0xFFFFu;
         const int b = static_cast<int>(r >> 48);
+        // the partials start at zero (the hash build kernel of this launch
+        // clears them): a sample alone in its bucket, or without a hit, has
+        // nothing to write
         double *out = sc.part + 2 * (static_cast<int64_t>(b) * n + i);
-        if (m < 2) {
-            out[0] = 0.0;
-            out[1] = 0.0;
-        } else {
+        if (m >= 2) {
             const Key<W> x = load_key<W>(sc.jkeys, p);
             double re = 0.0, im = 0.0, la = 0.0, ph = 0.0;
             bool have_psi = false;
@@ -458,12 +459,14 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
                     ++n_hit;
             }
             n_cand = m - 1;
-            if constexpr (P == NQS_FP64) {
-                out[0] = re;
-                out[1] = im;
-            } else {
-                out[0] = ar.value();
-                out[1] = ai.value();
+            if (n_hit) {
+                if constexpr (P == NQS_FP64) {
+                    out[0] = re;
+                    out[1] = im;
+                } else {
+                    out[0] = ar.value();
+                    out[1] = ai.value();
+                }
             }
         }
     }
@@ -592,6 +595,7 @@ void join_scratch_layout(const DevTable &tab, int64_t n, int log2m, char *base, 
     sc->jctl = reinterpret_cast<unsigned long long *>(base + off[7]);
     sc->jkeys = reinterpret_cast<uint64_t *>(base + off[8]);
     sc->join_log2m = log2m;
+    sc->join_n = n;
     sc->join_lshift = g.lshift;
     sc->join_parts = g.parts;
     sc->join_tile = g.tile;

@@ -86,8 +86,18 @@ __device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScr
         const int rb = __popcll(s0 & tab.spin_b0) + __popcll(s1 & tab.spin_b1);
         if (na != ra || nb != rb) atomicOr(sc.mixed, 1);
     }
-    // the pair join, when it runs, needs neither the hash nor the filters
-    if (bad || join_chosen(sc)) return;
+    // the pair join, when it runs, needs neither the hash nor the filters;
+    // it writes only the partials of samples with hits, so the others start
+    // at zero here (coalesced by sample)
+    if (join_chosen(sc)) {
+        for (int b = 0; b < tab.join_blocks; ++b) {
+            double *p = sc.part + 2 * (static_cast<int64_t>(b) * sc.join_n + i);
+            p[0] = 0.0;
+            p[1] = 0.0;
+        }
+        return;
+    }
+    if (bad) return;
     Key<W> k;
     k.w[0] = w0;
     if constexpr (W == 2) k.w[1] = w1;
@@ -2523,7 +2533,7 @@ EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tu
 
 hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capacity,
                        const uint64_t *samples, const int64_t *weights, int64_t n,
-                       hipStream_t st) {
+                       hipStream_t st, hipEvent_t after_grouping) {
     const int words = tab.n_qubits <= 63 ? 1 : 2;
     const uint32_t fwords = 1u << sc.filter_log2;
     const uint32_t efwords = sc.eparts_log2 > 0 ? (1u << (sc.eparts_log2 + sc.efilter_log2)) : 0u;
@@ -2541,6 +2551,10 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
         // skips its insertion when the join runs
         const hipError_t e = launch_join_prep(tab, sc, samples, n,
                                               tab.n_groups - (tab.has_diagonal ? 1 : 0), st);
+        if (e != hipSuccess) return e;
+    }
+    if (after_grouping) {
+        const hipError_t e = hipEventRecord(after_grouping, st);
         if (e != hipSuccess) return e;
     }
     const dim3 grid(static_cast<unsigned>((n + 255) / 256));
@@ -2625,6 +2639,10 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
         }
         e = launch_join_pairs(tab, sc, samples, log_amp, phase, n, precision, hit_idx, sign_bits,
                               sign_words, st);
+        if (e != hipSuccess) return e;
+    }
+    if (ev.after_pairs) {
+        e = hipEventRecord(ev.after_pairs, st);
         if (e != hipSuccess) return e;
     }
     if (en) {
