@@ -353,7 +353,9 @@ int nqs_debug_dump(nqs_ham h, int64_t n, const uint64_t *samples, const double *
  *     join when its counted cost (sum of squared bucket sizes plus a term
  *     per entry) is below the other strategy's (the
  *     enumeration's lookups, or half the sample-group pairs of streaming).
- *     Batches (nqs_batch_*) and the server never run the pair join.
+ *     Batches (nqs_batch_*) never run the pair join (their persistent
+ *     kernels have no join stage); served requests are planned as single
+ *     evaluations are, the join included.
  */
 enum { NQS_STRATEGY_AUTO = 0, NQS_STRATEGY_STREAM = 1, NQS_STRATEGY_ENUM = 2,
        NQS_STRATEGY_JOIN = 3 };

@@ -998,8 +998,10 @@ std::string shape_key(nqs_ham h, int64_t n, int precision) {
                         ? static_cast<int>(std::lround(std::log2(static_cast<double>(h->dt.n_groups))))
                         : 0;
     char buf[96];
-    std::snprintf(buf, sizeof(buf), "w%d_sec%d_s32_%d_en%d_lgn%d_lgg%d_p%d", h->words,
-                  h->dt.sector_filter, h->dt.sector32, h->dt.enum_ok, lgn, lgg, precision);
+    // (jb: the pair join's blocks; shapes tuned before the join had none)
+    std::snprintf(buf, sizeof(buf), "w%d_sec%d_s32_%d_en%d_jb%d_lgn%d_lgg%d_p%d", h->words,
+                  h->dt.sector_filter, h->dt.sector32, h->dt.enum_ok, h->dt.join_blocks, lgn,
+                  lgg, precision);
     return buf;
 }
 
@@ -1101,6 +1103,9 @@ int nqs_autotune(nqs_ham h, int64_t n, const uint64_t *samples, const double *lo
     // candidates: the streaming kernel's (threads, filter bits, items per
     // CU) grid, and for tables that allow it the enumeration's filter sizes
     std::vector<nqs::Tuning> cands;
+    // first the built-in plan (the device picks the join or the other
+    // strategy per batch): a forced strategy must beat it to be kept
+    cands.push_back(nqs::Tuning{0, 0, 0, nqs::kStrategyAuto});
     for (int th : {256, 512, 1024})
         for (int fb : {8, 16, 32})
             for (int bc : {2, 4, 8}) cands.push_back(nqs::Tuning{th, fb, bc, nqs::kStrategyStream});
@@ -1160,6 +1165,7 @@ int nqs_autotune(nqs_ham h, int64_t n, const uint64_t *samples, const double *lo
 struct nqs_batch_s {
     int precision = NQS_FP64;
     std::vector<nqs_ham> hams;
+    std::vector<nqs::JobDesc> jobs;  // host copy of d_jobs (the join's per-job launches)
     std::vector<int64_t> ns;
     nqs::JobDesc *d_jobs = nullptr;
     nqs::WorkItem *d_items = nullptr;
@@ -1209,6 +1215,7 @@ int nqs_batch_create(nqs_batch *out, int n_items, const nqs_batch_item *items, i
     nqs_batch b = new (std::nothrow) nqs_batch_s();
     if (!b) return fail(NQS_E_NOMEM, "host allocation failed");
     b->precision = precision;
+    b->jobs = jobs;
     b->n_jobs = n_items;
     b->n_items = static_cast<int>(work.size());
     b->shape = shape;
@@ -1239,7 +1246,7 @@ int nqs_batch_create(nqs_batch *out, int n_items, const nqs_batch_item *items, i
 int nqs_batch_launch(nqs_batch b, void *hip_stream) {
     if (!b || !b->d_jobs) return fail(NQS_E_STATE, "invalid batch");
     NQS_HIP(nqs::launch_batch(b->d_jobs, b->n_jobs, b->d_items, b->n_items, b->d_next, b->shape,
-                              b->precision, static_cast<hipStream_t>(hip_stream)));
+                              b->precision, static_cast<hipStream_t>(hip_stream), b->jobs.data()));
     batch_mark(b);
     return NQS_OK;
 }
@@ -1260,7 +1267,8 @@ int nqs_batch_capture(nqs_batch b, void *hip_stream) {
     NQS_HIP(nqs::prepare_batch_kernels());
     NQS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     const hipError_t le = nqs::launch_batch(b->d_jobs, b->n_jobs, b->d_items, b->n_items,
-                                            b->d_next, b->shape, b->precision, st);
+                                            b->d_next, b->shape, b->precision, st,
+                                            b->jobs.data());
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(st, &g);
     if (le != hipSuccess) {
@@ -1399,15 +1407,15 @@ int plan_batch(const nqs_batch_item *items, int n_items, int threads, hipStream_
         // enumeration rounds assume 1024-thread blocks
         if (th != kEnumThreads) t.strategy = kStrategyStream;
         EvalLaunch L = plan_eval(h->dt, std::max<int64_t>(it.n, 1), false, &t);
-        L.join = 0;  // batches run the enumeration or streaming items only
+        if (it.n == 0) L.join = 0;
         if (L.strategy == kStrategyEnum && L.chunk_len > 0) {
             // the streaming items are only a fallback here (mixed sectors):
             // one group chunk keeps their number small
             L.n_chunks = 1;
             L.chunk_len = h->dt.n_groups - L.g_first;
         }
-        int rc = ensure_scratch(h, std::max<int64_t>(it.n, 1), L.n_chunks, st,
-                                L.eparts_log2 > 0);
+        int rc = ensure_scratch(h, std::max<int64_t>(it.n, 1), plan_chunks(h, L), st,
+                                L.eparts_log2 > 0, plan_join_bytes(h, L));
         if (!rc) rc = scratch_ready(h, L);
         if (rc) return rc;
         JobDesc &J = jobs[k];
@@ -1437,6 +1445,9 @@ int plan_batch(const nqs_batch_item *items, int n_items, int threads, hipStream_
         if (L.eparts_log2 > 0)
             shape.max_clear = std::max<int64_t>(shape.max_clear,
                                                 int64_t(1) << (L.eparts_log2 + L.efilter_log2));
+        if (J.sc.jctl)
+            shape.max_clear = std::max<int64_t>(
+                shape.max_clear, std::max<int64_t>(J.sc.join_parts, nqs::kJoinCtl));
         cost[k] = it.n * (h->dt.n_groups - L.g_first);
     }
     // work list: largest jobs first (the persistent kernel drains it in order),

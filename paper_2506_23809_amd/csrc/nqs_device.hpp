@@ -385,8 +385,11 @@ struct BatchShape {
 
 // d_next: kBatchCounters counters (one per enumeration variant, then the
 // streaming items).
+// h_jobs: the host copy of the job descriptors (the pair join's per-job
+// launches read their tables and scratch from it).
 hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_items, int n_items,
-                        unsigned *d_next, const BatchShape &shape, int precision, hipStream_t st);
+                        unsigned *d_next, const BatchShape &shape, int precision, hipStream_t st,
+                        const JobDesc *h_jobs);
 size_t batch_lds_bytes(int threads, int max_filter_log2);
 // Set the dynamic-LDS limit of the batch kernels (outside any graph capture).
 hipError_t prepare_batch_kernels();

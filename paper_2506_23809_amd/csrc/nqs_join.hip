@@ -49,6 +49,9 @@ namespace {
 constexpr int kJoinGroupThreads = 1024;  // tile kernels, sorter, decision
 constexpr int kJoinPairThreads = 256;
 constexpr int kJoinSortThreads = 512;
+// Largest bucket ranked by a pass over its members; a partition with a
+// larger one is bitonic-sorted whole.
+constexpr unsigned long long kJoinRankMax = 64;
 constexpr int kJoinMaxParts = 8192;      // partitions of any planned launch
 constexpr int kJoinMaxLocal = 2048;      // buckets per partition (2^join_lshift)
 constexpr int kJoinTiles = 128;          // tiles of the grouping kernels, at most
@@ -282,7 +285,13 @@ __global__ __launch_bounds__(kJoinSortThreads) void join_sort_kernel(
         cnt[u] = static_cast<uint32_t>(run) | (v << 16);
         run += v;
     }
+    // the partition's sum of squares and largest bucket (also decides the
+    // ordering method below)
+    block_sum_max(sq, mx);
+    __shared__ unsigned long long s_mx;
+    if (threadIdx.x == 0) s_mx = mx;
     __syncthreads();
+    const unsigned long long mx_all = s_mx;
     for (uint32_t u = threadIdx.x; u < c; u += blockDim.x) {
         const unsigned long long e = sc.jent[s0 + u];
         const uint32_t loc = static_cast<uint32_t>(e >> 32);
@@ -290,6 +299,30 @@ __global__ __launch_bounds__(kJoinSortThreads) void join_sort_kernel(
         buf[at] = (loc << 21) | static_cast<uint32_t>(e);
     }
     __syncthreads();
+    // large buckets (clustered samples: few distinct block contents): sort
+    // the whole partition (bitonic, 4-byte keys in LDS) instead of ranking
+    // each entry by a pass over its bucket, which would be quadratic
+    const bool big = mx_all > kJoinRankMax;
+    if (big) {
+        uint32_t P2 = 2;
+        while (P2 < c) P2 <<= 1;
+        for (uint32_t u = c + threadIdx.x; u < P2; u += blockDim.x) buf[u] = 0xFFFFFFFFu;
+        for (uint32_t k = 2; k <= P2; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                __syncthreads();
+                for (uint32_t t = threadIdx.x; t < (P2 >> 1); t += blockDim.x) {
+                    // the t-th index with bit j clear, and its partner
+                    const uint32_t a = ((t & ~(j - 1u)) << 1) | (t & (j - 1u)), l = a + j;
+                    const uint32_t va = buf[a], vl = buf[l];
+                    if ((va > vl) == ((a & k) == 0)) {
+                        buf[a] = vl;
+                        buf[l] = va;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
     const unsigned long long blk =
         static_cast<unsigned long long>(p >> (sc.join_log2m - sc.join_lshift));
     uint4 *keys = reinterpret_cast<uint4 *>(sc.jkeys);
@@ -298,15 +331,19 @@ __global__ __launch_bounds__(kJoinSortThreads) void join_sort_kernel(
         const uint32_t loc = v >> 21, me = v & 0x1FFFFFu;
         const uint32_t r = cnt[loc];
         const uint32_t bs = r & 0xFFFFu, m = r >> 16;
-        uint32_t rank = 0;
-        for (uint32_t q = bs; q < bs + m; ++q) rank += (buf[q] & 0x1FFFFFu) < me ? 1u : 0u;
+        uint32_t rank;
+        if (big) {
+            rank = u - bs;  // sorted: the place in the bucket is the offset
+        } else {
+            rank = 0;
+            for (uint32_t q = bs; q < bs + m; ++q) rank += (buf[q] & 0x1FFFFFu) < me ? 1u : 0u;
+        }
         const uint32_t dst = s0 + bs + rank;
         sc.jent[dst] = (static_cast<unsigned long long>(loc) << 32) | me;
         sc.jrange[dst] = (s0 + bs) | (static_cast<unsigned long long>(m) << 32) | (blk << 48);
         // (a sample alone in its bucket is never paired: no bit string)
         if (m >= 2) keys[dst] = reinterpret_cast<const uint4 *>(samples)[me];
     }
-    block_sum_max(sq, mx);
     if (threadIdx.x == 0) {
         sc.jstat[2 * p] = sq;
         sc.jstat[2 * p + 1] = mx;
@@ -338,11 +375,19 @@ __global__ __launch_bounds__(kJoinGroupThreads) void join_decide_kernel(
     unsigned long long probes = 0;
     for (int k = 0; k < 64; ++k) probes += sc.jctl[kJoinCtlProbeSlots + k];
     sc.jctl[kJoinCtlProbes] = probes;
-    const double alt = enum_usable ? static_cast<double>(probes)
-                                   : 0.5 * static_cast<double>(n) * static_cast<double>(g_eff);
-    // the join's own fixed work: keys, placing and sorting the entries
+    // costs in units of one enumeration probe, from MI355X timings of both
+    // strategies over 64 molecule-shaped jobs (24..100 qubits, 10^3..2.6 10^5
+    // samples): a candidate pair of the join costs about 4 probes, an entry
+    // (its grouping and its share of the pair kernel) about 40, the join's
+    // extra launches about 10^7; a probe against a filter split into class
+    // partitions costs about 4 (each round walks the partitions).  Hits cost
+    // the same in every strategy and do not enter.
+    const double alt = enum_usable
+                           ? static_cast<double>(probes) * (sc.eparts_log2 > 0 ? 4.0 : 1.0)
+                           : 0.5 * static_cast<double>(n) * static_cast<double>(g_eff);
     const double entries = static_cast<double>(tab.join_blocks) * static_cast<double>(n);
-    const double cost = static_cast<double>(q) + 4.0 * entries;
+    const double cand = static_cast<double>(q) > entries ? static_cast<double>(q) - entries : 0.0;
+    const double cost = 4.0 * cand + 40.0 * entries + 1.0e7;
     const bool fits = sc.jctl[kJoinCtlOver] == 0ull;
     const bool chosen = fits && (sc.join_force != 0 || cost < alt);
     sc.jctl[kJoinCtlCost] = q;

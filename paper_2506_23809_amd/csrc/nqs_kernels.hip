@@ -1726,26 +1726,22 @@ __device__ __forceinline__ diag_v4i spread_bits16(uint32_t v) {
 // b = k); C row 4 (L / 16) + r, column L % 16 in its r-th value.  The digit
 // tiles are stored in that A layout.
 // One column tile jt of diag_occ_mfma for H groups of 16 samples: the
-// digit tiles at B + t (KB k-blocks), the samples' bit operands N, their
-// words m0/m1 for the row masks, the digit sums T.
+// digit tiles at B + t (KB k-blocks), the samples' bit operands N, the row
+// masks mk (bit 4 jt + r: n_s[j] for the lane's row j = 16 jt + 4 g + r),
+// the digit sums T.
 template <int H, int KB>
 __device__ __forceinline__ void diag_mfma_tile(const diag_v4i *__restrict__ B, int t, int jt,
-                                               int lane, int g, const diag_v4i (&N)[H][2],
-                                               const uint64_t (&m0)[H], const uint64_t (&m1)[H],
-                                               int (&T)[H][kDiagLimbs]) {
+                                               int lane, const diag_v4i (&N)[H][2],
+                                               const uint32_t (&mk)[H], int (&T)[H][kDiagLimbs]) {
     const diag_v4i zero = {0, 0, 0, 0};
-    // n_s[j] for the lane's rows j = 16 jt + 4 g + r, r = 0..3, as 0/1
-    // multipliers (hidden from the optimiser, so that each masked add stays
-    // a 24-bit multiply and an add)
-    const int j0 = 16 * jt + 4 * g;
+    // the row masks as 0/1 multipliers (hidden from the optimiser, so that
+    // each masked add stays a 24-bit multiply and an add)
     int bit[H][4];
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-        const uint32_t nib =
-            static_cast<uint32_t>(((j0 < 64 ? m0[h] : m1[h]) >> (j0 & 63)) & 0xFull);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            bit[h][r] = static_cast<int>((nib >> r) & 1u);
+            bit[h][r] = static_cast<int>((mk[h] >> (4 * jt + r)) & 1u);
             asm("" : "+v"(bit[h][r]));
         }
     }
@@ -1768,55 +1764,57 @@ __device__ __forceinline__ void diag_mfma_tile(const diag_v4i *__restrict__ B, i
 template <int W>
 __device__ __forceinline__ double diag_occ_mfma(const DevTable &tab, const Key<W> &x,
                                                 const diag_v4i *__restrict__ B) {
-    // groups of 16 samples per pass over the digit tiles (two passes: the
-    // registers of four groups at once would spill)
-    constexpr int H = 2;
+    // all four groups of 16 samples in one pass over the digit tiles
+    constexpr int H = 4;
     const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
     const uint64_t w0 = x.w[0], w1 = W == 2 ? x.w[W - 1] : 0ull;
     const int jtiles = tab.diag_jtiles;
+    // the column samples 16 h + c: their bits as the B operands of both
+    // k-blocks, and the lane's row masks (bits 16 jt + 4 g + r of them,
+    // packed as bit 4 jt + r)
+    diag_v4i N[H][2];
+    uint32_t mk[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const uint64_t m0 = __shfl(w0, 16 * h + c), m1 = __shfl(w1, 16 * h + c);
+        N[h][0] = spread_bits16(static_cast<uint32_t>(m0 >> (16 * g)) & 0xFFFFu);
+        N[h][1] = spread_bits16(static_cast<uint32_t>(m1 >> (16 * g)) & 0xFFFFu);
+        uint32_t v = 0;
+#pragma unroll
+        for (int jt = 0; jt < 8; ++jt) {
+            const uint64_t wd = jt < 4 ? m0 : m1;
+            v |= static_cast<uint32_t>((wd >> ((16 * jt + 4 * g) & 63)) & 0xFull) << (4 * jt);
+        }
+        mk[h] = v;
+    }
+    int T[H][kDiagLimbs];
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int l = 0; l < kDiagLimbs; ++l) T[h][l] = 0;
+    // column tiles 0..3 reach rows i < 64 (one k-block), later ones two
+    const int j1 = jtiles < 4 ? jtiles : 4;
+    for (int jt = 0; jt < j1; ++jt) diag_mfma_tile<H, 1>(B, jt, jt, lane, N, mk, T);
+    for (int jt = 4; jt < jtiles; ++jt) diag_mfma_tile<H, 2>(B, 4 + 2 * (jt - 4), jt, lane, N, mk, T);
     double mine = 0.0;
-    for (int pass = 0; pass < 4 / H; ++pass) {
-        // the column samples 16 (H pass + h) + c: their bits as the B
-        // operands of both k-blocks, and their words for the masks
-        diag_v4i N[H][2];
-        uint64_t m0[H], m1[H];
 #pragma unroll
-        for (int h = 0; h < H; ++h) {
-            const int src = 16 * (H * pass + h) + c;
-            m0[h] = __shfl(w0, src);
-            m1[h] = __shfl(w1, src);
-            N[h][0] = spread_bits16(static_cast<uint32_t>(m0[h] >> (16 * g)) & 0xFFFFu);
-            N[h][1] = spread_bits16(static_cast<uint32_t>(m1[h] >> (16 * g)) & 0xFFFFu);
+    for (int h = 0; h < H; ++h) {
+        // digits 0..3 and 4..7 recombined (each below 2^46 in magnitude),
+        // then summed over the four row groups of the lane's column
+        long long lo = 0, hi = 0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            lo += static_cast<long long>(T[h][l]) << (8 * l);
+            hi += static_cast<long long>(T[h][l + 4]) << (8 * l);
         }
-        int T[H][kDiagLimbs];
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-            for (int l = 0; l < kDiagLimbs; ++l) T[h][l] = 0;
-        // column tiles 0..3 reach rows i < 64 (one k-block), later ones two
-        const int j1 = jtiles < 4 ? jtiles : 4;
-        for (int jt = 0; jt < j1; ++jt) diag_mfma_tile<H, 1>(B, jt, jt, lane, g, N, m0, m1, T);
-        for (int jt = 4; jt < jtiles; ++jt)
-            diag_mfma_tile<H, 2>(B, 4 + 2 * (jt - 4), jt, lane, g, N, m0, m1, T);
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-            // digits 0..3 and 4..7 recombined (each below 2^46 in magnitude),
-            // then summed over the four row groups of the lane's column
-            long long lo = 0, hi = 0;
-#pragma unroll
-            for (int l = 0; l < 4; ++l) {
-                lo += static_cast<long long>(T[h][l]) << (8 * l);
-                hi += static_cast<long long>(T[h][l + 4]) << (8 * l);
-            }
-            lo += __shfl_xor(lo, 16);
-            hi += __shfl_xor(hi, 16);
-            lo += __shfl_xor(lo, 32);
-            hi += __shfl_xor(hi, 32);
-            // both terms exact in FP64, one rounding of the exact total; the
-            // lane of sample 16 (H pass + h) + c (row group H pass + h) keeps it
-            const double v = static_cast<double>(lo) + static_cast<double>(hi) * 4294967296.0;
-            if (g == H * pass + h) mine = v;
-        }
+        lo += __shfl_xor(lo, 16);
+        hi += __shfl_xor(hi, 16);
+        lo += __shfl_xor(lo, 32);
+        hi += __shfl_xor(hi, 32);
+        // both terms exact in FP64, one rounding of the exact total; the
+        // lane of sample 16 h + c (row group h) keeps it
+        const double v = static_cast<double>(lo) + static_cast<double>(hi) * 4294967296.0;
+        if (g == h) mine = v;
     }
     return tab.diag[0] + mine * tab.diag_scale;
 }
@@ -2106,6 +2104,10 @@ __global__ void batch_clear_kernel(const JobDesc *__restrict__ jobs) {
     if (s < (1u << J.sc.filter_log2)) J.sc.filter[s] = 0u;
     if (J.sc.eparts_log2 > 0 && s < (1u << (J.sc.eparts_log2 + J.sc.efilter_log2)))
         J.sc.efilter[s] = 0u;
+    if (J.sc.jctl) {
+        if (s < static_cast<uint32_t>(J.sc.join_parts)) J.sc.jcnt[s] = 0u;
+        if (s < static_cast<uint32_t>(kJoinCtl)) J.sc.jctl[s] = 0ull;
+    }
 }
 
 __global__ void batch_build_kernel(const JobDesc *__restrict__ jobs) {
@@ -2139,6 +2141,7 @@ __global__ __launch_bounds__(kEnumThreads) void batch_enum_kernel(
         if (it >= n_items) break;  // every block reaches this once the list is drained
         const WorkItem w = items[it];
         const JobDesc &J = jobs[w.job];
+        if (join_chosen(J.sc)) continue;  // the pair join does this job
         const EnumShape S = uniform_shape(enum_shape(J.tab, J.sc, J.samples, J.n));
         if (S.B <= 0) continue;  // the streaming items do this job
         const int per_round = S.solo ? kEnumWaves : S.B;
@@ -2186,6 +2189,7 @@ __global__ __launch_bounds__(kLookupThreads) void batch_lookup_kernel(
         if (it >= n_items) break;  // every block reaches this once the list is drained
         const WorkItem w = items[it];
         const JobDesc &J = jobs[w.job];
+        if (join_chosen(J.sc)) continue;  // the pair join does this job
         if (J.strategy == kStrategyEnum && enum_shape(J.tab, J.sc, J.samples, J.n).B > 0)
             continue;  // enumerated instead
         const bool load = w.job != last_job;
@@ -2302,12 +2306,22 @@ hipError_t prepare_batch_kernels() {
 
 hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_items, int n_items,
                         unsigned *d_next, const BatchShape &shape, int precision,
-                        hipStream_t st) {
+                        hipStream_t st, const JobDesc *h_jobs) {
     hipLaunchKernelGGL(batch_reset_kernel, dim3((n_jobs + 63) / 64), dim3(64), 0, st, d_jobs,
                        n_jobs, d_next);
     hipLaunchKernelGGL(batch_clear_kernel,
                        dim3(static_cast<unsigned>((shape.max_clear + 255) / 256), n_jobs),
                        dim3(256), 0, st, d_jobs);
+    // the pair join's grouping and decision for the jobs that plan it
+    // (the same kernels as a single launch; the build and the persistent
+    // kernels below skip a job the join takes)
+    for (int k = 0; h_jobs && k < n_jobs; ++k) {
+        const JobDesc &J = h_jobs[k];
+        if (!J.sc.jctl || J.n == 0) continue;
+        const hipError_t e = launch_join_prep(J.tab, J.sc, J.samples, J.n,
+                                              J.tab.n_groups - (J.tab.has_diagonal ? 1 : 0), st);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(batch_build_kernel,
                        dim3(static_cast<unsigned>((shape.max_n + 255) / 256), n_jobs), dim3(256),
                        0, st, d_jobs);
@@ -2332,6 +2346,14 @@ hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_ite
             default: NQS_EB(2, NQS_FP64, true); break;
         }
 #undef NQS_EB
+    }
+    for (int k = 0; h_jobs && k < n_jobs; ++k) {
+        const JobDesc &J = h_jobs[k];
+        if (!J.sc.jctl || J.n == 0) continue;
+        const int pr = (J.kind & kJobIntegrals) ? NQS_FP64 : precision;
+        const hipError_t e = launch_join_pairs(J.tab, J.sc, J.samples, J.log_amp, J.phase, J.n, pr,
+                                               nullptr, nullptr, 0, st);
+        if (e != hipSuccess) return e;
     }
     const int ne = shape.enum_begin[kEnumVariants];
     const WorkItem *s_items = d_items + ne;
@@ -2727,8 +2749,11 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
                          : sizeof(double) * stage_cap + (f32 ? size_t(256) * 4 * list_words : 0);
     if (!dump && !tab.sc && tab.diag_jtiles > 0) {
         // the occupation-form diagonal on the matrix cores
-        const dim3 mgrid(static_cast<unsigned>((n + kFinishMfmaThreads - 1) / kFinishMfmaThreads));
-        const dim3 mblk(kFinishMfmaThreads);
+        // 1024-thread blocks once they fill every CU (each block stages the
+        // digit tiles once), else 256-thread blocks to spread a small batch
+        const int mth = n >= 256 * int64_t(kFinishMfmaThreads) ? kFinishMfmaThreads : 256;
+        const dim3 mgrid(static_cast<unsigned>((n + mth - 1) / mth));
+        const dim3 mblk(mth);
         if (words == 1) {
             if (f32)
                 hipLaunchKernelGGL((eloc_finish_mfma_kernel<1, NQS_FP32_KAHAN>), mgrid, mblk, 0,

@@ -85,9 +85,8 @@ def test_batch_equals_single_launches(torch_dev, family):
     for w, h, (S, la, ph, wt, out), eb, sb in zip(family, hams, bufs, batched, stats_b):
         if w.n_samples == 0:
             continue
-        # a batch runs the enumeration (or streaming) items, never the pair
-        # join: compare with the single launch of the same strategy
-        h.set_tuning(strategy="enum")
+        # the same plan as the batch (auto: the device picks the pair join or
+        # the enumeration/streaming per job, the same way in both)
         e = h.eloc(S, la, ph, wt)
         h.sync()
         es = torch.view_as_real(e).cpu().numpy()
