@@ -353,9 +353,10 @@ int nqs_debug_dump(nqs_ham h, int64_t n, const uint64_t *samples, const double *
  *     join when its counted cost (sum of squared bucket sizes plus a term
  *     per entry) is below the other strategy's (the
  *     enumeration's lookups, or half the sample-group pairs of streaming).
- *     Batches (nqs_batch_*) never run the pair join (their persistent
- *     kernels have no join stage); served requests are planned as single
- *     evaluations are, the join included.
+ *     Batches (nqs_batch_*) make the same decision per job: a job's
+ *     grouping and pair kernels are launched around the persistent
+ *     kernels, which skip the job when its device chose the join.  Served
+ *     requests are planned as single evaluations are, the join included.
  */
 enum { NQS_STRATEGY_AUTO = 0, NQS_STRATEGY_STREAM = 1, NQS_STRATEGY_ENUM = 2,
        NQS_STRATEGY_JOIN = 3 };
