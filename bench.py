@@ -65,12 +65,14 @@ def algorithmic_ops_per_sample_diag(n_qubits):
     return 2 * 8 * n_qubits * (n_qubits + 1) // 2
 
 
-def algorithmic_bytes_join_pairs(entries, candidates):
-    """Bytes the pair kernel must move: per entry (sample, block) its packed
-    entry and bucket range (16 B), its bit string (16 B) and its partial sum
-    out (16 B); per candidate (another member of its bucket) the partner's
-    entry (8 B) and bit string (16 B)."""
-    return 48 * entries + 24 * candidates
+def algorithmic_bytes_join_pairs(entries, candidates, samples):
+    """Bytes the pair kernel's launch must move: per entry (sample, block)
+    its packed entry and bucket range (16 B), its bit string (16 B) and its
+    partial sum out (16 B); per candidate (another member of its bucket) the
+    partner's entry (8 B) and bit string (16 B); per sample, for the hash
+    build's checks carried by the same launch, its bit string (16 B) and
+    count (8 B)."""
+    return 48 * entries + 24 * candidates + 24 * samples
 
 
 def algorithmic_ops_per_probe_enum():
@@ -333,9 +335,10 @@ def main():
         bound, unit = "hbm", "GB/s"
         peak = HBM_PEAK_GBS * 1e9
         per_unit = None
-        units = {"entries": entries, "candidates": st["candidates"]}
-        unit_name = ("entry (sample, block): 48 B; candidate pair inside a bucket: 24 B")
-        b_pair = algorithmic_bytes_join_pairs(entries, st["candidates"])
+        units = {"entries": entries, "candidates": st["candidates"], "samples": w.n_samples}
+        unit_name = ("entry (sample, block): 48 B; candidate pair inside a bucket: 24 B; "
+                     "sample (hash-build checks in the same launch): 24 B")
+        b_pair = algorithmic_bytes_join_pairs(entries, st["candidates"], w.n_samples)
         achieved = b_pair / (kernel_ms / 1e3)
     elif kernel_name == "eloc_enum_kernel":
         bound, unit = "alu", "Tops/s (int32 VALU lane-ops)"

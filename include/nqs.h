@@ -213,10 +213,14 @@ int nqs_eloc_eval_noalloc(nqs_ham h, int64_t n, const uint64_t *samples, const i
 /*
  * Count-weighted energy of Eq. 1 over unique samples:
  *   out[0] = Re E, out[1] = Im E with E = sum w E_loc / sum w,
- *   out[2] = sum w |E_loc - E|^2 / sum w (population variance, second pass),
+ *   out[2] = sum w |E_loc - E|^2 / sum w (population variance),
  *   out[3] = sum w.
+ * Two launches: each of up to 256 blocks sums a fixed strided set of
+ * samples and their deviations about its own mean; one block combines them
+ * in block order (per block, M2_b + W_b |mean_b - E|^2).
  * weights: device [n] int64; eloc: device [n][2] double; out: host [4].
  * The reduction order is fixed, so repeated calls give identical bits.
+ * Calls are serialised per device (one scratch per device).
  * Synchronises hip_stream before returning.  Errors: NQS_E_ARG (n <= 0,
  * null pointers, sum w == 0), NQS_E_NOMEM, NQS_E_DEVICE.
  */
@@ -290,10 +294,12 @@ int nqs_last_kernel_ms(nqs_ham h, float out[3]);
 /*
  * Finer durations of the last profiled evaluation, in milliseconds, from
  * the same events plus two more (stages that did not run take ~0):
- *   out[0] hash clear and the pair join's grouping (bucket keys, partition
- *          counts, placing, per-partition sort, the device's decision)
- *   out[1] sample-hash build (checks only, when the join runs)
- *   out[2] the pair join's pair kernel
+ *   out[0] clear and the pair join's grouping (bucket keys and, in the same
+ *          launch, the hash clear; partition counts, placing, per-partition
+ *          sort, the device's decision)
+ *   out[1] sample-hash build (~0 when the join is launched: the build then
+ *          runs inside the pair kernel's launch)
+ *   out[2] the pair join's pair kernel (with the hash build)
  *   out[3] enumeration / streaming lookup kernels (return at once when the
  *          join runs)
  *   out[4] finish kernel (diagonal + partial sums)

@@ -315,8 +315,8 @@ hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunc
     const int64_t sign_words = (h->dt.n_terms + 31) / 32;
     nqs::EvalStageEvents stages{prof ? h->ev[2] : nullptr, prof ? h->ev[5] : nullptr,
                                 nullptr};
-    if ((e = nqs::launch_eloc(h->dt, sc, L, samples, log_amp, phase, eloc, precision, hit_idx,
-                              sign_bits, sign_words, stages, s)) != hipSuccess)
+    if ((e = nqs::launch_eloc(h->dt, sc, L, samples, weights, log_amp, phase, eloc, precision,
+                              hit_idx, sign_bits, sign_words, stages, s)) != hipSuccess)
         return e;
     if (prof && (e = hipEventRecord(h->ev[3], s)) != hipSuccess) return e;
     return hipSuccess;
@@ -553,7 +553,7 @@ int eval_noalloc(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *w
 
 // Process-wide scratch of nqs_energy, one per device, used under a lock.
 struct EnergyScratch {
-    double *dev = nullptr;   // part[3*256] | result[3] | out[4]
+    double *dev = nullptr;   // block partials | out[4]
     double *host = nullptr;  // pinned out[4]
 };
 std::mutex g_energy_mutex;
@@ -959,9 +959,8 @@ int nqs_energy(int64_t n, const int64_t *weights, const double *eloc, double out
         }
     }
     double *part = es.dev;
-    double *result = es.dev + nqs::kEnergyPartDoubles;
-    double *dout = result + 4;
-    NQS_HIP(nqs::launch_energy(weights, eloc, n, part, result, dout, st));
+    double *dout = es.dev + nqs::kEnergyPartDoubles;
+    NQS_HIP(nqs::launch_energy(weights, eloc, n, part, dout, st));
     NQS_HIP(hipMemcpyAsync(es.host, dout, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
     NQS_HIP(hipStreamSynchronize(st));
     std::memcpy(out, es.host, sizeof(double) * 4);

@@ -411,5 +411,78 @@ __device__ __forceinline__ int64_t group_find(const DevTable &tab, uint32_t hX, 
     return -1;
 }
 
+// ------------------------------------------------------------------ hash build
+
+// One thread per sample: range check, sector uniformity, counts >= 0, linear
+// hash, Bloom bit, and insertion by CAS on the slot index.  A duplicate key
+// is found by comparing against the sample that owns the slot.  With the
+// pair join chosen only the checks run.
+template <int W>
+__device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScratch &sc,
+                                               const uint64_t *__restrict__ samples,
+                                               const int64_t *__restrict__ weights, int64_t i) {
+    const uint64_t w0 = samples[2 * i], w1 = samples[2 * i + 1];
+    bool bad;
+    const int nq = tab.n_qubits;
+    if (nq >= 64) {
+        bad = (nq - 64 < 64) && ((w1 >> (nq - 64)) != 0);
+    } else {
+        bad = ((w0 >> nq) != 0) || (w1 != 0);
+    }
+    if (bad) latch(sc.err, NQS_E_RANGE);
+    if (weights && weights[i] < 0) latch(sc.err, NQS_E_RANGE);
+    if (tab.sector_filter) {
+        const uint64_t s0 = samples[0], s1 = samples[1];
+        const int na = __popcll(w0 & tab.spin_a0) + __popcll(w1 & tab.spin_a1);
+        const int nb = __popcll(w0 & tab.spin_b0) + __popcll(w1 & tab.spin_b1);
+        const int ra = __popcll(s0 & tab.spin_a0) + __popcll(s1 & tab.spin_a1);
+        const int rb = __popcll(s0 & tab.spin_b0) + __popcll(s1 & tab.spin_b1);
+        if (na != ra || nb != rb) atomicOr(sc.mixed, 1);
+    }
+    // the pair join, when it runs, needs neither the hash nor the filters
+    if (join_chosen(sc) || bad) return;
+    Key<W> k;
+    k.w[0] = w0;
+    if constexpr (W == 2) k.w[1] = w1;
+    const uint32_t h = linear_hash<W>(k, tab.hr);
+    sc.shx[i] = h;
+    const uint32_t fmask = (1u << sc.filter_log2) - 1u;
+    const uint32_t fbits = filter_bits(h);
+    atomicOr(&sc.filter[filter_word(h, fmask)], fbits);
+    if (sc.eparts_log2 > 0) {
+        // the partition of the enumeration filter: class of x, the XOR of
+        // the classes of its occupied beta qubits
+        uint32_t c = 0;
+        uint64_t m0 = w0 & tab.spin_b0, m1 = w1 & tab.spin_b1;
+        while (m0) {
+            c ^= tab.qcls[__builtin_ctzll(m0)];
+            m0 &= m0 - 1;
+        }
+        while (m1) {
+            c ^= tab.qcls[64 + __builtin_ctzll(m1)];
+            m1 &= m1 - 1;
+        }
+        c &= (1u << sc.eparts_log2) - 1u;
+        const uint32_t emask = (1u << sc.efilter_log2) - 1u;
+        atomicOr(&sc.efilter[(c << sc.efilter_log2) + filter_word(h, emask)], fbits);
+    }
+    uint32_t slot = slot_of(h, sc.slot_shift) << bucket_log2(W);
+    for (uint32_t probe = 0; probe <= sc.slot_mask; ++probe) {
+        const int32_t old = atomicCAS(&sc.sidx[slot], -1, static_cast<int32_t>(i));
+        if (old == -1) {
+            sc.skey[static_cast<size_t>(slot) * W] = w0;
+            if constexpr (W == 2) sc.skey[static_cast<size_t>(slot) * W + 1] = w1;
+            sc.sfp[slot] = h | 1u;
+            return;
+        }
+        bool same = samples[2 * old] == w0;
+        if constexpr (W == 2) same = same && samples[2 * old + 1] == w1;
+        if (same) {
+            latch(sc.err, NQS_E_DUPLICATE);
+            return;
+        }
+        slot = (slot + 1) & sc.slot_mask;
+    }
+}
 
 }  // namespace nqs

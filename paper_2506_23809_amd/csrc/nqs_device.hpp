@@ -282,14 +282,18 @@ size_t join_scratch_bytes(const DevTable &tab, int64_t n, int log2m);
 int join_log2m_for(int64_t n);
 // Lay the join scratch out from base (256-byte aligned pieces).
 void join_scratch_layout(const DevTable &tab, int64_t n, int log2m, char *base, DevScratch *sc);
-// The join's grouping (counts, scan, decision, scatter, sort) between the
-// hash clear and the hash build, and its pair kernel.
+// The join's grouping (counts, scatter, sort, then the decision) between
+// the clear of its counters and the hash build, and its pair kernel; with
+// clear_hash the grouping's first kernel also frees the hash slots and
+// clears the Bloom bitmaps.
 hipError_t launch_join_prep(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
-                            int64_t n, int64_t g_eff, hipStream_t st);
+                            int64_t n, int64_t g_eff, bool clear_hash, hipStream_t st);
+// With build, the same launch also carries the sample-hash build (checks,
+// and the insertion when the join is not chosen) in blocks of its own.
 hipError_t launch_join_pairs(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
-                             const double *log_amp, const double *phase, int64_t n, int precision,
-                             int32_t *hit_idx, uint32_t *sign_bits, int64_t sign_words,
-                             hipStream_t st);
+                             const int64_t *weights, bool build, const double *log_amp,
+                             const double *phase, int64_t n, int precision, int32_t *hit_idx,
+                             uint32_t *sign_bits, int64_t sign_words, hipStream_t st);
 
 constexpr int kStrategyAuto = 0, kStrategyStream = 1, kStrategyEnum = 2, kStrategyJoin = 3;
 
@@ -315,12 +319,15 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
                        const uint64_t *samples, const int64_t *weights, int64_t n,
                        hipStream_t st, hipEvent_t after_grouping = nullptr);
 hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
-                       const uint64_t *samples, const double *log_amp, const double *phase,
-                       double *eloc, int precision, int32_t *hit_idx, uint32_t *sign_bits,
-                       int64_t sign_words, EvalStageEvents ev, hipStream_t st);
+                       const uint64_t *samples, const int64_t *weights, const double *log_amp,
+                       const double *phase, double *eloc, int precision, int32_t *hit_idx,
+                       uint32_t *sign_bits, int64_t sign_words, EvalStageEvents ev,
+                       hipStream_t st);
+// Eq. 1: per-block partials, then one block combines them; out = {mean re,
+// mean im, variance, sum w}.
 hipError_t launch_energy(const int64_t *w, const double *e, int64_t n, double *part,
-                         double *result, double *out, hipStream_t st);
-constexpr int kEnergyPartDoubles = 4 * 256;  // pass-1 (3 per block), then pass-2 partials
+                         double *out, hipStream_t st);
+constexpr int kEnergyPartDoubles = 4 * 256;  // (sum w, sum w Re E, sum w Im E, M2) per block
 constexpr int kCounters = 8;
 // The counters are kept in kCounterSlots copies, one 64-byte line each; a
 // block adds to copy (blockIdx.x % kCounterSlots), so the device's atomics

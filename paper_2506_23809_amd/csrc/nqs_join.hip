@@ -46,7 +46,7 @@ namespace nqs {
 
 namespace {
 
-constexpr int kJoinGroupThreads = 1024;  // tile kernels, sorter, decision
+constexpr int kJoinGroupThreads = 1024;  // tile kernels
 constexpr int kJoinPairThreads = 256;
 constexpr int kJoinSortThreads = 512;
 // Largest bucket ranked by a pass over its members; a partition with a
@@ -157,6 +157,28 @@ template <int W>
 __global__ __launch_bounds__(kJoinGroupThreads) void join_hist_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n) {
     __shared__ uint32_t hist[kJoinMaxParts];
+    if (blockIdx.x >= static_cast<unsigned>(sc.join_tiles)) {
+        // blocks beyond the tiles free the hash slots and clear the Bloom
+        // bitmaps that the hash build of this launch may fill
+        const uint32_t cap = sc.slot_mask + 1u;
+        const uint32_t fw = 1u << sc.filter_log2;
+        const uint32_t efw = sc.eparts_log2 > 0 ? 1u << (sc.eparts_log2 + sc.efilter_log2) : 0u;
+        uint32_t span = cap > fw ? cap : fw;
+        span = span > efw ? span : efw;
+        const uint32_t stride = (gridDim.x - static_cast<unsigned>(sc.join_tiles)) * blockDim.x;
+        for (uint32_t s = (blockIdx.x - static_cast<unsigned>(sc.join_tiles)) * blockDim.x +
+                          threadIdx.x;
+             s < span; s += stride) {
+            if (s < cap) {
+                sc.sidx[s] = -1;
+                sc.sfp[s] = 0u;
+                sc.skey[static_cast<size_t>(s) * W + W - 1] = kFreeKey;
+            }
+            if (s < fw) sc.filter[s] = 0u;
+            if (s < efw) sc.efilter[s] = 0u;
+        }
+        return;
+    }
     const int parts = sc.join_parts, lshift = sc.join_lshift, log2m = sc.join_log2m;
     for (int p = threadIdx.x; p < parts; p += blockDim.x) hist[p] = 0u;
     __syncthreads();
@@ -233,32 +255,15 @@ __global__ __launch_bounds__(kJoinGroupThreads) void join_place_kernel(DevTable 
     }
 }
 
-// One block per partition: its entries ordered by (bucket, sample) and
-// written back, each with its bucket's range and block and its bit string;
-// the partition's sum of squared bucket sizes and largest bucket.  A
-// counting sort by bucket (LDS counts, their scan, then each entry at its
-// bucket's start plus a second atomic count) groups the buckets; an
-// entry's place inside its bucket is then the number of members with a
-// smaller sample index (a pass over the bucket, as long as the pair
-// kernel's).  LDS holds 4 bytes per entry (bucket << 21 | sample), so that
-// several blocks share a CU.  A partition of more than kJoinPartCap entries
-// is only flagged (the join then does not run).
-__global__ __launch_bounds__(kJoinSortThreads) void join_sort_kernel(
-    DevScratch sc, const uint64_t *__restrict__ samples) {
+// One partition (c entries, at most kJoinPartCap) ordered by (bucket,
+// sample); thread 0 writes its statistics.
+__device__ __forceinline__ void join_sort_partition(const DevScratch &sc,
+                                                    const uint64_t *__restrict__ samples, int p,
+                                                    uint32_t c) {
     __shared__ uint32_t buf[kJoinPartCap];
     __shared__ uint32_t cnt[kJoinMaxLocal];
     __shared__ uint32_t fill[kJoinMaxLocal];
-    const int p = blockIdx.x;
-    const uint32_t c = sc.jcnt[p];
     const uint32_t s0 = sc.jpoff[p];
-    if (c > static_cast<uint32_t>(kJoinPartCap)) {
-        if (threadIdx.x == 0) {
-            sc.jstat[2 * p] = static_cast<unsigned long long>(c) * c;
-            sc.jstat[2 * p + 1] = c;
-            sc.jctl[kJoinCtlOver] = 1ull;
-        }
-        return;
-    }
     const int L = 1 << sc.join_lshift;
     for (int u = threadIdx.x; u < L; u += blockDim.x) {
         cnt[u] = 0u;
@@ -350,10 +355,11 @@ __global__ __launch_bounds__(kJoinSortThreads) void join_sort_kernel(
     }
 }
 
-// One block: the join's cost and largest bucket over the partitions, and
-// the decision.
-__global__ __launch_bounds__(kJoinGroupThreads) void join_decide_kernel(
-    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n, int64_t g_eff) {
+// The join's cost and largest bucket over the partitions, and the decision
+// (by one whole block).
+__device__ __forceinline__ void join_decide(const DevTable &tab, const DevScratch &sc,
+                                            const uint64_t *__restrict__ samples, int64_t n,
+                                            int64_t g_eff) {
     unsigned long long q = 0, m = 0;
     for (int p = threadIdx.x; p < sc.join_parts; p += blockDim.x) {
         q += sc.jstat[2 * p];
@@ -393,6 +399,40 @@ __global__ __launch_bounds__(kJoinGroupThreads) void join_decide_kernel(
     sc.jctl[kJoinCtlCost] = q;
     sc.jctl[kJoinCtlMax] = m;
     sc.jctl[kJoinCtlChosen] = chosen ? 1ull : 0ull;
+}
+
+// One block per partition: its entries ordered by (bucket, sample) and
+// written back, each with its bucket's range and block and its bit string;
+// the partition's sum of squared bucket sizes and largest bucket.  A
+// counting sort by bucket (LDS counts, their scan, then each entry at its
+// bucket's start plus a second atomic count) groups the buckets; an
+// entry's place inside its bucket is then the number of members with a
+// smaller sample index (a pass over the bucket, as long as the pair
+// kernel's).  LDS holds 4 bytes per entry (bucket << 21 | sample), so that
+// several blocks share a CU.  A partition of more than kJoinPartCap entries
+// is only flagged (the join then does not run).
+__global__ __launch_bounds__(kJoinSortThreads) void join_sort_kernel(
+    DevScratch sc, const uint64_t *__restrict__ samples) {
+    const int p = blockIdx.x;
+    const uint32_t c = sc.jcnt[p];
+    if (c > static_cast<uint32_t>(kJoinPartCap)) {
+        if (threadIdx.x == 0) {
+            sc.jstat[2 * p] = static_cast<unsigned long long>(c) * c;
+            sc.jstat[2 * p + 1] = c;
+            sc.jctl[kJoinCtlOver] = 1ull;
+        }
+        return;
+    }
+    join_sort_partition(sc, samples, p, c);
+}
+
+// One block: the decision, once every partition is sorted.  (Taking it in
+// the sort kernel's last block would need a device-scope release fence in
+// every block, which writes back the L2 of each XCD: far slower than a
+// launch.)
+__global__ __launch_bounds__(kJoinGroupThreads) void join_decide_kernel(
+    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n, int64_t g_eff) {
+    join_decide(tab, sc, samples, n, g_eff);
 }
 
 // The contribution of partner j (bit string y = x ^ d) to E_loc(x), or no
@@ -440,15 +480,23 @@ __device__ __forceinline__ bool join_hit(const DevTable &tab, const Key<W> &x, c
 }
 
 // One lane per entry (block b, sample i): the partners of i in its bucket,
-// in index order; its partial sum goes to part[b][i] when it has a hit (the
-// hash build kernel has cleared the partials).
+// in index order; its partial sum (zero without a hit) goes to part[b][i].
+// The first build_blocks blocks are the sample-hash build of the same
+// launch instead (its checks always; its insertion when the join is not
+// chosen): both need only the decision, so one launch carries both.
 template <int W, bool DUMP, int P, bool SCV>
 __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
-    const double *__restrict__ log_amp, const double *__restrict__ phase, int64_t n,
+    const int64_t *__restrict__ weights, const double *__restrict__ log_amp,
+    const double *__restrict__ phase, int64_t n, unsigned build_blocks,
     int32_t *__restrict__ hit_idx, uint32_t *__restrict__ sign_bits, int64_t sign_words) {
+    if (blockIdx.x < build_blocks) {
+        const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+        if (i < n) hash_build_one<W>(tab, sc, samples, weights, i);
+        return;
+    }
     if (!join_chosen(sc)) return;
-    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t p = static_cast<int64_t>(blockIdx.x - build_blocks) * blockDim.x + threadIdx.x;
     const unsigned long long *__restrict__ ent = sc.jent;
     const int maxf = tab.max_flip;
     unsigned long long n_cand = 0, n_probe = 0, n_hit = 0, n_term = 0;
@@ -457,18 +505,16 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
         const unsigned long long r = sc.jrange[p];
         const uint32_t bs = static_cast<uint32_t>(r), m = static_cast<uint32_t>(r >> 32) & 0xFFFFu;
         const int b = static_cast<int>(r >> 48);
-        // the partials start at zero (the hash build kernel of this launch
-        // clears them): a sample alone in its bucket, or without a hit, has
-        // nothing to write
         double *out = sc.part + 2 * (static_cast<int64_t>(b) * n + i);
+        double2 sum = make_double2(0.0, 0.0);
         if (m >= 2) {
             const Key<W> x = load_key<W>(sc.jkeys, p);
             double re = 0.0, im = 0.0, la = 0.0, ph = 0.0;
             bool have_psi = false;
             AccF32 ar, ai;
-            for (uint32_t q = bs; q < bs + m; ++q) {
-                if (q == static_cast<uint32_t>(p)) continue;
-                const Key<W> y = load_key<W>(sc.jkeys, q);
+            // one candidate: distance, first agreeing block, then the hit
+            auto visit = [&](uint32_t q, const Key<W> &y) {
+                if (q == static_cast<uint32_t>(p)) return;
                 Key<W> d;
                 int pop = 0;
 #pragma unroll
@@ -476,7 +522,7 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
                     d.w[w] = x.w[w] ^ y.w[w];
                     pop += __popcll(d.w[w]);
                 }
-                if (pop > maxf) continue;
+                if (pop > maxf) return;
                 // the first block on which x and y agree must be this one
                 int first = tab.join_blocks;
 #pragma unroll
@@ -487,10 +533,10 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
                         if (v == 0ull) first = cb;
                     }
                 }
-                if (first != b) continue;
+                if (first != b) return;
                 if (pop == 0) {
                     latch(sc.err, NQS_E_DUPLICATE);
-                    continue;
+                    return;
                 }
                 const int32_t j = static_cast<int32_t>(static_cast<uint32_t>(ent[q]));
                 ++n_probe;
@@ -502,18 +548,33 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
                 if (join_hit<W, DUMP, P, SCV>(tab, x, y, d, i, j, la, ph, log_amp, phase, hit_idx,
                                               sign_bits, sign_words, &n_term, re, im, ar, ai))
                     ++n_hit;
+            };
+            // partners in index order; one-word bit strings four at a time
+            // (large buckets wait on these loads; two-word strings would
+            // cost the kernel a wave per SIMD in registers)
+            uint32_t q = bs;
+            if constexpr (W == 1) {
+                for (; q + 4 <= bs + m; q += 4) {
+                    const Key<W> y0 = load_key<W>(sc.jkeys, q), y1 = load_key<W>(sc.jkeys, q + 1);
+                    const Key<W> y2 = load_key<W>(sc.jkeys, q + 2),
+                                 y3 = load_key<W>(sc.jkeys, q + 3);
+                    visit(q, y0);
+                    visit(q + 1, y1);
+                    visit(q + 2, y2);
+                    visit(q + 3, y3);
+                }
             }
+            for (; q < bs + m; ++q) visit(q, load_key<W>(sc.jkeys, q));
             n_cand = m - 1;
             if (n_hit) {
                 if constexpr (P == NQS_FP64) {
-                    out[0] = re;
-                    out[1] = im;
+                    sum = make_double2(re, im);
                 } else {
-                    out[0] = ar.value();
-                    out[1] = ai.value();
+                    sum = make_double2(ar.value(), ai.value());
                 }
             }
         }
+        *reinterpret_cast<double2 *>(out) = sum;
     }
     // one set of counter atomics per block
     __shared__ unsigned long long cnt[4][kJoinPairThreads / 64];
@@ -539,10 +600,22 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
 
 template <int W>
 hipError_t launch_join_prep_w(const DevTable &tab, const DevScratch &sc,
-                              const uint64_t *samples, int64_t n, int64_t g_eff, hipStream_t st) {
+                              const uint64_t *samples, int64_t n, int64_t g_eff, bool clear_hash,
+                              hipStream_t st) {
     const dim3 tiles(static_cast<unsigned>(sc.join_tiles));
     const dim3 blk(kJoinGroupThreads);
-    hipLaunchKernelGGL(join_hist_kernel<W>, tiles, blk, 0, st, tab, sc, samples, n);
+    // the hash clear rides along: four slots a thread in the blocks after
+    // the tiles
+    unsigned extra = 0;
+    if (clear_hash) {
+        const uint64_t cap = uint64_t(sc.slot_mask) + 1u, fw = uint64_t(1) << sc.filter_log2;
+        const uint64_t efw = sc.eparts_log2 > 0 ? uint64_t(1) << (sc.eparts_log2 + sc.efilter_log2)
+                                                : 0u;
+        uint64_t span = cap > fw ? cap : fw;
+        span = span > efw ? span : efw;
+        extra = static_cast<unsigned>((span + 4 * kJoinGroupThreads - 1) / (4 * kJoinGroupThreads));
+    }
+    hipLaunchKernelGGL(join_hist_kernel<W>, dim3(tiles.x + extra), blk, 0, st, tab, sc, samples, n);
     hipLaunchKernelGGL(join_place_kernel, tiles, blk, 0, st, tab, sc, n);
     hipLaunchKernelGGL(join_sort_kernel, dim3(static_cast<unsigned>(sc.join_parts)),
                        dim3(kJoinSortThreads), 0, st, sc, samples);
@@ -552,13 +625,17 @@ hipError_t launch_join_prep_w(const DevTable &tab, const DevScratch &sc,
 
 template <int W, bool D, int P, bool SCV>
 hipError_t launch_pairs_w(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
-                          const double *log_amp, const double *phase, int64_t n,
-                          int32_t *hit_idx, uint32_t *sign_bits, int64_t sign_words,
-                          hipStream_t st) {
+                          const int64_t *weights, bool build, const double *log_amp,
+                          const double *phase, int64_t n, int32_t *hit_idx, uint32_t *sign_bits,
+                          int64_t sign_words, hipStream_t st) {
     const int64_t entries = static_cast<int64_t>(tab.join_blocks) * n;
-    const dim3 grid(static_cast<unsigned>((entries + kJoinPairThreads - 1) / kJoinPairThreads));
+    const unsigned build_blocks =
+        build ? static_cast<unsigned>((n + kJoinPairThreads - 1) / kJoinPairThreads) : 0u;
+    const dim3 grid(build_blocks +
+                    static_cast<unsigned>((entries + kJoinPairThreads - 1) / kJoinPairThreads));
     hipLaunchKernelGGL((join_pair_kernel<W, D, P, SCV>), grid, dim3(kJoinPairThreads), 0, st, tab,
-                       sc, samples, log_amp, phase, n, hit_idx, sign_bits, sign_words);
+                       sc, samples, weights, log_amp, phase, n, build_blocks, hit_idx, sign_bits,
+                       sign_words);
     return hipGetLastError();
 }
 
@@ -648,21 +725,22 @@ void join_scratch_layout(const DevTable &tab, int64_t n, int log2m, char *base, 
 }
 
 hipError_t launch_join_prep(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
-                            int64_t n, int64_t g_eff, hipStream_t st) {
-    if (tab.n_qubits <= 63) return launch_join_prep_w<1>(tab, sc, samples, n, g_eff, st);
-    return launch_join_prep_w<2>(tab, sc, samples, n, g_eff, st);
+                            int64_t n, int64_t g_eff, bool clear_hash, hipStream_t st) {
+    if (tab.n_qubits <= 63)
+        return launch_join_prep_w<1>(tab, sc, samples, n, g_eff, clear_hash, st);
+    return launch_join_prep_w<2>(tab, sc, samples, n, g_eff, clear_hash, st);
 }
 
 hipError_t launch_join_pairs(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
-                             const double *log_amp, const double *phase, int64_t n, int precision,
-                             int32_t *hit_idx, uint32_t *sign_bits, int64_t sign_words,
-                             hipStream_t st) {
+                             const int64_t *weights, bool build, const double *log_amp,
+                             const double *phase, int64_t n, int precision, int32_t *hit_idx,
+                             uint32_t *sign_bits, int64_t sign_words, hipStream_t st) {
     const bool dump = hit_idx || sign_bits;
     const bool f32 = precision == NQS_FP32_KAHAN && !dump && !tab.sc;
     const bool w1 = tab.n_qubits <= 63;
 #define NQS_PAIRS(Wd, D, Pr, SCI) \
-    return launch_pairs_w<Wd, D, Pr, SCI>(tab, sc, samples, log_amp, phase, n, hit_idx, sign_bits, \
-                                          sign_words, st)
+    return launch_pairs_w<Wd, D, Pr, SCI>(tab, sc, samples, weights, build, log_amp, phase, n, \
+                                          hit_idx, sign_bits, sign_words, st)
     if (tab.sc) {
         if (w1) {
             if (dump) NQS_PAIRS(1, true, NQS_FP64, true);

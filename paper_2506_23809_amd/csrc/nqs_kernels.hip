@@ -61,87 +61,6 @@ __global__ void hash_clear_kernel(uint64_t *__restrict__ skey, int32_t *__restri
     if (s < efilter_words) efilter[s] = 0u;
 }
 
-// One thread per sample: range check, sector uniformity, counts >= 0, linear
-// hash, Bloom bit, and insertion by CAS on the slot index.  A duplicate key
-// is found by comparing against the sample that owns the slot.
-template <int W>
-__device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScratch &sc,
-                                               const uint64_t *__restrict__ samples,
-                                               const int64_t *__restrict__ weights, int64_t i) {
-    const uint64_t w0 = samples[2 * i], w1 = samples[2 * i + 1];
-    bool bad;
-    const int nq = tab.n_qubits;
-    if (nq >= 64) {
-        bad = (nq - 64 < 64) && ((w1 >> (nq - 64)) != 0);
-    } else {
-        bad = ((w0 >> nq) != 0) || (w1 != 0);
-    }
-    if (bad) latch(sc.err, NQS_E_RANGE);
-    if (weights && weights[i] < 0) latch(sc.err, NQS_E_RANGE);
-    if (tab.sector_filter) {
-        const uint64_t s0 = samples[0], s1 = samples[1];
-        const int na = __popcll(w0 & tab.spin_a0) + __popcll(w1 & tab.spin_a1);
-        const int nb = __popcll(w0 & tab.spin_b0) + __popcll(w1 & tab.spin_b1);
-        const int ra = __popcll(s0 & tab.spin_a0) + __popcll(s1 & tab.spin_a1);
-        const int rb = __popcll(s0 & tab.spin_b0) + __popcll(s1 & tab.spin_b1);
-        if (na != ra || nb != rb) atomicOr(sc.mixed, 1);
-    }
-    // the pair join, when it runs, needs neither the hash nor the filters;
-    // it writes only the partials of samples with hits, so the others start
-    // at zero here (coalesced by sample)
-    if (join_chosen(sc)) {
-        for (int b = 0; b < tab.join_blocks; ++b) {
-            double *p = sc.part + 2 * (static_cast<int64_t>(b) * sc.join_n + i);
-            p[0] = 0.0;
-            p[1] = 0.0;
-        }
-        return;
-    }
-    if (bad) return;
-    Key<W> k;
-    k.w[0] = w0;
-    if constexpr (W == 2) k.w[1] = w1;
-    const uint32_t h = linear_hash<W>(k, tab.hr);
-    sc.shx[i] = h;
-    const uint32_t fmask = (1u << sc.filter_log2) - 1u;
-    const uint32_t fbits = filter_bits(h);
-    atomicOr(&sc.filter[filter_word(h, fmask)], fbits);
-    if (sc.eparts_log2 > 0) {
-        // the partition of the enumeration filter: class of x, the XOR of
-        // the classes of its occupied beta qubits
-        uint32_t c = 0;
-        uint64_t m0 = w0 & tab.spin_b0, m1 = w1 & tab.spin_b1;
-        while (m0) {
-            c ^= tab.qcls[__builtin_ctzll(m0)];
-            m0 &= m0 - 1;
-        }
-        while (m1) {
-            c ^= tab.qcls[64 + __builtin_ctzll(m1)];
-            m1 &= m1 - 1;
-        }
-        c &= (1u << sc.eparts_log2) - 1u;
-        const uint32_t emask = (1u << sc.efilter_log2) - 1u;
-        atomicOr(&sc.efilter[(c << sc.efilter_log2) + filter_word(h, emask)], fbits);
-    }
-    uint32_t slot = slot_of(h, sc.slot_shift) << bucket_log2(W);
-    for (uint32_t probe = 0; probe <= sc.slot_mask; ++probe) {
-        const int32_t old = atomicCAS(&sc.sidx[slot], -1, static_cast<int32_t>(i));
-        if (old == -1) {
-            sc.skey[static_cast<size_t>(slot) * W] = w0;
-            if constexpr (W == 2) sc.skey[static_cast<size_t>(slot) * W + 1] = w1;
-            sc.sfp[slot] = h | 1u;
-            return;
-        }
-        bool same = samples[2 * old] == w0;
-        if constexpr (W == 2) same = same && samples[2 * old + 1] == w1;
-        if (same) {
-            latch(sc.err, NQS_E_DUPLICATE);
-            return;
-        }
-        slot = (slot + 1) & sc.slot_mask;
-    }
-}
-
 template <int W>
 __global__ void hash_build_kernel(DevTable tab, DevScratch sc,
                                   const uint64_t *__restrict__ samples,
@@ -1735,7 +1654,7 @@ __device__ __forceinline__ void diag_mfma_tile(const diag_v4i *__restrict__ B, i
                                                const uint32_t (&mk)[H], int (&T)[H][kDiagLimbs]) {
     const diag_v4i zero = {0, 0, 0, 0};
     // the row masks as 0/1 multipliers (hidden from the optimiser, so that
-    // each masked add stays a 24-bit multiply and an add)
+    // each masked add stays a 24-bit multiply-add)
     int bit[H][4];
 #pragma unroll
     for (int h = 0; h < H; ++h) {
@@ -1756,7 +1675,12 @@ __device__ __forceinline__ void diag_mfma_tile(const diag_v4i *__restrict__ B, i
             if constexpr (KB == 2)
                 acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[1], N[h][1], acc, 0, 0, 0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) T[h][l] = __mul24(acc[r], bit[h][r]) + T[h][l];
+            for (int r = 0; r < 4; ++r) {
+                T[h][l] = __mul24(acc[r], bit[h][r]) + T[h][l];
+                // one 24-bit multiply-add per value (not two products
+                // summed by a three-input add)
+                asm("" : "+v"(T[h][l]));
+            }
         }
     }
 }
@@ -1952,10 +1876,19 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
                 if (hit_idx) hit_idx[i * tab.n_groups] = static_cast<int32_t>(i);
             }
         }
-        for (int64_t c = 0; c < n_chunks; ++c) {
-            const double *p = sc.part + 2 * (c * n + i);
-            re += p[0];
-            im += p[1];
+        // the partials in chunk order, eight loads in flight at a time
+        for (int64_t c0 = 0; c0 < n_chunks; c0 += 8) {
+            double2 v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (c0 + k < n_chunks)
+                    v[k] = *reinterpret_cast<const double2 *>(sc.part + 2 * ((c0 + k) * n + i));
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (c0 + k < n_chunks) {
+                    re += v[k].x;
+                    im += v[k].y;
+                }
         }
         eloc[2 * i] = re;
         eloc[2 * i + 1] = im;
@@ -2319,7 +2252,8 @@ hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_ite
         const JobDesc &J = h_jobs[k];
         if (!J.sc.jctl || J.n == 0) continue;
         const hipError_t e = launch_join_prep(J.tab, J.sc, J.samples, J.n,
-                                              J.tab.n_groups - (J.tab.has_diagonal ? 1 : 0), st);
+                                              J.tab.n_groups - (J.tab.has_diagonal ? 1 : 0),
+                                              false, st);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(batch_build_kernel,
@@ -2351,8 +2285,8 @@ hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_ite
         const JobDesc &J = h_jobs[k];
         if (!J.sc.jctl || J.n == 0) continue;
         const int pr = (J.kind & kJobIntegrals) ? NQS_FP64 : precision;
-        const hipError_t e = launch_join_pairs(J.tab, J.sc, J.samples, J.log_amp, J.phase, J.n, pr,
-                                               nullptr, nullptr, 0, st);
+        const hipError_t e = launch_join_pairs(J.tab, J.sc, J.samples, J.weights, false, J.log_amp,
+                                               J.phase, J.n, pr, nullptr, nullptr, 0, st);
         if (e != hipSuccess) return e;
     }
     const int ne = shape.enum_begin[kEnumVariants];
@@ -2392,14 +2326,24 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
     return r;
 }
 
-// Pass 1: per-block sum w, sum w Re E, sum w Im E over a fixed strided set.
-__global__ __launch_bounds__(kRedThreads) void energy_pass1_kernel(
+// Eq. 1 in two launches.  Each block of the first takes a fixed strided set
+// of samples: its sums W_b = sum w, sum w Re E, sum w Im E, its own mean m_b
+// and M2_b = sum w |E - m_b|^2 about that mean (a second pass over the same
+// samples, still in cache).  One block then combines the block partials in
+// block order: the mean from the sums, and
+//   sum_i w_i |E_i - mean|^2 = sum_b (M2_b + W_b |m_b - mean|^2),
+// exact because each block's weighted deviations from its own mean sum to
+// zero.  (Combining them in the first launch's last block would need a
+// device-scope release fence in every block, which costs more than the
+// launch on a chip of several L2s.)
+__global__ __launch_bounds__(kRedThreads) void energy_block_kernel(
     const int64_t *__restrict__ w, const double *__restrict__ e, int64_t n,
     double *__restrict__ part) {
     __shared__ double lds[kRedThreads];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kRedThreads + threadIdx.x;
+    const int64_t step = static_cast<int64_t>(gridDim.x) * kRedThreads;
     double sw = 0.0, sr = 0.0, si = 0.0;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRedThreads + threadIdx.x; i < n;
-         i += static_cast<int64_t>(gridDim.x) * kRedThreads) {
+    for (int64_t i = i0; i < n; i += step) {
         const double wi = static_cast<double>(w[i]);
         sw += wi;
         sr += wi * e[2 * i];
@@ -2408,70 +2352,44 @@ __global__ __launch_bounds__(kRedThreads) void energy_pass1_kernel(
     sw = block_sum(sw, lds);
     sr = block_sum(sr, lds);
     si = block_sum(si, lds);
-    if (threadIdx.x == 0) {
-        part[3 * blockIdx.x] = sw;
-        part[3 * blockIdx.x + 1] = sr;
-        part[3 * blockIdx.x + 2] = si;
-    }
-}
-
-// The pass-1 partials combined in block order (every block of pass 2 does
-// this the same way, to the same bits): sum w, mean re, mean im.
-__device__ __forceinline__ void energy_mean(const double *__restrict__ part1, int nparts,
-                                            double *lds, double &sw, double &mr, double &mi) {
-    double sr = 0.0, si = 0.0;
-    sw = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += kRedThreads) {
-        sw += part1[3 * b];
-        sr += part1[3 * b + 1];
-        si += part1[3 * b + 2];
-    }
-    sw = block_sum(sw, lds);
-    sr = block_sum(sr, lds);
-    si = block_sum(si, lds);
-    mr = sw != 0.0 ? sr / sw : 0.0;
-    mi = sw != 0.0 ? si / sw : 0.0;
-}
-
-// Pass 2: the mean from the pass-1 partials (block 0 keeps it in result[0..2]
-// = sum w, mean re, mean im), then per-block sum w |E - mean|^2.
-__global__ __launch_bounds__(kRedThreads) void energy_pass2_kernel(
-    const int64_t *__restrict__ w, const double *__restrict__ e, int64_t n,
-    const double *__restrict__ part1, int nparts, double *__restrict__ result,
-    double *__restrict__ part) {
-    __shared__ double lds[kRedThreads];
-    double sw, mr, mi;
-    energy_mean(part1, nparts, lds, sw, mr, mi);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        result[0] = sw;
-        result[1] = mr;
-        result[2] = mi;
-    }
+    const double mr = sw != 0.0 ? sr / sw : 0.0, mi = sw != 0.0 ? si / sw : 0.0;
     double sv = 0.0;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRedThreads + threadIdx.x; i < n;
-         i += static_cast<int64_t>(gridDim.x) * kRedThreads) {
+    for (int64_t i = i0; i < n; i += step) {
         const double dr = e[2 * i] - mr, di = e[2 * i + 1] - mi;
         sv += static_cast<double>(w[i]) * (dr * dr + di * di);
     }
     sv = block_sum(sv, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = sv;
+    if (threadIdx.x == 0) {
+        double *pb = part + 4 * blockIdx.x;
+        pb[0] = sw;
+        pb[1] = sr;
+        pb[2] = si;
+        pb[3] = sv;
+    }
 }
 
-// Single block: out = {mean re, mean im, var, sum w}.
-__global__ __launch_bounds__(kRedThreads) void energy_var_kernel(const double *__restrict__ part,
-                                                                 int nparts,
-                                                                 const double *__restrict__ result,
-                                                                 double *__restrict__ out) {
+// Single block: out = {mean re, mean im, variance, sum w} from the nb block
+// partials (one a thread; nb <= kRedThreads).
+__global__ __launch_bounds__(kRedThreads) void energy_combine_kernel(
+    const double *__restrict__ part, int nb, double *__restrict__ out) {
     __shared__ double lds[kRedThreads];
-    double sv = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += kRedThreads) sv += part[b];
-    sv = block_sum(sv, lds);
+    const int b = threadIdx.x;
+    const bool have = b < nb;
+    const double bw = have ? part[4 * b] : 0.0, br = have ? part[4 * b + 1] : 0.0;
+    const double bi = have ? part[4 * b + 2] : 0.0, bv = have ? part[4 * b + 3] : 0.0;
+    const double SW = block_sum(bw, lds), SR = block_sum(br, lds), SI = block_sum(bi, lds);
+    const double MR = SW != 0.0 ? SR / SW : 0.0, MI = SW != 0.0 ? SI / SW : 0.0;
+    double c = bv;
+    if (bw != 0.0) {
+        const double ur = br / bw - MR, ui = bi / bw - MI;
+        c += bw * (ur * ur + ui * ui);
+    }
+    const double SV = block_sum(c, lds);
     if (threadIdx.x == 0) {
-        const double sw = result[0];
-        out[0] = result[1];
-        out[1] = result[2];
-        out[2] = sw != 0.0 ? sv / sw : 0.0;
-        out[3] = sw;
+        out[0] = MR;
+        out[1] = MI;
+        out[2] = SW != 0.0 ? SV / SW : 0.0;
+        out[3] = SW;
     }
 }
 
@@ -2557,28 +2475,37 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
                        const uint64_t *samples, const int64_t *weights, int64_t n,
                        hipStream_t st, hipEvent_t after_grouping) {
     const int words = tab.n_qubits <= 63 ? 1 : 2;
-    const uint32_t fwords = 1u << sc.filter_log2;
-    const uint32_t efwords = sc.eparts_log2 > 0 ? (1u << (sc.eparts_log2 + sc.efilter_log2)) : 0u;
-    const uint32_t jparts = sc.jctl ? static_cast<uint32_t>(sc.join_parts) : 0u;
-    uint32_t span = capacity > fwords ? capacity : fwords;
+    // with the pair join launched, its histogram kernel frees the hash slots
+    // and clears the bitmaps in blocks of its own (the grouping does not use
+    // them); this kernel then clears only the counters and control words
+    const bool join = sc.jctl != nullptr;
+    const uint32_t cap = join ? 0u : capacity;
+    const uint32_t fwords = join ? 0u : 1u << sc.filter_log2;
+    const uint32_t efwords =
+        (join || sc.eparts_log2 <= 0) ? 0u : (1u << (sc.eparts_log2 + sc.efilter_log2));
+    const uint32_t jparts = join ? static_cast<uint32_t>(sc.join_parts) : 0u;
+    uint32_t span = cap > fwords ? cap : fwords;
     span = span > efwords ? span : efwords;
     span = span > jparts ? span : jparts;
     const uint32_t n_counters = static_cast<uint32_t>(kCounters * kCounterSlots);
     span = span > n_counters ? span : n_counters;
+    span = span > static_cast<uint32_t>(kJoinCtl) ? span : static_cast<uint32_t>(kJoinCtl);
     hipLaunchKernelGGL(hash_clear_kernel, dim3((span + 255) / 256), dim3(256), 0, st, sc.skey,
-                       sc.sidx, sc.sfp, words, capacity, sc.filter, fwords, sc.efilter, efwords,
+                       sc.sidx, sc.sfp, words, cap, sc.filter, fwords, sc.efilter, efwords,
                        sc.counters, sc.mixed, sc.jcnt, jparts, sc.jctl);
-    if (sc.jctl) {
+    if (join) {
         // the pair join's grouping and decision come before the build, which
         // skips its insertion when the join runs
         const hipError_t e = launch_join_prep(tab, sc, samples, n,
-                                              tab.n_groups - (tab.has_diagonal ? 1 : 0), st);
+                                              tab.n_groups - (tab.has_diagonal ? 1 : 0), true, st);
         if (e != hipSuccess) return e;
     }
     if (after_grouping) {
         const hipError_t e = hipEventRecord(after_grouping, st);
         if (e != hipSuccess) return e;
     }
+    // with the join launched the build runs inside its pair kernel's launch
+    if (join) return hipGetLastError();
     const dim3 grid(static_cast<unsigned>((n + 255) / 256));
     if (words == 1)
         hipLaunchKernelGGL(hash_build_kernel<1>, grid, dim3(256), 0, st, tab, sc, samples, weights, n);
@@ -2640,9 +2567,10 @@ hipError_t allow_finish_lds() {
 }
 
 hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
-                       const uint64_t *samples, const double *log_amp, const double *phase,
-                       double *eloc, int precision, int32_t *hit_idx, uint32_t *sign_bits,
-                       int64_t sign_words, EvalStageEvents ev, hipStream_t st) {
+                       const uint64_t *samples, const int64_t *weights, const double *log_amp,
+                       const double *phase, double *eloc, int precision, int32_t *hit_idx,
+                       uint32_t *sign_bits, int64_t sign_words, EvalStageEvents ev,
+                       hipStream_t st) {
     const int words = tab.n_qubits <= 63 ? 1 : 2;
     const bool dump = hit_idx || sign_bits;
     const bool f32 = precision == NQS_FP32_KAHAN && !dump;
@@ -2659,8 +2587,9 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
             hipLaunchKernelGGL(fill_i32_kernel, dim3(static_cast<unsigned>((cnt + 255) / 256)),
                                dim3(256), 0, st, hit_idx, cnt, -1);
         }
-        e = launch_join_pairs(tab, sc, samples, log_amp, phase, n, precision, hit_idx, sign_bits,
-                              sign_words, st);
+        // the hash build rides in the same launch (launch_hash left it out)
+        e = launch_join_pairs(tab, sc, samples, weights, true, log_amp, phase, n, precision,
+                              hit_idx, sign_bits, sign_words, st);
         if (e != hipSuccess) return e;
     }
     if (ev.after_pairs) {
@@ -2802,18 +2731,15 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
 }
 
 hipError_t launch_energy(const int64_t *w, const double *e, int64_t n, double *part,
-                         double *result, double *out, hipStream_t st) {
+                         double *out, hipStream_t st) {
     int64_t blocks = (n + kRedThreads - 1) / kRedThreads;
     if (blocks > kRedBlocks) blocks = kRedBlocks;
     if (blocks < 1) blocks = 1;
-    // pass-1 partials, then (apart: pass 2 still reads those) pass-2 partials
-    double *part2 = part + 3 * kRedBlocks;
-    static_assert(4 * kRedBlocks <= kEnergyPartDoubles, "both partial sets fit");
-    hipLaunchKernelGGL(energy_pass1_kernel, dim3(blocks), dim3(kRedThreads), 0, st, w, e, n, part);
-    hipLaunchKernelGGL(energy_pass2_kernel, dim3(blocks), dim3(kRedThreads), 0, st, w, e, n,
-                       part, static_cast<int>(blocks), result, part2);
-    hipLaunchKernelGGL(energy_var_kernel, dim3(1), dim3(kRedThreads), 0, st, part2,
-                       static_cast<int>(blocks), result, out);
+    static_assert(4 * kRedBlocks <= kEnergyPartDoubles, "the block partials fit");
+    static_assert(kRedBlocks <= kRedThreads, "one partial set per thread of the combine");
+    hipLaunchKernelGGL(energy_block_kernel, dim3(blocks), dim3(kRedThreads), 0, st, w, e, n, part);
+    hipLaunchKernelGGL(energy_combine_kernel, dim3(1), dim3(kRedThreads), 0, st, part,
+                       static_cast<int>(blocks), out);
     return hipGetLastError();
 }
 
