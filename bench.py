@@ -2,8 +2,10 @@
 """Benchmark of the local-energy path on one MI355X.
 
 One step = one pass of the hot path over one batch already resident in HBM:
-sample-hash build + E_loc lookup kernel + finish kernel (nqs_eloc_eval) and
-the weighted energy/variance reduction (nqs_energy, which synchronises).  The
+E_loc (Eq. 5: the pair join's grouping and pair kernel, or the sample hash
+and the enumeration / streaming lookups, then the finish kernel) and the
+weighted energy and variance over it (Eq. 1), one nqs_eloc_energy call, which
+synchronises.  The
 Pauli table is built and uploaded once before the timed region (it is
 resident across VMC steps); its setup time is reported separately.
 
@@ -240,14 +242,14 @@ def main():
     def timed(precision):
         """Warm-up, then EXACTLY args.steps timed steps of one precision.
 
-        The timed steps call nqs_eloc_eval with the same arguments each time,
-        as a VMC loop does: after its first call the library replays the
-        evaluation as one captured HIP graph.  Then as many profiled steps
-        (eager launches, HIP events around every stage on the launch stream)
-        give the per-kernel durations and the eager step time."""
+        The timed steps call nqs_eloc_energy (E_loc, then Eq. 1 over it,
+        one launch sequence) with the same arguments each time, as a VMC loop
+        does: after its first calls the library replays the step as one
+        captured HIP graph.  Then as many profiled steps (eager launches, HIP
+        events around every stage on the launch stream) give the per-kernel
+        durations and the eager step time."""
         def step():
-            ham.eloc_into(out, S, la, ph, wt, precision=precision)
-            return nqs.energy(wt, out)
+            return ham.eloc_energy_into(out, S, la, ph, wt, precision=precision)
 
         for k in range(args.warmup):
             step()
@@ -259,7 +261,7 @@ def main():
         t0 = time.perf_counter()
         for k in range(args.steps):
             ts = time.perf_counter()
-            mean, var, sw = step()          # nqs_energy synchronises the stream
+            mean, var, sw = step()          # nqs_eloc_energy synchronises the stream
             per_step.append((time.perf_counter() - ts) * 1e3)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
@@ -466,15 +468,13 @@ def compare_enumeration(ham, out, S, la, ph, wt, args, log, pairs):
     import paper_2506_23809_amd as nqs
     ham.set_tuning(strategy="enum")
     for _ in range(args.warmup):
-        ham.eloc_into(out, S, la, ph, wt)
-        nqs.energy(wt, out)
+        ham.eloc_energy_into(out, S, la, ph, wt)
     ham.sync()
     ham.profile(True)
     per, kms = [], []
     for _ in range(args.steps):
         t0 = time.perf_counter()
-        ham.eloc_into(out, S, la, ph, wt)
-        nqs.energy(wt, out)
+        ham.eloc_energy_into(out, S, la, ph, wt)
         per.append((time.perf_counter() - t0) * 1e3)
         kms.append(ham.last_kernel_ms())
     ham.profile(False)
@@ -514,14 +514,12 @@ def secondary(args, log, dev):
         e = torch.empty((w.n_samples, 2), dtype=torch.float64, device=dev)
         steps = max(args.steps, 50) if name == "nq12" else args.steps
         for _ in range(args.warmup):
-            ham.eloc_into(e, S, la, ph, wt)
-            nqs.energy(wt, e)
+            ham.eloc_energy_into(e, S, la, ph, wt)
         ham.sync()
         per = []
         for _ in range(steps):
             t0 = time.perf_counter()
-            ham.eloc_into(e, S, la, ph, wt)
-            nqs.energy(wt, e)
+            ham.eloc_energy_into(e, S, la, ph, wt)
             per.append((time.perf_counter() - t0) * 1e3)
         ham.sync()
         st = ham.stats()

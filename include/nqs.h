@@ -227,6 +227,26 @@ int nqs_eloc_eval_noalloc(nqs_ham h, int64_t n, const uint64_t *samples, const i
 int nqs_energy(int64_t n, const int64_t *weights, const double *eloc, double out[4],
                void *hip_stream);
 
+/*
+ * One VMC step's evaluation: nqs_eloc_eval followed by Eq. 1 (§II-A) over
+ * its result, in one launch sequence (replayed as one graph when the same
+ * arguments repeat).  The finish kernel also writes each block's weighted
+ * sums and its deviations about the block's own mean; one block combines
+ * them in block order (M2_b + W_b |mean_b - E|^2 per block), so out[] is
+ * the same quantity as nqs_energy's, summed in another fixed order (equal
+ * to it within rounding; repeated calls give identical bits).
+ *   eloc: device [n][2] double, written as by nqs_eloc_eval;
+ *   out:  host [4] = {Re E, Im E, variance, sum w}, as nqs_energy.
+ * weights are required (device [n] int64).  Synchronises hip_stream before
+ * returning and reports the errors the device latched during this call
+ * (NQS_E_DUPLICATE, NQS_E_RANGE) as nqs_sync would.  Errors: those of
+ * nqs_eloc_eval and nqs_energy (NQS_E_ARG for n <= 0, null weights or out,
+ * sum w == 0).
+ */
+int nqs_eloc_energy(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weights,
+                    const double *log_amp, const double *phase, double *eloc, int precision,
+                    double out[4], void *hip_stream);
+
 /* Wait for hip_stream and return the first error latched by device work of
  * this handle since the previous nqs_sync (then clear it). */
 int nqs_sync(nqs_ham h, void *hip_stream);

@@ -38,7 +38,8 @@ _PRECISION = {"fp64": NQS_FP64, "fp32k": NQS_FP32_KAHAN, "fp32_kahan": NQS_FP32_
 # Every symbol include/nqs.h declares.
 EXPORTS = ("nqs_last_error", "nqs_version", "nqs_ham_create", "nqs_ham_create_integrals",
            "nqs_ham_info", "nqs_ham_destroy",
-           "nqs_table_host", "nqs_diag_tiles_host", "nqs_eloc_eval", "nqs_energy", "nqs_sync", "nqs_eval_stats",
+           "nqs_table_host", "nqs_diag_tiles_host", "nqs_eloc_eval", "nqs_energy",
+           "nqs_eloc_energy", "nqs_sync", "nqs_eval_stats",
            "nqs_eval_plan", "nqs_debug_fail_allocs", "nqs_eloc_eval_noalloc",
            "nqs_debug_dump", "nqs_profile", "nqs_last_kernel_ms", "nqs_last_stage_ms", "nqs_set_tuning",
            "nqs_get_tuning", "nqs_autotune", "nqs_batch_create", "nqs_batch_launch",
@@ -105,6 +106,7 @@ def load_library(path: str = LIB_PATH):
         "nqs_eloc_eval": (I, [P, I64, P, P, P, P, P, I, P]),
         "nqs_eloc_eval_noalloc": (I, [P, I64, P, P, P, P, P, I, P]),
         "nqs_energy": (I, [I64, P, P, P, P]),
+        "nqs_eloc_energy": (I, [P, I64, P, P, P, P, P, I, P, P]),
         "nqs_sync": (I, [P, P]),
         "nqs_eval_stats": (I, [P, P]),
         "nqs_eval_plan": (I, [P, P]),
@@ -297,6 +299,20 @@ class Hamiltonian:
             _dptr(phase, torch.float64), _dptr(out, torch.float64, 2), _PRECISION[precision],
             _stream(stream)))
         return out
+
+    def eloc_energy_into(self, out, samples, log_amp, phase, weights, precision="fp64",
+                         stream=None):
+        """nqs_eloc_energy: E_loc into out (float64 [n, 2]) and Eq. 1 over it
+        in one launch sequence; returns (mean complex, variance, sum_w) and
+        synchronises the stream."""
+        import torch
+        n = samples.shape[0]
+        res = (ctypes.c_double * 4)()
+        _check(load_library().nqs_eloc_energy(
+            self._h, n, _dptr(samples, torch.int64, 2), _dptr(weights, torch.int64),
+            _dptr(log_amp, torch.float64), _dptr(phase, torch.float64),
+            _dptr(out, torch.float64, 2), _PRECISION[precision], res, _stream(stream)))
+        return complex(res[0], res[1]), res[2], res[3]
 
     def eloc(self, samples, log_amp, phase, weights=None, precision="fp64", stream=None):
         """E_loc for a batch; returns a complex128 device tensor [n]."""

@@ -42,6 +42,11 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // counters (kCounterSlots copies), error latch, sector flag
 constexpr size_t kErrOffset = 8 * nqs::kCounters * nqs::kCounterSlots;
 constexpr size_t kSmallBytes = kErrOffset + 64;
+// nqs_eloc_energy's pinned host buffer: the error word, then out[4]
+constexpr size_t kEnergyHostSeq = 4;  // sequence number the host polls
+constexpr size_t kEnergyHostOut = 16;
+constexpr size_t kSeqOffset = kErrOffset + 8;  // the device's copy of it (in small)
+constexpr size_t kEnergyHostBytes = kEnergyHostOut + 4 * sizeof(double);
 constexpr size_t kMaxFilterWords = size_t(1) << 15;  // 128 KB Bloom bitmap
 constexpr size_t kMaxEFilterWords = kMaxFilterWords * nqs::kEnumMaxParts;
 constexpr int64_t kMaxGroups = int64_t(1) << 26;     // queue entries pack the group in 26 bits
@@ -71,6 +76,11 @@ struct nqs_ham_s {
     void *jmem = nullptr;  // the pair join's buckets and entries
     size_t jmem_bytes = 0;
     void *small = nullptr; // counters[8] u64, err, mixed
+    // nqs_eloc_energy: per-finish-block partials of Eq. 1 (device) and the
+    // pinned host buffer its last kernel writes {err, pad, out[4]} to
+    double *epart = nullptr;
+    int64_t epart_cap = 0;  // doubles
+    char *ehost = nullptr;
     // an error a server lane saw for one of this handle's requests, reported
     // by the next nqs_sync like a latched device error
     std::atomic<int> host_err{0};
@@ -297,6 +307,8 @@ struct EvalKey {
     int join, join_force, join_log2m;
     const void *slots, *shx, *part, *filter, *efilter, *small, *eblk, *jmem;
     uint32_t slot_cap;
+    int energy;
+    const void *epart, *ehost;
 };
 static_assert(sizeof(EvalKey) <= sizeof(nqs_ham_s::eval_key), "key fits");
 
@@ -304,7 +316,8 @@ static_assert(sizeof(EvalKey) <= sizeof(nqs_ham_s::eval_key), "key fits");
 hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunch &L, int64_t n,
                       const uint64_t *samples, const int64_t *weights, const double *log_amp,
                       const double *phase, double *eloc, int precision, int32_t *hit_idx,
-                      uint32_t *sign_bits, hipStream_t s, bool may_profile = true) {
+                      uint32_t *sign_bits, hipStream_t s, bool may_profile = true,
+                      bool energy = false) {
     hipError_t e;
     const bool prof = h->profiling && may_profile;
     if (prof && (e = hipEventRecord(h->ev[0], s)) != hipSuccess) return e;
@@ -315,8 +328,18 @@ hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunc
     const int64_t sign_words = (h->dt.n_terms + 31) / 32;
     nqs::EvalStageEvents stages{prof ? h->ev[2] : nullptr, prof ? h->ev[5] : nullptr,
                                 nullptr};
+    // with the energy, its combining kernel writes the result and the error
+    // word straight to the handle's pinned host buffer (no copy to wait for)
+    const nqs::EnergyFused ef =
+        energy ? nqs::EnergyFused{weights, h->epart,
+                                  reinterpret_cast<double *>(h->ehost + kEnergyHostOut),
+                                  reinterpret_cast<int *>(h->ehost),
+                                  reinterpret_cast<unsigned *>(static_cast<char *>(h->small) +
+                                                               kSeqOffset),
+                                  reinterpret_cast<unsigned *>(h->ehost + kEnergyHostSeq)}
+               : nqs::EnergyFused{weights, nullptr, nullptr, nullptr, nullptr, nullptr};
     if ((e = nqs::launch_eloc(h->dt, sc, L, samples, weights, log_amp, phase, eloc, precision,
-                              hit_idx, sign_bits, sign_words, stages, s)) != hipSuccess)
+                              hit_idx, sign_bits, sign_words, stages, ef, s)) != hipSuccess)
         return e;
     if (prof && (e = hipEventRecord(h->ev[3], s)) != hipSuccess) return e;
     return hipSuccess;
@@ -327,14 +350,15 @@ hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunc
 // Never with profiling on (its events are recorded eagerly).
 hipError_t capture_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunch &L, int64_t n,
                         const uint64_t *samples, const int64_t *weights, const double *log_amp,
-                        const double *phase, double *eloc, int precision, hipGraphExec_t *out) {
+                        const double *phase, double *eloc, int precision, bool energy,
+                        hipGraphExec_t *out) {
     hipError_t e = hipSuccess;
     if (!h->cap_stream) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) return e;
     e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     const hipError_t e1 = issue_eval(h, sc, L, n, samples, weights, log_amp, phase, eloc,
-                                     precision, nullptr, nullptr, h->cap_stream);
+                                     precision, nullptr, nullptr, h->cap_stream, true, energy);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
     e = e1 != hipSuccess ? e1 : e2;
@@ -343,9 +367,26 @@ hipError_t capture_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLau
     return e;
 }
 
+// The device's error word back to zero (after the host has read it).
+hipError_t clear_device_error(nqs_ham h) {
+    const int zero = 0;
+    return hipMemcpy(static_cast<char *>(h->small) + kErrOffset, &zero, sizeof(int),
+                     hipMemcpyHostToDevice);
+}
+
+int report_device_error(int err) {
+    switch (err) {
+        case 0: return NQS_OK;
+        case NQS_E_DUPLICATE: return fail(err, "a sample occurs more than once in the batch");
+        case NQS_E_RANGE:
+            return fail(err, "a sample has bits at or above n_qubits, or a count is negative");
+        default: return fail(err, "device-detected error");
+    }
+}
+
 int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weights,
               const double *log_amp, const double *phase, double *eloc, int precision,
-              int32_t *hit_idx, uint32_t *sign_bits, void *stream) {
+              int32_t *hit_idx, uint32_t *sign_bits, void *stream, bool energy = false) {
     if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
     if (n < 0) return fail(NQS_E_ARG, "n < 0");
     if (precision != NQS_FP64 && precision != NQS_FP32_KAHAN)
@@ -398,6 +439,9 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
         key.small = h->small;
         key.eblk = h->eblk;
         key.slot_cap = h->slot_cap;
+        key.energy = energy ? 1 : 0;
+        key.epart = energy ? h->epart : nullptr;
+        key.ehost = energy ? h->ehost : nullptr;
         const bool same = h->have_key && std::memcmp(h->eval_key, &key, sizeof key) == 0;
         if (!same) {
             // a new argument set: run it eagerly, remember it
@@ -411,7 +455,7 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
             if (!h->eval_exec) {
                 hipGraphExec_t ex = nullptr;
                 if (capture_eval(h, sc, L, n, samples, weights, log_amp, phase, eloc, precision,
-                                 &ex) == hipSuccess) {
+                                 energy, &ex) == hipSuccess) {
                     h->eval_exec = ex;
                 } else {
                     // graphs unavailable: stay eager from now on
@@ -428,7 +472,7 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
     }
     if (!done)
         NQS_HIP(issue_eval(h, sc, L, n, samples, weights, log_amp, phase, eloc, precision, hit_idx,
-                           sign_bits, st));
+                           sign_bits, st, true, energy));
     if (h->profiling) h->profiled = true;
     h->last_pairs = n * h->dt.n_groups;
     h->last_plan = L;
@@ -802,6 +846,8 @@ int nqs_ham_destroy(nqs_ham h) {
     if (h->shx) (void)hipFree(h->shx);
     if (h->part) (void)hipFree(h->part);
     if (h->jmem) (void)hipFree(h->jmem);
+    if (h->epart) (void)hipFree(h->epart);
+    if (h->ehost) (void)hipHostFree(h->ehost);
     for (hipEvent_t e : h->ev)
         if (e) (void)hipEventDestroy(e);
     if (h->eval_exec) (void)hipGraphExecDestroy(h->eval_exec);
@@ -875,21 +921,64 @@ int nqs_sync(nqs_ham h, void *hip_stream) {
     NQS_HIP(hipStreamSynchronize(st));
     int err = h->host_err.exchange(0);
     if (err == 0) {
-    NQS_HIP(hipMemcpy(&err, static_cast<char *>(h->small) + kErrOffset, sizeof(int),
-                      hipMemcpyDeviceToHost));
-    if (err != 0) {
-        const int zero = 0;
-        NQS_HIP(hipMemcpy(static_cast<char *>(h->small) + kErrOffset, &zero, sizeof(int),
-                          hipMemcpyHostToDevice));
+        NQS_HIP(hipMemcpy(&err, static_cast<char *>(h->small) + kErrOffset, sizeof(int),
+                          hipMemcpyDeviceToHost));
+        if (err != 0) NQS_HIP(clear_device_error(h));
     }
+    return report_device_error(err);
+}
+
+int nqs_eloc_energy(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weights,
+                    const double *log_amp, const double *phase, double *eloc, int precision,
+                    double out[4], void *hip_stream) {
+    if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
+    if (n <= 0) return fail(NQS_E_ARG, "n must be positive");
+    if (!weights || !out) return fail(NQS_E_ARG, "null weights or output");
+    if (n > (int64_t(1) << 30)) return fail(NQS_E_ARG, "batch larger than 2^30 samples");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    // one partial set per block of the finish kernel (256 samples or more)
+    const int64_t need = 4 * ((n + 255) / 256);
+    if (need > h->epart_cap) {
+        NQS_HIP(hipStreamSynchronize(st));
+        const int rc = regrow(&h->epart, &h->epart_cap, need, sizeof(double) * need,
+                              "the energy partials");
+        if (rc) return rc;
     }
-    if (err != 0) {
-        switch (err) {
-            case NQS_E_DUPLICATE: return fail(err, "a sample occurs more than once in the batch");
-            case NQS_E_RANGE: return fail(err, "a sample has bits at or above n_qubits, or a count is negative");
-            default: return fail(err, "device-detected error");
+    if (!h->ehost) {
+        void *p = nullptr;
+        // fine-grained: the device's writes reach the host without a cache flush
+        if (hipHostMalloc(&p, kEnergyHostBytes, hipHostMallocCoherent) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(NQS_E_NOMEM, "pinned host allocation failed");
+        }
+        std::memset(p, 0, kEnergyHostBytes);
+        h->ehost = static_cast<char *>(p);
+    }
+    // the last kernel publishes a new sequence number after the results:
+    // wait for it rather than for the stream (the stream's completion is
+    // seen later); the stream's state ends the wait if the kernel never runs
+    volatile unsigned *hseq = reinterpret_cast<volatile unsigned *>(h->ehost + kEnergyHostSeq);
+    const unsigned before = *hseq;
+    const int rc = eval_impl(h, n, samples, weights, log_amp, phase, eloc, precision, nullptr,
+                             nullptr, hip_stream, true);
+    if (rc) return rc;
+    for (uint64_t k = 1; *hseq == before; ++k) {
+        if ((k & 1023u) == 0) {
+            const hipError_t q = hipStreamQuery(st);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return fail_hip(q, "hipStreamQuery");
+            if (*hseq == before) return fail(NQS_E_DEVICE, "the energy kernel did not report");
         }
     }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    int err = h->host_err.exchange(0);
+    if (err == 0) {
+        std::memcpy(&err, h->ehost, sizeof(int));
+        if (err != 0) NQS_HIP(clear_device_error(h));
+    }
+    if (err != 0) return report_device_error(err);
+    std::memcpy(out, h->ehost + kEnergyHostOut, 4 * sizeof(double));
+    if (out[3] == 0.0) return fail(NQS_E_ARG, "sum of weights is zero");
     return NQS_OK;
 }
 

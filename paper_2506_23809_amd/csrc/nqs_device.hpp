@@ -318,11 +318,26 @@ EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tu
 hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capacity,
                        const uint64_t *samples, const int64_t *weights, int64_t n,
                        hipStream_t st, hipEvent_t after_grouping = nullptr);
+// Eq. 1 taken beside an evaluation: the finish kernel writes one partial set
+// (sum w, sum w Re E, sum w Im E, M2 about the block mean) per block to part
+// (at least ceil(n / 256) sets), and one block combines them into out[4] =
+// {mean re, mean im, variance, sum w}, copies the device's error word to
+// *err_out and then, with seq, publishes *seq + 1 (kept in *seq) to *seq_out
+// (out, err_out and seq_out may be pinned host memory, which the host polls).
+// part == nullptr: not taken.
+struct EnergyFused {
+    const int64_t *weights;
+    double *part;
+    double *out;
+    int *err_out;
+    unsigned *seq;
+    unsigned *seq_out;
+};
 hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
                        const uint64_t *samples, const int64_t *weights, const double *log_amp,
                        const double *phase, double *eloc, int precision, int32_t *hit_idx,
                        uint32_t *sign_bits, int64_t sign_words, EvalStageEvents ev,
-                       hipStream_t st);
+                       EnergyFused ef, hipStream_t st);
 // Eq. 1: per-block partials, then one block combines them; out = {mean re,
 // mean im, variance, sum w}.
 hipError_t launch_energy(const int64_t *w, const double *e, int64_t n, double *part,

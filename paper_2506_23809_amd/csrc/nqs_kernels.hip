@@ -1944,12 +1944,63 @@ __device__ __forceinline__ const double *stage_diag_occ(const DevTable &tab, dou
     return buf;
 }
 
+// Eq. 1 beside the finish: the weighted sums of one block's samples
+// (w = 0 for a thread without a sample), W_b = sum w, sum w Re E,
+// sum w Im E, and M2_b = sum w |E - m_b|^2 about the block's own mean m_b,
+// written by thread 0 to part[0..3].  Sums over each wave by a fixed XOR
+// pattern, then over the waves in order: the same bits on every call.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ void energy_block_partial(double w, double re, double im, double *__restrict__ part) {
+    __shared__ double red[16][3];
+    __shared__ double mean[2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int waves = static_cast<int>(blockDim.x >> 6);
+    const double sw = wave_sum_f64(w), sr = wave_sum_f64(w * re), si = wave_sum_f64(w * im);
+    if (lane == 0) {
+        red[wave][0] = sw;
+        red[wave][1] = sr;
+        red[wave][2] = si;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double W = 0.0, R = 0.0, I = 0.0;
+        for (int k = 0; k < waves; ++k) {
+            W += red[k][0];
+            R += red[k][1];
+            I += red[k][2];
+        }
+        part[0] = W;
+        part[1] = R;
+        part[2] = I;
+        mean[0] = W != 0.0 ? R / W : 0.0;
+        mean[1] = W != 0.0 ? I / W : 0.0;
+    }
+    __syncthreads();
+    const double dr = re - mean[0], di = im - mean[1];
+    const double sv = wave_sum_f64(w * (dr * dr + di * di));
+    __syncthreads();  // every wave has read red[] and mean[]
+    if (lane == 0) red[wave][0] = sv;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double V = 0.0;
+        for (int k = 0; k < waves; ++k) V += red[k][0];
+        part[3] = V;
+    }
+}
+
 template <int W, bool DUMP, int P, bool SCV>
 __global__ __launch_bounds__(256) void eloc_finish_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n,
     int64_t n_chunks, int enum_on, double *__restrict__ eloc, int32_t *__restrict__ hit_idx,
-    uint32_t *__restrict__ sign_bits, int64_t sign_words, int stage_cap, int list_words) {
+    uint32_t *__restrict__ sign_bits, int64_t sign_words, int stage_cap, int list_words,
+    const int64_t *__restrict__ weights, double *__restrict__ epart) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    bool done = false;
     if constexpr (!DUMP && !SCV) {
         // staging area (dynamic LDS of stage_cap doubles, at least
         // 3 kDiagLds): the diagonal's Z masks and coefficients, or its
@@ -1965,19 +2016,28 @@ __global__ __launch_bounds__(256) void eloc_finish_kernel(
             finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc,
                                         hit_idx, sign_bits, sign_words, i, nullptr, nullptr, 0,
                                         dq, olist);
-            return;
-        }
-        uint64_t *dz = reinterpret_cast<uint64_t *>(stage);
-        double *dc = stage + 2 * kDiagLds;
-        const int nd = stage_diagonal<P>(tab, dz, dc);
-        if (nd >= 0) {
-            finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc,
-                                        hit_idx, sign_bits, sign_words, i, dz, dc, nd);
-            return;
+            done = true;
+        } else {
+            uint64_t *dz = reinterpret_cast<uint64_t *>(stage);
+            double *dc = stage + 2 * kDiagLds;
+            const int nd = stage_diagonal<P>(tab, dz, dc);
+            if (nd >= 0) {
+                finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc,
+                                            hit_idx, sign_bits, sign_words, i, dz, dc, nd);
+                done = true;
+            }
         }
     }
-    finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc, hit_idx,
-                                sign_bits, sign_words, i);
+    if (!done)
+        finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc, hit_idx,
+                                    sign_bits, sign_words, i);
+    if (epart) {
+        // this thread's E_loc, just written by it
+        const bool have = i < n;
+        energy_block_partial(have ? static_cast<double>(weights[i]) : 0.0,
+                             have ? eloc[2 * i] : 0.0, have ? eloc[2 * i + 1] : 0.0,
+                             epart + 4 * static_cast<int64_t>(blockIdx.x));
+    }
 }
 
 // The finish kernel of tables with the occupation-form diagonal (no debug
@@ -1989,7 +2049,8 @@ constexpr int kDiagMaxTiles = diag_mfma_tiles(8);
 template <int W, int P>
 __global__ __launch_bounds__(kFinishMfmaThreads) void eloc_finish_mfma_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n,
-    int64_t n_chunks, int enum_on, double *__restrict__ eloc) {
+    int64_t n_chunks, int enum_on, double *__restrict__ eloc, const int64_t *__restrict__ weights,
+    double *__restrict__ epart) {
     __shared__ diag_v4i tiles[kDiagMaxTiles * kDiagLimbs * 64];
     const int words = diag_mfma_tiles(tab.diag_jtiles) * kDiagLimbs * 64;
     const diag_v4i *src = reinterpret_cast<const diag_v4i *>(tab.diag_q8);
@@ -2003,6 +2064,12 @@ __global__ __launch_bounds__(kFinishMfmaThreads) void eloc_finish_mfma_kernel(
     const double d = diag_occ_mfma<W>(tab, x, tiles);
     finish_one<W, false, P, false>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc, nullptr,
                                    nullptr, 0, i, nullptr, nullptr, 0, nullptr, nullptr, true, d);
+    if (epart) {
+        const bool have = i < n;
+        energy_block_partial(have ? static_cast<double>(weights[i]) : 0.0,
+                             have ? eloc[2 * i] : 0.0, have ? eloc[2 * i + 1] : 0.0,
+                             epart + 4 * static_cast<int64_t>(blockIdx.x));
+    }
 }
 
 // ------------------------------------------------------------------ batched form
@@ -2368,21 +2435,31 @@ __global__ __launch_bounds__(kRedThreads) void energy_block_kernel(
     }
 }
 
-// Single block: out = {mean re, mean im, variance, sum w} from the nb block
-// partials (one a thread; nb <= kRedThreads).
+// Single block: out = {mean re, mean im, variance, sum w} from nb block
+// partials (thread t takes partials t, t + kRedThreads, ... in that order).
+// out may be pinned host memory; with err, the device's error word is
+// copied to *err_out beside it (the host reads both after one wait).
 __global__ __launch_bounds__(kRedThreads) void energy_combine_kernel(
-    const double *__restrict__ part, int nb, double *__restrict__ out) {
+    const double *__restrict__ part, int64_t nb, double *__restrict__ out,
+    const int *__restrict__ err, int *__restrict__ err_out, unsigned *__restrict__ seq,
+    unsigned *__restrict__ seq_out) {
     __shared__ double lds[kRedThreads];
-    const int b = threadIdx.x;
-    const bool have = b < nb;
-    const double bw = have ? part[4 * b] : 0.0, br = have ? part[4 * b + 1] : 0.0;
-    const double bi = have ? part[4 * b + 2] : 0.0, bv = have ? part[4 * b + 3] : 0.0;
+    double bw = 0.0, br = 0.0, bi = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += kRedThreads) {
+        bw += part[4 * b];
+        br += part[4 * b + 1];
+        bi += part[4 * b + 2];
+    }
     const double SW = block_sum(bw, lds), SR = block_sum(br, lds), SI = block_sum(bi, lds);
     const double MR = SW != 0.0 ? SR / SW : 0.0, MI = SW != 0.0 ? SI / SW : 0.0;
-    double c = bv;
-    if (bw != 0.0) {
-        const double ur = br / bw - MR, ui = bi / bw - MI;
-        c += bw * (ur * ur + ui * ui);
+    double c = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += kRedThreads) {
+        const double w = part[4 * b];
+        c += part[4 * b + 3];
+        if (w != 0.0) {
+            const double ur = part[4 * b + 1] / w - MR, ui = part[4 * b + 2] / w - MI;
+            c += w * (ur * ur + ui * ui);
+        }
     }
     const double SV = block_sum(c, lds);
     if (threadIdx.x == 0) {
@@ -2390,6 +2467,15 @@ __global__ __launch_bounds__(kRedThreads) void energy_combine_kernel(
         out[1] = MI;
         out[2] = SW != 0.0 ? SV / SW : 0.0;
         out[3] = SW;
+        if (err) *err_out = *err;
+        if (seq) {
+            // a new sequence number, published after the results (system
+            // scope: the host polls it)
+            const unsigned v = *seq + 1u;
+            *seq = v;
+            __threadfence_system();
+            *reinterpret_cast<volatile unsigned *>(seq_out) = v;
+        }
     }
 }
 
@@ -2570,7 +2656,7 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
                        const uint64_t *samples, const int64_t *weights, const double *log_amp,
                        const double *phase, double *eloc, int precision, int32_t *hit_idx,
                        uint32_t *sign_bits, int64_t sign_words, EvalStageEvents ev,
-                       hipStream_t st) {
+                       EnergyFused ef, hipStream_t st) {
     const int words = tab.n_qubits <= 63 ? 1 : 2;
     const bool dump = hit_idx || sign_bits;
     const bool f32 = precision == NQS_FP32_KAHAN && !dump;
@@ -2686,30 +2772,37 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
         if (words == 1) {
             if (f32)
                 hipLaunchKernelGGL((eloc_finish_mfma_kernel<1, NQS_FP32_KAHAN>), mgrid, mblk, 0,
-                                   st, tab, sc, samples, n, chunks, fb, eloc);
+                                   st, tab, sc, samples, n, chunks, fb, eloc, ef.weights, ef.part);
             else
                 hipLaunchKernelGGL((eloc_finish_mfma_kernel<1, NQS_FP64>), mgrid, mblk, 0, st, tab,
-                                   sc, samples, n, chunks, fb, eloc);
+                                   sc, samples, n, chunks, fb, eloc, ef.weights, ef.part);
         } else {
             if (f32)
                 hipLaunchKernelGGL((eloc_finish_mfma_kernel<2, NQS_FP32_KAHAN>), mgrid, mblk, 0,
-                                   st, tab, sc, samples, n, chunks, fb, eloc);
+                                   st, tab, sc, samples, n, chunks, fb, eloc, ef.weights, ef.part);
             else
                 hipLaunchKernelGGL((eloc_finish_mfma_kernel<2, NQS_FP64>), mgrid, mblk, 0, st, tab,
-                                   sc, samples, n, chunks, fb, eloc);
+                                   sc, samples, n, chunks, fb, eloc, ef.weights, ef.part);
         }
+        if (ef.part)
+            hipLaunchKernelGGL(energy_combine_kernel, dim3(1), dim3(kRedThreads), 0, st, ef.part,
+                               static_cast<int64_t>(mgrid.x), ef.out, sc.err, ef.err_out, ef.seq,
+                               ef.seq_out);
         return hipGetLastError();
     }
+    // (the energy partials only where no dump is taken)
+    double *const ep = dump ? nullptr : ef.part;
 #define NQS_FINISH(Wd, D, Pr)                                                                 \
     do {                                                                                      \
         if ((e = allow_finish_lds<Wd, D, Pr>()) != hipSuccess) return e;                     \
         hipLaunchKernelGGL((eloc_finish_kernel<Wd, D, Pr, false>), fgrid, dim3(256),          \
                            stage_bytes, st, tab, sc, samples, n, chunks, fb, eloc, hit_idx,   \
-                           sign_bits, sign_words, stage_cap, list_words);                     \
+                           sign_bits, sign_words, stage_cap, list_words, ef.weights, ep);     \
     } while (0)
 #define NQS_FINISH_SC(Wd, D)                                                                     \
     hipLaunchKernelGGL((eloc_finish_kernel<Wd, D, NQS_FP64, true>), fgrid, dim3(256), 0, st, tab, \
-                       sc, samples, n, chunks, fb, eloc, hit_idx, sign_bits, sign_words, 0, 0)
+                       sc, samples, n, chunks, fb, eloc, hit_idx, sign_bits, sign_words, 0, 0,    \
+                       ef.weights, ep)
     if (tab.sc) {
         if (words == 1) {
             if (dump) NQS_FINISH_SC(1, true); else NQS_FINISH_SC(1, false);
@@ -2727,6 +2820,10 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
     }
 #undef NQS_FINISH
 #undef NQS_FINISH_SC
+    if (ep)
+        hipLaunchKernelGGL(energy_combine_kernel, dim3(1), dim3(kRedThreads), 0, st, ep,
+                           static_cast<int64_t>(fgrid.x), ef.out, sc.err, ef.err_out, ef.seq,
+                           ef.seq_out);
     return hipGetLastError();
 }
 
@@ -2736,10 +2833,9 @@ hipError_t launch_energy(const int64_t *w, const double *e, int64_t n, double *p
     if (blocks > kRedBlocks) blocks = kRedBlocks;
     if (blocks < 1) blocks = 1;
     static_assert(4 * kRedBlocks <= kEnergyPartDoubles, "the block partials fit");
-    static_assert(kRedBlocks <= kRedThreads, "one partial set per thread of the combine");
     hipLaunchKernelGGL(energy_block_kernel, dim3(blocks), dim3(kRedThreads), 0, st, w, e, n, part);
-    hipLaunchKernelGGL(energy_combine_kernel, dim3(1), dim3(kRedThreads), 0, st, part,
-                       static_cast<int>(blocks), out);
+    hipLaunchKernelGGL(energy_combine_kernel, dim3(1), dim3(kRedThreads), 0, st, part, blocks, out,
+                       nullptr, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 
