@@ -237,9 +237,13 @@ int nqs_energy(int64_t n, const int64_t *weights, const double *eloc, double out
  * to it within rounding; repeated calls give identical bits).
  *   eloc: device [n][2] double, written as by nqs_eloc_eval;
  *   out:  host [4] = {Re E, Im E, variance, sum w}, as nqs_energy.
- * weights are required (device [n] int64).  Synchronises hip_stream before
- * returning and reports the errors the device latched during this call
- * (NQS_E_DUPLICATE, NQS_E_RANGE) as nqs_sync would.  Errors: those of
+ * weights are required (device [n] int64).  Returns once the result is on
+ * the host: the last kernel writes it, with the device's error word and a
+ * new sequence number, to a pinned buffer of the handle that this call
+ * polls (all reads of the caller's arrays are done by then; later work on
+ * hip_stream still runs after this call's kernels).  Reports the errors the
+ * device latched during this call (NQS_E_DUPLICATE, NQS_E_RANGE) as
+ * nqs_sync would.  Calls on one handle must not overlap.  Errors: those of
  * nqs_eloc_eval and nqs_energy (NQS_E_ARG for n <= 0, null weights or out,
  * sum w == 0).
  */
