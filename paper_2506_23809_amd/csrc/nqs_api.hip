@@ -1535,7 +1535,8 @@ int plan_batch(const nqs_batch_item *items, int n_items, int threads, hipStream_
                                                 int64_t(1) << (L.eparts_log2 + L.efilter_log2));
         if (J.sc.jctl)
             shape.max_clear = std::max<int64_t>(
-                shape.max_clear, std::max<int64_t>(J.sc.join_parts, nqs::kJoinCtl));
+                shape.max_clear, std::max<int64_t>(std::max<int64_t>(J.sc.join_parts, nqs::kJoinCtl),
+                                                   (J.tab.join_blocks * J.n + 31) / 32));
         cost[k] = it.n * (h->dt.n_groups - L.g_first);
     }
     // work list: largest jobs first (the persistent kernel drains it in order),

@@ -209,6 +209,8 @@ struct DevScratch {
     unsigned long long *jrange; // [blocks * n] first entry of the entry's bucket |
                                 // bucket size << 32 | block << 48
     uint64_t *jkeys;            // [blocks * n][2] the entry's bit string
+    uint32_t *jhit;             // [ceil(blocks * n / 32)] bit b * n + i: entry (b, i) has a
+                                // hit and wrote its partial
     unsigned long long *jstat;  // [parts][2] sum of squared bucket sizes, largest bucket
     unsigned long long *jctl;   // [kJoinCtl] see kJoinCtl*
     int join_log2m;

@@ -480,7 +480,8 @@ __device__ __forceinline__ bool join_hit(const DevTable &tab, const Key<W> &x, c
 }
 
 // One lane per entry (block b, sample i): the partners of i in its bucket,
-// in index order; its partial sum (zero without a hit) goes to part[b][i].
+// in index order; with a hit, its partial sum goes to part[b][i] and bit
+// b * n + i of the hit map is set (the finish reads only flagged partials).
 // The first build_blocks blocks are the sample-hash build of the same
 // launch instead (its checks always; its insertion when the join is not
 // chosen): both need only the decision, so one launch carries both.
@@ -505,8 +506,7 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
         const unsigned long long r = sc.jrange[p];
         const uint32_t bs = static_cast<uint32_t>(r), m = static_cast<uint32_t>(r >> 32) & 0xFFFFu;
         const int b = static_cast<int>(r >> 48);
-        double *out = sc.part + 2 * (static_cast<int64_t>(b) * n + i);
-        double2 sum = make_double2(0.0, 0.0);
+        const int64_t e = static_cast<int64_t>(b) * n + i;
         if (m >= 2) {
             const Key<W> x = load_key<W>(sc.jkeys, p);
             double re = 0.0, im = 0.0, la = 0.0, ph = 0.0;
@@ -567,14 +567,16 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
             for (; q < bs + m; ++q) visit(q, load_key<W>(sc.jkeys, q));
             n_cand = m - 1;
             if (n_hit) {
+                double2 sum;
                 if constexpr (P == NQS_FP64) {
                     sum = make_double2(re, im);
                 } else {
                     sum = make_double2(ar.value(), ai.value());
                 }
+                *reinterpret_cast<double2 *>(sc.part + 2 * e) = sum;
+                atomicOr(&sc.jhit[e >> 5], 1u << (e & 31));
             }
         }
-        *reinterpret_cast<double2 *>(out) = sum;
     }
     // one set of counter atomics per block
     __shared__ unsigned long long cnt[4][kJoinPairThreads / 64];
@@ -670,7 +672,7 @@ int join_log2m_for(int64_t n) {
 namespace {
 
 // Byte sizes of the join's pieces, in layout order.
-constexpr int kJoinPieces = 9;
+constexpr int kJoinPieces = 10;
 void join_sizes(const DevTable &tab, int64_t n, int log2m, size_t sizes[kJoinPieces]) {
     const JoinGeometry g = join_geometry(tab, n, log2m);
     const size_t entries = static_cast<size_t>(tab.join_blocks) * static_cast<size_t>(n);
@@ -684,6 +686,7 @@ void join_sizes(const DevTable &tab, int64_t n, int log2m, size_t sizes[kJoinPie
     sizes[6] = 16 * parts;                                // jstat
     sizes[7] = 8 * static_cast<size_t>(kJoinCtl);         // jctl
     sizes[8] = 16 * entries;                              // jkeys
+    sizes[9] = 4 * ((entries + 31) / 32);                 // jhit
 }
 
 }  // namespace
@@ -716,6 +719,7 @@ void join_scratch_layout(const DevTable &tab, int64_t n, int log2m, char *base, 
     sc->jstat = reinterpret_cast<unsigned long long *>(base + off[6]);
     sc->jctl = reinterpret_cast<unsigned long long *>(base + off[7]);
     sc->jkeys = reinterpret_cast<uint64_t *>(base + off[8]);
+    sc->jhit = reinterpret_cast<uint32_t *>(base + off[9]);
     sc->join_log2m = log2m;
     sc->join_n = n;
     sc->join_lshift = g.lshift;

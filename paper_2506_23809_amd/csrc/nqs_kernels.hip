@@ -44,7 +44,8 @@ __global__ void hash_clear_kernel(uint64_t *__restrict__ skey, int32_t *__restri
                                   uint32_t filter_words, uint32_t *__restrict__ efilter,
                                   uint32_t efilter_words, unsigned long long *__restrict__ counters,
                                   int *__restrict__ mixed, uint32_t *__restrict__ jcnt,
-                                  uint32_t jparts, unsigned long long *__restrict__ jctl) {
+                                  uint32_t jparts, unsigned long long *__restrict__ jctl,
+                                  uint32_t *__restrict__ jhit, uint32_t jhit_words) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     // the batch's counters and sector flag start at zero as well, and so do
     // the pair join's partition counts and control words
@@ -52,6 +53,7 @@ __global__ void hash_clear_kernel(uint64_t *__restrict__ skey, int32_t *__restri
     if (s == 0) *mixed = 0;
     if (jctl && s < static_cast<uint32_t>(kJoinCtl)) jctl[s] = 0;
     if (s < jparts) jcnt[s] = 0u;
+    if (s < jhit_words) jhit[s] = 0u;
     if (s < capacity) {
         sidx[s] = -1;
         sfp[s] = 0u;
@@ -1876,6 +1878,26 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
                 if (hit_idx) hit_idx[i * tab.n_groups] = static_cast<int32_t>(i);
             }
         }
+        if (join_chosen(sc)) {
+            // the pair join: the blocks' partials in block order, only
+            // those its hit map flags (the others were never written)
+            uint32_t w[kJoinMaxBlocks];
+#pragma unroll
+            for (int b = 0; b < kJoinMaxBlocks; ++b) {
+                const int64_t e = static_cast<int64_t>(b) * n + i;
+                w[b] = b < n_chunks ? sc.jhit[e >> 5] : 0u;
+            }
+#pragma unroll
+            for (int b = 0; b < kJoinMaxBlocks; ++b) {
+                const int64_t e = static_cast<int64_t>(b) * n + i;
+                if ((w[b] >> (e & 31)) & 1u) {
+                    const double2 v = *reinterpret_cast<const double2 *>(sc.part + 2 * e);
+                    re += v.x;
+                    im += v.y;
+                }
+            }
+            n_chunks = 0;
+        }
         // the partials in chunk order, eight loads in flight at a time
         for (int64_t c0 = 0; c0 < n_chunks; c0 += 8) {
             double2 v[8];
@@ -2106,6 +2128,7 @@ __global__ void batch_clear_kernel(const JobDesc *__restrict__ jobs) {
         J.sc.efilter[s] = 0u;
     if (J.sc.jctl) {
         if (s < static_cast<uint32_t>(J.sc.join_parts)) J.sc.jcnt[s] = 0u;
+        if (s < static_cast<uint32_t>((J.tab.join_blocks * J.n + 31) / 32)) J.sc.jhit[s] = 0u;
         if (s < static_cast<uint32_t>(kJoinCtl)) J.sc.jctl[s] = 0ull;
     }
 }
@@ -2570,15 +2593,17 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
     const uint32_t efwords =
         (join || sc.eparts_log2 <= 0) ? 0u : (1u << (sc.eparts_log2 + sc.efilter_log2));
     const uint32_t jparts = join ? static_cast<uint32_t>(sc.join_parts) : 0u;
+    const uint32_t jhw = join ? static_cast<uint32_t>((tab.join_blocks * n + 31) / 32) : 0u;
     uint32_t span = cap > fwords ? cap : fwords;
     span = span > efwords ? span : efwords;
     span = span > jparts ? span : jparts;
+    span = span > jhw ? span : jhw;
     const uint32_t n_counters = static_cast<uint32_t>(kCounters * kCounterSlots);
     span = span > n_counters ? span : n_counters;
     span = span > static_cast<uint32_t>(kJoinCtl) ? span : static_cast<uint32_t>(kJoinCtl);
     hipLaunchKernelGGL(hash_clear_kernel, dim3((span + 255) / 256), dim3(256), 0, st, sc.skey,
                        sc.sidx, sc.sfp, words, cap, sc.filter, fwords, sc.efilter, efwords,
-                       sc.counters, sc.mixed, sc.jcnt, jparts, sc.jctl);
+                       sc.counters, sc.mixed, sc.jcnt, jparts, sc.jctl, sc.jhit, jhw);
     if (join) {
         // the pair join's grouping and decision come before the build, which
         // skips its insertion when the join runs
