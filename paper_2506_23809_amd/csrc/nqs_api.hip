@@ -43,7 +43,8 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 constexpr size_t kErrOffset = 8 * nqs::kCounters * nqs::kCounterSlots;
 constexpr size_t kSmallBytes = kErrOffset + 64;
 // nqs_eloc_energy's pinned host buffer: the error word, then out[4]
-constexpr size_t kEnergyHostSeq = 4;  // sequence number the host polls
+constexpr size_t kEnergyHostSeq = 4;     // sequence number the host polls
+constexpr size_t kEnergyHostChosen = 8;  // the join's decision (2: no join launched)
 constexpr size_t kEnergyHostOut = 16;
 constexpr size_t kSeqOffset = kErrOffset + 8;  // the device's copy of it (in small)
 constexpr size_t kEnergyHostBytes = kEnergyHostOut + 4 * sizeof(double);
@@ -81,6 +82,9 @@ struct nqs_ham_s {
     double *epart = nullptr;
     int64_t epart_cap = 0;  // doubles
     char *ehost = nullptr;
+    // the previous nqs_eloc_energy ran the pair join: the next one launches
+    // only the join's kernels (checked against the device's decision)
+    bool join_likely = false;
     // an error a server lane saw for one of this handle's requests, reported
     // by the next nqs_sync like a latched device error
     std::atomic<int> host_err{0};
@@ -307,7 +311,7 @@ struct EvalKey {
     int join, join_force, join_log2m;
     const void *slots, *shx, *part, *filter, *efilter, *small, *eblk, *jmem;
     uint32_t slot_cap;
-    int energy;
+    int energy, join_only;
     const void *epart, *ehost;
 };
 static_assert(sizeof(EvalKey) <= sizeof(nqs_ham_s::eval_key), "key fits");
@@ -336,8 +340,9 @@ hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunc
                                   reinterpret_cast<int *>(h->ehost),
                                   reinterpret_cast<unsigned *>(static_cast<char *>(h->small) +
                                                                kSeqOffset),
-                                  reinterpret_cast<unsigned *>(h->ehost + kEnergyHostSeq)}
-               : nqs::EnergyFused{weights, nullptr, nullptr, nullptr, nullptr, nullptr};
+                                  reinterpret_cast<unsigned *>(h->ehost + kEnergyHostSeq),
+                                  reinterpret_cast<unsigned *>(h->ehost + kEnergyHostChosen)}
+               : nqs::EnergyFused{weights, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     if ((e = nqs::launch_eloc(h->dt, sc, L, samples, weights, log_amp, phase, eloc, precision,
                               hit_idx, sign_bits, sign_words, stages, ef, s)) != hipSuccess)
         return e;
@@ -386,7 +391,8 @@ int report_device_error(int err) {
 
 int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weights,
               const double *log_amp, const double *phase, double *eloc, int precision,
-              int32_t *hit_idx, uint32_t *sign_bits, void *stream, bool energy = false) {
+              int32_t *hit_idx, uint32_t *sign_bits, void *stream, bool energy = false,
+              bool join_only = false) {
     if (!valid_handle(h)) return fail(NQS_E_STATE, "invalid handle");
     if (n < 0) return fail(NQS_E_ARG, "n < 0");
     if (precision != NQS_FP64 && precision != NQS_FP32_KAHAN)
@@ -399,7 +405,9 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
     if (n > (int64_t(1) << 30)) return fail(NQS_E_ARG, "batch larger than 2^30 samples");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool dump = hit_idx || sign_bits;
-    const nqs::EvalLaunch L = nqs::plan_eval(h->dt, n, dump, &h->tune);
+    nqs::EvalLaunch L = nqs::plan_eval(h->dt, n, dump, &h->tune);
+    // (only where a join is launched and may be chosen)
+    L.join_only = join_only && L.join && !dump ? 1 : 0;
     int rc = ensure_scratch(h, n, plan_chunks(h, L), st, L.eparts_log2 > 0, plan_join_bytes(h, L));
     if (!rc) rc = scratch_ready(h, L);
     if (rc) return rc;
@@ -440,6 +448,7 @@ int eval_impl(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weig
         key.eblk = h->eblk;
         key.slot_cap = h->slot_cap;
         key.energy = energy ? 1 : 0;
+        key.join_only = L.join_only;
         key.epart = energy ? h->epart : nullptr;
         key.ehost = energy ? h->ehost : nullptr;
         const bool same = h->have_key && std::memcmp(h->eval_key, &key, sizeof key) == 0;
@@ -958,19 +967,29 @@ int nqs_eloc_energy(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t
     // wait for it rather than for the stream (the stream's completion is
     // seen later); the stream's state ends the wait if the kernel never runs
     volatile unsigned *hseq = reinterpret_cast<volatile unsigned *>(h->ehost + kEnergyHostSeq);
-    const unsigned before = *hseq;
-    const int rc = eval_impl(h, n, samples, weights, log_amp, phase, eloc, precision, nullptr,
-                             nullptr, hip_stream, true);
-    if (rc) return rc;
-    for (uint64_t k = 1; *hseq == before; ++k) {
-        if ((k & 1023u) == 0) {
-            const hipError_t q = hipStreamQuery(st);
-            if (q == hipErrorNotReady) continue;
-            if (q != hipSuccess) return fail_hip(q, "hipStreamQuery");
-            if (*hseq == before) return fail(NQS_E_DEVICE, "the energy kernel did not report");
+    const volatile unsigned *hchosen =
+        reinterpret_cast<const volatile unsigned *>(h->ehost + kEnergyHostChosen);
+    // after a call that chose the join, launch only the join's kernels (the
+    // enumeration and streaming launches would return at once); if the
+    // device decides otherwise this time, evaluate again with every launch
+    for (bool join_only = h->join_likely;; join_only = false) {
+        const unsigned before = *hseq;
+        const int rc = eval_impl(h, n, samples, weights, log_amp, phase, eloc, precision, nullptr,
+                                 nullptr, hip_stream, true, join_only);
+        if (rc) return rc;
+        for (uint64_t k = 1; *hseq == before; ++k) {
+            if ((k & 1023u) == 0) {
+                const hipError_t q = hipStreamQuery(st);
+                if (q == hipErrorNotReady) continue;
+                if (q != hipSuccess) return fail_hip(q, "hipStreamQuery");
+                if (*hseq == before) return fail(NQS_E_DEVICE, "the energy kernel did not report");
+            }
         }
+        std::atomic_thread_fence(std::memory_order_acquire);
+        const unsigned chosen = *hchosen;
+        h->join_likely = chosen == 1u;
+        if (!join_only || chosen == 1u) break;
     }
-    std::atomic_thread_fence(std::memory_order_acquire);
     int err = h->host_err.exchange(0);
     if (err == 0) {
         std::memcpy(&err, h->ehost, sizeof(int));

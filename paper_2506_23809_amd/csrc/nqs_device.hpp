@@ -275,6 +275,10 @@ struct EvalLaunch {
     int join;           // 1: the pair join is launched (the device decides whether it runs)
     int join_force;     // 1: it runs whenever it can (tuning asked for it)
     int join_log2m;     // log2 of the buckets per block
+    // 1: only the join's kernels and the finish (no enumeration or streaming
+    // launch); its result is valid only if the device chose the join, which
+    // the caller checks (nqs_eloc_energy, after its previous call chose it)
+    int join_only;
 };
 
 // Bytes of the pair join's scratch for n samples and the table's blocks
@@ -324,7 +328,8 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
 // (sum w, sum w Re E, sum w Im E, M2 about the block mean) per block to part
 // (at least ceil(n / 256) sets), and one block combines them into out[4] =
 // {mean re, mean im, variance, sum w}, copies the device's error word to
-// *err_out and then, with seq, publishes *seq + 1 (kept in *seq) to *seq_out
+// *err_out and the join's decision to *chosen_out, then, with seq, publishes
+// *seq + 1 (kept in *seq) to *seq_out
 // (out, err_out and seq_out may be pinned host memory, which the host polls).
 // part == nullptr: not taken.
 struct EnergyFused {
@@ -334,6 +339,7 @@ struct EnergyFused {
     int *err_out;
     unsigned *seq;
     unsigned *seq_out;
+    unsigned *chosen_out;  // the join's decision (2: no join launched)
 };
 hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaunch &L,
                        const uint64_t *samples, const int64_t *weights, const double *log_amp,

@@ -2465,7 +2465,8 @@ __global__ __launch_bounds__(kRedThreads) void energy_block_kernel(
 __global__ __launch_bounds__(kRedThreads) void energy_combine_kernel(
     const double *__restrict__ part, int64_t nb, double *__restrict__ out,
     const int *__restrict__ err, int *__restrict__ err_out, unsigned *__restrict__ seq,
-    unsigned *__restrict__ seq_out) {
+    unsigned *__restrict__ seq_out, const unsigned long long *__restrict__ jctl,
+    unsigned *__restrict__ chosen_out) {
     __shared__ double lds[kRedThreads];
     double bw = 0.0, br = 0.0, bi = 0.0;
     for (int64_t b = threadIdx.x; b < nb; b += kRedThreads) {
@@ -2491,6 +2492,7 @@ __global__ __launch_bounds__(kRedThreads) void energy_combine_kernel(
         out[2] = SW != 0.0 ? SV / SW : 0.0;
         out[3] = SW;
         if (err) *err_out = *err;
+        if (chosen_out) *chosen_out = jctl ? (jctl[kJoinCtlChosen] != 0ull ? 1u : 0u) : 2u;
         if (seq) {
             // a new sequence number, published after the results (system
             // scope: the host polls it)
@@ -2570,6 +2572,7 @@ EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tu
     // device whether it runs
     L.join = 0;
     L.join_force = 0;
+    L.join_only = 0;
     L.join_log2m = 0;
     if (tab.join_blocks > 0 && (want == kStrategyAuto || want == kStrategyJoin) &&
         n <= kJoinMaxSamples) {
@@ -2707,7 +2710,7 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
         e = hipEventRecord(ev.after_pairs, st);
         if (e != hipSuccess) return e;
     }
-    if (en) {
+    if (en && !L.join_only) {
         // a dump marks every pair first; the enumeration writes only its hits
         // (done above when a join was launched too)
         if (hit_idx && !sc.jctl) {
@@ -2736,7 +2739,7 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
 #undef NQS_ENUM
         if (e != hipSuccess) return e;
     }
-    if (L.chunk_len > 0) {
+    if (L.chunk_len > 0 && !L.join_only) {
 #define NQS_LOOKUP(Wd, S, SE, D, Pr)                                                       \
     e = launch_lookup<Wd, S, SE, D, Pr, false>(tab, sc, L, samples, log_amp, phase, hit_idx,  \
                                                sign_bits, sign_words, fb, st)
@@ -2812,7 +2815,7 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
         if (ef.part)
             hipLaunchKernelGGL(energy_combine_kernel, dim3(1), dim3(kRedThreads), 0, st, ef.part,
                                static_cast<int64_t>(mgrid.x), ef.out, sc.err, ef.err_out, ef.seq,
-                               ef.seq_out);
+                               ef.seq_out, sc.jctl, ef.chosen_out);
         return hipGetLastError();
     }
     // (the energy partials only where no dump is taken)
@@ -2848,7 +2851,7 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
     if (ep)
         hipLaunchKernelGGL(energy_combine_kernel, dim3(1), dim3(kRedThreads), 0, st, ep,
                            static_cast<int64_t>(fgrid.x), ef.out, sc.err, ef.err_out, ef.seq,
-                           ef.seq_out);
+                           ef.seq_out, sc.jctl, ef.chosen_out);
     return hipGetLastError();
 }
 
@@ -2860,7 +2863,7 @@ hipError_t launch_energy(const int64_t *w, const double *e, int64_t n, double *p
     static_assert(4 * kRedBlocks <= kEnergyPartDoubles, "the block partials fit");
     hipLaunchKernelGGL(energy_block_kernel, dim3(blocks), dim3(kRedThreads), 0, st, w, e, n, part);
     hipLaunchKernelGGL(energy_combine_kernel, dim3(1), dim3(kRedThreads), 0, st, part, blocks, out,
-                       nullptr, nullptr, nullptr, nullptr);
+                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 

@@ -11,8 +11,13 @@ samples in 1024-sample blocks), eagerly and through the replayed graph:
     variance) and with nqs_energy over the same array;
   * repeated calls give identical bits;
   * device-detected errors come back from the call itself, and a clean
-    call afterwards succeeds.
+    call afterwards succeeds;
+  * after a call that ran the pair join, the next one launches only the
+    join's kernels: when the device declines the join for new contents of
+    the same buffers, the call evaluates again with every launch and its
+    result still equals nqs_eloc_eval's.
 """
+import math
 import sys
 
 import numpy as np
@@ -20,6 +25,7 @@ import pytest
 
 import oracle
 import paper_2506_23809_amd as nqs
+import workloads as W
 
 pytestmark = pytest.mark.gpu
 
@@ -111,3 +117,44 @@ def test_eloc_energy_errors(torch_dev, workload_cache):
         ham.eloc_energy_into(out[:0], S[:0], la[:0], ph[:0], wt[:0])
     assert ex.value.code == nqs.NQS_E_ARG
     ham.close()
+
+
+def test_join_only_launch_recovers_when_the_join_is_declined(torch_dev, workload_cache):
+    torch = torch_dev
+    w = workload_cache(("workload", "nq40", 256))
+    rng = np.random.default_rng(91)
+    n = 9000
+    # spread samples of the 40-qubit sector: the device runs the join
+    spread = W.sector_samples(rng, 20, 10, 10, n)
+    # the same sector with the first block's qubits always occupied: one
+    # bucket holds every sample, the join cannot run
+    rest = W.sector_samples(rng, 16, 6, 6, n)
+    bits = np.zeros((n, 40), bool)
+    bits[:, :8] = True
+    bits[:, 8:] = W.unpack_bits(rest, 32)
+    clustered = W.pack_bits(bits)
+    la = torch.from_numpy(rng.normal(0.0, 1.0, n)).cuda()
+    ph = torch.from_numpy(rng.uniform(0.0, 2 * math.pi, n)).cuda()
+    wt = torch.from_numpy(rng.integers(1, 5, n).astype(np.int64)).cuda()
+    ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
+    ref_ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
+    S = nqs.to_device_samples(spread)
+    out = torch.empty((n, 2), dtype=torch.float64, device="cuda")
+    for label, contents, join_ran in (("spread", spread, 1), ("spread", spread, 1),
+                                      ("spread", spread, 1), ("clustered", clustered, 0),
+                                      ("clustered", clustered, 0), ("spread", spread, 1)):
+        say(f"join-only launch: {label}")
+        S.copy_(nqs.to_device_samples(contents))
+        ref = torch.view_as_real(ref_ham.eloc(S, la, ph, wt)).cpu().numpy()
+        ref_ham.sync()
+        assert ref_ham.plan()["join_ran"] == join_ran
+        out.fill_(float("nan"))
+        m, v, sw = ham.eloc_energy_into(out, S, la, ph, wt)
+        got = out.cpu().numpy()
+        assert np.array_equal(got.view(np.uint64), ref.view(np.uint64)), label
+        m2, v2, sw2 = nqs.energy(wt, out)
+        scale = float(np.sum(np.abs(got[:, 0] + 1j * got[:, 1])) / n)
+        assert sw == sw2 and abs(m - m2) <= 1e-12 * scale
+        assert ham.plan()["join_ran"] == join_ran
+    ham.close()
+    ref_ham.close()
