@@ -326,7 +326,7 @@ hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunc
     const bool prof = h->profiling && may_profile;
     if (prof && (e = hipEventRecord(h->ev[0], s)) != hipSuccess) return e;
     if ((e = nqs::launch_hash(h->dt, sc, sc.slot_mask + 1u, samples, weights, n, s,
-                              prof ? h->ev[4] : nullptr)) != hipSuccess)
+                              prof ? h->ev[4] : nullptr, L.join_only != 0)) != hipSuccess)
         return e;
     if (prof && (e = hipEventRecord(h->ev[1], s)) != hipSuccess) return e;
     const int64_t sign_words = (h->dt.n_terms + 31) / 32;

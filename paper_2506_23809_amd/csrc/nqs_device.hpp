@@ -294,10 +294,11 @@ void join_scratch_layout(const DevTable &tab, int64_t n, int log2m, char *base, 
 // clears the Bloom bitmaps.
 hipError_t launch_join_prep(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
                             int64_t n, int64_t g_eff, bool clear_hash, hipStream_t st);
-// With build, the same launch also carries the sample-hash build (checks,
-// and the insertion when the join is not chosen) in blocks of its own.
+// With build (1), the same launch also carries the sample-hash build (checks,
+// and the insertion when the join is not chosen) in blocks of its own; with
+// build 2 only its checks.
 hipError_t launch_join_pairs(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
-                             const int64_t *weights, bool build, const double *log_amp,
+                             const int64_t *weights, int build, const double *log_amp,
                              const double *phase, int64_t n, int precision, int32_t *hit_idx,
                              uint32_t *sign_bits, int64_t sign_words, hipStream_t st);
 
@@ -321,9 +322,12 @@ struct Tuning {
 };
 
 EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tune);
+// With join_only (a launch of the join's kernels alone) the sample hash is
+// neither cleared nor filled: nothing reads it.
 hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capacity,
                        const uint64_t *samples, const int64_t *weights, int64_t n,
-                       hipStream_t st, hipEvent_t after_grouping = nullptr);
+                       hipStream_t st, hipEvent_t after_grouping = nullptr,
+                       bool join_only = false);
 // Eq. 1 taken beside an evaluation: the finish kernel writes one partial set
 // (sum w, sum w Re E, sum w Im E, M2 about the block mean) per block to part
 // (at least ceil(n / 256) sets), and one block combines them into out[4] =

@@ -484,16 +484,17 @@ __device__ __forceinline__ bool join_hit(const DevTable &tab, const Key<W> &x, c
 // b * n + i of the hit map is set (the finish reads only flagged partials).
 // The first build_blocks blocks are the sample-hash build of the same
 // launch instead (its checks always; its insertion when the join is not
-// chosen): both need only the decision, so one launch carries both.
+// chosen, unless checks_only): both need only the decision, so one launch
+// carries both.
 template <int W, bool DUMP, int P, bool SCV>
 __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
     const int64_t *__restrict__ weights, const double *__restrict__ log_amp,
-    const double *__restrict__ phase, int64_t n, unsigned build_blocks,
+    const double *__restrict__ phase, int64_t n, unsigned build_blocks, int checks_only,
     int32_t *__restrict__ hit_idx, uint32_t *__restrict__ sign_bits, int64_t sign_words) {
     if (blockIdx.x < build_blocks) {
         const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-        if (i < n) hash_build_one<W>(tab, sc, samples, weights, i);
+        if (i < n) hash_build_one<W>(tab, sc, samples, weights, i, checks_only != 0);
         return;
     }
     if (!join_chosen(sc)) return;
@@ -627,7 +628,7 @@ hipError_t launch_join_prep_w(const DevTable &tab, const DevScratch &sc,
 
 template <int W, bool D, int P, bool SCV>
 hipError_t launch_pairs_w(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
-                          const int64_t *weights, bool build, const double *log_amp,
+                          const int64_t *weights, int build, const double *log_amp,
                           const double *phase, int64_t n, int32_t *hit_idx, uint32_t *sign_bits,
                           int64_t sign_words, hipStream_t st) {
     const int64_t entries = static_cast<int64_t>(tab.join_blocks) * n;
@@ -636,8 +637,8 @@ hipError_t launch_pairs_w(const DevTable &tab, const DevScratch &sc, const uint6
     const dim3 grid(build_blocks +
                     static_cast<unsigned>((entries + kJoinPairThreads - 1) / kJoinPairThreads));
     hipLaunchKernelGGL((join_pair_kernel<W, D, P, SCV>), grid, dim3(kJoinPairThreads), 0, st, tab,
-                       sc, samples, weights, log_amp, phase, n, build_blocks, hit_idx, sign_bits,
-                       sign_words);
+                       sc, samples, weights, log_amp, phase, n, build_blocks, build == 2 ? 1 : 0,
+                       hit_idx, sign_bits, sign_words);
     return hipGetLastError();
 }
 
@@ -736,7 +737,7 @@ hipError_t launch_join_prep(const DevTable &tab, const DevScratch &sc, const uin
 }
 
 hipError_t launch_join_pairs(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
-                             const int64_t *weights, bool build, const double *log_amp,
+                             const int64_t *weights, int build, const double *log_amp,
                              const double *phase, int64_t n, int precision, int32_t *hit_idx,
                              uint32_t *sign_bits, int64_t sign_words, hipStream_t st) {
     const bool dump = hit_idx || sign_bits;

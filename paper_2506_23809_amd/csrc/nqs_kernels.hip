@@ -2375,7 +2375,7 @@ hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_ite
         const JobDesc &J = h_jobs[k];
         if (!J.sc.jctl || J.n == 0) continue;
         const int pr = (J.kind & kJobIntegrals) ? NQS_FP64 : precision;
-        const hipError_t e = launch_join_pairs(J.tab, J.sc, J.samples, J.weights, false, J.log_amp,
+        const hipError_t e = launch_join_pairs(J.tab, J.sc, J.samples, J.weights, 0, J.log_amp,
                                                J.phase, J.n, pr, nullptr, nullptr, 0, st);
         if (e != hipSuccess) return e;
     }
@@ -2585,7 +2585,7 @@ EvalLaunch plan_eval(const DevTable &tab, int64_t n, bool dump, const Tuning *tu
 
 hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capacity,
                        const uint64_t *samples, const int64_t *weights, int64_t n,
-                       hipStream_t st, hipEvent_t after_grouping) {
+                       hipStream_t st, hipEvent_t after_grouping, bool join_only) {
     const int words = tab.n_qubits <= 63 ? 1 : 2;
     // with the pair join launched, its histogram kernel frees the hash slots
     // and clears the bitmaps in blocks of its own (the grouping does not use
@@ -2611,7 +2611,8 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
         // the pair join's grouping and decision come before the build, which
         // skips its insertion when the join runs
         const hipError_t e = launch_join_prep(tab, sc, samples, n,
-                                              tab.n_groups - (tab.has_diagonal ? 1 : 0), true, st);
+                                              tab.n_groups - (tab.has_diagonal ? 1 : 0),
+                                              !join_only, st);
         if (e != hipSuccess) return e;
     }
     if (after_grouping) {
@@ -2701,9 +2702,11 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
             hipLaunchKernelGGL(fill_i32_kernel, dim3(static_cast<unsigned>((cnt + 255) / 256)),
                                dim3(256), 0, st, hit_idx, cnt, -1);
         }
-        // the hash build rides in the same launch (launch_hash left it out)
-        e = launch_join_pairs(tab, sc, samples, weights, true, log_amp, phase, n, precision,
-                              hit_idx, sign_bits, sign_words, st);
+        // the hash build rides in the same launch (launch_hash left it out);
+        // a join-only launch only checks the samples there (its hash is not
+        // cleared, and nothing would read it)
+        e = launch_join_pairs(tab, sc, samples, weights, L.join_only ? 2 : 1, log_amp, phase, n,
+                              precision, hit_idx, sign_bits, sign_words, st);
         if (e != hipSuccess) return e;
     }
     if (ev.after_pairs) {
