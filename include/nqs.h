@@ -374,8 +374,8 @@ int nqs_debug_dump(nqs_ham h, int64_t n, const uint64_t *samples, const double *
  *     index).  Its cost is the sum of squared bucket sizes, independent of
  *     the table's size: for samples spread over a large sector it is far
  *     below both others.  Needs m + 1 <= 8, at most 2^21 samples, and at
- *     most 8192 entries in one partition of 2^10 buckets (a hash range of
- *     the bucket keys; about a thousand entries each on average);
+ *     most 8192 entries in one partition of 2^11 buckets (a hash range of
+ *     the bucket keys; about two thousand entries each on average);
  *     otherwise (decided on the device) the enumeration or streaming
  *     strategy runs instead.
  *   NQS_STRATEGY_AUTO (0): the pair join is launched beside the enumeration

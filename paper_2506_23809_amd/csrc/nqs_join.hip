@@ -643,16 +643,18 @@ hipError_t launch_pairs_w(const DevTable &tab, const DevScratch &sc, const uint6
 }
 
 // Partitions and tiles of a launch of n samples with 2^log2m buckets per
-// block: a partition covers 2^lshift buckets (1024, fewer for a small batch,
-// 2048 at the largest), about as many entries; the grouping kernels take at
-// most kJoinTiles tiles of a multiple of 1024 samples.
+// block: a partition covers 2^lshift buckets (2048, fewer for a small
+// batch), about as many entries (fewer, larger partitions: the sorter's
+// blocks all fit on the chip at once, and the tiles reserve fewer ranges);
+// the grouping kernels take at most kJoinTiles tiles of a multiple of 1024
+// samples.
 struct JoinGeometry {
     int lshift, parts, tile, tiles;
 };
 
 JoinGeometry join_geometry(const DevTable &tab, int64_t n, int log2m) {
     JoinGeometry g;
-    g.lshift = log2m <= 10 ? log2m : (log2m <= 20 ? 10 : log2m - 10);
+    g.lshift = log2m <= 11 ? log2m : (log2m <= 21 ? 11 : log2m - 10);
     g.parts = tab.join_blocks << (log2m - g.lshift);
     const int64_t per = (n + int64_t(kJoinTiles) * kJoinGroupThreads - 1) /
                         (int64_t(kJoinTiles) * kJoinGroupThreads);
