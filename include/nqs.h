@@ -199,13 +199,13 @@ int nqs_eloc_eval(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *
  * call's own kernels.  Two calls that overlap on one device (different
  * streams, threads or handles) race on it and give undefined results: the
  * caller serialises them.  The scratch needed grows with n (at 100 qubits
- * and 262,144 samples about 125 MB, the pair join's entries included): a
- * batch that needs more than the array holds returns NQS_E_ARG before
- * anything is launched.  Arguments, other
+ * and 262,144 samples about 160 MB, the pair join's partition regions and
+ * entries included): a batch that needs more than the array holds returns
+ * NQS_E_ARG before anything is launched.  Arguments, other
  * errors and asynchrony as nqs_eloc_eval; NQS_E_STATE also when the
  * handle's device is not the current one.
  */
-#define NQS_NOALLOC_SCRATCH_BYTES (160ull << 20)
+#define NQS_NOALLOC_SCRATCH_BYTES (192ull << 20)
 int nqs_eloc_eval_noalloc(nqs_ham h, int64_t n, const uint64_t *samples, const int64_t *weights,
                           const double *log_amp, const double *phase, double *eloc, int precision,
                           void *hip_stream);

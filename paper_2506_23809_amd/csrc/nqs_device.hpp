@@ -201,9 +201,7 @@ struct DevScratch {
     // | slot; a partition is the buckets of one key prefix,
     // key >> join_lshift, join_parts of them
     uint32_t *jcnt;             // [parts] entries per partition
-    uint32_t *jkey;             // [blocks][n] bucket key of each (block, sample)
-    uint32_t *jtbase;           // [tiles][parts] each tile's first slot in a partition
-    uint32_t *jpoff;            // [parts + 1] first entry of each partition
+    unsigned long long *jreg;   // [parts][join_cap] each partition's entries, scatter order
     // entries by partition, then bucket, then sample index
     unsigned long long *jent;   // [blocks * n] (key & (2^join_lshift - 1)) << 32 | sample
     unsigned long long *jrange; // [blocks * n] first entry of the entry's bucket |
@@ -219,6 +217,7 @@ struct DevScratch {
     int join_parts;
     int join_tile;              // samples per tile of the grouping kernels
     int join_tiles;
+    int join_cap;               // entries of a partition's region
     int join_force;             // 1: join whenever it can run, 0: when cheaper
 };
 

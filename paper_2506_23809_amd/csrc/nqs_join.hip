@@ -148,15 +148,18 @@ __device__ __forceinline__ void block_sum_max(unsigned long long &s, unsigned lo
 // ---- kernels
 
 // One block per tile of samples: the bucket key of every (block, sample),
-// the tile's entries per partition (LDS) and its reserved range in each
-// partition (one global atomic per partition it touches); also whether the
-// batch spans several (N_alpha, N_beta) sectors and the enumeration's
-// lookups for it (its spin-conserving singles and doubles), summed for the
-// decision.
+// the tile's entries per partition (LDS), its range in each partition it
+// touches (one global atomic per partition: the partition's count so far),
+// then each entry written at its place in its partition's region (regions
+// of join_cap entries, in partition order; a partition that outgrows its
+// region keeps counting but writes nothing, and the join then stands down).
+// Also whether the batch spans several (N_alpha, N_beta) sectors and the
+// enumeration's lookups for it (its spin-conserving singles and doubles),
+// summed for the decision.
 template <int W>
-__global__ __launch_bounds__(kJoinGroupThreads) void join_hist_kernel(
+__global__ __launch_bounds__(kJoinGroupThreads) void join_scatter_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n) {
-    __shared__ uint32_t hist[kJoinMaxParts];
+    __shared__ uint32_t cur[kJoinMaxParts];
     if (blockIdx.x >= static_cast<unsigned>(sc.join_tiles)) {
         // blocks beyond the tiles free the hash slots and clear the Bloom
         // bitmaps that the hash build of this launch may fill
@@ -180,18 +183,15 @@ __global__ __launch_bounds__(kJoinGroupThreads) void join_hist_kernel(
         return;
     }
     const int parts = sc.join_parts, lshift = sc.join_lshift, log2m = sc.join_log2m;
-    for (int p = threadIdx.x; p < parts; p += blockDim.x) hist[p] = 0u;
+    for (int p = threadIdx.x; p < parts; p += blockDim.x) cur[p] = 0u;
     __syncthreads();
     const int64_t t0 = static_cast<int64_t>(blockIdx.x) * sc.join_tile;
     const int64_t t1 = t0 + sc.join_tile < n ? t0 + sc.join_tile : n;
     unsigned long long probes = 0;
     for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
         const Key<W> x = load_key<W>(samples, i);
-        for (int b = 0; b < tab.join_blocks; ++b) {
-            const uint32_t k = join_bucket<W>(tab, x, b, log2m);
-            sc.jkey[static_cast<int64_t>(b) * n + i] = k;
-            atomicAdd(&hist[k >> lshift], 1u);
-        }
+        for (int b = 0; b < tab.join_blocks; ++b)
+            atomicAdd(&cur[join_bucket<W>(tab, x, b, log2m) >> lshift], 1u);
         if (tab.sector_filter) {
             const uint64_t w0 = x.w[0], w1 = W == 2 ? x.w[W - 1] : 0ull;
             const uint64_t s0 = samples[0], s1 = samples[1];
@@ -209,48 +209,29 @@ __global__ __launch_bounds__(kJoinGroupThreads) void join_hist_kernel(
         }
     }
     __syncthreads();
-    uint32_t *tbase = sc.jtbase + static_cast<int64_t>(blockIdx.x) * parts;
+    // the tile's first place in each partition it touches
     for (int p = threadIdx.x; p < parts; p += blockDim.x) {
-        const uint32_t c = hist[p];
-        if (c) tbase[p] = atomicAdd(&sc.jcnt[p], c);
+        const uint32_t c = cur[p];
+        if (c) cur[p] = atomicAdd(&sc.jcnt[p], c);
     }
     probes = wave_sum(probes);
     if ((threadIdx.x & 63) == 0 && probes)
         atomicAdd(&sc.jctl[kJoinCtlProbeSlots + (blockIdx.x * 16 + (threadIdx.x >> 6)) % 64],
                   probes);
-}
-
-// One block per tile: the partition starts (every block scans the
-// partition counts itself; block 0 stores them), then each entry of the
-// tile goes to the next free place of its partition's range for the tile.
-__global__ __launch_bounds__(kJoinGroupThreads) void join_place_kernel(DevTable tab, DevScratch sc,
-                                                                       int64_t n) {
-    __shared__ uint32_t base[kJoinMaxParts];
-    const int parts = sc.join_parts, lshift = sc.join_lshift;
-    const int per = (parts + blockDim.x - 1) / blockDim.x;
-    const int p0 = threadIdx.x * per;
-    unsigned long long own = 0;
-    for (int p = p0; p < p0 + per && p < parts; ++p) own += sc.jcnt[p];
-    unsigned long long total;
-    unsigned long long run = block_exclusive_scan(own, &total);
-    const uint32_t *tbase = sc.jtbase + static_cast<int64_t>(blockIdx.x) * parts;
-    for (int p = p0; p < p0 + per && p < parts; ++p) {
-        if (blockIdx.x == 0) sc.jpoff[p] = static_cast<uint32_t>(run);
-        // a partition this tile has no entry in is never looked up
-        base[p] = static_cast<uint32_t>(run) + tbase[p];
-        run += sc.jcnt[p];
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc.jpoff[parts] = static_cast<uint32_t>(total);
     __syncthreads();
+    // the entries (keys computed again: cheaper than keeping them)
     const uint32_t lmask = (1u << lshift) - 1u;
-    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * sc.join_tile;
-    const int64_t t1 = t0 + sc.join_tile < n ? t0 + sc.join_tile : n;
+    const uint32_t cap = static_cast<uint32_t>(sc.join_cap);
     for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
+        const Key<W> x = load_key<W>(samples, i);
         for (int b = 0; b < tab.join_blocks; ++b) {
-            const uint32_t k = sc.jkey[static_cast<int64_t>(b) * n + i];
-            const uint32_t pos = atomicAdd(&base[k >> lshift], 1u);
-            sc.jent[pos] = (static_cast<unsigned long long>(k & lmask) << 32) |
-                           static_cast<unsigned long long>(i);
+            const uint32_t k = join_bucket<W>(tab, x, b, log2m);
+            const uint32_t part = k >> lshift;
+            const uint32_t pos = atomicAdd(&cur[part], 1u);
+            if (pos < cap)
+                sc.jreg[static_cast<int64_t>(part) * cap + pos] =
+                    (static_cast<unsigned long long>(k & lmask) << 32) |
+                    static_cast<unsigned long long>(i);
         }
     }
 }
@@ -259,11 +240,13 @@ __global__ __launch_bounds__(kJoinGroupThreads) void join_place_kernel(DevTable 
 // sample); thread 0 writes its statistics.
 __device__ __forceinline__ void join_sort_partition(const DevScratch &sc,
                                                     const uint64_t *__restrict__ samples, int p,
-                                                    uint32_t c) {
+                                                    uint32_t c, uint32_t s0) {
     __shared__ uint32_t buf[kJoinPartCap];
     __shared__ uint32_t cnt[kJoinMaxLocal];
     __shared__ uint32_t fill[kJoinMaxLocal];
-    const uint32_t s0 = sc.jpoff[p];
+    // the partition's entries, in its region (scatter order)
+    const unsigned long long *__restrict__ reg =
+        sc.jreg + static_cast<int64_t>(p) * static_cast<uint32_t>(sc.join_cap);
     const int L = 1 << sc.join_lshift;
     for (int u = threadIdx.x; u < L; u += blockDim.x) {
         cnt[u] = 0u;
@@ -271,7 +254,7 @@ __device__ __forceinline__ void join_sort_partition(const DevScratch &sc,
     }
     __syncthreads();
     for (uint32_t u = threadIdx.x; u < c; u += blockDim.x)
-        atomicAdd(&cnt[static_cast<uint32_t>(sc.jent[s0 + u] >> 32)], 1u);
+        atomicAdd(&cnt[static_cast<uint32_t>(reg[u] >> 32)], 1u);
     __syncthreads();
     // bucket starts (exclusive scan of the counts), packed with the sizes
     const int per = (L + blockDim.x - 1) / blockDim.x;
@@ -298,7 +281,7 @@ __device__ __forceinline__ void join_sort_partition(const DevScratch &sc,
     __syncthreads();
     const unsigned long long mx_all = s_mx;
     for (uint32_t u = threadIdx.x; u < c; u += blockDim.x) {
-        const unsigned long long e = sc.jent[s0 + u];
+        const unsigned long long e = reg[u];
         const uint32_t loc = static_cast<uint32_t>(e >> 32);
         const uint32_t at = (cnt[loc] & 0xFFFFu) + atomicAdd(&fill[loc], 1u);
         buf[at] = (loc << 21) | static_cast<uint32_t>(e);
@@ -415,6 +398,12 @@ __global__ __launch_bounds__(kJoinSortThreads) void join_sort_kernel(
     DevScratch sc, const uint64_t *__restrict__ samples) {
     const int p = blockIdx.x;
     const uint32_t c = sc.jcnt[p];
+    // the partition's first output place: the entries of the partitions
+    // before it (every sample has one entry per block, so they all fit)
+    unsigned long long before = 0;
+    for (int q = threadIdx.x; q < p; q += blockDim.x) before += sc.jcnt[q];
+    unsigned long long s0;
+    (void)block_exclusive_scan(before, &s0);
     if (c > static_cast<uint32_t>(kJoinPartCap)) {
         if (threadIdx.x == 0) {
             sc.jstat[2 * p] = static_cast<unsigned long long>(c) * c;
@@ -423,7 +412,7 @@ __global__ __launch_bounds__(kJoinSortThreads) void join_sort_kernel(
         }
         return;
     }
-    join_sort_partition(sc, samples, p, c);
+    join_sort_partition(sc, samples, p, c, static_cast<uint32_t>(s0));
 }
 
 // One block: the decision, once every partition is sorted.  (Taking it in
@@ -618,8 +607,8 @@ hipError_t launch_join_prep_w(const DevTable &tab, const DevScratch &sc,
         span = span > efw ? span : efw;
         extra = static_cast<unsigned>((span + 4 * kJoinGroupThreads - 1) / (4 * kJoinGroupThreads));
     }
-    hipLaunchKernelGGL(join_hist_kernel<W>, dim3(tiles.x + extra), blk, 0, st, tab, sc, samples, n);
-    hipLaunchKernelGGL(join_place_kernel, tiles, blk, 0, st, tab, sc, n);
+    hipLaunchKernelGGL(join_scatter_kernel<W>, dim3(tiles.x + extra), blk, 0, st, tab, sc, samples,
+                       n);
     hipLaunchKernelGGL(join_sort_kernel, dim3(static_cast<unsigned>(sc.join_parts)),
                        dim3(kJoinSortThreads), 0, st, sc, samples);
     hipLaunchKernelGGL(join_decide_kernel, dim3(1), blk, 0, st, tab, sc, samples, n, g_eff);
@@ -649,7 +638,7 @@ hipError_t launch_pairs_w(const DevTable &tab, const DevScratch &sc, const uint6
 // the grouping kernels take at most kJoinTiles tiles of a multiple of 1024
 // samples.
 struct JoinGeometry {
-    int lshift, parts, tile, tiles;
+    int lshift, parts, tile, tiles, cap;
 };
 
 JoinGeometry join_geometry(const DevTable &tab, int64_t n, int log2m) {
@@ -661,6 +650,9 @@ JoinGeometry join_geometry(const DevTable &tab, int64_t n, int log2m) {
     g.tile = static_cast<int>((per < 1 ? 1 : per) * kJoinGroupThreads);
     g.tiles = static_cast<int>((n + g.tile - 1) / g.tile);
     if (g.tiles < 1) g.tiles = 1;
+    // a partition's region: as many entries as the sorter takes (a partition
+    // belongs to one block, so it never has more than n)
+    g.cap = static_cast<int>(n < kJoinPartCap ? n : kJoinPartCap);
     return g;
 }
 
@@ -675,21 +667,19 @@ int join_log2m_for(int64_t n) {
 namespace {
 
 // Byte sizes of the join's pieces, in layout order.
-constexpr int kJoinPieces = 10;
+constexpr int kJoinPieces = 8;
 void join_sizes(const DevTable &tab, int64_t n, int log2m, size_t sizes[kJoinPieces]) {
     const JoinGeometry g = join_geometry(tab, n, log2m);
     const size_t entries = static_cast<size_t>(tab.join_blocks) * static_cast<size_t>(n);
     const size_t parts = static_cast<size_t>(g.parts);
     sizes[0] = 4 * parts;                                 // jcnt
-    sizes[1] = 4 * entries;                               // jkey
-    sizes[2] = 4 * parts * static_cast<size_t>(g.tiles);  // jtbase
-    sizes[3] = 4 * (parts + 1);                           // jpoff
-    sizes[4] = 8 * entries;                               // jent
-    sizes[5] = 8 * entries;                               // jrange
-    sizes[6] = 16 * parts;                                // jstat
-    sizes[7] = 8 * static_cast<size_t>(kJoinCtl);         // jctl
-    sizes[8] = 16 * entries;                              // jkeys
-    sizes[9] = 4 * ((entries + 31) / 32);                 // jhit
+    sizes[1] = 8 * parts * static_cast<size_t>(g.cap);    // jreg
+    sizes[2] = 8 * entries;                               // jent
+    sizes[3] = 8 * entries;                               // jrange
+    sizes[4] = 16 * parts;                                // jstat
+    sizes[5] = 8 * static_cast<size_t>(kJoinCtl);         // jctl
+    sizes[6] = 16 * entries;                              // jkeys
+    sizes[7] = 4 * ((entries + 31) / 32);                 // jhit
 }
 
 }  // namespace
@@ -714,21 +704,20 @@ void join_scratch_layout(const DevTable &tab, int64_t n, int log2m, char *base, 
     }
     const JoinGeometry g = join_geometry(tab, n, log2m);
     sc->jcnt = reinterpret_cast<uint32_t *>(base + off[0]);
-    sc->jkey = reinterpret_cast<uint32_t *>(base + off[1]);
-    sc->jtbase = reinterpret_cast<uint32_t *>(base + off[2]);
-    sc->jpoff = reinterpret_cast<uint32_t *>(base + off[3]);
-    sc->jent = reinterpret_cast<unsigned long long *>(base + off[4]);
-    sc->jrange = reinterpret_cast<unsigned long long *>(base + off[5]);
-    sc->jstat = reinterpret_cast<unsigned long long *>(base + off[6]);
-    sc->jctl = reinterpret_cast<unsigned long long *>(base + off[7]);
-    sc->jkeys = reinterpret_cast<uint64_t *>(base + off[8]);
-    sc->jhit = reinterpret_cast<uint32_t *>(base + off[9]);
+    sc->jreg = reinterpret_cast<unsigned long long *>(base + off[1]);
+    sc->jent = reinterpret_cast<unsigned long long *>(base + off[2]);
+    sc->jrange = reinterpret_cast<unsigned long long *>(base + off[3]);
+    sc->jstat = reinterpret_cast<unsigned long long *>(base + off[4]);
+    sc->jctl = reinterpret_cast<unsigned long long *>(base + off[5]);
+    sc->jkeys = reinterpret_cast<uint64_t *>(base + off[6]);
+    sc->jhit = reinterpret_cast<uint32_t *>(base + off[7]);
     sc->join_log2m = log2m;
     sc->join_n = n;
     sc->join_lshift = g.lshift;
     sc->join_parts = g.parts;
     sc->join_tile = g.tile;
     sc->join_tiles = g.tiles;
+    sc->join_cap = g.cap;
 }
 
 hipError_t launch_join_prep(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
