@@ -330,8 +330,8 @@ hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunc
         return e;
     if (prof && (e = hipEventRecord(h->ev[1], s)) != hipSuccess) return e;
     const int64_t sign_words = (h->dt.n_terms + 31) / 32;
-    nqs::EvalStageEvents stages{prof ? h->ev[2] : nullptr, prof ? h->ev[5] : nullptr,
-                                nullptr};
+    nqs::EvalStageEvents stages{prof ? h->ev[2] : nullptr, prof ? h->ev[5] : nullptr, nullptr,
+                                prof ? h->ev[3] : nullptr};
     // with the energy, its combining kernel writes the result and the error
     // word straight to the handle's pinned host buffer (no copy to wait for)
     const nqs::EnergyFused ef =
@@ -346,7 +346,8 @@ hipError_t issue_eval(nqs_ham h, const nqs::DevScratch &sc, const nqs::EvalLaunc
     if ((e = nqs::launch_eloc(h->dt, sc, L, samples, weights, log_amp, phase, eloc, precision,
                               hit_idx, sign_bits, sign_words, stages, ef, s)) != hipSuccess)
         return e;
-    if (prof && (e = hipEventRecord(h->ev[3], s)) != hipSuccess) return e;
+    // (ev[3], after the finish kernel, is recorded inside the launch: an
+    // energy's combining kernel follows it)
     return hipSuccess;
 }
 

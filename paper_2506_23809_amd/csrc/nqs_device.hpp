@@ -308,6 +308,7 @@ struct EvalStageEvents {
     hipEvent_t after_lookup;
     hipEvent_t after_pairs;     // after the pair join's pair kernel (when launched)
     hipEvent_t after_grouping;  // after the pair join's grouping (before the hash build)
+    hipEvent_t after_finish;    // after the finish kernel (before an energy's combining)
 };
 
 // Launch parameters chosen by the autotuner; 0 means the built-in default

@@ -2815,6 +2815,7 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
                 hipLaunchKernelGGL((eloc_finish_mfma_kernel<2, NQS_FP64>), mgrid, mblk, 0, st, tab,
                                    sc, samples, n, chunks, fb, eloc, ef.weights, ef.part);
         }
+        if (ev.after_finish && (e = hipEventRecord(ev.after_finish, st)) != hipSuccess) return e;
         if (ef.part)
             hipLaunchKernelGGL(energy_combine_kernel, dim3(1), dim3(kRedThreads), 0, st, ef.part,
                                static_cast<int64_t>(mgrid.x), ef.out, sc.err, ef.err_out, ef.seq,
@@ -2851,6 +2852,7 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
     }
 #undef NQS_FINISH
 #undef NQS_FINISH_SC
+    if (ev.after_finish && (e = hipEventRecord(ev.after_finish, st)) != hipSuccess) return e;
     if (ep)
         hipLaunchKernelGGL(energy_combine_kernel, dim3(1), dim3(kRedThreads), 0, st, ep,
                            static_cast<int64_t>(fgrid.x), ef.out, sc.err, ef.err_out, ef.seq,
