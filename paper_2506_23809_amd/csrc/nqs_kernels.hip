@@ -1705,12 +1705,14 @@ __device__ __forceinline__ double diag_occ_mfma(const DevTable &tab, const Key<W
         const uint64_t m0 = __shfl(w0, 16 * h + c), m1 = __shfl(w1, 16 * h + c);
         N[h][0] = spread_bits16(static_cast<uint32_t>(m0 >> (16 * g)) & 0xFFFFu);
         N[h][1] = spread_bits16(static_cast<uint32_t>(m1 >> (16 * g)) & 0xFFFFu);
+        // (row group g of tile jt: bits 16 jt + 4 g .. + 3, inside one
+        // 32-bit half of the sample: one bit-field extract each)
+        const uint32_t half[4] = {static_cast<uint32_t>(m0), static_cast<uint32_t>(m0 >> 32),
+                                  static_cast<uint32_t>(m1), static_cast<uint32_t>(m1 >> 32)};
         uint32_t v = 0;
 #pragma unroll
-        for (int jt = 0; jt < 8; ++jt) {
-            const uint64_t wd = jt < 4 ? m0 : m1;
-            v |= static_cast<uint32_t>((wd >> ((16 * jt + 4 * g) & 63)) & 0xFull) << (4 * jt);
-        }
+        for (int jt = 0; jt < 8; ++jt)
+            v |= __builtin_amdgcn_ubfe(half[jt >> 1], 16 * (jt & 1) + 4 * g, 4) << (4 * jt);
         mk[h] = v;
     }
     int T[H][kDiagLimbs];
