@@ -142,13 +142,15 @@ int nqs_table_host(int n_qubits, int64_t n_terms, const uint64_t *x_masks,
  * Host-only form of the occupation-form diagonal that the finish kernel
  * evaluates on the matrix cores (no device needed).  For a table whose X = 0
  * group has only Z strings of at most two qubits, Z_i = 1 - 2 n_i turns the
- * group into d0 + sum_{i <= j} n_i n_j U[j][i]; the U are stored as 64-bit
- * fixed point (U 2^S rounded, S the largest integer keeping every |U| 2^S
- * below 2^62) in eight balanced base-256 int8 digits, least significant
- * first, as 16 x 16 x 64 int8 MFMA operand tiles: for column tile jt (j in
- * [16 jt, 16 jt + 16), ceil(n_qubits / 16) of them) its k-blocks kb of 64
- * rows i (one for jt < 4, two after), then per digit 64 lanes x 16 bytes,
- * lane L byte b holding the digit of U[16 jt + L % 16][64 kb + 16 (L / 16)
+ * group into d0 + sum_{i <= j} n_i n_j U[j][i]; the U are stored as fixed
+ * point (U 2^S rounded, S the largest integer keeping every |U| 2^S below
+ * 2^59) in four base-2^15 digits, least significant first (the lower three
+ * balanced in [-2^14, 2^14), the top one in [-2^14, 2^14]), each digit E as
+ * two int8 byte planes a, b with E = a - 128 b, as 16 x 16 x 64 int8 MFMA
+ * operand tiles: for column tile jt (j in [16 jt, 16 jt + 16),
+ * ceil(n_qubits / 16) of them) its k-blocks kb of 64 rows i (one for jt < 4,
+ * two after), then per digit its planes a and b, each 64 lanes x 16 bytes,
+ * lane L byte b holding the plane's byte for U[16 jt + L % 16][64 kb + 16 (L / 16)
  * + b] (zero where i > j or outside the register).  Call with tiles NULL to
  * obtain *n_bytes (0: the table has no such form), then with a buffer of
  * that size.  *d0 receives d0 and *scale 2^-S.  Same arguments, validation

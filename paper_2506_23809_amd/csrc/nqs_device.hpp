@@ -10,8 +10,8 @@
 namespace nqs {
 
 // The occupation-form diagonal for the matrix cores: digit tiles of the
-// 16 x 16 x 64 int8 MFMA (64 lanes x 16 bytes each, kDiagLimbs digits; see
-// build_diag_tiles).  Column tile jt (qubits j in [16 jt, 16 jt + 16))
+// 16 x 16 x 64 int8 MFMA (64 lanes x 16 bytes each, kDiagLimbs byte planes:
+// two per base-2^15 digit; see build_diag_tiles).  Column tile jt (qubits j in [16 jt, 16 jt + 16))
 // needs the rows i <= j: one k-block of 64 rows for jt < 4, two after.
 constexpr int kDiagTileBytes = 64 * 16;
 __host__ __device__ constexpr int diag_mfma_tiles(int jtiles) {
@@ -56,7 +56,7 @@ struct DevTable {
     int diag_occ;
     const double *diag;
     const float *diag32;
-    // the same form for the matrix cores (see kDiagLimbs): digit tiles
+    // the same form for the matrix cores (see kDiagDigits): digit tiles
     // [diag_mfma_tiles(diag_jtiles)][kDiagLimbs][64][16], 2^-S, and the
     // column tiles (ceil(n_qubits / 16); 0 without the form)
     const int8_t *diag_q8;

@@ -1631,29 +1631,32 @@ __device__ __forceinline__ diag_v4i spread_bits16(uint32_t v) {
 // The occupation-form diagonal of the 64 samples of a wave (each lane's x;
 // zero for a lane without a sample) on the matrix cores, called by every
 // lane of the wave together.  With n the 0/1 occupations and Q the
-// fixed-point terms (see kDiagLimbs), the value is
-//   d0 + 2^-S sum_j n_j sum_{i <= j} n_i Q[j][i].
-// Per digit l, column tile jt and group of 16 samples: C = D_l N (16 x 16
-// x 64 int8 products; D_l the digit tile, rows j, k = i; N the samples'
-// bits, k = i, one column per sample), so C[j][s] = sum_i D_l[j][i] n_s[i];
-// each lane masks its four C[j][s] by n_s[j] and adds them to its digit
-// sum.  All of it is exact integer arithmetic (|C| <= 2^14, a digit sum
-// below 2^21), the digits are recombined in 64-bit integers and the total
-// is rounded once to FP64, so the result does not depend on any order of
-// summation.  B holds the digit tiles (LDS or global memory).
+// fixed-point terms in base-2^15 digits E_l (see kDiagDigits), the value is
+//   d0 + 2^-S sum_l 2^(15 l) sum_j n_j sum_{i <= j} n_i E_l[j][i].
+// Per digit l, column tile jt and group of 16 samples: C = E_l N (16 x 16
+// products over k = i; N the samples' bits, one column per sample), so
+// C[j][s] = sum_i E_l[j][i] n_s[i].  E_l = a - 128 b is held as two int8
+// byte planes: one chain of MFMAs multiplies plane a by N and plane b by
+// -128 N (the bits as bytes 0x80) into the same accumulator, so C arrives
+// whole in 32 bits; each lane masks its four C[j][s] by n_s[j] and adds them
+// to its digit sum.  All of it is exact integer arithmetic (|C| <= 2^21,
+// a digit sum below 2^28), the digits are recombined in 64-bit integers and
+// the total is rounded once to FP64, so the result does not depend on any
+// order of summation.  B holds the digit tiles (LDS or global memory).
 //
 // Lane layout of the instruction: lane L holds row L % 16 of A and column
 // L % 16 of B, with k in [16 (L / 16), +16) of the 64-wide k-block (byte
 // b = k); C row 4 (L / 16) + r, column L % 16 in its r-th value.  The digit
 // tiles are stored in that A layout.
 // One column tile jt of diag_occ_mfma for H groups of 16 samples: the
-// digit tiles at B + t (KB k-blocks), the samples' bit operands N, the row
-// masks mk (bit 4 jt + r: n_s[j] for the lane's row j = 16 jt + 4 g + r),
-// the digit sums T.
+// digit tiles at B + t (KB k-blocks), the samples' bit operands N and M
+// (-128 N), the row masks mk (bit 4 jt + r: n_s[j] for the lane's row
+// j = 16 jt + 4 g + r), the digit sums T.
 template <int H, int KB>
 __device__ __forceinline__ void diag_mfma_tile(const diag_v4i *__restrict__ B, int t, int jt,
                                                int lane, const diag_v4i (&N)[H][2],
-                                               const uint32_t (&mk)[H], int (&T)[H][kDiagLimbs]) {
+                                               const diag_v4i (&M)[H][2],
+                                               const uint32_t (&mk)[H], int (&T)[H][kDiagDigits]) {
     const diag_v4i zero = {0, 0, 0, 0};
     // the row masks as 0/1 multipliers (hidden from the optimiser, so that
     // each masked add stays a 24-bit multiply-add)
@@ -1667,15 +1670,22 @@ __device__ __forceinline__ void diag_mfma_tile(const diag_v4i *__restrict__ B, i
         }
     }
 #pragma unroll
-    for (int l = 0; l < kDiagLimbs; ++l) {
-        diag_v4i a[KB];
+    for (int l = 0; l < kDiagDigits; ++l) {
+        diag_v4i a[KB], b[KB];
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) a[kb] = B[((t + kb) * kDiagLimbs + l) * 64 + lane];
+        for (int kb = 0; kb < KB; ++kb) {
+            a[kb] = B[((t + kb) * kDiagLimbs + 2 * l) * 64 + lane];
+            b[kb] = B[((t + kb) * kDiagLimbs + 2 * l + 1) * 64 + lane];
+        }
 #pragma unroll
         for (int h = 0; h < H; ++h) {
+            // both planes of every k-block into one accumulator
             diag_v4i acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0], N[h][0], zero, 0, 0, 0);
-            if constexpr (KB == 2)
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(b[0], M[h][0], acc, 0, 0, 0);
+            if constexpr (KB == 2) {
                 acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[1], N[h][1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(b[1], M[h][1], acc, 0, 0, 0);
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 T[h][l] = __mul24(acc[r], bit[h][r]) + T[h][l];
@@ -1696,15 +1706,19 @@ __device__ __forceinline__ double diag_occ_mfma(const DevTable &tab, const Key<W
     const uint64_t w0 = x.w[0], w1 = W == 2 ? x.w[W - 1] : 0ull;
     const int jtiles = tab.diag_jtiles;
     // the column samples 16 h + c: their bits as the B operands of both
-    // k-blocks, and the lane's row masks (bits 16 jt + 4 g + r of them,
-    // packed as bit 4 jt + r)
-    diag_v4i N[H][2];
+    // k-blocks (bytes 0/1 in N, 0/0x80 in M), and the lane's row masks
+    // (bits 16 jt + 4 g + r of them, packed as bit 4 jt + r)
+    diag_v4i N[H][2], M[H][2];
     uint32_t mk[H];
 #pragma unroll
     for (int h = 0; h < H; ++h) {
         const uint64_t m0 = __shfl(w0, 16 * h + c), m1 = __shfl(w1, 16 * h + c);
         N[h][0] = spread_bits16(static_cast<uint32_t>(m0 >> (16 * g)) & 0xFFFFu);
         N[h][1] = spread_bits16(static_cast<uint32_t>(m1 >> (16 * g)) & 0xFFFFu);
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) M[h][kb][v] = N[h][kb][v] << 7;
         // (row group g of tile jt: bits 16 jt + 4 g .. + 3, inside one
         // 32-bit half of the sample: one bit-field extract each)
         const uint32_t half[4] = {static_cast<uint32_t>(m0), static_cast<uint32_t>(m0 >> 32),
@@ -1715,33 +1729,31 @@ __device__ __forceinline__ double diag_occ_mfma(const DevTable &tab, const Key<W
             v |= __builtin_amdgcn_ubfe(half[jt >> 1], 16 * (jt & 1) + 4 * g, 4) << (4 * jt);
         mk[h] = v;
     }
-    int T[H][kDiagLimbs];
+    int T[H][kDiagDigits];
 #pragma unroll
     for (int h = 0; h < H; ++h)
 #pragma unroll
-        for (int l = 0; l < kDiagLimbs; ++l) T[h][l] = 0;
+        for (int l = 0; l < kDiagDigits; ++l) T[h][l] = 0;
     // column tiles 0..3 reach rows i < 64 (one k-block), later ones two
     const int j1 = jtiles < 4 ? jtiles : 4;
-    for (int jt = 0; jt < j1; ++jt) diag_mfma_tile<H, 1>(B, jt, jt, lane, N, mk, T);
-    for (int jt = 4; jt < jtiles; ++jt) diag_mfma_tile<H, 2>(B, 4 + 2 * (jt - 4), jt, lane, N, mk, T);
+    for (int jt = 0; jt < j1; ++jt) diag_mfma_tile<H, 1>(B, jt, jt, lane, N, M, mk, T);
+    for (int jt = 4; jt < jtiles; ++jt)
+        diag_mfma_tile<H, 2>(B, 4 + 2 * (jt - 4), jt, lane, N, M, mk, T);
     double mine = 0.0;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-        // digits 0..3 and 4..7 recombined (each below 2^46 in magnitude),
-        // then summed over the four row groups of the lane's column
-        long long lo = 0, hi = 0;
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            lo += static_cast<long long>(T[h][l]) << (8 * l);
-            hi += static_cast<long long>(T[h][l + 4]) << (8 * l);
-        }
+        // digits 0, 1 and 2, 3 recombined (each pair below 2^44 in
+        // magnitude), then summed over the four row groups of the lane's
+        // column
+        long long lo = static_cast<long long>(T[h][0]) + (static_cast<long long>(T[h][1]) << 15);
+        long long hi = static_cast<long long>(T[h][2]) + (static_cast<long long>(T[h][3]) << 15);
         lo += __shfl_xor(lo, 16);
         hi += __shfl_xor(hi, 16);
         lo += __shfl_xor(lo, 32);
         hi += __shfl_xor(hi, 32);
         // both terms exact in FP64, one rounding of the exact total; the
         // lane of sample 16 h + c (row group h) keeps it
-        const double v = static_cast<double>(lo) + static_cast<double>(hi) * 4294967296.0;
+        const double v = static_cast<double>(lo) + static_cast<double>(hi) * 1073741824.0;
         if (g == h) mine = v;
     }
     return tab.diag[0] + mine * tab.diag_scale;
@@ -2076,16 +2088,23 @@ __global__ __launch_bounds__(kFinishMfmaThreads) void eloc_finish_mfma_kernel(
     int64_t n_chunks, int enum_on, double *__restrict__ eloc, const int64_t *__restrict__ weights,
     double *__restrict__ epart) {
     __shared__ diag_v4i tiles[kDiagMaxTiles * kDiagLimbs * 64];
+    // the sample first: its load overlaps the staging of the tiles
+    Key<W> x;
+#pragma unroll
+    for (int w = 0; w < W; ++w) x.w[w] = 0ull;
+    {
+        const int64_t i0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+        if (i0 < n) x = load_key<W>(samples, i0);
+    }
     const int words = diag_mfma_tiles(tab.diag_jtiles) * kDiagLimbs * 64;
     const diag_v4i *src = reinterpret_cast<const diag_v4i *>(tab.diag_q8);
     for (int k = threadIdx.x; k < words; k += blockDim.x) tiles[k] = src[k];
     __syncthreads();
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    Key<W> x;
-#pragma unroll
-    for (int w = 0; w < W; ++w) x.w[w] = 0ull;
-    if (i < n) x = load_key<W>(samples, i);
     const double d = diag_occ_mfma<W>(tab, x, tiles);
+    // the index again (two registers not held across the diagonal)
+    unsigned tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + tid;
     finish_one<W, false, P, false>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc, nullptr,
                                    nullptr, 0, i, nullptr, nullptr, 0, nullptr, nullptr, true, d);
     if (epart) {

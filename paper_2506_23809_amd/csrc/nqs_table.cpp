@@ -333,7 +333,7 @@ void build_diag_tiles(const HostTable &T, std::vector<int8_t> *out, double *scal
         for (int i = 0; i <= j; ++i) maxabs = std::max(maxabs, std::fabs(u(j, i)));
     int e = 0;
     if (maxabs > 0.0) std::frexp(maxabs, &e);  // maxabs < 2^e
-    const int S = maxabs > 0.0 ? 62 - e : 0;
+    const int S = maxabs > 0.0 ? kDiagBits - e : 0;
     *scale = std::ldexp(1.0, -S);
     const int tiles = jtiles <= 4 ? jtiles : 4 + 2 * (jtiles - 4);
     out->assign(size_t(tiles) * kDiagLimbs * 64 * 16, 0);
@@ -344,13 +344,25 @@ void build_diag_tiles(const HostTable &T, std::vector<int8_t> *out, double *scal
             for (int L = 0; L < 64; ++L) {
                 for (int b = 0; b < 16; ++b) {
                     const int j = 16 * jt + L % 16, i = 64 * kb + 16 * (L / 16) + b;
+                    // |q| < 2^kDiagBits (a double below 2^59 is at most
+                    // 2^59 - 64, so rounding keeps it there)
                     int64_t q = std::llround(std::ldexp(u(j, i), S));
-                    for (int l = 0; l < kDiagLimbs; ++l) {
-                        int d = static_cast<int>(q & 0xFF);
-                        if (d >= 128) d -= 256;
-                        q = (q - d) / 256;
-                        (*out)[((size_t(t) * kDiagLimbs + l) * 64 + L) * 16 + b] =
-                            static_cast<int8_t>(d);
+                    for (int l = 0; l < kDiagDigits; ++l) {
+                        // base-2^15 digit: balanced for the lower three, the
+                        // rest for the top one (then within [-2^14, 2^14])
+                        int64_t E = q;
+                        if (l + 1 < kDiagDigits) {
+                            E = ((q + 16384) & 32767) - 16384;
+                            q = (q - E) / 32768;
+                        }
+                        // E = a - 128 b with a, b int8: b the nearest
+                        // multiple's quotient, kept in range at E = -2^14
+                        int64_t bq = -((E + 64) >> 7);
+                        if (bq > 127) bq = 127;
+                        const int64_t a = E + 128 * bq;
+                        const size_t at = (size_t(t) * kDiagLimbs + 2 * l) * 64 + L;
+                        (*out)[at * 16 + b] = static_cast<int8_t>(a);
+                        (*out)[(at + 64) * 16 + b] = static_cast<int8_t>(bq);
                     }
                 }
             }

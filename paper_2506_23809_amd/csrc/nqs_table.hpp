@@ -75,14 +75,21 @@ void build_diag_occ(HostTable *T);
 // The occupation form as the digit tiles of the matrix-core diagonal: the
 // terms U[j][i] (i <= j < nq; i == j: d[1 + j], the single terms; i < j:
 // the pair terms) times 2^S, with S the largest integer keeping every
-// |U| 2^S below 2^62, rounded to 64-bit integers and split into kDiagLimbs
-// balanced base-256 digits (in [-128, 127], least significant first).
+// |U| 2^S below 2^kDiagBits, rounded to integers q and written in
+// kDiagDigits base-2^15 digits E_l (least significant first; the lower ones
+// balanced in [-2^14, 2^14), the top one in [-2^14, 2^14]), each digit as two
+// int8 byte planes, E = a - 128 b.  The MFMA multiplies plane a by the
+// samples' 0/1 bits and plane b by the same bits times -128 into one
+// accumulator, so that one 32-bit sum per digit carries both planes.
 // Tiles: for column tile jt (j in [16 jt, 16 jt + 16), ceil(nq / 16) of
 // them) the k-blocks kb of 64 rows i (one for jt < 4, two after), in that
-// order; per tile and digit, lane L holds in byte b the digit of
-// U[16 jt + L % 16][64 kb + 16 (L / 16) + b] (the A-operand layout of the
-// 16 x 16 x 64 int8 MFMA).  *scale = 2^-S.  Empty without the form.
-constexpr int kDiagLimbs = 8;
+// order; per tile, digit l and plane p (a, then b: plane 2 l + p), lane L
+// holds in byte b the plane's byte for U[16 jt + L % 16][64 kb + 16 (L / 16)
+// + b] (the A-operand layout of the 16 x 16 x 64 int8 MFMA).  *scale =
+// 2^-S.  Empty without the form.
+constexpr int kDiagDigits = 4;
+constexpr int kDiagLimbs = 2 * kDiagDigits;  // byte planes
+constexpr int kDiagBits = 59;
 void build_diag_tiles(const HostTable &T, std::vector<int8_t> *out, double *scale);
 
 // Sector key: half of popc(X & alpha) | half of popc(X & beta) << 8, or

@@ -3,12 +3,15 @@ host (nqs_diag_tiles_host), against the diagonal's definition.
 
 The finish kernel evaluates the X = 0 group of a JW molecular table as
 d0 + sum_{i <= j} n_i n_j U[j][i] on the matrix cores, from U stored as
-64-bit fixed point in eight int8 digits.  Here, on the CPU:
-  * the digits decode (least significant first, balanced base 256) to
-    integers Q with |Q| < 2^62, and Q * scale is U rounded to the grid,
-    where U is rewritten in this test from the Z strings (c Z_i = c (1 - 2 n_i),
-    c Z_i Z_j = c (1 - 2 n_i)(1 - 2 n_j)); zero above the diagonal and
-    outside the register; the grid is the finest that keeps |Q| below 2^62;
+fixed point in four base-2^15 digits, each held as two int8 byte planes
+(E = a - 128 b).  Here, on the CPU:
+  * the planes decode (digit l weighs 2^(15 l); plane a once, plane b
+    times -128) to integers Q with |Q| < 2^59, and Q * scale is U rounded to
+    the grid, where U is rewritten in this test from the Z strings
+    (c Z_i = c (1 - 2 n_i), c Z_i Z_j = c (1 - 2 n_i)(1 - 2 n_j)); zero above
+    the diagonal and outside the register; the grid is the finest that
+    keeps |Q| below 2^59; every digit lies in [-2^14, 2^14] (so that the
+    kernel's 32-bit sums cannot overflow);
   * the exact integer sum over the occupied pairs, scaled once, equals the
     Z-string sum sum_t c_t (-1)^{popc(Z_t & x)} of the X = 0 terms (the
     definition, no rewrite) within 1e-13 of D = sum_t |c_t|.
@@ -24,7 +27,9 @@ import pytest
 import paper_2506_23809_amd as nqs
 import workloads as W
 
-LIMBS = 8
+DIGITS = 4
+PLANES = 2 * DIGITS
+GRID_BITS = 59
 
 
 def _tile_order(jtiles):
@@ -33,20 +38,22 @@ def _tile_order(jtiles):
 
 
 def _decode(tiles, nq):
-    """Q[j][i] (Python ints) from the digit tiles; also checks the digit range
-    and that every stored entry outside i <= j < nq is zero."""
+    """Q[j][i] (Python ints) from the digit tiles; also checks the plane and
+    digit ranges and that every stored entry outside i <= j < nq is zero."""
     jtiles = (nq + 15) // 16
     order = _tile_order(jtiles)
-    assert tiles.size == len(order) * LIMBS * 64 * 16
-    t = tiles.reshape(len(order), LIMBS, 64, 16).astype(np.int64)
+    assert tiles.size == len(order) * PLANES * 64 * 16
+    t = tiles.reshape(len(order), DIGITS, 2, 64, 16).astype(np.int64)
     assert t.min() >= -128 and t.max() <= 127
-    weights = np.array([256 ** l for l in range(LIMBS)], dtype=object)
+    digits = t[:, :, 0] - 128 * t[:, :, 1]
+    assert np.abs(digits).max() <= 2 ** 14
+    weights = np.array([2 ** (15 * l) for l in range(DIGITS)], dtype=object)
     Q = {}
     for k, (jt, kb) in enumerate(order):
         for L in range(64):
             for b in range(16):
                 j, i = 16 * jt + L % 16, 64 * kb + 16 * (L // 16) + b
-                q = int(np.dot(t[k, :, L, b].astype(object), weights))
+                q = int(np.dot(digits[k, :, L, b].astype(object), weights))
                 if i > j or j >= nq:
                     assert q == 0, (j, i)
                 else:
@@ -121,8 +128,8 @@ def test_digit_tiles_decode_to_the_occupation_form(name, nq):
     assert abs(d0 - d0_ref) <= 1e-12 * max(1.0, abs(d0_ref))
     Q = _decode(tiles, nq)
     maxq = max(abs(q) for q in Q.values())
-    assert maxq < 2 ** 62
-    assert maxq >= 2 ** 61  # the finest grid that fits
+    assert maxq < 2 ** GRID_BITS
+    assert maxq >= 2 ** (GRID_BITS - 1)  # the finest grid that fits
     # every entry is U on the grid, rounded to nearest (U rewritten in FP64
     # here in another order: allow a few ulps of U beside the half step)
     for (j, i), q in Q.items():
