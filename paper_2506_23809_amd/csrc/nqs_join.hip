@@ -18,11 +18,12 @@
 // partitions by their high bits (about a thousand entries each).  A tile of
 // samples counts its entries per partition in LDS and reserves its share
 // of each partition with one atomic; the entries are then placed, each
-// partition is sorted in LDS by (bucket, sample), and its bucket starts and
-// sizes are written beside the entries.  The pair kernel then takes one
-// lane per entry.
+// partition is sorted in LDS by (bucket, content fingerprint, sample), and
+// the start and size of each entry's group (its bucket's members with its
+// fingerprint: hash-colliding contents mostly fall apart) are written beside
+// the entries.  The pair kernel then takes one lane per entry.
 //
-// Cost: the ordered pairs inside buckets, the sum of squared bucket sizes.
+// Cost: the ordered pairs inside groups, the sum of squared group sizes.
 // For samples spread over a large sector this is far below the
 // enumeration's N x (connected states per sample) lookups.  The decision is
 // taken on the device from the bucket sizes, between the hash clear and the
@@ -30,7 +31,7 @@
 // insertion, the enumeration and the streaming kernels of the same launch
 // stand down; otherwise those run and the pair kernel returns at once.
 //
-// Determinism: a partition is sorted by sample index within each bucket, so
+// Determinism: a partition is sorted by sample index within each group, so
 // each sample's hits are added in a fixed order (one partial per block,
 // partners in index order), and the finish kernel adds the block partials
 // in block order.
@@ -58,20 +59,33 @@ constexpr int kJoinTiles = 128;          // tiles of the grouping kernels, at mo
 
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
-// Bucket key of block b of x: the block index in the top bits, a hash of
-// the block's contents below (equal contents, equal bucket).  The hash is a
-// 64-bit multiply-xorshift mix of the masked words (any hash serves: only
-// equal contents must meet).
+// The 64-bit multiply-xorshift mix of block b's masked words (any hash
+// serves: only equal contents must meet).
 template <int W>
-__device__ __forceinline__ uint32_t join_bucket(const DevTable &tab, const Key<W> &x, int b,
-                                                int log2m) {
+__device__ __forceinline__ uint64_t join_mix(const DevTable &tab, const Key<W> &x, int b) {
     uint64_t z = x.w[0] & tab.jmask[b][0];
     if constexpr (W == 2) z ^= (x.w[W - 1] & tab.jmask[b][1]) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z ^= z >> 31;
-    const uint32_t slot = static_cast<uint32_t>(z >> (64 - log2m));
+    return z ^ (z >> 31);
+}
+
+// Bucket key of block b of x: the block index in the top bits, the mix's
+// top log2m bits below (equal contents, equal bucket).
+template <int W>
+__device__ __forceinline__ uint32_t join_bucket(const DevTable &tab, const Key<W> &x, int b,
+                                                int log2m) {
+    const uint32_t slot = static_cast<uint32_t>(join_mix<W>(tab, x, b) >> (64 - log2m));
     return (static_cast<uint32_t>(b) << log2m) | slot;
+}
+
+// The content fingerprint of block b of x: the mix's low byte, which the
+// bucket does not use.  Equal contents have equal fingerprints, so a bucket
+// splits into groups of equal fingerprint without separating any pair that
+// agrees on the block.
+template <int W>
+__device__ __forceinline__ uint32_t join_fingerprint(const DevTable &tab, const Key<W> &x, int b) {
+    return static_cast<uint32_t>(join_mix<W>(tab, x, b)) & 0xFFu;
 }
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
@@ -237,8 +251,9 @@ __global__ __launch_bounds__(kJoinGroupThreads) void join_scatter_kernel(
 }
 
 // One partition (c entries, at most kJoinPartCap) ordered by (bucket,
-// sample); thread 0 writes its statistics.
-__device__ __forceinline__ void join_sort_partition(const DevScratch &sc,
+// content fingerprint, sample); thread 0 writes its statistics.
+template <int W>
+__device__ __forceinline__ void join_sort_partition(const DevTable &tab, const DevScratch &sc,
                                                     const uint64_t *__restrict__ samples, int p,
                                                     uint32_t c, uint32_t s0) {
     __shared__ uint32_t buf[kJoinPartCap];
@@ -259,11 +274,10 @@ __device__ __forceinline__ void join_sort_partition(const DevScratch &sc,
     // bucket starts (exclusive scan of the counts), packed with the sizes
     const int per = (L + blockDim.x - 1) / blockDim.x;
     const int u0 = threadIdx.x * per;
-    unsigned long long own = 0, sq = 0, mx = 0;
+    unsigned long long own = 0, mx = 0;
     for (int u = u0; u < u0 + per && u < L; ++u) {
         const unsigned long long v = cnt[u];
         own += v;
-        sq += v * v;
         mx = v > mx ? v : mx;
     }
     unsigned long long total;
@@ -273,9 +287,10 @@ __device__ __forceinline__ void join_sort_partition(const DevScratch &sc,
         cnt[u] = static_cast<uint32_t>(run) | (v << 16);
         run += v;
     }
-    // the partition's sum of squares and largest bucket (also decides the
-    // ordering method below)
-    block_sum_max(sq, mx);
+    // the partition's largest bucket (also decides the ordering method
+    // below)
+    unsigned long long none = 0;
+    block_sum_max(none, mx);
     __shared__ unsigned long long s_mx;
     if (threadIdx.x == 0) s_mx = mx;
     __syncthreads();
@@ -311,30 +326,66 @@ __device__ __forceinline__ void join_sort_partition(const DevScratch &sc,
         }
         __syncthreads();
     }
-    const unsigned long long blk =
-        static_cast<unsigned long long>(p >> (sc.join_log2m - sc.join_lshift));
+    const int blk = p >> (sc.join_log2m - sc.join_lshift);
+    const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(samples);
     uint4 *keys = reinterpret_cast<uint4 *>(sc.jkeys);
+    // the fingerprint of every entry whose bucket has company, one byte each
+    // in the words of fill[] (free since the placement)
+    uint8_t *fpr = reinterpret_cast<uint8_t *>(fill);
+    static_assert(sizeof(fill) >= kJoinPartCap, "one fingerprint byte per entry");
+    if (!big) {
+        for (uint32_t u = threadIdx.x; u < c; u += blockDim.x) {
+            const uint32_t v = buf[u];
+            if ((cnt[v >> 21] >> 16) < 2u) continue;
+            const uint4 w = src[v & 0x1FFFFFu];
+            Key<W> x;
+            x.w[0] = static_cast<uint64_t>(w.x) | (static_cast<uint64_t>(w.y) << 32);
+            if constexpr (W == 2)
+                x.w[W - 1] = static_cast<uint64_t>(w.z) | (static_cast<uint64_t>(w.w) << 32);
+            fpr[u] = static_cast<uint8_t>(join_fingerprint<W>(tab, x, blk));
+        }
+        __syncthreads();
+    }
+    // each entry's place: its bucket's start, the members of its bucket with
+    // a smaller fingerprint, then those of its own fingerprint with a smaller
+    // sample index; its range is its fingerprint group (the whole bucket for
+    // a bitonic-sorted partition)
+    unsigned long long pairs = 0;
     for (uint32_t u = threadIdx.x; u < c; u += blockDim.x) {
         const uint32_t v = buf[u];
         const uint32_t loc = v >> 21, me = v & 0x1FFFFFu;
         const uint32_t r = cnt[loc];
         const uint32_t bs = r & 0xFFFFu, m = r >> 16;
-        uint32_t rank;
+        uint32_t rank = 0, gs = bs, gm = m;
         if (big) {
             rank = u - bs;  // sorted: the place in the bucket is the offset
-        } else {
-            rank = 0;
-            for (uint32_t q = bs; q < bs + m; ++q) rank += (buf[q] & 0x1FFFFFu) < me ? 1u : 0u;
+        } else if (m >= 2) {
+            const uint32_t f = fpr[u];
+            uint32_t below = 0, same = 0;
+            for (uint32_t q = bs; q < bs + m; ++q) {
+                const uint32_t fq = fpr[q], mq = buf[q] & 0x1FFFFFu;
+                below += fq < f ? 1u : 0u;
+                same += fq == f ? 1u : 0u;
+                rank += (fq < f || (fq == f && mq < me)) ? 1u : 0u;
+            }
+            gs = bs + below;
+            gm = same;
         }
+        pairs += gm;
         const uint32_t dst = s0 + bs + rank;
         sc.jent[dst] = (static_cast<unsigned long long>(loc) << 32) | me;
-        sc.jrange[dst] = (s0 + bs) | (static_cast<unsigned long long>(m) << 32) | (blk << 48);
-        // (a sample alone in its bucket is never paired: no bit string)
-        if (m >= 2) keys[dst] = reinterpret_cast<const uint4 *>(samples)[me];
+        sc.jrange[dst] = (s0 + gs) | (static_cast<unsigned long long>(gm) << 32) |
+                         (static_cast<unsigned long long>(blk) << 48);
+        // (a sample alone in its group is never paired: no bit string)
+        if (gm >= 2) keys[dst] = src[me];
     }
+    // the partition's sum of squared group sizes (each entry adds its
+    // group's size) and its largest bucket
+    unsigned long long unused = 0;
+    block_sum_max(pairs, unused);
     if (threadIdx.x == 0) {
-        sc.jstat[2 * p] = sq;
-        sc.jstat[2 * p + 1] = mx;
+        sc.jstat[2 * p] = pairs;
+        sc.jstat[2 * p + 1] = mx_all;
     }
 }
 
@@ -384,18 +435,25 @@ __device__ __forceinline__ void join_decide(const DevTable &tab, const DevScratc
     sc.jctl[kJoinCtlChosen] = chosen ? 1ull : 0ull;
 }
 
-// One block per partition: its entries ordered by (bucket, sample) and
-// written back, each with its bucket's range and block and its bit string;
-// the partition's sum of squared bucket sizes and largest bucket.  A
+// One block per partition: its entries ordered by (bucket, content
+// fingerprint, sample) and written back, each with the range of its group
+// (the members of its bucket with its fingerprint), its block and its bit
+// string; the partition's sum of squared group sizes and largest bucket.  A
 // counting sort by bucket (LDS counts, their scan, then each entry at its
-// bucket's start plus a second atomic count) groups the buckets; an
-// entry's place inside its bucket is then the number of members with a
-// smaller sample index (a pass over the bucket, as long as the pair
-// kernel's).  LDS holds 4 bytes per entry (bucket << 21 | sample), so that
-// several blocks share a CU.  A partition of more than kJoinPartCap entries
-// is only flagged (the join then does not run).
+// bucket's start plus a second atomic count) groups the buckets; the
+// entries of a bucket with company then take the fingerprint of their
+// block's contents, and an entry's place inside its bucket is the number of
+// members with a smaller fingerprint, or the same one and a smaller sample
+// index (a pass over the bucket, as long as the pair kernel's).  Buckets of
+// hash-colliding contents thus split, and the pair kernel tests only the
+// pairs whose contents agree up to 2^-8.  LDS holds 4 bytes per entry
+// (bucket << 21 | sample) and a fingerprint byte, so that several blocks
+// share a CU.  A partition whose largest bucket needs the bitonic sort keeps
+// whole buckets as its groups.  A partition of more than kJoinPartCap
+// entries is only flagged (the join then does not run).
+template <int W>
 __global__ __launch_bounds__(kJoinSortThreads) void join_sort_kernel(
-    DevScratch sc, const uint64_t *__restrict__ samples) {
+    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples) {
     const int p = blockIdx.x;
     const uint32_t c = sc.jcnt[p];
     // the partition's first output place: the entries of the partitions
@@ -412,7 +470,7 @@ __global__ __launch_bounds__(kJoinSortThreads) void join_sort_kernel(
         }
         return;
     }
-    join_sort_partition(sc, samples, p, c, static_cast<uint32_t>(s0));
+    join_sort_partition<W>(tab, sc, samples, p, c, static_cast<uint32_t>(s0));
 }
 
 // One block: the decision, once every partition is sorted.  (Taking it in
@@ -609,8 +667,8 @@ hipError_t launch_join_prep_w(const DevTable &tab, const DevScratch &sc,
     }
     hipLaunchKernelGGL(join_scatter_kernel<W>, dim3(tiles.x + extra), blk, 0, st, tab, sc, samples,
                        n);
-    hipLaunchKernelGGL(join_sort_kernel, dim3(static_cast<unsigned>(sc.join_parts)),
-                       dim3(kJoinSortThreads), 0, st, sc, samples);
+    hipLaunchKernelGGL(join_sort_kernel<W>, dim3(static_cast<unsigned>(sc.join_parts)),
+                       dim3(kJoinSortThreads), 0, st, tab, sc, samples);
     hipLaunchKernelGGL(join_decide_kernel, dim3(1), blk, 0, st, tab, sc, samples, n, g_eff);
     return hipGetLastError();
 }
