@@ -416,12 +416,11 @@ __device__ __forceinline__ int64_t group_find(const DevTable &tab, uint32_t hX, 
 // One thread per sample: range check, sector uniformity, counts >= 0, linear
 // hash, Bloom bit, and insertion by CAS on the slot index.  A duplicate key
 // is found by comparing against the sample that owns the slot.  With the
-// pair join chosen (or checks_only) only the checks run.
+// pair join chosen only the checks run.
 template <int W>
 __device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScratch &sc,
                                                const uint64_t *__restrict__ samples,
-                                               const int64_t *__restrict__ weights, int64_t i,
-                                               bool checks_only = false) {
+                                               const int64_t *__restrict__ weights, int64_t i) {
     const uint64_t w0 = samples[2 * i], w1 = samples[2 * i + 1];
     bool bad;
     const int nq = tab.n_qubits;
@@ -441,7 +440,7 @@ __device__ __forceinline__ void hash_build_one(const DevTable &tab, const DevScr
         if (na != ra || nb != rb) atomicOr(sc.mixed, 1);
     }
     // the pair join, when it runs, needs neither the hash nor the filters
-    if (checks_only || join_chosen(sc) || bad) return;
+    if (join_chosen(sc) || bad) return;
     Key<W> k;
     k.w[0] = w0;
     if constexpr (W == 2) k.w[1] = w1;

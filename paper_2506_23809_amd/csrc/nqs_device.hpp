@@ -290,12 +290,14 @@ void join_scratch_layout(const DevTable &tab, int64_t n, int log2m, char *base, 
 // The join's grouping (counts, scatter, sort, then the decision) between
 // the clear of its counters and the hash build, and its pair kernel; with
 // clear_hash the grouping's first kernel also frees the hash slots and
-// clears the Bloom bitmaps.
+// clears the Bloom bitmaps.  The grouping also makes the hash build's checks
+// of every sample (register range, negative counts, mixed sectors).
 hipError_t launch_join_prep(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
-                            int64_t n, int64_t g_eff, bool clear_hash, hipStream_t st);
+                            const int64_t *weights, int64_t n, int64_t g_eff, bool clear_hash,
+                            hipStream_t st);
 // With build (1), the same launch also carries the sample-hash build (checks,
 // and the insertion when the join is not chosen) in blocks of its own; with
-// build 2 only its checks.
+// build 0 none (a launch that only joins: the grouping made the checks).
 hipError_t launch_join_pairs(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
                              const int64_t *weights, int build, const double *log_amp,
                              const double *phase, int64_t n, int precision, int32_t *hit_idx,

@@ -49,6 +49,7 @@ namespace {
 
 constexpr int kJoinGroupThreads = 1024;  // tile kernels
 constexpr int kJoinPairThreads = 256;
+constexpr int kJoinPairPer = 4;  // entries per lane of the pair kernel, at most
 constexpr int kJoinSortThreads = 512;
 // Largest bucket ranked by a pass over its members; a partition with a
 // larger one is bitonic-sorted whole.
@@ -172,7 +173,8 @@ __device__ __forceinline__ void block_sum_max(unsigned long long &s, unsigned lo
 // summed for the decision.
 template <int W>
 __global__ __launch_bounds__(kJoinGroupThreads) void join_scatter_kernel(
-    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples, int64_t n) {
+    DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
+    const int64_t *__restrict__ weights, int64_t n) {
     __shared__ uint32_t cur[kJoinMaxParts];
     if (blockIdx.x >= static_cast<unsigned>(sc.join_tiles)) {
         // blocks beyond the tiles free the hash slots and clear the Bloom
@@ -202,10 +204,17 @@ __global__ __launch_bounds__(kJoinGroupThreads) void join_scatter_kernel(
     const int64_t t0 = static_cast<int64_t>(blockIdx.x) * sc.join_tile;
     const int64_t t1 = t0 + sc.join_tile < n ? t0 + sc.join_tile : n;
     unsigned long long probes = 0;
+    const int nq = tab.n_qubits;
     for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
         const Key<W> x = load_key<W>(samples, i);
         for (int b = 0; b < tab.join_blocks; ++b)
             atomicAdd(&cur[join_bucket<W>(tab, x, b, log2m) >> lshift], 1u);
+        // the checks of the sample-hash build (a launch that only joins has
+        // no build): bits beyond the register, negative counts
+        const uint64_t hw = samples[2 * i + 1];
+        const bool bad = nq >= 64 ? (nq < 128 && (hw >> (nq - 64)) != 0)
+                                  : ((x.w[0] >> nq) != 0 || hw != 0);
+        if (bad || (weights && weights[i] < 0)) latch(sc.err, NQS_E_RANGE);
         if (tab.sector_filter) {
             const uint64_t w0 = x.w[0], w1 = W == 2 ? x.w[W - 1] : 0ull;
             const uint64_t s0 = samples[0], s1 = samples[1];
@@ -526,30 +535,51 @@ __device__ __forceinline__ bool join_hit(const DevTable &tab, const Key<W> &x, c
     return true;
 }
 
-// One lane per entry (block b, sample i): the partners of i in its bucket,
-// in index order; with a hit, its partial sum goes to part[b][i] and bit
-// b * n + i of the hit map is set (the finish reads only flagged partials).
-// The first build_blocks blocks are the sample-hash build of the same
-// launch instead (its checks always; its insertion when the join is not
-// chosen, unless checks_only): both need only the decision, so one launch
+// One lane per entry with partners (block b, sample i; each wave gathers
+// them from its per x 64 consecutive entries, so that with per > 1 lanes
+// are not spent on the many entries alone in their group): the partners of
+// i in its group, in index order; with a hit, its partial sum goes to
+// part[b][i] and bit b * n + i of the hit map is set (the finish reads only
+// flagged partials).  The first build_blocks blocks are the sample-hash
+// build of the same launch instead (its checks always; its insertion when
+// the join is not chosen): both need only the decision, so one launch
 // carries both.
 template <int W, bool DUMP, int P, bool SCV>
 __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
     const int64_t *__restrict__ weights, const double *__restrict__ log_amp,
-    const double *__restrict__ phase, int64_t n, unsigned build_blocks, int checks_only,
+    const double *__restrict__ phase, int64_t n, unsigned build_blocks, int per,
     int32_t *__restrict__ hit_idx, uint32_t *__restrict__ sign_bits, int64_t sign_words) {
     if (blockIdx.x < build_blocks) {
         const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-        if (i < n) hash_build_one<W>(tab, sc, samples, weights, i, checks_only != 0);
+        if (i < n) hash_build_one<W>(tab, sc, samples, weights, i);
         return;
     }
     if (!join_chosen(sc)) return;
-    const int64_t p = static_cast<int64_t>(blockIdx.x - build_blocks) * blockDim.x + threadIdx.x;
+    // each wave takes per x 64 consecutive entries (per <= kJoinPairPer)
+    // and gathers those with partners into its lanes
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ uint32_t picks[kJoinPairThreads / 64][64 * kJoinPairPer];
+    const int64_t entries = static_cast<int64_t>(tab.join_blocks) * n;
+    const int64_t base =
+        (static_cast<int64_t>(blockIdx.x - build_blocks) * (kJoinPairThreads / 64) + wave) *
+        (64 * per);
+    uint32_t listed = 0;
+    for (int k = 0; k < per; ++k) {
+        const int64_t p = base + 64 * k + lane;
+        const bool grouped = p < entries && ((sc.jrange[p] >> 32) & 0xFFFFull) >= 2ull;
+        const unsigned long long mask = __ballot(grouped);
+        if (grouped)
+            picks[wave][listed + __popcll(mask & ((1ull << lane) - 1ull))] =
+                static_cast<uint32_t>(64 * k + lane);
+        listed += static_cast<uint32_t>(__popcll(mask));
+    }
+    __syncthreads();
     const unsigned long long *__restrict__ ent = sc.jent;
     const int maxf = tab.max_flip;
     unsigned long long n_cand = 0, n_probe = 0, n_hit = 0, n_term = 0;
-    if (p < static_cast<int64_t>(tab.join_blocks) * n) {
+    for (uint32_t t = static_cast<uint32_t>(lane); t < listed; t += 64) {
+        const int64_t p = base + picks[wave][t];
         const int64_t i = static_cast<uint32_t>(ent[p]);
         const unsigned long long r = sc.jrange[p];
         const uint32_t bs = static_cast<uint32_t>(r), m = static_cast<uint32_t>(r >> 32) & 0xFFFFu;
@@ -613,7 +643,7 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
                 }
             }
             for (; q < bs + m; ++q) visit(q, load_key<W>(sc.jkeys, q));
-            n_cand = m - 1;
+            n_cand += m - 1;
             if (n_hit) {
                 double2 sum;
                 if constexpr (P == NQS_FP64) {
@@ -628,7 +658,6 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
     }
     // one set of counter atomics per block
     __shared__ unsigned long long cnt[4][kJoinPairThreads / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     n_cand = wave_sum(n_cand);
     n_probe = wave_sum(n_probe);
     n_hit = wave_sum(n_hit);
@@ -650,8 +679,8 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
 
 template <int W>
 hipError_t launch_join_prep_w(const DevTable &tab, const DevScratch &sc,
-                              const uint64_t *samples, int64_t n, int64_t g_eff, bool clear_hash,
-                              hipStream_t st) {
+                              const uint64_t *samples, const int64_t *weights, int64_t n,
+                              int64_t g_eff, bool clear_hash, hipStream_t st) {
     const dim3 tiles(static_cast<unsigned>(sc.join_tiles));
     const dim3 blk(kJoinGroupThreads);
     // the hash clear rides along: four slots a thread in the blocks after
@@ -666,7 +695,7 @@ hipError_t launch_join_prep_w(const DevTable &tab, const DevScratch &sc,
         extra = static_cast<unsigned>((span + 4 * kJoinGroupThreads - 1) / (4 * kJoinGroupThreads));
     }
     hipLaunchKernelGGL(join_scatter_kernel<W>, dim3(tiles.x + extra), blk, 0, st, tab, sc, samples,
-                       n);
+                       weights, n);
     hipLaunchKernelGGL(join_sort_kernel<W>, dim3(static_cast<unsigned>(sc.join_parts)),
                        dim3(kJoinSortThreads), 0, st, tab, sc, samples);
     hipLaunchKernelGGL(join_decide_kernel, dim3(1), blk, 0, st, tab, sc, samples, n, g_eff);
@@ -681,11 +710,21 @@ hipError_t launch_pairs_w(const DevTable &tab, const DevScratch &sc, const uint6
     const int64_t entries = static_cast<int64_t>(tab.join_blocks) * n;
     const unsigned build_blocks =
         build ? static_cast<unsigned>((n + kJoinPairThreads - 1) / kJoinPairThreads) : 0u;
-    const dim3 grid(build_blocks +
-                    static_cast<unsigned>((entries + kJoinPairThreads - 1) / kJoinPairThreads));
+    // several entries a lane where most samples are alone in their groups:
+    // blocks whose contents outnumber the samples (fewer waves, each
+    // gathering its few entries with partners); one a lane where blocks
+    // are short and groups large (every entry has work: parallelism first)
+    int qmin = 128;
+    for (int b = 0; b < tab.join_blocks; ++b) {
+        const int q = __builtin_popcountll(tab.jmask[b][0]) + __builtin_popcountll(tab.jmask[b][1]);
+        qmin = q < qmin ? q : qmin;
+    }
+    const int per = (qmin >= 62 || (int64_t(1) << qmin) >= 2 * n) ? kJoinPairPer : 1;
+    const int64_t per_block = int64_t(kJoinPairThreads) * per;
+    const dim3 grid(build_blocks + static_cast<unsigned>((entries + per_block - 1) / per_block));
     hipLaunchKernelGGL((join_pair_kernel<W, D, P, SCV>), grid, dim3(kJoinPairThreads), 0, st, tab,
-                       sc, samples, weights, log_amp, phase, n, build_blocks, build == 2 ? 1 : 0,
-                       hit_idx, sign_bits, sign_words);
+                       sc, samples, weights, log_amp, phase, n, build_blocks, per, hit_idx,
+                       sign_bits, sign_words);
     return hipGetLastError();
 }
 
@@ -779,10 +818,11 @@ void join_scratch_layout(const DevTable &tab, int64_t n, int log2m, char *base, 
 }
 
 hipError_t launch_join_prep(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,
-                            int64_t n, int64_t g_eff, bool clear_hash, hipStream_t st) {
+                            const int64_t *weights, int64_t n, int64_t g_eff, bool clear_hash,
+                            hipStream_t st) {
     if (tab.n_qubits <= 63)
-        return launch_join_prep_w<1>(tab, sc, samples, n, g_eff, clear_hash, st);
-    return launch_join_prep_w<2>(tab, sc, samples, n, g_eff, clear_hash, st);
+        return launch_join_prep_w<1>(tab, sc, samples, weights, n, g_eff, clear_hash, st);
+    return launch_join_prep_w<2>(tab, sc, samples, weights, n, g_eff, clear_hash, st);
 }
 
 hipError_t launch_join_pairs(const DevTable &tab, const DevScratch &sc, const uint64_t *samples,

@@ -2362,7 +2362,7 @@ hipError_t launch_batch(const JobDesc *d_jobs, int n_jobs, const WorkItem *d_ite
     for (int k = 0; h_jobs && k < n_jobs; ++k) {
         const JobDesc &J = h_jobs[k];
         if (!J.sc.jctl || J.n == 0) continue;
-        const hipError_t e = launch_join_prep(J.tab, J.sc, J.samples, J.n,
+        const hipError_t e = launch_join_prep(J.tab, J.sc, J.samples, J.weights, J.n,
                                               J.tab.n_groups - (J.tab.has_diagonal ? 1 : 0),
                                               false, st);
         if (e != hipSuccess) return e;
@@ -2631,7 +2631,7 @@ hipError_t launch_hash(const DevTable &tab, const DevScratch &sc, uint32_t capac
     if (join) {
         // the pair join's grouping and decision come before the build, which
         // skips its insertion when the join runs
-        const hipError_t e = launch_join_prep(tab, sc, samples, n,
+        const hipError_t e = launch_join_prep(tab, sc, samples, weights, n,
                                               tab.n_groups - (tab.has_diagonal ? 1 : 0),
                                               !join_only, st);
         if (e != hipSuccess) return e;
@@ -2724,9 +2724,9 @@ hipError_t launch_eloc(const DevTable &tab, const DevScratch &sc, const EvalLaun
                                dim3(256), 0, st, hit_idx, cnt, -1);
         }
         // the hash build rides in the same launch (launch_hash left it out);
-        // a join-only launch only checks the samples there (its hash is not
-        // cleared, and nothing would read it)
-        e = launch_join_pairs(tab, sc, samples, weights, L.join_only ? 2 : 1, log_amp, phase, n,
+        // a join-only launch has none (its hash is not cleared, nothing would
+        // read it, and the grouping made the sample checks)
+        e = launch_join_pairs(tab, sc, samples, weights, L.join_only ? 0 : 1, log_amp, phase, n,
                               precision, hit_idx, sign_bits, sign_words, st);
         if (e != hipSuccess) return e;
     }
