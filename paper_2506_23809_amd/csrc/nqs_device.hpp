@@ -201,15 +201,17 @@ struct DevScratch {
     // | slot; a partition is the buckets of one key prefix,
     // key >> join_lshift, join_parts of them
     uint32_t *jcnt;             // [parts] entries per partition
-    unsigned long long *jreg;   // [parts][join_cap] each partition's entries, scatter order
-    // entries by partition, then bucket, then sample index
+    unsigned long long *jreg;   // [parts][join_cap] each partition's entries, scatter order:
+                                // fingerprint << 56 | (key & (2^join_lshift - 1)) << 32 | sample
+    // entries by partition, then bucket, then fingerprint, then sample index
     unsigned long long *jent;   // [blocks * n] (key & (2^join_lshift - 1)) << 32 | sample
-    unsigned long long *jrange; // [blocks * n] first entry of the entry's bucket |
-                                // bucket size << 32 | block << 48
-    uint64_t *jkeys;            // [blocks * n][2] the entry's bit string
+    unsigned long long *jrange; // [blocks * n] first entry of the entry's group (its bucket's
+                                // members of its fingerprint) | group size << 32 | block << 48
+    uint64_t *jkeys;            // [blocks * n][2] the entry's bit string (entries in a group
+                                // of two or more)
     uint32_t *jhit;             // [ceil(blocks * n / 32)] bit b * n + i: entry (b, i) has a
                                 // hit and wrote its partial
-    unsigned long long *jstat;  // [parts][2] sum of squared bucket sizes, largest bucket
+    unsigned long long *jstat;  // [parts][2] sum of squared group sizes, largest bucket
     unsigned long long *jctl;   // [kJoinCtl] see kJoinCtl*
     int join_log2m;
     int64_t join_n;             // samples of the launch (the partials' row length)

@@ -57,6 +57,8 @@ constexpr unsigned long long kJoinRankMax = 64;
 constexpr int kJoinMaxParts = 8192;      // partitions of any planned launch
 constexpr int kJoinMaxLocal = 2048;      // buckets per partition (2^join_lshift)
 constexpr int kJoinTiles = 128;          // tiles of the grouping kernels, at most
+constexpr int kScatterStash = 10240;     // bucket keys a scatter tile keeps in LDS
+constexpr int kJoinFpShift = 56;         // fingerprint byte of a partition-region entry
 
 inline size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -71,22 +73,17 @@ __device__ __forceinline__ uint64_t join_mix(const DevTable &tab, const Key<W> &
     return z ^ (z >> 31);
 }
 
-// Bucket key of block b of x: the block index in the top bits, the mix's
-// top log2m bits below (equal contents, equal bucket).
+// The bucket key of block b of x (below 2^24: at most 8 blocks, 2^21
+// buckets each) and, in the top byte, the content fingerprint: the mix's
+// low byte, which the bucket does not use.  Equal contents have equal
+// fingerprints, so a bucket splits into groups of equal fingerprint without
+// separating any pair that agrees on the block.
 template <int W>
-__device__ __forceinline__ uint32_t join_bucket(const DevTable &tab, const Key<W> &x, int b,
+__device__ __forceinline__ uint32_t join_key_fp(const DevTable &tab, const Key<W> &x, int b,
                                                 int log2m) {
-    const uint32_t slot = static_cast<uint32_t>(join_mix<W>(tab, x, b) >> (64 - log2m));
-    return (static_cast<uint32_t>(b) << log2m) | slot;
-}
-
-// The content fingerprint of block b of x: the mix's low byte, which the
-// bucket does not use.  Equal contents have equal fingerprints, so a bucket
-// splits into groups of equal fingerprint without separating any pair that
-// agrees on the block.
-template <int W>
-__device__ __forceinline__ uint32_t join_fingerprint(const DevTable &tab, const Key<W> &x, int b) {
-    return static_cast<uint32_t>(join_mix<W>(tab, x, b)) & 0xFFu;
+    const uint64_t z = join_mix<W>(tab, x, b);
+    const uint32_t slot = static_cast<uint32_t>(z >> (64 - log2m));
+    return ((static_cast<uint32_t>(b) << log2m) | slot) | (static_cast<uint32_t>(z) << 24);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
@@ -176,6 +173,10 @@ __global__ __launch_bounds__(kJoinGroupThreads) void join_scatter_kernel(
     DevTable tab, DevScratch sc, const uint64_t *__restrict__ samples,
     const int64_t *__restrict__ weights, int64_t n) {
     __shared__ uint32_t cur[kJoinMaxParts];
+    // the tile's first bucket keys and fingerprints, kept for the placing
+    // pass (sample s of the tile, block b: stash[s * join_blocks + b]; keys
+    // beyond it are computed again)
+    __shared__ uint32_t stash[kScatterStash];
     if (blockIdx.x >= static_cast<unsigned>(sc.join_tiles)) {
         // blocks beyond the tiles free the hash slots and clear the Bloom
         // bitmaps that the hash build of this launch may fill
@@ -205,10 +206,15 @@ __global__ __launch_bounds__(kJoinGroupThreads) void join_scatter_kernel(
     const int64_t t1 = t0 + sc.join_tile < n ? t0 + sc.join_tile : n;
     unsigned long long probes = 0;
     const int nq = tab.n_qubits;
+    const int nb = tab.join_blocks;
     for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
         const Key<W> x = load_key<W>(samples, i);
-        for (int b = 0; b < tab.join_blocks; ++b)
-            atomicAdd(&cur[join_bucket<W>(tab, x, b, log2m) >> lshift], 1u);
+        const int64_t at = (i - t0) * nb;
+        for (int b = 0; b < nb; ++b) {
+            const uint32_t v = join_key_fp<W>(tab, x, b, log2m);
+            atomicAdd(&cur[(v & 0xFFFFFFu) >> lshift], 1u);
+            if (at + b < kScatterStash) stash[at + b] = v;
+        }
         // the checks of the sample-hash build (a launch that only joins has
         // no build): bits beyond the register, negative counts
         const uint64_t hw = samples[2 * i + 1];
@@ -219,13 +225,13 @@ __global__ __launch_bounds__(kJoinGroupThreads) void join_scatter_kernel(
             const uint64_t w0 = x.w[0], w1 = W == 2 ? x.w[W - 1] : 0ull;
             const uint64_t s0 = samples[0], s1 = samples[1];
             const int na = __popcll(w0 & tab.spin_a0) + __popcll(w1 & tab.spin_a1);
-            const int nb = __popcll(w0 & tab.spin_b0) + __popcll(w1 & tab.spin_b1);
+            const int nbe = __popcll(w0 & tab.spin_b0) + __popcll(w1 & tab.spin_b1);
             const int ra = __popcll(s0 & tab.spin_a0) + __popcll(s1 & tab.spin_a1);
             const int rb = __popcll(s0 & tab.spin_b0) + __popcll(s1 & tab.spin_b1);
-            if (na != ra || nb != rb) atomicOr(sc.mixed, 1);
+            if (na != ra || nbe != rb) atomicOr(sc.mixed, 1);
             if (tab.enum_ok) {
-                const unsigned long long va = tab.k_alpha - na, vb = tab.k_beta - nb;
-                const unsigned long long a = na, bb = nb;
+                const unsigned long long va = tab.k_alpha - na, vb = tab.k_beta - nbe;
+                const unsigned long long a = na, bb = nbe;
                 probes += a * va + bb * vb + (a * (a - 1) / 2) * (va * (va - 1) / 2) +
                           (bb * (bb - 1) / 2) * (vb * (vb - 1) / 2) + a * va * bb * vb;
             }
@@ -242,17 +248,22 @@ __global__ __launch_bounds__(kJoinGroupThreads) void join_scatter_kernel(
         atomicAdd(&sc.jctl[kJoinCtlProbeSlots + (blockIdx.x * 16 + (threadIdx.x >> 6)) % 64],
                   probes);
     __syncthreads();
-    // the entries (keys computed again: cheaper than keeping them)
+    // the entries (keys from the stash, or computed again past it)
     const uint32_t lmask = (1u << lshift) - 1u;
     const uint32_t cap = static_cast<uint32_t>(sc.join_cap);
     for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
-        const Key<W> x = load_key<W>(samples, i);
-        for (int b = 0; b < tab.join_blocks; ++b) {
-            const uint32_t k = join_bucket<W>(tab, x, b, log2m);
+        const int64_t at = (i - t0) * nb;
+        Key<W> x;
+        if (at + nb > kScatterStash) x = load_key<W>(samples, i);
+        for (int b = 0; b < nb; ++b) {
+            const uint32_t v =
+                at + b < kScatterStash ? stash[at + b] : join_key_fp<W>(tab, x, b, log2m);
+            const uint32_t k = v & 0xFFFFFFu;
             const uint32_t part = k >> lshift;
             const uint32_t pos = atomicAdd(&cur[part], 1u);
             if (pos < cap)
                 sc.jreg[static_cast<int64_t>(part) * cap + pos] =
+                    (static_cast<unsigned long long>(v >> 24) << kJoinFpShift) |
                     (static_cast<unsigned long long>(k & lmask) << 32) |
                     static_cast<unsigned long long>(i);
         }
@@ -267,18 +278,17 @@ __device__ __forceinline__ void join_sort_partition(const DevTable &tab, const D
                                                     uint32_t c, uint32_t s0) {
     __shared__ uint32_t buf[kJoinPartCap];
     __shared__ uint32_t cnt[kJoinMaxLocal];
-    __shared__ uint32_t fill[kJoinMaxLocal];
+    // each placed entry's content fingerprint (from the scatter)
+    __shared__ uint8_t fpr[kJoinPartCap];
     // the partition's entries, in its region (scatter order)
     const unsigned long long *__restrict__ reg =
         sc.jreg + static_cast<int64_t>(p) * static_cast<uint32_t>(sc.join_cap);
     const int L = 1 << sc.join_lshift;
-    for (int u = threadIdx.x; u < L; u += blockDim.x) {
-        cnt[u] = 0u;
-        fill[u] = 0u;
-    }
+    const uint32_t lmask = static_cast<uint32_t>(L - 1);
+    for (int u = threadIdx.x; u < L; u += blockDim.x) cnt[u] = 0u;
     __syncthreads();
     for (uint32_t u = threadIdx.x; u < c; u += blockDim.x)
-        atomicAdd(&cnt[static_cast<uint32_t>(reg[u] >> 32)], 1u);
+        atomicAdd(&cnt[static_cast<uint32_t>(reg[u] >> 32) & lmask], 1u);
     __syncthreads();
     // bucket starts (exclusive scan of the counts), packed with the sizes
     const int per = (L + blockDim.x - 1) / blockDim.x;
@@ -304,11 +314,14 @@ __device__ __forceinline__ void join_sort_partition(const DevTable &tab, const D
     if (threadIdx.x == 0) s_mx = mx;
     __syncthreads();
     const unsigned long long mx_all = s_mx;
+    // each entry at its bucket's next place: the low half of cnt[] serves as
+    // the cursor (it ends at the bucket's end, below 2^16)
     for (uint32_t u = threadIdx.x; u < c; u += blockDim.x) {
         const unsigned long long e = reg[u];
-        const uint32_t loc = static_cast<uint32_t>(e >> 32);
-        const uint32_t at = (cnt[loc] & 0xFFFFu) + atomicAdd(&fill[loc], 1u);
+        const uint32_t loc = static_cast<uint32_t>(e >> 32) & lmask;
+        const uint32_t at = atomicAdd(&cnt[loc], 1u) & 0xFFFFu;
         buf[at] = (loc << 21) | static_cast<uint32_t>(e);
+        fpr[at] = static_cast<uint8_t>(e >> kJoinFpShift);
     }
     __syncthreads();
     // large buckets (clustered samples: few distinct block contents): sort
@@ -338,23 +351,6 @@ __device__ __forceinline__ void join_sort_partition(const DevTable &tab, const D
     const int blk = p >> (sc.join_log2m - sc.join_lshift);
     const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(samples);
     uint4 *keys = reinterpret_cast<uint4 *>(sc.jkeys);
-    // the fingerprint of every entry whose bucket has company, one byte each
-    // in the words of fill[] (free since the placement)
-    uint8_t *fpr = reinterpret_cast<uint8_t *>(fill);
-    static_assert(sizeof(fill) >= kJoinPartCap, "one fingerprint byte per entry");
-    if (!big) {
-        for (uint32_t u = threadIdx.x; u < c; u += blockDim.x) {
-            const uint32_t v = buf[u];
-            if ((cnt[v >> 21] >> 16) < 2u) continue;
-            const uint4 w = src[v & 0x1FFFFFu];
-            Key<W> x;
-            x.w[0] = static_cast<uint64_t>(w.x) | (static_cast<uint64_t>(w.y) << 32);
-            if constexpr (W == 2)
-                x.w[W - 1] = static_cast<uint64_t>(w.z) | (static_cast<uint64_t>(w.w) << 32);
-            fpr[u] = static_cast<uint8_t>(join_fingerprint<W>(tab, x, blk));
-        }
-        __syncthreads();
-    }
     // each entry's place: its bucket's start, the members of its bucket with
     // a smaller fingerprint, then those of its own fingerprint with a smaller
     // sample index; its range is its fingerprint group (the whole bucket for
@@ -364,7 +360,7 @@ __device__ __forceinline__ void join_sort_partition(const DevTable &tab, const D
         const uint32_t v = buf[u];
         const uint32_t loc = v >> 21, me = v & 0x1FFFFFu;
         const uint32_t r = cnt[loc];
-        const uint32_t bs = r & 0xFFFFu, m = r >> 16;
+        const uint32_t m = r >> 16, bs = (r & 0xFFFFu) - m;
         uint32_t rank = 0, gs = bs, gm = m;
         if (big) {
             rank = u - bs;  // sorted: the place in the bucket is the offset
@@ -449,15 +445,14 @@ __device__ __forceinline__ void join_decide(const DevTable &tab, const DevScratc
 // (the members of its bucket with its fingerprint), its block and its bit
 // string; the partition's sum of squared group sizes and largest bucket.  A
 // counting sort by bucket (LDS counts, their scan, then each entry at its
-// bucket's start plus a second atomic count) groups the buckets; the
-// entries of a bucket with company then take the fingerprint of their
-// block's contents, and an entry's place inside its bucket is the number of
-// members with a smaller fingerprint, or the same one and a smaller sample
-// index (a pass over the bucket, as long as the pair kernel's).  Buckets of
-// hash-colliding contents thus split, and the pair kernel tests only the
-// pairs whose contents agree up to 2^-8.  LDS holds 4 bytes per entry
-// (bucket << 21 | sample) and a fingerprint byte, so that several blocks
-// share a CU.  A partition whose largest bucket needs the bitonic sort keeps
+// bucket's start plus a cursor in the same word) groups the buckets; an
+// entry's place inside its bucket is then the number of members with a
+// smaller content fingerprint (which the scatter put in the entry's top
+// byte), or the same one and a smaller sample index (a pass over the
+// bucket, as long as the pair kernel's).  Buckets of hash-colliding
+// contents thus split, and the pair kernel tests only the pairs whose
+// contents agree up to 2^-8.  LDS holds 4 bytes per entry (bucket << 21 |
+// sample) and its fingerprint byte, so that several blocks share a CU.  A partition whose largest bucket needs the bitonic sort keeps
 // whole buckets as its groups.  A partition of more than kJoinPartCap
 // entries is only flagged (the join then does not run).
 template <int W>
