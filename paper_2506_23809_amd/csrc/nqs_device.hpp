@@ -204,7 +204,7 @@ struct DevScratch {
     unsigned long long *jreg;   // [parts][join_cap] each partition's entries, scatter order:
                                 // fingerprint << 56 | (key & (2^join_lshift - 1)) << 32 | sample
     // entries by partition, then bucket, then fingerprint, then sample index
-    unsigned long long *jent;   // [blocks * n] (key & (2^join_lshift - 1)) << 32 | sample
+    uint32_t *jent;             // [blocks * n] the entry's sample
     unsigned long long *jrange; // [blocks * n] first entry of the entry's group (its bucket's
                                 // members of its fingerprint) | group size << 32 | block << 48
     uint64_t *jkeys;            // [blocks * n][2] the entry's bit string (entries in a group

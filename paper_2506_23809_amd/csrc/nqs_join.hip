@@ -378,7 +378,7 @@ __device__ __forceinline__ void join_sort_partition(const DevTable &tab, const D
         }
         pairs += gm;
         const uint32_t dst = s0 + bs + rank;
-        sc.jent[dst] = (static_cast<unsigned long long>(loc) << 32) | me;
+        sc.jent[dst] = me;
         sc.jrange[dst] = (s0 + gs) | (static_cast<unsigned long long>(gm) << 32) |
                          (static_cast<unsigned long long>(blk) << 48);
         // (a sample alone in its group is never paired: no bit string)
@@ -570,12 +570,12 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
         listed += static_cast<uint32_t>(__popcll(mask));
     }
     __syncthreads();
-    const unsigned long long *__restrict__ ent = sc.jent;
+    const uint32_t *__restrict__ ent = sc.jent;
     const int maxf = tab.max_flip;
     unsigned long long n_cand = 0, n_probe = 0, n_hit = 0, n_term = 0;
     for (uint32_t t = static_cast<uint32_t>(lane); t < listed; t += 64) {
         const int64_t p = base + picks[wave][t];
-        const int64_t i = static_cast<uint32_t>(ent[p]);
+        const int64_t i = ent[p];
         const unsigned long long r = sc.jrange[p];
         const uint32_t bs = static_cast<uint32_t>(r), m = static_cast<uint32_t>(r >> 32) & 0xFFFFu;
         const int b = static_cast<int>(r >> 48);
@@ -611,7 +611,7 @@ __global__ __launch_bounds__(kJoinPairThreads) void join_pair_kernel(
                     latch(sc.err, NQS_E_DUPLICATE);
                     return;
                 }
-                const int32_t j = static_cast<int32_t>(static_cast<uint32_t>(ent[q]));
+                const int32_t j = static_cast<int32_t>(ent[q]);
                 ++n_probe;
                 if (!have_psi) {
                     la = log_amp[i];
@@ -766,7 +766,7 @@ void join_sizes(const DevTable &tab, int64_t n, int log2m, size_t sizes[kJoinPie
     const size_t parts = static_cast<size_t>(g.parts);
     sizes[0] = 4 * parts;                                 // jcnt
     sizes[1] = 8 * parts * static_cast<size_t>(g.cap);    // jreg
-    sizes[2] = 8 * entries;                               // jent
+    sizes[2] = 4 * entries;                               // jent
     sizes[3] = 8 * entries;                               // jrange
     sizes[4] = 16 * parts;                                // jstat
     sizes[5] = 8 * static_cast<size_t>(kJoinCtl);         // jctl
@@ -797,7 +797,7 @@ void join_scratch_layout(const DevTable &tab, int64_t n, int log2m, char *base, 
     const JoinGeometry g = join_geometry(tab, n, log2m);
     sc->jcnt = reinterpret_cast<uint32_t *>(base + off[0]);
     sc->jreg = reinterpret_cast<unsigned long long *>(base + off[1]);
-    sc->jent = reinterpret_cast<unsigned long long *>(base + off[2]);
+    sc->jent = reinterpret_cast<uint32_t *>(base + off[2]);
     sc->jrange = reinterpret_cast<unsigned long long *>(base + off[3]);
     sc->jstat = reinterpret_cast<unsigned long long *>(base + off[4]);
     sc->jctl = reinterpret_cast<unsigned long long *>(base + off[5]);

@@ -1836,7 +1836,7 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
                                            const double *dc = nullptr, int nd = 0,
                                            const double *dq = nullptr,
                                            uint32_t *olist = nullptr, bool have_d = false,
-                                           double dval = 0.0) {
+                                           double dval = 0.0, double2 *value = nullptr) {
     unsigned long long n_terms = 0;
     // the pair join leaves one partial per block, an enumeration one per sample
     if (join_chosen(sc))
@@ -1928,6 +1928,7 @@ __device__ __forceinline__ void finish_one(const DevTable &tab, const DevScratch
         }
         eloc[2 * i] = re;
         eloc[2 * i + 1] = im;
+        if (value) *value = make_double2(re, im);
     }
     // every sample sums the whole X = 0 group: one count for the batch
     (void)n_terms;
@@ -2037,6 +2038,7 @@ __global__ __launch_bounds__(256) void eloc_finish_kernel(
     const int64_t *__restrict__ weights, double *__restrict__ epart) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     bool done = false;
+    double2 v = make_double2(0.0, 0.0);
     if constexpr (!DUMP && !SCV) {
         // staging area (dynamic LDS of stage_cap doubles, at least
         // 3 kDiagLds): the diagonal's Z masks and coefficients, or its
@@ -2051,7 +2053,7 @@ __global__ __launch_bounds__(256) void eloc_finish_kernel(
                                   : nullptr;
             finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc,
                                         hit_idx, sign_bits, sign_words, i, nullptr, nullptr, 0,
-                                        dq, olist);
+                                        dq, olist, false, 0.0, &v);
             done = true;
         } else {
             uint64_t *dz = reinterpret_cast<uint64_t *>(stage);
@@ -2059,19 +2061,19 @@ __global__ __launch_bounds__(256) void eloc_finish_kernel(
             const int nd = stage_diagonal<P>(tab, dz, dc);
             if (nd >= 0) {
                 finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc,
-                                            hit_idx, sign_bits, sign_words, i, dz, dc, nd);
+                                            hit_idx, sign_bits, sign_words, i, dz, dc, nd,
+                                            nullptr, nullptr, false, 0.0, &v);
                 done = true;
             }
         }
     }
     if (!done)
         finish_one<W, DUMP, P, SCV>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc, hit_idx,
-                                    sign_bits, sign_words, i);
+                                    sign_bits, sign_words, i, nullptr, nullptr, 0, nullptr,
+                                    nullptr, false, 0.0, &v);
     if (epart) {
-        // this thread's E_loc, just written by it
-        const bool have = i < n;
-        energy_block_partial(have ? static_cast<double>(weights[i]) : 0.0,
-                             have ? eloc[2 * i] : 0.0, have ? eloc[2 * i + 1] : 0.0,
+        // this thread's E_loc, as just written (not read back)
+        energy_block_partial(i < n ? static_cast<double>(weights[i]) : 0.0, v.x, v.y,
                              epart + 4 * static_cast<int64_t>(blockIdx.x));
     }
 }
@@ -2105,12 +2107,13 @@ __global__ __launch_bounds__(kFinishMfmaThreads) void eloc_finish_mfma_kernel(
     unsigned tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + tid;
+    double2 v = make_double2(0.0, 0.0);
     finish_one<W, false, P, false>(tab, sc, samples, n, n_chunks, enum_on != 0, eloc, nullptr,
-                                   nullptr, 0, i, nullptr, nullptr, 0, nullptr, nullptr, true, d);
+                                   nullptr, 0, i, nullptr, nullptr, 0, nullptr, nullptr, true, d,
+                                   &v);
     if (epart) {
-        const bool have = i < n;
-        energy_block_partial(have ? static_cast<double>(weights[i]) : 0.0,
-                             have ? eloc[2 * i] : 0.0, have ? eloc[2 * i + 1] : 0.0,
+        // this thread's E_loc, as just written (not read back)
+        energy_block_partial(i < n ? static_cast<double>(weights[i]) : 0.0, v.x, v.y,
                              epart + 4 * static_cast<int64_t>(blockIdx.x));
     }
 }
