@@ -382,6 +382,17 @@ __device__ __forceinline__ AccF32 group_sum_f32(const DevTable &tab, int64_t g, 
     return a;
 }
 
+// psi(x') / psi(x) in FP64 from the log-amplitude and phase differences,
+// out of line: inlined into a kernel's partner or probe loop, the exp and
+// sincos constants stay in registers across the whole loop and cost it
+// waves per SIMD (the call is made only on a hit).
+static __device__ __noinline__ double2 amp_ratio_f64(double da, double dphi) {
+    double sn, cs;
+    sincos(dphi, &sn, &cs);
+    const double mag = exp(da);
+    return make_double2(mag * cs, mag * sn);
+}
+
 // psi(x') / psi(x) in FP32 from the FP64 log-psi difference; the phase
 // difference is reduced to (-pi, pi] in FP64 before rounding.
 __device__ __forceinline__ void ratio_f32(double da, double dphi, float &rr, float &ri) {

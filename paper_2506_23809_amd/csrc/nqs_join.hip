@@ -486,17 +486,6 @@ __global__ __launch_bounds__(kJoinGroupThreads) void join_decide_kernel(
     join_decide(tab, sc, samples, n, g_eff);
 }
 
-// psi(x') / psi(x) from the log-amplitude and phase differences, out of
-// line: inlined, the FP64 exp and sincos constants stay in registers across
-// the partner loop of the pair kernel and cost it two waves per SIMD
-// (the call is made only on a hit).
-__device__ __noinline__ double2 join_amp_ratio(double da, double dphi) {
-    double sn, cs;
-    sincos(dphi, &sn, &cs);
-    const double mag = exp(da);
-    return make_double2(mag * cs, mag * sn);
-}
-
 // The contribution of partner j (bit string y = x ^ d) to E_loc(x), or no
 // hit when the table has no group with X = d.
 template <int W, bool DUMP, int P, bool SCV>
@@ -525,7 +514,7 @@ __device__ __forceinline__ bool join_hit(const DevTable &tab, const Key<W> &x, c
         } else {
             hsum = group_sum<W, DUMP>(tab, g, x, row, terms);
         }
-        const double2 rat = join_amp_ratio(log_amp[j] - la, phase[j] - ph);
+        const double2 rat = amp_ratio_f64(log_amp[j] - la, phase[j] - ph);
         re += hsum * rat.x;
         im += hsum * rat.y;
     } else {

@@ -198,11 +198,9 @@ __device__ __forceinline__ void lookup_item(
                     } else {
                         hsum = group_sum<W, DUMP>(tab, g, xl, row, &n_terms);
                     }
-                    double sn, cs;
-                    sincos(phase[j] - phl, &sn, &cs);
-                    const double mag = exp(log_amp[j] - lal);
-                    cre = hsum * (mag * cs);
-                    cim = hsum * (mag * sn);
+                    const double2 rat = amp_ratio_f64(log_amp[j] - lal, phase[j] - phl);
+                    cre = hsum * rat.x;
+                    cim = hsum * rat.y;
                 } else {
                     const AccF32 hs = group_sum_f32<W>(tab, g, xl, &n_terms);
                     float rr, ri;
@@ -595,6 +593,8 @@ __device__ __forceinline__ void enum_candidate(
         } else {
             hsum = group_sum<W, DUMP>(tab, g, x, row, &cnt.terms);
         }
+        // (inline: this kernel's occupancy is set by its LDS, and a call
+        // would only add a stack)
         double sn, cs;
         sincos(phase[j] - ph, &sn, &cs);
         const double mag = exp(log_amp[j] - la);
