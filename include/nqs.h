@@ -264,7 +264,8 @@ int nqs_sync(nqs_ham h, void *hip_stream);
  *   out[2] hits       = lookups that found x' in S (off-diagonal)
  *   out[3] terms      = Pauli terms evaluated (diagonal group plus hit groups)
  *   out[4] candidates = lookups that passed the on-chip filter and went to
- *                       the hash table in device memory
+ *                       the hash table in device memory (with the pair
+ *                       join: the ordered pairs of samples sharing a group)
  *   out[5] rounds     = sample rounds run by the flip enumeration (0 when
  *                       the group-streaming kernel did the lookups)
  * With the enumeration, probes counts every spin-conserving single and
@@ -320,12 +321,14 @@ int nqs_last_kernel_ms(nqs_ham h, float out[3]);
 /*
  * Finer durations of the last profiled evaluation, in milliseconds, from
  * the same events plus two more (stages that did not run take ~0):
- *   out[0] clear and the pair join's grouping (bucket keys and, in the same
- *          launch, the hash clear; partition counts, placing, per-partition
- *          sort, the device's decision)
+ *   out[0] clear and the pair join's grouping (bucket keys, fingerprints
+ *          and the sample checks and, in the same launch, the hash clear;
+ *          partition counts, placing, per-partition sort, the device's
+ *          decision)
  *   out[1] sample-hash build (~0 when the join is launched: the build then
  *          runs inside the pair kernel's launch)
- *   out[2] the pair join's pair kernel (with the hash build)
+ *   out[2] the pair join's pair kernel (with the hash build, except in a
+ *          launch that only joins)
  *   out[3] enumeration / streaming lookup kernels (return at once when the
  *          join runs)
  *   out[4] finish kernel (diagonal + partial sums)
@@ -371,18 +374,18 @@ int nqs_debug_dump(nqs_ham h, int64_t n, const uint64_t *samples, const double *
  *   NQS_STRATEGY_JOIN: the pair join.  Every group of the table flips at
  *     most m qubits (m = 4 for molecular tables), so two samples a term
  *     connects agree on at least one of m + 1 disjoint qubit blocks; the
- *     samples are bucketed by the contents of each block, and only pairs of
- *     samples sharing a bucket are tested (Hamming distance, then the group
- *     index).  Its cost is the sum of squared bucket sizes, independent of
- *     the table's size: for samples spread over a large sector it is far
- *     below both others.  Needs m + 1 <= 8, at most 2^21 samples, and at
+ *     samples are grouped by the contents of each block (a hash bucket,
+ *     split by a content fingerprint), and only pairs of samples sharing a
+ *     group are tested (Hamming distance, then the group index).  Its cost
+ *     is the sum of squared group sizes, independent of the table's size:
+ *     for samples spread over a large sector it is far below both others.  Needs m + 1 <= 8, at most 2^21 samples, and at
  *     most 8192 entries in one partition of 2^11 buckets (a hash range of
  *     the bucket keys; about two thousand entries each on average);
  *     otherwise (decided on the device) the enumeration or streaming
  *     strategy runs instead.
  *   NQS_STRATEGY_AUTO (0): the pair join is launched beside the enumeration
  *     (where the table allows it) or streaming, and the device runs the
- *     join when its counted cost (sum of squared bucket sizes plus a term
+ *     join when its counted cost (sum of squared group sizes plus a term
  *     per entry) is below the other strategy's (the
  *     enumeration's lookups, or half the sample-group pairs of streaming).
  *     Batches (nqs_batch_*) make the same decision per job: a job's

@@ -224,7 +224,7 @@ struct DevScratch {
 };
 
 // Pair-join control words (jctl): the enumeration's probe count, the join's
-// ordered candidate pairs (sum of squared bucket sizes), the largest bucket,
+// ordered candidate pairs (sum of squared group sizes), the largest bucket,
 // whether a partition exceeded kJoinPartCap, and the decision (1: the join
 // runs); then 64 slots of the probe count.
 enum { kJoinCtlProbes = 0, kJoinCtlCost = 1, kJoinCtlMax = 2, kJoinCtlOver = 3,

@@ -26,7 +26,7 @@
 // Cost: the ordered pairs inside groups, the sum of squared group sizes.
 // For samples spread over a large sector this is far below the
 // enumeration's N x (connected states per sample) lookups.  The decision is
-// taken on the device from the bucket sizes, between the hash clear and the
+// taken on the device from the group sizes, between the hash clear and the
 // hash build: when the join is cheaper it runs, and the hash build's
 // insertion, the enumeration and the streaming kernels of the same launch
 // stand down; otherwise those run and the pair kernel returns at once.
