@@ -15,7 +15,9 @@ samples in 1024-sample blocks), eagerly and through the replayed graph:
   * after a call that ran the pair join, the next one launches only the
     join's kernels: when the device declines the join for new contents of
     the same buffers, the call evaluates again with every launch and its
-    result still equals nqs_eloc_eval's.
+    result still equals nqs_eloc_eval's;
+  * such a launch carries no hash build, yet a negative count or a bit
+    beyond the register still fails the call (the grouping checks them).
 """
 import math
 import sys
@@ -158,3 +160,49 @@ def test_join_only_launch_recovers_when_the_join_is_declined(torch_dev, workload
         assert ham.plan()["join_ran"] == join_ran
     ham.close()
     ref_ham.close()
+
+
+def test_join_only_launch_still_checks_the_samples(torch_dev, workload_cache):
+    """A launch that only joins carries no hash build: the grouping makes
+    its checks.  After calls that chose the join (so that the next one
+    launches the join alone), a negative count and then a bit beyond the
+    register must still come back as NQS_E_RANGE from the call itself, and a
+    clean call afterwards must match nqs_eloc_eval."""
+    torch = torch_dev
+    w = workload_cache(("workload", "nq40", 256))
+    rng = np.random.default_rng(93)
+    n = 9000
+    spread = W.sector_samples(rng, 20, 10, 10, n)
+    la = torch.from_numpy(rng.normal(0.0, 1.0, n)).cuda()
+    ph = torch.from_numpy(rng.uniform(0.0, 2 * math.pi, n)).cuda()
+    wt = torch.from_numpy(rng.integers(1, 5, n).astype(np.int64)).cuda()
+    ham = nqs.Hamiltonian(w.x, w.z, w.c, w.n_qubits, w.spin_masks)
+    S = nqs.to_device_samples(spread)
+    out = torch.empty((n, 2), dtype=torch.float64, device="cuda")
+    for r in range(3):
+        say(f"checks in join-only launches: clean call {r}")
+        ham.eloc_energy_into(out, S, la, ph, wt)
+        assert ham.plan()["join_ran"] == 1
+    say("checks in join-only launches: a negative count")
+    bad_w = wt.clone()
+    bad_w[4321] = -1
+    wt.copy_(bad_w)
+    with pytest.raises(nqs.NQSError) as ex:
+        ham.eloc_energy_into(out, S, la, ph, wt)
+    assert ex.value.code == nqs.NQS_E_RANGE
+    wt[4321] = 2
+    say("checks in join-only launches: a bit beyond the register")
+    bad = spread.copy()
+    bad[777, 0] |= np.uint64(1) << np.uint64(45)
+    S.copy_(nqs.to_device_samples(bad))
+    with pytest.raises(nqs.NQSError) as ex:
+        ham.eloc_energy_into(out, S, la, ph, wt)
+    assert ex.value.code == nqs.NQS_E_RANGE
+    say("checks in join-only launches: clean again")
+    S.copy_(nqs.to_device_samples(spread))
+    ref = torch.view_as_real(ham.eloc(S, la, ph, wt)).cpu().numpy()
+    ham.sync()
+    out.fill_(float("nan"))
+    ham.eloc_energy_into(out, S, la, ph, wt)
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), ref.view(np.uint64))
+    ham.close()
